@@ -1,0 +1,44 @@
+"""Plain FP64 CPU oracle for the plane-parallel formal solution and the
+accelerated Lambda iteration.
+
+THIS PACKAGE IS TEST INFRASTRUCTURE.  Only the test-suite, the smoke check and
+the benchmark's CPU-baseline leg may import it.  The product path (the HIP
+library and its Python binding) never imports, links or calls it, and this
+package imports nothing from the product package: the two share only the
+seeded input description in ``paper_0903_1949_amd.workloads``, which the
+callers (tests, bench) pass in as plain arrays.
+
+Everything here is written for readability against the mathematics, not for
+speed: numpy vectorises over frequency and angle, depth is a Python loop, and
+every result is in float64.
+
+The paper (Hauschildt & Baron, "A 3D radiative transfer framework IV",
+Sect. 2) defers the formal solution and the operator-splitting equations to
+its Papers I and II.  What is computed here is therefore the standard statement
+of 1D plane-parallel transfer that those methods discretise:
+
+* formal solution with a source function linear in optical depth between nodes
+  (exact integration of the transfer equation along each ray), Gauss angles
+  per hemisphere, zero incident intensity at the top and a diffusion inner
+  boundary (Sect. 3.1, items 3-4);
+* the diagonal approximate Lambda operator (the "local" operator of Sect. 3.2.1)
+  as the exact diagonal of the discrete Lambda matrix;
+* the two-level operator-splitting update of Olson, Auer & Buchler (1986) /
+  Rybicki & Hummer (1991) with that diagonal operator;
+* a homogeneous isotropically scattering layer (the parameterised coherent
+  continuum scattering of Sect. 3.1, item 6) solved exactly and combined by
+  the adding method (transmission t, reflection r, source beta per layer);
+* preconditioned radiative rates and the per-depth statistical-equilibrium
+  solve for a multilevel atom.
+
+Modules
+-------
+quadrature  Gauss-Legendre angles on (0, 1).
+formal      diagonal (omega = 0) formal solution, Lambda* and the brute-force
+            Lambda matrix.
+ali         two-level ALI and the direct fixed-point solve.
+dense       omega > 0: exact layer operators by matrix exponential + doubling,
+            adding recursion, dense Lambda*.
+rates       multilevel preconditioned rates and statistical equilibrium.
+grad        gradients of the emergent spectrum (complex step, central FD).
+"""

@@ -1,0 +1,118 @@
+"""Pins of the two-level ALI oracle: the fixed point equals a direct dense
+solve built from brute-force Lambda columns (P5), the sqrt(eps) surface law
+of a semi-infinite constant-property atmosphere (P3), the error bound of a
+contraction at a finite tolerance, and the continuum-free flux invariant."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import ali, formal
+from oracle.quadrature import gauss_legendre01
+from paper_0903_1949_amd import workloads as W
+
+
+def test_ali_fixed_point_equals_direct_solve():
+    rng = np.random.default_rng(7)
+    nd, nf, na, eps = 12, 5, 3, 1e-2
+    tau = np.logspace(-3, 3, nd)
+    x, phi, wnu = W.doppler_grid(nf, 3.0)
+    q = rng.lognormal(0, 0.4, size=nd)[:, None] * phi[None, :]
+    B = rng.uniform(0.8, 1.2, size=nd)
+    mu, w = gauss_legendre01(na)
+    r = ali.two_level_ali(tau, q, phi, wnu, eps, B, mu, w, tol=1e-14, max_iter=5000)
+    assert r["converged"]
+    Sd = ali.direct_fixed_point(tau, q, phi, wnu, eps, B, mu, w)
+    assert np.max(np.abs(r["S"] - Sd) / np.abs(Sd)) < 1e-11
+    # S satisfies S = (1-eps) Jbar + eps B with Jbar from its own formal solution
+    out = formal.formal_solution(tau, q, r["S"], mu, w, lower="diffusion",
+                                 Bbot=np.full(nf, B[-1]), Bbot_prev=np.full(nf, B[-2]))
+    Jbar = out["J"] @ (wnu * phi)
+    assert np.allclose(r["S"], (1 - eps) * Jbar + eps * B, rtol=1e-12, atol=0)
+
+
+def test_ali_finite_tolerance_error_bound():
+    """At tolerance tol the error of a linear contraction with ratio rho is
+    at most about tol / (1 - rho); rho is read off the last iterations."""
+    c = W.single_two_level(nd=64, na=4, nf=21, eps=1e-4)
+    mu, w = gauss_legendre01(c.na)
+    r = ali.two_level_ali(c.tau, c.q, c.phi, c.wnu, 1e-4, c.B, mu, w, tol=1e-8)
+    assert r["converged"]
+    h = r["max_rel"]
+    rho = h[-1] / h[-2]
+    Sd = ali.direct_fixed_point(c.tau, c.q, c.phi, c.wnu, 1e-4, c.B, mu, w)
+    err = np.max(np.abs(r["S"] - Sd) / Sd)
+    assert err <= 1.5 * 1e-8 / (1 - rho)
+    # the iteration history is monotone in its tail (a clean contraction)
+    assert np.all(np.diff(h[-50:]) < 0)
+
+
+def _surface_ratio(eps, nd):
+    c = W.single_two_level(nd=nd, na=4, nf=21, eps=eps, tau_lo=1e-4, tau_hi=1e8)
+    mu, w = gauss_legendre01(c.na)
+    S = ali.direct_fixed_point(c.tau, c.q, c.phi, c.wnu, eps, c.B, mu, w)
+    assert np.all(S <= 1 + 1e-9) and np.all(np.diff(S) > -1e-12)
+    assert abs(S[-1] - 1.0) < 1e-6
+    return S[0] / math.sqrt(eps)
+
+
+def test_sqrt_eps_surface_law_converges():
+    """Semi-infinite, constant-property two-level atom with complete
+    redistribution: S(0) = sqrt(eps) B exactly for the depth-continuous
+    problem with normalised quadratures.  The discrete surface value must
+    approach it monotonically as the depth grid is refined (97 -> 193 -> 385
+    points over 1e-4..1e8), and a Richardson extrapolation of the three must
+    land on it."""
+    r = [_surface_ratio(1e-2, nd) for nd in (97, 193, 385)]
+    assert r[0] < r[1] < r[2] < 1.0
+    order = math.log2((r[1] - r[0]) / (r[2] - r[1]))
+    ext = r[2] + (r[2] - r[1]) / (2 ** order - 1)
+    assert 1.0 < order < 3.0
+    assert abs(ext - 1.0) < 5e-3
+    assert abs(r[2] - 1.0) < 1e-2
+
+
+def test_sqrt_eps_surface_law_small_eps_trend():
+    """eps = 1e-4 is still pre-asymptotic at these grids; the surface ratio
+    must nevertheless rise monotonically toward 1 with refinement."""
+    r = [_surface_ratio(1e-4, nd) for nd in (97, 193, 385)]
+    assert r[0] < r[1] < r[2] < 1.0
+    assert (1 - r[2]) < 0.6 * (1 - r[1]) < 0.6 * 0.6 * (1 - r[0]) * 1.2
+    assert abs(r[2] - 1.0) < 0.1
+
+
+def test_flux_constant_at_eps_zero_diagnostic():
+    """eps = 0 (pure scattering line): integrating mu dI_k/dtau = phi_k (I_k - S)
+    over angle and frequency gives d/dtau sum_k wnu_k H_k = Jbar - S = 0, so the
+    frequency-integrated flux is constant with depth up to discretisation error."""
+    nd, nf, na = 64, 11, 4
+    tau = np.logspace(-4, 2, nd)
+    x, phi, wnu = W.doppler_grid(nf, 4.0)
+    q = np.broadcast_to(phi, (nd, nf)).copy()
+    mu, w = gauss_legendre01(na)
+    B = 1.0 + 0.75 * tau       # diffusion-consistent lower boundary drives a flux
+    S = ali.direct_fixed_point(tau, q, phi, wnu, 0.0, B, mu, w)
+    out = formal.formal_solution(tau, q, S, mu, w, lower="diffusion",
+                                 Bbot=np.full(nf, B[-1]), Bbot_prev=np.full(nf, B[-2]))
+    Hbar = out["H"] @ wnu
+    spread = (Hbar.max() - Hbar.min()) / Hbar.mean()
+    assert spread < 2e-2
+
+
+def test_batch_update_matches_single():
+    nd = np.array([3, 4])
+    S = np.array([0.5, 0.6, 0.7, 0.4, 0.5, 0.6, 0.7])
+    B = np.ones(7)
+    eps = np.array([1e-2, 1e-3])
+    jms = np.array([0.1, -0.05, 0.0, 0.2, 0.1, 0.0, -0.1])
+    olb = np.array([0.9, 0.5, 0.1, 0.8, 0.4, 0.2, 0.05])
+    Sn, mx = ali.batch_two_level_update(nd, S, B, eps, jms, olb)
+    e = np.repeat(eps, nd)
+    ref = S + ((1 - e) * jms + e * (B - S)) / (e + (1 - e) * olb)
+    assert np.allclose(Sn, ref, rtol=1e-15)
+    # same update written as (1-eps)(Jbar - Lbar S) + eps B over 1 - (1-eps) Lbar
+    L = 1 - olb
+    Jbar = jms + S
+    alt = ((1 - e) * (Jbar - L * S) + e * B) / (1 - (1 - e) * L)
+    assert np.allclose(Sn, alt, rtol=1e-13)
+    assert mx[0] == pytest.approx(np.max(np.abs(Sn[:3] - S[:3]) / np.abs(Sn[:3])))
