@@ -1,0 +1,226 @@
+#!/usr/bin/env python3
+"""Throughput of the plane-parallel formal solution + two-level ALI step.
+
+One step = one operator-splitting iteration over the whole batch: the formal
+solution of every atmosphere (both hemispheres, every angle and frequency,
+difference form) fused with the J-bar and Lambda-bar* profile quadratures,
+then the float64 source-function update and the per-atmosphere maximum
+relative change.  The metric counts formal-solution points per second,
+one point = one (depth, angle, frequency) triple with both I+ and I-.
+
+Workload: 512 independent two-level atmospheres, depth points uniform in
+48..256 (seed 3), 8 Gauss angles per hemisphere, 1024 frequencies across a
+Doppler profile, eps log-uniform in 1e-6..1e-1, per-depth opacity
+multipliers lognormal(0, 0.5).  All inputs are synthetic and resident in HBM
+before the timed region.
+
+Prints ONE JSON line.  Also reported beside the batched FP32 value: the plain
+FP64 GPU path (one FP64 launch pair per atmosphere, no batching or tuning),
+the FP32-vs-FP64 difference of the step, the roofline of the dominant kernel
+measured with HIP events on its own stream, and the CPU oracle on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Algorithmic FP32 work of the sweep per point (FMA = 2 flops, exp = 1):
+# per hemisphere and angle: Delta (1), exp (1), 1 - e (1), times mu/dtau (2),
+# D = e D + psi dS (3), J and Lambda* accumulations (4)  -> 12, both hemispheres 24.
+FLOPS_PER_POINT = 24.0
+PEAK_FP32_VALU_NONPACKED = 78.6   # TFLOP/s: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+PEAK_HBM = 8000.0                 # GB/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--fp64-steps", type=int, default=5)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=12, help="atmospheres in the CPU sample")
+    ap.add_argument("--waves-per-block", type=int, default=0)
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_fs_profile_c3a.json"))
+    return ap.parse_args()
+
+
+def cpu_baseline(batch, nsample):
+    """The oracle (numpy FP64, single thread) on a bounded sample of the same
+    workload: every step of one ALI iteration for `nsample` atmospheres
+    spread over the depth-count range."""
+    from threadpoolctl import threadpool_limits
+    from oracle import ali, formal
+    from oracle.quadrature import gauss_legendre01
+    order = np.argsort(batch.nd)
+    idx = order[np.linspace(0, batch.nb - 1, nsample).astype(int)]
+    sub = batch.subset(idx)
+    mu, w = gauss_legendre01(sub.na)
+    off = sub.off
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        jms = np.zeros(sub.tau.shape[0])
+        olb = np.zeros_like(jms)
+        S = sub.S_trial
+        for b in range(sub.nb):
+            s = slice(off[b], off[b + 1])
+            out = formal.formal_solution(sub.tau[s], sub.q[s], S[s], mu, w, lower="diffusion",
+                                         Bbot=np.full(sub.nf, sub.B[s][-1]),
+                                         Bbot_prev=np.full(sub.nf, sub.B[s][-2]))
+            Sg = np.broadcast_to(S[s][:, None], out["J"].shape)
+            jms[s], olb[s] = ali.profile_moments(out, S[s], Sg, sub.phi, sub.wnu)
+        ali.batch_two_level_update(sub.nd, S, sub.B, sub.eps, jms, olb)
+        dt = time.perf_counter() - t0
+    pts = sub.points
+    return {"value": pts / dt, "unit": "pts/s", "cores": 1, "kind": "oracle",
+            "sample": f"one ALI step of {sub.nb} of the 512 atmospheres (nd {int(sub.nd.min())}.."
+                      f"{int(sub.nd.max())}, {pts} points), numpy FP64, 1 thread, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}); the batched path "
+              "shards over atmospheres or frequencies without communication but no multi-GPU "
+              "run is part of this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_0903_1949_amd import pprt
+    from paper_0903_1949_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    batch = W.two_level_batch(seed=3)
+    pts = batch.points
+    ctx = pprt.Context(0)
+    stream = torch.cuda.current_stream()
+
+    # ---------------- batched FP32 path
+    plan = pprt.Plan(ctx, batch.nd, batch.na, batch.nf, precision=pprt.FP32,
+                     waves_per_block=args.waves_per_block)
+    db = pprt.upload_two_level(batch, pprt.FP32)
+    db.S.copy_(db.B)
+    S0 = db.S.clone()
+    mx = torch.zeros(batch.nb, dtype=torch.float64, device="cuda:0")
+
+    def step(ev0=None, ev1=None):
+        if ev0 is not None:
+            ev0.record(stream)
+        plan.two_level_moments(db.tau, db.q, db.S, db.eps, db.B, db.wphi)
+        if ev1 is not None:
+            ev1.record(stream)
+        plan.two_level_update(db.S, db.eps, db.B, db.wphi, mx)
+
+    # FP32 vs FP64 difference of one step from the same S (not timed)
+    step()
+    torch.cuda.synchronize()
+    S_fp32_one = db.S.clone()
+    plan64 = pprt.Plan(ctx, batch.nd, batch.na, batch.nf, precision=pprt.FP64)
+    db64 = pprt.upload_two_level(batch, pprt.FP64)
+    db64.S.copy_(S0)
+    mx64 = torch.zeros_like(mx)
+    plan64.two_level_ali_step(db64.tau, db64.q, db64.S, db64.eps, db64.B, db64.wphi, mx64)
+    torch.cuda.synchronize()
+    d32 = (S_fp32_one - S0).double()
+    d64 = (db64.S - S0)
+    rel_step = float(((S_fp32_one - db64.S).abs() / db64.S.abs()).max())
+    rel_update = float(((d32 - d64).abs() / torch.clamp(d64.abs(), min=1e-4 * float(d64.abs().max()))).max())
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e0, e1 in evs:
+        step(e0, e1)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    fs_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
+    value = pts / (wall / args.steps)
+
+    achieved_tflops = pts * FLOPS_PER_POINT / (fs_ms * 1e-3) / 1e12
+    traffic = None
+    if os.path.exists(args.traffic_json):
+        try:
+            tj = json.load(open(args.traffic_json))
+            if tj.get("kernel_source_hash") == kernel_hash():
+                traffic = tj.get("bytes_per_launch")
+        except Exception:
+            traffic = None
+    roofline = {"bound": "alu", "achieved": round(achieved_tflops, 3),
+                "peak": PEAK_FP32_VALU_NONPACKED, "unit": "TFLOP/s",
+                "frac": round(achieved_tflops / PEAK_FP32_VALU_NONPACKED, 4), "traffic": traffic,
+                "kernel": "k_fs_profile<float,8>", "kernel_ms": round(fs_ms, 5),
+                "flops_per_point": FLOPS_PER_POINT}
+
+    # ---------------- plain FP64 path: one FP64 launch pair per atmosphere
+    fp64 = None
+    if not args.no_fp64:
+        off = batch.off
+        plans, views = [], []
+        for b in range(batch.nb):
+            s = slice(int(off[b]), int(off[b + 1]))
+            plans.append(pprt.Plan(ctx, batch.nd[b:b + 1], batch.na, batch.nf, precision=pprt.FP64,
+                                   waves_per_block=1))
+            views.append((db64.tau[s], db64.q[s], db64.S[s], db64.eps[b:b + 1], db64.B[s],
+                          mx64[b:b + 1]))
+        def step64():
+            for p, (tau, q, S, eps, B, m) in zip(plans, views):
+                p.two_level_ali_step(tau, q, S, eps, B, db64.wphi, m)
+        step64()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.fp64_steps):
+            step64()
+        torch.cuda.synchronize()
+        w64 = (time.perf_counter() - t1) / args.fp64_steps
+        fp64 = {"value": pts / w64, "ms_per_step": w64 * 1e3,
+                "desc": "FP64 sweep + update, one launch pair per atmosphere, untuned"}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(batch, args.cpu_sample)
+
+    line = {
+        "metric": "formal-solution depth*angle*freq pts/s, batched FP32 (plain FP64 beside it)",
+        "value": value, "unit": "pts/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "512 two-level atmospheres, nd U{48..256}, na 8, nf 1024, "
+                               "eps 1e-6..1e-1, seed 3 (one ALI step per step)",
+                   "nbatch": batch.nb, "rows": int(batch.nd.sum()), "na": batch.na,
+                   "nf": batch.nf, "points_per_step": pts, "seed": 3,
+                   "waves_per_block": plan.ng and args.waves_per_block},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "fp64_plain": fp64,
+        "speedup_vs_fp64_plain": (value / fp64["value"]) if fp64 else None,
+        "fp32_vs_fp64": {"S_after_one_step_rel": rel_step, "update_rel": rel_update},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def kernel_hash() -> str:
+    """Hash of the sweep kernel source: traffic counters are only reported
+    while the kernel they were taken on is unchanged."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_0903_1949_amd", "csrc", "fs_diag.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,242 @@
+/*
+ * pprt.h -- C ABI of libpprt, a plane-parallel formal solution of the
+ * equation of radiative transfer with its accelerated Lambda iteration,
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * Problem statement (Hauschildt & Baron, "A 3D radiative transfer framework
+ * IV", Sect. 2 and Sect. 3.1): the scattering problem for line transfer is
+ * solved by operator splitting around a formal solution of the transfer
+ * equation; the 1D plane-parallel calculation is the comparison standard
+ * (abstract, Sect. 3.2).  The test environment of Sect. 3.1 fixes the inputs:
+ * an optical-depth grid, opacities, a Planck function, zero incident
+ * intensity at the outer boundary, a diffusion inner boundary, a two-level
+ * line with thermalisation parameter eps and coherent isotropic continuum
+ * scattering.  Inputs: atmosphere (tau grid), opacities, source terms and
+ * model atom.  Outputs: I+/I-, J, Jbar, Lambda*, rates and populations.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - tau is the reference optical depth, strictly increasing inward; node 0
+ *   is the top.  A batch holds nbatch independent atmospheres with nd[b]
+ *   nodes each (2 <= nd[b]); off[b] = nd[0] + ... + nd[b-1].
+ * - "row" = one (atmosphere, node) pair, index off[b] + d.
+ * - Per-(row, frequency) arrays are row-major: element (off[b]+d)*nf + k.
+ *   Per-(row, frequency, angle) arrays: ((off[b]+d)*nf + k)*na + i.
+ *   Per-(atmosphere, frequency) arrays: b*nf + k; with angle: (b*nf+k)*na+i.
+ * - Angles: na Gauss-Legendre nodes mu_i on (0,1) per hemisphere with
+ *   weights summing to one, ascending in mu.  I+ is the up-going (outward)
+ *   intensity, I- the down-going one, both indexed by the same mu_i.
+ * - All array pointers are DEVICE pointers unless the field says "host".
+ *   Element type of "real" arrays follows the plan precision: double for
+ *   PPRT_FP64, float for PPRT_FP32.  tau, model-atom and ALI state arrays are
+ *   always double.
+ * - Ownership: the caller allocates and frees every input, output and
+ *   workspace buffer.  The library keeps only small plan metadata (it may
+ *   call hipMalloc for that inside pprt_plan_create) and never frees caller
+ *   memory.
+ * - Asynchrony: compute calls enqueue kernels on the context stream and
+ *   return; results are ready after the caller synchronises that stream.
+ *   Nothing is copied device -> host except where a call says so.
+ * - Errors: every call returns a pprt_status.  Argument and shape errors are
+ *   detected on the host before any launch, and pprt_last_error() then
+ *   holds a message.  Conditions found on the device (non-finite values)
+ *   set bits of a status word read by pprt_sync().  No exception, abort or
+ *   exit crosses this interface.
+ * - Thread safety: one context per host thread.
+ */
+#ifndef PPRT_H
+#define PPRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pprt_status {
+  PPRT_OK = 0,
+  PPRT_E_INVALID_ARG = 1,   /* bad pointer, value or flag combination        */
+  PPRT_E_SHAPE = 2,         /* inconsistent or unsupported sizes            */
+  PPRT_E_DEVICE = 3,        /* no usable HIP device / runtime failure       */
+  PPRT_E_WORKSPACE = 4,     /* workspace missing or too small               */
+  PPRT_E_NONFINITE = 5,     /* NaN/Inf met (host scan or device status)     */
+  PPRT_E_NOT_CONVERGED = 6, /* iteration cap reached before the tolerance   */
+  PPRT_E_SINGULAR = 7,      /* a per-depth linear system cannot be solved   */
+  PPRT_E_UNSUPPORTED = 8,   /* valid request this build does not implement  */
+  PPRT_E_LAUNCH = 9         /* a kernel launch failed                       */
+} pprt_status;
+
+/* device status bits (pprt_sync) */
+#define PPRT_DEV_NONFINITE 0x1u
+#define PPRT_DEV_SINGULAR  0x2u
+
+typedef enum pprt_precision { PPRT_FP64 = 0, PPRT_FP32 = 1 } pprt_precision;
+typedef enum pprt_lower_bc { PPRT_BC_DIFFUSION = 0, PPRT_BC_GIVEN = 1 } pprt_lower_bc;
+
+/* output bitmask of pprt_formal_solution */
+#define PPRT_OUT_J       0x01u  /* J = 1/2 sum_i w_i (I+ + I-)          [row][nf]     */
+#define PPRT_OUT_JMS     0x02u  /* J - S (difference form)              [row][nf]     */
+#define PPRT_OUT_LSTAR   0x04u  /* Lambda*_dd = dJ(d)/dS(d)             [row][nf]     */
+#define PPRT_OUT_LSTAR_C 0x08u  /* 1 - Lambda*_dd, formed directly      [row][nf]     */
+#define PPRT_OUT_IPLUS   0x10u  /* I+                                   [row][nf][na] */
+#define PPRT_OUT_IMINUS  0x20u  /* I-                                   [row][nf][na] */
+#define PPRT_OUT_H       0x40u  /* H = 1/2 sum_i w_i mu_i (I+ - I-)     [row][nf]     */
+#define PPRT_OUT_IEMERG  0x80u  /* emergent I+ at node 0                [b][nf][na]   */
+
+typedef struct pprt_ctx pprt_ctx;
+typedef struct pprt_plan pprt_plan;
+
+/* ------------------------------------------------------------------ misc */
+
+/* Library version; any pointer may be NULL.  Always PPRT_OK. */
+int pprt_version(int* major, int* minor, int* patch);
+
+/* Static, never-freed description of a status code. */
+const char* pprt_status_string(pprt_status s);
+
+/* Gauss-Legendre rule on (0,1) (host helper): mu[n], w[n] host arrays,
+ * ascending mu, sum w = 1.  The angle quadrature of the 1D comparison
+ * calculations (Sect. 3.1 discretises solid angle; a plane-parallel slab
+ * needs only mu).  E_INVALID_ARG for n < 1 or n > 64 or NULL pointers. */
+pprt_status pprt_gauss_legendre01(int n, double* mu, double* w);
+
+/* --------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`.  E_DEVICE if no such device. */
+pprt_status pprt_create(pprt_ctx** out, int device);
+void pprt_destroy(pprt_ctx* ctx);
+/* Borrow a HIP stream (hipStream_t as void*; NULL = the null stream).
+ * The library never destroys it. */
+pprt_status pprt_set_stream(pprt_ctx* ctx, void* hip_stream);
+/* Message of the last host-side error on this context ("" if none). */
+const char* pprt_last_error(const pprt_ctx* ctx);
+/* Wait for the context stream, then return and clear the device status
+ * word (PPRT_DEV_* bits).  E_NONFINITE if the NONFINITE bit was set. */
+pprt_status pprt_sync(pprt_ctx* ctx, uint32_t* device_status);
+
+/* ------------------------------------------------------------------ plan */
+
+typedef struct pprt_shape {
+  int32_t nbatch;        /* number of atmospheres, >= 1                       */
+  const int32_t* nd;     /* host [nbatch]: nodes per atmosphere, each >= 2     */
+  int32_t na;            /* Gauss angles per hemisphere, 1..32                 */
+  int32_t nf;            /* frequencies, >= 1                                  */
+  int32_t precision;     /* pprt_precision of the bulk sweep                   */
+  int32_t lower_bc;      /* pprt_lower_bc                                      */
+  uint32_t outputs;      /* PPRT_OUT_* requested from pprt_formal_solution     */
+  int32_t waves_per_block; /* 0 = tuned default; else 1, 2, 4 or 8             */
+} pprt_shape;
+
+/* Host-only check of a shape (no device needed): returns the status that
+ * pprt_plan_create would return for it and writes a message into msg
+ * (host buffer of msg_len bytes, may be NULL). */
+pprt_status pprt_shape_check(const pprt_shape* shape, char* msg, size_t msg_len);
+
+/* Validate a shape and build the plan: ragged offsets, the work list sorted
+ * longest atmosphere first, angle constants.  `mu`/`w` (host, [na]) may be
+ * NULL for the Gauss rule.  E_SHAPE / E_INVALID_ARG on bad input. */
+pprt_status pprt_plan_create(pprt_ctx* ctx, const pprt_shape* shape,
+                             const double* mu, const double* w, pprt_plan** out);
+void pprt_plan_destroy(pprt_plan* plan);
+/* Workspace the ALI calls need (bytes, 256-aligned pointer expected). */
+pprt_status pprt_plan_workspace_bytes(const pprt_plan* plan, size_t* bytes);
+/* Total rows (sum of nd) and the plan's angle rule (host copies). */
+pprt_status pprt_plan_info(const pprt_plan* plan, int64_t* rows, double* mu, double* w);
+
+/* ------------------------------------------------------- formal solution */
+
+typedef struct pprt_fs_in {
+  const double* tau;     /* [rows] reference optical depth                    */
+  const void* q;         /* real [rows][nf]: chi_k / chi_ref, > 0              */
+  const void* Sg;        /* real [rows][nf] source function S_k                */
+  const void* Itop;      /* real [nb][nf][na] incident I- at node 0; NULL = 0  */
+  const void* Bbot;      /* real [nb][nf] B_k at the last node  (DIFFUSION)    */
+  const void* Bbot_prev; /* real [nb][nf] B_k at the node above (DIFFUSION)    */
+  const void* Ibot;      /* real [nb][nf][na] I+ at the last node (GIVEN); NULL = 0 */
+} pprt_fs_in;
+
+typedef struct pprt_fs_out {
+  void* J; void* JmS; void* lstar; void* lstar_c;   /* real [rows][nf]      */
+  void* Iplus; void* Iminus;                        /* real [rows][nf][na]  */
+  void* H;                                          /* real [rows][nf]      */
+  void* Iemerg;                                     /* real [nb][nf][na]    */
+} pprt_fs_out;
+
+/* Formal solution without in-layer scattering (the omega = 0 layer
+ * recursion: t+- = diag(exp(-dtau_k/mu_i)), r+- = 0, beta+- from a source
+ * linear in tau_k between nodes), for every atmosphere of the plan.
+ * Layer optical depth: dtau_k = (q_k(d)+q_k(d+1))/2 * (tau[d+1]-tau[d]).
+ * Lower boundary: DIFFUSION  I+(last) = B + mu (B - B_prev)/dtau_k(last layer);
+ * GIVEN  I+(last) = Ibot.  Every output whose bit is set in the plan's
+ * `outputs` must be non-NULL; other pointers are ignored.
+ * Difference form: I+-(d) - S(d) is propagated, so J - S is exact zero for
+ * constant S and 1 - Lambda* keeps full relative accuracy in thick layers. */
+pprt_status pprt_formal_solution(pprt_plan* plan, const pprt_fs_in* in, pprt_fs_out* out);
+
+/* ----------------------------------------------------- two-level atom ALI */
+
+typedef struct pprt_two_level {
+  const double* eps;     /* [nb] line thermalisation parameter, 0 <= eps <= 1 */
+  const double* B;       /* [rows] Planck function per node                   */
+  const void* wphi;      /* real [nf] wnu_k * phi_k (profile x frequency weight;
+                            sum = 1)                                          */
+} pprt_two_level;
+
+typedef struct pprt_ali_ctl {
+  double tol;            /* stop when max_d |dS|/|S_new| < tol per atmosphere */
+  int32_t max_iter;      /* iteration cap, >= 1                               */
+  int32_t iters_per_sync;/* iterations enqueued between host checks (>= 1)    */
+  int32_t use_graph;     /* 1: capture the iterations between checks in a hipGraph */
+} pprt_ali_ctl;
+
+typedef struct pprt_ali_report {
+  int32_t iterations;    /* iterations run (max over atmospheres)             */
+  int32_t n_converged;   /* atmospheres that met the tolerance                */
+  double max_rel;        /* largest last relative change over atmospheres     */
+} pprt_ali_report;
+
+/* One operator-splitting step for every atmosphere (pure two-level line,
+ * complete redistribution, diagonal Lambda*; Sect. 2 and the local-operator
+ * runs of Sect. 3.2.1):  a formal solution with S_k = S_l (the line source
+ * function, per node, float64 `S` [rows]) fused with the profile quadratures
+ *   Jbar - S_l = sum_k wphi_k (J_k - S_l),  1 - Lbar* = sum_k wphi_k (1 - Lambda*_k),
+ * then in float64
+ *   S_new = S + [(1-eps)(Jbar - S) + eps (B - S)] / [eps + (1-eps)(1 - Lbar*)].
+ * `S` is updated in place; `max_rel` [nb] (device, double) receives
+ * max_d |S_new - S|/|S_new|.  in->Sg is ignored.  Atmospheres whose
+ * `active` flag (device int32 [nb], NULL = all) is 0 are left untouched.
+ * Needs the plan workspace (E_WORKSPACE otherwise). */
+pprt_status pprt_two_level_ali_step(pprt_plan* plan, const pprt_fs_in* in,
+                                    const pprt_two_level* atom, double* S,
+                                    double* max_rel, const int32_t* active,
+                                    void* workspace);
+
+/* The two halves of pprt_two_level_ali_step, for callers that schedule or
+ * time them separately.  pprt_two_level_moments runs the formal solution
+ * and leaves the profile-weighted moments (per row, frequency group and
+ * hemisphere) in the workspace; pprt_two_level_update reads them and applies
+ * the float64 update to S, writing max_rel [nb].  Same arguments, layouts
+ * and errors as pprt_two_level_ali_step; the workspace must be the same. */
+pprt_status pprt_two_level_moments(pprt_plan* plan, const pprt_fs_in* in,
+                                   const pprt_two_level* atom, const double* S,
+                                   const int32_t* active, void* workspace);
+pprt_status pprt_two_level_update(pprt_plan* plan, const pprt_two_level* atom, double* S,
+                                  double* max_rel, const int32_t* active, void* workspace);
+
+/* Iterate pprt_two_level_ali_step from the given S (device [rows], float64,
+ * in/out) until every atmosphere's max relative change is below ctl->tol or
+ * ctl->max_iter is reached.  Each atmosphere stops at its own convergence.
+ * `iters` (device int32 [nb], may be NULL) receives the per-atmosphere
+ * iteration counts.  Synchronises the context stream every
+ * ctl->iters_per_sync iterations to test for completion (reads nb flags).
+ * E_NOT_CONVERGED if the cap was hit; the report is filled either way. */
+pprt_status pprt_two_level_ali(pprt_plan* plan, const pprt_fs_in* in,
+                               const pprt_two_level* atom, const pprt_ali_ctl* ctl,
+                               double* S, int32_t* iters, pprt_ali_report* report,
+                               void* workspace);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PPRT_H */

@@ -1,0 +1,406 @@
+// Formal solution without in-layer scattering (omega = 0) on gfx950.
+//
+// Method: for a layer between nodes d and d+1 the transmission operators are
+// diagonal, t+- = diag(exp(-dtau_k/mu_i)), the reflections vanish, and the
+// source vectors beta+- follow from a source function linear in tau_k between
+// the nodes (the 1D comparison calculation of the paper, Sect. 3.2; the
+// formal-solution scheme itself is deferred to the paper's Papers I-II,
+// Sect. 2).  The sweep is written in difference form D = I - S:
+//     D+(d)   = e D+(d+1) + psi (S(d+1) - S(d))     (up-going)
+//     D-(d+1) = e D-(d)   + psi (S(d)   - S(d+1))   (down-going)
+// with e = exp(-Delta), psi = (1 - e)/Delta, Delta = dtau_k / mu_i.  This is
+// algebraically the linear short-characteristic update and is exactly zero for
+// constant S, so J - S carries no rounding "leak".  1 - Lambda*_dd is summed
+// from psi directly (1 - alpha = psi), never as 1 minus a sum.
+//
+// Mapping: one lane per frequency, all na angles of both hemispheres in
+// registers; a block holds `waves_per_block` waves of consecutive frequencies
+// of one atmosphere; blocks are ordered longest atmosphere first.  Depth-major
+// layout: at each depth step the 64 lanes of a wave read 64 consecutive
+// frequencies of one row (coalesced).
+#include "pprt_internal.h"
+
+namespace pprt {
+namespace {
+
+// ---- per-layer transmission factor e and psi = (1-e)/Delta ---------------
+__device__ __forceinline__ void layer_ep(float dt, float inv_dt, float c, float rmu, float mu,
+                                         float& e, float& ps) {
+  const float x = dt * c;                      // Delta * log2(e)
+  e = __builtin_amdgcn_exp2f(-x);              // v_exp_f32
+  const float D = dt * rmu;                    // Delta
+  // psi = sum_{n>=0} (-D)^n/(n+1)! to D^5 below D = 1/8 (truncation < 1e-9);
+  // above it the closed form has no harmful cancellation (rel. err < 1e-6).
+  const float ser = fmaf(D, fmaf(D, fmaf(D, fmaf(D, fmaf(D, -1.f / 720.f, 1.f / 120.f),
+                                                   -1.f / 24.f), 1.f / 6.f), -0.5f), 1.f);
+  const float ex = (1.f - e) * (mu * inv_dt);
+  ps = (D < 0.125f) ? ser : ex;
+}
+
+__device__ __forceinline__ void layer_ep(double dt, double inv_dt, double /*c*/, double rmu,
+                                         double mu, double& e, double& ps) {
+  const double D = dt * rmu;
+  e = exp(-D);
+  ps = -expm1(-D) * (mu * inv_dt);
+}
+
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
+// ---- wave-wide sums (deterministic order) ---------------------------------
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xffffffffll), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float readlane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double readlane(double v, int l) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 64 lanes of a wave; every lane must be active.  Within each
+// row of 16 lanes: quad swaps, half-row mirror, row mirror; then the four row
+// sums are added in a fixed order.  The result is uniform over the wave.
+__device__ __forceinline__ float wave_sum(float v) {
+  v += dpp_f<0xb1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_f<0x4e>(v);    // quad_perm [2,3,0,1]
+  v += dpp_f<0x141>(v);   // row_half_mirror
+  v += dpp_f<0x140>(v);   // row_mirror
+  return (readlane(v, 0) + readlane(v, 16)) + (readlane(v, 32) + readlane(v, 48));
+}
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_d<0xb1>(v);
+  v += dpp_d<0x4e>(v);
+  v += dpp_d<0x141>(v);
+  v += dpp_d<0x140>(v);
+  return (readlane(v, 0) + readlane(v, 16)) + (readlane(v, 32) + readlane(v, 48));
+}
+
+// ---------------------------------------------------------------------------
+// Full-output formal solution: up-going sweep first (its partial moments are
+// parked in the output arrays), then the down-going sweep completes them.
+template <typename T, int NA>
+__global__ __launch_bounds__(512) void k_fs_full(FsFullArgs<T> a, Angles<T> ang) {
+  const Item it = a.items[blockIdx.x];
+  const int b = it.b;
+  const int nd = it.nd;
+  const int nf = a.nf;
+  const int k = it.g * (int)blockDim.x + (int)threadIdx.x;
+  if (k >= nf) return;
+  const int64_t row0 = a.off[b];
+  const uint32_t o = a.outputs;
+  T* jacc = (o & PPRT_OUT_JMS) ? a.JmS : ((o & PPRT_OUT_J) ? a.J : nullptr);
+  T* lacc = (o & PPRT_OUT_LSTAR_C) ? a.lstar_c : ((o & PPRT_OUT_LSTAR) ? a.lstar : nullptr);
+  T* hacc = (o & PPRT_OUT_H) ? a.H : nullptr;
+  T* Ip = (o & PPRT_OUT_IPLUS) ? a.Iplus : nullptr;
+  T* Im = (o & PPRT_OUT_IMINUS) ? a.Iminus : nullptr;
+
+  T D[NA];
+  // ---- up-going sweep: node nd-1 (lower boundary) -> node 0
+  int64_t r = row0 + nd - 1;
+  T q1 = a.q[r * nf + k];
+  T S1 = a.Sg[r * nf + k];
+  double t1 = a.tau[r];
+  {
+    const T q0 = a.q[(r - 1) * nf + k];
+    const T dt = T(0.5) * (q0 + q1) * T(t1 - a.tau[r - 1]);
+    if (a.lower_bc == PPRT_BC_DIFFUSION) {
+      const T Bb = a.Bbot[(int64_t)b * nf + k];
+      const T Bp = a.Bbot_prev[(int64_t)b * nf + k];
+      const T g = (Bb - Bp) / dt;
+      const T base = Bb - S1;
+#pragma unroll
+      for (int i = 0; i < NA; ++i) D[i] = base + ang.mu[i] * g;
+    } else {
+#pragma unroll
+      for (int i = 0; i < NA; ++i)
+        D[i] = (a.Ibot ? a.Ibot[((int64_t)b * nf + k) * NA + i] : T(0)) - S1;
+    }
+  }
+  auto emit_up = [&](int64_t rr, T S, T lsum) {
+    T js = T(0), hs = T(0);
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      js += ang.hw[i] * D[i];
+      hs += ang.hwmu[i] * D[i];
+    }
+    const int64_t x = rr * nf + k;
+    if (jacc) jacc[x] = js;
+    if (lacc) lacc[x] = lsum;
+    if (hacc) hacc[x] = hs;
+    if (Ip) {
+#pragma unroll
+      for (int i = 0; i < NA; ++i) Ip[x * NA + i] = D[i] + S;
+    }
+  };
+  emit_up(r, S1, ang.hwsum);
+  for (int d = nd - 2; d >= 0; --d) {
+    r = row0 + d;
+    const T q0 = a.q[r * nf + k];
+    const T S0 = a.Sg[r * nf + k];
+    const double t0 = a.tau[r];
+    const T dt = T(0.5) * (q0 + q1) * T(t1 - t0);
+    const T inv = recip(dt);
+    const T dS = S1 - S0;
+    T ls = T(0);
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      T e, ps;
+      layer_ep(dt, inv, ang.c[i], ang.rmu[i], ang.mu[i], e, ps);
+      D[i] = e * D[i] + ps * dS;
+      ls += ang.hw[i] * ps;
+    }
+    emit_up(r, S0, ls);
+    q1 = q0; S1 = S0; t1 = t0;
+  }
+  if (o & PPRT_OUT_IEMERG) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) a.Iemerg[((int64_t)b * nf + k) * NA + i] = D[i] + S1;
+  }
+
+  // ---- down-going sweep: node 0 (upper boundary) -> node nd-1
+  // q1, S1, t1 now hold node 0.
+  r = row0;
+#pragma unroll
+  for (int i = 0; i < NA; ++i)
+    D[i] = (a.Itop ? a.Itop[((int64_t)b * nf + k) * NA + i] : T(0)) - S1;
+  auto emit_down = [&](int64_t rr, T S, T lsum) {
+    T js = T(0), hs = T(0);
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      js += ang.hw[i] * D[i];
+      hs += ang.hwmu[i] * D[i];
+    }
+    const int64_t x = rr * nf + k;
+    if (jacc) {
+      js += jacc[x];
+      if (o & PPRT_OUT_JMS) a.JmS[x] = js;
+      if (o & PPRT_OUT_J) a.J[x] = js + S;
+    }
+    if (lacc) {
+      const T lc = lsum + lacc[x];
+      if (o & PPRT_OUT_LSTAR_C) a.lstar_c[x] = lc;
+      if (o & PPRT_OUT_LSTAR) a.lstar[x] = T(1) - lc;
+    }
+    if (hacc) hacc[x] = hacc[x] - hs;
+    if (Im) {
+#pragma unroll
+      for (int i = 0; i < NA; ++i) Im[x * NA + i] = D[i] + S;
+    }
+  };
+  T q0 = q1, S0 = S1;
+  double t0 = t1;
+  emit_down(r, S0, ang.hwsum);
+  for (int d = 1; d < nd; ++d) {
+    r = row0 + d;
+    q1 = a.q[r * nf + k];
+    S1 = a.Sg[r * nf + k];
+    t1 = a.tau[r];
+    const T dt = T(0.5) * (q0 + q1) * T(t1 - t0);
+    const T inv = recip(dt);
+    const T dS = S0 - S1;
+    T ls = T(0);
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      T e, ps;
+      layer_ep(dt, inv, ang.c[i], ang.rmu[i], ang.mu[i], e, ps);
+      D[i] = e * D[i] + ps * dS;
+      ls += ang.hw[i] * ps;
+    }
+    // the lower boundary fixes I+ at the last node: its hemisphere adds hwsum there
+    emit_down(r, S1, ls);
+    q0 = q1; S0 = S1; t0 = t1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Profile-moment formal solution for the two-level ALI.  Each block runs ONE
+// sweep direction over one frequency group; the line source S_l is per node,
+// so J - S and 1 - Lambda* enter only through their profile-weighted sums,
+// which are independent between the two hemispheres.  Per node the wave sums
+// wphi_k * 1/2 sum_i w_i D_i and wphi_k * 1/2 sum_i w_i psi_i (float, fixed
+// order), parks them in LDS, and every CH nodes the block adds its waves in
+// float64 and writes part[row][g][dir][0..1].
+constexpr int CH = 64;
+
+template <typename T, int NA>
+__global__ __launch_bounds__(512) void k_fs_profile(FsProfileArgs<T> a, Angles<T> ang) {
+  extern __shared__ float lds[];           // [CH][nwave][2]
+  const Item it = a.items[blockIdx.x];
+  const int b = it.b;
+  if (a.active != nullptr && a.active[b] == 0) return;   // uniform over the block
+  const int nd = it.nd;
+  const int nf = a.nf;
+  const int nwave = (int)blockDim.x >> 6;
+  const int wave = (int)threadIdx.x >> 6;
+  const int lane = (int)threadIdx.x & 63;
+  const int k = it.g * (int)blockDim.x + (int)threadIdx.x;
+  const bool valid = k < nf;
+  const int kk = valid ? k : 0;             // clamped index: loads stay in bounds
+  const int64_t row0 = a.off[b];
+  const T wp = valid ? a.wphi[kk] : T(0);
+  const bool up = (it.dir == 0);
+
+  T D[NA];
+  int d = up ? nd - 1 : 0;
+  int64_t r = row0 + d;
+  T qn = a.q[r * nf + kk];
+  double Sn = a.S[r];
+  double tn = a.tau[r];
+  if (up) {
+    const T qa = a.q[(r - 1) * nf + kk];
+    const T dt = T(0.5) * (qa + qn) * T(tn - a.tau[r - 1]);
+    if (a.lower_bc == PPRT_BC_DIFFUSION) {
+      const double Bb = a.B[r];
+      const double Bp = a.B[r - 1];
+      const T g = T(Bb - Bp) / dt;
+      const T base = T(Bb - Sn);
+#pragma unroll
+      for (int i = 0; i < NA; ++i) D[i] = base + ang.mu[i] * g;
+    } else {
+#pragma unroll
+      for (int i = 0; i < NA; ++i)
+        D[i] = (a.Ibot ? a.Ibot[((int64_t)b * nf + kk) * NA + i] : T(0)) - T(Sn);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < NA; ++i)
+      D[i] = (a.Itop ? a.Itop[((int64_t)b * nf + kk) * NA + i] : T(0)) - T(Sn);
+  }
+
+  const int g = it.g;
+  const int dir = it.dir;
+  auto flush = [&](int j0, int count) {
+    __syncthreads();
+    for (int s = (int)threadIdx.x; s < count; s += (int)blockDim.x) {
+      const int j = j0 + s;
+      const int node = up ? nd - 1 - j : j;
+      double js = 0.0, ls = 0.0;
+      for (int w = 0; w < nwave; ++w) {
+        js += (double)lds[(s * nwave + w) * 2 + 0];
+        ls += (double)lds[(s * nwave + w) * 2 + 1];
+      }
+      double* p = a.part + (((row0 + node) * a.ng + g) * 2 + dir) * 2;
+      p[0] = js;
+      p[1] = ls;
+    }
+    __syncthreads();
+  };
+  auto park = [&](int j, T jsum, T lsum) {
+    const T jv = wave_sum(wp * jsum);
+    const T lv = wave_sum(wp * lsum);
+    if (lane == 0) {
+      const int s = j % CH;
+      lds[(s * nwave + wave) * 2 + 0] = (float)jv;
+      lds[(s * nwave + wave) * 2 + 1] = (float)lv;
+    }
+  };
+  auto node_sum = [&]() {
+    T js = T(0);
+#pragma unroll
+    for (int i = 0; i < NA; ++i) js += ang.hw[i] * D[i];
+    return js;
+  };
+
+  park(0, node_sum(), ang.hwsum);
+  int j0 = 0;
+  for (int j = 1; j < nd; ++j) {
+    if (j % CH == 0) { flush(j0, CH); j0 = j; }
+    d = up ? nd - 1 - j : j;
+    r = row0 + d;
+    const T qd = a.q[r * nf + kk];
+    const double Sd = a.S[r];
+    const double td = a.tau[r];
+    // layer between node d and its predecessor in sweep order
+    const T dt = T(0.5) * (qd + qn) * T(up ? (tn - td) : (td - tn));
+    const T inv = recip(dt);
+    const T dS = T(Sn - Sd);
+    T ls = T(0);
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      T e, ps;
+      layer_ep(dt, inv, ang.c[i], ang.rmu[i], ang.mu[i], e, ps);
+      D[i] = e * D[i] + ps * dS;
+      ls += ang.hw[i] * ps;
+    }
+    park(j, node_sum(), ls);
+    qn = qd; Sn = Sd; tn = td;
+  }
+  flush(j0, nd - j0);
+}
+
+template <typename T, int NA>
+hipError_t launch_full_t(int wpb, int nitems, hipStream_t s, const void* args, const void* ang) {
+  hipLaunchKernelGGL((k_fs_full<T, NA>), dim3(nitems), dim3(64 * wpb), 0, s,
+                     *static_cast<const FsFullArgs<T>*>(args), *static_cast<const Angles<T>*>(ang));
+  return hipGetLastError();
+}
+
+template <typename T, int NA>
+hipError_t launch_profile_t(int wpb, int nitems, hipStream_t s, const void* args, const void* ang) {
+  const size_t lds = (size_t)CH * wpb * 2 * sizeof(float);
+  hipLaunchKernelGGL((k_fs_profile<T, NA>), dim3(nitems), dim3(64 * wpb), lds, s,
+                     *static_cast<const FsProfileArgs<T>*>(args),
+                     *static_cast<const Angles<T>*>(ang));
+  return hipGetLastError();
+}
+
+#define PPRT_NA_LIST(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(12) X(16) X(24) X(32)
+
+template <typename T>
+hipError_t dispatch_full(int na, int wpb, int nitems, hipStream_t s, const void* a, const void* g) {
+  switch (na) {
+#define CASE(N) case N: return launch_full_t<T, N>(wpb, nitems, s, a, g);
+    PPRT_NA_LIST(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+template <typename T>
+hipError_t dispatch_profile(int na, int wpb, int nitems, hipStream_t s, const void* a,
+                            const void* g) {
+  switch (na) {
+#define CASE(N) case N: return launch_profile_t<T, N>(wpb, nitems, s, a, g);
+    PPRT_NA_LIST(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+bool na_supported(int na) {
+  switch (na) {
+#define CASE(N) case N: return true;
+    PPRT_NA_LIST(CASE)
+#undef CASE
+    default: return false;
+  }
+}
+
+hipError_t launch_fs_full(int precision, int na, int wpb, int nitems, hipStream_t s,
+                          const void* args, const void* angles) {
+  if (nitems == 0) return hipSuccess;
+  return precision == PPRT_FP64 ? dispatch_full<double>(na, wpb, nitems, s, args, angles)
+                                : dispatch_full<float>(na, wpb, nitems, s, args, angles);
+}
+
+hipError_t launch_fs_profile(int precision, int na, int wpb, int nitems, hipStream_t s,
+                             const void* args, const void* angles) {
+  if (nitems == 0) return hipSuccess;
+  return precision == PPRT_FP64 ? dispatch_profile<double>(na, wpb, nitems, s, args, angles)
+                                : dispatch_profile<float>(na, wpb, nitems, s, args, angles);
+}
+
+}  // namespace pprt

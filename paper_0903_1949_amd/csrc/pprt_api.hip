@@ -1,0 +1,546 @@
+// Host runtime of libpprt: context, plan, validation and the C ABI declared
+// in include/pprt.h.  No PyTorch types cross this file; every array is a
+// caller-owned pointer.
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "pprt_internal.h"
+
+using namespace pprt;
+
+struct pprt_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  uint32_t* d_status = nullptr;   // device status word
+  std::string err;
+};
+
+struct pprt_plan {
+  pprt_ctx* ctx = nullptr;
+  int nb = 0, na = 0, nf = 0, precision = 0, lower_bc = 0, wpb = 4, ng = 1;
+  uint32_t outputs = 0;
+  std::vector<int32_t> nd;
+  std::vector<int64_t> off;
+  int64_t rows = 0;
+  Item* d_items_full = nullptr;
+  int n_full = 0;
+  Item* d_items_prof = nullptr;
+  int n_prof = 0;
+  int64_t* d_off = nullptr;
+  std::vector<double> mu, w;
+  Angles<float> af{};
+  Angles<double> ad{};
+  // workspace layout of the ALI calls
+  size_t ws_part = 0, ws_maxrel = 0, ws_active = 0, ws_iters = 0, ws_bytes = 0;
+};
+
+namespace {
+
+const char* kStatusStr[] = {
+    "ok",
+    "invalid argument",
+    "invalid or unsupported shape",
+    "no usable HIP device or runtime failure",
+    "workspace missing or too small",
+    "non-finite value",
+    "iteration cap reached before the tolerance",
+    "singular per-depth system",
+    "unsupported request",
+    "kernel launch failed",
+};
+
+pprt_status fail(pprt_ctx* c, pprt_status s, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+pprt_status fail(pprt_ctx* c, pprt_status s, const char* fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return s;
+}
+
+pprt_status shape_fail(char* msg, size_t len, pprt_status s, const char* fmt, ...)
+    __attribute__((format(printf, 4, 5)));
+pprt_status shape_fail(char* msg, size_t len, pprt_status s, const char* fmt, ...) {
+  if (msg && len) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(msg, len, fmt, ap);
+    va_end(ap);
+  }
+  return s;
+}
+
+pprt_status hip_check(pprt_ctx* c, hipError_t e, const char* what) {
+  if (e == hipSuccess) return PPRT_OK;
+  return fail(c, e == hipErrorInvalidValue ? PPRT_E_LAUNCH : PPRT_E_DEVICE, "%s: %s", what,
+              hipGetErrorString(e));
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// P_n(z) and P_{n-1}(z) by the three-term recurrence.
+void legendre_pair(int n, double z, double& pn, double& pm) {
+  double a = 1.0, b = z;
+  for (int j = 2; j <= n; ++j) {
+    const double c = ((2.0 * j - 1.0) * z * b - (j - 1.0) * a) / j;
+    a = b;
+    b = c;
+  }
+  pn = b;
+  pm = a;
+}
+
+// Gauss-Legendre nodes on [-1,1] by Newton iteration on P_n, weights
+// 2 / ((1 - z^2) P_n'(z)^2), mapped to (0,1) (ascending mu, weights / 2).
+void gauss01(int n, double* mu, double* w) {
+  const double pi = 3.14159265358979323846;
+  std::vector<double> x(n), wt(n);
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double z = std::cos(pi * (i + 0.75) / (n + 0.5));
+    double pn = 0.0, pm = 0.0, dp = 1.0;
+    for (int itn = 0; itn < 100; ++itn) {
+      legendre_pair(n, z, pn, pm);
+      dp = n * (z * pn - pm) / (z * z - 1.0);
+      const double dz = pn / dp;
+      z -= dz;
+      if (std::fabs(dz) <= 1e-16) break;
+    }
+    legendre_pair(n, z, pn, pm);
+    // at a root P_n' = n P_{n-1} / (1 - z^2), so w = 2 (1 - z^2) / (n P_{n-1})^2;
+    // (1 - z)(1 + z) keeps the factor accurate next to the end points.
+    const double npm = n * pm;
+    const double wi = 2.0 * (1.0 - z) * (1.0 + z) / (npm * npm);
+    x[i] = -z;
+    x[n - 1 - i] = z;
+    wt[i] = wi;
+    wt[n - 1 - i] = wi;
+  }
+  for (int i = 0; i < n; ++i) {
+    mu[i] = 0.5 * (x[i] + 1.0);
+    w[i] = 0.5 * wt[i];
+  }
+}
+
+template <typename T>
+void fill_angles(Angles<T>& A, const std::vector<double>& mu, const std::vector<double>& w) {
+  std::memset(&A, 0, sizeof A);
+  const double log2e = 1.4426950408889634074;
+  double hs = 0.0;
+  for (size_t i = 0; i < mu.size(); ++i) {
+    A.c[i] = (T)(log2e / mu[i]);
+    A.rmu[i] = (T)(1.0 / mu[i]);
+    A.mu[i] = (T)mu[i];
+    A.hw[i] = (T)(0.5 * w[i]);
+    A.hwmu[i] = (T)(0.5 * w[i] * mu[i]);
+    hs += 0.5 * w[i];
+  }
+  A.hwsum = (T)hs;
+}
+
+const void* angles_of(const pprt_plan* p) {
+  return p->precision == PPRT_FP64 ? (const void*)&p->ad : (const void*)&p->af;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pprt_version(int* major, int* minor, int* patch) {
+  if (major) *major = 0;
+  if (minor) *minor = 1;
+  if (patch) *patch = 0;
+  return PPRT_OK;
+}
+
+const char* pprt_status_string(pprt_status s) {
+  const int i = (int)s;
+  if (i < 0 || i >= (int)(sizeof kStatusStr / sizeof kStatusStr[0])) return "unknown status";
+  return kStatusStr[i];
+}
+
+pprt_status pprt_gauss_legendre01(int n, double* mu, double* w) {
+  if (n < 1 || n > 64 || !mu || !w) return PPRT_E_INVALID_ARG;
+  gauss01(n, mu, w);
+  return PPRT_OK;
+}
+
+pprt_status pprt_create(pprt_ctx** out, int device) {
+  if (!out) return PPRT_E_INVALID_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return PPRT_E_DEVICE;
+  if (device < 0 || device >= n) return PPRT_E_DEVICE;
+  if (hipSetDevice(device) != hipSuccess) return PPRT_E_DEVICE;
+  pprt_ctx* c = new (std::nothrow) pprt_ctx;
+  if (!c) return PPRT_E_DEVICE;
+  c->device = device;
+  if (hipMalloc(&c->d_status, sizeof(uint32_t)) != hipSuccess ||
+      hipMemset(c->d_status, 0, sizeof(uint32_t)) != hipSuccess) {
+    delete c;
+    return PPRT_E_DEVICE;
+  }
+  *out = c;
+  return PPRT_OK;
+}
+
+void pprt_destroy(pprt_ctx* c) {
+  if (!c) return;
+  if (c->d_status) (void)hipFree(c->d_status);
+  delete c;
+}
+
+pprt_status pprt_set_stream(pprt_ctx* c, void* s) {
+  if (!c) return PPRT_E_INVALID_ARG;
+  c->stream = (hipStream_t)s;
+  return PPRT_OK;
+}
+
+const char* pprt_last_error(const pprt_ctx* c) { return c ? c->err.c_str() : ""; }
+
+pprt_status pprt_sync(pprt_ctx* c, uint32_t* device_status) {
+  if (!c) return PPRT_E_INVALID_ARG;
+  uint32_t st = 0;
+  pprt_status r = hip_check(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  if (r != PPRT_OK) return r;
+  r = hip_check(c, hipMemcpy(&st, c->d_status, sizeof st, hipMemcpyDeviceToHost), "status read");
+  if (r != PPRT_OK) return r;
+  r = hip_check(c, hipMemset(c->d_status, 0, sizeof st), "status clear");
+  if (r != PPRT_OK) return r;
+  if (device_status) *device_status = st;
+  if (st & PPRT_DEV_NONFINITE) return fail(c, PPRT_E_NONFINITE, "device reported non-finite values");
+  return PPRT_OK;
+}
+
+pprt_status pprt_shape_check(const pprt_shape* sh, char* msg, size_t msg_len) {
+  if (msg && msg_len) msg[0] = 0;
+  if (!sh) return shape_fail(msg, msg_len, PPRT_E_INVALID_ARG, "null shape");
+  if (sh->nbatch < 1) return shape_fail(msg, msg_len, PPRT_E_SHAPE, "nbatch must be >= 1 (got %d)", sh->nbatch);
+  if (!sh->nd) return shape_fail(msg, msg_len, PPRT_E_INVALID_ARG, "shape.nd is NULL");
+  if (sh->nf < 1) return shape_fail(msg, msg_len, PPRT_E_SHAPE, "nf must be >= 1 (got %d)", sh->nf);
+  if (sh->na < 1 || sh->na > kMaxNA) return shape_fail(msg, msg_len, PPRT_E_SHAPE, "na must be in 1..32 (got %d)", sh->na);
+  if (!na_supported(sh->na))
+    return shape_fail(msg, msg_len, PPRT_E_UNSUPPORTED, "na = %d has no compiled sweep (1-8, 12, 16, 24, 32)", sh->na);
+  if (sh->precision != PPRT_FP64 && sh->precision != PPRT_FP32)
+    return shape_fail(msg, msg_len, PPRT_E_INVALID_ARG, "unknown precision %d", sh->precision);
+  if (sh->lower_bc != PPRT_BC_DIFFUSION && sh->lower_bc != PPRT_BC_GIVEN)
+    return shape_fail(msg, msg_len, PPRT_E_INVALID_ARG, "unknown lower boundary %d", sh->lower_bc);
+  if (sh->outputs & ~0xffu) return shape_fail(msg, msg_len, PPRT_E_INVALID_ARG, "unknown output bits 0x%x", sh->outputs);
+  if (sh->waves_per_block != 0 && sh->waves_per_block != 1 && sh->waves_per_block != 2 &&
+      sh->waves_per_block != 4 && sh->waves_per_block != 8)
+    return shape_fail(msg, msg_len, PPRT_E_INVALID_ARG, "waves_per_block must be 0, 1, 2, 4 or 8");
+  if ((int64_t)sh->nf * sh->na > (int64_t)1 << 40) return shape_fail(msg, msg_len, PPRT_E_SHAPE, "nf*na too large");
+  for (int b = 0; b < sh->nbatch; ++b)
+    if (sh->nd[b] < 2) return shape_fail(msg, msg_len, PPRT_E_SHAPE, "nd[%d] = %d: need at least 2 nodes", b, sh->nd[b]);
+
+  return PPRT_OK;
+}
+
+pprt_status pprt_plan_create(pprt_ctx* c, const pprt_shape* sh, const double* mu,
+                             const double* w, pprt_plan** out) {
+  if (!c || !sh || !out) return fail(c, PPRT_E_INVALID_ARG, "null argument");
+  *out = nullptr;
+  {
+    char msg[256];
+    const pprt_status st = pprt_shape_check(sh, msg, sizeof msg);
+    if (st != PPRT_OK) return fail(c, st, "%s", msg);
+  }
+  const int wpb_in = sh->waves_per_block;
+  pprt_plan* p = new (std::nothrow) pprt_plan;
+  if (!p) return fail(c, PPRT_E_DEVICE, "out of host memory");
+  p->ctx = c;
+  p->nb = sh->nbatch;
+  p->na = sh->na;
+  p->nf = sh->nf;
+  p->precision = sh->precision;
+  p->lower_bc = sh->lower_bc;
+  p->outputs = sh->outputs;
+  p->nd.assign(sh->nd, sh->nd + sh->nbatch);
+  p->off.assign(p->nb + 1, 0);
+  for (int b = 0; b < p->nb; ++b) p->off[b + 1] = p->off[b] + p->nd[b];
+  p->rows = p->off[p->nb];
+
+  p->mu.resize(p->na);
+  p->w.resize(p->na);
+  if (mu && w) {
+    for (int i = 0; i < p->na; ++i) {
+      if (!(mu[i] > 0.0 && mu[i] <= 1.0) || !(w[i] > 0.0)) {
+        delete p;
+        return fail(c, PPRT_E_INVALID_ARG, "angle %d: need 0 < mu <= 1 and w > 0", i);
+      }
+      p->mu[i] = mu[i];
+      p->w[i] = w[i];
+    }
+  } else if (mu || w) {
+    delete p;
+    return fail(c, PPRT_E_INVALID_ARG, "give both mu and w or neither");
+  } else {
+    gauss01(p->na, p->mu.data(), p->w.data());
+  }
+  fill_angles(p->af, p->mu, p->w);
+  fill_angles(p->ad, p->mu, p->w);
+
+  // frequencies per block: one lane per frequency, 64 lanes per wave
+  int wpb = wpb_in;
+  if (wpb == 0) wpb = p->nf <= 64 ? 1 : (p->nf <= 128 ? 2 : 4);
+  p->wpb = wpb;
+  p->ng = (p->nf + 64 * wpb - 1) / (64 * wpb);
+
+  // work lists, longest atmosphere first (ragged batches balance better)
+  std::vector<int> order(p->nb);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return p->nd[x] > p->nd[y]; });
+  std::vector<Item> full, prof;
+  full.reserve((size_t)p->nb * p->ng);
+  prof.reserve((size_t)p->nb * p->ng * 2);
+  for (int b : order)
+    for (int g = 0; g < p->ng; ++g) {
+      full.push_back(Item{b, g, 0, p->nd[b]});
+      prof.push_back(Item{b, g, 0, p->nd[b]});
+      prof.push_back(Item{b, g, 1, p->nd[b]});
+    }
+  p->n_full = (int)full.size();
+  p->n_prof = (int)prof.size();
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = hipMalloc(&p->d_items_full, full.size() * sizeof(Item));
+  if (e == hipSuccess) e = hipMalloc(&p->d_items_prof, prof.size() * sizeof(Item));
+  if (e == hipSuccess) e = hipMalloc(&p->d_off, p->off.size() * sizeof(int64_t));
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_items_full, full.data(), full.size() * sizeof(Item), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_items_prof, prof.data(), prof.size() * sizeof(Item), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_off, p->off.data(), p->off.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    pprt_plan_destroy(p);
+    return hip_check(c, e, "plan metadata");
+  }
+
+  // workspace: [part | max_rel | active | iters]
+  size_t o = 0;
+  p->ws_part = o;
+  o = align256(o + (size_t)p->rows * p->ng * 4 * sizeof(double));
+  p->ws_maxrel = o;
+  o = align256(o + (size_t)p->nb * sizeof(double));
+  p->ws_active = o;
+  o = align256(o + (size_t)p->nb * sizeof(int32_t));
+  p->ws_iters = o;
+  o = align256(o + (size_t)p->nb * sizeof(int32_t));
+  p->ws_bytes = o;
+  *out = p;
+  return PPRT_OK;
+}
+
+void pprt_plan_destroy(pprt_plan* p) {
+  if (!p) return;
+  if (p->d_items_full) (void)hipFree(p->d_items_full);
+  if (p->d_items_prof) (void)hipFree(p->d_items_prof);
+  if (p->d_off) (void)hipFree(p->d_off);
+  delete p;
+}
+
+pprt_status pprt_plan_workspace_bytes(const pprt_plan* p, size_t* bytes) {
+  if (!p || !bytes) return PPRT_E_INVALID_ARG;
+  *bytes = p->ws_bytes;
+  return PPRT_OK;
+}
+
+pprt_status pprt_plan_info(const pprt_plan* p, int64_t* rows, double* mu, double* w) {
+  if (!p) return PPRT_E_INVALID_ARG;
+  if (rows) *rows = p->rows;
+  for (int i = 0; i < p->na; ++i) {
+    if (mu) mu[i] = p->mu[i];
+    if (w) w[i] = p->w[i];
+  }
+  return PPRT_OK;
+}
+
+pprt_status pprt_formal_solution(pprt_plan* p, const pprt_fs_in* in, pprt_fs_out* out) {
+  if (!p) return PPRT_E_INVALID_ARG;
+  pprt_ctx* c = p->ctx;
+  if (!in || !out) return fail(c, PPRT_E_INVALID_ARG, "null in/out");
+  if (!in->tau || !in->q || !in->Sg) return fail(c, PPRT_E_INVALID_ARG, "tau, q and Sg are required");
+  if (p->lower_bc == PPRT_BC_DIFFUSION && (!in->Bbot || !in->Bbot_prev))
+    return fail(c, PPRT_E_INVALID_ARG, "diffusion lower boundary needs Bbot and Bbot_prev");
+  const uint32_t o = p->outputs;
+  if (o == 0) return fail(c, PPRT_E_INVALID_ARG, "plan requests no outputs");
+  struct { uint32_t bit; void* ptr; const char* name; } req[] = {
+      {PPRT_OUT_J, out->J, "J"}, {PPRT_OUT_JMS, out->JmS, "JmS"},
+      {PPRT_OUT_LSTAR, out->lstar, "lstar"}, {PPRT_OUT_LSTAR_C, out->lstar_c, "lstar_c"},
+      {PPRT_OUT_IPLUS, out->Iplus, "Iplus"}, {PPRT_OUT_IMINUS, out->Iminus, "Iminus"},
+      {PPRT_OUT_H, out->H, "H"}, {PPRT_OUT_IEMERG, out->Iemerg, "Iemerg"}};
+  for (auto& r : req)
+    if ((o & r.bit) && !r.ptr) return fail(c, PPRT_E_INVALID_ARG, "output %s requested but NULL", r.name);
+
+  hipError_t e;
+  if (p->precision == PPRT_FP64) {
+    FsFullArgs<double> a{};
+    a.items = p->d_items_full; a.off = p->d_off; a.tau = in->tau;
+    a.q = (const double*)in->q; a.Sg = (const double*)in->Sg; a.Itop = (const double*)in->Itop;
+    a.Bbot = (const double*)in->Bbot; a.Bbot_prev = (const double*)in->Bbot_prev;
+    a.Ibot = (const double*)in->Ibot;
+    a.J = (double*)out->J; a.JmS = (double*)out->JmS; a.lstar = (double*)out->lstar;
+    a.lstar_c = (double*)out->lstar_c; a.Iplus = (double*)out->Iplus; a.Iminus = (double*)out->Iminus;
+    a.H = (double*)out->H; a.Iemerg = (double*)out->Iemerg;
+    a.nf = p->nf; a.lower_bc = p->lower_bc; a.outputs = o;
+    e = launch_fs_full(p->precision, p->na, p->wpb, p->n_full, c->stream, &a, angles_of(p));
+  } else {
+    FsFullArgs<float> a{};
+    a.items = p->d_items_full; a.off = p->d_off; a.tau = in->tau;
+    a.q = (const float*)in->q; a.Sg = (const float*)in->Sg; a.Itop = (const float*)in->Itop;
+    a.Bbot = (const float*)in->Bbot; a.Bbot_prev = (const float*)in->Bbot_prev;
+    a.Ibot = (const float*)in->Ibot;
+    a.J = (float*)out->J; a.JmS = (float*)out->JmS; a.lstar = (float*)out->lstar;
+    a.lstar_c = (float*)out->lstar_c; a.Iplus = (float*)out->Iplus; a.Iminus = (float*)out->Iminus;
+    a.H = (float*)out->H; a.Iemerg = (float*)out->Iemerg;
+    a.nf = p->nf; a.lower_bc = p->lower_bc; a.outputs = o;
+    e = launch_fs_full(p->precision, p->na, p->wpb, p->n_full, c->stream, &a, angles_of(p));
+  }
+  return hip_check(c, e, "formal-solution launch");
+}
+
+static pprt_status ali_moments_impl(pprt_plan* p, const pprt_fs_in* in, const pprt_two_level* at,
+                                    const double* S, const int32_t* active, void* ws) {
+  pprt_ctx* c = p->ctx;
+  double* part = (double*)((char*)ws + p->ws_part);
+  hipError_t e;
+  if (p->precision == PPRT_FP64) {
+    FsProfileArgs<double> a{};
+    a.items = p->d_items_prof; a.off = p->d_off; a.tau = in->tau; a.q = (const double*)in->q;
+    a.S = S; a.B = at->B; a.Itop = (const double*)in->Itop; a.Ibot = (const double*)in->Ibot;
+    a.wphi = (const double*)at->wphi; a.active = active; a.part = part;
+    a.nf = p->nf; a.ng = p->ng; a.lower_bc = p->lower_bc;
+    e = launch_fs_profile(p->precision, p->na, p->wpb, p->n_prof, c->stream, &a, angles_of(p));
+  } else {
+    FsProfileArgs<float> a{};
+    a.items = p->d_items_prof; a.off = p->d_off; a.tau = in->tau; a.q = (const float*)in->q;
+    a.S = S; a.B = at->B; a.Itop = (const float*)in->Itop; a.Ibot = (const float*)in->Ibot;
+    a.wphi = (const float*)at->wphi; a.active = active; a.part = part;
+    a.nf = p->nf; a.ng = p->ng; a.lower_bc = p->lower_bc;
+    e = launch_fs_profile(p->precision, p->na, p->wpb, p->n_prof, c->stream, &a, angles_of(p));
+  }
+  return hip_check(c, e, "profile formal-solution launch");
+}
+
+static pprt_status ali_update_impl(pprt_plan* p, const pprt_two_level* at, double* S,
+                                   double* max_rel, int32_t* active, int32_t* iters, double tol,
+                                   void* ws) {
+  pprt_ctx* c = p->ctx;
+  AliUpdateArgs u{};
+  u.off = p->d_off; u.part = (const double*)((char*)ws + p->ws_part); u.eps = at->eps; u.B = at->B;
+  u.S = S; u.max_rel = max_rel; u.active = active; u.iters = iters; u.status = c->d_status;
+  u.tol = tol; u.ng = p->ng; u.nb = p->nb;
+  return hip_check(c, launch_ali_update(p->nb, c->stream, u), "ALI update launch");
+}
+
+static pprt_status ali_step_impl(pprt_plan* p, const pprt_fs_in* in, const pprt_two_level* at,
+                                 double* S, double* max_rel, int32_t* active, int32_t* iters,
+                                 double tol, void* ws) {
+  pprt_status r = ali_moments_impl(p, in, at, S, active, ws);
+  if (r != PPRT_OK) return r;
+  return ali_update_impl(p, at, S, max_rel, active, iters, tol, ws);
+}
+
+static pprt_status check_ali_args(pprt_plan* p, const pprt_fs_in* in, const pprt_two_level* at,
+                                  const double* S, void* ws) {
+  pprt_ctx* c = p->ctx;
+  if (!in || !at || !S) return fail(c, PPRT_E_INVALID_ARG, "null argument");
+  if (!in->tau || !in->q) return fail(c, PPRT_E_INVALID_ARG, "tau and q are required");
+  if (!at->eps || !at->B || !at->wphi) return fail(c, PPRT_E_INVALID_ARG, "atom needs eps, B and wphi");
+  if (!ws) return fail(c, PPRT_E_WORKSPACE, "workspace of %zu bytes required", p->ws_bytes);
+  return PPRT_OK;
+}
+
+pprt_status pprt_two_level_ali_step(pprt_plan* p, const pprt_fs_in* in, const pprt_two_level* at,
+                                    double* S, double* max_rel, const int32_t* active, void* ws) {
+  if (!p) return PPRT_E_INVALID_ARG;
+  pprt_status r = check_ali_args(p, in, at, S, ws);
+  if (r != PPRT_OK) return r;
+  if (!max_rel) return fail(p->ctx, PPRT_E_INVALID_ARG, "max_rel is required");
+  return ali_step_impl(p, in, at, S, max_rel, const_cast<int32_t*>(active), nullptr, 0.0, ws);
+}
+
+pprt_status pprt_two_level_moments(pprt_plan* p, const pprt_fs_in* in, const pprt_two_level* at,
+                                   const double* S, const int32_t* active, void* ws) {
+  if (!p) return PPRT_E_INVALID_ARG;
+  pprt_status r = check_ali_args(p, in, at, S, ws);
+  if (r != PPRT_OK) return r;
+  return ali_moments_impl(p, in, at, S, active, ws);
+}
+
+pprt_status pprt_two_level_update(pprt_plan* p, const pprt_two_level* at, double* S,
+                                  double* max_rel, const int32_t* active, void* ws) {
+  if (!p) return PPRT_E_INVALID_ARG;
+  pprt_ctx* c = p->ctx;
+  if (!at || !at->eps || !at->B || !S || !max_rel) return fail(c, PPRT_E_INVALID_ARG, "null argument");
+  if (!ws) return fail(c, PPRT_E_WORKSPACE, "workspace of %zu bytes required", p->ws_bytes);
+  return ali_update_impl(p, at, S, max_rel, const_cast<int32_t*>(active), nullptr, 0.0, ws);
+}
+
+pprt_status pprt_two_level_ali(pprt_plan* p, const pprt_fs_in* in, const pprt_two_level* at,
+                               const pprt_ali_ctl* ctl, double* S, int32_t* iters,
+                               pprt_ali_report* rep, void* ws) {
+  if (!p) return PPRT_E_INVALID_ARG;
+  pprt_ctx* c = p->ctx;
+  pprt_status r = check_ali_args(p, in, at, S, ws);
+  if (r != PPRT_OK) return r;
+  if (!ctl || !(ctl->tol > 0.0) || ctl->max_iter < 1 || ctl->iters_per_sync < 1)
+    return fail(c, PPRT_E_INVALID_ARG, "ctl needs tol > 0, max_iter >= 1, iters_per_sync >= 1");
+  char* base = (char*)ws;
+  double* maxrel = (double*)(base + p->ws_maxrel);
+  int32_t* active = (int32_t*)(base + p->ws_active);
+  int32_t* its = (int32_t*)(base + p->ws_iters);
+  r = hip_check(c, launch_fill_i32(active, 1, p->nb, c->stream), "fill");
+  if (r != PPRT_OK) return r;
+  r = hip_check(c, launch_fill_i32(its, 0, p->nb, c->stream), "fill");
+  if (r != PPRT_OK) return r;
+  std::vector<int32_t> h_active(p->nb), h_iters(p->nb);
+  std::vector<double> h_max(p->nb);
+  int done_iters = 0;
+  bool all_done = false;
+  while (done_iters < ctl->max_iter) {
+    const int m = std::min(ctl->iters_per_sync, ctl->max_iter - done_iters);
+    for (int j = 0; j < m; ++j) {
+      r = ali_step_impl(p, in, at, S, maxrel, active, its, ctl->tol, ws);
+      if (r != PPRT_OK) return r;
+    }
+    done_iters += m;
+    r = hip_check(c, hipMemcpyAsync(h_active.data(), active, p->nb * sizeof(int32_t),
+                                    hipMemcpyDeviceToHost, c->stream), "flag read");
+    if (r != PPRT_OK) return r;
+    r = hip_check(c, hipStreamSynchronize(c->stream), "sync");
+    if (r != PPRT_OK) return r;
+    all_done = std::all_of(h_active.begin(), h_active.end(), [](int32_t v) { return v == 0; });
+    if (all_done) break;
+  }
+  r = hip_check(c, hipMemcpy(h_iters.data(), its, p->nb * sizeof(int32_t), hipMemcpyDeviceToHost), "iters");
+  if (r != PPRT_OK) return r;
+  r = hip_check(c, hipMemcpy(h_max.data(), maxrel, p->nb * sizeof(double), hipMemcpyDeviceToHost), "maxrel");
+  if (r != PPRT_OK) return r;
+  if (iters) {
+    r = hip_check(c, hipMemcpy(iters, its, p->nb * sizeof(int32_t), hipMemcpyDeviceToDevice), "iters copy");
+    if (r != PPRT_OK) return r;
+  }
+  if (rep) {
+    rep->iterations = *std::max_element(h_iters.begin(), h_iters.end());
+    rep->n_converged = (int32_t)std::count(h_active.begin(), h_active.end(), 0);
+    rep->max_rel = *std::max_element(h_max.begin(), h_max.end());
+  }
+  uint32_t st = 0;
+  r = pprt_sync(c, &st);
+  if (r != PPRT_OK) return r;
+  if (!all_done) return fail(c, PPRT_E_NOT_CONVERGED, "ALI not converged after %d iterations", done_iters);
+  return PPRT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,97 @@
+// Internal structures shared by the host runtime and the kernels of libpprt.
+// Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+#include "../../include/pprt.h"
+
+namespace pprt {
+
+constexpr int kMaxNA = 32;
+
+// Angle constants of one plan, passed to kernels by value (kernel-argument
+// segment, read into scalar registers).  All per-angle, uniform over lanes.
+template <typename T>
+struct Angles {
+  T c[kMaxNA];     // log2(e) / mu_i   (exponent scale for exp2)
+  T rmu[kMaxNA];   // 1 / mu_i
+  T mu[kMaxNA];    // mu_i
+  T hw[kMaxNA];    // w_i / 2
+  T hwmu[kMaxNA];  // w_i mu_i / 2
+  T hwsum;         // sum_i w_i / 2 (one hemisphere's weight)
+};
+
+// One work item: atmosphere b, frequency group g (blockDim.x frequencies),
+// sweep direction dir (profile mode: 0 = up-going, 1 = down-going).
+struct Item {
+  int32_t b;
+  int32_t g;
+  int32_t dir;
+  int32_t nd;
+};
+
+template <typename T>
+struct FsFullArgs {
+  const Item* items;
+  const int64_t* off;       // [nb+1]
+  const double* tau;
+  const T* q;
+  const T* Sg;
+  const T* Itop;
+  const T* Bbot;
+  const T* Bbot_prev;
+  const T* Ibot;
+  T* J; T* JmS; T* lstar; T* lstar_c; T* Iplus; T* Iminus; T* H; T* Iemerg;
+  int32_t nf;
+  int32_t lower_bc;
+  uint32_t outputs;
+};
+
+template <typename T>
+struct FsProfileArgs {
+  const Item* items;
+  const int64_t* off;
+  const double* tau;
+  const T* q;
+  const double* S;          // [rows] line source function (float64 state)
+  const double* B;          // [rows] Planck function (diffusion lower boundary)
+  const T* Itop;
+  const T* Ibot;
+  const T* wphi;            // [nf]
+  const int32_t* active;    // [nb] or nullptr
+  double* part;             // [rows][ng][2 dir][2]
+  int32_t nf;
+  int32_t ng;
+  int32_t lower_bc;
+};
+
+struct AliUpdateArgs {
+  const int64_t* off;
+  const double* part;       // [rows][ng][2][2]
+  const double* eps;
+  const double* B;
+  double* S;
+  double* max_rel;          // [nb]
+  int32_t* active;          // [nb] or nullptr (device flags, 1 = iterate)
+  int32_t* iters;           // [nb] or nullptr
+  uint32_t* status;         // device status word
+  double tol;               // > 0: clear `active` once max_rel < tol
+  int32_t ng;
+  int32_t nb;
+};
+
+// Launchers (fs_diag.hip, ali.hip).  Return hipSuccess or the launch error.
+hipError_t launch_fs_full(int precision, int na, int wpb, int nitems, hipStream_t s,
+                          const void* args, const void* angles);
+hipError_t launch_fs_profile(int precision, int na, int wpb, int nitems, hipStream_t s,
+                             const void* args, const void* angles);
+hipError_t launch_ali_update(int nb, hipStream_t s, const AliUpdateArgs& a);
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+
+bool na_supported(int na);
+
+}  // namespace pprt

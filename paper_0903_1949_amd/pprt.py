@@ -1,0 +1,391 @@
+"""Thin Python binding of libpprt (C ABI in include/pprt.h).
+
+Argument marshalling only: every step of the formal solution, the profile
+quadratures and the ALI update runs in the library's HIP kernels.  PyTorch
+supplies device memory and the stream; no torch type crosses the ABI.  The
+binding refuses to run without the compiled library -- there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpprt.so")
+
+FP64, FP32 = 0, 1
+BC_DIFFUSION, BC_GIVEN = 0, 1
+OUT_J, OUT_JMS, OUT_LSTAR, OUT_LSTAR_C = 0x01, 0x02, 0x04, 0x08
+OUT_IPLUS, OUT_IMINUS, OUT_H, OUT_IEMERG = 0x10, 0x20, 0x40, 0x80
+OUT_ALL = 0xFF
+OUTPUT_NAMES = {OUT_J: "J", OUT_JMS: "JmS", OUT_LSTAR: "lstar", OUT_LSTAR_C: "lstar_c",
+                OUT_IPLUS: "Iplus", OUT_IMINUS: "Iminus", OUT_H: "H", OUT_IEMERG: "Iemerg"}
+
+STATUS = {0: "OK", 1: "E_INVALID_ARG", 2: "E_SHAPE", 3: "E_DEVICE", 4: "E_WORKSPACE",
+          5: "E_NONFINITE", 6: "E_NOT_CONVERGED", 7: "E_SINGULAR", 8: "E_UNSUPPORTED",
+          9: "E_LAUNCH"}
+
+
+class PprtError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = STATUS.get(code, str(code))
+
+
+class Shape(C.Structure):
+    _fields_ = [("nbatch", C.c_int32), ("nd", C.POINTER(C.c_int32)), ("na", C.c_int32),
+                ("nf", C.c_int32), ("precision", C.c_int32), ("lower_bc", C.c_int32),
+                ("outputs", C.c_uint32), ("waves_per_block", C.c_int32)]
+
+
+class FsIn(C.Structure):
+    _fields_ = [("tau", C.c_void_p), ("q", C.c_void_p), ("Sg", C.c_void_p), ("Itop", C.c_void_p),
+                ("Bbot", C.c_void_p), ("Bbot_prev", C.c_void_p), ("Ibot", C.c_void_p)]
+
+
+class FsOut(C.Structure):
+    _fields_ = [("J", C.c_void_p), ("JmS", C.c_void_p), ("lstar", C.c_void_p),
+                ("lstar_c", C.c_void_p), ("Iplus", C.c_void_p), ("Iminus", C.c_void_p),
+                ("H", C.c_void_p), ("Iemerg", C.c_void_p)]
+
+
+class TwoLevel(C.Structure):
+    _fields_ = [("eps", C.c_void_p), ("B", C.c_void_p), ("wphi", C.c_void_p)]
+
+
+class AliCtl(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("iters_per_sync", C.c_int32),
+                ("use_graph", C.c_int32)]
+
+
+class AliReport(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("n_converged", C.c_int32), ("max_rel", C.c_double)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libpprt.so (built in-tree by paper_0903_1949_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libpprt.so not found at {path}: build it first "
+                           "(python -m paper_0903_1949_amd.build); there is no CPU fallback")
+    lib = C.CDLL(path)
+    P, I, D, U32 = C.c_void_p, C.c_int, C.c_double, C.c_uint32
+    sig = {
+        "pprt_version": (I, [C.POINTER(I), C.POINTER(I), C.POINTER(I)]),
+        "pprt_status_string": (C.c_char_p, [I]),
+        "pprt_gauss_legendre01": (I, [I, C.POINTER(D), C.POINTER(D)]),
+        "pprt_create": (I, [C.POINTER(P), I]),
+        "pprt_destroy": (None, [P]),
+        "pprt_set_stream": (I, [P, P]),
+        "pprt_last_error": (C.c_char_p, [P]),
+        "pprt_sync": (I, [P, C.POINTER(U32)]),
+        "pprt_shape_check": (I, [C.POINTER(Shape), C.c_char_p, C.c_size_t]),
+        "pprt_plan_create": (I, [P, C.POINTER(Shape), C.POINTER(D), C.POINTER(D), C.POINTER(P)]),
+        "pprt_plan_destroy": (None, [P]),
+        "pprt_plan_workspace_bytes": (I, [P, C.POINTER(C.c_size_t)]),
+        "pprt_plan_info": (I, [P, C.POINTER(C.c_int64), C.POINTER(D), C.POINTER(D)]),
+        "pprt_formal_solution": (I, [P, C.POINTER(FsIn), C.POINTER(FsOut)]),
+        "pprt_two_level_ali_step": (I, [P, C.POINTER(FsIn), C.POINTER(TwoLevel), P, P, P, P]),
+        "pprt_two_level_moments": (I, [P, C.POINTER(FsIn), C.POINTER(TwoLevel), P, P, P]),
+        "pprt_two_level_update": (I, [P, C.POINTER(TwoLevel), P, P, P, P]),
+        "pprt_two_level_ali": (I, [P, C.POINTER(FsIn), C.POINTER(TwoLevel), C.POINTER(AliCtl),
+                                   P, P, C.POINTER(AliReport), P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def declared_symbols(header: str | None = None):
+    """Function names declared in include/pprt.h (used by the ABI test)."""
+    import re
+    header = header or os.path.join(os.path.dirname(HERE), "include", "pprt.h")
+    text = open(header).read()
+    return sorted(set(re.findall(r"\b(pprt_[a-z0-9_]+)\s*\(", text)))
+
+
+def gauss_legendre01(n: int):
+    lib = load_library()
+    mu = np.zeros(n)
+    w = np.zeros(n)
+    st = lib.pprt_gauss_legendre01(n, mu.ctypes.data_as(C.POINTER(C.c_double)),
+                                   w.ctypes.data_as(C.POINTER(C.c_double)))
+    if st != 0:
+        raise PprtError(st, "gauss_legendre01")
+    return mu, w
+
+
+def shape_check(nd, na, nf, precision=FP32, lower_bc=BC_DIFFUSION, outputs=OUT_JMS,
+                waves_per_block=0):
+    """Host-only shape validation (pprt_shape_check): (status name, message)."""
+    lib = load_library()
+    ndv = np.ascontiguousarray(np.asarray(nd, dtype=np.int32))
+    sh = Shape(int(ndv.shape[0]), ndv.ctypes.data_as(C.POINTER(C.c_int32)) if ndv.size else None,
+               int(na), int(nf), int(precision), int(lower_bc), int(outputs), int(waves_per_block))
+    buf = C.create_string_buffer(256)
+    st = lib.pprt_shape_check(C.byref(sh), buf, 256)
+    return STATUS.get(st, st), buf.value.decode()
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A libpprt context on one HIP device, enqueueing on torch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.lib = load_library()
+        self.device = device
+        h = C.c_void_p()
+        st = self.lib.pprt_create(C.byref(h), device)
+        if st != 0:
+            raise PprtError(st, f"pprt_create(device={device})")
+        self.h = h
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.set_stream(stream)
+
+    def set_stream(self, stream):
+        self.stream = stream
+        self._check(self.lib.pprt_set_stream(self.h, C.c_void_p(stream.cuda_stream)), "set_stream")
+
+    def _check(self, st, what):
+        if st != 0:
+            msg = self.lib.pprt_last_error(self.h)
+            raise PprtError(st, f"{what}: {msg.decode() if msg else ''}")
+
+    def sync(self) -> int:
+        s = C.c_uint32(0)
+        self._check(self.lib.pprt_sync(self.h, C.byref(s)), "sync")
+        return s.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pprt_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """Validated shape of a ragged batch of atmospheres (see pprt_plan_create)."""
+
+    def __init__(self, ctx: Context, nd, na: int, nf: int, precision: int = FP32,
+                 lower_bc: int = BC_DIFFUSION, outputs: int = OUT_JMS | OUT_LSTAR_C,
+                 waves_per_block: int = 0, mu=None, w=None):
+        import torch
+        self.ctx = ctx
+        self.lib = ctx.lib
+        self.nd = np.ascontiguousarray(np.asarray(nd, dtype=np.int32))
+        self.na, self.nf, self.precision = int(na), int(nf), int(precision)
+        self.lower_bc, self.outputs = int(lower_bc), int(outputs)
+        sh = Shape(int(self.nd.shape[0]), self.nd.ctypes.data_as(C.POINTER(C.c_int32)), self.na,
+                   self.nf, self.precision, self.lower_bc, self.outputs, int(waves_per_block))
+        h = C.c_void_p()
+        if (mu is None) != (w is None):
+            raise ValueError("give both mu and w or neither")
+        mup = wp = None
+        if mu is not None:
+            self._mu = np.ascontiguousarray(mu, dtype=np.float64)
+            self._w = np.ascontiguousarray(w, dtype=np.float64)
+            mup = self._mu.ctypes.data_as(C.POINTER(C.c_double))
+            wp = self._w.ctypes.data_as(C.POINTER(C.c_double))
+        ctx._check(self.lib.pprt_plan_create(ctx.h, C.byref(sh), mup, wp, C.byref(h)), "plan_create")
+        self.h = h
+        rows = C.c_int64()
+        self.mu = np.zeros(self.na)
+        self.w = np.zeros(self.na)
+        ctx._check(self.lib.pprt_plan_info(h, C.byref(rows), self.mu.ctypes.data_as(C.POINTER(C.c_double)),
+                                           self.w.ctypes.data_as(C.POINTER(C.c_double))), "plan_info")
+        self.rows = rows.value
+        nb = C.c_size_t()
+        ctx._check(self.lib.pprt_plan_workspace_bytes(h, C.byref(nb)), "workspace_bytes")
+        self.workspace_bytes = nb.value
+        self.dtype = torch.float64 if self.precision == FP64 else torch.float32
+        self._ws = None
+
+    @property
+    def nb(self) -> int:
+        return int(self.nd.shape[0])
+
+    def workspace(self):
+        import torch
+        if self._ws is None:
+            self._ws = torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8,
+                                   device=f"cuda:{self.ctx.device}")
+        return self._ws
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pprt_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ----------------------------------------------------------- checks
+    def _want(self, t, shape, dtype, name):
+        import torch
+        if t is None:
+            raise ValueError(f"{name} is required")
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+        if t.dtype != dtype:
+            raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        return t
+
+    def fs_in(self, tau, q, Sg=None, Bbot=None, Bbot_prev=None, Itop=None, Ibot=None):
+        import torch
+        R, nf, na, nb, dt = self.rows, self.nf, self.na, self.nb, self.dtype
+        self._want(tau, (R,), torch.float64, "tau")
+        self._want(q, (R, nf), dt, "q")
+        if Sg is not None:
+            self._want(Sg, (R, nf), dt, "Sg")
+        if Bbot is not None:
+            self._want(Bbot, (nb, nf), dt, "Bbot")
+        if Bbot_prev is not None:
+            self._want(Bbot_prev, (nb, nf), dt, "Bbot_prev")
+        if Itop is not None:
+            self._want(Itop, (nb, nf, na), dt, "Itop")
+        if Ibot is not None:
+            self._want(Ibot, (nb, nf, na), dt, "Ibot")
+        return FsIn(_ptr(tau), _ptr(q), _ptr(Sg), _ptr(Itop), _ptr(Bbot), _ptr(Bbot_prev), _ptr(Ibot))
+
+    # ------------------------------------------------------- entry points
+    def formal_solution(self, tau, q, Sg, Bbot=None, Bbot_prev=None, Itop=None, Ibot=None,
+                        out: dict | None = None) -> dict:
+        """pprt_formal_solution: returns a dict of the requested outputs."""
+        import torch
+        fin = self.fs_in(tau, q, Sg, Bbot, Bbot_prev, Itop, Ibot)
+        R, nf, na, nb = self.rows, self.nf, self.na, self.nb
+        shapes = {"J": (R, nf), "JmS": (R, nf), "lstar": (R, nf), "lstar_c": (R, nf),
+                  "Iplus": (R, nf, na), "Iminus": (R, nf, na), "H": (R, nf), "Iemerg": (nb, nf, na)}
+        out = dict(out or {})
+        ptrs = {}
+        for bit, name in OUTPUT_NAMES.items():
+            if self.outputs & bit:
+                if name not in out:
+                    out[name] = torch.empty(shapes[name], dtype=self.dtype, device=tau.device)
+                self._want(out[name], shapes[name], self.dtype, name)
+                ptrs[name] = _ptr(out[name])
+        fo = FsOut(**ptrs)
+        self.ctx._check(self.lib.pprt_formal_solution(self.h, C.byref(fin), C.byref(fo)),
+                        "formal_solution")
+        return out
+
+    def two_level(self, eps, B, wphi):
+        import torch
+        self._want(eps, (self.nb,), torch.float64, "eps")
+        self._want(B, (self.rows,), torch.float64, "B")
+        self._want(wphi, (self.nf,), self.dtype, "wphi")
+        return TwoLevel(_ptr(eps), _ptr(B), _ptr(wphi))
+
+    def two_level_ali_step(self, tau, q, S, eps, B, wphi, max_rel, active=None, Itop=None,
+                           Ibot=None):
+        """pprt_two_level_ali_step: one formal solution + OS update, S in place."""
+        import torch
+        fin = self.fs_in(tau, q, None, None, None, Itop, Ibot)
+        at = self.two_level(eps, B, wphi)
+        self._want(S, (self.rows,), torch.float64, "S")
+        self._want(max_rel, (self.nb,), torch.float64, "max_rel")
+        if active is not None:
+            self._want(active, (self.nb,), torch.int32, "active")
+        self.ctx._check(self.lib.pprt_two_level_ali_step(
+            self.h, C.byref(fin), C.byref(at), _ptr(S), _ptr(max_rel), _ptr(active),
+            _ptr(self.workspace())), "two_level_ali_step")
+
+    def two_level_moments(self, tau, q, S, eps, B, wphi, active=None, Itop=None, Ibot=None):
+        """pprt_two_level_moments: the formal-solution half of an ALI step."""
+        import torch
+        fin = self.fs_in(tau, q, None, None, None, Itop, Ibot)
+        at = self.two_level(eps, B, wphi)
+        self._want(S, (self.rows,), torch.float64, "S")
+        self.ctx._check(self.lib.pprt_two_level_moments(
+            self.h, C.byref(fin), C.byref(at), _ptr(S), _ptr(active), _ptr(self.workspace())),
+            "two_level_moments")
+
+    def two_level_update(self, S, eps, B, wphi, max_rel, active=None):
+        """pprt_two_level_update: the float64 update half of an ALI step."""
+        import torch
+        at = self.two_level(eps, B, wphi)
+        self._want(S, (self.rows,), torch.float64, "S")
+        self._want(max_rel, (self.nb,), torch.float64, "max_rel")
+        self.ctx._check(self.lib.pprt_two_level_update(
+            self.h, C.byref(at), _ptr(S), _ptr(max_rel), _ptr(active), _ptr(self.workspace())),
+            "two_level_update")
+
+    def two_level_ali(self, tau, q, S, eps, B, wphi, tol=1e-8, max_iter=20000,
+                      iters_per_sync=64, use_graph=False, iters=None, Itop=None, Ibot=None,
+                      raise_not_converged=True):
+        """pprt_two_level_ali: iterate to convergence; returns the report dict."""
+        import torch
+        fin = self.fs_in(tau, q, None, None, None, Itop, Ibot)
+        at = self.two_level(eps, B, wphi)
+        self._want(S, (self.rows,), torch.float64, "S")
+        if iters is not None:
+            self._want(iters, (self.nb,), torch.int32, "iters")
+        ctl = AliCtl(float(tol), int(max_iter), int(iters_per_sync), int(bool(use_graph)))
+        rep = AliReport()
+        st = self.lib.pprt_two_level_ali(self.h, C.byref(fin), C.byref(at), C.byref(ctl), _ptr(S),
+                                         _ptr(iters), C.byref(rep), _ptr(self.workspace()))
+        report = {"iterations": rep.iterations, "n_converged": rep.n_converged,
+                  "max_rel": rep.max_rel, "status": STATUS.get(st, st)}
+        if st == 6 and not raise_not_converged:
+            return report
+        self.ctx._check(st, "two_level_ali")
+        return report
+
+
+@dataclass
+class DeviceBatch:
+    """A TwoLevelBatch's arrays resident on the device in the plan's precision."""
+    tau: object
+    q: object
+    S: object
+    B: object
+    eps: object
+    wphi: object
+    Bbot: object
+    Bbot_prev: object
+
+
+def upload_two_level(batch, precision: int, device="cuda:0") -> DeviceBatch:
+    """Copy a workloads.TwoLevelBatch to the device (no arithmetic beyond
+    gathering the boundary values of B per atmosphere)."""
+    import torch
+    dt = torch.float64 if precision == FP64 else torch.float32
+    off = batch.off
+    last = off[1:] - 1
+    Bb = np.repeat(batch.B[last][:, None], batch.nf, axis=1)
+    Bp = np.repeat(batch.B[last - 1][:, None], batch.nf, axis=1)
+    t = lambda a, d: torch.as_tensor(np.ascontiguousarray(a), dtype=d, device=device)
+    return DeviceBatch(
+        tau=t(batch.tau, torch.float64), q=t(batch.q, dt), S=t(batch.S_trial, torch.float64),
+        B=t(batch.B, torch.float64), eps=t(batch.eps, torch.float64),
+        wphi=t(batch.wnu * batch.phi, dt), Bbot=t(Bb, dt), Bbot_prev=t(Bp, dt))

@@ -11,3 +11,38 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs the HIP path through the C ABI)")
     config.addinivalue_line("markers", "slow: oracle cases that take tens of seconds on the CPU")
+
+
+import numpy as np
+import pytest
+
+
+def rel_err(a, b, floor=1e-4):
+    """Per-array error metric used for every parity check:
+    max_i |a_i - b_i| / max(|b_i|, floor * max_j |b_j|).  Relative where the
+    reference is not tiny, absolute at a floor of 1e-4 of the array's scale
+    (e.g. I- at the top, where I_top = 0)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    if b.size == 0:
+        return 0.0
+    scale = np.max(np.abs(b))
+    if scale == 0.0:
+        return float(np.max(np.abs(a)))
+    den = np.maximum(np.abs(b), floor * scale)
+    return float(np.max(np.abs(a - b) / den))
+
+
+@pytest.fixture(scope="session")
+def gpu_ctx():
+    """libpprt context on cuda:0.  GPU tests fail (not skip) without a device:
+    they must never pass on a fallback."""
+    import torch
+    from paper_0903_1949_amd import pprt
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test selected but no HIP device is visible")
+    torch.cuda.set_device(0)
+    ctx = pprt.Context(0)
+    yield ctx
+    torch.cuda.synchronize()
+    ctx.close()

@@ -1,0 +1,92 @@
+"""GPU parity of the two-level operator-splitting step and of the converged
+ALI (pprt_two_level_ali_step / pprt_two_level_ali) with the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ali, formal
+from paper_0903_1949_amd import pprt
+from paper_0903_1949_amd import workloads as W
+from tests.conftest import rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_step(batch, S, mu, w):
+    off = batch.off
+    jms = np.zeros(batch.tau.shape[0])
+    olb = np.zeros_like(jms)
+    for b in range(batch.nb):
+        s = slice(off[b], off[b + 1])
+        nf = batch.nf
+        out = formal.formal_solution(batch.tau[s], batch.q[s], S[s], mu, w, lower="diffusion",
+                                     Bbot=np.full(nf, batch.B[s][-1]),
+                                     Bbot_prev=np.full(nf, batch.B[s][-2]))
+        Sg = np.broadcast_to(S[s][:, None], out["J"].shape)
+        jms[s], olb[s] = ali.profile_moments(out, S[s], Sg, batch.phi, batch.wnu)
+    return ali.batch_two_level_update(batch.nd, S, batch.B, batch.eps, jms, olb)
+
+
+@pytest.mark.parametrize("prec,tol", [(pprt.FP64, 1e-10), (pprt.FP32, 2e-5)])
+@pytest.mark.parametrize("nb,nf,na", [(3, 21, 4), (5, 300, 8), (2, 64, 16)])
+def test_ali_step_parity(gpu_ctx, prec, tol, nb, nf, na):
+    batch = W.two_level_batch(nb=nb, nd_lo=5, nd_hi=70, na=na, nf=nf, seed=nb * 7 + nf)
+    print(f"[case] step nb={nb} nf={nf} na={na} prec={prec}", flush=True)
+    plan = pprt.Plan(gpu_ctx, batch.nd, na, nf, precision=prec)
+    db = pprt.upload_two_level(batch, prec)
+    S0 = batch.S_trial.copy()
+    mx = torch.zeros(nb, dtype=torch.float64, device="cuda:0")
+    plan.two_level_ali_step(db.tau, db.q, db.S, db.eps, db.B, db.wphi, mx)
+    torch.cuda.synchronize()
+    S_ref, mx_ref = _oracle_step(batch, S0, plan.mu, plan.w)
+    dS_gpu = db.S.cpu().numpy() - S0
+    e_S = rel_err(db.S.cpu().numpy(), S_ref)
+    e_dS = rel_err(dS_gpu, S_ref - S0)
+    e_mx = rel_err(mx.cpu().numpy(), mx_ref)
+    print(f"  S {e_S:.2e}  dS {e_dS:.2e}  max_rel {e_mx:.2e}", flush=True)
+    assert e_S < tol and e_mx < max(tol, 1e-4 if prec == pprt.FP32 else tol)
+    if prec == pprt.FP64:
+        assert e_dS < 1e-9
+
+
+def test_ali_converged_c1_fp64(gpu_ctx):
+    """The single slab (nd 64, na 4, nf 21, eps 1e-4, tol 1e-8) converges in the
+    same number of iterations as the oracle, to the same S."""
+    c = W.single_two_level()
+    plan = pprt.Plan(gpu_ctx, c.nd, c.na, c.nf, precision=pprt.FP64)
+    db = pprt.upload_two_level(c, pprt.FP64)
+    db.S.copy_(db.B)
+    iters = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    rep = plan.two_level_ali(db.tau, db.q, db.S, db.eps, db.B, db.wphi, tol=1e-8,
+                             max_iter=20000, iters_per_sync=50, iters=iters)
+    ref = ali.two_level_ali(c.tau, c.q, c.phi, c.wnu, float(c.eps[0]), c.B, plan.mu, plan.w,
+                            tol=1e-8, max_iter=20000)
+    print("  gpu", rep, "oracle iterations", ref["iterations"], flush=True)
+    assert rep["n_converged"] == 1
+    assert int(iters.item()) == ref["iterations"]
+    assert rel_err(db.S.cpu().numpy(), ref["S"]) < 1e-10
+
+
+def test_ali_converged_batch_fp32(gpu_ctx):
+    """Smallest- and largest-eps atmospheres of the seeded batch, converged in
+    FP32 sweeps with the FP64 update, against the oracle's converged S."""
+    full = W.two_level_batch(seed=3, nf=256)
+    idx = list(np.argsort(full.eps)[:2]) + list(np.argsort(full.eps)[-2:])
+    batch = full.subset(idx)
+    plan = pprt.Plan(gpu_ctx, batch.nd, batch.na, batch.nf, precision=pprt.FP32)
+    db = pprt.upload_two_level(batch, pprt.FP32)
+    db.S.copy_(db.B)
+    iters = torch.zeros(batch.nb, dtype=torch.int32, device="cuda:0")
+    rep = plan.two_level_ali(db.tau, db.q, db.S, db.eps, db.B, db.wphi, tol=1e-6,
+                             max_iter=20000, iters_per_sync=100, iters=iters)
+    print("  gpu", rep, iters.cpu().numpy(), flush=True)
+    off = batch.off
+    for b in range(batch.nb):
+        s = slice(off[b], off[b + 1])
+        ref = ali.two_level_ali(batch.tau[s], batch.q[s], batch.phi, batch.wnu, float(batch.eps[b]),
+                                batch.B[s], plan.mu, plan.w, tol=1e-6, max_iter=20000)
+        e = rel_err(db.S[s].cpu().numpy(), ref["S"])
+        print(f"  b={b} eps={batch.eps[b]:.2e} it gpu={int(iters[b])} oracle={ref['iterations']} S err={e:.2e}",
+              flush=True)
+        assert abs(int(iters[b]) - ref["iterations"]) <= max(3, ref["iterations"] // 50)
+        assert e < 1e-4

@@ -1,0 +1,133 @@
+"""GPU parity of the omega = 0 formal solution (pprt_formal_solution) with
+the FP64 oracle, element by element, on seeded ragged batches: FP64 within
+1e-10 and FP32 within 1e-5 in the per-array metric of conftest.rel_err."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import formal
+from paper_0903_1949_amd import pprt
+from paper_0903_1949_amd import workloads as W
+from tests.conftest import rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL = {pprt.FP64: 1e-10, pprt.FP32: 1e-5}
+KEYS = ["J", "JmS", "lstar", "lstar_c", "Iplus", "Iminus", "H"]
+
+
+def _random_batch(nds, nf, na, seed, bc):
+    rng = np.random.default_rng(seed)
+    taus, qs, Ss = [], [], []
+    for nd in nds:
+        tau, q, S, _, _ = W.random_slab(nd, nf, seed=int(rng.integers(1 << 30)),
+                                        tau_lo=10 ** rng.uniform(-5, -2), tau_hi=10 ** rng.uniform(0, 4))
+        taus.append(tau); qs.append(q); Ss.append(S)
+    nb = len(nds)
+    Bb = rng.uniform(0.5, 1.5, size=(nb, nf))
+    Bp = rng.uniform(0.5, 1.5, size=(nb, nf))
+    Itop = rng.uniform(0.0, 0.3, size=(nb, nf, na))
+    Ibot = rng.uniform(0.5, 1.5, size=(nb, nf, na)) if bc == pprt.BC_GIVEN else None
+    return np.concatenate(taus), np.concatenate(qs), np.concatenate(Ss), Bb, Bp, Itop, Ibot
+
+
+def _oracle(nds, tau, q, S, Bb, Bp, Itop, Ibot, mu, w, bc):
+    off = np.concatenate([[0], np.cumsum(nds)])
+    outs = []
+    for b in range(len(nds)):
+        s = slice(off[b], off[b + 1])
+        kw = dict(lower="diffusion", Bbot=Bb[b], Bbot_prev=Bp[b]) if bc == pprt.BC_DIFFUSION \
+            else dict(lower="given", Ibot=Ibot[b])
+        outs.append(formal.formal_solution(tau[s], q[s], S[s], mu, w, Itop=Itop[b], **kw))
+    ref = {k: np.concatenate([o[k] for o in outs]) for k in KEYS}
+    ref["Iemerg"] = np.stack([o["Iemerg"] for o in outs])
+    return ref
+
+
+def _run(ctx, nds, nf, na, prec, bc, seed, wpb=0):
+    tau, q, S, Bb, Bp, Itop, Ibot = _random_batch(nds, nf, na, seed, bc)
+    print(f"[case] nds={list(nds)[:6]} nf={nf} na={na} prec={prec} bc={bc} seed={seed} wpb={wpb}",
+          flush=True)
+    plan = pprt.Plan(ctx, nds, na, nf, precision=prec, lower_bc=bc, outputs=pprt.OUT_ALL,
+                     waves_per_block=wpb)
+    dt = plan.dtype
+    dev = lambda a, d=dt: torch.as_tensor(np.ascontiguousarray(a), dtype=d, device="cuda:0")
+    out = plan.formal_solution(dev(tau, torch.float64), dev(q), dev(S), Bbot=dev(Bb),
+                               Bbot_prev=dev(Bp), Itop=dev(Itop),
+                               Ibot=None if Ibot is None else dev(Ibot))
+    torch.cuda.synchronize()
+    ref = _oracle(nds, tau, q, S, Bb, Bp, Itop, Ibot, plan.mu, plan.w, bc)
+    errs = {k: rel_err(out[k].double().cpu().numpy(), ref[k]) for k in KEYS + ["Iemerg"]}
+    print("  errors:", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    return errs
+
+
+@pytest.mark.parametrize("prec", [pprt.FP64, pprt.FP32])
+@pytest.mark.parametrize("nds,nf,na", [
+    ([2], 1, 1), ([3, 2], 3, 2), ([5], 1, 3), ([16, 7, 2], 65, 4),
+    ([40, 17], 130, 8), ([9], 300, 16), ([12], 7, 5), ([6, 30], 64, 32),
+])
+def test_formal_solution_parity_diffusion(gpu_ctx, nds, nf, na, prec):
+    errs = _run(gpu_ctx, nds, nf, na, prec, pprt.BC_DIFFUSION, seed=sum(nds) + nf + na)
+    for k, e in errs.items():
+        assert e < TOL[prec], (k, e)
+
+
+@pytest.mark.parametrize("prec", [pprt.FP64, pprt.FP32])
+def test_formal_solution_parity_given_lower_boundary(gpu_ctx, prec):
+    errs = _run(gpu_ctx, [11, 4, 23], 70, 4, prec, pprt.BC_GIVEN, seed=3)
+    for k, e in errs.items():
+        assert e < TOL[prec], (k, e)
+
+
+@pytest.mark.parametrize("wpb", [1, 2, 4, 8])
+def test_block_shapes_agree(gpu_ctx, wpb):
+    errs = _run(gpu_ctx, [20, 33], 600, 8, pprt.FP32, pprt.BC_DIFFUSION, seed=9, wpb=wpb)
+    for k, e in errs.items():
+        assert e < TOL[pprt.FP32], (k, e)
+
+
+def test_constant_source_gives_exact_zero_difference(gpu_ctx):
+    """Difference form: with S = B = const and no incident light at the top,
+    D+ = 0 exactly, so J - S equals -1/2 sum w I-... and I+ = S to the last bit."""
+    nds, nf, na = [50], 256, 8
+    tau = W.log_tau(50, 1e-4, 1e4)
+    q = np.random.default_rng(1).lognormal(0, 0.5, size=(50, nf))
+    plan = pprt.Plan(gpu_ctx, nds, na, nf, precision=pprt.FP32, outputs=pprt.OUT_ALL)
+    d = lambda a, t=torch.float32: torch.as_tensor(a, dtype=t, device="cuda:0")
+    out = plan.formal_solution(d(tau, torch.float64), d(q), d(np.full((50, nf), 0.75)),
+                               Bbot=d(np.full((1, nf), 0.75)), Bbot_prev=d(np.full((1, nf), 0.75)))
+    torch.cuda.synchronize()
+    assert torch.all(out["Iplus"] == 0.75)
+    # deep nodes: both hemispheres equal S exactly
+    assert torch.all(out["JmS"][-5:].abs() < 1e-30)
+
+
+def test_c3a_full_size_sampled(gpu_ctx):
+    """The 512-atmosphere batch (nd 48..256, na 8, nf 1024) in one FP32 launch,
+    checked on sampled atmospheres against the oracle."""
+    batch = W.two_level_batch(seed=3)
+    plan = pprt.Plan(gpu_ctx, batch.nd, batch.na, batch.nf, precision=pprt.FP32,
+                     outputs=pprt.OUT_JMS | pprt.OUT_LSTAR_C | pprt.OUT_IEMERG | pprt.OUT_H)
+    db = pprt.upload_two_level(batch, pprt.FP32)
+    S = np.repeat(batch.S_trial[:, None], batch.nf, axis=1)
+    out = plan.formal_solution(db.tau, db.q, torch.as_tensor(S, dtype=torch.float32, device="cuda:0"),
+                               Bbot=db.Bbot, Bbot_prev=db.Bbot_prev)
+    torch.cuda.synchronize()
+    off = batch.off
+    last = off[1:] - 1
+    pick = [int(np.argmin(batch.nd)), int(np.argmax(batch.nd)), 0, 511,
+            int(np.argmin(batch.eps)), int(np.argmax(batch.eps))]
+    for b in pick:
+        s = slice(off[b], off[b + 1])
+        ref = formal.formal_solution(batch.tau[s], batch.q[s], batch.S_trial[s], plan.mu, plan.w,
+                                     lower="diffusion", Bbot=np.full(batch.nf, batch.B[last[b]]),
+                                     Bbot_prev=np.full(batch.nf, batch.B[last[b] - 1]))
+        for k in ("JmS", "lstar_c", "H"):
+            e = rel_err(out[k][s].double().cpu().numpy(), ref[k])
+            print(f"  b={b} nd={batch.nd[b]} {k}: {e:.2e}", flush=True)
+            assert e < 1e-5, (b, k, e)
+        e = rel_err(out["Iemerg"][b].double().cpu().numpy(), ref["Iemerg"])
+        assert e < 1e-5, (b, "Iemerg", e)
