@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=12, help="atmospheres in the CPU sample")
+    ap.add_argument("--cpu-sample", type=int, default=48, help="atmospheres in the CPU sample")
     ap.add_argument("--waves-per-block", type=int, default=0)
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_fs_profile_c3a.json"))
     return ap.parse_args()
@@ -204,7 +204,7 @@ def main():
                                "eps 1e-6..1e-1, seed 3 (one ALI step per step)",
                    "nbatch": batch.nb, "rows": int(batch.nd.sum()), "na": batch.na,
                    "nf": batch.nf, "points_per_step": pts, "seed": 3,
-                   "waves_per_block": plan.ng and args.waves_per_block},
+                   "waves_per_block": args.waves_per_block or "auto"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fp64_plain": fp64,

@@ -87,9 +87,36 @@ __device__ __forceinline__ double wave_sum(double v) {
   return (readlane(v, 0) + readlane(v, 16)) + (readlane(v, 32) + readlane(v, 48));
 }
 
+// ---- plain-form weights alpha = 1 - psi and gamma = psi - e ---------------
+// Below D = 1/8 both are summed from their series (the closed forms cancel):
+//   alpha = sum_{n>=1} (-1)^(n+1) D^n/(n+1)!,  gamma = sum_{n>=1} (-1)^(n+1) n D^n/(n+1)!.
+__device__ __forceinline__ void layer_ag(float dt, float rmu, float e, float ps, float& al,
+                                         float& ga) {
+  const float D = dt * rmu;
+  const bool sm = D < 0.125f;
+  const float as = D * fmaf(-D, fmaf(-D, fmaf(-D, fmaf(-D, 1.f / 720.f, 1.f / 120.f), 1.f / 24.f),
+                                     1.f / 6.f), 0.5f);
+  const float gs = D * fmaf(-D, fmaf(-D, fmaf(-D, fmaf(-D, fmaf(-D, 1.f / 840.f, 1.f / 144.f),
+                                                       1.f / 30.f), 1.f / 8.f), 1.f / 3.f), 0.5f);
+  al = sm ? as : 1.f - ps;
+  ga = sm ? gs : ps - e;
+}
+__device__ __forceinline__ void layer_ag(double /*dt*/, double /*rmu*/, double e, double ps,
+                                         double& al, double& ga) {
+  al = 1.0 - ps;     // absolute error ~1e-16, below every use of alpha
+  ga = ps - e;
+}
+
 // ---------------------------------------------------------------------------
-// Full-output formal solution: up-going sweep first (its partial moments are
-// parked in the output arrays), then the down-going sweep completes them.
+// Full-output formal solution.  Two recurrences run side by side per angle:
+// the difference form D = I - S (for J - S and H, which are small differences
+// deep in the atmosphere) and the plain form
+//     I+(d) = e I+(d+1) + alpha S(d) + gamma S(d+1)
+// (for I+-, J, the emergent intensity and Lambda*, which are small where the
+// medium is optically thin).  Each form is accurate where the other loses
+// digits; both are the same linear short-characteristic update.  The
+// up-going sweep runs first and parks its hemisphere's moments in the output
+// arrays; the down-going sweep completes them.
 template <typename T, int NA>
 __global__ __launch_bounds__(512) void k_fs_full(FsFullArgs<T> a, Angles<T> ang) {
   const Item it = a.items[blockIdx.x];
@@ -100,13 +127,16 @@ __global__ __launch_bounds__(512) void k_fs_full(FsFullArgs<T> a, Angles<T> ang)
   if (k >= nf) return;
   const int64_t row0 = a.off[b];
   const uint32_t o = a.outputs;
-  T* jacc = (o & PPRT_OUT_JMS) ? a.JmS : ((o & PPRT_OUT_J) ? a.J : nullptr);
-  T* lacc = (o & PPRT_OUT_LSTAR_C) ? a.lstar_c : ((o & PPRT_OUT_LSTAR) ? a.lstar : nullptr);
-  T* hacc = (o & PPRT_OUT_H) ? a.H : nullptr;
+  // parking places for the up-going hemisphere's moments
+  T* pj = (o & PPRT_OUT_JMS) ? a.JmS : nullptr;           // 1/2 sum w D+
+  T* pJ = (o & PPRT_OUT_J) ? a.J : nullptr;               // 1/2 sum w I+
+  T* pc = (o & PPRT_OUT_LSTAR_C) ? a.lstar_c : nullptr;   // 1/2 sum w psi
+  T* pa = (o & PPRT_OUT_LSTAR) ? a.lstar : nullptr;       // 1/2 sum w alpha
+  T* ph = (o & PPRT_OUT_H) ? a.H : nullptr;               // 1/2 sum w mu D+
   T* Ip = (o & PPRT_OUT_IPLUS) ? a.Iplus : nullptr;
   T* Im = (o & PPRT_OUT_IMINUS) ? a.Iminus : nullptr;
 
-  T D[NA];
+  T D[NA], I[NA];
   // ---- up-going sweep: node nd-1 (lower boundary) -> node 0
   int64_t r = row0 + nd - 1;
   T q1 = a.q[r * nf + k];
@@ -121,30 +151,38 @@ __global__ __launch_bounds__(512) void k_fs_full(FsFullArgs<T> a, Angles<T> ang)
       const T g = (Bb - Bp) / dt;
       const T base = Bb - S1;
 #pragma unroll
-      for (int i = 0; i < NA; ++i) D[i] = base + ang.mu[i] * g;
+      for (int i = 0; i < NA; ++i) {
+        D[i] = base + ang.mu[i] * g;
+        I[i] = Bb + ang.mu[i] * g;
+      }
     } else {
 #pragma unroll
-      for (int i = 0; i < NA; ++i)
-        D[i] = (a.Ibot ? a.Ibot[((int64_t)b * nf + k) * NA + i] : T(0)) - S1;
+      for (int i = 0; i < NA; ++i) {
+        I[i] = a.Ibot ? a.Ibot[((int64_t)b * nf + k) * NA + i] : T(0);
+        D[i] = I[i] - S1;
+      }
     }
   }
-  auto emit_up = [&](int64_t rr, T S, T lsum) {
-    T js = T(0), hs = T(0);
+  auto emit_up = [&](int64_t rr, T csum, T asum) {
+    T js = T(0), hs = T(0), Js = T(0);
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
       js += ang.hw[i] * D[i];
       hs += ang.hwmu[i] * D[i];
+      Js += ang.hw[i] * I[i];
     }
     const int64_t x = rr * nf + k;
-    if (jacc) jacc[x] = js;
-    if (lacc) lacc[x] = lsum;
-    if (hacc) hacc[x] = hs;
+    if (pj) pj[x] = js;
+    if (pJ) pJ[x] = Js;
+    if (pc) pc[x] = csum;
+    if (pa) pa[x] = asum;
+    if (ph) ph[x] = hs;
     if (Ip) {
 #pragma unroll
-      for (int i = 0; i < NA; ++i) Ip[x * NA + i] = D[i] + S;
+      for (int i = 0; i < NA; ++i) Ip[x * NA + i] = I[i];
     }
   };
-  emit_up(r, S1, ang.hwsum);
+  emit_up(r, ang.hwsum, T(0));
   for (int d = nd - 2; d >= 0; --d) {
     r = row0 + d;
     const T q0 = a.q[r * nf + k];
@@ -153,55 +191,54 @@ __global__ __launch_bounds__(512) void k_fs_full(FsFullArgs<T> a, Angles<T> ang)
     const T dt = T(0.5) * (q0 + q1) * T(t1 - t0);
     const T inv = recip(dt);
     const T dS = S1 - S0;
-    T ls = T(0);
+    T cs = T(0), as = T(0);
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
-      T e, ps;
+      T e, ps, al, ga;
       layer_ep(dt, inv, ang.c[i], ang.rmu[i], ang.mu[i], e, ps);
+      layer_ag(dt, ang.rmu[i], e, ps, al, ga);
       D[i] = e * D[i] + ps * dS;
-      ls += ang.hw[i] * ps;
+      I[i] = e * I[i] + al * S0 + ga * S1;
+      cs += ang.hw[i] * ps;
+      as += ang.hw[i] * al;
     }
-    emit_up(r, S0, ls);
+    emit_up(r, cs, as);
     q1 = q0; S1 = S0; t1 = t0;
   }
   if (o & PPRT_OUT_IEMERG) {
 #pragma unroll
-    for (int i = 0; i < NA; ++i) a.Iemerg[((int64_t)b * nf + k) * NA + i] = D[i] + S1;
+    for (int i = 0; i < NA; ++i) a.Iemerg[((int64_t)b * nf + k) * NA + i] = I[i];
   }
 
   // ---- down-going sweep: node 0 (upper boundary) -> node nd-1
   // q1, S1, t1 now hold node 0.
-  r = row0;
 #pragma unroll
-  for (int i = 0; i < NA; ++i)
-    D[i] = (a.Itop ? a.Itop[((int64_t)b * nf + k) * NA + i] : T(0)) - S1;
-  auto emit_down = [&](int64_t rr, T S, T lsum) {
-    T js = T(0), hs = T(0);
+  for (int i = 0; i < NA; ++i) {
+    I[i] = a.Itop ? a.Itop[((int64_t)b * nf + k) * NA + i] : T(0);
+    D[i] = I[i] - S1;
+  }
+  auto emit_down = [&](int64_t rr, T csum, T asum) {
+    T js = T(0), hs = T(0), Js = T(0);
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
       js += ang.hw[i] * D[i];
       hs += ang.hwmu[i] * D[i];
+      Js += ang.hw[i] * I[i];
     }
     const int64_t x = rr * nf + k;
-    if (jacc) {
-      js += jacc[x];
-      if (o & PPRT_OUT_JMS) a.JmS[x] = js;
-      if (o & PPRT_OUT_J) a.J[x] = js + S;
-    }
-    if (lacc) {
-      const T lc = lsum + lacc[x];
-      if (o & PPRT_OUT_LSTAR_C) a.lstar_c[x] = lc;
-      if (o & PPRT_OUT_LSTAR) a.lstar[x] = T(1) - lc;
-    }
-    if (hacc) hacc[x] = hacc[x] - hs;
+    if (pj) pj[x] = pj[x] + js;
+    if (pJ) pJ[x] = pJ[x] + Js;
+    if (pc) pc[x] = pc[x] + csum;
+    if (pa) pa[x] = pa[x] + asum;
+    if (ph) ph[x] = ph[x] - hs;
     if (Im) {
 #pragma unroll
-      for (int i = 0; i < NA; ++i) Im[x * NA + i] = D[i] + S;
+      for (int i = 0; i < NA; ++i) Im[x * NA + i] = I[i];
     }
   };
   T q0 = q1, S0 = S1;
   double t0 = t1;
-  emit_down(r, S0, ang.hwsum);
+  emit_down(row0, ang.hwsum, T(0));
   for (int d = 1; d < nd; ++d) {
     r = row0 + d;
     q1 = a.q[r * nf + k];
@@ -210,16 +247,18 @@ __global__ __launch_bounds__(512) void k_fs_full(FsFullArgs<T> a, Angles<T> ang)
     const T dt = T(0.5) * (q0 + q1) * T(t1 - t0);
     const T inv = recip(dt);
     const T dS = S0 - S1;
-    T ls = T(0);
+    T cs = T(0), as = T(0);
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
-      T e, ps;
+      T e, ps, al, ga;
       layer_ep(dt, inv, ang.c[i], ang.rmu[i], ang.mu[i], e, ps);
+      layer_ag(dt, ang.rmu[i], e, ps, al, ga);
       D[i] = e * D[i] + ps * dS;
-      ls += ang.hw[i] * ps;
+      I[i] = e * I[i] + al * S1 + ga * S0;
+      cs += ang.hw[i] * ps;
+      as += ang.hw[i] * al;
     }
-    // the lower boundary fixes I+ at the last node: its hemisphere adds hwsum there
-    emit_down(r, S1, ls);
+    emit_down(r, cs, as);
     q0 = q1; S0 = S1; t0 = t1;
   }
 }
@@ -230,13 +269,14 @@ __global__ __launch_bounds__(512) void k_fs_full(FsFullArgs<T> a, Angles<T> ang)
 // so J - S and 1 - Lambda* enter only through their profile-weighted sums,
 // which are independent between the two hemispheres.  Per node the wave sums
 // wphi_k * 1/2 sum_i w_i D_i and wphi_k * 1/2 sum_i w_i psi_i (float, fixed
-// order), parks them in LDS, and every CH nodes the block adds its waves in
-// float64 and writes part[row][g][dir][0..1].
+// order), parks them in LDS (in T), and every CH nodes the block adds its
+// waves in float64 and writes part[row][g][dir][0..1].
 constexpr int CH = 64;
 
 template <typename T, int NA>
 __global__ __launch_bounds__(512) void k_fs_profile(FsProfileArgs<T> a, Angles<T> ang) {
-  extern __shared__ float lds[];           // [CH][nwave][2]
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* lds = reinterpret_cast<T*>(lds_raw);  // [CH][nwave][2]; T keeps FP64 sums exact
   const Item it = a.items[blockIdx.x];
   const int b = it.b;
   if (a.active != nullptr && a.active[b] == 0) return;   // uniform over the block
@@ -302,8 +342,8 @@ __global__ __launch_bounds__(512) void k_fs_profile(FsProfileArgs<T> a, Angles<T
     const T lv = wave_sum(wp * lsum);
     if (lane == 0) {
       const int s = j % CH;
-      lds[(s * nwave + wave) * 2 + 0] = (float)jv;
-      lds[(s * nwave + wave) * 2 + 1] = (float)lv;
+      lds[(s * nwave + wave) * 2 + 0] = jv;
+      lds[(s * nwave + wave) * 2 + 1] = lv;
     }
   };
   auto node_sum = [&]() {
@@ -349,7 +389,7 @@ hipError_t launch_full_t(int wpb, int nitems, hipStream_t s, const void* args, c
 
 template <typename T, int NA>
 hipError_t launch_profile_t(int wpb, int nitems, hipStream_t s, const void* args, const void* ang) {
-  const size_t lds = (size_t)CH * wpb * 2 * sizeof(float);
+  const size_t lds = (size_t)CH * wpb * 2 * sizeof(T);
   hipLaunchKernelGGL((k_fs_profile<T, NA>), dim3(nitems), dim3(64 * wpb), lds, s,
                      *static_cast<const FsProfileArgs<T>*>(args),
                      *static_cast<const Angles<T>*>(ang));
