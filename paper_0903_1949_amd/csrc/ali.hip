@@ -5,8 +5,8 @@
 // local-operator update of Olson, Auer & Buchler (1986) reads, per node,
 //     S_new = S + [(1-eps)(Jbar - S) + eps (B - S)] / [eps + (1-eps)(1 - Lbar*)]
 // with Jbar - S and 1 - Lbar* taken from the profile-weighted partial sums
-// the formal-solution sweep left in `part` (both hemispheres, every frequency
-// group; added here in float64 in a fixed order).  The block also forms the
+// the formal-solution sweep left in `part` (one per wave: both hemispheres,
+// every 64-frequency tile; added here in float64 in a fixed order).  The block also forms the
 // atmosphere's maximum relative change max_d |S_new - S| / |S_new|, the
 // stopping quantity of Sect. 3.2.1 applied to S, and retires the atmosphere
 // once it falls below the tolerance.
@@ -22,15 +22,23 @@ __global__ __launch_bounds__(256) void k_ali_update(AliUpdateArgs a) {
   const int64_t r0 = a.off[b];
   const int64_t r1 = a.off[b + 1];
   const double eps = a.eps[b];
-  const int stride = a.ng * 4;
+  const int stride = a.nw * 4;
   double mx = 0.0;
   bool bad = false;
   for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
-    const double* p = a.part + r * stride;
     double jms = 0.0, olb = 0.0;
-    for (int g = 0; g < a.ng; ++g) {
-      jms += p[g * 4 + 0] + p[g * 4 + 2];     // up + down hemispheres
-      olb += p[g * 4 + 1] + p[g * 4 + 3];
+    if (a.part_fp64) {
+      const double* p = static_cast<const double*>(a.part) + r * stride;
+      for (int g = 0; g < a.nw; ++g) {
+        jms += p[g * 4 + 0] + p[g * 4 + 2];     // up + down hemispheres
+        olb += p[g * 4 + 1] + p[g * 4 + 3];
+      }
+    } else {
+      const float* p = static_cast<const float*>(a.part) + r * stride;
+      for (int g = 0; g < a.nw; ++g) {
+        jms += (double)p[g * 4 + 0] + (double)p[g * 4 + 2];
+        olb += (double)p[g * 4 + 1] + (double)p[g * 4 + 3];
+      }
     }
     const double S = a.S[r];
     const double dS = ((1.0 - eps) * jms + eps * (a.B[r] - S)) / (eps + (1.0 - eps) * olb);

@@ -23,25 +23,74 @@
 namespace pprt {
 namespace {
 
-// ---- per-layer transmission factor e and psi = (1-e)/Delta ---------------
-__device__ __forceinline__ void layer_ep(float dt, float inv_dt, float c, float rmu, float mu,
-                                         float& e, float& ps) {
-  const float x = dt * c;                      // Delta * log2(e)
-  e = __builtin_amdgcn_exp2f(-x);              // v_exp_f32
-  const float D = dt * rmu;                    // Delta
-  // psi = sum_{n>=0} (-D)^n/(n+1)! to D^5 below D = 1/8 (truncation < 1e-9);
-  // above it the closed form has no harmful cancellation (rel. err < 1e-6).
-  const float ser = fmaf(D, fmaf(D, fmaf(D, fmaf(D, fmaf(D, -1.f / 720.f, 1.f / 120.f),
-                                                   -1.f / 24.f), 1.f / 6.f), -0.5f), 1.f);
-  const float ex = (1.f - e) * (mu * inv_dt);
-  ps = (D < 0.125f) ? ser : ex;
+// ---- per-layer weights of one angle --------------------------------------
+// e = exp(-Delta), psi = (1-e)/Delta, and for the plain form
+// alpha = 1 - psi, gamma = psi - e, with Delta = dtau_k / mu_i.
+//
+// FP32: optically thin layers (Delta < 1/4) take the series
+//   psi   = sum_{n>=0} (-Delta)^n/(n+1)!           (to Delta^5, truncation < 5e-8)
+//   alpha = sum_{n>=1} (-1)^(n+1) Delta^n/(n+1)!   (to Delta^6)
+// and e = 1 - Delta psi, gamma = Delta psi - alpha (both exact identities), so
+// they need no exponential at all; thicker layers take the closed forms with
+// v_exp_f32, psi = m - e m where m = mu_i / dtau_k.  The choice is made per
+// wave: when all 64 lanes agree only one branch executes (over 90% of the
+// (wave, layer, angle) triples in line-formation atmospheres), otherwise both
+// run and each lane selects its own.
+template <bool AG>
+__device__ __forceinline__ void layer_w(float dt, float inv_dt, float c, float rmu, float mu,
+                                        float& e, float& ps, float& al, float& ga) {
+  const float D = dt * rmu;
+  const bool thin = D < 0.25f;
+  const unsigned long long act = __ballot(1);
+  const unsigned long long tb = __ballot(thin);
+  auto thin_w = [&](float& e_, float& ps_, float& al_, float& ga_) {
+    ps_ = fmaf(D, fmaf(D, fmaf(D, fmaf(D, fmaf(D, -1.f / 720.f, 1.f / 120.f), -1.f / 24.f),
+                               1.f / 6.f), -0.5f), 1.f);
+    e_ = fmaf(-D, ps_, 1.f);
+    if (AG) {
+      al_ = D * fmaf(-D, fmaf(-D, fmaf(-D, fmaf(-D, fmaf(-D, 1.f / 5040.f, 1.f / 720.f),
+                                                 1.f / 120.f), 1.f / 24.f), 1.f / 6.f), 0.5f);
+      ga_ = fmaf(D, ps_, -al_);
+    }
+  };
+  auto thick_w = [&](float& e_, float& ps_, float& al_, float& ga_) {
+    e_ = __builtin_amdgcn_exp2f(-(dt * c));      // v_exp_f32; c = log2(e)/mu
+    const float m = mu * inv_dt;
+    ps_ = fmaf(-e_, m, m);
+    if (AG) {
+      al_ = 1.f - ps_;
+      ga_ = ps_ - e_;
+    }
+  };
+  if (tb == act) {
+    thin_w(e, ps, al, ga);
+  } else if (tb == 0) {
+    thick_w(e, ps, al, ga);
+  } else {
+    float e1, p1, a1 = 0.f, g1 = 0.f, e2, p2, a2 = 0.f, g2 = 0.f;
+    thin_w(e1, p1, a1, g1);
+    thick_w(e2, p2, a2, g2);
+    e = thin ? e1 : e2;
+    ps = thin ? p1 : p2;
+    if (AG) {
+      al = thin ? a1 : a2;
+      ga = thin ? g1 : g2;
+    }
+  }
 }
 
-__device__ __forceinline__ void layer_ep(double dt, double inv_dt, double /*c*/, double rmu,
-                                         double mu, double& e, double& ps) {
+// FP64: closed forms throughout (expm1 keeps psi accurate for any Delta > 0;
+// alpha and gamma then carry absolute errors ~1e-16, below every use).
+template <bool AG>
+__device__ __forceinline__ void layer_w(double dt, double inv_dt, double /*c*/, double rmu,
+                                        double mu, double& e, double& ps, double& al, double& ga) {
   const double D = dt * rmu;
   e = exp(-D);
   ps = -expm1(-D) * (mu * inv_dt);
+  if (AG) {
+    al = 1.0 - ps;
+    ga = ps - e;
+  }
 }
 
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -87,25 +136,11 @@ __device__ __forceinline__ double wave_sum(double v) {
   return (readlane(v, 0) + readlane(v, 16)) + (readlane(v, 32) + readlane(v, 48));
 }
 
-// ---- plain-form weights alpha = 1 - psi and gamma = psi - e ---------------
-// Below D = 1/8 both are summed from their series (the closed forms cancel):
-//   alpha = sum_{n>=1} (-1)^(n+1) D^n/(n+1)!,  gamma = sum_{n>=1} (-1)^(n+1) n D^n/(n+1)!.
-__device__ __forceinline__ void layer_ag(float dt, float rmu, float e, float ps, float& al,
-                                         float& ga) {
-  const float D = dt * rmu;
-  const bool sm = D < 0.125f;
-  const float as = D * fmaf(-D, fmaf(-D, fmaf(-D, fmaf(-D, 1.f / 720.f, 1.f / 120.f), 1.f / 24.f),
-                                     1.f / 6.f), 0.5f);
-  const float gs = D * fmaf(-D, fmaf(-D, fmaf(-D, fmaf(-D, fmaf(-D, 1.f / 840.f, 1.f / 144.f),
-                                                       1.f / 30.f), 1.f / 8.f), 1.f / 3.f), 0.5f);
-  al = sm ? as : 1.f - ps;
-  ga = sm ? gs : ps - e;
-}
-__device__ __forceinline__ void layer_ag(double /*dt*/, double /*rmu*/, double e, double ps,
-                                         double& al, double& ga) {
-  al = 1.0 - ps;     // absolute error ~1e-16, below every use of alpha
-  ga = ps - e;
-}
+// Quad-local swaps (lanes 4q..4q+3): partner 1 and partner 2.
+__device__ __forceinline__ float dpp_quad_swap1(float v) { return dpp_f<0xb1>(v); }
+__device__ __forceinline__ float dpp_quad_swap2(float v) { return dpp_f<0x4e>(v); }
+__device__ __forceinline__ double dpp_quad_swap1(double v) { return dpp_d<0xb1>(v); }
+__device__ __forceinline__ double dpp_quad_swap2(double v) { return dpp_d<0x4e>(v); }
 
 // ---------------------------------------------------------------------------
 // Full-output formal solution.  Two recurrences run side by side per angle:
@@ -195,8 +230,7 @@ __global__ __launch_bounds__(512) void k_fs_full(FsFullArgs<T> a, Angles<T> ang)
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
       T e, ps, al, ga;
-      layer_ep(dt, inv, ang.c[i], ang.rmu[i], ang.mu[i], e, ps);
-      layer_ag(dt, ang.rmu[i], e, ps, al, ga);
+      layer_w<true>(dt, inv, ang.c[i], ang.rmu[i], ang.mu[i], e, ps, al, ga);
       D[i] = e * D[i] + ps * dS;
       I[i] = e * I[i] + al * S0 + ga * S1;
       cs += ang.hw[i] * ps;
@@ -251,8 +285,7 @@ __global__ __launch_bounds__(512) void k_fs_full(FsFullArgs<T> a, Angles<T> ang)
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
       T e, ps, al, ga;
-      layer_ep(dt, inv, ang.c[i], ang.rmu[i], ang.mu[i], e, ps);
-      layer_ag(dt, ang.rmu[i], e, ps, al, ga);
+      layer_w<true>(dt, inv, ang.c[i], ang.rmu[i], ang.mu[i], e, ps, al, ga);
       D[i] = e * D[i] + ps * dS;
       I[i] = e * I[i] + al * S1 + ga * S0;
       cs += ang.hw[i] * ps;
@@ -264,46 +297,45 @@ __global__ __launch_bounds__(512) void k_fs_full(FsFullArgs<T> a, Angles<T> ang)
 }
 
 // ---------------------------------------------------------------------------
-// Profile-moment formal solution for the two-level ALI.  Each block runs ONE
-// sweep direction over one frequency group; the line source S_l is per node,
-// so J - S and 1 - Lambda* enter only through their profile-weighted sums,
-// which are independent between the two hemispheres.  Per node the wave sums
-// wphi_k * 1/2 sum_i w_i D_i and wphi_k * 1/2 sum_i w_i psi_i (float, fixed
-// order), parks them in LDS (in T), and every CH nodes the block adds its
-// waves in float64 and writes part[row][g][dir][0..1].
-constexpr int CH = 64;
+// Profile-moment formal solution for the two-level ALI.  The line source S_l
+// is one value per node, so J - S and 1 - Lambda* enter only through their
+// profile-weighted sums, and those are additive over hemispheres and over
+// frequencies.  Every wave therefore runs independently: ONE sweep direction
+// over 64 consecutive frequencies of one atmosphere, no barrier, no sharing.
+//
+// Per node each lane forms wphi_k * 1/2 sum_i w_i D_i and
+// wphi_k * 1/2 sum_i w_i psi_i and parks the pair in the wave's LDS slab
+// [CH nodes][2][64 lanes].  Every CH nodes the wave reduces the slab
+// transposed: lane l sums 16 contiguous entries of one (node, quantity)
+// (ds_read_b128), a quad DPP step adds the four parts, and one lane per
+// (node, quantity) writes part[row][wave][dir][q].  The per-node cost is one
+// ds_write2 instead of a 64-lane DPP tree.
+constexpr int CH = 8;
 
-template <typename T, int NA>
-__global__ __launch_bounds__(512) void k_fs_profile(FsProfileArgs<T> a, Angles<T> ang) {
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  T* lds = reinterpret_cast<T*>(lds_raw);  // [CH][nwave][2]; T keeps FP64 sums exact
-  const Item it = a.items[blockIdx.x];
+template <typename T, int NA, bool UP>
+__device__ __forceinline__ void profile_sweep(const FsProfileArgs<T>& a, const Angles<T>& ang,
+                                              const Item it, T* slab) {
   const int b = it.b;
-  if (a.active != nullptr && a.active[b] == 0) return;   // uniform over the block
   const int nd = it.nd;
   const int nf = a.nf;
-  const int nwave = (int)blockDim.x >> 6;
-  const int wave = (int)threadIdx.x >> 6;
-  const int lane = (int)threadIdx.x & 63;
-  const int k = it.g * (int)blockDim.x + (int)threadIdx.x;
-  const bool valid = k < nf;
-  const int kk = valid ? k : 0;             // clamped index: loads stay in bounds
+  const int lane = (int)(threadIdx.x & 63);
+  const int k = it.g * 64 + lane;
+  const int kk = k < nf ? k : nf - 1;         // clamped: loads stay in bounds
   const int64_t row0 = a.off[b];
-  const T wp = valid ? a.wphi[kk] : T(0);
-  const bool up = (it.dir == 0);
+  const T wp = k < nf ? a.wphi[kk] : T(0);
+  const T* __restrict__ qcol = a.q + kk;
 
   T D[NA];
-  int d = up ? nd - 1 : 0;
-  int64_t r = row0 + d;
-  T qn = a.q[r * nf + kk];
-  double Sn = a.S[r];
-  double tn = a.tau[r];
-  if (up) {
-    const T qa = a.q[(r - 1) * nf + kk];
-    const T dt = T(0.5) * (qa + qn) * T(tn - a.tau[r - 1]);
+  int d = UP ? nd - 1 : 0;
+  T qn = qcol[(row0 + d) * nf];
+  double Sn = a.S[row0 + d];
+  double tn = a.tau[row0 + d];
+  if (UP) {
+    const T qa = qcol[(row0 + d - 1) * nf];
+    const T dt = T(0.5) * (qa + qn) * T(tn - a.tau[row0 + d - 1]);
     if (a.lower_bc == PPRT_BC_DIFFUSION) {
-      const double Bb = a.B[r];
-      const double Bp = a.B[r - 1];
+      const double Bb = a.B[row0 + d];
+      const double Bp = a.B[row0 + d - 1];
       const T g = T(Bb - Bp) / dt;
       const T base = T(Bb - Sn);
 #pragma unroll
@@ -319,32 +351,38 @@ __global__ __launch_bounds__(512) void k_fs_profile(FsProfileArgs<T> a, Angles<T
       D[i] = (a.Itop ? a.Itop[((int64_t)b * nf + kk) * NA + i] : T(0)) - T(Sn);
   }
 
-  const int g = it.g;
-  const int dir = it.dir;
+  // slab reduction: lane -> (sigma = 2*slot + quantity, part p of 4)
+  const int sig = lane >> 2;
+  const int prt = lane & 3;
+  T* const out = a.part;
+  const int nw = a.nw;
   auto flush = [&](int j0, int count) {
-    __syncthreads();
-    for (int s = (int)threadIdx.x; s < count; s += (int)blockDim.x) {
-      const int j = j0 + s;
-      const int node = up ? nd - 1 - j : j;
-      double js = 0.0, ls = 0.0;
-      for (int w = 0; w < nwave; ++w) {
-        js += (double)lds[(s * nwave + w) * 2 + 0];
-        ls += (double)lds[(s * nwave + w) * 2 + 1];
-      }
-      double* p = a.part + (((row0 + node) * a.ng + g) * 2 + dir) * 2;
-      p[0] = js;
-      p[1] = ls;
+    // every lane of the wave has written its slots: order those LDS writes
+    // before the transposed reads (the wave's LDS operations execute in order)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const T* src = slab + sig * 64 + prt * 16;
+    T acc = T(0);
+#pragma unroll
+    for (int t = 0; t < 16; ++t) acc += src[t];
+    acc += dpp_quad_swap1(acc);
+    acc += dpp_quad_swap2(acc);
+    const int slot = sig >> 1;
+    if (prt == 0 && slot < count) {
+      const int j = j0 + slot;
+      const int node = UP ? nd - 1 - j : j;
+      out[(((row0 + node) * nw + it.g) * 2 + (UP ? 0 : 1)) * 2 + (sig & 1)] = acc;
     }
-    __syncthreads();
+    // the next chunk overwrites the slab: keep these reads before those writes
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   };
   auto park = [&](int j, T jsum, T lsum) {
-    const T jv = wave_sum(wp * jsum);
-    const T lv = wave_sum(wp * lsum);
-    if (lane == 0) {
-      const int s = j % CH;
-      lds[(s * nwave + wave) * 2 + 0] = jv;
-      lds[(s * nwave + wave) * 2 + 1] = lv;
-    }
+    const int slot = j % CH;
+    slab[(2 * slot + 0) * 64 + lane] = wp * jsum;
+    slab[(2 * slot + 1) * 64 + lane] = wp * lsum;
   };
   auto node_sum = [&]() {
     T js = T(0);
@@ -355,22 +393,34 @@ __global__ __launch_bounds__(512) void k_fs_profile(FsProfileArgs<T> a, Angles<T
 
   park(0, node_sum(), ang.hwsum);
   int j0 = 0;
+  // prefetch the next node of the sweep
+  int dn = UP ? nd - 2 : 1;
+  T qf = qcol[(row0 + dn) * nf];
+  double Sf = a.S[row0 + dn];
+  double tf = a.tau[row0 + dn];
   for (int j = 1; j < nd; ++j) {
-    if (j % CH == 0) { flush(j0, CH); j0 = j; }
-    d = up ? nd - 1 - j : j;
-    r = row0 + d;
-    const T qd = a.q[r * nf + kk];
-    const double Sd = a.S[r];
-    const double td = a.tau[r];
-    // layer between node d and its predecessor in sweep order
-    const T dt = T(0.5) * (qd + qn) * T(up ? (tn - td) : (td - tn));
+    if (j % CH == 0) {
+      flush(j0, CH);
+      j0 = j;
+    }
+    const T qd = qf;
+    const double Sd = Sf;
+    const double td = tf;
+    if (j + 1 < nd) {
+      dn = UP ? nd - 2 - j : j + 1;
+      qf = qcol[(row0 + dn) * nf];
+      Sf = a.S[row0 + dn];
+      tf = a.tau[row0 + dn];
+    }
+    // layer between this node and its predecessor in sweep order
+    const T dt = T(0.5) * (qd + qn) * T(UP ? (tn - td) : (td - tn));
     const T inv = recip(dt);
     const T dS = T(Sn - Sd);
     T ls = T(0);
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
-      T e, ps;
-      layer_ep(dt, inv, ang.c[i], ang.rmu[i], ang.mu[i], e, ps);
+      T e, ps, al, ga;
+      layer_w<false>(dt, inv, ang.c[i], ang.rmu[i], ang.mu[i], e, ps, al, ga);
       D[i] = e * D[i] + ps * dS;
       ls += ang.hw[i] * ps;
     }
@@ -378,6 +428,21 @@ __global__ __launch_bounds__(512) void k_fs_profile(FsProfileArgs<T> a, Angles<T
     qn = qd; Sn = Sd; tn = td;
   }
   flush(j0, nd - j0);
+}
+
+template <typename T, int NA>
+__global__ __launch_bounds__(512) void k_fs_profile(FsProfileArgs<T> a, Angles<T> ang) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int wave = (int)(threadIdx.x >> 6);
+  const int item = (int)blockIdx.x * (int)(blockDim.x >> 6) + wave;
+  if (item >= a.nitems) return;                       // whole wave
+  const Item it = a.items[item];
+  if (a.active != nullptr && a.active[it.b] == 0) return;   // whole wave
+  T* slab = reinterpret_cast<T*>(lds_raw) + (size_t)wave * (2 * CH * 64);
+  if (it.dir == 0)
+    profile_sweep<T, NA, true>(a, ang, it, slab);
+  else
+    profile_sweep<T, NA, false>(a, ang, it, slab);
 }
 
 template <typename T, int NA>
@@ -389,8 +454,9 @@ hipError_t launch_full_t(int wpb, int nitems, hipStream_t s, const void* args, c
 
 template <typename T, int NA>
 hipError_t launch_profile_t(int wpb, int nitems, hipStream_t s, const void* args, const void* ang) {
-  const size_t lds = (size_t)CH * wpb * 2 * sizeof(T);
-  hipLaunchKernelGGL((k_fs_profile<T, NA>), dim3(nitems), dim3(64 * wpb), lds, s,
+  const size_t lds = (size_t)wpb * 2 * CH * 64 * sizeof(T);
+  const int nblocks = (nitems + wpb - 1) / wpb;
+  hipLaunchKernelGGL((k_fs_profile<T, NA>), dim3(nblocks), dim3(64 * wpb), lds, s,
                      *static_cast<const FsProfileArgs<T>*>(args),
                      *static_cast<const Angles<T>*>(ang));
   return hipGetLastError();

@@ -24,7 +24,7 @@ struct pprt_ctx {
 
 struct pprt_plan {
   pprt_ctx* ctx = nullptr;
-  int nb = 0, na = 0, nf = 0, precision = 0, lower_bc = 0, wpb = 4, ng = 1;
+  int nb = 0, na = 0, nf = 0, precision = 0, lower_bc = 0, wpb = 4, ng = 1, nw = 1;
   uint32_t outputs = 0;
   std::vector<int32_t> nd;
   std::vector<int64_t> off;
@@ -295,6 +295,7 @@ pprt_status pprt_plan_create(pprt_ctx* c, const pprt_shape* sh, const double* mu
   if (wpb == 0) wpb = p->nf <= 64 ? 1 : (p->nf <= 128 ? 2 : 4);
   p->wpb = wpb;
   p->ng = (p->nf + 64 * wpb - 1) / (64 * wpb);
+  p->nw = (p->nf + 63) / 64;
 
   // work lists, longest atmosphere first (ragged batches balance better)
   std::vector<int> order(p->nb);
@@ -303,12 +304,14 @@ pprt_status pprt_plan_create(pprt_ctx* c, const pprt_shape* sh, const double* mu
   std::vector<Item> full, prof;
   full.reserve((size_t)p->nb * p->ng);
   prof.reserve((size_t)p->nb * p->ng * 2);
-  for (int b : order)
-    for (int g = 0; g < p->ng; ++g) {
-      full.push_back(Item{b, g, 0, p->nd[b]});
-      prof.push_back(Item{b, g, 0, p->nd[b]});
-      prof.push_back(Item{b, g, 1, p->nd[b]});
+  for (int b : order) {
+    for (int g = 0; g < p->ng; ++g) full.push_back(Item{b, g, 0, p->nd[b]});
+    // profile mode: one independent wave per (64-frequency tile, hemisphere)
+    for (int t = 0; t < p->nw; ++t) {
+      prof.push_back(Item{b, t, 0, p->nd[b]});
+      prof.push_back(Item{b, t, 1, p->nd[b]});
     }
+  }
   p->n_full = (int)full.size();
   p->n_prof = (int)prof.size();
   hipError_t e = hipSuccess;
@@ -329,7 +332,8 @@ pprt_status pprt_plan_create(pprt_ctx* c, const pprt_shape* sh, const double* mu
   // workspace: [part | max_rel | active | iters]
   size_t o = 0;
   p->ws_part = o;
-  o = align256(o + (size_t)p->rows * p->ng * 4 * sizeof(double));
+  o = align256(o + (size_t)p->rows * p->nw * 4 *
+                      (p->precision == PPRT_FP64 ? sizeof(double) : sizeof(float)));
   p->ws_maxrel = o;
   o = align256(o + (size_t)p->nb * sizeof(double));
   p->ws_active = o;
@@ -412,21 +416,21 @@ pprt_status pprt_formal_solution(pprt_plan* p, const pprt_fs_in* in, pprt_fs_out
 static pprt_status ali_moments_impl(pprt_plan* p, const pprt_fs_in* in, const pprt_two_level* at,
                                     const double* S, const int32_t* active, void* ws) {
   pprt_ctx* c = p->ctx;
-  double* part = (double*)((char*)ws + p->ws_part);
+  void* part = (char*)ws + p->ws_part;
   hipError_t e;
   if (p->precision == PPRT_FP64) {
     FsProfileArgs<double> a{};
     a.items = p->d_items_prof; a.off = p->d_off; a.tau = in->tau; a.q = (const double*)in->q;
     a.S = S; a.B = at->B; a.Itop = (const double*)in->Itop; a.Ibot = (const double*)in->Ibot;
-    a.wphi = (const double*)at->wphi; a.active = active; a.part = part;
-    a.nf = p->nf; a.ng = p->ng; a.lower_bc = p->lower_bc;
+    a.wphi = (const double*)at->wphi; a.active = active; a.part = (double*)part;
+    a.nf = p->nf; a.nw = p->nw; a.nitems = p->n_prof; a.lower_bc = p->lower_bc;
     e = launch_fs_profile(p->precision, p->na, p->wpb, p->n_prof, c->stream, &a, angles_of(p));
   } else {
     FsProfileArgs<float> a{};
     a.items = p->d_items_prof; a.off = p->d_off; a.tau = in->tau; a.q = (const float*)in->q;
     a.S = S; a.B = at->B; a.Itop = (const float*)in->Itop; a.Ibot = (const float*)in->Ibot;
-    a.wphi = (const float*)at->wphi; a.active = active; a.part = part;
-    a.nf = p->nf; a.ng = p->ng; a.lower_bc = p->lower_bc;
+    a.wphi = (const float*)at->wphi; a.active = active; a.part = (float*)part;
+    a.nf = p->nf; a.nw = p->nw; a.nitems = p->n_prof; a.lower_bc = p->lower_bc;
     e = launch_fs_profile(p->precision, p->na, p->wpb, p->n_prof, c->stream, &a, angles_of(p));
   }
   return hip_check(c, e, "profile formal-solution launch");
@@ -437,9 +441,9 @@ static pprt_status ali_update_impl(pprt_plan* p, const pprt_two_level* at, doubl
                                    void* ws) {
   pprt_ctx* c = p->ctx;
   AliUpdateArgs u{};
-  u.off = p->d_off; u.part = (const double*)((char*)ws + p->ws_part); u.eps = at->eps; u.B = at->B;
+  u.off = p->d_off; u.part = (const void*)((char*)ws + p->ws_part); u.eps = at->eps; u.B = at->B;
   u.S = S; u.max_rel = max_rel; u.active = active; u.iters = iters; u.status = c->d_status;
-  u.tol = tol; u.ng = p->ng; u.nb = p->nb;
+  u.tol = tol; u.nw = p->nw; u.nb = p->nb; u.part_fp64 = (p->precision == PPRT_FP64);
   return hip_check(c, launch_ali_update(p->nb, c->stream, u), "ALI update launch");
 }
 

@@ -63,15 +63,16 @@ struct FsProfileArgs {
   const T* Ibot;
   const T* wphi;            // [nf]
   const int32_t* active;    // [nb] or nullptr
-  double* part;             // [rows][ng][2 dir][2]
+  T* part;                  // [rows][nw][2 dir][2] per-wave profile moments
   int32_t nf;
-  int32_t ng;
+  int32_t nw;               // waves across the frequency range, ceil(nf/64)
+  int32_t nitems;           // one item per wave: (b, 64-frequency tile, dir)
   int32_t lower_bc;
 };
 
 struct AliUpdateArgs {
   const int64_t* off;
-  const double* part;       // [rows][ng][2][2]
+  const void* part;         // [rows][nw][2][2], float or double (part_fp64)
   const double* eps;
   const double* B;
   double* S;
@@ -80,8 +81,9 @@ struct AliUpdateArgs {
   int32_t* iters;           // [nb] or nullptr
   uint32_t* status;         // device status word
   double tol;               // > 0: clear `active` once max_rel < tol
-  int32_t ng;
+  int32_t nw;
   int32_t nb;
+  int32_t part_fp64;
 };
 
 // Launchers (fs_diag.hip, ali.hip).  Return hipSuccess or the launch error.
