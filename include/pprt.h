@@ -174,6 +174,26 @@ typedef struct pprt_fs_out {
  * constant S and 1 - Lambda* keeps full relative accuracy in thick layers. */
 pprt_status pprt_formal_solution(pprt_plan* plan, const pprt_fs_in* in, pprt_fs_out* out);
 
+/* Formal solution with coherent isotropic scattering inside every layer
+ * (the parameterised continuum scattering of Sect. 3.1, item 6; the layer
+ * recursion with transmission t+-, reflection r+- and source beta+- of the
+ * paper's notation).  `omega` (real [rows][nf]) is the single-scattering
+ * albedo at each node, 0 <= omega <= 1; a layer takes the mean of its two
+ * nodes and S^g = in->Sg, linear in the layer optical depth, is the
+ * non-scattering source: S = (1 - omega) S^g + omega J.  Each layer is solved
+ * exactly (discrete-ordinate eigen solution, no growing exponentials), layers
+ * are combined by the adding method top-down and bottom-up, and every node
+ * gets I+-, J, J - S^g, H and the exact diagonal Lambda*_dd = dJ(d)/dS^g(d)
+ * with 1 - Lambda*.  FP64 plans only, na in {1, 2, 4, 8, 16}
+ * (E_UNSUPPORTED otherwise).  Needs a workspace of
+ * pprt_plan_scattering_workspace_bytes() (it holds the composite reflection
+ * and source of every node and frequency between the two passes); omega = 0
+ * everywhere reproduces pprt_formal_solution to rounding. */
+pprt_status pprt_plan_scattering_workspace_bytes(const pprt_plan* plan, size_t* bytes);
+pprt_status pprt_formal_solution_scattering(pprt_plan* plan, const pprt_fs_in* in,
+                                            const void* omega, pprt_fs_out* out,
+                                            void* workspace);
+
 /* ----------------------------------------------------- two-level atom ALI */
 
 typedef struct pprt_two_level {

@@ -35,7 +35,9 @@ source Sigma_d of everything above node d seen from below
     G_d = (I - r- R_d)^-1,  P_d = G_d t+,  u_d = G_d (r- Sigma_d + beta+)
     R_{d+1} = r+ + t- R_d P_d,  Sigma_{d+1} = t- (Sigma_d + R_d u_d) + beta-
 and back-substitution I+(d) = P_d I+(d+1) + u_d, I-(d) = R_d I+(d) + Sigma_d
-from the lower boundary up.
+from the lower boundary up.  J - S^g and H come from the same recursion run
+on D = I - S^g, whose layer sources are +-(S^g(d+1) - S^g(d)) Q,
+Q = beta_l+ + t 1 (exact: a constant S^g is reproduced by every layer).
 
 Lambda*_dd = dJ(d)/dS^g(d): S^g(d) enters beta of the layer above and the
 layer below node d.  With the composite reflection R^up_d of everything below
@@ -250,14 +252,52 @@ def formal_solution_dense(tau, q, S, mu, w, omega=None, Itop=None, lower="diffus
         Im[d] = _mv(R[d], Ip[d]) + Sig[d]
 
     J = 0.5 * np.einsum("dki,i->dk", Ip + Im, w)
-    H = 0.5 * np.einsum("dki,i->dk", Ip - Im, w * mu)
-    out = {"Iplus": Ip, "Iminus": Im, "J": J, "JmS": J - S, "H": H, "Iemerg": Ip[0].copy(),
+    # J - S^g and H in difference form: the same adding recursion carries
+    # D = I - S^g, whose layer sources are +- (S^g(d+1) - S^g(d)) Q with
+    # Q = beta_l+ + t 1 (a constant S^g reproduces itself exactly:
+    # beta_c + t 1 + r 1 = 1), so small J - S^g keeps its relative accuracy.
+    Q = L["bsp"] / dtau[..., None] + L["tp"] @ np.ones(na)
+    dS = (S[1:] - S[:-1])[..., None]
+    Dt = (np.zeros((nf, na)) if Itop is None else np.asarray(Itop)) - S[0][:, None]
+    Db = Ip[nd - 1] - S[nd - 1][:, None]
+    Dp, Dm = _adding_backsub(L, dS * Q, -dS * Q, Dt, Db)
+    JmS = 0.5 * np.einsum("dki,i->dk", Dp + Dm, w)
+    H = 0.5 * np.einsum("dki,i->dk", Dp - Dm, w * mu)
+    out = {"Iplus": Ip, "Iminus": Im, "J": J, "JmS": JmS, "H": H, "Iemerg": Ip[0].copy(),
            "ops": L}
     if want_lstar:
         lst = lstar_dense(L, dtau, R, G, mu, w)
         out["lstar"] = lst
         out["lstar_c"] = 1.0 - lst
     return out
+
+
+def _adding_backsub(L, bp, bm, top, bottom):
+    """Intensities at every node from layer operators, layer sources bp/bm
+    [L, nf, na], the incident vector at the top and the up-going vector at
+    the bottom (adding down, back-substitution up)."""
+    nl, nf, na = bp.shape
+    nd = nl + 1
+    I = np.eye(na)
+    R = np.zeros((nd, nf, na, na))
+    Sig = np.zeros((nd, nf, na))
+    Sig[0] = top
+    P = np.zeros((nl, nf, na, na))
+    u = np.zeros((nl, nf, na))
+    for d in range(nl):
+        G = np.linalg.inv(I - L["rm"][d] @ R[d])
+        P[d] = G @ L["tp"][d]
+        u[d] = _mv(G, _mv(L["rm"][d], Sig[d]) + bp[d])
+        R[d + 1] = L["rp"][d] + L["tm"][d] @ R[d] @ P[d]
+        Sig[d + 1] = _mv(L["tm"][d], Sig[d] + _mv(R[d], u[d])) + bm[d]
+    Xp = np.zeros((nd, nf, na))
+    Xm = np.zeros((nd, nf, na))
+    Xp[nd - 1] = bottom
+    Xm[nd - 1] = _mv(R[nd - 1], Xp[nd - 1]) + Sig[nd - 1]
+    for d in range(nd - 2, -1, -1):
+        Xp[d] = _mv(P[d], Xp[d + 1]) + u[d]
+        Xm[d] = _mv(R[d], Xp[d]) + Sig[d]
+    return Xp, Xm
 
 
 def lstar_dense(L, dtau, R, G, mu, w):

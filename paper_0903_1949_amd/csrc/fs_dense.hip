@@ -1,0 +1,629 @@
+// Formal solution with coherent isotropic scattering inside the layers
+// (omega > 0) on gfx950, FP64: exact homogeneous-layer operators t, r, beta
+// from the discrete-ordinate eigen solution, the adding recursion down, a
+// bottom-up adding pass, and the two-sided combination that yields I+-, J and
+// the exact diagonal Lambda* at every node.
+//
+// Reading (the paper names t+-, r+-, beta+- and I+- in its notation and
+// parameterises coherent isotropic continuum scattering, Sect. 3.1 item 6;
+// the equations are deferred to its Papers I-II, Sect. 2): each layer is
+// homogeneous with albedo omega = mean of its two node values and a source
+// S^g linear in the layer optical depth; the total source is
+// S = (1-omega) S^g + omega J.  Layer equations:
+//     I+(d) = t I+(d+1) + r I-(d) + beta+,   I-(d+1) = t I-(d) + r I+(d+1) + beta-
+// (a homogeneous layer has t+ = t-, r+ = r-).
+//
+// Layer operators.  In scaled intensities I^ = diag(sqrt w) I the homogeneous
+// problem reduces to the symmetric matrix diag(1/mu^2) - omega u u^T,
+// u_i = sqrt(w_i)/mu_i: its eigenvalues lambda = k^2 are the roots of the
+// secular equation 1 = omega sum_j w_j / (1 - mu_j^2 lambda) (found with the
+// origin at the nearer pole), and orthonormal eigenvectors V follow from the
+// Gu & Eisenstat (1994) recomputed vector.  With M = diag(1/mu), D the layer
+// optical depth, x = k D/2, Q_T = V diag(k tanh x) V^T,
+// Q_C' = V diag(2 x coth x) V^T, F_T = (M + Q_T)^-1, F_C' = (D M + Q_C')^-1
+// (both symmetric positive definite):
+//     r^ = M (F_T + D F_C') - I,     t^ = M (F_T - D F_C'),
+//     beta^_c  = 2 Q_T F_T sqrt(w)                        (unit constant S^g)
+//     Qv       = 2 M F_C' (sqrt(w) mu)
+//     beta^_l+ = Qv - t^ sqrt(w),    beta^_l- = (I - r^) sqrt(w) - Qv
+//                                                         (unit node difference)
+// exact for every thickness and for omega = 1 (k = 0 is regular), with no
+// growing exponential and no 1/D.
+//
+// Mapping: NA lanes per frequency (lane i holds row i of every NA x NA matrix
+// and element i of every vector), 64/NA frequencies per wave, one wave per
+// block.  Matrix products broadcast the right operand through the group's LDS
+// slab; the LDS operations of one wave execute in order and compiler fences
+// keep the program order.  Intensities travel in difference form
+// D = I - S^g (scaled), whose layer sources are +-(S^g(d+1) - S^g(d)) Q with
+// Q = beta_l+ + t sqrt(w), exact because a layer reproduces a constant S^g
+// (beta_c + t sqrt(w) + r sqrt(w) = sqrt(w)); J - S^g and H then keep their
+// relative accuracy where they are small.  Pass 1 (top -> bottom) stores the composite
+// reflection R_d and source Sigma_d of every node in the workspace; pass 2
+// (bottom -> top) recomputes the layer operators, builds the composites R^up,
+// Sigma^up of the layers below and emits the node outputs:
+//     I+ = (I - R^up R)^-1 (R^up Sigma + Sigma^up),  I- = R I+ + Sigma,
+// and the same combination of the unit-source responses of the two layers
+// that touch the node gives Lambda*_dd = dJ(d)/dS^g(d).
+#include "pprt_internal.h"
+
+namespace pprt {
+namespace {
+
+template <int NA>
+struct DenseTab {
+  // internal angle order: descending mu (ascending d = 1/mu^2)
+  double mu[NA], m[NA], d[NA], z2[NA], w[NA], sw[NA], swmu[NA];
+  int ext[NA];  // index of internal angle i in the caller's (ascending mu) order
+};
+
+__device__ __forceinline__ void wsync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int NA>
+struct Slab {
+  static constexpr int MAT = (NA * NA > 2 * NA + 2) ? NA * NA : 2 * NA + 2;
+  static constexpr int VEC = MAT;            // 4 vector slots of NA
+  static constexpr int ROOT = MAT + 4 * NA;  // 2 NA: root origin and offset
+  static constexpr int SIZE = MAT + 6 * NA;
+};
+
+// lane-group toolkit: lane i holds row i
+template <int NA>
+struct Grp {
+  double* buf;
+  int i;
+
+  __device__ __forceinline__ void put_mat(const double (&A)[NA]) {
+    wsync();
+#pragma unroll
+    for (int j = 0; j < NA; ++j) buf[i * NA + j] = A[j];
+    wsync();
+  }
+  __device__ __forceinline__ void put_vec(double v, int slot) {
+    wsync();
+    buf[Slab<NA>::VEC + slot * NA + i] = v;
+    wsync();
+  }
+  __device__ __forceinline__ double vec(int j, int slot) const {
+    return buf[Slab<NA>::VEC + slot * NA + j];
+  }
+  // C = A B
+  __device__ __forceinline__ void mul(double (&C)[NA], const double (&A)[NA], const double (&B)[NA]) {
+    put_mat(B);
+    double acc[NA];
+#pragma unroll
+    for (int j = 0; j < NA; ++j) acc[j] = 0.0;
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+      const double a = A[k];
+#pragma unroll
+      for (int j = 0; j < NA; ++j) acc[j] = fma(a, buf[k * NA + j], acc[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < NA; ++j) C[j] = acc[j];
+  }
+  // (A x)_i
+  __device__ __forceinline__ double mv(const double (&A)[NA], double x) {
+    put_vec(x, 0);
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < NA; ++j) acc = fma(A[j], vec(j, 0), acc);
+    return acc;
+  }
+  // sum over the group of v
+  __device__ __forceinline__ double sum(double v) {
+    put_vec(v, 1);
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < NA; ++j) acc += vec(j, 1);
+    return acc;
+  }
+  // X = A^-1 by Gauss-Jordan without pivoting; A is destroyed.  Used on
+  // symmetric positive definite matrices and on I - (reflection products).
+  __device__ __forceinline__ void inv(double (&X)[NA], double (&A)[NA]) {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) X[j] = (j == i) ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+      wsync();
+      if (i == k) {
+        const double p = 1.0 / A[k];
+#pragma unroll
+        for (int j = 0; j < NA; ++j) {
+          A[j] *= p;
+          X[j] *= p;
+          buf[j] = A[j];
+          buf[NA + j] = X[j];
+        }
+      }
+      wsync();
+      if (i != k) {
+        const double f = A[k];
+#pragma unroll
+        for (int j = 0; j < NA; ++j) {
+          A[j] = fma(-f, buf[j], A[j]);
+          X[j] = fma(-f, buf[NA + j], X[j]);
+        }
+      }
+    }
+    wsync();
+  }
+  // y with A y = b (b_i in this lane); A is destroyed
+  __device__ __forceinline__ double solve(double (&A)[NA], double b) {
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+      wsync();
+      if (i == k) {
+        const double p = 1.0 / A[k];
+#pragma unroll
+        for (int j = 0; j < NA; ++j) {
+          A[j] *= p;
+          buf[j] = A[j];
+        }
+        b *= p;
+        buf[NA] = b;
+      }
+      wsync();
+      if (i != k) {
+        const double f = A[k];
+#pragma unroll
+        for (int j = 0; j < NA; ++j) A[j] = fma(-f, buf[j], A[j]);
+        b = fma(-f, buf[NA], b);
+      }
+    }
+    wsync();
+    return b;
+  }
+};
+
+template <int NA>
+struct LaneTab {  // per-lane copies of the angle constants of row i
+  double mu, m, d, z2, w, sw, swmu;
+  int ext;
+};
+
+// ---- eigen solution of diag(d) - omega z z^T (d ascending) ------------------
+// Lane i finds root i in (d_{i-1}, d_i) (d_{-1} = 0) as org + del, org the
+// nearer end, by bracketed Newton on the secular function; the group then
+// forms the Gu-Eisenstat vector and lane i keeps row i of V and its root.
+template <int NA>
+__device__ void eigen(Grp<NA>& g, const DenseTab<NA>& T, const LaneTab<NA>& L, double om,
+                      double (&V)[NA], double& k_i) {
+  const int i = g.i;
+  double lo = 0.0;
+#pragma unroll
+  for (int j = 0; j < NA; ++j)
+    if (j == i - 1) lo = T.d[j];
+  const double hi = L.d;
+  double org = hi, del = 0.0;
+  const double om1 = 1.0 - om;
+  if (om > 0.0) {
+    // f(lam) = 1 - om sum z2_j/(d_j - lam), or for root 0 near lam = 0 the
+    // equivalent (1 - om) - om lam sum w_j/(d_j - lam); both decrease in lam.
+    auto feval = [&](double o, double sgn, double x, double& f, double& df) {
+      double s = 0.0, s2 = 0.0;
+      if (i == 0 && o == 0.0) {
+#pragma unroll
+        for (int j = 0; j < NA; ++j) {
+          const double r = 1.0 / (T.d[j] - sgn * x);
+          s = fma(T.w[j], r, s);
+          s2 = fma(T.w[j] * T.d[j], r * r, s2);
+        }
+        f = om1 - om * x * s;
+        df = -om * s2;
+      } else {
+#pragma unroll
+        for (int j = 0; j < NA; ++j) {
+          const double r = 1.0 / ((T.d[j] - o) - sgn * x);
+          s = fma(T.z2[j], r, s);
+          s2 = fma(T.z2[j] * r, r, s2);
+        }
+        f = 1.0 - om * s;
+        df = -om * s2;
+      }
+    };
+    const double mid = 0.5 * (lo + hi);
+    double fm, dfm;
+    if (i == 0) feval(0.0, 1.0, mid, fm, dfm);
+    else feval(lo, 1.0, mid - lo, fm, dfm);
+    double sgn, xl, xh;
+    if (fm > 0.0) { org = hi; sgn = -1.0; xl = 0.0; xh = hi - mid; }
+    else { org = lo; sgn = 1.0; xl = 0.0; xh = mid - lo; }
+    if (i == 0 && sgn > 0.0 && om1 <= 0.0) {
+      del = 0.0;                       // omega = 1: the diffusion root is exactly 0
+    } else {
+      double x = 0.5 * (xl + xh);
+      for (int it = 0; it < 200; ++it) {
+        double f, df;
+        feval(org, sgn, x, f, df);
+        // lam = org + sgn x is too small when f > 0
+        if ((f > 0.0) == (sgn > 0.0)) xl = x; else xh = x;
+        double xn = x - f / (df * sgn);
+        if (!(xn > xl && xn < xh)) xn = 0.5 * (xl + xh);
+        const double step = fabs(xn - x);
+        x = xn;
+        if (step <= 2e-16 * x || xh - xl <= 4e-16 * xh) break;
+      }
+      del = sgn * x;
+    }
+  }
+  // broadcast roots
+  wsync();
+  g.buf[Slab<NA>::ROOT + 2 * i + 0] = org;
+  g.buf[Slab<NA>::ROOT + 2 * i + 1] = del;
+  wsync();
+  const double lam = org + del;
+  k_i = sqrt(fmax(lam, 0.0));
+  if (!(om > 0.0)) {
+#pragma unroll
+    for (int a = 0; a < NA; ++a) V[a] = (a == i) ? 1.0 : 0.0;
+    return;
+  }
+  // Gu-Eisenstat: zhat_i^2 = prod_a (lam_a - d_i) / (-omega prod_{j != i} (d_j - d_i))
+  double num = 1.0, den = -om;
+#pragma unroll
+  for (int a = 0; a < NA; ++a) {
+    const double oa = g.buf[Slab<NA>::ROOT + 2 * a];
+    const double da = g.buf[Slab<NA>::ROOT + 2 * a + 1];
+    num *= (oa - L.d) + da;
+    if (a != i) den *= (T.d[a] - L.d);
+  }
+  const double zh = sqrt(fabs(num / den));
+  g.put_vec(zh, 2);
+  // column norm of eigenvector i: sum_j zh_j^2 / (d_j - lam_i)^2
+  double nrm = 0.0;
+#pragma unroll
+  for (int j = 0; j < NA; ++j) {
+    const double q = g.vec(j, 2) / ((T.d[j] - org) - del);
+    nrm = fma(q, q, nrm);
+  }
+  g.put_vec(1.0 / sqrt(nrm), 3);
+#pragma unroll
+  for (int a = 0; a < NA; ++a) {
+    const double oa = g.buf[Slab<NA>::ROOT + 2 * a];
+    const double da = g.buf[Slab<NA>::ROOT + 2 * a + 1];
+    V[a] = zh / ((L.d - oa) - da) * g.vec(a, 3);
+  }
+}
+
+// x / tanh(x) for x >= 0, series below 0.05
+__device__ __forceinline__ double x_coth_x(double x) {
+  if (x < 0.05) {
+    const double x2 = x * x;
+    return 1.0 + x2 * (1.0 / 3.0 + x2 * (-1.0 / 45.0 + x2 * (2.0 / 945.0)));
+  }
+  return x / tanh(x);
+}
+
+// Layer operators in scaled variables (row i in this lane).
+template <int NA>
+struct LayerOps {
+  double t[NA], r[NA];
+  double bc, blp, blm;  // element i of beta_c, beta_l+, beta_l-
+  double qv;            // element i of Q = beta_l+ + t sqrt(w) (difference-form source)
+};
+
+template <int NA>
+__device__ void layer_ops(Grp<NA>& g, const DenseTab<NA>& T, const LaneTab<NA>& L,
+                          const double (&V)[NA], double k_i, double Dl, LayerOps<NA>& o) {
+  const int i = g.i;
+  // per-root factors of root i, broadcast
+  const double x = 0.5 * k_i * Dl;
+  const double tx = k_i * tanh(x);
+  const double cx = 2.0 * x_coth_x(x);
+  g.put_vec(tx, 2);
+  g.put_vec(cx, 3);
+  // Q_T = V diag(tx) V^T and Q_C' = V diag(cx) V^T: broadcast V
+  g.put_mat(V);
+  double AT[NA], AC[NA];
+  double vt[NA], vc[NA];
+#pragma unroll
+  for (int a = 0; a < NA; ++a) {
+    vt[a] = V[a] * g.vec(a, 2);
+    vc[a] = V[a] * g.vec(a, 3);
+  }
+#pragma unroll
+  for (int j = 0; j < NA; ++j) {
+    double st = 0.0, sc = 0.0;
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+      const double vja = g.buf[j * NA + a];
+      st = fma(vt[a], vja, st);
+      sc = fma(vc[a], vja, sc);
+    }
+    AT[j] = st;
+    AC[j] = sc;
+  }
+  double QT[NA];
+#pragma unroll
+  for (int j = 0; j < NA; ++j) QT[j] = AT[j];
+  AT[i] += L.m;                 // M + Q_T      (lane-dependent diagonal)
+  AC[i] += Dl * L.m;            // D M + Q_C'
+  double FT[NA], FC[NA];
+  g.inv(FT, AT);
+  g.inv(FC, AC);
+  double tw = 0.0, rw = 0.0, fw = 0.0, qv = 0.0;
+#pragma unroll
+  for (int j = 0; j < NA; ++j) {
+    const double ft = FT[j], fc = Dl * FC[j];
+    o.r[j] = L.m * (ft + fc) - ((j == i) ? 1.0 : 0.0);
+    o.t[j] = L.m * (ft - fc);
+    tw = fma(o.t[j], T.sw[j], tw);
+    rw = fma(o.r[j], T.sw[j], rw);
+    fw = fma(ft, T.sw[j], fw);
+    qv = fma(FC[j], T.swmu[j], qv);
+  }
+  qv *= 2.0 * L.m;
+  o.qv = qv;
+  o.bc = 2.0 * g.mv(QT, fw);
+  o.blp = qv - tw;
+  o.blm = (L.sw - rw) - qv;
+}
+
+template <int NA>
+struct FsDenseArgs {
+  const Item* items;
+  const int64_t* off;
+  const double* tau;
+  const double* q;
+  const double* Sg;
+  const double* omega;
+  const double* Itop;
+  const double* Bbot;
+  const double* Bbot_prev;
+  const double* Ibot;
+  double *J, *JmS, *lstar, *lstar_c, *Iplus, *Iminus, *H, *Iemerg;
+  double* wsR;     // [rows][nf][NA][NA]
+  double* wsS;     // [rows][nf][NA]
+  int32_t nf;
+  int32_t nitems;
+  int32_t lower_bc;
+  uint32_t outputs;
+};
+
+template <int NA>
+__global__ __launch_bounds__(64) void k_fs_dense(FsDenseArgs<NA> a, DenseTab<NA> T) {
+  constexpr int F = 64 / NA;
+  __shared__ double slab[F * Slab<NA>::SIZE];
+  const int lane = (int)threadIdx.x;
+  const int grp = lane / NA;
+  const int item = (int)blockIdx.x;
+  if (item >= a.nitems) return;
+  const Item it = a.items[item];
+  const int b = it.b;
+  const int nd = it.nd;
+  const int nf = a.nf;
+  const int k = it.g * F + grp;
+  if (k >= nf) return;   // a whole group: groups never talk to each other
+  const int64_t row0 = a.off[b];
+  Grp<NA> g{slab + grp * Slab<NA>::SIZE, lane % NA};
+  const int i = g.i;
+  LaneTab<NA> L{};
+#pragma unroll
+  for (int j = 0; j < NA; ++j)
+    if (j == i) {
+      L.mu = T.mu[j]; L.m = T.m[j]; L.d = T.d[j]; L.z2 = T.z2[j]; L.w = T.w[j];
+      L.sw = T.sw[j]; L.swmu = T.swmu[j]; L.ext = T.ext[j];
+    }
+  const uint32_t o = a.outputs;
+  auto at = [&](const double* p, int64_t row) { return p[row * nf + k]; };
+  auto layer_depth = [&](int d) {   // optical depth of layer (d, d+1)
+    return 0.5 * (at(a.q, row0 + d) + at(a.q, row0 + d + 1)) * (a.tau[row0 + d + 1] - a.tau[row0 + d]);
+  };
+  auto layer_omega = [&](int d) {
+    return a.omega ? 0.5 * (at(a.omega, row0 + d) + at(a.omega, row0 + d + 1)) : 0.0;
+  };
+  double* wsR = a.wsR + ((row0 * nf + k) * NA + i) * NA;   // + node * nf * NA * NA
+  double* wsS = a.wsS + (row0 * nf + k) * NA + i;           // + node * nf * NA
+  const int64_t strideR = (int64_t)nf * NA * NA;
+  const int64_t strideS = (int64_t)nf * NA;
+
+  double V[NA];
+  double kk = 0.0;
+  double om_prev = -1.0;
+  LayerOps<NA> op;
+
+  // ---------------- pass 1: adding recursion, top -> bottom
+  double R[NA];
+#pragma unroll
+  for (int j = 0; j < NA; ++j) R[j] = 0.0;
+  // difference form: D = I - S^g, scaled by sqrt(w)
+  double Sig = L.sw * ((a.Itop ? a.Itop[((int64_t)b * nf + k) * NA + L.ext] : 0.0) - at(a.Sg, row0));
+  for (int d = 0; d < nd - 1; ++d) {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) wsR[d * strideR + j] = R[j];
+    wsS[d * strideS] = Sig;
+    const double om = layer_omega(d);
+    if (om != om_prev) {
+      eigen<NA>(g, T, L, om, V, kk);
+      om_prev = om;
+    }
+    const double Dl = layer_depth(d);
+    layer_ops<NA>(g, T, L, V, kk, Dl, op);
+    const double dSg = at(a.Sg, row0 + d + 1) - at(a.Sg, row0 + d);
+    const double bp = dSg * op.qv;        // difference-form layer sources
+    const double bm = -dSg * op.qv;
+    // G = (I - r R)^-1, P = G t, u = G (r Sigma + beta+)
+    double X[NA], G[NA], P[NA];
+    g.mul(X, op.r, R);
+#pragma unroll
+    for (int j = 0; j < NA; ++j) X[j] = ((j == i) ? 1.0 : 0.0) - X[j];
+    g.inv(G, X);
+    g.mul(P, G, op.t);
+    const double v = g.mv(op.r, Sig) + bp;
+    const double u = g.mv(G, v);
+    // Sigma_{d+1} = t (Sigma + R u) + beta-,  R_{d+1} = r + t R P
+    const double Ru = g.mv(R, u);
+    const double Sig_n = g.mv(op.t, Sig + Ru) + bm;
+    double RP[NA], tRP[NA];
+    g.mul(RP, R, P);
+    g.mul(tRP, op.t, RP);
+#pragma unroll
+    for (int j = 0; j < NA; ++j) R[j] = op.r[j] + tRP[j];
+    Sig = Sig_n;
+  }
+#pragma unroll
+  for (int j = 0; j < NA; ++j) wsR[(nd - 1) * strideR + j] = R[j];
+  wsS[(nd - 1) * strideS] = Sig;
+
+  // ---------------- pass 2: bottom -> top, outputs per node
+  double Rup[NA];
+#pragma unroll
+  for (int j = 0; j < NA; ++j) Rup[j] = 0.0;
+  double Sup;
+  {
+    const int64_t rl = row0 + nd - 1;
+    const double S_last = at(a.Sg, rl);
+    if (a.lower_bc == PPRT_BC_DIFFUSION) {
+      const double Bb = a.Bbot[(int64_t)b * nf + k];
+      const double Bp = a.Bbot_prev[(int64_t)b * nf + k];
+      const double gr = (Bb - Bp) / layer_depth(nd - 2);
+      Sup = L.sw * ((Bb - S_last) + L.mu * gr);
+    } else {
+      Sup = L.sw * ((a.Ibot ? a.Ibot[((int64_t)b * nf + k) * NA + L.ext] : 0.0) - S_last);
+    }
+    (void)rl;
+  }
+  double dSu = 0.0;           // dSigma^up of the node being emitted (layer below)
+  om_prev = -1.0;
+  for (int d = nd - 1; d >= 0; --d) {
+    const bool has_a = d >= 1;  // layer a = (d-1, d) above node d
+    if (has_a) {
+      const double om = layer_omega(d - 1);
+      if (om != om_prev) {
+        eigen<NA>(g, T, L, om, V, kk);
+        om_prev = om;
+      }
+      layer_ops<NA>(g, T, L, V, kk, layer_depth(d - 1), op);
+    }
+    // ---- emit node d
+    double Rd[NA];
+#pragma unroll
+    for (int j = 0; j < NA; ++j) Rd[j] = wsR[d * strideR + j];
+    const double Sd = wsS[d * strideS];
+    double X[NA], Xi[NA];
+    g.mul(X, Rup, Rd);
+#pragma unroll
+    for (int j = 0; j < NA; ++j) X[j] = ((j == i) ? 1.0 : 0.0) - X[j];
+    g.inv(Xi, X);
+    const double Ip = g.mv(Xi, g.mv(Rup, Sd) + Sup);
+    const double Im = g.mv(Rd, Ip) + Sd;
+    // unit response: layer above (S^g 0 -> 1) through R_{d-1}, G_{d-1}
+    double dS = 0.0;
+    if (has_a) {
+      double Rm[NA], Y[NA];
+#pragma unroll
+      for (int j = 0; j < NA; ++j) Rm[j] = wsR[(d - 1) * strideR + j];
+      g.mul(Y, op.r, Rm);
+#pragma unroll
+      for (int j = 0; j < NA; ++j) Y[j] = ((j == i) ? 1.0 : 0.0) - Y[j];
+      const double y = g.solve(Y, op.blp);          // G_{d-1} dbeta+_a
+      dS = g.mv(op.t, g.mv(Rm, y)) + op.blm;
+    }
+    const double dIp = g.mv(Xi, g.mv(Rup, dS) + dSu);
+    const double dIm = g.mv(Rd, dIp) + dS;
+    // Ip, Im are the scaled differences D+- = sqrt(w) (I+- - S^g)
+    const double JmSn = 0.5 * g.sum(L.sw * (Ip + Im));
+    const double Ln = 0.5 * g.sum(L.sw * (dIp + dIm));
+    const double Hn = 0.5 * g.sum(L.swmu * (Ip - Im));
+    {
+      const int64_t x = (row0 + d) * nf + k;
+      const double S = a.Sg[x];
+      if (i == 0) {
+        if (o & PPRT_OUT_J) a.J[x] = JmSn + S;
+        if (o & PPRT_OUT_JMS) a.JmS[x] = JmSn;
+        if (o & PPRT_OUT_LSTAR) a.lstar[x] = Ln;
+        if (o & PPRT_OUT_LSTAR_C) a.lstar_c[x] = 1.0 - Ln;
+        if (o & PPRT_OUT_H) a.H[x] = Hn;
+      }
+      if (o & PPRT_OUT_IPLUS) a.Iplus[x * NA + L.ext] = Ip / L.sw + S;
+      if (o & PPRT_OUT_IMINUS) a.Iminus[x * NA + L.ext] = Im / L.sw + S;
+      if (d == 0 && (o & PPRT_OUT_IEMERG))
+        a.Iemerg[((int64_t)b * nf + k) * NA + L.ext] = Ip / L.sw + S;
+    }
+    // ---- move the lower composite up through layer a
+    if (has_a) {
+      const double dSg = at(a.Sg, row0 + d) - at(a.Sg, row0 + d - 1);
+      const double bp = dSg * op.qv;
+      const double bm = -dSg * op.qv;
+      double Y[NA], Gu[NA], RG[NA];
+      g.mul(Y, op.r, Rup);
+#pragma unroll
+      for (int j = 0; j < NA; ++j) Y[j] = ((j == i) ? 1.0 : 0.0) - Y[j];
+      g.inv(Gu, Y);                                  // (I - r R^up)^-1
+      g.mul(RG, Rup, Gu);                            // R^up G^up
+      const double w1 = g.mv(RG, g.mv(op.r, Sup) + bm);
+      const double Sup_n = g.mv(op.t, Sup + w1) + bp;
+      // unit response of layer a seen from node d-1 (S^g 1 -> 0)
+      const double dbm = op.bc - op.blm, dbp = op.bc - op.blp;
+      dSu = g.mv(op.t, g.mv(RG, dbm)) + dbp;
+      double RGt[NA], tRGt[NA];
+      g.mul(RGt, RG, op.t);
+      g.mul(tRGt, op.t, RGt);
+#pragma unroll
+      for (int j = 0; j < NA; ++j) Rup[j] = op.r[j] + tRGt[j];
+      Sup = Sup_n;
+    }
+  }
+}
+
+template <int NA>
+hipError_t launch_dense_t(int nitems, hipStream_t s, const void* args, const void* tab) {
+  hipLaunchKernelGGL((k_fs_dense<NA>), dim3(nitems), dim3(64), 0, s,
+                     *static_cast<const FsDenseArgs<NA>*>(args), *static_cast<const DenseTab<NA>*>(tab));
+  return hipGetLastError();
+}
+
+template <int NA>
+void fill_tab(DenseTab<NA>& T, const double* mu_asc, const double* w_asc) {
+  // internal order: descending mu
+  for (int i = 0; i < NA; ++i) {
+    const int e = NA - 1 - i;
+    const double m = mu_asc[e], w = w_asc[e];
+    T.mu[i] = m; T.m[i] = 1.0 / m; T.d[i] = 1.0 / (m * m); T.w[i] = w;
+    T.z2[i] = w / (m * m); T.sw[i] = sqrt(w); T.swmu[i] = sqrt(w) * m; T.ext[i] = e;
+  }
+}
+
+template <int NA>
+hipError_t run_dense(const DenseLaunch& L, hipStream_t s) {
+  FsDenseArgs<NA> a{};
+  a.items = L.items; a.off = L.off; a.tau = L.tau; a.q = L.q; a.Sg = L.Sg; a.omega = L.omega;
+  a.Itop = L.Itop; a.Bbot = L.Bbot; a.Bbot_prev = L.Bbot_prev; a.Ibot = L.Ibot;
+  a.J = L.J; a.JmS = L.JmS; a.lstar = L.lstar; a.lstar_c = L.lstar_c; a.Iplus = L.Iplus;
+  a.Iminus = L.Iminus; a.H = L.H; a.Iemerg = L.Iemerg;
+  a.wsR = L.ws;
+  a.wsS = L.ws + (size_t)L.rows * L.nf * NA * NA;
+  a.nf = L.nf; a.nitems = L.nitems; a.lower_bc = L.lower_bc; a.outputs = L.outputs;
+  DenseTab<NA> T{};
+  fill_tab<NA>(T, L.mu, L.w);
+  return launch_dense_t<NA>(L.nitems, s, &a, &T);
+}
+
+}  // namespace
+
+bool dense_na_supported(int na) { return na == 1 || na == 2 || na == 4 || na == 8 || na == 16; }
+
+size_t dense_workspace_bytes(int na, int64_t rows, int nf) {
+  return (size_t)rows * nf * (size_t)(na * na + na) * sizeof(double);
+}
+
+int dense_freqs_per_item(int na) { return 64 / na; }
+
+hipError_t launch_fs_dense(const DenseLaunch& L, hipStream_t s) {
+  if (L.nitems == 0) return hipSuccess;
+  switch (L.na) {
+    case 1: return run_dense<1>(L, s);
+    case 2: return run_dense<2>(L, s);
+    case 4: return run_dense<4>(L, s);
+    case 8: return run_dense<8>(L, s);
+    case 16: return run_dense<16>(L, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace pprt

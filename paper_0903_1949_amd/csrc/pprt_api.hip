@@ -33,6 +33,8 @@ struct pprt_plan {
   int n_full = 0;
   Item* d_items_prof = nullptr;
   int n_prof = 0;
+  Item* d_items_dense = nullptr;
+  int n_dense = 0;
   int64_t* d_off = nullptr;
   std::vector<double> mu, w;
   Angles<float> af{};
@@ -301,7 +303,7 @@ pprt_status pprt_plan_create(pprt_ctx* c, const pprt_shape* sh, const double* mu
   std::vector<int> order(p->nb);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return p->nd[x] > p->nd[y]; });
-  std::vector<Item> full, prof;
+  std::vector<Item> full, prof, dns;
   full.reserve((size_t)p->nb * p->ng);
   prof.reserve((size_t)p->nb * p->ng * 2);
   for (int b : order) {
@@ -311,13 +313,21 @@ pprt_status pprt_plan_create(pprt_ctx* c, const pprt_shape* sh, const double* mu
       prof.push_back(Item{b, t, 0, p->nd[b]});
       prof.push_back(Item{b, t, 1, p->nd[b]});
     }
+    if (dense_na_supported(p->na)) {
+      const int F = dense_freqs_per_item(p->na);
+      for (int t = 0; t < (p->nf + F - 1) / F; ++t) dns.push_back(Item{b, t, 0, p->nd[b]});
+    }
   }
+  p->n_dense = (int)dns.size();
   p->n_full = (int)full.size();
   p->n_prof = (int)prof.size();
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = hipMalloc(&p->d_items_full, full.size() * sizeof(Item));
   if (e == hipSuccess) e = hipMalloc(&p->d_items_prof, prof.size() * sizeof(Item));
   if (e == hipSuccess) e = hipMalloc(&p->d_off, p->off.size() * sizeof(int64_t));
+  if (e == hipSuccess && !dns.empty()) e = hipMalloc(&p->d_items_dense, dns.size() * sizeof(Item));
+  if (e == hipSuccess && !dns.empty())
+    e = hipMemcpy(p->d_items_dense, dns.data(), dns.size() * sizeof(Item), hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(p->d_items_full, full.data(), full.size() * sizeof(Item), hipMemcpyHostToDevice);
   if (e == hipSuccess)
@@ -350,6 +360,7 @@ void pprt_plan_destroy(pprt_plan* p) {
   if (p->d_items_full) (void)hipFree(p->d_items_full);
   if (p->d_items_prof) (void)hipFree(p->d_items_prof);
   if (p->d_off) (void)hipFree(p->d_off);
+  if (p->d_items_dense) (void)hipFree(p->d_items_dense);
   delete p;
 }
 
@@ -411,6 +422,48 @@ pprt_status pprt_formal_solution(pprt_plan* p, const pprt_fs_in* in, pprt_fs_out
     e = launch_fs_full(p->precision, p->na, p->wpb, p->n_full, c->stream, &a, angles_of(p));
   }
   return hip_check(c, e, "formal-solution launch");
+}
+
+pprt_status pprt_plan_scattering_workspace_bytes(const pprt_plan* p, size_t* bytes) {
+  if (!p || !bytes) return PPRT_E_INVALID_ARG;
+  *bytes = dense_na_supported(p->na) ? dense_workspace_bytes(p->na, p->rows, p->nf) : 0;
+  return PPRT_OK;
+}
+
+pprt_status pprt_formal_solution_scattering(pprt_plan* p, const pprt_fs_in* in, const void* omega,
+                                            pprt_fs_out* out, void* ws) {
+  if (!p) return PPRT_E_INVALID_ARG;
+  pprt_ctx* c = p->ctx;
+  if (p->precision != PPRT_FP64)
+    return fail(c, PPRT_E_UNSUPPORTED, "in-layer scattering runs in FP64 plans only");
+  if (!dense_na_supported(p->na))
+    return fail(c, PPRT_E_UNSUPPORTED, "in-layer scattering needs na in {1,2,4,8,16} (got %d)", p->na);
+  if (!in || !out || !omega) return fail(c, PPRT_E_INVALID_ARG, "null in/out/omega");
+  if (!in->tau || !in->q || !in->Sg) return fail(c, PPRT_E_INVALID_ARG, "tau, q and Sg are required");
+  if (p->lower_bc == PPRT_BC_DIFFUSION && (!in->Bbot || !in->Bbot_prev))
+    return fail(c, PPRT_E_INVALID_ARG, "diffusion lower boundary needs Bbot and Bbot_prev");
+  if (!ws) return fail(c, PPRT_E_WORKSPACE, "workspace of %zu bytes required",
+                       dense_workspace_bytes(p->na, p->rows, p->nf));
+  const uint32_t o = p->outputs;
+  if (o == 0) return fail(c, PPRT_E_INVALID_ARG, "plan requests no outputs");
+  struct { uint32_t bit; void* ptr; const char* name; } req[] = {
+      {PPRT_OUT_J, out->J, "J"}, {PPRT_OUT_JMS, out->JmS, "JmS"},
+      {PPRT_OUT_LSTAR, out->lstar, "lstar"}, {PPRT_OUT_LSTAR_C, out->lstar_c, "lstar_c"},
+      {PPRT_OUT_IPLUS, out->Iplus, "Iplus"}, {PPRT_OUT_IMINUS, out->Iminus, "Iminus"},
+      {PPRT_OUT_H, out->H, "H"}, {PPRT_OUT_IEMERG, out->Iemerg, "Iemerg"}};
+  for (auto& r : req)
+    if ((o & r.bit) && !r.ptr) return fail(c, PPRT_E_INVALID_ARG, "output %s requested but NULL", r.name);
+  DenseLaunch L{};
+  L.items = p->d_items_dense; L.off = p->d_off; L.tau = in->tau; L.q = (const double*)in->q;
+  L.Sg = (const double*)in->Sg; L.omega = (const double*)omega; L.Itop = (const double*)in->Itop;
+  L.Bbot = (const double*)in->Bbot; L.Bbot_prev = (const double*)in->Bbot_prev;
+  L.Ibot = (const double*)in->Ibot;
+  L.J = (double*)out->J; L.JmS = (double*)out->JmS; L.lstar = (double*)out->lstar;
+  L.lstar_c = (double*)out->lstar_c; L.Iplus = (double*)out->Iplus; L.Iminus = (double*)out->Iminus;
+  L.H = (double*)out->H; L.Iemerg = (double*)out->Iemerg;
+  L.ws = (double*)ws; L.rows = p->rows; L.nf = p->nf; L.na = p->na; L.nitems = p->n_dense;
+  L.lower_bc = p->lower_bc; L.outputs = o; L.mu = p->mu.data(); L.w = p->w.data();
+  return hip_check(c, launch_fs_dense(L, c->stream), "scattering formal-solution launch");
 }
 
 static pprt_status ali_moments_impl(pprt_plan* p, const pprt_fs_in* in, const pprt_two_level* at,

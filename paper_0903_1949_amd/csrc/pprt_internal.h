@@ -86,6 +86,31 @@ struct AliUpdateArgs {
   int32_t part_fp64;
 };
 
+// Dense (in-layer scattering) formal solution, FP64 (fs_dense.hip).
+struct DenseLaunch {
+  const Item* items;
+  const int64_t* off;
+  const double* tau;
+  const double* q;
+  const double* Sg;
+  const double* omega;
+  const double* Itop;
+  const double* Bbot;
+  const double* Bbot_prev;
+  const double* Ibot;
+  double *J, *JmS, *lstar, *lstar_c, *Iplus, *Iminus, *H, *Iemerg;
+  double* ws;
+  int64_t rows;
+  int32_t nf, na, nitems, lower_bc;
+  uint32_t outputs;
+  const double* mu;   // host, ascending
+  const double* w;
+};
+bool dense_na_supported(int na);
+size_t dense_workspace_bytes(int na, int64_t rows, int nf);
+int dense_freqs_per_item(int na);
+hipError_t launch_fs_dense(const DenseLaunch& L, hipStream_t s);
+
 // Launchers (fs_diag.hip, ali.hip).  Return hipSuccess or the launch error.
 hipError_t launch_fs_full(int precision, int na, int wpb, int nitems, hipStream_t s,
                           const void* args, const void* angles);

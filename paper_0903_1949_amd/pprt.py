@@ -96,6 +96,8 @@ def load_library(path: str = LIB_PATH):
         "pprt_plan_info": (I, [P, C.POINTER(C.c_int64), C.POINTER(D), C.POINTER(D)]),
         "pprt_formal_solution": (I, [P, C.POINTER(FsIn), C.POINTER(FsOut)]),
         "pprt_two_level_ali_step": (I, [P, C.POINTER(FsIn), C.POINTER(TwoLevel), P, P, P, P]),
+        "pprt_plan_scattering_workspace_bytes": (I, [P, C.POINTER(C.c_size_t)]),
+        "pprt_formal_solution_scattering": (I, [P, C.POINTER(FsIn), P, C.POINTER(FsOut), P]),
         "pprt_two_level_moments": (I, [P, C.POINTER(FsIn), C.POINTER(TwoLevel), P, P, P]),
         "pprt_two_level_update": (I, [P, C.POINTER(TwoLevel), P, P, P, P]),
         "pprt_two_level_ali": (I, [P, C.POINTER(FsIn), C.POINTER(TwoLevel), C.POINTER(AliCtl),
@@ -297,6 +299,34 @@ class Plan:
         fo = FsOut(**ptrs)
         self.ctx._check(self.lib.pprt_formal_solution(self.h, C.byref(fin), C.byref(fo)),
                         "formal_solution")
+        return out
+
+    def formal_solution_scattering(self, tau, q, Sg, omega, Bbot=None, Bbot_prev=None, Itop=None,
+                                   Ibot=None, out: dict | None = None, workspace=None) -> dict:
+        """pprt_formal_solution_scattering (in-layer coherent isotropic scattering)."""
+        import torch
+        fin = self.fs_in(tau, q, Sg, Bbot, Bbot_prev, Itop, Ibot)
+        self._want(omega, (self.rows, self.nf), self.dtype, "omega")
+        R, nf, na, nb = self.rows, self.nf, self.na, self.nb
+        shapes = {"J": (R, nf), "JmS": (R, nf), "lstar": (R, nf), "lstar_c": (R, nf),
+                  "Iplus": (R, nf, na), "Iminus": (R, nf, na), "H": (R, nf), "Iemerg": (nb, nf, na)}
+        out = dict(out or {})
+        ptrs = {}
+        for bit, name in OUTPUT_NAMES.items():
+            if self.outputs & bit:
+                if name not in out:
+                    out[name] = torch.empty(shapes[name], dtype=self.dtype, device=tau.device)
+                self._want(out[name], shapes[name], self.dtype, name)
+                ptrs[name] = _ptr(out[name])
+        nbytes = C.c_size_t()
+        self.ctx._check(self.lib.pprt_plan_scattering_workspace_bytes(self.h, C.byref(nbytes)),
+                        "scattering_workspace_bytes")
+        if workspace is None:
+            workspace = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=tau.device)
+        fo = FsOut(**ptrs)
+        self.ctx._check(self.lib.pprt_formal_solution_scattering(
+            self.h, C.byref(fin), _ptr(omega), C.byref(fo), _ptr(workspace)), "formal_solution_scattering")
+        out["_workspace"] = workspace
         return out
 
     def two_level(self, eps, B, wphi):
