@@ -244,6 +244,35 @@ pprt_status pprt_two_level_moments(pprt_plan* plan, const pprt_fs_in* in,
 pprt_status pprt_two_level_update(pprt_plan* plan, const pprt_two_level* atom, double* S,
                                   double* max_rel, const int32_t* active, void* workspace);
 
+/* Two-level line on a background continuum (Sect. 3.1, items 5-6: grey
+ * continuum opacity with coherent isotropic scattering).  Per node and
+ * frequency the non-scattering source is S^g_k = p_k S_l + c_k (p_k is the
+ * line's share of the absorptive opacity, c_k the continuum's thermal part)
+ * and omega_k the continuum albedo (NULL: no scattering inside layers). */
+typedef struct pprt_continuum {
+  const void* pfrac;     /* real [rows][nf] p_k = dS^g_k / dS_l, 0 < p <= 1   */
+  const void* sg_const;  /* real [rows][nf] c_k                                */
+  const void* omega;     /* real [rows][nf] or NULL                            */
+} pprt_continuum;
+
+/* Workspace of pprt_two_level_ali_step_continuum (bytes). */
+pprt_status pprt_plan_continuum_workspace_bytes(const pprt_plan* plan, size_t* bytes);
+
+/* One operator-splitting step of the line on a continuum: S^g assembly,
+ * formal solution (with in-layer scattering when cont->omega is given: FP64
+ * plans, na in {1,2,4,8,16}), then per node the profile quadratures
+ *   Jbar - S_l = sum_k wphi_k [(J_k - S^g_k) + (S^g_k - S_l)],
+ *   1 - Lbar*  = sum_k wphi_k [(1 - p_k) + p_k (1 - Lambda*_k)]
+ * and the float64 update of pprt_two_level_ali_step.  in->Bbot/Bbot_prev are
+ * required for the diffusion lower boundary; in->Sg is ignored.  Other
+ * arguments as pprt_two_level_ali_step; the workspace is
+ * pprt_plan_continuum_workspace_bytes(). */
+pprt_status pprt_two_level_ali_step_continuum(pprt_plan* plan, const pprt_fs_in* in,
+                                              const pprt_two_level* atom,
+                                              const pprt_continuum* cont, double* S,
+                                              double* max_rel, const int32_t* active,
+                                              void* workspace);
+
 /* Iterate pprt_two_level_ali_step from the given S (device [rows], float64,
  * in/out) until every atmosphere's max relative change is below ctl->tol or
  * ctl->max_iter is reached.  Each atmosphere stops at its own convergence.

@@ -266,9 +266,9 @@ def formal_solution_dense(tau, q, S, mu, w, omega=None, Itop=None, lower="diffus
     out = {"Iplus": Ip, "Iminus": Im, "J": J, "JmS": JmS, "H": H, "Iemerg": Ip[0].copy(),
            "ops": L}
     if want_lstar:
-        lst = lstar_dense(L, dtau, R, G, mu, w)
+        lst, lstc = lstar_dense(L, dtau, R, G, mu, w)
         out["lstar"] = lst
-        out["lstar_c"] = 1.0 - lst
+        out["lstar_c"] = lstc
     return out
 
 
@@ -301,37 +301,51 @@ def _adding_backsub(L, bp, bm, top, bottom):
 
 
 def lstar_dense(L, dtau, R, G, mu, w):
-    """Diagonal Lambda* from the two-sided composites (see module doc)."""
+    """Diagonal Lambda* and its complement 1 - Lambda* from the two-sided
+    composites (see module doc).  The complement is the response of
+    J - S^g to the same unit change of S^g(d), taken through the
+    difference-form sources (+Q on the layer above the node, -Q on the layer
+    below, -1 where a boundary fixes the incoming intensity), so it keeps full
+    relative accuracy where Lambda* -> 1."""
     nl, nf, na = L["bcp"].shape
     nd = nl + 1
     I = np.eye(na)
-    # bottom-up composite: I+(d) = Rup_d I-(d) + ...; Rup at the last node is 0
     Rup = np.zeros((nd, nf, na, na))
     Gup = np.zeros((nd, nf, na, na))      # Gup[d+1] = (I - r+_b Rup[d+1])^-1 for layer b = (d, d+1)
     for d in range(nd - 2, -1, -1):
         Gup[d + 1] = np.linalg.inv(I - L["rp"][d] @ Rup[d + 1])
         Rup[d] = L["rm"][d] + L["tp"][d] @ Rup[d + 1] @ Gup[d + 1] @ L["tm"][d]
+    Q = L["bsp"] / dtau[..., None] + L["tp"] @ np.ones(na)
     lst = np.zeros((nd, nf))
+    lstc = np.zeros((nd, nf))
+    ones = np.ones((nf, na))
     for d in range(nd):
         dS = np.zeros((nf, na))
         dSu = np.zeros((nf, na))
+        eS = -ones if d == 0 else np.zeros((nf, na))          # difference form
+        eSu = -ones if d == nd - 1 else np.zeros((nf, na))
         if d > 0:                                  # layer a = (d-1, d): S^g 0 -> 1
             a = d - 1
             inv = 1.0 / dtau[a]
-            dbp = inv[:, None] * L["bsp"][a]
-            dbm = inv[:, None] * L["bsm"][a]
-            dS = _mv(L["tm"][a] @ R[d - 1] @ G[d - 1], dbp) + dbm
+            M = L["tm"][a] @ R[d - 1] @ G[d - 1]
+            dS = _mv(M, inv[:, None] * L["bsp"][a]) + inv[:, None] * L["bsm"][a]
+            eS = _mv(M, Q[a]) - Q[a]
         if d < nd - 1:                             # layer b = (d, d+1): S^g 1 -> 0
             b = d
             inv = 1.0 / dtau[b]
             dbp = L["bcp"][b] - inv[:, None] * L["bsp"][b]
             dbm = L["bcm"][b] - inv[:, None] * L["bsm"][b]
-            dSu = _mv(L["tp"][b] @ Rup[d + 1] @ Gup[d + 1], dbm) + dbp
+            M = L["tp"][b] @ Rup[d + 1] @ Gup[d + 1]
+            dSu = _mv(M, dbm) + dbp
+            eSu = _mv(M, Q[b]) - Q[b]
         A = I - Rup[d] @ R[d]
         dIp = np.linalg.solve(A, (_mv(Rup[d], dS) + dSu)[..., None])[..., 0]
         dIm = _mv(R[d], dIp) + dS
         lst[d] = 0.5 * (dIp + dIm) @ w
-    return lst
+        eDp = np.linalg.solve(A, (_mv(Rup[d], eS) + eSu)[..., None])[..., 0]
+        eDm = _mv(R[d], eDp) + eS
+        lstc[d] = -0.5 * (eDp + eDm) @ w
+    return lst, lstc
 
 
 def lambda_matrix_dense(tau, q, omega, mu, w):

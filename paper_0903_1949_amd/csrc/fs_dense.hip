@@ -44,7 +44,8 @@
 // Sigma^up of the layers below and emits the node outputs:
 //     I+ = (I - R^up R)^-1 (R^up Sigma + Sigma^up),  I- = R I+ + Sigma,
 // and the same combination of the unit-source responses of the two layers
-// that touch the node gives Lambda*_dd = dJ(d)/dS^g(d).
+// that touch the node gives Lambda*_dd = dJ(d)/dS^g(d) (plain form) and
+// 1 - Lambda*_dd (difference form, so it stays accurate as Lambda* -> 1).
 #include "pprt_internal.h"
 
 namespace pprt {
@@ -148,6 +149,34 @@ struct Grp {
           A[j] = fma(-f, buf[j], A[j]);
           X[j] = fma(-f, buf[NA + j], X[j]);
         }
+      }
+    }
+    wsync();
+  }
+  // y1, y2 with A y = b1, A y = b2; A is destroyed
+  __device__ __forceinline__ void solve2(double (&A)[NA], double& b1, double& b2) {
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+      wsync();
+      if (i == k) {
+        const double p = 1.0 / A[k];
+#pragma unroll
+        for (int j = 0; j < NA; ++j) {
+          A[j] *= p;
+          buf[j] = A[j];
+        }
+        b1 *= p;
+        b2 *= p;
+        buf[NA] = b1;
+        buf[NA + 1] = b2;
+      }
+      wsync();
+      if (i != k) {
+        const double f = A[k];
+#pragma unroll
+        for (int j = 0; j < NA; ++j) A[j] = fma(-f, buf[j], A[j]);
+        b1 = fma(-f, buf[NA], b1);
+        b2 = fma(-f, buf[NA + 1], b2);
       }
     }
     wsync();
@@ -489,6 +518,7 @@ __global__ __launch_bounds__(64) void k_fs_dense(FsDenseArgs<NA> a, DenseTab<NA>
     (void)rl;
   }
   double dSu = 0.0;           // dSigma^up of the node being emitted (layer below)
+  double eSu = -L.sw;         // its difference-form counterpart (lower boundary: -1)
   om_prev = -1.0;
   for (int d = nd - 1; d >= 0; --d) {
     const bool has_a = d >= 1;  // layer a = (d-1, d) above node d
@@ -512,8 +542,10 @@ __global__ __launch_bounds__(64) void k_fs_dense(FsDenseArgs<NA> a, DenseTab<NA>
     g.inv(Xi, X);
     const double Ip = g.mv(Xi, g.mv(Rup, Sd) + Sup);
     const double Im = g.mv(Rd, Ip) + Sd;
-    // unit response: layer above (S^g 0 -> 1) through R_{d-1}, G_{d-1}
-    double dS = 0.0;
+    // unit response: layer above (S^g 0 -> 1) through R_{d-1}, G_{d-1}; in
+    // plain form (dS, for Lambda*) and in difference form (eS, sources +-Q
+    // and -1 at a boundary, for 1 - Lambda* with full relative accuracy)
+    double dS = 0.0, eS = -L.sw;
     if (has_a) {
       double Rm[NA], Y[NA];
 #pragma unroll
@@ -521,14 +553,19 @@ __global__ __launch_bounds__(64) void k_fs_dense(FsDenseArgs<NA> a, DenseTab<NA>
       g.mul(Y, op.r, Rm);
 #pragma unroll
       for (int j = 0; j < NA; ++j) Y[j] = ((j == i) ? 1.0 : 0.0) - Y[j];
-      const double y = g.solve(Y, op.blp);          // G_{d-1} dbeta+_a
-      dS = g.mv(op.t, g.mv(Rm, y)) + op.blm;
+      double y1 = op.blp, y2 = op.qv;
+      g.solve2(Y, y1, y2);                            // G_{d-1} (dbeta+_a, Q_a)
+      dS = g.mv(op.t, g.mv(Rm, y1)) + op.blm;
+      eS = g.mv(op.t, g.mv(Rm, y2)) - op.qv;
     }
     const double dIp = g.mv(Xi, g.mv(Rup, dS) + dSu);
     const double dIm = g.mv(Rd, dIp) + dS;
+    const double eDp = g.mv(Xi, g.mv(Rup, eS) + eSu);
+    const double eDm = g.mv(Rd, eDp) + eS;
     // Ip, Im are the scaled differences D+- = sqrt(w) (I+- - S^g)
     const double JmSn = 0.5 * g.sum(L.sw * (Ip + Im));
     const double Ln = 0.5 * g.sum(L.sw * (dIp + dIm));
+    const double Lcn = -0.5 * g.sum(L.sw * (eDp + eDm));
     const double Hn = 0.5 * g.sum(L.swmu * (Ip - Im));
     {
       const int64_t x = (row0 + d) * nf + k;
@@ -537,7 +574,7 @@ __global__ __launch_bounds__(64) void k_fs_dense(FsDenseArgs<NA> a, DenseTab<NA>
         if (o & PPRT_OUT_J) a.J[x] = JmSn + S;
         if (o & PPRT_OUT_JMS) a.JmS[x] = JmSn;
         if (o & PPRT_OUT_LSTAR) a.lstar[x] = Ln;
-        if (o & PPRT_OUT_LSTAR_C) a.lstar_c[x] = 1.0 - Ln;
+        if (o & PPRT_OUT_LSTAR_C) a.lstar_c[x] = Lcn;
         if (o & PPRT_OUT_H) a.H[x] = Hn;
       }
       if (o & PPRT_OUT_IPLUS) a.Iplus[x * NA + L.ext] = Ip / L.sw + S;
@@ -561,6 +598,7 @@ __global__ __launch_bounds__(64) void k_fs_dense(FsDenseArgs<NA> a, DenseTab<NA>
       // unit response of layer a seen from node d-1 (S^g 1 -> 0)
       const double dbm = op.bc - op.blm, dbp = op.bc - op.blp;
       dSu = g.mv(op.t, g.mv(RG, dbm)) + dbp;
+      eSu = g.mv(op.t, g.mv(RG, op.qv)) - op.qv;
       double RGt[NA], tRGt[NA];
       g.mul(RGt, RG, op.t);
       g.mul(tRGt, op.t, RGt);

@@ -544,6 +544,93 @@ pprt_status pprt_two_level_update(pprt_plan* p, const pprt_two_level* at, double
   return ali_update_impl(p, at, S, max_rel, const_cast<int32_t*>(active), nullptr, 0.0, ws);
 }
 
+// workspace of the continuum step: [Sg | JmS | Lc | part(rows x 4 doubles) | dense ws]
+static void continuum_layout(const pprt_plan* p, size_t off[6]) {
+  const size_t es = p->precision == PPRT_FP64 ? sizeof(double) : sizeof(float);
+  const size_t arr = align256((size_t)p->rows * p->nf * es);
+  off[0] = 0;
+  off[1] = off[0] + arr;
+  off[2] = off[1] + arr;
+  off[3] = off[2] + arr;
+  off[4] = off[3] + align256((size_t)p->rows * 4 * sizeof(double));
+  off[5] = off[4] + (dense_na_supported(p->na) && p->precision == PPRT_FP64
+                         ? align256(dense_workspace_bytes(p->na, p->rows, p->nf)) : 0);
+}
+
+pprt_status pprt_plan_continuum_workspace_bytes(const pprt_plan* p, size_t* bytes) {
+  if (!p || !bytes) return PPRT_E_INVALID_ARG;
+  size_t off[6];
+  continuum_layout(p, off);
+  *bytes = off[5];
+  return PPRT_OK;
+}
+
+pprt_status pprt_two_level_ali_step_continuum(pprt_plan* p, const pprt_fs_in* in,
+                                              const pprt_two_level* at, const pprt_continuum* ct,
+                                              double* S, double* max_rel, const int32_t* active,
+                                              void* ws) {
+  if (!p) return PPRT_E_INVALID_ARG;
+  pprt_ctx* c = p->ctx;
+  if (!in || !at || !ct || !S || !max_rel) return fail(c, PPRT_E_INVALID_ARG, "null argument");
+  if (!in->tau || !in->q || !ct->pfrac || !ct->sg_const)
+    return fail(c, PPRT_E_INVALID_ARG, "tau, q, pfrac and sg_const are required");
+  if (!at->eps || !at->B || !at->wphi) return fail(c, PPRT_E_INVALID_ARG, "atom needs eps, B and wphi");
+  if (p->lower_bc == PPRT_BC_DIFFUSION && (!in->Bbot || !in->Bbot_prev))
+    return fail(c, PPRT_E_INVALID_ARG, "diffusion lower boundary needs Bbot and Bbot_prev");
+  if (!ws) return fail(c, PPRT_E_WORKSPACE, "workspace required (pprt_plan_continuum_workspace_bytes)");
+  if (ct->omega && (p->precision != PPRT_FP64 || !dense_na_supported(p->na)))
+    return fail(c, PPRT_E_UNSUPPORTED, "in-layer scattering needs an FP64 plan and na in {1,2,4,8,16}");
+  size_t off[6];
+  continuum_layout(p, off);
+  char* base = (char*)ws;
+  void* Sg = base + off[0];
+  void* JmS = base + off[1];
+  void* Lc = base + off[2];
+  double* part = (double*)(base + off[3]);
+  pprt_status r = hip_check(c, launch_sg_assemble(p->precision, S, ct->pfrac, ct->sg_const, Sg,
+                                                  p->rows, p->nf, c->stream), "S^g assembly");
+  if (r != PPRT_OK) return r;
+  hipError_t e;
+  if (ct->omega) {
+    DenseLaunch L{};
+    L.items = p->d_items_dense; L.off = p->d_off; L.tau = in->tau; L.q = (const double*)in->q;
+    L.Sg = (const double*)Sg; L.omega = (const double*)ct->omega; L.Itop = (const double*)in->Itop;
+    L.Bbot = (const double*)in->Bbot; L.Bbot_prev = (const double*)in->Bbot_prev;
+    L.Ibot = (const double*)in->Ibot;
+    L.JmS = (double*)JmS; L.lstar_c = (double*)Lc;
+    L.ws = (double*)(base + off[4]); L.rows = p->rows; L.nf = p->nf; L.na = p->na;
+    L.nitems = p->n_dense; L.lower_bc = p->lower_bc; L.outputs = PPRT_OUT_JMS | PPRT_OUT_LSTAR_C;
+    L.mu = p->mu.data(); L.w = p->w.data();
+    e = launch_fs_dense(L, c->stream);
+  } else if (p->precision == PPRT_FP64) {
+    FsFullArgs<double> a{};
+    a.items = p->d_items_full; a.off = p->d_off; a.tau = in->tau; a.q = (const double*)in->q;
+    a.Sg = (const double*)Sg; a.Itop = (const double*)in->Itop; a.Bbot = (const double*)in->Bbot;
+    a.Bbot_prev = (const double*)in->Bbot_prev; a.Ibot = (const double*)in->Ibot;
+    a.JmS = (double*)JmS; a.lstar_c = (double*)Lc;
+    a.nf = p->nf; a.lower_bc = p->lower_bc; a.outputs = PPRT_OUT_JMS | PPRT_OUT_LSTAR_C;
+    e = launch_fs_full(p->precision, p->na, p->wpb, p->n_full, c->stream, &a, angles_of(p));
+  } else {
+    FsFullArgs<float> a{};
+    a.items = p->d_items_full; a.off = p->d_off; a.tau = in->tau; a.q = (const float*)in->q;
+    a.Sg = (const float*)Sg; a.Itop = (const float*)in->Itop; a.Bbot = (const float*)in->Bbot;
+    a.Bbot_prev = (const float*)in->Bbot_prev; a.Ibot = (const float*)in->Ibot;
+    a.JmS = (float*)JmS; a.lstar_c = (float*)Lc;
+    a.nf = p->nf; a.lower_bc = p->lower_bc; a.outputs = PPRT_OUT_JMS | PPRT_OUT_LSTAR_C;
+    e = launch_fs_full(p->precision, p->na, p->wpb, p->n_full, c->stream, &a, angles_of(p));
+  }
+  r = hip_check(c, e, "continuum formal-solution launch");
+  if (r != PPRT_OK) return r;
+  r = hip_check(c, launch_profile_reduce(p->precision, S, JmS, Lc, Sg, ct->pfrac, at->wphi, part,
+                                         p->rows, p->nf, c->stream), "profile reduction");
+  if (r != PPRT_OK) return r;
+  AliUpdateArgs u{};
+  u.off = p->d_off; u.part = part; u.eps = at->eps; u.B = at->B; u.S = S; u.max_rel = max_rel;
+  u.active = const_cast<int32_t*>(active); u.iters = nullptr; u.status = c->d_status; u.tol = 0.0;
+  u.nw = 1; u.nb = p->nb; u.part_fp64 = 1;
+  return hip_check(c, launch_ali_update(p->nb, c->stream, u), "ALI update launch");
+}
+
 pprt_status pprt_two_level_ali(pprt_plan* p, const pprt_fs_in* in, const pprt_two_level* at,
                                const pprt_ali_ctl* ctl, double* S, int32_t* iters,
                                pprt_ali_report* rep, void* ws) {

@@ -118,6 +118,11 @@ hipError_t launch_fs_profile(int precision, int na, int wpb, int nitems, hipStre
                              const void* args, const void* angles);
 hipError_t launch_ali_update(int nb, hipStream_t s, const AliUpdateArgs& a);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+hipError_t launch_sg_assemble(int precision, const double* S, const void* p, const void* c, void* Sg,
+                              int64_t rows, int nf, hipStream_t s);
+hipError_t launch_profile_reduce(int precision, const double* S, const void* JmS, const void* Lc,
+                                 const void* Sg, const void* p, const void* wphi, double* part,
+                                 int64_t rows, int nf, hipStream_t s);
 
 bool na_supported(int na);
 

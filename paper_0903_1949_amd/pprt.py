@@ -58,6 +58,10 @@ class TwoLevel(C.Structure):
     _fields_ = [("eps", C.c_void_p), ("B", C.c_void_p), ("wphi", C.c_void_p)]
 
 
+class Continuum(C.Structure):
+    _fields_ = [("pfrac", C.c_void_p), ("sg_const", C.c_void_p), ("omega", C.c_void_p)]
+
+
 class AliCtl(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("iters_per_sync", C.c_int32),
                 ("use_graph", C.c_int32)]
@@ -98,6 +102,9 @@ def load_library(path: str = LIB_PATH):
         "pprt_two_level_ali_step": (I, [P, C.POINTER(FsIn), C.POINTER(TwoLevel), P, P, P, P]),
         "pprt_plan_scattering_workspace_bytes": (I, [P, C.POINTER(C.c_size_t)]),
         "pprt_formal_solution_scattering": (I, [P, C.POINTER(FsIn), P, C.POINTER(FsOut), P]),
+        "pprt_plan_continuum_workspace_bytes": (I, [P, C.POINTER(C.c_size_t)]),
+        "pprt_two_level_ali_step_continuum": (I, [P, C.POINTER(FsIn), C.POINTER(TwoLevel),
+                                                  C.POINTER(Continuum), P, P, P, P]),
         "pprt_two_level_moments": (I, [P, C.POINTER(FsIn), C.POINTER(TwoLevel), P, P, P]),
         "pprt_two_level_update": (I, [P, C.POINTER(TwoLevel), P, P, P, P]),
         "pprt_two_level_ali": (I, [P, C.POINTER(FsIn), C.POINTER(TwoLevel), C.POINTER(AliCtl),
@@ -349,6 +356,33 @@ class Plan:
         self.ctx._check(self.lib.pprt_two_level_ali_step(
             self.h, C.byref(fin), C.byref(at), _ptr(S), _ptr(max_rel), _ptr(active),
             _ptr(self.workspace())), "two_level_ali_step")
+
+    def two_level_ali_step_continuum(self, tau, q, S, eps, B, wphi, pfrac, sg_const, omega,
+                                     Bbot, Bbot_prev, max_rel, active=None, Itop=None, Ibot=None,
+                                     workspace=None):
+        """pprt_two_level_ali_step_continuum: S^g assembly, formal solution
+        (with in-layer scattering if omega is given), profile quadratures and
+        the OS update, S in place."""
+        import torch
+        fin = self.fs_in(tau, q, None, Bbot, Bbot_prev, Itop, Ibot)
+        at = self.two_level(eps, B, wphi)
+        for name, t in (("pfrac", pfrac), ("sg_const", sg_const)):
+            self._want(t, (self.rows, self.nf), self.dtype, name)
+        if omega is not None:
+            self._want(omega, (self.rows, self.nf), self.dtype, "omega")
+        self._want(S, (self.rows,), torch.float64, "S")
+        self._want(max_rel, (self.nb,), torch.float64, "max_rel")
+        if workspace is None:
+            nbytes = C.c_size_t()
+            self.ctx._check(self.lib.pprt_plan_continuum_workspace_bytes(self.h, C.byref(nbytes)),
+                            "continuum_workspace_bytes")
+            if getattr(self, "_cws", None) is None or self._cws.numel() < nbytes.value:
+                self._cws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=S.device)
+            workspace = self._cws
+        ct = Continuum(_ptr(pfrac), _ptr(sg_const), _ptr(omega))
+        self.ctx._check(self.lib.pprt_two_level_ali_step_continuum(
+            self.h, C.byref(fin), C.byref(at), C.byref(ct), _ptr(S), _ptr(max_rel), _ptr(active),
+            _ptr(workspace)), "two_level_ali_step_continuum")
 
     def two_level_moments(self, tau, q, S, eps, B, wphi, active=None, Itop=None, Ibot=None):
         """pprt_two_level_moments: the formal-solution half of an ALI step."""

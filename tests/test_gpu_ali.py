@@ -90,3 +90,78 @@ def test_ali_converged_batch_fp32(gpu_ctx):
               flush=True)
         assert abs(int(iters[b]) - ref["iterations"]) <= max(3, ref["iterations"] // 50)
         assert e < 1e-4
+
+
+def _cont_device(batch, prec):
+    dt = torch.float64 if prec == pprt.FP64 else torch.float32
+    d = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda:0")
+    return d(batch.pfrac), d(batch.sg_const), (None if batch.omega is None else d(batch.omega))
+
+
+def _oracle_one_step(batch, S0, mu, w, scattering):
+    from oracle import dense
+    off = batch.off
+    out = np.zeros_like(S0)
+    for b in range(batch.nb):
+        s = slice(off[b], off[b + 1])
+        fs = dense.formal_solution_dense if scattering else formal.formal_solution
+        kw = {"omega": batch.omega[s]} if scattering else {}
+        r = ali.two_level_ali(batch.tau[s], batch.q[s], batch.phi, batch.wnu, float(batch.eps[b]),
+                              batch.B[s], mu, w, tol=1e-300, max_iter=1, S0=S0[s],
+                              pfrac=batch.pfrac[s], sg_const=batch.sg_const[s], fs=fs, fs_kwargs=kw)
+        out[s] = r["S"]
+    return out
+
+
+@pytest.mark.parametrize("scattering,prec,tol", [(True, pprt.FP64, 1e-10), (False, pprt.FP64, 1e-10),
+                                                 (False, pprt.FP32, 2e-5)])
+def test_continuum_step_parity(gpu_ctx, scattering, prec, tol):
+    """Line on a grey continuum (r_c = 1e-2, eps_c = 1e-2; with coherent
+    scattering inside the layers or, without it, a purely absorbing one)."""
+    batch = W.two_level_batch(nb=3, nd_lo=8, nd_hi=40, na=8, nf=40, seed=21, cont_ratio=1e-2,
+                              eps_c=1e-2 if scattering else 1.0, x_max=4.0)
+    if not scattering:
+        batch.omega = None
+    print(f"[case] continuum step scattering={scattering} prec={prec}", flush=True)
+    plan = pprt.Plan(gpu_ctx, batch.nd, batch.na, batch.nf, precision=prec)
+    db = pprt.upload_two_level(batch, prec)
+    pf, sc, om = _cont_device(batch, prec)
+    S0 = batch.S_trial.copy()
+    mx = torch.zeros(batch.nb, dtype=torch.float64, device="cuda:0")
+    plan.two_level_ali_step_continuum(db.tau, db.q, db.S, db.eps, db.B, db.wphi, pf, sc, om,
+                                      db.Bbot, db.Bbot_prev, mx)
+    torch.cuda.synchronize()
+    ref = _oracle_one_step(batch, S0, plan.mu, plan.w, scattering)
+    e = rel_err(db.S.cpu().numpy(), ref)
+    e_d = rel_err(db.S.cpu().numpy() - S0, ref - S0)
+    print(f"  S {e:.2e}  dS {e_d:.2e}", flush=True)
+    assert e < tol
+    if prec == pprt.FP64:
+        assert e_d < 1e-9
+
+
+def test_continuum_ali_converges_to_oracle(gpu_ctx):
+    """Iterate the dense-continuum step on the GPU to 1e-10 and compare with
+    the oracle's converged source function."""
+    from oracle import dense
+    batch = W.two_level_batch(nb=1, nd_lo=30, nd_hi=30, na=4, nf=21, seed=5, cont_ratio=1e-2,
+                              eps_c=1e-2, x_max=4.0, eps_lo=1e-2, eps_hi=1e-2)
+    plan = pprt.Plan(gpu_ctx, batch.nd, batch.na, batch.nf, precision=pprt.FP64)
+    db = pprt.upload_two_level(batch, pprt.FP64)
+    db.S.copy_(db.B)
+    pf, sc, om = _cont_device(batch, pprt.FP64)
+    mx = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    its = 0
+    for its in range(1, 3001):
+        plan.two_level_ali_step_continuum(db.tau, db.q, db.S, db.eps, db.B, db.wphi, pf, sc, om,
+                                          db.Bbot, db.Bbot_prev, mx)
+        if its % 50 == 0 and float(mx.item()) < 1e-10:
+            break
+    torch.cuda.synchronize()
+    ref = ali.two_level_ali(batch.tau, batch.q, batch.phi, batch.wnu, float(batch.eps[0]), batch.B,
+                            plan.mu, plan.w, tol=1e-12, max_iter=5000, pfrac=batch.pfrac,
+                            sg_const=batch.sg_const, fs=dense.formal_solution_dense,
+                            fs_kwargs={"omega": batch.omega})
+    e = rel_err(db.S.cpu().numpy(), ref["S"])
+    print(f"  gpu iterations {its}, oracle {ref['iterations']}, S err {e:.2e}", flush=True)
+    assert e < 1e-8

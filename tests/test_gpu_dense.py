@@ -96,7 +96,7 @@ def test_scattering_with_zero_albedo_equals_diagonal_path(gpu_ctx):
     torch.cuda.synchronize()
     for k in KEYS:
         e = rel_err(got[k], out[k].cpu().numpy())
-        assert e < 1e-12, (k, e)
+        assert e < 1e-11, (k, e)
 
 
 @pytest.mark.parametrize("omega", [0.5, 0.99, 0.9999])

@@ -152,6 +152,7 @@ def test_dense_lstar_equals_brute_force(nd, nf, na, seed):
     out = dense.formal_solution_dense(tau, q, S, mu, w, omega=om, lower="given")
     diag = np.stack([np.diag(Lm[k]) for k in range(nf)], axis=1)
     assert np.max(np.abs(out["lstar"] - diag)) < 1e-13
+    assert np.max(np.abs(out["lstar_c"] - (1.0 - diag))) < 1e-13
     # linearity: the Lambda matrix reproduces J for zero boundary light
     J = np.einsum("kij,jk->ik", Lm, S)
     assert np.max(np.abs(out["J"] - J)) < 1e-13
@@ -195,3 +196,18 @@ def test_two_level_with_continuum_ali_fixed_point():
     J0 = zero["J"] @ wp
     Sd = np.linalg.solve(np.eye(nd) - (1 - eps) * Lbar, (1 - eps) * J0 + eps * b.B)
     assert np.max(np.abs(r["S"] - Sd) / Sd) < 1e-10
+
+
+def test_dense_lstar_complement_keeps_relative_accuracy():
+    """Thick layers: 1 - Lambda* is tiny and must keep its relative accuracy.
+    With omega = 0 it equals the short-characteristic complement
+    1/2 sum w (psi_above + psi_below) exactly; with omega > 0 it must sit
+    between the omega = 0 value scaled by (1 - omega) and the omega = 0 value."""
+    mu, w = gauss_legendre01(4)
+    tau = np.array([1.0, 2e4, 4e4, 6e4, 8e4])
+    nd = tau.shape[0]
+    q = np.ones((nd, 1))
+    o0 = dense.formal_solution_dense(tau, q, np.ones(nd), mu, w, omega=np.zeros((nd, 1)), lower="given")
+    f0 = formal.formal_solution(tau, q, np.ones(nd), mu, w, lower="given")
+    assert np.max(np.abs(o0["lstar_c"][1:-1] / f0["lstar_c"][1:-1] - 1)) < 1e-12
+    assert f0["lstar_c"][2, 0] < 1e-4
