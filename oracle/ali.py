@@ -37,7 +37,7 @@ def _sg(S_l, pfrac, sg_const, nf):
 def profile_moments(out, S_l, Sg, phi, wnu, pfrac=None):
     """(Jbar - S_l, 1 - Lbar*) per depth from one formal solution."""
     wp = np.asarray(wnu) * np.asarray(phi)
-    jms = out["J"] - Sg                                   # J_k - S^g_k
+    jms = out["JmS"]                                      # J_k - S^g_k
     if pfrac is None:
         jbar_m_s = jms @ wp
         one_m_lbar = out["lstar_c"] @ wp

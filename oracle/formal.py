@@ -21,7 +21,9 @@ its Papers I-II, Sect. 2):
   I+(bottom, mu) = B(ND) + mu (B(ND) - B(ND-1)) / dtau_k(ND-1/2)
   or a given intensity.
 * Angle moments with Gauss weights w (sum 1) per hemisphere:
-  J = 1/2 sum w (I+ + I-),  H = 1/2 sum w mu (I+ - I-).
+  J = 1/2 sum w (I+ + I-),  H = 1/2 sum w mu (I+ - I-).  J - S and H are
+  taken from the same recursion written for D = I - S (algebraically
+  identical), which keeps them accurate where they are small.
 * Lambda*: the exact diagonal of the discrete Lambda operator,
   Lambda_dd = dJ(d)/dS(d) = 1/2 sum w [alpha(Delta_{d+1/2}) [d<ND] + alpha(Delta_{d-1/2}) [d>1]],
   and its complement 1 - Lambda_dd, formed from 1 - alpha = (1-e)/Delta so
@@ -129,7 +131,20 @@ def formal_solution(tau, q, S, mu, w, Itop=None, lower="diffusion", Bbot=None,
         Im[d + 1] = e[d] * Im[d] + alpha[d] * Sk[d + 1] + gamma[d] * Sk[d]
 
     J = 0.5 * np.einsum("dki,i->dk", Ip + Im, w)
-    H = 0.5 * np.einsum("dki,i->dk", Ip - Im, w * mu)
+    # J - S and H also from the same recursion written for D = I - S:
+    #   D+(d) = e D+(d+1) + psi (S(d+1) - S(d)),  D-(d+1) = e D-(d) + psi (S(d) - S(d+1))
+    # (substitute alpha = 1 - psi, gamma = psi - e above); where J ~ S deep in
+    # the atmosphere this keeps the small difference's relative accuracy.
+    Dp = np.zeros((nd, nf, na))
+    Dm = np.zeros((nd, nf, na))
+    Dp[nd - 1] = Ip[nd - 1] - Sk[nd - 1]
+    Dm[0] = Im[0] - Sk[0]
+    for d in range(nd - 2, -1, -1):
+        Dp[d] = e[d] * Dp[d + 1] + psi[d] * (Sk[d + 1] - Sk[d])
+    for d in range(0, nd - 1):
+        Dm[d + 1] = e[d] * Dm[d] + psi[d] * (Sk[d] - Sk[d + 1])
+    JmS = 0.5 * np.einsum("dki,i->dk", Dp + Dm, w)
+    H = 0.5 * np.einsum("dki,i->dk", Dp - Dm, w * mu)
     lstar = np.zeros((nd, nf))
     lstar_c = np.zeros((nd, nf))
     half_w = 0.5 * w
@@ -144,7 +159,7 @@ def formal_solution(tau, q, S, mu, w, Itop=None, lower="diffusion", Bbot=None,
     lstar_c[0] += 0.5 * np.sum(w)
     lstar_c[nd - 1] += 0.5 * np.sum(w)
     return {
-        "Iplus": Ip, "Iminus": Im, "J": J, "JmS": J - S, "H": H,
+        "Iplus": Ip, "Iminus": Im, "J": J, "JmS": JmS, "H": H,
         "lstar": lstar, "lstar_c": lstar_c, "Iemerg": Ip[0].copy(),
     }
 

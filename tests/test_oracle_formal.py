@@ -159,3 +159,22 @@ def test_constant_source_top_mean_intensity():
     assert abs(out["J"][0, 0] - 0.5) < 1e-15
     assert abs(out["JmS"][0, 0] + 0.5) < 1e-15
     assert np.allclose(out["J"][-1], 1.0, atol=1e-15)
+
+
+def test_difference_form_moments_match_plain_form():
+    """J - S and H from the difference-form recursion equal J - S and H from
+    the plain-form intensities to rounding relative to |S|; with constant S
+    deep in a thick slab the difference form gives exactly zero."""
+    rng = np.random.default_rng(8)
+    nd, nf = 40, 6
+    tau = np.logspace(-4, 4, nd)
+    q = rng.lognormal(0, 0.5, size=(nd, nf))
+    S = rng.uniform(0.5, 1.5, size=(nd, nf))
+    mu, w = gauss_legendre01(6)
+    out = formal.formal_solution(tau, q, S, mu, w, lower="diffusion", Bbot=S[-1], Bbot_prev=S[-2])
+    assert np.max(np.abs(out["JmS"] - (out["J"] - S))) < 1e-14 * np.abs(S).max()
+    H = 0.5 * np.einsum("dki,i->dk", out["Iplus"] - out["Iminus"], w * mu)
+    assert np.max(np.abs(out["H"] - H)) < 1e-14 * np.abs(S).max()
+    c = formal.formal_solution(tau, np.ones((nd, 1)), np.full(nd, 0.8), mu, w, lower="diffusion",
+                               Bbot=np.full(1, 0.8), Bbot_prev=np.full(1, 0.8))
+    assert np.all(c["JmS"][tau > 100] == 0.0)
