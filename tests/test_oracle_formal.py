@@ -164,7 +164,7 @@ def test_constant_source_top_mean_intensity():
 def test_difference_form_moments_match_plain_form():
     """J - S and H from the difference-form recursion equal J - S and H from
     the plain-form intensities to rounding relative to |S|; with constant S
-    deep in a thick slab the difference form gives exactly zero."""
+    deep in a thick slab the difference form carries no rounding leak."""
     rng = np.random.default_rng(8)
     nd, nf = 40, 6
     tau = np.logspace(-4, 4, nd)
@@ -177,4 +177,6 @@ def test_difference_form_moments_match_plain_form():
     assert np.max(np.abs(out["H"] - H)) < 1e-14 * np.abs(S).max()
     c = formal.formal_solution(tau, np.ones((nd, 1)), np.full(nd, 0.8), mu, w, lower="diffusion",
                                Bbot=np.full(1, 0.8), Bbot_prev=np.full(1, 0.8))
-    assert np.all(c["JmS"][tau > 100] == 0.0)
+    # deep down only the top boundary's exponentially small deficit remains:
+    # no rounding "leak" of order 1e-16 |S|, which J - S by subtraction carries
+    assert np.all(np.abs(c["JmS"][tau > 100]) < 1e-60)
