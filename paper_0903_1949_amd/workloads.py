@@ -197,3 +197,204 @@ def random_slab(nd=9, nf=3, seed=0, tau_lo=1e-3, tau_hi=1e2, q_sigma=0.7,
     Bb = rng.uniform(s_lo, s_hi, size=nf)
     Bp = rng.uniform(s_lo, s_hi, size=nf)
     return tau, q, S, Bb, Bp
+
+
+# ---------------------------------------------------------------------------
+# Multilevel model atom (hydrogen-like) on a grey atmosphere.
+#
+# Reduced units: frequencies in units of the ionisation energy (13.6 eV),
+# opacities per unit reference optical depth (the grey continuum defines it,
+# chi_ref = kappa_c + sigma_c = 1 per unit tau_ref), b_k = nu_k^3 stands for
+# 2 h nu^3 / c^2 and the radiative-rate weight is W_k = w_k / nu_k (the common
+# factor 4 pi / h multiplies every radiative and collisional rate alike).
+# Each frequency point belongs to exactly one transition (its "window");
+# transitions do not overlap in frequency (a builder's simplification).
+@dataclass
+class MultiLevelAtom:
+    nd: np.ndarray            # [nb] int32
+    tau: np.ndarray           # [rows] reference optical depth
+    T: np.ndarray             # [rows] temperature (K)
+    na: int
+    # levels
+    g: np.ndarray             # [nl]
+    E: np.ndarray             # [nl] energy (units of 13.6 eV); ion last
+    # transitions
+    lo: np.ndarray            # [nt] int32 lower level
+    up: np.ndarray            # [nt] int32 upper level
+    kind: np.ndarray          # [nt] 0 line, 1 bound-free
+    k0: np.ndarray            # [nt] first frequency of the window
+    k1: np.ndarray            # [nt] one past the last
+    # frequency grid
+    nu: np.ndarray            # [nf]
+    wnu: np.ndarray           # [nf] trapezoid weights in nu within each window
+    owner: np.ndarray         # [nf] int32 transition owning the frequency
+    sigma: np.ndarray         # [nf] cross-section of the owning transition
+    bfac: np.ndarray          # [nf] b = nu0^3 (lines) or nu^3 (continua)
+    W: np.ndarray             # [nf] w_k / nu_k
+    # depth-dependent data
+    Gst: np.ndarray           # [rows, nf] stimulated-emission factor G
+    Bnu: np.ndarray           # [rows, nf] Planck function (reduced)
+    kc: np.ndarray            # [rows] continuum absorption per unit tau_ref (eps_c)
+    sc: np.ndarray            # [rows] continuum scattering per unit tau_ref (1 - eps_c)
+    nstar: np.ndarray         # [rows, nl] LTE populations
+    ntot: np.ndarray          # [rows]
+    Cul: np.ndarray           # [rows, nt] downward collision rates
+    Clu: np.ndarray           # [rows, nt] upward collision rates (detailed balance)
+    name: str = ""
+
+    @property
+    def nb(self):
+        return int(self.nd.shape[0])
+
+    @property
+    def nf(self):
+        return int(self.nu.shape[0])
+
+    @property
+    def nl(self):
+        return int(self.g.shape[0])
+
+    @property
+    def nt(self):
+        return int(self.lo.shape[0])
+
+    @property
+    def off(self):
+        o = np.zeros(self.nb + 1, dtype=np.int64)
+        o[1:] = np.cumsum(self.nd)
+        return o
+
+
+_KB_EV = 8.617333262e-5     # Boltzmann constant, eV/K
+_RY_EV = 13.605693          # ionisation energy of hydrogen, eV
+_SAHA = 2.0706e-16          # (h^2 / (2 pi m_e k))^(3/2) in cm^3 K^(3/2), hydrogen-like factor
+
+
+def multilevel_atom(nbound=6, ncont=5, nd=128, na=8, nline_pts=100, ncont_pts=100,
+                    tau_lo=1e-6, tau_hi=1e2, teff=5800.0, eps_c=1e-2, strength_lo=1e-2,
+                    strength_hi=1e4, a_lo=1e-3, a_hi=1e-2, x_max=50.0, coll_scale=1e-3,
+                    line_pairs=None, nb=1, seed=2) -> MultiLevelAtom:
+    """Hydrogen-like atom with `nbound` bound levels (E_i = 1 - 1/i^2,
+    g_i = 2 i^2) and a continuum level, all bound-bound pairs as lines (or
+    `line_pairs`) and bound-free continua from levels 1..ncont, on a grey
+    Eddington atmosphere T = Teff (3/4 (tau + 2/3))^(1/4).
+
+    Line strengths: LTE line-centre chi_l / chi_c at tau_ref = 1,
+    log-uniform on [strength_lo, strength_hi]; Voigt damping a uniform on
+    [a_lo, a_hi]; each line sampled by nline_pts points symmetric about the
+    centre and concentrated in the core (x = x_max sinh-spaced).  Continua:
+    hydrogenic nu^-3 cross-sections from the edge to 4x the edge on
+    ncont_pts log-spaced points, strength at the edge log-uniform in
+    [0.1, 10] (times chi_c at tau_ref = 1).  Collisions: C_ul = A_ul *
+    coll_scale * tau_ref, C_lu by detailed balance.  n_tot = 1e14 tau_ref,
+    n_e = 1e13 sqrt(tau_ref) (cm^-3, builder's choice).  nb identical
+    atmospheres are stacked when nb > 1 (a batch of the same model)."""
+    from scipy.special import wofz
+
+    rng = np.random.default_rng(seed)
+    nl = nbound + 1
+    lev = np.arange(1, nbound + 1)
+    g = np.concatenate([2.0 * lev ** 2, [1.0]])
+    E = np.concatenate([1.0 - 1.0 / lev ** 2, [1.0]])
+    pairs = line_pairs if line_pairs is not None else [(i, j) for i in range(nbound) for j in range(i + 1, nbound)]
+    lo, up, kind = [], [], []
+    for (i, j) in pairs:
+        lo.append(i); up.append(j); kind.append(0)
+    for i in range(ncont):
+        lo.append(i); up.append(nl - 1); kind.append(1)
+    lo = np.array(lo, np.int32); up = np.array(up, np.int32); kind = np.array(kind, np.int32)
+    nt = lo.shape[0]
+    # depth structure
+    tau = log_tau(nd, tau_lo, tau_hi)
+    T = teff * (0.75 * (tau + 2.0 / 3.0)) ** 0.25
+    kT = _KB_EV * T / _RY_EV                        # kT in units of 13.6 eV
+    ntot = 1e14 * tau
+    ne = 1e13 * np.sqrt(tau)
+    # LTE populations: Boltzmann within bound levels, Saha to the continuum
+    bound_rel = g[None, :nbound] * np.exp(-(E[None, :nbound] - E[0]) / kT[:, None])   # n_i / (n_1/g_1 ...)
+    # n_i / n_ion = g_i / g_ion * n_e * Phi(T) * exp((E_ion - E_i)/kT),  Phi = _SAHA T^-3/2 / 2
+    phi_s = 0.5 * _SAHA * T ** -1.5
+    ratio = g[None, :nbound] / g[nl - 1] * (ne * phi_s)[:, None] * np.exp((E[nl - 1] - E[None, :nbound]) / kT[:, None])
+    nion = ntot / (1.0 + ratio.sum(axis=1))
+    nstar = np.empty((nd, nl))
+    nstar[:, :nbound] = ratio * nion[:, None]
+    nstar[:, nl - 1] = nion
+    del bound_rel
+    # frequency windows
+    nus, ws, owner, sig, bfac = [], [], [], [], []
+    k0 = np.zeros(nt, np.int32); k1 = np.zeros(nt, np.int32)
+    kpos = 0
+    i1 = int(np.argmin(np.abs(tau - 1.0)))
+    strengths = np.exp(rng.uniform(math.log(strength_lo), math.log(strength_hi), size=nt))
+    damp = rng.uniform(a_lo, a_hi, size=nt)
+    cstr = np.exp(rng.uniform(math.log(0.1), math.log(10.0), size=nt))
+    for t in range(nt):
+        l, u = int(lo[t]), int(up[t])
+        if kind[t] == 0:
+            nu0 = E[u] - E[l]
+            dop = 1e-4 * nu0                        # Doppler width (builder's choice)
+            s = np.sinh(np.linspace(-math.asinh(x_max), math.asinh(x_max), nline_pts))
+            nu = nu0 + dop * s
+            prof = np.real(wofz(s + 1j * damp[t])) / math.sqrt(math.pi) / dop      # Voigt, per unit nu
+            w = _trapz_weights(nu)
+            prof = prof / np.sum(w * prof)          # normalised on the discrete grid
+            # line-centre LTE opacity ratio at tau_ref = 1 sets the strength
+            centre = prof[nline_pts // 2]
+            Gc = g[l] / g[u]
+            stim = 1.0 - nstar[i1, u] * Gc / nstar[i1, l]
+            s_t = strengths[t] / (nstar[i1, l] * centre * stim)
+            sigma = s_t * prof
+            b = np.full(nline_pts, nu0 ** 3)
+        else:
+            edge = E[u] - E[l]
+            nu = np.geomspace(edge, 4.0 * edge, ncont_pts)
+            w = _trapz_weights(nu)
+            stim = 1.0 - math.exp(-edge / kT[i1])
+            s_t = cstr[t] / (nstar[i1, l] * stim)
+            sigma = s_t * (edge / nu) ** 3
+            b = nu ** 3
+        k0[t] = kpos
+        kpos += nu.shape[0]
+        k1[t] = kpos
+        nus.append(nu); ws.append(w); owner.append(np.full(nu.shape[0], t, np.int32))
+        sig.append(sigma); bfac.append(b)
+    nu = np.concatenate(nus); wnu = np.concatenate(ws); owner = np.concatenate(owner)
+    sigma = np.concatenate(sig); bfac = np.concatenate(bfac)
+    W = wnu / nu
+    nf = nu.shape[0]
+    # stimulated-emission factor and Planck function per (depth, frequency)
+    Gst = np.empty((nd, nf))
+    for t in range(nt):
+        sl = slice(k0[t], k1[t])
+        l, u = int(lo[t]), int(up[t])
+        if kind[t] == 0:
+            Gst[:, sl] = g[l] / g[u]
+        else:
+            Gst[:, sl] = (nstar[:, l] / nstar[:, u])[:, None] * np.exp(-nu[None, sl] / kT[:, None])
+    Bnu = nu[None, :] ** 3 / np.expm1(nu[None, :] / kT[:, None])
+    # collisions: A_ul = sum_k W_k b_k G_k sigma_k (depth-independent part of lines;
+    # for continua evaluated with the local G)
+    Cul = np.empty((nd, nt))
+    Clu = np.empty((nd, nt))
+    for t in range(nt):
+        sl = slice(k0[t], k1[t])
+        A = np.sum(W[None, sl] * bfac[None, sl] * Gst[:, sl] * sigma[None, sl], axis=1)
+        Cul[:, t] = A * coll_scale * tau
+        Clu[:, t] = Cul[:, t] * nstar[:, up[t]] / nstar[:, lo[t]]
+    kc = np.full(nd, eps_c)
+    sc = np.full(nd, 1.0 - eps_c)
+    rep = lambda a: np.concatenate([a] * nb, axis=0) if nb > 1 else a
+    return MultiLevelAtom(
+        nd=np.full(nb, nd, np.int32), tau=rep(tau), T=rep(T), na=na, g=g, E=E, lo=lo, up=up,
+        kind=kind, k0=k0, k1=k1, nu=nu, wnu=wnu, owner=owner, sigma=sigma, bfac=bfac, W=W,
+        Gst=rep(Gst), Bnu=rep(Bnu), kc=rep(kc), sc=rep(sc), nstar=rep(nstar), ntot=rep(ntot),
+        Cul=rep(Cul), Clu=rep(Clu),
+        name=f"{nl}-level atom ({nt} transitions), nd={nd}, nf={nf}, na={na}")
+
+
+def _trapz_weights(x):
+    w = np.zeros_like(x)
+    d = np.diff(x)
+    w[:-1] += 0.5 * d
+    w[1:] += 0.5 * d
+    return w
