@@ -285,6 +285,78 @@ pprt_status pprt_two_level_ali(pprt_plan* plan, const pprt_fs_in* in,
                                double* S, int32_t* iters, pprt_ali_report* report,
                                void* workspace);
 
+/* ---------------------------------------------------- multilevel atom */
+
+/* A multilevel model atom on a grey background (the paper's rate operators
+ * [R_ij], [R*_ij], [Delta R_ij] and rate matrix A, read as the full
+ * preconditioning of Rybicki & Hummer 1991 with the diagonal Lambda*).
+ * Every frequency belongs to exactly one transition (its window); units are
+ * the caller's, consistent between radiative and collisional rates.  All
+ * pointers are device memory, float64 except the int32 tables. */
+typedef struct pprt_atom {
+  int32_t nlev;              /* levels incl. any continuum level, 2..32            */
+  int32_t ntr;               /* transitions, >= 1                                  */
+  const int32_t* lower;      /* [ntr] lower level (0-based); level 0 is replaced    */
+  const int32_t* upper;      /* [ntr] upper level  by number conservation          */
+  const int32_t* k0;         /* [ntr] first frequency of the window                */
+  const int32_t* k1;         /* [ntr] one past the last frequency of the window    */
+  const int32_t* owner;      /* [nf] transition owning frequency k                 */
+  const double* sigma;       /* [nf] absorption cross-section                      */
+  const double* bfac;        /* [nf] b (2 h nu^3 / c^2 in the caller's units)       */
+  const double* W;           /* [nf] rate quadrature weight (4 pi w / (h nu))       */
+  const double* G;           /* [rows][nf] stimulated-emission factor               */
+  const double* Bnu;         /* [rows][nf] Planck function                          */
+  const double* kc;          /* [rows] continuum absorption per unit tau_ref        */
+  const double* sc;          /* [rows] continuum scattering per unit tau_ref        */
+  const double* ntot;        /* [rows] total number density of the atom             */
+  const double* Cul;         /* [rows][ntr] downward collision rates                */
+  const double* Clu;         /* [rows][ntr] upward collision rates                  */
+} pprt_atom;
+
+/* Host validation of the atom's tables (copies the int32 tables to the
+ * host): level and window indices in range, windows inside [0, nf), every
+ * frequency owned by the transition whose window holds it.  E_INVALID_ARG /
+ * E_SHAPE with a message otherwise.  The compute calls below validate the
+ * first time they see a given set of table pointers. */
+pprt_status pprt_atom_check(pprt_plan* plan, const pprt_atom* atom);
+
+/* Opacity and source assembly from populations pops [rows][nlev]:
+ * q = kappa + sigma_c (per unit tau_ref), omega = sigma_c / q and
+ * S^g = (eta + kappa_c B) / kappa, each [rows][nf] float64. */
+pprt_status pprt_nlte_opacity(pprt_plan* plan, const pprt_atom* atom, const double* pops,
+                              double* q, double* omega, double* Sg);
+
+/* Preconditioned rates per (row, transition) [rows][ntr] from the old
+ * populations and a formal solution's J and Lambda* ([rows][nf]):
+ * [dR_lu] = sum W sigma dJ, [dR_ul] = sum W G sigma dJ,
+ * [R*_ul] = sum W b G sigma (1 - p Lambda*), dJ = J - Lambda* eta/kappa. */
+pprt_status pprt_rates_assemble(pprt_plan* plan, const pprt_atom* atom, const double* pops_old,
+                                const double* J, const double* lstar, double* dRlu,
+                                double* dRul, double* Rsul);
+
+/* Statistical equilibrium per depth with P_lu = [dR_lu] + C_lu,
+ * P_ul = [R*_ul] + [dR_ul] + C_ul and the ground-level equation replaced by
+ * sum n = n_tot; LU with partial pivoting in float64.  pops_new [rows][nlev];
+ * max_rel [nb] (may be NULL) = max |n_new - n_old| / n_new per atmosphere.
+ * A singular system sets PPRT_DEV_SINGULAR (read by pprt_sync). */
+pprt_status pprt_rates_solve(pprt_plan* plan, const pprt_atom* atom, const double* pops_old,
+                             const double* dRlu, const double* dRul, const double* Rsul,
+                             double* pops_new, double* max_rel);
+
+/* Workspace of pprt_nlte_step (bytes) for an atom of nlev levels and ntr
+ * transitions. */
+pprt_status pprt_plan_nlte_workspace_bytes(const pprt_plan* plan, int32_t nlev, int32_t ntr,
+                                           size_t* bytes);
+
+/* One accelerated-Lambda iteration of the multilevel atom: opacities from
+ * pops, formal solution with in-layer continuum scattering (FP64 plans,
+ * na in {1,2,4,8,16}), rate assembly and the per-depth solve; pops
+ * [rows][nlev] is replaced by the new populations and max_rel [nb] gets the
+ * largest relative change.  in->tau (and in->Itop, NULL = 0) are used; the
+ * diffusion lower boundary takes B from atom->Bnu. */
+pprt_status pprt_nlte_step(pprt_plan* plan, const pprt_fs_in* in, const pprt_atom* atom,
+                           double* pops, double* max_rel, void* workspace);
+
 #ifdef __cplusplus
 }
 #endif

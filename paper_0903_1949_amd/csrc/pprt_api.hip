@@ -39,6 +39,9 @@ struct pprt_plan {
   std::vector<double> mu, w;
   Angles<float> af{};
   Angles<double> ad{};
+  // last atom tables that passed pprt_atom_check
+  const void* checked_atom[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  int checked_nlev = 0, checked_ntr = 0;
   // workspace layout of the ALI calls
   size_t ws_part = 0, ws_maxrel = 0, ws_active = 0, ws_iters = 0, ws_bytes = 0;
 };
@@ -685,6 +688,167 @@ pprt_status pprt_two_level_ali(pprt_plan* p, const pprt_fs_in* in, const pprt_tw
   if (r != PPRT_OK) return r;
   if (!all_done) return fail(c, PPRT_E_NOT_CONVERGED, "ALI not converged after %d iterations", done_iters);
   return PPRT_OK;
+}
+
+static MlArgs ml_args(const pprt_plan* p, const pprt_atom* at, const double* pops) {
+  MlArgs a{};
+  a.pops = pops; a.lower = at->lower; a.upper = at->upper; a.k0 = at->k0; a.k1 = at->k1;
+  a.owner = at->owner; a.sigma = at->sigma; a.bfac = at->bfac; a.W = at->W; a.G = at->G;
+  a.Bnu = at->Bnu; a.kc = at->kc; a.sc = at->sc; a.ntot = at->ntot; a.Cul = at->Cul; a.Clu = at->Clu;
+  a.rows = p->rows; a.nf = p->nf; a.nlev = at->nlev; a.ntr = at->ntr;
+  return a;
+}
+
+pprt_status pprt_atom_check(pprt_plan* p, const pprt_atom* at) {
+  if (!p) return PPRT_E_INVALID_ARG;
+  pprt_ctx* c = p->ctx;
+  if (!at) return fail(c, PPRT_E_INVALID_ARG, "null atom");
+  if (at->nlev < 2 || at->nlev > ml_max_levels())
+    return fail(c, PPRT_E_SHAPE, "nlev must be in 2..%d (got %d)", ml_max_levels(), at->nlev);
+  if (at->ntr < 1) return fail(c, PPRT_E_SHAPE, "ntr must be >= 1");
+  const void* req[] = {at->lower, at->upper, at->k0, at->k1, at->owner, at->sigma, at->bfac, at->W,
+                       at->G, at->Bnu, at->kc, at->sc, at->ntot, at->Cul, at->Clu};
+  for (const void* ptr : req)
+    if (!ptr) return fail(c, PPRT_E_INVALID_ARG, "atom arrays must all be given");
+  if (p->checked_atom[0] == at->lower && p->checked_atom[1] == at->upper &&
+      p->checked_atom[2] == at->k0 && p->checked_atom[3] == at->k1 &&
+      p->checked_atom[4] == at->owner && p->checked_nlev == at->nlev && p->checked_ntr == at->ntr)
+    return PPRT_OK;
+  std::vector<int32_t> lo(at->ntr), up(at->ntr), k0(at->ntr), k1(at->ntr), own(p->nf);
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = hipMemcpy(lo.data(), at->lower, at->ntr * 4, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(up.data(), at->upper, at->ntr * 4, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(k0.data(), at->k0, at->ntr * 4, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(k1.data(), at->k1, at->ntr * 4, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(own.data(), at->owner, (size_t)p->nf * 4, hipMemcpyDeviceToHost);
+  pprt_status r = hip_check(c, e, "atom table read");
+  if (r != PPRT_OK) return r;
+  for (int t = 0; t < at->ntr; ++t) {
+    if (lo[t] < 0 || up[t] >= at->nlev || !(lo[t] < up[t]))
+      return fail(c, PPRT_E_INVALID_ARG, "transition %d: need 0 <= lower < upper < nlev", t);
+    if (k0[t] < 0 || k1[t] > p->nf || !(k0[t] < k1[t]))
+      return fail(c, PPRT_E_INVALID_ARG, "transition %d: window [%d, %d) outside [0, %d)", t, k0[t],
+                  k1[t], p->nf);
+    for (int k = k0[t]; k < k1[t]; ++k)
+      if (own[k] != t) return fail(c, PPRT_E_INVALID_ARG, "frequency %d lies in window %d but owner says %d", k, t, own[k]);
+  }
+  for (int k = 0; k < p->nf; ++k)
+    if (own[k] < 0 || own[k] >= at->ntr)
+      return fail(c, PPRT_E_INVALID_ARG, "frequency %d has no owning transition", k);
+  p->checked_atom[0] = at->lower; p->checked_atom[1] = at->upper; p->checked_atom[2] = at->k0;
+  p->checked_atom[3] = at->k1; p->checked_atom[4] = at->owner;
+  p->checked_nlev = at->nlev; p->checked_ntr = at->ntr;
+  return PPRT_OK;
+}
+
+pprt_status pprt_nlte_opacity(pprt_plan* p, const pprt_atom* at, const double* pops, double* q,
+                              double* omega, double* Sg) {
+  if (!p) return PPRT_E_INVALID_ARG;
+  pprt_status r = pprt_atom_check(p, at);
+  if (r != PPRT_OK) return r;
+  if (!pops || !q || !omega || !Sg) return fail(p->ctx, PPRT_E_INVALID_ARG, "null array");
+  return hip_check(p->ctx, launch_ml_opacity(ml_args(p, at, pops), q, omega, Sg, p->ctx->stream),
+                   "opacity launch");
+}
+
+pprt_status pprt_rates_assemble(pprt_plan* p, const pprt_atom* at, const double* pops_old,
+                                const double* J, const double* lstar, double* dRlu, double* dRul,
+                                double* Rsul) {
+  if (!p) return PPRT_E_INVALID_ARG;
+  pprt_status r = pprt_atom_check(p, at);
+  if (r != PPRT_OK) return r;
+  if (!pops_old || !J || !lstar || !dRlu || !dRul || !Rsul)
+    return fail(p->ctx, PPRT_E_INVALID_ARG, "null array");
+  return hip_check(p->ctx, launch_ml_rates(ml_args(p, at, pops_old), J, lstar, dRlu, dRul, Rsul,
+                                           p->ctx->stream), "rate assembly launch");
+}
+
+pprt_status pprt_rates_solve(pprt_plan* p, const pprt_atom* at, const double* pops_old,
+                             const double* dRlu, const double* dRul, const double* Rsul,
+                             double* pops_new, double* max_rel) {
+  if (!p) return PPRT_E_INVALID_ARG;
+  pprt_status r = pprt_atom_check(p, at);
+  if (r != PPRT_OK) return r;
+  if (!pops_old || !dRlu || !dRul || !Rsul || !pops_new)
+    return fail(p->ctx, PPRT_E_INVALID_ARG, "null array");
+  if (pops_new == pops_old) return fail(p->ctx, PPRT_E_INVALID_ARG, "pops_new must not alias pops_old");
+  return hip_check(p->ctx, launch_ml_solve(ml_args(p, at, pops_old), p->d_off, p->nb, dRlu, dRul, Rsul,
+                                           pops_new, max_rel, p->ctx->d_status, p->ctx->stream),
+                   "rate solve launch");
+}
+
+// nlte workspace: [q | om | Sg | J | L (rows*nf) | Bb | Bp (nb*nf) | dRlu | dRul | Rsul (rows*ntr)
+//                  | pops_new (rows*nlev) | dense ws]
+static void nlte_layout(const pprt_plan* p, int nlev, int ntr, size_t off[12]) {
+  const size_t rf = align256((size_t)p->rows * p->nf * sizeof(double));
+  const size_t bf = align256((size_t)p->nb * p->nf * sizeof(double));
+  const size_t rt = align256((size_t)p->rows * ntr * sizeof(double));
+  const size_t rl = align256((size_t)p->rows * nlev * sizeof(double));
+  off[0] = 0;
+  for (int i = 1; i <= 5; ++i) off[i] = off[i - 1] + rf;
+  off[6] = off[5] + bf;
+  off[7] = off[6] + bf;
+  off[8] = off[7] + rt;
+  off[9] = off[8] + rt;
+  off[10] = off[9] + rt;
+  off[11] = off[10] + rl + align256(dense_workspace_bytes(p->na, p->rows, p->nf));
+}
+
+pprt_status pprt_plan_nlte_workspace_bytes(const pprt_plan* p, int32_t nlev, int32_t ntr, size_t* bytes) {
+  if (!p || !bytes || nlev < 2 || ntr < 1) return PPRT_E_INVALID_ARG;
+  size_t off[12];
+  nlte_layout(p, nlev, ntr, off);
+  *bytes = off[11];
+  return PPRT_OK;
+}
+
+pprt_status pprt_nlte_step(pprt_plan* p, const pprt_fs_in* in, const pprt_atom* at, double* pops,
+                           double* max_rel, void* ws) {
+  if (!p) return PPRT_E_INVALID_ARG;
+  pprt_ctx* c = p->ctx;
+  if (p->precision != PPRT_FP64 || !dense_na_supported(p->na))
+    return fail(c, PPRT_E_UNSUPPORTED, "multilevel step needs an FP64 plan and na in {1,2,4,8,16}");
+  if (p->lower_bc != PPRT_BC_DIFFUSION)
+    return fail(c, PPRT_E_UNSUPPORTED, "multilevel step uses the diffusion lower boundary");
+  if (!in || !in->tau || !pops || !max_rel) return fail(c, PPRT_E_INVALID_ARG, "null argument");
+  if (!ws) return fail(c, PPRT_E_WORKSPACE, "workspace required (pprt_plan_nlte_workspace_bytes)");
+  pprt_status r = pprt_atom_check(p, at);
+  if (r != PPRT_OK) return r;
+  size_t off[12];
+  nlte_layout(p, at->nlev, at->ntr, off);
+  char* base = (char*)ws;
+  double* q = (double*)(base + off[0]);
+  double* om = (double*)(base + off[1]);
+  double* Sg = (double*)(base + off[2]);
+  double* J = (double*)(base + off[3]);
+  double* Ls = (double*)(base + off[4]);
+  double* Bb = (double*)(base + off[5]);
+  double* Bp = (double*)(base + off[6]);
+  double* dRlu = (double*)(base + off[7]);
+  double* dRul = (double*)(base + off[8]);
+  double* Rsul = (double*)(base + off[9]);
+  double* pn = (double*)(base + off[10]);
+  double* dws = (double*)(base + off[10] + align256((size_t)p->rows * at->nlev * sizeof(double)));
+  const MlArgs a = ml_args(p, at, pops);
+  r = hip_check(c, launch_ml_opacity(a, q, om, Sg, c->stream), "opacity launch");
+  if (r != PPRT_OK) return r;
+  r = hip_check(c, launch_gather_bottom(at->Bnu, p->d_off, p->nb, p->nf, Bb, Bp, c->stream), "gather");
+  if (r != PPRT_OK) return r;
+  DenseLaunch L{};
+  L.items = p->d_items_dense; L.off = p->d_off; L.tau = in->tau; L.q = q; L.Sg = Sg; L.omega = om;
+  L.Itop = (const double*)in->Itop; L.Bbot = Bb; L.Bbot_prev = Bp; L.Ibot = nullptr;
+  L.J = J; L.lstar = Ls; L.ws = dws; L.rows = p->rows; L.nf = p->nf; L.na = p->na;
+  L.nitems = p->n_dense; L.lower_bc = PPRT_BC_DIFFUSION; L.outputs = PPRT_OUT_J | PPRT_OUT_LSTAR;
+  L.mu = p->mu.data(); L.w = p->w.data();
+  r = hip_check(c, launch_fs_dense(L, c->stream), "formal-solution launch");
+  if (r != PPRT_OK) return r;
+  r = hip_check(c, launch_ml_rates(a, J, Ls, dRlu, dRul, Rsul, c->stream), "rate assembly launch");
+  if (r != PPRT_OK) return r;
+  r = hip_check(c, launch_ml_solve(a, p->d_off, p->nb, dRlu, dRul, Rsul, pn, max_rel, c->d_status,
+                                   c->stream), "rate solve launch");
+  if (r != PPRT_OK) return r;
+  return hip_check(c, hipMemcpyAsync(pops, pn, (size_t)p->rows * at->nlev * sizeof(double),
+                                     hipMemcpyDeviceToDevice, c->stream), "population copy");
 }
 
 }  // extern "C"

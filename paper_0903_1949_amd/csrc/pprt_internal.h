@@ -111,6 +111,37 @@ size_t dense_workspace_bytes(int na, int64_t rows, int nf);
 int dense_freqs_per_item(int na);
 hipError_t launch_fs_dense(const DenseLaunch& L, hipStream_t s);
 
+// Multilevel atom (nlte.hip); every array is device memory, FP64.
+struct MlArgs {
+  const double* pops;     // [rows][nlev] populations the rates are built with
+  const int32_t* lower;   // [ntr]
+  const int32_t* upper;
+  const int32_t* k0;
+  const int32_t* k1;
+  const int32_t* owner;   // [nf]
+  const double* sigma;    // [nf]
+  const double* bfac;     // [nf]
+  const double* W;        // [nf]
+  const double* G;        // [rows][nf]
+  const double* Bnu;      // [rows][nf]
+  const double* kc;       // [rows]
+  const double* sc;       // [rows]
+  const double* ntot;     // [rows]
+  const double* Cul;      // [rows][ntr]
+  const double* Clu;      // [rows][ntr]
+  int64_t rows;
+  int32_t nf, nlev, ntr;
+};
+int ml_max_levels();
+hipError_t launch_ml_opacity(const MlArgs& a, double* q, double* om, double* Sg, hipStream_t s);
+hipError_t launch_ml_rates(const MlArgs& a, const double* J, const double* L, double* dRlu,
+                           double* dRul, double* Rsul, hipStream_t s);
+hipError_t launch_ml_solve(const MlArgs& a, const int64_t* off, int nb, const double* dRlu,
+                           const double* dRul, const double* Rsul, double* pops_new, double* max_rel,
+                           uint32_t* status, hipStream_t s);
+hipError_t launch_gather_bottom(const double* Bnu, const int64_t* off, int nb, int nf, double* Bb,
+                                double* Bp, hipStream_t s);
+
 // Launchers (fs_diag.hip, ali.hip).  Return hipSuccess or the launch error.
 hipError_t launch_fs_full(int precision, int na, int wpb, int nitems, hipStream_t s,
                           const void* args, const void* angles);

@@ -62,6 +62,12 @@ class Continuum(C.Structure):
     _fields_ = [("pfrac", C.c_void_p), ("sg_const", C.c_void_p), ("omega", C.c_void_p)]
 
 
+class Atom(C.Structure):
+    _fields_ = [("nlev", C.c_int32), ("ntr", C.c_int32)] + [
+        (n, C.c_void_p) for n in ("lower", "upper", "k0", "k1", "owner", "sigma", "bfac", "W", "G",
+                                  "Bnu", "kc", "sc", "ntot", "Cul", "Clu")]
+
+
 class AliCtl(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("iters_per_sync", C.c_int32),
                 ("use_graph", C.c_int32)]
@@ -105,6 +111,12 @@ def load_library(path: str = LIB_PATH):
         "pprt_plan_continuum_workspace_bytes": (I, [P, C.POINTER(C.c_size_t)]),
         "pprt_two_level_ali_step_continuum": (I, [P, C.POINTER(FsIn), C.POINTER(TwoLevel),
                                                   C.POINTER(Continuum), P, P, P, P]),
+        "pprt_atom_check": (I, [P, C.POINTER(Atom)]),
+        "pprt_nlte_opacity": (I, [P, C.POINTER(Atom), P, P, P, P]),
+        "pprt_rates_assemble": (I, [P, C.POINTER(Atom), P, P, P, P, P, P]),
+        "pprt_rates_solve": (I, [P, C.POINTER(Atom), P, P, P, P, P, P]),
+        "pprt_plan_nlte_workspace_bytes": (I, [P, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
+        "pprt_nlte_step": (I, [P, C.POINTER(FsIn), C.POINTER(Atom), P, P, P]),
         "pprt_two_level_moments": (I, [P, C.POINTER(FsIn), C.POINTER(TwoLevel), P, P, P]),
         "pprt_two_level_update": (I, [P, C.POINTER(TwoLevel), P, P, P, P]),
         "pprt_two_level_ali": (I, [P, C.POINTER(FsIn), C.POINTER(TwoLevel), C.POINTER(AliCtl),
@@ -384,6 +396,49 @@ class Plan:
             self.h, C.byref(fin), C.byref(at), C.byref(ct), _ptr(S), _ptr(max_rel), _ptr(active),
             _ptr(workspace)), "two_level_ali_step_continuum")
 
+    # ------------------------------------------------------ multilevel
+    def nlte_opacity(self, atom, pops):
+        import torch
+        R, nf = self.rows, self.nf
+        q = torch.empty((R, nf), dtype=torch.float64, device=pops.device)
+        om = torch.empty_like(q)
+        Sg = torch.empty_like(q)
+        self.ctx._check(self.lib.pprt_nlte_opacity(self.h, C.byref(atom.struct), _ptr(pops), _ptr(q),
+                                                   _ptr(om), _ptr(Sg)), "nlte_opacity")
+        return q, om, Sg
+
+    def rates_assemble(self, atom, pops_old, J, lstar):
+        import torch
+        shp = (self.rows, atom.ntr)
+        out = [torch.empty(shp, dtype=torch.float64, device=pops_old.device) for _ in range(3)]
+        self.ctx._check(self.lib.pprt_rates_assemble(
+            self.h, C.byref(atom.struct), _ptr(pops_old), _ptr(J), _ptr(lstar), *[_ptr(t) for t in out]),
+            "rates_assemble")
+        return tuple(out)
+
+    def rates_solve(self, atom, pops_old, dRlu, dRul, Rsul):
+        import torch
+        pn = torch.empty_like(pops_old)
+        mx = torch.empty(self.nb, dtype=torch.float64, device=pops_old.device)
+        self.ctx._check(self.lib.pprt_rates_solve(
+            self.h, C.byref(atom.struct), _ptr(pops_old), _ptr(dRlu), _ptr(dRul), _ptr(Rsul), _ptr(pn),
+            _ptr(mx)), "rates_solve")
+        return pn, mx
+
+    def nlte_step(self, tau, atom, pops, max_rel, Itop=None):
+        import torch
+        self._want(tau, (self.rows,), torch.float64, "tau")
+        self._want(pops, (self.rows, atom.nlev), torch.float64, "pops")
+        self._want(max_rel, (self.nb,), torch.float64, "max_rel")
+        fin = FsIn(_ptr(tau), None, None, _ptr(Itop), None, None, None)
+        nbytes = C.c_size_t()
+        self.ctx._check(self.lib.pprt_plan_nlte_workspace_bytes(self.h, atom.nlev, atom.ntr,
+                                                                C.byref(nbytes)), "nlte_workspace_bytes")
+        if getattr(self, "_nws", None) is None or self._nws.numel() < nbytes.value:
+            self._nws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=tau.device)
+        self.ctx._check(self.lib.pprt_nlte_step(self.h, C.byref(fin), C.byref(atom.struct), _ptr(pops),
+                                                _ptr(max_rel), _ptr(self._nws)), "nlte_step")
+
     def two_level_moments(self, tau, q, S, eps, B, wphi, active=None, Itop=None, Ibot=None):
         """pprt_two_level_moments: the formal-solution half of an ALI step."""
         import torch
@@ -424,6 +479,26 @@ class Plan:
             return report
         self.ctx._check(st, "two_level_ali")
         return report
+
+
+class DeviceAtom:
+    """A workloads.MultiLevelAtom resident on the device (tables as int32,
+    everything else float64) plus the pprt_atom struct pointing at it."""
+
+    def __init__(self, atom, device="cuda:0"):
+        import torch
+        i32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.int32), device=device)
+        f64 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=device)
+        self.nlev, self.ntr = int(atom.nl), int(atom.nt)
+        self.t = dict(lower=i32(atom.lo), upper=i32(atom.up), k0=i32(atom.k0), k1=i32(atom.k1),
+                      owner=i32(atom.owner), sigma=f64(atom.sigma), bfac=f64(atom.bfac), W=f64(atom.W),
+                      G=f64(atom.Gst), Bnu=f64(atom.Bnu), kc=f64(atom.kc), sc=f64(atom.sc),
+                      ntot=f64(atom.ntot), Cul=f64(atom.Cul), Clu=f64(atom.Clu))
+        self.tau = f64(atom.tau)
+        self.nstar = f64(atom.nstar)
+        self.struct = Atom(self.nlev, self.ntr, *[_ptr(self.t[n]) for n in (
+            "lower", "upper", "k0", "k1", "owner", "sigma", "bfac", "W", "G", "Bnu", "kc", "sc", "ntot",
+            "Cul", "Clu")])
 
 
 @dataclass

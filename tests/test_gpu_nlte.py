@@ -1,0 +1,130 @@
+"""GPU parity of the multilevel path (opacity assembly, preconditioned rate
+assembly, per-depth statistical-equilibrium solve, full ALI iteration) with
+the FP64 oracle."""
+import copy
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import rates
+from oracle.quadrature import gauss_legendre01
+from paper_0903_1949_amd import pprt
+from paper_0903_1949_amd import workloads as W
+from tests.conftest import rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def atom():
+    return W.multilevel_atom(nbound=4, ncont=3, nd=20, na=8, nline_pts=16, ncont_pts=10, seed=7, nb=2)
+
+
+def _dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0")
+
+
+def _plan(ctx, a):
+    return pprt.Plan(ctx, a.nd, a.na, a.nf, precision=pprt.FP64, outputs=pprt.OUT_J | pprt.OUT_LSTAR)
+
+
+def test_opacity_parity(gpu_ctx, atom):
+    plan = _plan(gpu_ctx, atom)
+    da = pprt.DeviceAtom(atom)
+    rng = np.random.default_rng(0)
+    pops = atom.nstar * rng.uniform(0.5, 2.0, size=atom.nstar.shape)
+    q, om, Sg = plan.nlte_opacity(da, _dev(pops))
+    torch.cuda.synchronize()
+    ref = rates.opacities(atom, pops)
+    for name, got in (("q", q), ("omega", om), ("Sg", Sg)):
+        assert rel_err(got.cpu().numpy(), ref[name]) < 1e-13, name
+
+
+def test_rate_assembly_and_solve_parity(gpu_ctx, atom):
+    plan = _plan(gpu_ctx, atom)
+    da = pprt.DeviceAtom(atom)
+    rng = np.random.default_rng(1)
+    rows = atom.tau.shape[0]
+    pops = atom.nstar * rng.uniform(0.5, 2.0, size=atom.nstar.shape)
+    J = rng.uniform(0.1, 2.0, size=(rows, atom.nf)) * atom.Bnu
+    L = rng.uniform(0.0, 1.0, size=(rows, atom.nf))
+    d = plan.rates_assemble(da, _dev(pops), _dev(J), _dev(L))
+    torch.cuda.synchronize()
+    ref = rates.preconditioned_rates(atom, pops, J, L)
+    for got, r in zip(d, ref):
+        assert rel_err(got.cpu().numpy(), r) < 1e-12
+    pn, mx = plan.rates_solve(da, _dev(pops), *[_dev(r) for r in ref])
+    torch.cuda.synchronize()
+    pref = rates.solve_populations(atom, *ref)
+    e = np.max(np.abs(pn.cpu().numpy() / pref - 1))
+    print(f"  populations rel err {e:.2e}", flush=True)
+    assert e < 1e-10
+    off = atom.off
+    relp = np.abs(pref - pops) / np.abs(pref)
+    mref = [relp[off[b]:off[b + 1]].max() for b in range(atom.nb)]
+    assert np.allclose(mx.cpu().numpy(), mref, rtol=1e-8)
+
+
+def test_nlte_iteration_parity(gpu_ctx, atom):
+    plan = _plan(gpu_ctx, atom)
+    da = pprt.DeviceAtom(atom)
+    mu, w = plan.mu, plan.w
+    pops = da.nstar.clone()
+    mx = torch.zeros(atom.nb, dtype=torch.float64, device="cuda:0")
+    p_ref = atom.nstar.copy()
+    for it in range(3):
+        plan.nlte_step(da.tau, da, pops, mx)
+        torch.cuda.synchronize()
+        p_ref, m_ref, _ = rates.nlte_iteration(atom, p_ref, mu, w)
+        e = np.max(np.abs(pops.cpu().numpy() / p_ref - 1))
+        print(f"  iteration {it + 1}: populations rel err {e:.2e}", flush=True)
+        assert e < 1e-9
+        assert np.allclose(mx.cpu().numpy(), m_ref, rtol=1e-6)
+
+
+def test_nlte_converges_to_oracle(gpu_ctx):
+    a = W.multilevel_atom(nbound=3, ncont=2, nd=16, na=4, nline_pts=10, ncont_pts=6, seed=11)
+    plan = _plan(gpu_ctx, a)
+    da = pprt.DeviceAtom(a)
+    pops = da.nstar.clone()
+    mx = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    it = 0
+    for it in range(1, 401):
+        plan.nlte_step(da.tau, da, pops, mx)
+        if it % 20 == 0 and float(mx.item()) < 1e-10:
+            break
+    torch.cuda.synchronize()
+    ref = rates.nlte_solve(a, plan.mu, plan.w, tol=1e-11, max_iter=400)
+    e = np.max(np.abs(pops.cpu().numpy() / ref["pops"] - 1))
+    print(f"  gpu iterations {it}, oracle {ref['iterations']}, rel err {e:.2e}", flush=True)
+    assert e < 1e-8
+
+
+def test_collision_dominated_limit_on_gpu(gpu_ctx, atom):
+    a = copy.deepcopy(atom)
+    A = np.zeros((a.tau.shape[0], a.nt))
+    for t in range(a.nt):
+        sl = slice(int(a.k0[t]), int(a.k1[t]))
+        A[:, t] = np.sum(a.W[None, sl] * a.bfac[None, sl] * a.Gst[:, sl] * a.sigma[None, sl], axis=1)
+    a.Cul = A * 1e14
+    a.Clu = a.Cul * a.nstar[:, a.up] / a.nstar[:, a.lo]
+    plan = _plan(gpu_ctx, a)
+    da = pprt.DeviceAtom(a)
+    pops = _dev(a.nstar * 1.2)
+    mx = torch.zeros(a.nb, dtype=torch.float64, device="cuda:0")
+    for _ in range(2):
+        plan.nlte_step(da.tau, da, pops, mx)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(pops.cpu().numpy() / a.nstar - 1)) < 1e-8
+
+
+def test_atom_table_validation(gpu_ctx, atom):
+    plan = _plan(gpu_ctx, atom)
+    bad = copy.deepcopy(atom)
+    bad.k1 = bad.k1.copy()
+    bad.k1[0] += 1          # window overlaps the next transition's first point
+    da = pprt.DeviceAtom(bad)
+    pops = _dev(atom.nstar)
+    with pytest.raises(pprt.PprtError, match="E_INVALID_ARG"):
+        plan.nlte_opacity(da, pops)
