@@ -22,7 +22,8 @@ and the new populations solve, at every depth,
     P_lu = [dR_lu] + C_lu,   P_ul = [R*_ul] + [dR_ul] + C_ul,
 
 (the ground-level equation replaced by number conservation), by LU with
-partial pivoting in float64.  The net radiative rate is linear in the new
+partial pivoting in float64, for the unknowns n_i / n_i^old (the columns
+scaled by the previous populations, which spans far fewer decades).  The net radiative rate is linear in the new
 populations because chi_t^new p S_t^new = p eta_t^new.  W_k is the
 frequency-integration weight of a rate (w_k / nu_k in reduced units).
 
@@ -92,12 +93,16 @@ def rate_matrix(atom, r, dRlu, dRul, Rsul):
     return A, rhs
 
 
-def solve_populations(atom, dRlu, dRul, Rsul):
+def solve_populations(atom, dRlu, dRul, Rsul, scale=None):
+    """New populations per row.  The unknowns span many decades, so the
+    system is solved for n_i / scale_i (columns scaled by `scale`, e.g. the
+    previous populations) and scaled back; the solution is the same."""
     rows = dRlu.shape[0]
     pops = np.zeros((rows, atom.nl))
     for r in range(rows):
         A, rhs = rate_matrix(atom, r, dRlu, dRul, Rsul)
-        pops[r] = np.linalg.solve(A, rhs)
+        s = np.ones(atom.nl) if scale is None else scale[r]
+        pops[r] = np.linalg.solve(A * s[None, :], rhs) * s
     return pops
 
 
@@ -121,7 +126,7 @@ def formal_solution_atom(atom, pops, mu, w, scattering=True):
 def nlte_iteration(atom, pops, mu, w, scattering=True):
     fs, _ = formal_solution_atom(atom, pops, mu, w, scattering)
     dRlu, dRul, Rsul = preconditioned_rates(atom, pops, fs["J"], fs["lstar"])
-    new = solve_populations(atom, dRlu, dRul, Rsul)
+    new = solve_populations(atom, dRlu, dRul, Rsul, scale=pops)
     rel = np.abs(new - pops) / np.abs(new)
     off = atom.off
     mx = np.array([rel[off[b]:off[b + 1]].max() for b in range(atom.nb)])

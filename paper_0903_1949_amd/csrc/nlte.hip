@@ -14,7 +14,8 @@
 //     [R*_ul] = sum_k W b G sigma (1 - p Lambda*),  p = chi_t / kappa,
 // and per depth  sum_{j!=i} n_j P_ji - n_i sum_{j!=i} P_ij = 0 (i != 0),
 // sum n = n_tot, with P_lu = [dR_lu] + C_lu, P_ul = [R*_ul] + [dR_ul] + C_ul,
-// solved by LU with partial pivoting.
+// solved by LU with partial pivoting for n_i / n_i^old (columns scaled by the
+// previous populations: the unknowns span many decades).
 #include "pprt_internal.h"
 
 namespace pprt {
@@ -117,6 +118,12 @@ __global__ __launch_bounds__(128) void k_ml_solve(MlArgs a, const int64_t* __res
     }
     for (int j = 0; j < n; ++j) A[0][j] = 1.0;   // number conservation
     x[0] = a.ntot[r];
+    // unknowns n_i / n_i^old: scale the columns by the previous populations
+    double sc[kMaxLev];
+    for (int j = 0; j < n; ++j) {
+      sc[j] = a.pops[r * n + j];
+      for (int i = 0; i < n; ++i) A[i][j] *= sc[j];
+    }
     // LU with partial pivoting, forward/back substitution
     for (int c = 0; c < n; ++c) {
       int p = c;
@@ -142,6 +149,7 @@ __global__ __launch_bounds__(128) void k_ml_solve(MlArgs a, const int64_t* __res
       for (int j = c + 1; j < n; ++j) s = fma(-A[c][j], x[j], s);
       x[c] = s / A[c][c];
     }
+    for (int i = 0; i < n; ++i) x[i] *= sc[i];
     for (int i = 0; i < n; ++i) {
       const double old = a.pops[r * n + i];
       const double rel = fabs(x[i] - old) / fabs(x[i]);
