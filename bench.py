@@ -47,11 +47,14 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=48, help="atmospheres in the CPU sample")
+    ap.add_argument("--cpu-sample", type=int, default=256, help="atmospheres in the CPU sample")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (read + write) 5 times and "
+                         "exit: the reference for scaling FETCH_SIZE / WRITE_SIZE counters")
     ap.add_argument("--waves-per-block", type=int, default=0)
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_fs_profile_c3a.json"))
     return ap.parse_args()
@@ -101,6 +104,15 @@ def main():
     from paper_0903_1949_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": n * 4, "launches": 5}), flush=True)
+        return
     batch = W.two_level_batch(seed=3)
     pts = batch.points
     ctx = pprt.Context(0)
