@@ -398,3 +398,32 @@ def _trapz_weights(x):
     w[:-1] += 0.5 * d
     w[1:] += 0.5 * d
     return w
+
+
+@dataclass
+class GradientCase:
+    """Inputs of the emergent-spectrum gradient workload: q = c_d f_k, S = B."""
+    tau: np.ndarray      # [nd]
+    c: np.ndarray        # [nd] per-depth opacity scale
+    f: np.ndarray        # [nf] per-frequency opacity shape
+    B: np.ndarray        # [nd, nf] Planck function B_nu(T(tau_d)), normalised by its max
+    nu: np.ndarray       # [nf] Hz
+    na: int
+
+
+def gradient_case(nd=256, na=16, nf=4096, tau_lo=1e-4, tau_hi=1e4, teff=5800.0,
+                  nu_lo=1.5e14, nu_hi=3e15, seed=4) -> GradientCase:
+    """Per-depth opacity c_d ~ lognormal(0, 0.5), per-frequency factor f_k
+    log-uniform on [0.1, 10], frequencies log-spaced nu_lo..nu_hi, grey
+    Eddington T(tau) at Teff and B = B_nu(T), normalised by its maximum."""
+    rng = np.random.default_rng(seed)
+    tau = log_tau(nd, tau_lo, tau_hi)
+    c = rng.lognormal(0.0, 0.5, size=nd)
+    f = np.exp(rng.uniform(math.log(0.1), math.log(10.0), size=nf))
+    nu = np.geomspace(nu_lo, nu_hi, nf)
+    T = teff * (0.75 * (tau + 2.0 / 3.0)) ** 0.25
+    h_over_k = 4.799243073e-11        # h / k_B in K s
+    x = h_over_k * nu[None, :] / T[:, None]
+    B = nu[None, :] ** 3 / np.expm1(x)
+    B = B / B.max()
+    return GradientCase(tau=tau, c=c, f=f, B=B, nu=nu, na=na)
