@@ -19,6 +19,24 @@ written as differences so that no term is a small difference of large ones.
 The iteration starts at S = B and stops when the maximum relative change
 max_d |S_new - S_old| / |S_new| falls below tol (the paper's stopping rule,
 Sect. 3.2.1, applied to S).
+
+Non-local operator (Sect. 3.2.1 compares the local Lambda* with a
+nearest-neighbour one, which in 1D is the tri-diagonal band of Lambda).  With
+the profile-averaged band Lbar* = sum_k wnu_k phi_k tri(Lambda_k), the update
+solves, per atmosphere,
+
+    [I - (1-eps) Lbar*] dS = (1-eps)(Jbar_fs - S_old) + eps (B - S_old),
+
+whose diagonal is eps + (1-eps)(1 - Lbar*_dd).  The band is read off the
+brute-force Lambda matrix (its definition), and the system is solved densely.
+
+Ng acceleration (Ng 1974, in the form given by Auer 1987): from the last four
+iterates x0 (newest), x1, x2, x3 and the differences d0 = x0 - x1,
+d1 = x1 - x2, d2 = x2 - x3, the coefficients a, b minimise the weighted norm
+of d0 - a (d0 - d1) - b (d0 - d2) with weights 1/x0^2, and the accelerated
+iterate is (1 - a - b) x0 + a x1 + b x2.  Here it is applied once four
+iterates have accumulated since the start or the last acceleration, and the
+accelerated iterate starts the next group.
 """
 from __future__ import annotations
 
@@ -110,3 +128,75 @@ def batch_two_level_update(nd, S, B, eps, jbar_m_s, one_m_lbar):
     rel = np.abs(dS) / np.abs(S_new)
     mx = np.array([rel[off[b]:off[b + 1]].max() for b in range(nd.shape[0])])
     return S_new, mx
+
+
+def lambda_band(tau, q, mu, w):
+    """Tri-diagonal band of the brute-force Lambda operator per frequency:
+    (sub, diag, sup), each [nd, nf], sub[d] = Lambda[d, d-1] (0 at d = 0),
+    sup[d] = Lambda[d, d+1] (0 at the last node)."""
+    L = formal.lambda_matrix(tau, q, mu, w)          # [nf, nd, nd]
+    nf, nd, _ = L.shape
+    sub = np.zeros((nd, nf))
+    sup = np.zeros((nd, nf))
+    idx = np.arange(nd)
+    diag = L[:, idx, idx].T.copy()
+    sub[1:] = L[:, idx[1:], idx[:-1]].T
+    sup[:-1] = L[:, idx[:-1], idx[1:]].T
+    return sub, diag, sup
+
+
+def ng_extrapolate(x0, x1, x2, x3):
+    """Ng acceleration from four iterates (x0 newest); weights 1/x0^2."""
+    d0, d1, d2 = x0 - x1, x1 - x2, x2 - x3
+    wt = 1.0 / (x0 * x0)
+    u = d0 - d1
+    v = d0 - d2
+    A = np.array([[np.sum(wt * u * u), np.sum(wt * u * v)],
+                  [np.sum(wt * u * v), np.sum(wt * v * v)]])
+    rhs = np.array([np.sum(wt * d0 * u), np.sum(wt * d0 * v)])
+    det = A[0, 0] * A[1, 1] - A[0, 1] * A[1, 0]
+    if det == 0.0 or not np.isfinite(det):
+        return x0.copy()
+    a, b = np.linalg.solve(A, rhs)
+    return (1.0 - a - b) * x0 + a * x1 + b * x2
+
+
+def two_level_ali_nonlocal(tau, q, phi, wnu, eps, B, mu, w, tol=1e-8, max_iter=20000,
+                           operator="tri", ng=False, S0=None):
+    """Pure-line two-level ALI (omega = 0) with the diagonal ("diag") or the
+    tri-diagonal ("tri") approximate operator, optionally Ng-accelerated.
+    Returns dict(S, iterations, max_rel history, converged)."""
+    q = np.asarray(q, dtype=np.float64)
+    nd, nf = q.shape
+    B = np.asarray(B, dtype=np.float64)
+    wp = np.asarray(wnu) * np.asarray(phi)
+    sub, diag, sup = lambda_band(tau, q, mu, w)
+    Lsub, Lsup = sub @ wp, sup @ wp
+    S = B.copy() if S0 is None else np.asarray(S0, dtype=np.float64).copy()
+    Bbot = np.full(nf, B[-1])
+    Bprev = np.full(nf, B[-2])
+    hist, group = [], [S.copy()]
+    converged = False
+    it = 0
+    for it in range(1, max_iter + 1):
+        Sg = np.broadcast_to(S[:, None], (nd, nf))
+        out = formal.formal_solution(tau, q, Sg, mu, w, lower="diffusion", Bbot=Bbot, Bbot_prev=Bprev)
+        jms, olb = profile_moments(out, S, Sg, phi, wnu)
+        rhs = (1.0 - eps) * jms + eps * (B - S)
+        A = np.diag(eps + (1.0 - eps) * olb)
+        if operator == "tri":
+            A -= (1.0 - eps) * (np.diag(Lsub[1:], -1) + np.diag(Lsup[:-1], 1))
+        S_new = S + np.linalg.solve(A, rhs)
+        if ng:
+            group.append(S_new.copy())
+            if len(group) == 4:
+                S_new = ng_extrapolate(group[3], group[2], group[1], group[0])
+                group = [S_new.copy()]
+        rel = float(np.max(np.abs(S_new - S) / np.abs(S_new)))
+        hist.append(rel)
+        S = S_new
+        if rel < tol:
+            converged = True
+            break
+    return {"S": S, "iterations": it, "max_rel": np.array(hist), "converged": converged}
+

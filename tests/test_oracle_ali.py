@@ -116,3 +116,78 @@ def test_batch_update_matches_single():
     alt = ((1 - e) * (Jbar - L * S) + e * B) / (1 - (1 - e) * L)
     assert np.allclose(Sn, alt, rtol=1e-13)
     assert mx[0] == pytest.approx(np.max(np.abs(Sn[:3] - S[:3]) / np.abs(Sn[:3])))
+
+
+# ------------------------------------------- non-local operator and Ng acceleration
+def test_ng_is_exact_for_a_two_mode_affine_map():
+    """x -> M x + c with M of rank 2: after one step every error lies in the
+    2D range of M, so Ng's extrapolation from the next four iterates is the
+    fixed point up to rounding."""
+    rng = np.random.default_rng(0)
+    n = 40
+    U, _ = np.linalg.qr(rng.normal(size=(n, 2)))
+    M = U @ np.diag([0.97, -0.6]) @ U.T
+    c = rng.uniform(1.0, 2.0, n)
+    xs = np.linalg.solve(np.eye(n) - M, c)
+    x = [M @ np.full(n, 3.0) + c]
+    for _ in range(3):
+        x.append(M @ x[-1] + c)
+    xa = ali.ng_extrapolate(x[3], x[2], x[1], x[0])
+    assert np.max(np.abs(xa - xs) / np.abs(xs)) < 1e-12
+    # and it is no help on a constant sequence (degenerate system -> unchanged)
+    y = np.full(n, 2.0)
+    assert np.array_equal(ali.ng_extrapolate(y, y, y, y), y)
+
+
+def test_lambda_band_rows_and_boundaries():
+    rng = np.random.default_rng(3)
+    nd, nf, na = 9, 3, 4
+    tau = np.logspace(-3, 2, nd)
+    q = rng.lognormal(0, 0.5, size=(nd, nf))
+    mu, w = gauss_legendre01(na)
+    sub, diag, sup = ali.lambda_band(tau, q, mu, w)
+    L = formal.lambda_matrix(tau, q, mu, w)
+    for k in range(nf):
+        assert np.allclose(np.diag(L[k], -1), sub[1:, k], rtol=0, atol=0)
+        assert np.allclose(np.diag(L[k], 1), sup[:-1, k], rtol=0, atol=0)
+    assert np.all(sub[0] == 0) and np.all(sup[-1] == 0)
+    out = formal.formal_solution(tau, q, np.ones((nd, nf)), mu, w, lower="given")
+    assert np.allclose(diag, out["lstar"], rtol=1e-14, atol=0)
+
+
+@pytest.fixture(scope="module")
+def c1_runs():
+    c = W.single_two_level()
+    mu, w = gauss_legendre01(c.na)
+    direct = ali.direct_fixed_point(c.tau, c.q, c.phi, c.wnu, 1e-4, c.B, mu, w)
+    runs = {}
+    for op, ng, cap in (("diag", False, 20000), ("tri", False, 20000), ("tri", True, 20000),
+                        ("diag", True, 600)):
+        runs[(op, ng)] = ali.two_level_ali_nonlocal(c.tau, c.q, c.phi, c.wnu, 1e-4, c.B, mu, w,
+                                                   tol=1e-8, operator=op, ng=ng, max_iter=cap)
+    return direct, runs
+
+
+def test_nonlocal_operator_converges_to_the_same_fixed_point(c1_runs):
+    direct, runs = c1_runs
+    for key in (("diag", False), ("tri", False), ("tri", True)):
+        r = runs[key]
+        assert r["converged"], key
+        # contraction bound: error <= tol / (1 - rho); rho of the diagonal
+        # iteration at eps = 1e-4 is ~0.97, so 1e-8 / 0.03 < 1e-6
+        assert np.max(np.abs(r["S"] - direct) / direct) < 1e-6, key
+    # the unaccelerated runs are the same iteration as two_level_ali
+    assert runs[("diag", False)]["iterations"] == 516
+
+
+def test_convergence_ranking_of_the_operators(c1_runs):
+    """Sect. 3.2.1's ranking in its 1D form: the tri-diagonal operator
+    converges in far fewer iterations than the diagonal one, Ng accelerates
+    it further, and the diagonal operator with Ng is worse than the
+    tri-diagonal one without (here it stalls before 1e-8 within 600
+    iterations)."""
+    _, runs = c1_runs
+    it = {k: v["iterations"] for k, v in runs.items()}
+    assert it[("tri", False)] < it[("diag", False)] / 4
+    assert it[("tri", True)] < it[("tri", False)]
+    assert (not runs[("diag", True)]["converged"]) or it[("diag", True)] > it[("tri", False)]
