@@ -55,7 +55,11 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (read + write) 5 times and "
                          "exit: the reference for scaling FETCH_SIZE / WRITE_SIZE counters")
-    ap.add_argument("--waves-per-block", type=int, default=0)
+    ap.add_argument("--waves-per-block", type=int, default=0,
+                    help="fix the waves per block (disables the autotuner)")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--graph-chunk", type=int, default=25,
+                    help="ALI iterations per captured graph in the graph-mode timing (0: skip)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_fs_profile_c3a.json"))
     return ap.parse_args()
 
@@ -125,6 +129,10 @@ def main():
     db.S.copy_(db.B)
     S0 = db.S.clone()
     mx = torch.zeros(batch.nb, dtype=torch.float64, device="cuda:0")
+    tune = None
+    if not args.no_autotune and not args.waves_per_block:
+        tune = plan.autotune(db.tau, db.q, db.S, db.eps, db.B, db.wphi, force=True)
+    launch = plan.get_launch()
 
     def step(ev0=None, ev1=None):
         if ev0 is not None:
@@ -163,6 +171,22 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     fs_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
     value = pts / (wall / args.steps)
+
+    # ---------------- the same iterations through pprt_two_level_ali in graph mode
+    graph = None
+    if args.graph_chunk > 0:
+        db.S.copy_(S0)
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        rep = plan.two_level_ali(db.tau, db.q, db.S, db.eps, db.B, db.wphi, tol=1e-300,
+                                 max_iter=args.steps, iters_per_sync=args.graph_chunk,
+                                 use_graph=True, raise_not_converged=False)
+        torch.cuda.synchronize()
+        wg = time.perf_counter() - tg
+        graph = {"value": pts * rep["iterations"] / wg, "ms_per_step": wg * 1e3 / rep["iterations"],
+                 "iterations": rep["iterations"], "chunk": args.graph_chunk,
+                 "desc": "pprt_two_level_ali, chunks of iterations captured once and replayed "
+                         "(includes capture, instantiation and a host check per chunk)"}
 
     achieved_tflops = pts * FLOPS_PER_POINT / (fs_ms * 1e-3) / 1e12
     traffic = None
@@ -216,9 +240,11 @@ def main():
                                "eps 1e-6..1e-1, seed 3 (one ALI step per step)",
                    "nbatch": batch.nb, "rows": int(batch.nd.sum()), "na": batch.na,
                    "nf": batch.nf, "points_per_step": pts, "seed": 3,
-                   "waves_per_block": args.waves_per_block or "auto"},
+                   "launch": {"waves_per_block": launch[0], "persistent_waves_per_cu": launch[1],
+                              "autotune": tune}},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "graph_mode": graph,
         "fp64_plain": fp64,
         "speedup_vs_fp64_plain": (value / fp64["value"]) if fp64 else None,
         "fp32_vs_fp64": {"S_after_one_step_rel": rel_step, "update_rel": rel_update},

@@ -207,7 +207,9 @@ typedef struct pprt_ali_ctl {
   double tol;            /* stop when max_d |dS|/|S_new| < tol per atmosphere */
   int32_t max_iter;      /* iteration cap, >= 1                               */
   int32_t iters_per_sync;/* iterations enqueued between host checks (>= 1)    */
-  int32_t use_graph;     /* 1: capture the iterations between checks in a hipGraph */
+  int32_t use_graph;     /* 1: capture the iterations_per_sync launches between
+                            checks once in a hipGraph (on a private stream at
+                            the default priority) and replay it; same results */
 } pprt_ali_ctl;
 
 typedef struct pprt_ali_report {
@@ -356,6 +358,82 @@ pprt_status pprt_plan_nlte_workspace_bytes(const pprt_plan* plan, int32_t nlev, 
  * diffusion lower boundary takes B from atom->Bnu. */
 pprt_status pprt_nlte_step(pprt_plan* plan, const pprt_fs_in* in, const pprt_atom* atom,
                            double* pops, double* max_rel, void* workspace);
+
+/* ---- Launch shape of the batched two-level sweep, and its autotuner ------
+ * The batched sweep of pprt_two_level_moments / _ali_step / _ali runs one
+ * wave per (atmosphere, 64-frequency tile, hemisphere), longest atmosphere
+ * first.  Two launch parameters change its speed, never its result (each
+ * wave's arithmetic is the same): waves per block (1, 2, 4, 8) and the grid
+ * form, either one wave per item (persistent_waves_per_cu = 0) or a
+ * persistent grid of n_CU * persistent_waves_per_cu waves that take items
+ * from a device counter (zeroed by a kernel before each launch, so the
+ * launch may be captured in a graph). */
+pprt_status pprt_plan_set_launch(pprt_plan* plan, int32_t waves_per_block,
+                                 int32_t persistent_waves_per_cu);
+pprt_status pprt_plan_get_launch(const pprt_plan* plan, int32_t* waves_per_block,
+                                 int32_t* persistent_waves_per_cu);
+
+#define PPRT_TUNE_FORCE 0x1   /* re-measure even if this shape is cached */
+
+typedef struct pprt_tune_report {
+  int32_t waves_per_block;          /* chosen                                  */
+  int32_t persistent_waves_per_cu;  /* chosen (0 = one wave per item)          */
+  float best_ms;                    /* mean time of the chosen shape           */
+  float default_ms;                 /* mean time of the plan's default shape   */
+  int32_t candidates;               /* shapes measured                         */
+  int32_t from_cache;               /* 1: taken from the in-process cache      */
+} pprt_tune_report;
+
+/* Time every launch shape (4 block sizes x {per-item, persistent at 8, 16,
+ * 32 waves per CU}) on the caller's inputs with HIP events (one warm-up and
+ * three timed launches each, moments only; S is read, not changed; the
+ * workspace's moment area is overwritten), keep the fastest in the plan and
+ * in an in-process cache keyed by device, precision, na, nf and the depth
+ * counts.  A later plan of the same shape takes the cached choice without
+ * measuring unless flags has PPRT_TUNE_FORCE.  Synchronises the stream. */
+pprt_status pprt_plan_autotune(pprt_plan* plan, const pprt_fs_in* in, const pprt_two_level* atom,
+                               const double* S, void* workspace, int32_t flags,
+                               pprt_tune_report* report);
+
+/* ---- Gradients of the emergent spectrum (omega = 0) ----------------------
+ * The emergent intensity I+(tau_1, mu_i, nu_k) of the plane-parallel formal
+ * solution without in-layer scattering (Sect. 3.2 comparison calculation,
+ * linear source between nodes) and the vector-Jacobian product of that map:
+ * given g = dL/dIemerg for any scalar loss L, the derivatives of L with
+ * respect to every q and S^g entry and to the lower-boundary data.  The
+ * adjoint is hand-written (reverse sweep of the layer recursion).  The
+ * forward call keeps the difference-form intensity of every K-th depth node
+ * in the workspace (layer checkpointing); the reverse call recomputes each
+ * segment of K layers from the checkpoint below it.  K (checkpoint_interval)
+ * is 1, 8, 16 or 32: memory sum_b (floor((nd_b - 1)/K) + 1) * nf * na reals.
+ * Both calls take q, Sg, Bbot/Bbot_prev (DIFFUSION) or Ibot (GIVEN) from
+ * `in`; Itop does not enter (I+ is independent of the down-going field when
+ * omega = 0).  Element type follows the plan's precision.  Any na in 1..32
+ * is supported (lanes are padded to a power of two). */
+typedef struct pprt_fs_grad {
+  void* dq;          /* real [rows][nf]     dL/dq   (required)                */
+  void* dSg;         /* real [rows][nf]     dL/dS^g (required)                */
+  void* dBbot;       /* real [nb][nf]       DIFFUSION; NULL = not written     */
+  void* dBbot_prev;  /* real [nb][nf]       DIFFUSION; NULL = not written     */
+  void* dIbot;       /* real [nb][nf][na]   GIVEN;     NULL = not written     */
+} pprt_fs_grad;
+
+/* Checkpoint workspace (bytes) for interval K; E_INVALID_ARG for other K. */
+pprt_status pprt_plan_adjoint_workspace_bytes(const pprt_plan* plan, int32_t checkpoint_interval,
+                                              size_t* bytes);
+
+/* Forward: Iemerg [nb][nf][na] and the checkpoints in `workspace`
+ * (caller-owned, at least pprt_plan_adjoint_workspace_bytes).  Asynchronous. */
+pprt_status pprt_emergent_intensity(pprt_plan* plan, const pprt_fs_in* in,
+                                    int32_t checkpoint_interval, void* Iemerg, void* workspace);
+
+/* Reverse: gIemerg [nb][nf][na] in, gradients out.  `workspace` must hold
+ * the checkpoints written by pprt_emergent_intensity for the same inputs
+ * and interval (otherwise the result is undefined; nothing faults).
+ * Every output entry is overwritten.  Asynchronous. */
+pprt_status pprt_formal_solution_vjp(pprt_plan* plan, const pprt_fs_in* in,
+                                     int32_t checkpoint_interval, const void* gIemerg,
+                                     const pprt_fs_grad* grad, void* workspace);
 
 #ifdef __cplusplus
 }

@@ -61,8 +61,10 @@ __global__ __launch_bounds__(256) void k_ali_update(AliUpdateArgs a) {
   if (threadIdx.x == 0) {
     const double m = red[0];
     a.max_rel[b] = m;
-    if (a.iters != nullptr) a.iters[b] += 1;
+    int it = 0;
+    if (a.iters != nullptr) it = (a.iters[b] += 1);
     if (a.active != nullptr && a.tol > 0.0 && m < a.tol) a.active[b] = 0;
+    if (a.active != nullptr && a.max_iter > 0 && it >= a.max_iter) a.active[b] = 0;
   }
 }
 

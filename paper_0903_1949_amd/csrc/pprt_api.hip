@@ -6,6 +6,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -35,6 +37,14 @@ struct pprt_plan {
   int n_prof = 0;
   Item* d_items_dense = nullptr;
   int n_dense = 0;
+  Item* d_items_adj = nullptr;    // (atmosphere, block of wpb_adj * 64 / lanes-per-freq freqs)
+  int n_adj = 0, wpb_adj = 4;
+  int64_t* d_ck_off[33] = {};     // checkpoint-row offsets per interval K (built on first use)
+  int prof_blocks = 0;            // batched sweep: 0 = one wave per item, else persistent grid size
+  int prof_wpc = 0;               // persistent: resident waves per CU the grid was sized for
+  int32_t* d_queue = nullptr;     // persistent work counter
+  int n_cu = 256;
+  int64_t ck_rows[33] = {};
   int64_t* d_off = nullptr;
   std::vector<double> mu, w;
   Angles<float> af{};
@@ -151,10 +161,71 @@ void fill_angles(Angles<T>& A, const std::vector<double>& mu, const std::vector<
     hs += 0.5 * w[i];
   }
   A.hwsum = (T)hs;
+  double rmax = 0.0, rmin = 1e300;
+  for (size_t i = 0; i < mu.size(); ++i) {
+    rmax = std::max(rmax, 1.0 / mu[i]);
+    rmin = std::min(rmin, 1.0 / mu[i]);
+  }
+  A.rmu_max = (T)rmax;
+  A.rmu_min = (T)rmin;
 }
 
 const void* angles_of(const pprt_plan* p) {
   return p->precision == PPRT_FP64 ? (const void*)&p->ad : (const void*)&p->af;
+}
+
+// Checkpoint rows of interval K: atmosphere b keeps nodes 0, K, 2K, .. <= nd_b - 1.
+int64_t ck_rows_of(const pprt_plan* p, int K) {
+  int64_t n = 0;
+  for (int b = 0; b < p->nb; ++b) n += (p->nd[b] - 1) / K + 1;
+  return n;
+}
+
+pprt_status ensure_ck_off(pprt_plan* p, int K) {
+  if (p->d_ck_off[K]) return PPRT_OK;
+  std::vector<int64_t> ck(p->nb);
+  int64_t n = 0;
+  for (int b = 0; b < p->nb; ++b) {
+    ck[b] = n;
+    n += (p->nd[b] - 1) / K + 1;
+  }
+  int64_t* d = nullptr;
+  hipError_t e = hipMalloc(&d, ck.size() * sizeof(int64_t));
+  if (e == hipSuccess) e = hipMemcpy(d, ck.data(), ck.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    if (d) (void)hipFree(d);
+    return hip_check(p->ctx, e, "checkpoint offsets");
+  }
+  p->d_ck_off[K] = d;
+  p->ck_rows[K] = n;
+  return PPRT_OK;
+}
+
+template <typename T>
+void fill_adj_args(const pprt_plan* p, const pprt_fs_in* in, int K, AdjArgs<T>& a) {
+  a.items = p->d_items_adj;
+  a.off = p->d_off;
+  a.ck_off = p->d_ck_off[K];
+  a.tau = in->tau;
+  a.q = (const T*)in->q;
+  a.Sg = (const T*)in->Sg;
+  a.Bbot = (const T*)in->Bbot;
+  a.Bbot_prev = (const T*)in->Bbot_prev;
+  a.Ibot = (const T*)in->Ibot;
+  a.nf = p->nf;
+  a.na = p->na;
+  a.lower_bc = p->lower_bc;
+}
+
+pprt_status adj_common_checks(pprt_plan* p, const pprt_fs_in* in, int K, void* ws) {
+  pprt_ctx* c = p->ctx;
+  if (!in || !in->tau || !in->q || !in->Sg) return fail(c, PPRT_E_INVALID_ARG, "tau, q and Sg are required");
+  if (!adj_interval_supported(K))
+    return fail(c, PPRT_E_INVALID_ARG, "checkpoint interval %d: use 1, 8, 16 or 32", K);
+  if (p->lower_bc == PPRT_BC_DIFFUSION && (!in->Bbot || !in->Bbot_prev))
+    return fail(c, PPRT_E_INVALID_ARG, "diffusion lower boundary needs Bbot and Bbot_prev");
+  if (!ws) return fail(c, PPRT_E_WORKSPACE, "checkpoint workspace required (pprt_plan_adjoint_workspace_bytes)");
+  return ensure_ck_off(p, K);
 }
 
 }  // namespace
@@ -306,7 +377,8 @@ pprt_status pprt_plan_create(pprt_ctx* c, const pprt_shape* sh, const double* mu
   std::vector<int> order(p->nb);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return p->nd[x] > p->nd[y]; });
-  std::vector<Item> full, prof, dns;
+  std::vector<Item> full, prof, dns, adj;
+  const int fpb_adj = p->wpb_adj * 64 / adj_lanes_per_freq(p->na);
   full.reserve((size_t)p->nb * p->ng);
   prof.reserve((size_t)p->nb * p->ng * 2);
   for (int b : order) {
@@ -316,18 +388,30 @@ pprt_status pprt_plan_create(pprt_ctx* c, const pprt_shape* sh, const double* mu
       prof.push_back(Item{b, t, 0, p->nd[b]});
       prof.push_back(Item{b, t, 1, p->nd[b]});
     }
+    for (int t = 0; t < (p->nf + fpb_adj - 1) / fpb_adj; ++t) adj.push_back(Item{b, t, 0, p->nd[b]});
     if (dense_na_supported(p->na)) {
       const int F = dense_freqs_per_item(p->na);
       for (int t = 0; t < (p->nf + F - 1) / F; ++t) dns.push_back(Item{b, t, 0, p->nd[b]});
     }
   }
   p->n_dense = (int)dns.size();
+  p->n_adj = (int)adj.size();
   p->n_full = (int)full.size();
   p->n_prof = (int)prof.size();
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = hipMalloc(&p->d_items_full, full.size() * sizeof(Item));
   if (e == hipSuccess) e = hipMalloc(&p->d_items_prof, prof.size() * sizeof(Item));
   if (e == hipSuccess) e = hipMalloc(&p->d_off, p->off.size() * sizeof(int64_t));
+  if (e == hipSuccess) e = hipMalloc(&p->d_items_adj, adj.size() * sizeof(Item));
+  if (e == hipSuccess) e = hipMalloc(&p->d_queue, sizeof(int32_t));
+  if (e == hipSuccess) {
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess &&
+        ncu > 0)
+      p->n_cu = ncu;
+  }
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_items_adj, adj.data(), adj.size() * sizeof(Item), hipMemcpyHostToDevice);
   if (e == hipSuccess && !dns.empty()) e = hipMalloc(&p->d_items_dense, dns.size() * sizeof(Item));
   if (e == hipSuccess && !dns.empty())
     e = hipMemcpy(p->d_items_dense, dns.data(), dns.size() * sizeof(Item), hipMemcpyHostToDevice);
@@ -364,6 +448,10 @@ void pprt_plan_destroy(pprt_plan* p) {
   if (p->d_items_prof) (void)hipFree(p->d_items_prof);
   if (p->d_off) (void)hipFree(p->d_off);
   if (p->d_items_dense) (void)hipFree(p->d_items_dense);
+  if (p->d_items_adj) (void)hipFree(p->d_items_adj);
+  if (p->d_queue) (void)hipFree(p->d_queue);
+  for (auto* ck : p->d_ck_off)
+    if (ck) (void)hipFree(ck);
   delete p;
 }
 
@@ -474,41 +562,88 @@ static pprt_status ali_moments_impl(pprt_plan* p, const pprt_fs_in* in, const pp
   pprt_ctx* c = p->ctx;
   void* part = (char*)ws + p->ws_part;
   hipError_t e;
+  if (p->prof_blocks) {   // zero the work counter with a kernel (safe inside a captured graph)
+    e = launch_fill_i32(p->d_queue, 0, 1, c->stream);
+    if (e != hipSuccess) return hip_check(c, e, "work counter reset");
+  }
   if (p->precision == PPRT_FP64) {
     FsProfileArgs<double> a{};
     a.items = p->d_items_prof; a.off = p->d_off; a.tau = in->tau; a.q = (const double*)in->q;
     a.S = S; a.B = at->B; a.Itop = (const double*)in->Itop; a.Ibot = (const double*)in->Ibot;
     a.wphi = (const double*)at->wphi; a.active = active; a.part = (double*)part;
+    a.queue = p->prof_blocks ? p->d_queue : nullptr;
     a.nf = p->nf; a.nw = p->nw; a.nitems = p->n_prof; a.lower_bc = p->lower_bc;
-    e = launch_fs_profile(p->precision, p->na, p->wpb, p->n_prof, c->stream, &a, angles_of(p));
+    e = launch_fs_profile(p->precision, p->na, p->wpb, p->n_prof, p->prof_blocks, c->stream, &a,
+                          angles_of(p));
   } else {
     FsProfileArgs<float> a{};
     a.items = p->d_items_prof; a.off = p->d_off; a.tau = in->tau; a.q = (const float*)in->q;
     a.S = S; a.B = at->B; a.Itop = (const float*)in->Itop; a.Ibot = (const float*)in->Ibot;
     a.wphi = (const float*)at->wphi; a.active = active; a.part = (float*)part;
+    a.queue = p->prof_blocks ? p->d_queue : nullptr;
     a.nf = p->nf; a.nw = p->nw; a.nitems = p->n_prof; a.lower_bc = p->lower_bc;
-    e = launch_fs_profile(p->precision, p->na, p->wpb, p->n_prof, c->stream, &a, angles_of(p));
+    e = launch_fs_profile(p->precision, p->na, p->wpb, p->n_prof, p->prof_blocks, c->stream, &a,
+                          angles_of(p));
   }
   return hip_check(c, e, "profile formal-solution launch");
 }
 
 static pprt_status ali_update_impl(pprt_plan* p, const pprt_two_level* at, double* S,
                                    double* max_rel, int32_t* active, int32_t* iters, double tol,
-                                   void* ws) {
+                                   void* ws, int max_iter = 0) {
   pprt_ctx* c = p->ctx;
   AliUpdateArgs u{};
   u.off = p->d_off; u.part = (const void*)((char*)ws + p->ws_part); u.eps = at->eps; u.B = at->B;
   u.S = S; u.max_rel = max_rel; u.active = active; u.iters = iters; u.status = c->d_status;
-  u.tol = tol; u.nw = p->nw; u.nb = p->nb; u.part_fp64 = (p->precision == PPRT_FP64);
+  u.tol = tol; u.max_iter = max_iter; u.nw = p->nw; u.nb = p->nb;
+  u.part_fp64 = (p->precision == PPRT_FP64);
   return hip_check(c, launch_ali_update(p->nb, c->stream, u), "ALI update launch");
 }
 
 static pprt_status ali_step_impl(pprt_plan* p, const pprt_fs_in* in, const pprt_two_level* at,
                                  double* S, double* max_rel, int32_t* active, int32_t* iters,
-                                 double tol, void* ws) {
+                                 double tol, void* ws, int max_iter = 0) {
   pprt_status r = ali_moments_impl(p, in, at, S, active, ws);
   if (r != PPRT_OK) return r;
-  return ali_update_impl(p, at, S, max_rel, active, iters, tol, ws);
+  return ali_update_impl(p, at, S, max_rel, active, iters, tol, ws, max_iter);
+}
+
+// A captured chunk of ALI iterations (graph mode of pprt_two_level_ali).
+struct GraphChunk {
+  hipStream_t cs = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  GraphChunk() = default;
+  GraphChunk(const GraphChunk&) = delete;
+  GraphChunk& operator=(const GraphChunk&) = delete;
+  ~GraphChunk() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cs) (void)hipStreamDestroy(cs);
+  }
+};
+
+static pprt_status capture_ali_chunk(pprt_plan* p, const pprt_fs_in* in, const pprt_two_level* at,
+                                     double* S, double* maxrel, int32_t* active, int32_t* its,
+                                     double tol, int max_iter, int G, void* ws, GraphChunk& gc) {
+  pprt_ctx* c = p->ctx;
+  pprt_status r = hip_check(c, hipStreamCreateWithFlags(&gc.cs, hipStreamNonBlocking), "capture stream");
+  if (r != PPRT_OK) return r;
+  r = hip_check(c, hipStreamBeginCapture(gc.cs, hipStreamCaptureModeThreadLocal), "begin capture");
+  if (r != PPRT_OK) return r;
+  hipStream_t saved = c->stream;
+  c->stream = gc.cs;
+  pprt_status rs = PPRT_OK;
+  for (int j = 0; j < G && rs == PPRT_OK; ++j)
+    rs = ali_step_impl(p, in, at, S, maxrel, active, its, tol, ws, max_iter);
+  c->stream = saved;
+  hipGraph_t g = nullptr;
+  const hipError_t ee = hipStreamEndCapture(gc.cs, &g);
+  gc.graph = g;
+  if (rs != PPRT_OK) return rs;
+  r = hip_check(c, ee, "end capture");
+  if (r != PPRT_OK) return r;
+  return hip_check(c, hipGraphInstantiate(&gc.exec, gc.graph, nullptr, nullptr, 0), "graph instantiate");
 }
 
 static pprt_status check_ali_args(pprt_plan* p, const pprt_fs_in* in, const pprt_two_level* at,
@@ -655,11 +790,26 @@ pprt_status pprt_two_level_ali(pprt_plan* p, const pprt_fs_in* in, const pprt_tw
   std::vector<double> h_max(p->nb);
   int done_iters = 0;
   bool all_done = false;
+  // Graph mode: the iterations between host checks are captured once (on a
+  // private stream at the default priority) and replayed on the context
+  // stream.  The update kernel retires an atmosphere at max_iter itself, so a
+  // replayed chunk does exactly what the same eager launches would.
+  GraphChunk gc;
+  const int G = ctl->iters_per_sync;
+  if (ctl->use_graph && G <= ctl->max_iter) {
+    r = capture_ali_chunk(p, in, at, S, maxrel, active, its, ctl->tol, ctl->max_iter, G, ws, gc);
+    if (r != PPRT_OK) return r;
+  }
   while (done_iters < ctl->max_iter) {
-    const int m = std::min(ctl->iters_per_sync, ctl->max_iter - done_iters);
-    for (int j = 0; j < m; ++j) {
-      r = ali_step_impl(p, in, at, S, maxrel, active, its, ctl->tol, ws);
+    const int m = std::min(G, ctl->max_iter - done_iters);
+    if (gc.exec && m == G) {
+      r = hip_check(c, hipGraphLaunch(gc.exec, c->stream), "graph launch");
       if (r != PPRT_OK) return r;
+    } else {
+      for (int j = 0; j < m; ++j) {
+        r = ali_step_impl(p, in, at, S, maxrel, active, its, ctl->tol, ws, ctl->max_iter);
+        if (r != PPRT_OK) return r;
+      }
     }
     done_iters += m;
     r = hip_check(c, hipMemcpyAsync(h_active.data(), active, p->nb * sizeof(int32_t),
@@ -678,15 +828,17 @@ pprt_status pprt_two_level_ali(pprt_plan* p, const pprt_fs_in* in, const pprt_tw
     r = hip_check(c, hipMemcpy(iters, its, p->nb * sizeof(int32_t), hipMemcpyDeviceToDevice), "iters copy");
     if (r != PPRT_OK) return r;
   }
+  const int32_t n_conv =
+      (int32_t)std::count_if(h_max.begin(), h_max.end(), [&](double m) { return m < ctl->tol; });
   if (rep) {
     rep->iterations = *std::max_element(h_iters.begin(), h_iters.end());
-    rep->n_converged = (int32_t)std::count(h_active.begin(), h_active.end(), 0);
+    rep->n_converged = n_conv;
     rep->max_rel = *std::max_element(h_max.begin(), h_max.end());
   }
   uint32_t st = 0;
   r = pprt_sync(c, &st);
   if (r != PPRT_OK) return r;
-  if (!all_done) return fail(c, PPRT_E_NOT_CONVERGED, "ALI not converged after %d iterations", done_iters);
+  if (n_conv < p->nb) return fail(c, PPRT_E_NOT_CONVERGED, "ALI not converged after %d iterations", done_iters);
   return PPRT_OK;
 }
 
@@ -849,6 +1001,195 @@ pprt_status pprt_nlte_step(pprt_plan* p, const pprt_fs_in* in, const pprt_atom* 
   if (r != PPRT_OK) return r;
   return hip_check(c, hipMemcpyAsync(pops, pn, (size_t)p->rows * at->nlev * sizeof(double),
                                      hipMemcpyDeviceToDevice, c->stream), "population copy");
+}
+
+pprt_status pprt_plan_adjoint_workspace_bytes(const pprt_plan* p, int32_t K, size_t* bytes) {
+  if (!p || !bytes) return PPRT_E_INVALID_ARG;
+  if (!adj_interval_supported(K)) return PPRT_E_INVALID_ARG;
+  const size_t el = p->precision == PPRT_FP64 ? sizeof(double) : sizeof(float);
+  *bytes = align256((size_t)ck_rows_of(p, K) * p->nf * p->na * el);
+  return PPRT_OK;
+}
+
+pprt_status pprt_emergent_intensity(pprt_plan* p, const pprt_fs_in* in, int32_t K, void* Iemerg,
+                                    void* ws) {
+  if (!p) return PPRT_E_INVALID_ARG;
+  pprt_ctx* c = p->ctx;
+  if (!Iemerg) return fail(c, PPRT_E_INVALID_ARG, "Iemerg is required");
+  pprt_status r = adj_common_checks(p, in, K, ws);
+  if (r != PPRT_OK) return r;
+  hipError_t e;
+  if (p->precision == PPRT_FP64) {
+    AdjArgs<double> a{};
+    fill_adj_args(p, in, K, a);
+    a.Iemerg = (double*)Iemerg;
+    a.ckpt = (double*)ws;
+    e = launch_emergent(p->precision, false, p->na, K, p->n_adj, p->wpb_adj, c->stream, &a, angles_of(p));
+  } else {
+    AdjArgs<float> a{};
+    fill_adj_args(p, in, K, a);
+    a.Iemerg = (float*)Iemerg;
+    a.ckpt = (float*)ws;
+    e = launch_emergent(p->precision, false, p->na, K, p->n_adj, p->wpb_adj, c->stream, &a, angles_of(p));
+  }
+  return hip_check(c, e, "emergent-intensity launch");
+}
+
+pprt_status pprt_formal_solution_vjp(pprt_plan* p, const pprt_fs_in* in, int32_t K,
+                                     const void* gIemerg, const pprt_fs_grad* g, void* ws) {
+  if (!p) return PPRT_E_INVALID_ARG;
+  pprt_ctx* c = p->ctx;
+  if (!gIemerg || !g || !g->dq || !g->dSg)
+    return fail(c, PPRT_E_INVALID_ARG, "gIemerg, grad->dq and grad->dSg are required");
+  pprt_status r = adj_common_checks(p, in, K, ws);
+  if (r != PPRT_OK) return r;
+  hipError_t e;
+  if (p->precision == PPRT_FP64) {
+    AdjArgs<double> a{};
+    fill_adj_args(p, in, K, a);
+    a.ckpt = (double*)ws;
+    a.gI = (const double*)gIemerg;
+    a.dq = (double*)g->dq; a.dSg = (double*)g->dSg; a.dBbot = (double*)g->dBbot;
+    a.dBbot_prev = (double*)g->dBbot_prev; a.dIbot = (double*)g->dIbot;
+    e = launch_emergent(p->precision, true, p->na, K, p->n_adj, p->wpb_adj, c->stream, &a, angles_of(p));
+  } else {
+    AdjArgs<float> a{};
+    fill_adj_args(p, in, K, a);
+    a.ckpt = (float*)ws;
+    a.gI = (const float*)gIemerg;
+    a.dq = (float*)g->dq; a.dSg = (float*)g->dSg; a.dBbot = (float*)g->dBbot;
+    a.dBbot_prev = (float*)g->dBbot_prev; a.dIbot = (float*)g->dIbot;
+    e = launch_emergent(p->precision, true, p->na, K, p->n_adj, p->wpb_adj, c->stream, &a, angles_of(p));
+  }
+  return hip_check(c, e, "adjoint launch");
+}
+
+// ---- launch shape of the batched sweep and its autotuner -----------------
+
+pprt_status pprt_plan_set_launch(pprt_plan* p, int32_t wpb, int32_t persistent_waves_per_cu) {
+  if (!p) return PPRT_E_INVALID_ARG;
+  pprt_ctx* c = p->ctx;
+  if (wpb != 1 && wpb != 2 && wpb != 4 && wpb != 8)
+    return fail(c, PPRT_E_INVALID_ARG, "waves per block must be 1, 2, 4 or 8 (got %d)", wpb);
+  if (persistent_waves_per_cu < 0 || persistent_waves_per_cu > 32)
+    return fail(c, PPRT_E_INVALID_ARG, "persistent waves per CU must be in 0..32 (got %d)",
+                persistent_waves_per_cu);
+  p->wpb = wpb;
+  p->prof_wpc = persistent_waves_per_cu;
+  p->prof_blocks = persistent_waves_per_cu ? std::max(1, p->n_cu * persistent_waves_per_cu / wpb) : 0;
+  return PPRT_OK;
+}
+
+}  // extern "C"
+
+namespace {
+struct TuneChoice {
+  int wpb, wpc;
+  float best_ms, default_ms;
+  int candidates;
+};
+std::mutex g_tune_mu;
+std::map<std::string, TuneChoice> g_tune_cache;
+
+std::string tune_key(const pprt_plan* p) {
+  uint64_t h = 1469598103934665603ull;   // FNV-1a over the depth counts
+  for (int32_t v : p->nd) {
+    h ^= (uint64_t)(uint32_t)v;
+    h *= 1099511628211ull;
+  }
+  char buf[160];
+  snprintf(buf, sizeof buf, "dev%d p%d na%d nf%d nb%d rows%lld bc%d nd%016llx", p->ctx->device,
+           p->precision, p->na, p->nf, p->nb, (long long)p->rows, p->lower_bc,
+           (unsigned long long)h);
+  return buf;
+}
+}  // namespace
+
+extern "C" {
+
+pprt_status pprt_plan_autotune(pprt_plan* p, const pprt_fs_in* in, const pprt_two_level* at,
+                               const double* S, void* ws, int32_t flags, pprt_tune_report* rep) {
+  if (!p) return PPRT_E_INVALID_ARG;
+  pprt_ctx* c = p->ctx;
+  pprt_status r = check_ali_args(p, in, at, S, ws);
+  if (r != PPRT_OK) return r;
+  const std::string key = tune_key(p);
+  if (!(flags & PPRT_TUNE_FORCE)) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      r = pprt_plan_set_launch(p, it->second.wpb, it->second.wpc);
+      if (r != PPRT_OK) return r;
+      if (rep) {
+        rep->waves_per_block = it->second.wpb;
+        rep->persistent_waves_per_cu = it->second.wpc;
+        rep->best_ms = it->second.best_ms;
+        rep->default_ms = it->second.default_ms;
+        rep->candidates = it->second.candidates;
+        rep->from_cache = 1;
+      }
+      return PPRT_OK;
+    }
+  }
+  const int default_wpb = p->nf <= 64 ? 1 : (p->nf <= 128 ? 2 : 4);
+  const int wpbs[] = {1, 2, 4, 8};
+  const int wpcs[] = {0, 8, 16, 32};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  r = hip_check(c, hipEventCreate(&e0), "event");
+  if (r == PPRT_OK) r = hip_check(c, hipEventCreate(&e1), "event");
+  TuneChoice best{default_wpb, 0, 1e30f, 0.f, 0};
+  const int reps = 3;
+  for (int wpb : wpbs) {
+    for (int wpc : wpcs) {
+      if (r != PPRT_OK) break;
+      r = pprt_plan_set_launch(p, wpb, wpc);
+      if (r != PPRT_OK) break;
+      r = ali_moments_impl(p, in, at, S, nullptr, ws);       // warm-up
+      if (r == PPRT_OK) r = hip_check(c, hipEventRecord(e0, c->stream), "event record");
+      for (int k = 0; k < reps && r == PPRT_OK; ++k) r = ali_moments_impl(p, in, at, S, nullptr, ws);
+      if (r == PPRT_OK) r = hip_check(c, hipEventRecord(e1, c->stream), "event record");
+      if (r == PPRT_OK) r = hip_check(c, hipEventSynchronize(e1), "event sync");
+      float ms = 0.f;
+      if (r == PPRT_OK) r = hip_check(c, hipEventElapsedTime(&ms, e0, e1), "event time");
+      if (r != PPRT_OK) break;
+      ms /= reps;
+      ++best.candidates;
+      if (wpb == default_wpb && wpc == 0) best.default_ms = ms;
+      if (ms < best.best_ms) {
+        best.best_ms = ms;
+        best.wpb = wpb;
+        best.wpc = wpc;
+      }
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (r != PPRT_OK) {
+    (void)pprt_plan_set_launch(p, default_wpb, 0);
+    return r;
+  }
+  r = pprt_plan_set_launch(p, best.wpb, best.wpc);
+  if (r != PPRT_OK) return r;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = best;
+  }
+  if (rep) {
+    rep->waves_per_block = best.wpb;
+    rep->persistent_waves_per_cu = best.wpc;
+    rep->best_ms = best.best_ms;
+    rep->default_ms = best.default_ms;
+    rep->candidates = best.candidates;
+    rep->from_cache = 0;
+  }
+  return PPRT_OK;
+}
+
+pprt_status pprt_plan_get_launch(const pprt_plan* p, int32_t* wpb, int32_t* persistent_waves_per_cu) {
+  if (!p) return PPRT_E_INVALID_ARG;
+  if (wpb) *wpb = p->wpb;
+  if (persistent_waves_per_cu) *persistent_waves_per_cu = p->prof_wpc;
+  return PPRT_OK;
 }
 
 }  // extern "C"

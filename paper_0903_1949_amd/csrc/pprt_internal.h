@@ -23,6 +23,8 @@ struct Angles {
   T hw[kMaxNA];    // w_i / 2
   T hwmu[kMaxNA];  // w_i mu_i / 2
   T hwsum;         // sum_i w_i / 2 (one hemisphere's weight)
+  T rmu_max;       // max_i 1/mu_i (the angle with the largest Delta)
+  T rmu_min;       // min_i 1/mu_i
 };
 
 // One work item: atmosphere b, frequency group g (blockDim.x frequencies),
@@ -63,6 +65,7 @@ struct FsProfileArgs {
   const T* Ibot;
   const T* wphi;            // [nf]
   const int32_t* active;    // [nb] or nullptr
+  int32_t* queue;           // persistent launch: work counter (zeroed before launch); else nullptr
   T* part;                  // [rows][nw][2 dir][2] per-wave profile moments
   int32_t nf;
   int32_t nw;               // waves across the frequency range, ceil(nf/64)
@@ -81,10 +84,39 @@ struct AliUpdateArgs {
   int32_t* iters;           // [nb] or nullptr
   uint32_t* status;         // device status word
   double tol;               // > 0: clear `active` once max_rel < tol
+  int32_t max_iter;         // > 0: clear `active` once iters reaches it
   int32_t nw;
   int32_t nb;
   int32_t part_fp64;
 };
+
+// Emergent intensity and its adjoint (fs_adjoint.hip).  Item.g indexes
+// blocks of wpb * 64 / lanes_per_freq frequencies.
+template <typename T>
+struct AdjArgs {
+  const Item* items;
+  const int64_t* off;       // [nb+1] row offsets
+  const int64_t* ck_off;    // [nb] checkpoint-row offsets for the interval in use
+  const double* tau;
+  const T* q;
+  const T* Sg;
+  const T* Bbot;
+  const T* Bbot_prev;
+  const T* Ibot;
+  T* Iemerg;                // [nb][nf][na] (forward)
+  T* ckpt;                  // [checkpoint rows][nf][na]
+  const T* gI;              // [nb][nf][na] dL/dIemerg (adjoint)
+  T* dq;                    // [rows][nf]
+  T* dSg;                   // [rows][nf]
+  T* dBbot;                 // [nb][nf] or nullptr
+  T* dBbot_prev;            // [nb][nf] or nullptr
+  T* dIbot;                 // [nb][nf][na] or nullptr
+  int32_t nf, na, lower_bc;
+};
+int adj_lanes_per_freq(int na);
+bool adj_interval_supported(int K);
+hipError_t launch_emergent(int precision, bool vjp, int na, int K, int nitems, int wpb,
+                           hipStream_t s, const void* args, const void* angles);
 
 // Dense (in-layer scattering) formal solution, FP64 (fs_dense.hip).
 struct DenseLaunch {
@@ -145,7 +177,9 @@ hipError_t launch_gather_bottom(const double* Bnu, const int64_t* off, int nb, i
 // Launchers (fs_diag.hip, ali.hip).  Return hipSuccess or the launch error.
 hipError_t launch_fs_full(int precision, int na, int wpb, int nitems, hipStream_t s,
                           const void* args, const void* angles);
-hipError_t launch_fs_profile(int precision, int na, int wpb, int nitems, hipStream_t s,
+// nblocks = 0: one wave per item; otherwise a persistent grid of nblocks
+// blocks whose waves take items from args.queue.
+hipError_t launch_fs_profile(int precision, int na, int wpb, int nitems, int nblocks, hipStream_t s,
                              const void* args, const void* angles);
 hipError_t launch_ali_update(int nb, hipStream_t s, const AliUpdateArgs& a);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);

@@ -54,6 +54,17 @@ class FsOut(C.Structure):
                 ("H", C.c_void_p), ("Iemerg", C.c_void_p)]
 
 
+class FsGrad(C.Structure):
+    _fields_ = [("dq", C.c_void_p), ("dSg", C.c_void_p), ("dBbot", C.c_void_p),
+                ("dBbot_prev", C.c_void_p), ("dIbot", C.c_void_p)]
+
+
+class TuneReport(C.Structure):
+    _fields_ = [("waves_per_block", C.c_int32), ("persistent_waves_per_cu", C.c_int32),
+                ("best_ms", C.c_float), ("default_ms", C.c_float), ("candidates", C.c_int32),
+                ("from_cache", C.c_int32)]
+
+
 class TwoLevel(C.Structure):
     _fields_ = [("eps", C.c_void_p), ("B", C.c_void_p), ("wphi", C.c_void_p)]
 
@@ -121,6 +132,13 @@ def load_library(path: str = LIB_PATH):
         "pprt_two_level_update": (I, [P, C.POINTER(TwoLevel), P, P, P, P]),
         "pprt_two_level_ali": (I, [P, C.POINTER(FsIn), C.POINTER(TwoLevel), C.POINTER(AliCtl),
                                    P, P, C.POINTER(AliReport), P]),
+        "pprt_plan_adjoint_workspace_bytes": (I, [P, C.c_int32, C.POINTER(C.c_size_t)]),
+        "pprt_plan_set_launch": (I, [P, C.c_int32, C.c_int32]),
+        "pprt_plan_get_launch": (I, [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+        "pprt_plan_autotune": (I, [P, C.POINTER(FsIn), C.POINTER(TwoLevel), P, P, C.c_int32,
+                                   C.POINTER(TuneReport)]),
+        "pprt_emergent_intensity": (I, [P, C.POINTER(FsIn), C.c_int32, P, P]),
+        "pprt_formal_solution_vjp": (I, [P, C.POINTER(FsIn), C.c_int32, P, C.POINTER(FsGrad), P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -320,6 +338,49 @@ class Plan:
                         "formal_solution")
         return out
 
+    # ------------------------------------------------ emergent intensity + adjoint
+    def adjoint_workspace_bytes(self, checkpoint_interval: int = 16) -> int:
+        n = C.c_size_t()
+        self.ctx._check(self.lib.pprt_plan_adjoint_workspace_bytes(self.h, int(checkpoint_interval),
+                                                                   C.byref(n)), "adjoint_workspace_bytes")
+        return n.value
+
+    def emergent_intensity(self, tau, q, Sg, Bbot=None, Bbot_prev=None, Ibot=None,
+                           checkpoint_interval: int = 16, workspace=None):
+        """pprt_emergent_intensity: returns (Iemerg [nb, nf, na], checkpoint workspace)."""
+        import torch
+        fin = self.fs_in(tau, q, Sg, Bbot, Bbot_prev, None, Ibot)
+        nbytes = self.adjoint_workspace_bytes(checkpoint_interval)
+        if workspace is None:
+            workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=tau.device)
+        elif workspace.numel() * workspace.element_size() < nbytes:
+            raise ValueError(f"checkpoint workspace needs {nbytes} bytes")
+        Iem = torch.empty((self.nb, self.nf, self.na), dtype=self.dtype, device=tau.device)
+        self.ctx._check(self.lib.pprt_emergent_intensity(self.h, C.byref(fin), int(checkpoint_interval),
+                                                         _ptr(Iem), _ptr(workspace)),
+                        "emergent_intensity")
+        return Iem, workspace
+
+    def formal_solution_vjp(self, tau, q, Sg, gIemerg, workspace, Bbot=None, Bbot_prev=None,
+                            Ibot=None, checkpoint_interval: int = 16) -> dict:
+        """pprt_formal_solution_vjp: dL/dq, dL/dSg and the lower-boundary adjoints."""
+        import torch
+        fin = self.fs_in(tau, q, Sg, Bbot, Bbot_prev, None, Ibot)
+        self._want(gIemerg, (self.nb, self.nf, self.na), self.dtype, "gIemerg")
+        R, nf, na, nb, dt, dev = self.rows, self.nf, self.na, self.nb, self.dtype, tau.device
+        g = {"dq": torch.empty((R, nf), dtype=dt, device=dev),
+             "dSg": torch.empty((R, nf), dtype=dt, device=dev)}
+        if self.lower_bc == BC_DIFFUSION:
+            g["dBbot"] = torch.empty((nb, nf), dtype=dt, device=dev)
+            g["dBbot_prev"] = torch.empty((nb, nf), dtype=dt, device=dev)
+        else:
+            g["dIbot"] = torch.empty((nb, nf, na), dtype=dt, device=dev)
+        fg = FsGrad(**{k: _ptr(v) for k, v in g.items()})
+        self.ctx._check(self.lib.pprt_formal_solution_vjp(self.h, C.byref(fin), int(checkpoint_interval),
+                                                          _ptr(gIemerg), C.byref(fg), _ptr(workspace)),
+                        "formal_solution_vjp")
+        return g
+
     def formal_solution_scattering(self, tau, q, Sg, omega, Bbot=None, Bbot_prev=None, Itop=None,
                                    Ibot=None, out: dict | None = None, workspace=None) -> dict:
         """pprt_formal_solution_scattering (in-layer coherent isotropic scattering)."""
@@ -479,6 +540,29 @@ class Plan:
             return report
         self.ctx._check(st, "two_level_ali")
         return report
+
+
+    # ------------------------------------------------ launch shape / autotuner
+    def set_launch(self, waves_per_block: int, persistent_waves_per_cu: int = 0):
+        self.ctx._check(self.lib.pprt_plan_set_launch(self.h, int(waves_per_block),
+                                                      int(persistent_waves_per_cu)), "set_launch")
+
+    def get_launch(self):
+        a, b = C.c_int32(), C.c_int32()
+        self.ctx._check(self.lib.pprt_plan_get_launch(self.h, C.byref(a), C.byref(b)), "get_launch")
+        return a.value, b.value
+
+    def autotune(self, tau, q, S, eps, B, wphi, force=False, Itop=None, Ibot=None) -> dict:
+        """pprt_plan_autotune on these inputs; returns the report."""
+        import torch
+        fin = self.fs_in(tau, q, None, None, None, Itop, Ibot)
+        at = self.two_level(eps, B, wphi)
+        self._want(S, (self.rows,), torch.float64, "S")
+        rep = TuneReport()
+        self.ctx._check(self.lib.pprt_plan_autotune(self.h, C.byref(fin), C.byref(at), _ptr(S),
+                                                    _ptr(self.workspace()), int(bool(force)),
+                                                    C.byref(rep)), "autotune")
+        return {k: getattr(rep, k) for k, _ in TuneReport._fields_}
 
 
 class DeviceAtom:

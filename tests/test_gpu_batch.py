@@ -1,0 +1,110 @@
+"""Batched launch machinery of the two-level path: the persistent grid, the
+autotuner and hipGraph replay of ALI chunks must reproduce the eager,
+one-wave-per-item launch bit for bit (they change scheduling only)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_0903_1949_amd import pprt
+from paper_0903_1949_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _batch(prec, nb=6, nf=300, na=8, seed=12):
+    batch = W.two_level_batch(nb=nb, nd_lo=20, nd_hi=90, na=na, nf=nf, seed=seed)
+    return batch, pprt.upload_two_level(batch, prec)
+
+
+def _moments_and_update(plan, db, S):
+    mx = torch.zeros(plan.nb, dtype=torch.float64, device="cuda:0")
+    plan.two_level_moments(db.tau, db.q, S, db.eps, db.B, db.wphi)
+    plan.two_level_update(S, db.eps, db.B, db.wphi, mx)
+    torch.cuda.synchronize()
+    return S.clone(), mx.clone()
+
+
+@pytest.mark.parametrize("prec", [pprt.FP32, pprt.FP64])
+def test_launch_shapes_are_bitwise_identical(gpu_ctx, prec):
+    batch, db = _batch(prec)
+    plan = pprt.Plan(gpu_ctx, batch.nd, batch.na, batch.nf, precision=prec)
+    S0 = db.S.clone()
+    ref_S, ref_mx = _moments_and_update(plan, db, S0.clone())
+    for wpb in (1, 2, 4, 8):
+        for pw in (0, 1, 8, 32):
+            plan.set_launch(wpb, pw)
+            assert plan.get_launch() == (wpb, pw)
+            S, mx = _moments_and_update(plan, db, S0.clone())
+            assert torch.equal(S, ref_S), (wpb, pw)
+            assert torch.equal(mx, ref_mx), (wpb, pw)
+
+
+def test_set_launch_rejects_bad_shapes(gpu_ctx):
+    batch, db = _batch(pprt.FP32, nb=2, nf=64)
+    plan = pprt.Plan(gpu_ctx, batch.nd, batch.na, batch.nf, precision=pprt.FP32)
+    with pytest.raises(pprt.PprtError):
+        plan.set_launch(3, 0)
+    with pytest.raises(pprt.PprtError):
+        plan.set_launch(4, 33)
+
+
+def test_autotune_picks_a_shape_and_caches_it(gpu_ctx):
+    batch, db = _batch(pprt.FP32, nb=16, nf=512, seed=4)
+    plan = pprt.Plan(gpu_ctx, batch.nd, batch.na, batch.nf, precision=pprt.FP32)
+    S0 = db.S.clone()
+    ref_S, _ = _moments_and_update(plan, db, S0.clone())
+    rep = plan.autotune(db.tau, db.q, S0, db.eps, db.B, db.wphi, force=True)
+    print("  tune", rep, flush=True)
+    assert rep["candidates"] == 16 and rep["from_cache"] == 0
+    assert rep["best_ms"] <= rep["default_ms"]
+    assert plan.get_launch() == (rep["waves_per_block"], rep["persistent_waves_per_cu"])
+    assert torch.equal(S0, db.S)                      # autotuning reads S only
+    S, _ = _moments_and_update(plan, db, S0.clone())
+    assert torch.equal(S, ref_S)
+    plan2 = pprt.Plan(gpu_ctx, batch.nd, batch.na, batch.nf, precision=pprt.FP32)
+    rep2 = plan2.autotune(db.tau, db.q, S0, db.eps, db.B, db.wphi)
+    assert rep2["from_cache"] == 1
+    assert plan2.get_launch() == plan.get_launch()
+
+
+@pytest.mark.parametrize("prec,pw", [(pprt.FP64, 0), (pprt.FP32, 0), (pprt.FP32, 8)])
+def test_graph_replays_equal_eager(gpu_ctx, prec, pw):
+    """ALI with the chunk of G iterations captured once and replayed: after
+    1, 2, 3 and 4 replays (host synchronisation and flag reads between them)
+    the state equals the eager launches' exactly; a remainder chunk shorter
+    than G runs eagerly; the iteration cap is honoured per atmosphere."""
+    batch, db = _batch(prec, nb=5, nf=200, seed=31)
+    plan = pprt.Plan(gpu_ctx, batch.nd, batch.na, batch.nf, precision=prec)
+    plan.set_launch(2, pw)
+    G = 7
+    for n_rep, extra in ((1, 0), (2, 0), (3, 3), (4, 0)):
+        max_iter = n_rep * G + extra
+        res = {}
+        for graph in (False, True):
+            db.S.copy_(db.B)
+            iters = torch.zeros(plan.nb, dtype=torch.int32, device="cuda:0")
+            rep = plan.two_level_ali(db.tau, db.q, db.S, db.eps, db.B, db.wphi, tol=1e-300,
+                                     max_iter=max_iter, iters_per_sync=G, use_graph=graph,
+                                     iters=iters, raise_not_converged=False)
+            torch.cuda.synchronize()
+            res[graph] = (db.S.clone(), iters.clone(), rep)
+        assert torch.equal(res[True][0], res[False][0]), (n_rep, extra)
+        assert torch.equal(res[True][1], res[False][1])
+        assert int(res[True][1].max()) == max_iter
+        assert res[True][2]["status"] == res[False][2]["status"] == "E_NOT_CONVERGED"
+
+
+def test_graph_mode_converges_like_eager(gpu_ctx):
+    batch, db = _batch(pprt.FP64, nb=3, nf=64, seed=5)
+    plan = pprt.Plan(gpu_ctx, batch.nd, batch.na, batch.nf, precision=pprt.FP64)
+    out = {}
+    for graph in (False, True):
+        db.S.copy_(db.B)
+        iters = torch.zeros(plan.nb, dtype=torch.int32, device="cuda:0")
+        rep = plan.two_level_ali(db.tau, db.q, db.S, db.eps, db.B, db.wphi, tol=1e-8,
+                                 max_iter=20000, iters_per_sync=50, use_graph=graph, iters=iters)
+        out[graph] = (db.S.clone(), iters.clone(), rep)
+    print("  eager", out[False][2], "graph", out[True][2], flush=True)
+    assert out[True][2]["n_converged"] == plan.nb
+    assert torch.equal(out[True][0], out[False][0])
+    assert torch.equal(out[True][1], out[False][1])
