@@ -83,6 +83,9 @@ typedef enum pprt_lower_bc { PPRT_BC_DIFFUSION = 0, PPRT_BC_GIVEN = 1 } pprt_low
 #define PPRT_OUT_IMINUS  0x20u  /* I-                                   [row][nf][na] */
 #define PPRT_OUT_H       0x40u  /* H = 1/2 sum_i w_i mu_i (I+ - I-)     [row][nf]     */
 #define PPRT_OUT_IEMERG  0x80u  /* emergent I+ at node 0                [b][nf][na]   */
+#define PPRT_OUT_LSTAR_SUB 0x100u /* Lambda_{d,d-1} = dJ(d)/dS(d-1), 0 at d = 0  [row][nf] */
+#define PPRT_OUT_LSTAR_SUP 0x200u /* Lambda_{d,d+1} = dJ(d)/dS(d+1), 0 at the last node [row][nf]
+                                     (the tri-diagonal band; omega = 0 plans only) */
 
 typedef struct pprt_ctx pprt_ctx;
 typedef struct pprt_plan pprt_plan;
@@ -161,6 +164,7 @@ typedef struct pprt_fs_out {
   void* Iplus; void* Iminus;                        /* real [rows][nf][na]  */
   void* H;                                          /* real [rows][nf]      */
   void* Iemerg;                                     /* real [nb][nf][na]    */
+  void* lstar_sub; void* lstar_sup;                 /* real [rows][nf]      */
 } pprt_fs_out;
 
 /* Formal solution without in-layer scattering (the omega = 0 layer
@@ -358,6 +362,30 @@ pprt_status pprt_plan_nlte_workspace_bytes(const pprt_plan* plan, int32_t nlev, 
  * diffusion lower boundary takes B from atom->Bnu. */
 pprt_status pprt_nlte_step(pprt_plan* plan, const pprt_fs_in* in, const pprt_atom* atom,
                            double* pops, double* max_rel, void* workspace);
+
+/* ---- Approximate operator of the two-level ALI ---------------------------
+ * PPRT_LSTAR_DIAG (default): the local operator, the exact diagonal of the
+ * discrete Lambda.  PPRT_LSTAR_TRI: the non-local operator, its exact
+ * tri-diagonal band (the 1D counterpart of the nearest-neighbour operator
+ * whose convergence Sect. 3.2.1 compares with the local one):
+ *   Lambda_{d,d+1} = 1/2 sum_i w_i [gamma_{d+1/2} + e_{d+1/2} alpha_{d+3/2}]  (up-going rays)
+ *   Lambda_{d,d-1} = 1/2 sum_i w_i [gamma_{d-1/2} + e_{d-1/2} alpha_{d-3/2}]  (down-going rays)
+ * (no alpha term next to a boundary node), profile-averaged like the
+ * diagonal; the update then solves, per atmosphere in float64,
+ *   [I - (1-eps) Lbar*] dS = (1-eps)(Jbar - S) + eps (B - S)
+ * (tri-diagonal, diagonally dominant; Thomas elimination).
+ * ng = 1 adds Ng acceleration (Ng 1974 in Auer's 1987 form, weights
+ * 1/S^2): whenever four iterates have gathered since the first update or
+ * the last extrapolation, S is replaced by the extrapolated iterate.
+ * Applies to pprt_two_level_ali_step / _update / _ali (not to the continuum
+ * step).  Changes the workspace size: call before
+ * pprt_plan_workspace_bytes.  pprt_two_level_ali resets Ng's history at
+ * its start; callers stepping with pprt_two_level_ali_step call
+ * pprt_two_level_reset before the first step. */
+#define PPRT_LSTAR_DIAG 0
+#define PPRT_LSTAR_TRI 1
+pprt_status pprt_plan_set_operator(pprt_plan* plan, int32_t lstar, int32_t ng);
+pprt_status pprt_two_level_reset(pprt_plan* plan, void* workspace);
 
 /* ---- Launch shape of the batched two-level sweep, and its autotuner ------
  * The batched sweep of pprt_two_level_moments / _ali_step / _ali runs one

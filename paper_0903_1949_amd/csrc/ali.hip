@@ -117,6 +117,159 @@ __global__ __launch_bounds__(256) void k_profile_reduce(const double* __restrict
   }
 }
 
+// Non-local update (tri-diagonal approximate operator) and/or Ng
+// acceleration, one block per atmosphere, float64.  With the profile-averaged
+// band from the sweep (part[row][tile][hemisphere] = (J-S, 1-Lambda*, band, -);
+// the up-going hemisphere's band is Lambda*_{d,d+1}, the down-going one's
+// Lambda*_{d,d-1}) each atmosphere solves
+//     [I - (1-eps) Lbar*] dS = (1-eps)(Jbar - S) + eps (B - S)
+// by Thomas elimination (the matrix is diagonally dominant: the rows of
+// Lambda sum to at most one, so no pivoting is needed).  Ng's extrapolation
+// (in Auer's form, weights 1/x0^2) is applied whenever four iterates have
+// gathered since the first update or the last extrapolation; the group
+// history lives in hist[3][rows] and ng_count[nb].
+__global__ __launch_bounds__(256) void k_ali_update_nl(AliUpdateArgs a, AliNlArgs n) {
+  __shared__ double red[5][256];
+  __shared__ double ab[3];
+  const int b = blockIdx.x;
+  if (a.active != nullptr && a.active[b] == 0) return;   // uniform over the block
+  const int64_t r0 = a.off[b];
+  const int64_t r1 = a.off[b + 1];
+  const int64_t rows = n.rows;
+  const double eps = a.eps[b];
+  const int nqp = n.tri ? 4 : 2;
+  const int stride = a.nw * 2 * nqp;
+  double* cf = n.coef;
+  // ---- coefficients of the per-atmosphere system
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+    double jms = 0.0, olb = 0.0, sup = 0.0, sub = 0.0;
+    for (int g = 0; g < a.nw; ++g) {
+      double v[2][3];
+      for (int dir = 0; dir < 2; ++dir)
+        for (int q = 0; q < (n.tri ? 3 : 2); ++q) {
+          const int64_t x = r * stride + (g * 2 + dir) * nqp + q;
+          v[dir][q] = a.part_fp64 ? static_cast<const double*>(a.part)[x]
+                                  : (double)static_cast<const float*>(a.part)[x];
+        }
+      jms += v[0][0] + v[1][0];
+      olb += v[0][1] + v[1][1];
+      if (n.tri) {
+        sup += v[0][2];
+        sub += v[1][2];
+      }
+    }
+    const double S = a.S[r];
+    cf[r * 4 + 0] = -(1.0 - eps) * sub;
+    cf[r * 4 + 1] = eps + (1.0 - eps) * olb;
+    cf[r * 4 + 2] = -(1.0 - eps) * sup;
+    cf[r * 4 + 3] = (1.0 - eps) * jms + eps * (a.B[r] - S);
+  }
+  __syncthreads();
+  if (n.tri && threadIdx.x == 0) {
+    double cp = 0.0, dp = 0.0;
+    for (int64_t r = r0; r < r1; ++r) {
+      const double lo = cf[r * 4 + 0];
+      const double m = cf[r * 4 + 1] - lo * cp;
+      cp = cf[r * 4 + 2] / m;
+      dp = (cf[r * 4 + 3] - lo * dp) / m;
+      cf[r * 4 + 2] = cp;
+      cf[r * 4 + 3] = dp;
+    }
+    double xv = cf[(r1 - 1) * 4 + 3];
+    for (int64_t r = r1 - 2; r >= r0; --r) {
+      xv = cf[r * 4 + 3] - cf[r * 4 + 2] * xv;
+      cf[r * 4 + 3] = xv;
+    }
+  }
+  __syncthreads();
+  // ---- new iterate (and Ng's group)
+  const int cnt0 = n.ng ? n.ng_count[b] : 0;
+  const int cnt = (n.ng && cnt0 == 0) ? 1 : cnt0;   // the first update opens a group with S_old
+  const bool extrap = n.ng && cnt == 3;
+  double mx = 0.0;
+  bool bad = false;
+  double s5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+    const double So = a.S[r];
+    const double dS = n.tri ? cf[r * 4 + 3] : cf[r * 4 + 3] / cf[r * 4 + 1];
+    const double Sn = So + dS;
+    if (n.ng && cnt0 == 0) n.hist[r] = So;
+    if (extrap) {
+      const double x0 = Sn, x1 = n.hist[2 * rows + r], x2 = n.hist[rows + r], x3 = n.hist[r];
+      const double d0 = x0 - x1, d1 = x1 - x2, d2 = x2 - x3;
+      const double wt = 1.0 / (x0 * x0);
+      const double u = d0 - d1, v = d0 - d2;
+      s5[0] += wt * u * u;
+      s5[1] += wt * u * v;
+      s5[2] += wt * v * v;
+      s5[3] += wt * d0 * u;
+      s5[4] += wt * d0 * v;
+      cf[r * 4 + 0] = Sn;                 // keep x0 for the second pass
+      continue;
+    }
+    if (n.ng) n.hist[(int64_t)cnt * rows + r] = Sn;
+    double rel = fabs(dS) / fabs(Sn);
+    if (!isfinite(Sn) || !isfinite(rel)) {
+      bad = true;
+      rel = INFINITY;
+    }
+    a.S[r] = Sn;
+    mx = fmax(mx, rel);
+  }
+  if (extrap) {
+    for (int q = 0; q < 5; ++q) red[q][threadIdx.x] = s5[q];
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+      if ((int)threadIdx.x < st)
+        for (int q = 0; q < 5; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      const double A00 = red[0][0], A01 = red[1][0], A11 = red[2][0], b0 = red[3][0], b1 = red[4][0];
+      const double det = A00 * A11 - A01 * A01;
+      if (det == 0.0 || !isfinite(det)) {
+        ab[0] = 0.0;
+        ab[1] = 0.0;
+      } else {
+        ab[0] = (b0 * A11 - A01 * b1) / det;
+        ab[1] = (A00 * b1 - A01 * b0) / det;
+      }
+    }
+    __syncthreads();
+    const double ca = ab[0], cb = ab[1];
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+      const double So = a.S[r];
+      const double x0 = cf[r * 4 + 0], x1 = n.hist[2 * rows + r], x2 = n.hist[rows + r];
+      const double Sa = (1.0 - ca - cb) * x0 + ca * x1 + cb * x2;
+      n.hist[r] = Sa;
+      double rel = fabs(Sa - So) / fabs(Sa);
+      if (!isfinite(Sa) || !isfinite(rel)) {
+        bad = true;
+        rel = INFINITY;
+      }
+      a.S[r] = Sa;
+      mx = fmax(mx, rel);
+    }
+  }
+  if (bad && a.status != nullptr) atomicOr(a.status, (unsigned)PPRT_DEV_NONFINITE);
+  __syncthreads();
+  red[0][threadIdx.x] = mx;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[0][threadIdx.x] = fmax(red[0][threadIdx.x], red[0][threadIdx.x + st]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double m = red[0][0];
+    a.max_rel[b] = m;
+    int it = 0;
+    if (a.iters != nullptr) it = (a.iters[b] += 1);
+    if (a.active != nullptr && a.tol > 0.0 && m < a.tol) a.active[b] = 0;
+    if (a.active != nullptr && a.max_iter > 0 && it >= a.max_iter) a.active[b] = 0;
+    if (n.ng) n.ng_count[b] = extrap ? 1 : cnt + 1;
+  }
+}
+
 __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -127,6 +280,12 @@ __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
 hipError_t launch_ali_update(int nb, hipStream_t s, const AliUpdateArgs& a) {
   if (nb == 0) return hipSuccess;
   hipLaunchKernelGGL(k_ali_update, dim3(nb), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_ali_update_nl(int nb, hipStream_t s, const AliUpdateArgs& a, const AliNlArgs& n) {
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ali_update_nl, dim3(nb), dim3(256), 0, s, a, n);
   return hipGetLastError();
 }
 

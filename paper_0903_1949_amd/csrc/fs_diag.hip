@@ -170,8 +170,15 @@ __global__ __launch_bounds__(512) void k_fs_full(FsFullArgs<T> a, Angles<T> ang)
   T* ph = (o & PPRT_OUT_H) ? a.H : nullptr;               // 1/2 sum w mu D+
   T* Ip = (o & PPRT_OUT_IPLUS) ? a.Iplus : nullptr;
   T* Im = (o & PPRT_OUT_IMINUS) ? a.Iminus : nullptr;
+  T* Lsup = (o & PPRT_OUT_LSTAR_SUP) ? a.lsup : nullptr;   // dJ(d)/dS(d+1): up-going rays
+  T* Lsub = (o & PPRT_OUT_LSTAR_SUB) ? a.lsub : nullptr;   // dJ(d)/dS(d-1): down-going rays
 
   T D[NA], I[NA];
+  // alpha of the previous layer in sweep order (0 next to the boundary node,
+  // whose intensity does not depend on S): band = 1/2 sum w (gamma + e alpha_prev)
+  T aprev[NA];
+#pragma unroll
+  for (int i = 0; i < NA; ++i) aprev[i] = T(0);
   // ---- up-going sweep: node nd-1 (lower boundary) -> node 0
   int64_t r = row0 + nd - 1;
   T q1 = a.q[r * nf + k];
@@ -218,6 +225,7 @@ __global__ __launch_bounds__(512) void k_fs_full(FsFullArgs<T> a, Angles<T> ang)
     }
   };
   emit_up(r, ang.hwsum, T(0));
+  if (Lsup) Lsup[r * nf + k] = T(0);
   for (int d = nd - 2; d >= 0; --d) {
     r = row0 + d;
     const T q0 = a.q[r * nf + k];
@@ -226,7 +234,7 @@ __global__ __launch_bounds__(512) void k_fs_full(FsFullArgs<T> a, Angles<T> ang)
     const T dt = T(0.5) * (q0 + q1) * T(t1 - t0);
     const T inv = recip(dt);
     const T dS = S1 - S0;
-    T cs = T(0), as = T(0);
+    T cs = T(0), as = T(0), bs = T(0);
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
       T e, ps, al, ga;
@@ -235,8 +243,11 @@ __global__ __launch_bounds__(512) void k_fs_full(FsFullArgs<T> a, Angles<T> ang)
       I[i] = e * I[i] + al * S0 + ga * S1;
       cs += ang.hw[i] * ps;
       as += ang.hw[i] * al;
+      bs += ang.hw[i] * (ga + e * aprev[i]);
+      aprev[i] = al;
     }
     emit_up(r, cs, as);
+    if (Lsup) Lsup[r * nf + k] = bs;
     q1 = q0; S1 = S0; t1 = t0;
   }
   if (o & PPRT_OUT_IEMERG) {
@@ -273,6 +284,9 @@ __global__ __launch_bounds__(512) void k_fs_full(FsFullArgs<T> a, Angles<T> ang)
   T q0 = q1, S0 = S1;
   double t0 = t1;
   emit_down(row0, ang.hwsum, T(0));
+  if (Lsub) Lsub[row0 * nf + k] = T(0);
+#pragma unroll
+  for (int i = 0; i < NA; ++i) aprev[i] = T(0);
   for (int d = 1; d < nd; ++d) {
     r = row0 + d;
     q1 = a.q[r * nf + k];
@@ -281,7 +295,7 @@ __global__ __launch_bounds__(512) void k_fs_full(FsFullArgs<T> a, Angles<T> ang)
     const T dt = T(0.5) * (q0 + q1) * T(t1 - t0);
     const T inv = recip(dt);
     const T dS = S0 - S1;
-    T cs = T(0), as = T(0);
+    T cs = T(0), as = T(0), bs = T(0);
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
       T e, ps, al, ga;
@@ -290,8 +304,11 @@ __global__ __launch_bounds__(512) void k_fs_full(FsFullArgs<T> a, Angles<T> ang)
       I[i] = e * I[i] + al * S1 + ga * S0;
       cs += ang.hw[i] * ps;
       as += ang.hw[i] * al;
+      bs += ang.hw[i] * (ga + e * aprev[i]);
+      aprev[i] = al;
     }
     emit_down(r, cs, as);
+    if (Lsub) Lsub[r * nf + k] = bs;
     q0 = q1; S0 = S1; t0 = t1;
   }
 }
@@ -312,6 +329,16 @@ __global__ __launch_bounds__(512) void k_fs_full(FsFullArgs<T> a, Angles<T> ang)
 // ds_write2 instead of a 64-lane DPP tree.
 constexpr int CH = 8;
 
+// Moments reduced per node: (J-S, 1-Lambda*) or, with the tri-diagonal
+// operator, also the neighbour band; the slab holds CHN nodes of NQ
+// quantities (NQ * CHN <= 16 lane groups) and part[] has NQP per hemisphere.
+template <bool TRI>
+struct ProfileLayout {
+  static constexpr int NQ = TRI ? 3 : 2;
+  static constexpr int NQP = TRI ? 4 : 2;
+  static constexpr int CHN = TRI ? 5 : CH;
+};
+
 // One layer of the difference-form sweep for all angles, with the
 // Lambda*-complement sum ls += sum_i (w_i/2) psi_i.
 //
@@ -322,11 +349,11 @@ constexpr int CH = 8;
 //     D <- D + psi (dS - Delta D)        (= e D + psi dS).
 // Thick: e = 2^(-dtau c) (v_exp_f32), psi = m - e m, m = mu / dtau.
 // Because Delta_i = dtau / mu_i, the wave decides once per layer: all angles
-// thin when dtau * max_i(1/mu_i) < 1/2 in every lane, all thick when
-// dtau * min_i(1/mu_i) >= 1/2 in every lane, otherwise per angle (and per
-// lane when the lanes disagree).
+// thin when dtau < min_i(mu_i)/2 in every lane, all thick when
+// dtau >= max_i(mu_i)/2 in every lane, otherwise per angle (and per lane when
+// the lanes disagree).  The reciprocal of dtau is formed only for thick work.
 template <int NA>
-__device__ __forceinline__ void sweep_layer(const Angles<float>& ang, float dt, float inv, float dS,
+__device__ __forceinline__ void sweep_layer(const Angles<float>& ang, float dt, float dS,
                                             float (&D)[NA], float& ls) {
   constexpr float kThin = 0.5f;
   auto psi_poly = [](float x) {
@@ -337,8 +364,8 @@ __device__ __forceinline__ void sweep_layer(const Angles<float>& ang, float dt, 
     return fmaf(x, p, 1.0f);
   };
   const unsigned long long act = __ballot(1);
-  const bool all_thin = __ballot(dt * ang.rmu_max < kThin) == act;
-  const bool all_thick = !all_thin && __ballot(dt * ang.rmu_min >= kThin) == act;
+  const bool all_thin = __ballot(dt < ang.dt_all_thin) == act;
+  const bool all_thick = !all_thin && __ballot(dt >= ang.dt_all_thick) == act;
   if (all_thin) {
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
@@ -347,7 +374,10 @@ __device__ __forceinline__ void sweep_layer(const Angles<float>& ang, float dt, 
       D[i] = fmaf(ps, fmaf(-x, D[i], dS), D[i]);
       ls = fmaf(ang.hw[i], ps, ls);
     }
-  } else if (all_thick) {
+    return;
+  }
+  const float inv = recip(dt);
+  if (all_thick) {
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
       const float e = __builtin_amdgcn_exp2f(-(dt * ang.c[i]));
@@ -356,41 +386,42 @@ __device__ __forceinline__ void sweep_layer(const Angles<float>& ang, float dt, 
       D[i] = fmaf(e, D[i], ps * dS);
       ls = fmaf(ang.hw[i], ps, ls);
     }
-  } else {
+    return;
+  }
 #pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      const float x = dt * ang.rmu[i];
-      const bool thin = x < kThin;
-      const unsigned long long tb = __ballot(thin);
-      float ps, Dn;
-      if (tb == act) {
-        ps = psi_poly(x);
-        Dn = fmaf(ps, fmaf(-x, D[i], dS), D[i]);
-      } else if (tb == 0) {
-        const float e = __builtin_amdgcn_exp2f(-(dt * ang.c[i]));
-        const float m = ang.mu[i] * inv;
-        ps = fmaf(-e, m, m);
-        Dn = fmaf(e, D[i], ps * dS);
-      } else {
-        const float p1 = psi_poly(x);
-        const float D1 = fmaf(p1, fmaf(-x, D[i], dS), D[i]);
-        const float e = __builtin_amdgcn_exp2f(-(dt * ang.c[i]));
-        const float m = ang.mu[i] * inv;
-        const float p2 = fmaf(-e, m, m);
-        const float D2 = fmaf(e, D[i], p2 * dS);
-        ps = thin ? p1 : p2;
-        Dn = thin ? D1 : D2;
-      }
-      D[i] = Dn;
-      ls = fmaf(ang.hw[i], ps, ls);
+  for (int i = 0; i < NA; ++i) {
+    const float x = dt * ang.rmu[i];
+    const bool thin = x < kThin;
+    const unsigned long long tb = __ballot(thin);
+    float ps, Dn;
+    if (tb == act) {
+      ps = psi_poly(x);
+      Dn = fmaf(ps, fmaf(-x, D[i], dS), D[i]);
+    } else if (tb == 0) {
+      const float e = __builtin_amdgcn_exp2f(-(dt * ang.c[i]));
+      const float m = ang.mu[i] * inv;
+      ps = fmaf(-e, m, m);
+      Dn = fmaf(e, D[i], ps * dS);
+    } else {
+      const float p1 = psi_poly(x);
+      const float D1 = fmaf(p1, fmaf(-x, D[i], dS), D[i]);
+      const float e = __builtin_amdgcn_exp2f(-(dt * ang.c[i]));
+      const float m = ang.mu[i] * inv;
+      const float p2 = fmaf(-e, m, m);
+      const float D2 = fmaf(e, D[i], p2 * dS);
+      ps = thin ? p1 : p2;
+      Dn = thin ? D1 : D2;
     }
+    D[i] = Dn;
+    ls = fmaf(ang.hw[i], ps, ls);
   }
 }
 
 // FP64: closed forms (exp, expm1) for every layer.
 template <int NA>
-__device__ __forceinline__ void sweep_layer(const Angles<double>& ang, double dt, double inv,
-                                            double dS, double (&D)[NA], double& ls) {
+__device__ __forceinline__ void sweep_layer(const Angles<double>& ang, double dt, double dS,
+                                            double (&D)[NA], double& ls) {
+  const double inv = recip(dt);
 #pragma unroll
   for (int i = 0; i < NA; ++i) {
     double e, ps, al, ga;
@@ -400,7 +431,7 @@ __device__ __forceinline__ void sweep_layer(const Angles<double>& ang, double dt
   }
 }
 
-template <typename T, int NA, bool UP>
+template <typename T, int NA, bool UP, bool TRI>
 __device__ __forceinline__ void profile_sweep(const FsProfileArgs<T>& a, const Angles<T>& ang,
                                               const Item it, T* slab) {
   const int b = it.b;
@@ -439,7 +470,10 @@ __device__ __forceinline__ void profile_sweep(const FsProfileArgs<T>& a, const A
       D[i] = (a.Itop ? a.Itop[((int64_t)b * nf + kk) * NA + i] : T(0)) - T(Sn);
   }
 
-  // slab reduction: lane -> (sigma = 2*slot + quantity, part p of 4)
+  // slab reduction: lane -> (sigma = NQ*slot + quantity, part p of 4)
+  constexpr int NQ = ProfileLayout<TRI>::NQ;
+  constexpr int NQP = ProfileLayout<TRI>::NQP;
+  constexpr int CHN = ProfileLayout<TRI>::CHN;
   const int sig = lane >> 2;
   const int prt = lane & 3;
   T* const out = a.part;
@@ -450,27 +484,29 @@ __device__ __forceinline__ void profile_sweep(const FsProfileArgs<T>& a, const A
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const T* src = slab + sig * 64 + prt * 16;
+    const int sg = sig < NQ * CHN ? sig : 0;     // groups past the slab read a valid one
+    const T* src = slab + sg * 64 + prt * 16;
     T acc = T(0);
 #pragma unroll
     for (int t = 0; t < 16; ++t) acc += src[t];
     acc += dpp_quad_swap1(acc);
     acc += dpp_quad_swap2(acc);
-    const int slot = sig >> 1;
-    if (prt == 0 && slot < count) {
+    const int slot = sig / NQ;
+    if (prt == 0 && sig < NQ * CHN && slot < count) {
       const int j = j0 + slot;
       const int node = UP ? nd - 1 - j : j;
-      out[(((row0 + node) * nw + it.g) * 2 + (UP ? 0 : 1)) * 2 + (sig & 1)] = acc;
+      out[(((row0 + node) * nw + it.g) * 2 + (UP ? 0 : 1)) * NQP + (sig % NQ)] = acc;
     }
     // the next chunk overwrites the slab: keep these reads before those writes
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   };
-  auto park = [&](int j, T jsum, T lsum) {
-    const int slot = j % CH;
-    slab[(2 * slot + 0) * 64 + lane] = wp * jsum;
-    slab[(2 * slot + 1) * 64 + lane] = wp * lsum;
+  auto park = [&](int j, T jsum, T lsum, T band) {
+    const int slot = j % CHN;
+    slab[(NQ * slot + 0) * 64 + lane] = wp * jsum;
+    slab[(NQ * slot + 1) * 64 + lane] = wp * lsum;
+    if (TRI) slab[(NQ * slot + 2) * 64 + lane] = wp * band;
   };
   auto node_sum = [&]() {
     T js = T(0);
@@ -479,16 +515,21 @@ __device__ __forceinline__ void profile_sweep(const FsProfileArgs<T>& a, const A
     return js;
   };
 
-  park(0, node_sum(), ang.hwsum);
+  park(0, node_sum(), ang.hwsum, T(0));
   int j0 = 0;
+  // TRI: alpha of the previous layer in sweep order, per angle (0 before the
+  // first layer: the boundary node's intensity does not depend on S)
+  T aprev[TRI ? NA : 1];
+#pragma unroll
+  for (int i = 0; i < (TRI ? NA : 1); ++i) aprev[i] = T(0);
   // prefetch the next node of the sweep
   int dn = UP ? nd - 2 : 1;
   T qf = qcol[(row0 + dn) * nf];
   double Sf = a.S[row0 + dn];
   double tf = a.tau[row0 + dn];
   for (int j = 1; j < nd; ++j) {
-    if (j % CH == 0) {
-      flush(j0, CH);
+    if (j % CHN == 0) {
+      flush(j0, CHN);
       j0 = j;
     }
     const T qd = qf;
@@ -502,30 +543,45 @@ __device__ __forceinline__ void profile_sweep(const FsProfileArgs<T>& a, const A
     }
     // layer between this node and its predecessor in sweep order
     const T dt = T(0.5) * (qd + qn) * T(UP ? (tn - td) : (td - tn));
-    const T inv = recip(dt);
     const T dS = T(Sn - Sd);
-    T ls = T(0);
-    sweep_layer(ang, dt, inv, dS, D, ls);
-    park(j, node_sum(), ls);
+    T ls = T(0), band = T(0);
+    if (TRI) {
+      // with the neighbour coupling: the layer's alpha, gamma and e per angle
+      // (accurate series for thin layers), band = 1/2 sum w (gamma + e alpha_prev)
+      const T inv = recip(dt);
+#pragma unroll
+      for (int i = 0; i < NA; ++i) {
+        T e, ps, al, ga;
+        layer_w<true>(dt, inv, ang.c[i], ang.rmu[i], ang.mu[i], e, ps, al, ga);
+        D[i] = e * D[i] + ps * dS;
+        ls += ang.hw[i] * ps;
+        band += ang.hw[i] * (ga + e * aprev[i]);
+        aprev[i] = al;
+      }
+    } else {
+      sweep_layer(ang, dt, dS, D, ls);
+    }
+    park(j, node_sum(), ls, band);
     qn = qd; Sn = Sd; tn = td;
   }
   flush(j0, nd - j0);
 }
 
-template <typename T, int NA>
+template <typename T, int NA, bool TRI>
 __global__ __launch_bounds__(512) void k_fs_profile(FsProfileArgs<T> a, Angles<T> ang) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int wave = (int)(threadIdx.x >> 6);
-  T* slab = reinterpret_cast<T*>(lds_raw) + (size_t)wave * (2 * CH * 64);
+  T* slab = reinterpret_cast<T*>(lds_raw) +
+            (size_t)wave * (ProfileLayout<TRI>::NQ * ProfileLayout<TRI>::CHN * 64);
   if (a.queue == nullptr) {
     const int item = (int)blockIdx.x * (int)(blockDim.x >> 6) + wave;
     if (item >= a.nitems) return;                       // whole wave
     const Item it = a.items[item];
     if (a.active != nullptr && a.active[it.b] == 0) return;   // whole wave
     if (it.dir == 0)
-      profile_sweep<T, NA, true>(a, ang, it, slab);
+      profile_sweep<T, NA, true, TRI>(a, ang, it, slab);
     else
-      profile_sweep<T, NA, false>(a, ang, it, slab);
+      profile_sweep<T, NA, false, TRI>(a, ang, it, slab);
     return;
   }
   // Persistent grid: every wave takes the next item (longest atmosphere
@@ -539,9 +595,9 @@ __global__ __launch_bounds__(512) void k_fs_profile(FsProfileArgs<T> a, Angles<T
     const Item it = a.items[item];
     if (a.active != nullptr && a.active[it.b] == 0) continue;
     if (it.dir == 0)
-      profile_sweep<T, NA, true>(a, ang, it, slab);
+      profile_sweep<T, NA, true, TRI>(a, ang, it, slab);
     else
-      profile_sweep<T, NA, false>(a, ang, it, slab);
+      profile_sweep<T, NA, false, TRI>(a, ang, it, slab);
   }
 }
 
@@ -553,13 +609,18 @@ hipError_t launch_full_t(int wpb, int nitems, hipStream_t s, const void* args, c
 }
 
 template <typename T, int NA>
-hipError_t launch_profile_t(int wpb, int nitems, int nblocks, hipStream_t s, const void* args,
-                            const void* ang) {
-  const size_t lds = (size_t)wpb * 2 * CH * 64 * sizeof(T);
+hipError_t launch_profile_t(int wpb, int nitems, int nblocks, bool tri, hipStream_t s,
+                            const void* args, const void* ang) {
   if (nblocks <= 0) nblocks = (nitems + wpb - 1) / wpb;
-  hipLaunchKernelGGL((k_fs_profile<T, NA>), dim3(nblocks), dim3(64 * wpb), lds, s,
-                     *static_cast<const FsProfileArgs<T>*>(args),
-                     *static_cast<const Angles<T>*>(ang));
+  const auto& A = *static_cast<const FsProfileArgs<T>*>(args);
+  const auto& G = *static_cast<const Angles<T>*>(ang);
+  if (tri) {
+    const size_t lds = (size_t)wpb * ProfileLayout<true>::NQ * ProfileLayout<true>::CHN * 64 * sizeof(T);
+    hipLaunchKernelGGL((k_fs_profile<T, NA, true>), dim3(nblocks), dim3(64 * wpb), lds, s, A, G);
+  } else {
+    const size_t lds = (size_t)wpb * ProfileLayout<false>::NQ * ProfileLayout<false>::CHN * 64 * sizeof(T);
+    hipLaunchKernelGGL((k_fs_profile<T, NA, false>), dim3(nblocks), dim3(64 * wpb), lds, s, A, G);
+  }
   return hipGetLastError();
 }
 
@@ -575,10 +636,10 @@ hipError_t dispatch_full(int na, int wpb, int nitems, hipStream_t s, const void*
   }
 }
 template <typename T>
-hipError_t dispatch_profile(int na, int wpb, int nitems, int nblocks, hipStream_t s, const void* a,
-                            const void* g) {
+hipError_t dispatch_profile(int na, int wpb, int nitems, int nblocks, bool tri, hipStream_t s,
+                            const void* a, const void* g) {
   switch (na) {
-#define CASE(N) case N: return launch_profile_t<T, N>(wpb, nitems, nblocks, s, a, g);
+#define CASE(N) case N: return launch_profile_t<T, N>(wpb, nitems, nblocks, tri, s, a, g);
     PPRT_NA_LIST(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;
@@ -603,12 +664,12 @@ hipError_t launch_fs_full(int precision, int na, int wpb, int nitems, hipStream_
                                 : dispatch_full<float>(na, wpb, nitems, s, args, angles);
 }
 
-hipError_t launch_fs_profile(int precision, int na, int wpb, int nitems, int nblocks, hipStream_t s,
-                             const void* args, const void* angles) {
+hipError_t launch_fs_profile(int precision, int na, int wpb, int nitems, int nblocks, bool tri,
+                             hipStream_t s, const void* args, const void* angles) {
   if (nitems == 0) return hipSuccess;
   return precision == PPRT_FP64
-             ? dispatch_profile<double>(na, wpb, nitems, nblocks, s, args, angles)
-             : dispatch_profile<float>(na, wpb, nitems, nblocks, s, args, angles);
+             ? dispatch_profile<double>(na, wpb, nitems, nblocks, tri, s, args, angles)
+             : dispatch_profile<float>(na, wpb, nitems, nblocks, tri, s, args, angles);
 }
 
 }  // namespace pprt

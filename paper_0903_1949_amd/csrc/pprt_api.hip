@@ -54,6 +54,9 @@ struct pprt_plan {
   int checked_nlev = 0, checked_ntr = 0;
   // workspace layout of the ALI calls
   size_t ws_part = 0, ws_maxrel = 0, ws_active = 0, ws_iters = 0, ws_bytes = 0;
+  // two-level operator: tri-diagonal Lambda* and/or Ng acceleration
+  int lstar_tri = 0, use_ng = 0;
+  size_t ws_coef = 0, ws_hist = 0, ws_ngc = 0;
 };
 
 namespace {
@@ -168,10 +171,39 @@ void fill_angles(Angles<T>& A, const std::vector<double>& mu, const std::vector<
   }
   A.rmu_max = (T)rmax;
   A.rmu_min = (T)rmin;
+  // thin/thick split of the FP32 sweep at Delta = dtau/mu = 1/2
+  A.dt_all_thin = (T)(0.5 / rmax);
+  A.dt_all_thick = (T)(0.5 / rmin);
 }
 
 const void* angles_of(const pprt_plan* p) {
   return p->precision == PPRT_FP64 ? (const void*)&p->ad : (const void*)&p->af;
+}
+
+// Workspace of the two-level calls: [part | max_rel | active | iters] and,
+// with the tri-diagonal operator or Ng, [coef | hist | ng_count].
+void layout_ali_workspace(pprt_plan* p) {
+  const size_t es = p->precision == PPRT_FP64 ? sizeof(double) : sizeof(float);
+  const int nqp = p->lstar_tri ? 4 : 2;
+  size_t o = 0;
+  p->ws_part = o;
+  o = align256(o + (size_t)p->rows * p->nw * 2 * nqp * es);
+  p->ws_maxrel = o;
+  o = align256(o + (size_t)p->nb * sizeof(double));
+  p->ws_active = o;
+  o = align256(o + (size_t)p->nb * sizeof(int32_t));
+  p->ws_iters = o;
+  o = align256(o + (size_t)p->nb * sizeof(int32_t));
+  p->ws_coef = p->ws_hist = p->ws_ngc = 0;
+  if (p->lstar_tri || p->use_ng) {
+    p->ws_coef = o;
+    o = align256(o + (size_t)p->rows * 4 * sizeof(double));
+    p->ws_hist = o;
+    o = align256(o + (p->use_ng ? (size_t)p->rows * 3 * sizeof(double) : 0));
+    p->ws_ngc = o;
+    o = align256(o + (p->use_ng ? (size_t)p->nb * sizeof(int32_t) : 0));
+  }
+  p->ws_bytes = o;
 }
 
 // Checkpoint rows of interval K: atmosphere b keeps nodes 0, K, 2K, .. <= nd_b - 1.
@@ -311,7 +343,7 @@ pprt_status pprt_shape_check(const pprt_shape* sh, char* msg, size_t msg_len) {
     return shape_fail(msg, msg_len, PPRT_E_INVALID_ARG, "unknown precision %d", sh->precision);
   if (sh->lower_bc != PPRT_BC_DIFFUSION && sh->lower_bc != PPRT_BC_GIVEN)
     return shape_fail(msg, msg_len, PPRT_E_INVALID_ARG, "unknown lower boundary %d", sh->lower_bc);
-  if (sh->outputs & ~0xffu) return shape_fail(msg, msg_len, PPRT_E_INVALID_ARG, "unknown output bits 0x%x", sh->outputs);
+  if (sh->outputs & ~0x3ffu) return shape_fail(msg, msg_len, PPRT_E_INVALID_ARG, "unknown output bits 0x%x", sh->outputs);
   if (sh->waves_per_block != 0 && sh->waves_per_block != 1 && sh->waves_per_block != 2 &&
       sh->waves_per_block != 4 && sh->waves_per_block != 8)
     return shape_fail(msg, msg_len, PPRT_E_INVALID_ARG, "waves_per_block must be 0, 1, 2, 4 or 8");
@@ -426,18 +458,7 @@ pprt_status pprt_plan_create(pprt_ctx* c, const pprt_shape* sh, const double* mu
     return hip_check(c, e, "plan metadata");
   }
 
-  // workspace: [part | max_rel | active | iters]
-  size_t o = 0;
-  p->ws_part = o;
-  o = align256(o + (size_t)p->rows * p->nw * 4 *
-                      (p->precision == PPRT_FP64 ? sizeof(double) : sizeof(float)));
-  p->ws_maxrel = o;
-  o = align256(o + (size_t)p->nb * sizeof(double));
-  p->ws_active = o;
-  o = align256(o + (size_t)p->nb * sizeof(int32_t));
-  p->ws_iters = o;
-  o = align256(o + (size_t)p->nb * sizeof(int32_t));
-  p->ws_bytes = o;
+  layout_ali_workspace(p);
   *out = p;
   return PPRT_OK;
 }
@@ -484,7 +505,8 @@ pprt_status pprt_formal_solution(pprt_plan* p, const pprt_fs_in* in, pprt_fs_out
       {PPRT_OUT_J, out->J, "J"}, {PPRT_OUT_JMS, out->JmS, "JmS"},
       {PPRT_OUT_LSTAR, out->lstar, "lstar"}, {PPRT_OUT_LSTAR_C, out->lstar_c, "lstar_c"},
       {PPRT_OUT_IPLUS, out->Iplus, "Iplus"}, {PPRT_OUT_IMINUS, out->Iminus, "Iminus"},
-      {PPRT_OUT_H, out->H, "H"}, {PPRT_OUT_IEMERG, out->Iemerg, "Iemerg"}};
+      {PPRT_OUT_H, out->H, "H"}, {PPRT_OUT_IEMERG, out->Iemerg, "Iemerg"},
+      {PPRT_OUT_LSTAR_SUB, out->lstar_sub, "lstar_sub"}, {PPRT_OUT_LSTAR_SUP, out->lstar_sup, "lstar_sup"}};
   for (auto& r : req)
     if ((o & r.bit) && !r.ptr) return fail(c, PPRT_E_INVALID_ARG, "output %s requested but NULL", r.name);
 
@@ -498,6 +520,7 @@ pprt_status pprt_formal_solution(pprt_plan* p, const pprt_fs_in* in, pprt_fs_out
     a.J = (double*)out->J; a.JmS = (double*)out->JmS; a.lstar = (double*)out->lstar;
     a.lstar_c = (double*)out->lstar_c; a.Iplus = (double*)out->Iplus; a.Iminus = (double*)out->Iminus;
     a.H = (double*)out->H; a.Iemerg = (double*)out->Iemerg;
+    a.lsub = (double*)out->lstar_sub; a.lsup = (double*)out->lstar_sup;
     a.nf = p->nf; a.lower_bc = p->lower_bc; a.outputs = o;
     e = launch_fs_full(p->precision, p->na, p->wpb, p->n_full, c->stream, &a, angles_of(p));
   } else {
@@ -509,6 +532,7 @@ pprt_status pprt_formal_solution(pprt_plan* p, const pprt_fs_in* in, pprt_fs_out
     a.J = (float*)out->J; a.JmS = (float*)out->JmS; a.lstar = (float*)out->lstar;
     a.lstar_c = (float*)out->lstar_c; a.Iplus = (float*)out->Iplus; a.Iminus = (float*)out->Iminus;
     a.H = (float*)out->H; a.Iemerg = (float*)out->Iemerg;
+    a.lsub = (float*)out->lstar_sub; a.lsup = (float*)out->lstar_sup;
     a.nf = p->nf; a.lower_bc = p->lower_bc; a.outputs = o;
     e = launch_fs_full(p->precision, p->na, p->wpb, p->n_full, c->stream, &a, angles_of(p));
   }
@@ -536,6 +560,8 @@ pprt_status pprt_formal_solution_scattering(pprt_plan* p, const pprt_fs_in* in, 
   if (!ws) return fail(c, PPRT_E_WORKSPACE, "workspace of %zu bytes required",
                        dense_workspace_bytes(p->na, p->rows, p->nf));
   const uint32_t o = p->outputs;
+  if (o & (PPRT_OUT_LSTAR_SUB | PPRT_OUT_LSTAR_SUP))
+    return fail(c, PPRT_E_UNSUPPORTED, "the tri-diagonal band is available for omega = 0 only");
   if (o == 0) return fail(c, PPRT_E_INVALID_ARG, "plan requests no outputs");
   struct { uint32_t bit; void* ptr; const char* name; } req[] = {
       {PPRT_OUT_J, out->J, "J"}, {PPRT_OUT_JMS, out->JmS, "JmS"},
@@ -573,8 +599,8 @@ static pprt_status ali_moments_impl(pprt_plan* p, const pprt_fs_in* in, const pp
     a.wphi = (const double*)at->wphi; a.active = active; a.part = (double*)part;
     a.queue = p->prof_blocks ? p->d_queue : nullptr;
     a.nf = p->nf; a.nw = p->nw; a.nitems = p->n_prof; a.lower_bc = p->lower_bc;
-    e = launch_fs_profile(p->precision, p->na, p->wpb, p->n_prof, p->prof_blocks, c->stream, &a,
-                          angles_of(p));
+    e = launch_fs_profile(p->precision, p->na, p->wpb, p->n_prof, p->prof_blocks, p->lstar_tri != 0,
+                          c->stream, &a, angles_of(p));
   } else {
     FsProfileArgs<float> a{};
     a.items = p->d_items_prof; a.off = p->d_off; a.tau = in->tau; a.q = (const float*)in->q;
@@ -582,8 +608,8 @@ static pprt_status ali_moments_impl(pprt_plan* p, const pprt_fs_in* in, const pp
     a.wphi = (const float*)at->wphi; a.active = active; a.part = (float*)part;
     a.queue = p->prof_blocks ? p->d_queue : nullptr;
     a.nf = p->nf; a.nw = p->nw; a.nitems = p->n_prof; a.lower_bc = p->lower_bc;
-    e = launch_fs_profile(p->precision, p->na, p->wpb, p->n_prof, p->prof_blocks, c->stream, &a,
-                          angles_of(p));
+    e = launch_fs_profile(p->precision, p->na, p->wpb, p->n_prof, p->prof_blocks, p->lstar_tri != 0,
+                          c->stream, &a, angles_of(p));
   }
   return hip_check(c, e, "profile formal-solution launch");
 }
@@ -597,6 +623,17 @@ static pprt_status ali_update_impl(pprt_plan* p, const pprt_two_level* at, doubl
   u.S = S; u.max_rel = max_rel; u.active = active; u.iters = iters; u.status = c->d_status;
   u.tol = tol; u.max_iter = max_iter; u.nw = p->nw; u.nb = p->nb;
   u.part_fp64 = (p->precision == PPRT_FP64);
+  if (p->lstar_tri || p->use_ng) {
+    char* base = (char*)ws;
+    AliNlArgs n{};
+    n.tri = p->lstar_tri;
+    n.ng = p->use_ng;
+    n.rows = p->rows;
+    n.coef = (double*)(base + p->ws_coef);
+    n.hist = (double*)(base + p->ws_hist);
+    n.ng_count = (int32_t*)(base + p->ws_ngc);
+    return hip_check(c, launch_ali_update_nl(p->nb, c->stream, u, n), "ALI update launch");
+  }
   return hip_check(c, launch_ali_update(p->nb, c->stream, u), "ALI update launch");
 }
 
@@ -786,6 +823,10 @@ pprt_status pprt_two_level_ali(pprt_plan* p, const pprt_fs_in* in, const pprt_tw
   if (r != PPRT_OK) return r;
   r = hip_check(c, launch_fill_i32(its, 0, p->nb, c->stream), "fill");
   if (r != PPRT_OK) return r;
+  if (p->use_ng) {
+    r = hip_check(c, launch_fill_i32((int32_t*)(base + p->ws_ngc), 0, p->nb, c->stream), "fill");
+    if (r != PPRT_OK) return r;
+  }
   std::vector<int32_t> h_active(p->nb), h_iters(p->nb);
   std::vector<double> h_max(p->nb);
   int done_iters = 0;
@@ -1190,6 +1231,25 @@ pprt_status pprt_plan_get_launch(const pprt_plan* p, int32_t* wpb, int32_t* pers
   if (wpb) *wpb = p->wpb;
   if (persistent_waves_per_cu) *persistent_waves_per_cu = p->prof_wpc;
   return PPRT_OK;
+}
+
+pprt_status pprt_plan_set_operator(pprt_plan* p, int32_t lstar, int32_t ng) {
+  if (!p) return PPRT_E_INVALID_ARG;
+  if (lstar != PPRT_LSTAR_DIAG && lstar != PPRT_LSTAR_TRI)
+    return fail(p->ctx, PPRT_E_INVALID_ARG, "unknown approximate operator %d", lstar);
+  if (ng != 0 && ng != 1) return fail(p->ctx, PPRT_E_INVALID_ARG, "ng must be 0 or 1");
+  p->lstar_tri = lstar == PPRT_LSTAR_TRI;
+  p->use_ng = ng;
+  layout_ali_workspace(p);
+  return PPRT_OK;
+}
+
+pprt_status pprt_two_level_reset(pprt_plan* p, void* ws) {
+  if (!p) return PPRT_E_INVALID_ARG;
+  if (!ws) return fail(p->ctx, PPRT_E_WORKSPACE, "workspace required");
+  if (!p->use_ng) return PPRT_OK;
+  return hip_check(p->ctx, launch_fill_i32((int32_t*)((char*)ws + p->ws_ngc), 0, p->nb, p->ctx->stream),
+                   "Ng reset");
 }
 
 }  // extern "C"

@@ -25,6 +25,8 @@ struct Angles {
   T hwsum;         // sum_i w_i / 2 (one hemisphere's weight)
   T rmu_max;       // max_i 1/mu_i (the angle with the largest Delta)
   T rmu_min;       // min_i 1/mu_i
+  T dt_all_thin;   // FP32 sweep: every angle is optically thin when dtau < this
+  T dt_all_thick;  // FP32 sweep: every angle is optically thick when dtau >= this
 };
 
 // One work item: atmosphere b, frequency group g (blockDim.x frequencies),
@@ -48,6 +50,7 @@ struct FsFullArgs {
   const T* Bbot_prev;
   const T* Ibot;
   T* J; T* JmS; T* lstar; T* lstar_c; T* Iplus; T* Iminus; T* H; T* Iemerg;
+  T* lsub; T* lsup;         // tri-diagonal band of Lambda
   int32_t nf;
   int32_t lower_bc;
   uint32_t outputs;
@@ -66,7 +69,7 @@ struct FsProfileArgs {
   const T* wphi;            // [nf]
   const int32_t* active;    // [nb] or nullptr
   int32_t* queue;           // persistent launch: work counter (zeroed before launch); else nullptr
-  T* part;                  // [rows][nw][2 dir][2] per-wave profile moments
+  T* part;                  // [rows][nw][2 dir][2 or 4] per-wave profile moments
   int32_t nf;
   int32_t nw;               // waves across the frequency range, ceil(nf/64)
   int32_t nitems;           // one item per wave: (b, 64-frequency tile, dir)
@@ -117,6 +120,17 @@ int adj_lanes_per_freq(int na);
 bool adj_interval_supported(int K);
 hipError_t launch_emergent(int precision, bool vjp, int na, int K, int nitems, int wpb,
                            hipStream_t s, const void* args, const void* angles);
+
+// Non-local (tri-diagonal) operator and Ng acceleration in the update.
+struct AliNlArgs {
+  int32_t tri;              // 1: tri-diagonal band in part[] (4 entries per hemisphere)
+  int32_t ng;               // 1: Ng acceleration
+  int64_t rows;
+  double* coef;             // [rows][4] scratch
+  double* hist;             // [3][rows] Ng group history
+  int32_t* ng_count;        // [nb] iterates in the current group (0 = not started)
+};
+hipError_t launch_ali_update_nl(int nb, hipStream_t s, const AliUpdateArgs& a, const AliNlArgs& n);
 
 // Dense (in-layer scattering) formal solution, FP64 (fs_dense.hip).
 struct DenseLaunch {
@@ -179,8 +193,10 @@ hipError_t launch_fs_full(int precision, int na, int wpb, int nitems, hipStream_
                           const void* args, const void* angles);
 // nblocks = 0: one wave per item; otherwise a persistent grid of nblocks
 // blocks whose waves take items from args.queue.
-hipError_t launch_fs_profile(int precision, int na, int wpb, int nitems, int nblocks, hipStream_t s,
-                             const void* args, const void* angles);
+// tri: also reduce the tri-diagonal band (part[] then has 4 entries per
+// (row, tile, hemisphere): J-S, 1-Lambda*, band, unused).
+hipError_t launch_fs_profile(int precision, int na, int wpb, int nitems, int nblocks, bool tri,
+                             hipStream_t s, const void* args, const void* angles);
 hipError_t launch_ali_update(int nb, hipStream_t s, const AliUpdateArgs& a);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_sg_assemble(int precision, const double* S, const void* p, const void* c, void* Sg,

@@ -21,9 +21,12 @@ FP64, FP32 = 0, 1
 BC_DIFFUSION, BC_GIVEN = 0, 1
 OUT_J, OUT_JMS, OUT_LSTAR, OUT_LSTAR_C = 0x01, 0x02, 0x04, 0x08
 OUT_IPLUS, OUT_IMINUS, OUT_H, OUT_IEMERG = 0x10, 0x20, 0x40, 0x80
+OUT_LSTAR_SUB, OUT_LSTAR_SUP = 0x100, 0x200
 OUT_ALL = 0xFF
 OUTPUT_NAMES = {OUT_J: "J", OUT_JMS: "JmS", OUT_LSTAR: "lstar", OUT_LSTAR_C: "lstar_c",
-                OUT_IPLUS: "Iplus", OUT_IMINUS: "Iminus", OUT_H: "H", OUT_IEMERG: "Iemerg"}
+                OUT_IPLUS: "Iplus", OUT_IMINUS: "Iminus", OUT_H: "H", OUT_IEMERG: "Iemerg",
+                OUT_LSTAR_SUB: "lstar_sub", OUT_LSTAR_SUP: "lstar_sup"}
+LSTAR_DIAG, LSTAR_TRI = 0, 1
 
 STATUS = {0: "OK", 1: "E_INVALID_ARG", 2: "E_SHAPE", 3: "E_DEVICE", 4: "E_WORKSPACE",
           5: "E_NONFINITE", 6: "E_NOT_CONVERGED", 7: "E_SINGULAR", 8: "E_UNSUPPORTED",
@@ -51,7 +54,8 @@ class FsIn(C.Structure):
 class FsOut(C.Structure):
     _fields_ = [("J", C.c_void_p), ("JmS", C.c_void_p), ("lstar", C.c_void_p),
                 ("lstar_c", C.c_void_p), ("Iplus", C.c_void_p), ("Iminus", C.c_void_p),
-                ("H", C.c_void_p), ("Iemerg", C.c_void_p)]
+                ("H", C.c_void_p), ("Iemerg", C.c_void_p), ("lstar_sub", C.c_void_p),
+                ("lstar_sup", C.c_void_p)]
 
 
 class FsGrad(C.Structure):
@@ -134,6 +138,8 @@ def load_library(path: str = LIB_PATH):
                                    P, P, C.POINTER(AliReport), P]),
         "pprt_plan_adjoint_workspace_bytes": (I, [P, C.c_int32, C.POINTER(C.c_size_t)]),
         "pprt_plan_set_launch": (I, [P, C.c_int32, C.c_int32]),
+        "pprt_plan_set_operator": (I, [P, C.c_int32, C.c_int32]),
+        "pprt_two_level_reset": (I, [P, P]),
         "pprt_plan_get_launch": (I, [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
         "pprt_plan_autotune": (I, [P, C.POINTER(FsIn), C.POINTER(TwoLevel), P, P, C.c_int32,
                                    C.POINTER(TuneReport)]),
@@ -324,6 +330,7 @@ class Plan:
         fin = self.fs_in(tau, q, Sg, Bbot, Bbot_prev, Itop, Ibot)
         R, nf, na, nb = self.rows, self.nf, self.na, self.nb
         shapes = {"J": (R, nf), "JmS": (R, nf), "lstar": (R, nf), "lstar_c": (R, nf),
+                  "lstar_sub": (R, nf), "lstar_sup": (R, nf),
                   "Iplus": (R, nf, na), "Iminus": (R, nf, na), "H": (R, nf), "Iemerg": (nb, nf, na)}
         out = dict(out or {})
         ptrs = {}
@@ -389,6 +396,7 @@ class Plan:
         self._want(omega, (self.rows, self.nf), self.dtype, "omega")
         R, nf, na, nb = self.rows, self.nf, self.na, self.nb
         shapes = {"J": (R, nf), "JmS": (R, nf), "lstar": (R, nf), "lstar_c": (R, nf),
+                  "lstar_sub": (R, nf), "lstar_sup": (R, nf),
                   "Iplus": (R, nf, na), "Iminus": (R, nf, na), "H": (R, nf), "Iemerg": (nb, nf, na)}
         out = dict(out or {})
         ptrs = {}
@@ -541,6 +549,19 @@ class Plan:
         self.ctx._check(st, "two_level_ali")
         return report
 
+
+    # ------------------------------------------------ approximate operator
+    def set_operator(self, lstar: int = LSTAR_DIAG, ng: bool = False):
+        """pprt_plan_set_operator; resizes (and drops) the cached workspace."""
+        self.ctx._check(self.lib.pprt_plan_set_operator(self.h, int(lstar), int(bool(ng))),
+                        "set_operator")
+        nb = C.c_size_t()
+        self.ctx._check(self.lib.pprt_plan_workspace_bytes(self.h, C.byref(nb)), "workspace_bytes")
+        self.workspace_bytes = nb.value
+        self._ws = None
+
+    def two_level_reset(self):
+        self.ctx._check(self.lib.pprt_two_level_reset(self.h, _ptr(self.workspace())), "two_level_reset")
 
     # ------------------------------------------------ launch shape / autotuner
     def set_launch(self, waves_per_block: int, persistent_waves_per_cu: int = 0):

@@ -67,7 +67,8 @@ def test_gauss_rejects_bad_n():
     (dict(nd=[5], na=4, nf=0), "E_SHAPE"),
     (dict(nd=[5], na=4, nf=8, precision=7), "E_INVALID_ARG"),
     (dict(nd=[5], na=4, nf=8, lower_bc=3), "E_INVALID_ARG"),
-    (dict(nd=[5], na=4, nf=8, outputs=0x100), "E_INVALID_ARG"),
+    (dict(nd=[5], na=4, nf=8, outputs=0x400), "E_INVALID_ARG"),
+    (dict(nd=[5], na=4, nf=8, outputs=0x300), "OK"),
     (dict(nd=[5], na=4, nf=8, waves_per_block=3), "E_INVALID_ARG"),
 ])
 def test_shape_validation(kw, status):
