@@ -194,14 +194,19 @@ def main():
         try:
             tj = json.load(open(args.traffic_json))
             if tj.get("kernel_source_hash") == kernel_hash():
-                traffic = tj.get("bytes_per_launch")
+                traffic = tj.get("bytes_per_launch", {}).get("total")
         except Exception:
             traffic = None
+    peaks = ctx.measure_peaks()
     roofline = {"bound": "alu", "achieved": round(achieved_tflops, 3),
                 "peak": PEAK_FP32_VALU_NONPACKED, "unit": "TFLOP/s",
                 "frac": round(achieved_tflops / PEAK_FP32_VALU_NONPACKED, 4), "traffic": traffic,
                 "kernel": "k_fs_profile<float,8>", "kernel_ms": round(fs_ms, 5),
-                "flops_per_point": FLOPS_PER_POINT}
+                "flops_per_point": FLOPS_PER_POINT,
+                "peak_measured": round(peaks["fp32_tflops"], 2),
+                "frac_of_measured": round(achieved_tflops / peaks["fp32_tflops"], 4),
+                "hbm_gbs": round(traffic / (fs_ms * 1e-3) / 1e9, 1) if traffic else None,
+                "copy_gbs_measured": round(peaks["copy_gbs"], 1)}
 
     # ---------------- plain FP64 path: one FP64 launch pair per atmosphere
     fp64 = None

@@ -363,6 +363,21 @@ pprt_status pprt_plan_nlte_workspace_bytes(const pprt_plan* plan, int32_t nlev, 
 pprt_status pprt_nlte_step(pprt_plan* plan, const pprt_fs_in* in, const pprt_atom* atom,
                            double* pops, double* max_rel, void* workspace);
 
+/* ---- Measured device peaks (diagnostic) ----------------------------------
+ * Sustained rates of plain (non-packed) FP32 and FP64 vector FMA, of the
+ * hardware exp2, and of a device-memory copy (read + write bytes), timed
+ * with HIP events on the context stream (best of four launches).  `scratch`
+ * is caller-owned device memory: at least n_CU * 16 * 256 * 8 bytes; the
+ * copy is measured (half the buffer copied to the other half) when it holds
+ * at least 128 MiB, else copy_gbs = 0.  Synchronises the stream. */
+typedef struct pprt_peaks {
+  double fp32_tflops;
+  double fp64_tflops;
+  double exp2_trate;     /* 1e12 exp2 per second */
+  double copy_gbs;
+} pprt_peaks;
+pprt_status pprt_measure_peaks(pprt_ctx* ctx, void* scratch, size_t bytes, pprt_peaks* out);
+
 /* ---- Approximate operator of the two-level ALI ---------------------------
  * PPRT_LSTAR_DIAG (default): the local operator, the exact diagonal of the
  * discrete Lambda.  PPRT_LSTAR_TRI: the non-local operator, its exact

@@ -342,25 +342,25 @@ struct ProfileLayout {
 // One layer of the difference-form sweep for all angles, with the
 // Lambda*-complement sum ls += sum_i (w_i/2) psi_i.
 //
-// FP32.  Optically thin (Delta < 1/2): psi from a degree-5 polynomial fitted
-// to (1 - e^-Delta)/Delta on [0, 1/2] for least maximum relative error
-// (Remez exchange; fitted error 1.4e-9, below FP32 rounding), and the update
-// written without e, using 1 - e = Delta psi:
+// FP32.  Optically thin (Delta < 1/4): psi from a degree-4 polynomial fitted
+// to (1 - e^-Delta)/Delta on [0, 1/4] for least maximum relative error
+// (Remez exchange; fitted error 2.5e-9, below FP32 rounding; evaluated in
+// FP32 the error is 4.5e-8), and the update written without e, using
+// 1 - e = Delta psi:
 //     D <- D + psi (dS - Delta D)        (= e D + psi dS).
 // Thick: e = 2^(-dtau c) (v_exp_f32), psi = m - e m, m = mu / dtau.
 // Because Delta_i = dtau / mu_i, the wave decides once per layer: all angles
-// thin when dtau < min_i(mu_i)/2 in every lane, all thick when
-// dtau >= max_i(mu_i)/2 in every lane, otherwise per angle (and per lane when
+// thin when dtau < min_i(mu_i)/4 in every lane, all thick when
+// dtau >= max_i(mu_i)/4 in every lane, otherwise per angle (and per lane when
 // the lanes disagree).  The reciprocal of dtau is formed only for thick work.
 template <int NA>
 __device__ __forceinline__ void sweep_layer(const Angles<float>& ang, float dt, float dS,
                                             float (&D)[NA], float& ls) {
-  constexpr float kThin = 0.5f;
+  constexpr float kThin = 0.25f;
   auto psi_poly = [](float x) {
-    float p = fmaf(x, -1.1216348502784967e-3f, 8.187386207282543e-3f);
-    p = fmaf(x, p, -4.1629090905189514e-2f);
-    p = fmaf(x, p, 1.6666224598884583e-1f);
-    p = fmaf(x, p, -4.999998211860657e-1f);
+    float p = fmaf(x, 7.510221563279629e-3f, -4.1488952934741974e-2f);
+    p = fmaf(x, p, 1.6665081679821014e-1f);
+    p = fmaf(x, p, -4.999994933605194e-1f);
     return fmaf(x, p, 1.0f);
   };
   const unsigned long long act = __ballot(1);

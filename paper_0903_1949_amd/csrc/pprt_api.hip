@@ -171,9 +171,9 @@ void fill_angles(Angles<T>& A, const std::vector<double>& mu, const std::vector<
   }
   A.rmu_max = (T)rmax;
   A.rmu_min = (T)rmin;
-  // thin/thick split of the FP32 sweep at Delta = dtau/mu = 1/2
-  A.dt_all_thin = (T)(0.5 / rmax);
-  A.dt_all_thick = (T)(0.5 / rmin);
+  // thin/thick split of the FP32 sweep at Delta = dtau/mu = 1/4
+  A.dt_all_thin = (T)(0.25 / rmax);
+  A.dt_all_thick = (T)(0.25 / rmin);
 }
 
 const void* angles_of(const pprt_plan* p) {
@@ -592,6 +592,7 @@ static pprt_status ali_moments_impl(pprt_plan* p, const pprt_fs_in* in, const pp
     e = launch_fill_i32(p->d_queue, 0, 1, c->stream);
     if (e != hipSuccess) return hip_check(c, e, "work counter reset");
   }
+
   if (p->precision == PPRT_FP64) {
     FsProfileArgs<double> a{};
     a.items = p->d_items_prof; a.off = p->d_off; a.tau = in->tau; a.q = (const double*)in->q;
@@ -1250,6 +1251,19 @@ pprt_status pprt_two_level_reset(pprt_plan* p, void* ws) {
   if (!p->use_ng) return PPRT_OK;
   return hip_check(p->ctx, launch_fill_i32((int32_t*)((char*)ws + p->ws_ngc), 0, p->nb, p->ctx->stream),
                    "Ng reset");
+}
+
+pprt_status pprt_measure_peaks(pprt_ctx* c, void* scratch, size_t bytes, pprt_peaks* out) {
+  if (!c || !out) return PPRT_E_INVALID_ARG;
+  if (!scratch) return fail(c, PPRT_E_WORKSPACE, "scratch buffer required");
+  int ncu = 0;
+  pprt_status r = hip_check(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device),
+                            "device attribute");
+  if (r != PPRT_OK) return r;
+  if (bytes < (size_t)ncu * 16 * 256 * sizeof(double))
+    return fail(c, PPRT_E_WORKSPACE, "scratch must hold at least %zu bytes", (size_t)ncu * 16 * 256 * sizeof(double));
+  return hip_check(c, measure_peaks(ncu, scratch, bytes, c->stream, &out->fp32_tflops, &out->fp64_tflops,
+                                    &out->exp2_trate, &out->copy_gbs), "peak kernels");
 }
 
 }  // extern "C"

@@ -207,4 +207,8 @@ hipError_t launch_profile_reduce(int precision, const double* S, const void* JmS
 
 bool na_supported(int na);
 
+// Measured peaks (peaks.hip): FP32 / FP64 FMA TFLOP/s, exp2 Texp/s, copy GB/s.
+hipError_t measure_peaks(int n_cu, void* scratch, size_t bytes, hipStream_t s, double* fp32,
+                         double* fp64, double* exp_rate, double* copy_gbs);
+
 }  // namespace pprt

@@ -69,6 +69,11 @@ class TuneReport(C.Structure):
                 ("from_cache", C.c_int32)]
 
 
+class Peaks(C.Structure):
+    _fields_ = [("fp32_tflops", C.c_double), ("fp64_tflops", C.c_double),
+                ("exp2_trate", C.c_double), ("copy_gbs", C.c_double)]
+
+
 class TwoLevel(C.Structure):
     _fields_ = [("eps", C.c_void_p), ("B", C.c_void_p), ("wphi", C.c_void_p)]
 
@@ -138,6 +143,7 @@ def load_library(path: str = LIB_PATH):
                                    P, P, C.POINTER(AliReport), P]),
         "pprt_plan_adjoint_workspace_bytes": (I, [P, C.c_int32, C.POINTER(C.c_size_t)]),
         "pprt_plan_set_launch": (I, [P, C.c_int32, C.c_int32]),
+        "pprt_measure_peaks": (I, [P, P, C.c_size_t, C.POINTER(Peaks)]),
         "pprt_plan_set_operator": (I, [P, C.c_int32, C.c_int32]),
         "pprt_two_level_reset": (I, [P, P]),
         "pprt_plan_get_launch": (I, [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
@@ -218,6 +224,15 @@ class Context:
         s = C.c_uint32(0)
         self._check(self.lib.pprt_sync(self.h, C.byref(s)), "sync")
         return s.value
+
+    def measure_peaks(self, scratch_mib: int = 1024) -> dict:
+        """pprt_measure_peaks with a scratch buffer of scratch_mib MiB."""
+        import torch
+        buf = torch.empty(scratch_mib << 20, dtype=torch.uint8, device=f"cuda:{self.device}")
+        pk = Peaks()
+        self._check(self.lib.pprt_measure_peaks(self.h, _ptr(buf), buf.numel(), C.byref(pk)),
+                    "measure_peaks")
+        return {k: getattr(pk, k) for k, _ in Peaks._fields_}
 
     def close(self):
         if getattr(self, "h", None):
