@@ -27,6 +27,13 @@ scaled by the previous populations, which spans far fewer decades).  The net rad
 populations because chi_t^new p S_t^new = p eta_t^new.  W_k is the
 frequency-integration weight of a rate (w_k / nu_k in reduced units).
 
+Depth-dependent line profiles (when the atom carries line_nu0, line_s,
+line_a and dopp): for a frequency k in the window of line t and depth d,
+sigma_{d,k} = s_t H(a_t, x) / (sqrt(pi) dnu_D), dnu_D = nu0_t dopp_d,
+x = (nu_k - nu0_t) / dnu_D, with the Voigt function H(a, x) = Re w(x + i a)
+taken from the Faddeeva function of scipy (a library step); continua keep
+their depth-independent cross-sections.
+
 The formal solution that supplies J and Lambda* is the omega > 0 oracle
 (continuum scattering inside the layers), with q = kappa + sigma_c per unit
 reference optical depth, omega = sigma_c / q and S^g = (eta_t + kappa_c B)/kappa.
@@ -35,7 +42,30 @@ from __future__ import annotations
 
 import numpy as np
 
+from scipy.special import wofz
+
 from . import dense, formal
+
+
+def voigt_H(a, x):
+    """H(a, x) = Re w(x + i a) (Faddeeva function)."""
+    return np.real(wofz(np.asarray(x) + 1j * np.asarray(a)))
+
+
+def cross_sections(atom):
+    """sigma [rows, nf]: per frequency, or depth-dependent Voigt lines."""
+    rows = atom.tau.shape[0]
+    sig = np.broadcast_to(atom.sigma[None, :], (rows, atom.nf)).copy()
+    if getattr(atom, "line_a", None) is None:
+        return sig
+    for t in range(atom.nt):
+        if atom.line_nu0[t] <= 0.0:
+            continue
+        sl = slice(int(atom.k0[t]), int(atom.k1[t]))
+        dnu = atom.line_nu0[t] * atom.dopp[:, None]
+        x = (atom.nu[None, sl] - atom.line_nu0[t]) / dnu
+        sig[:, sl] = atom.line_s[t] * voigt_H(atom.line_a[t], x) / (np.sqrt(np.pi) * dnu)
+    return sig
 
 
 def opacities(atom, pops):
@@ -45,7 +75,7 @@ def opacities(atom, pops):
     nl_ = pops[:, atom.lo[t]]
     nu_ = pops[:, atom.up[t]]
     G = atom.Gst
-    sig = atom.sigma[None, :]
+    sig = cross_sections(atom)
     chi_t = (nl_ - nu_ * G) * sig
     eta_t = nu_ * atom.bfac[None, :] * G * sig
     kappa = chi_t + atom.kc[:, None]
@@ -60,7 +90,7 @@ def preconditioned_rates(atom, pops_old, J, lstar):
     p = o["chi_t"] / o["kappa"]
     dJ = J - lstar * o["eta_t"] / o["kappa"]
     Wk = atom.W[None, :]
-    sig = atom.sigma[None, :]
+    sig = cross_sections(atom)
     G = atom.Gst
     U = atom.bfac[None, :] * G * sig
     rows = pops_old.shape[0]
@@ -152,7 +182,7 @@ def net_rate_residual(atom, pops, J):
     radiative rates of the given J: max over rows and levels of
     |sum in - sum out| / (sum in + sum out)."""
     Wk = atom.W[None, :]
-    sig = atom.sigma[None, :]
+    sig = cross_sections(atom)
     G = atom.Gst
     U = atom.bfac[None, :] * G * sig
     worst = 0.0
@@ -162,8 +192,8 @@ def net_rate_residual(atom, pops, J):
         for t in range(atom.nt):
             sl = slice(int(atom.k0[t]), int(atom.k1[t]))
             l, u = int(atom.lo[t]), int(atom.up[t])
-            Rlu = np.sum(Wk[0, sl] * sig[0, sl] * J[r, sl])
-            Rul = np.sum(Wk[0, sl] * (U[r, sl] + G[r, sl] * sig[0, sl] * J[r, sl]))
+            Rlu = np.sum(Wk[0, sl] * sig[r, sl] * J[r, sl])
+            Rul = np.sum(Wk[0, sl] * (U[r, sl] + G[r, sl] * sig[r, sl] * J[r, sl]))
             up_flow = pops[r, l] * (Rlu + atom.Clu[r, t])
             down_flow = pops[r, u] * (Rul + atom.Cul[r, t])
             flow_out[l] += up_flow; flow_in[u] += up_flow

@@ -241,6 +241,11 @@ class MultiLevelAtom:
     Cul: np.ndarray           # [rows, nt] downward collision rates
     Clu: np.ndarray           # [rows, nt] upward collision rates (detailed balance)
     name: str = ""
+    # depth-dependent Voigt line profiles (None: sigma[k] holds every profile)
+    line_nu0: np.ndarray = None   # [nt] line centre (0 for continua)
+    line_s: np.ndarray = None     # [nt] strength: sigma = s H(a, x) / (sqrt(pi) dnu_D)
+    line_a: np.ndarray = None     # [nt] Voigt damping parameter
+    dopp: np.ndarray = None       # [rows] Doppler width / line centre at each depth
 
     @property
     def nb(self):
@@ -273,7 +278,7 @@ _SAHA = 2.0706e-16          # (h^2 / (2 pi m_e k))^(3/2) in cm^3 K^(3/2), hydrog
 def multilevel_atom(nbound=6, ncont=5, nd=128, na=8, nline_pts=100, ncont_pts=100,
                     tau_lo=1e-6, tau_hi=1e2, teff=5800.0, eps_c=1e-2, strength_lo=1e-2,
                     strength_hi=1e4, a_lo=1e-3, a_hi=1e-2, x_max=50.0, coll_scale=1e-3,
-                    line_pairs=None, nb=1, seed=2) -> MultiLevelAtom:
+                    line_pairs=None, nb=1, seed=2, depth_profiles=False) -> MultiLevelAtom:
     """Hydrogen-like atom with `nbound` bound levels (E_i = 1 - 1/i^2,
     g_i = 2 i^2) and a continuum level, all bound-bound pairs as lines (or
     `line_pairs`) and bound-free continua from levels 1..ncont, on a grey
@@ -288,7 +293,13 @@ def multilevel_atom(nbound=6, ncont=5, nd=128, na=8, nline_pts=100, ncont_pts=10
     [0.1, 10] (times chi_c at tau_ref = 1).  Collisions: C_ul = A_ul *
     coll_scale * tau_ref, C_lu by detailed balance.  n_tot = 1e14 tau_ref,
     n_e = 1e13 sqrt(tau_ref) (cm^-3, builder's choice).  nb identical
-    atmospheres are stacked when nb > 1 (a batch of the same model)."""
+    atmospheres are stacked when nb > 1 (a batch of the same model).
+
+    depth_profiles=True: line profiles depend on depth through the Doppler
+    width dnu_D = nu0 * 1e-4 * sqrt(T / T(tau_ref = 1)) and are not
+    renormalised on the grid; sigma_{d,k} = s_t H(a_t, x) / (sqrt(pi) dnu_D),
+    x = (nu_k - nu0) / dnu_D, is then evaluated by the consumer (line_nu0,
+    line_s, line_a, dopp; sigma[k] keeps the reference-depth values)."""
     from scipy.special import wofz
 
     rng = np.random.default_rng(seed)
@@ -326,6 +337,8 @@ def multilevel_atom(nbound=6, ncont=5, nd=128, na=8, nline_pts=100, ncont_pts=10
     kpos = 0
     i1 = int(np.argmin(np.abs(tau - 1.0)))
     strengths = np.exp(rng.uniform(math.log(strength_lo), math.log(strength_hi), size=nt))
+    line_nu0 = np.zeros(nt)
+    line_s = np.zeros(nt)
     damp = rng.uniform(a_lo, a_hi, size=nt)
     cstr = np.exp(rng.uniform(math.log(0.1), math.log(10.0), size=nt))
     for t in range(nt):
@@ -337,7 +350,8 @@ def multilevel_atom(nbound=6, ncont=5, nd=128, na=8, nline_pts=100, ncont_pts=10
             nu = nu0 + dop * s
             prof = np.real(wofz(s + 1j * damp[t])) / math.sqrt(math.pi) / dop      # Voigt, per unit nu
             w = _trapz_weights(nu)
-            prof = prof / np.sum(w * prof)          # normalised on the discrete grid
+            if not depth_profiles:
+                prof = prof / np.sum(w * prof)      # normalised on the discrete grid
             # line-centre LTE opacity ratio at tau_ref = 1 sets the strength
             centre = prof[nline_pts // 2]
             Gc = g[l] / g[u]
@@ -345,6 +359,7 @@ def multilevel_atom(nbound=6, ncont=5, nd=128, na=8, nline_pts=100, ncont_pts=10
             s_t = strengths[t] / (nstar[i1, l] * centre * stim)
             sigma = s_t * prof
             b = np.full(nline_pts, nu0 ** 3)
+            line_nu0[t], line_s[t] = nu0, s_t
         else:
             edge = E[u] - E[l]
             nu = np.geomspace(edge, 4.0 * edge, ncont_pts)
@@ -372,13 +387,22 @@ def multilevel_atom(nbound=6, ncont=5, nd=128, na=8, nline_pts=100, ncont_pts=10
         else:
             Gst[:, sl] = (nstar[:, l] / nstar[:, u])[:, None] * np.exp(-nu[None, sl] / kT[:, None])
     Bnu = nu[None, :] ** 3 / np.expm1(nu[None, :] / kT[:, None])
-    # collisions: A_ul = sum_k W_k b_k G_k sigma_k (depth-independent part of lines;
-    # for continua evaluated with the local G)
+    dopp = 1e-4 * np.sqrt(T / T[i1])
+    sig_rows = sigma[None, :]
+    if depth_profiles:
+        sig_rows = np.broadcast_to(sigma, (nd, nf)).copy()
+        for t in range(nt):
+            if kind[t] == 0:
+                sl = slice(k0[t], k1[t])
+                dnu = line_nu0[t] * dopp[:, None]
+                x = (nu[None, sl] - line_nu0[t]) / dnu
+                sig_rows[:, sl] = line_s[t] * np.real(wofz(x + 1j * damp[t])) / (math.sqrt(math.pi) * dnu)
+    # collisions: A_ul = sum_k W_k b_k G_k sigma_k (for continua evaluated with the local G)
     Cul = np.empty((nd, nt))
     Clu = np.empty((nd, nt))
     for t in range(nt):
         sl = slice(k0[t], k1[t])
-        A = np.sum(W[None, sl] * bfac[None, sl] * Gst[:, sl] * sigma[None, sl], axis=1)
+        A = np.sum(W[None, sl] * bfac[None, sl] * Gst[:, sl] * sig_rows[:, sl], axis=1)
         Cul[:, t] = A * coll_scale * tau
         Clu[:, t] = Cul[:, t] * nstar[:, up[t]] / nstar[:, lo[t]]
     kc = np.full(nd, eps_c)
@@ -389,7 +413,10 @@ def multilevel_atom(nbound=6, ncont=5, nd=128, na=8, nline_pts=100, ncont_pts=10
         kind=kind, k0=k0, k1=k1, nu=nu, wnu=wnu, owner=owner, sigma=sigma, bfac=bfac, W=W,
         Gst=rep(Gst), Bnu=rep(Bnu), kc=rep(kc), sc=rep(sc), nstar=rep(nstar), ntot=rep(ntot),
         Cul=rep(Cul), Clu=rep(Clu),
-        name=f"{nl}-level atom ({nt} transitions), nd={nd}, nf={nf}, na={na}")
+        name=f"{nl}-level atom ({nt} transitions), nd={nd}, nf={nf}, na={na}",
+        line_nu0=line_nu0 if depth_profiles else None, line_s=line_s if depth_profiles else None,
+        line_a=np.where(kind == 0, damp, 0.0) if depth_profiles else None,
+        dopp=rep(dopp) if depth_profiles else None)
 
 
 def _trapz_weights(x):

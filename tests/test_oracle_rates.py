@@ -132,3 +132,50 @@ def test_converged_populations_satisfy_statistical_equilibrium():
     fs, _ = rates.formal_solution_atom(a, r["pops"], mu, w)
     assert rates.net_rate_residual(a, r["pops"], fs["J"]) < 1e-8
     assert np.allclose(r["pops"].sum(axis=1), a.ntot, rtol=1e-13)
+
+
+# ------------------------------------------------ depth-dependent Voigt profiles
+def test_voigt_function_limits():
+    """H(a, x) = Re w(x + i a): Gaussian for a -> 0, Lorentzian wings
+    a / (sqrt(pi) x^2) (1 + 3/(2 x^2)) far out, and integral sqrt(pi)."""
+    x = np.linspace(-6, 6, 241)
+    assert np.max(np.abs(rates.voigt_H(1e-12, x) - np.exp(-x * x))) < 1e-11
+    a, X = 0.01, np.array([300.0, 1000.0, 3000.0])
+    asym = a / (math.sqrt(math.pi) * X ** 2) * (1 + 1.5 / X ** 2)
+    assert np.max(np.abs(rates.voigt_H(a, X) / asym - 1)) < 1e-6
+    xs = np.linspace(-2000, 2000, 4_000_001)
+    integral = np.trapezoid(rates.voigt_H(a, xs), xs) + 2 * a / (math.sqrt(math.pi) * 2000.0)
+    assert abs(integral / math.sqrt(math.pi) - 1) < 1e-6
+
+
+def test_depth_profiles_match_the_reference_depth_grid():
+    """At the reference depth (Doppler width 1e-4 of the line centre) the
+    oracle's depth-dependent cross-sections equal the generator's profile,
+    built independently on its own sinh-spaced grid."""
+    a = W.multilevel_atom(nbound=4, ncont=3, nd=14, na=4, nline_pts=12, ncont_pts=8, seed=7,
+                          depth_profiles=True)
+    sig = rates.cross_sections(a)
+    r1 = int(np.argmin(np.abs(a.dopp - 1e-4)))
+    assert abs(a.dopp[r1] / 1e-4 - 1) < 1e-12
+    # (x = (nu - nu0)/dnu_D recomputed from the stored grid carries the
+    # cancellation of nu - nu0 ~ 1e-4 nu0, so ~12 digits survive)
+    assert np.allclose(sig[r1], a.sigma, rtol=1e-8, atol=0)
+    # other depths differ (the profiles really depend on depth)
+    assert np.max(np.abs(sig[0] / a.sigma - 1)) > 1e-3
+
+
+def test_depth_profiles_collision_dominated_limit_is_lte():
+    a = W.multilevel_atom(nbound=4, ncont=3, nd=14, na=4, nline_pts=12, ncont_pts=8, seed=7,
+                          depth_profiles=True)
+    A = np.zeros((a.tau.shape[0], a.nt))
+    sig = rates.cross_sections(a)
+    for t in range(a.nt):
+        sl = slice(int(a.k0[t]), int(a.k1[t]))
+        A[:, t] = np.sum(a.W[None, sl] * a.bfac[None, sl] * a.Gst[:, sl] * sig[:, sl], axis=1)
+    a.Cul = A * 1e14
+    a.Clu = a.Cul * a.nstar[:, a.up] / a.nstar[:, a.lo]
+    mu, w = gauss_legendre01(a.na)
+    p = a.nstar * (1 + 0.3 * np.sin(np.arange(a.nl))[None, :])
+    for _ in range(2):
+        p, mx, _ = rates.nlte_iteration(a, p, mu, w)
+    assert np.max(np.abs(p / a.nstar - 1)) < 1e-8
