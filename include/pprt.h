@@ -317,6 +317,17 @@ typedef struct pprt_atom {
   const double* ntot;        /* [rows] total number density of the atom             */
   const double* Cul;         /* [rows][ntr] downward collision rates                */
   const double* Clu;         /* [rows][ntr] upward collision rates                  */
+  /* Optional depth-dependent Voigt lines (all four NULL: sigma[k] is used).
+   * For k in the window of a line t (line_nu0[t] > 0) and row d:
+   *   sigma = line_s[t] H(line_a[t], x) / (sqrt(pi) dnu_D),
+   *   dnu_D = line_nu0[t] dopp[d],  x = (nu[k] - line_nu0[t]) / dnu_D,
+   * H(a, x) = Re w(x + i a) evaluated on the device (see pprt_voigt).
+   * Windows with line_nu0[t] == 0 (continua) keep sigma[k]. */
+  const double* nu;          /* [nf] frequency of each point                        */
+  const double* line_nu0;    /* [ntr] line centre, 0 for continua                   */
+  const double* line_s;      /* [ntr] line strength                                 */
+  const double* line_a;      /* [ntr] Voigt damping parameter (>= 0)                */
+  const double* dopp;        /* [rows] Doppler width relative to the line centre    */
 } pprt_atom;
 
 /* Host validation of the atom's tables (copies the int32 tables to the
@@ -362,6 +373,17 @@ pprt_status pprt_plan_nlte_workspace_bytes(const pprt_plan* plan, int32_t nlev, 
  * diffusion lower boundary takes B from atom->Bnu. */
 pprt_status pprt_nlte_step(pprt_plan* plan, const pprt_fs_in* in, const pprt_atom* atom,
                            double* pops, double* max_rel, void* workspace);
+
+/* ---- Voigt function ----------------------------------------------------
+ * H(a, x) = Re w(x + i a), w the Faddeeva function, for a >= 0, by the
+ * rational expansion of Weideman (1994) with N = 40 terms,
+ *   w(z) ~ 2 p(Z) / (L - i z)^2 + (1/sqrt(pi)) / (L - i z),
+ *   Z = (L + i z) / (L - i z),  L = (N / sqrt 2)^(1/2),
+ * p(Z) = sum_{n<N} a_{n+1} Z^n, a_n the Fourier coefficients of
+ * exp(-t^2)(L^2 + t^2), t = L tan(theta/2) (computed once on the host).
+ * The same evaluation serves the multilevel opacity and rate kernels.
+ * a, x, H: device [n] float64.  Asynchronous on the context stream. */
+pprt_status pprt_voigt(pprt_ctx* ctx, int64_t n, const double* a, const double* x, double* H);
 
 /* ---- Measured device peaks (diagnostic) ----------------------------------
  * Sustained rates of plain (non-packed) FP32 and FP64 vector FMA, of the

@@ -16,10 +16,53 @@
 // sum n = n_tot, with P_lu = [dR_lu] + C_lu, P_ul = [R*_ul] + [dR_ul] + C_ul,
 // solved by LU with partial pivoting for n_i / n_i^old (columns scaled by the
 // previous populations: the unknowns span many decades).
+#include <cmath>
+
 #include "pprt_internal.h"
 
 namespace pprt {
 namespace {
+
+// H(a, x) = Re w(x + i a) by Weideman's expansion (coefficients in vc):
+// with i z = -a + i x,  L - i z = (L + a) - i x,  L + i z = (L - a) + i x.
+__device__ __forceinline__ double voigt_H(const VoigtCoef& vc, double aa, double x) {
+  const double L = vc.L;
+  const double dr = L + aa, di = -x;             // L - i z
+  const double nr = L - aa, ni = x;              // L + i z
+  const double den = dr * dr + di * di;
+  const double zr = (nr * dr + ni * di) / den;   // Z = (L + i z) / (L - i z)
+  const double zi = (ni * dr - nr * di) / den;
+  double pr = vc.a[kVoigtN], pi = 0.0;
+  for (int n = kVoigtN - 1; n >= 1; --n) {       // p = sum a_{n+1} Z^n by Horner
+    const double tr = pr * zr - pi * zi + vc.a[n];
+    pi = pr * zi + pi * zr;
+    pr = tr;
+  }
+  // 1 / (L - i z) = (dr - i di) / den
+  const double ur = dr / den, ui = -di / den;
+  const double u2r = ur * ur - ui * ui, u2i = 2.0 * ur * ui;
+  const double wr = 2.0 * (pr * u2r - pi * u2i) + 0.56418958354775628695 * ur;   // 1/sqrt(pi)
+  return wr;
+}
+
+// cross-section of the point (row r, frequency k) owned by transition t
+__device__ __forceinline__ double cross_section(const MlArgs& a, int64_t r, int k, int t) {
+  if (a.line_a != nullptr) {
+    const double nu0 = a.line_nu0[t];
+    if (nu0 > 0.0) {
+      const double dnu = nu0 * a.dopp[r];
+      const double x = (a.nu[k] - nu0) / dnu;
+      return a.line_s[t] * voigt_H(a.vc, a.line_a[t], x) * (0.56418958354775628695 / dnu);
+    }
+  }
+  return a.sigma[k];
+}
+
+__global__ void k_voigt(VoigtCoef vc, int64_t n, const double* __restrict__ av,
+                        const double* __restrict__ xv, double* __restrict__ H) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) H[i] = voigt_H(vc, av[i], xv[i]);
+}
 
 __global__ void k_ml_opacity(MlArgs a, double* __restrict__ q, double* __restrict__ om,
                              double* __restrict__ Sg) {
@@ -30,7 +73,7 @@ __global__ void k_ml_opacity(MlArgs a, double* __restrict__ q, double* __restric
   const int t = a.owner[k];
   const double nl = a.pops[r * a.nlev + a.lower[t]];
   const double nu = a.pops[r * a.nlev + a.upper[t]];
-  const double G = a.G[x], s = a.sigma[k];
+  const double G = a.G[x], s = cross_section(a, r, k, t);
   const double chi = (nl - nu * G) * s;
   const double eta = nu * a.bfac[k] * G * s;
   const double kap = chi + a.kc[r];
@@ -53,7 +96,7 @@ __global__ __launch_bounds__(64) void k_ml_rates(MlArgs a, const double* __restr
   double s1 = 0.0, s2 = 0.0, s3 = 0.0;
   for (int k = a.k0[t] + lane; k < a.k1[t]; k += 64) {
     const int64_t x = r * a.nf + k;
-    const double G = a.G[x], s = a.sigma[k], W = a.W[k];
+    const double G = a.G[x], s = cross_section(a, r, k, t), W = a.W[k];
     const double chi = (nl - nu * G) * s;
     const double U = a.bfac[k] * G * s;
     const double kap = chi + a.kc[r];
@@ -213,6 +256,36 @@ hipError_t launch_gather_bottom(const double* Bnu, const int64_t* off, int nb, i
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_gather_bottom, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, Bnu, off,
                      nb, nf, Bb, Bp);
+  return hipGetLastError();
+}
+
+const VoigtCoef& voigt_coefficients() {
+  // Fourier cosine coefficients of F(theta) = exp(-t^2)(L^2 + t^2),
+  // t = L tan(theta/2), on the M = 2N point grid theta_k = k pi / M
+  // (F is even and vanishes at theta = pi), as Weideman's method prescribes.
+  static const VoigtCoef vc = [] {
+    VoigtCoef c{};
+    const int N = kVoigtN, M = 2 * N;
+    const double pi = 3.14159265358979323846;
+    c.L = std::sqrt(N / std::sqrt(2.0));
+    for (int n = 0; n <= N; ++n) {
+      double acc = 0.5 * c.L * c.L;              // theta = 0 term, weight 1/2
+      for (int k = 1; k < M; ++k) {
+        const double th = k * pi / M;
+        const double t = c.L * std::tan(0.5 * th);
+        acc += std::exp(-t * t) * (c.L * c.L + t * t) * std::cos(n * th);
+      }
+      c.a[n] = acc / M;
+    }
+    return c;
+  }();
+  return vc;
+}
+
+hipError_t launch_voigt(int64_t n, const double* a, const double* x, double* H, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_voigt, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, voigt_coefficients(),
+                     n, a, x, H);
   return hipGetLastError();
 }
 

@@ -890,6 +890,11 @@ static MlArgs ml_args(const pprt_plan* p, const pprt_atom* at, const double* pop
   a.owner = at->owner; a.sigma = at->sigma; a.bfac = at->bfac; a.W = at->W; a.G = at->G;
   a.Bnu = at->Bnu; a.kc = at->kc; a.sc = at->sc; a.ntot = at->ntot; a.Cul = at->Cul; a.Clu = at->Clu;
   a.rows = p->rows; a.nf = p->nf; a.nlev = at->nlev; a.ntr = at->ntr;
+  if (at->line_a) {
+    a.nu = at->nu; a.line_nu0 = at->line_nu0; a.line_s = at->line_s; a.line_a = at->line_a;
+    a.dopp = at->dopp;
+    a.vc = voigt_coefficients();
+  }
   return a;
 }
 
@@ -904,6 +909,13 @@ pprt_status pprt_atom_check(pprt_plan* p, const pprt_atom* at) {
                        at->G, at->Bnu, at->kc, at->sc, at->ntot, at->Cul, at->Clu};
   for (const void* ptr : req)
     if (!ptr) return fail(c, PPRT_E_INVALID_ARG, "atom arrays must all be given");
+  {
+    const void* vo[] = {at->nu, at->line_nu0, at->line_s, at->line_a, at->dopp};
+    int given = 0;
+    for (const void* ptr : vo) given += ptr != nullptr;
+    if (at->line_a ? given != 5 : given != 0)
+      return fail(c, PPRT_E_INVALID_ARG, "Voigt lines need nu, line_nu0, line_s, line_a and dopp together");
+  }
   if (p->checked_atom[0] == at->lower && p->checked_atom[1] == at->upper &&
       p->checked_atom[2] == at->k0 && p->checked_atom[3] == at->k1 &&
       p->checked_atom[4] == at->owner && p->checked_nlev == at->nlev && p->checked_ntr == at->ntr)
@@ -1264,6 +1276,12 @@ pprt_status pprt_measure_peaks(pprt_ctx* c, void* scratch, size_t bytes, pprt_pe
     return fail(c, PPRT_E_WORKSPACE, "scratch must hold at least %zu bytes", (size_t)ncu * 16 * 256 * sizeof(double));
   return hip_check(c, measure_peaks(ncu, scratch, bytes, c->stream, &out->fp32_tflops, &out->fp64_tflops,
                                     &out->exp2_trate, &out->copy_gbs), "peak kernels");
+}
+
+pprt_status pprt_voigt(pprt_ctx* c, int64_t n, const double* a, const double* x, double* H) {
+  if (!c) return PPRT_E_INVALID_ARG;
+  if (n < 0 || (n > 0 && (!a || !x || !H))) return fail(c, PPRT_E_INVALID_ARG, "a, x and H are required");
+  return hip_check(c, launch_voigt(n, a, x, H, c->stream), "Voigt launch");
 }
 
 }  // extern "C"

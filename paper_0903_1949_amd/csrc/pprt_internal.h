@@ -157,6 +157,15 @@ size_t dense_workspace_bytes(int na, int64_t rows, int nf);
 int dense_freqs_per_item(int na);
 hipError_t launch_fs_dense(const DenseLaunch& L, hipStream_t s);
 
+// Weideman's expansion of the Faddeeva function (nlte.hip): N terms.
+constexpr int kVoigtN = 40;
+struct VoigtCoef {
+  double L;
+  double a[kVoigtN + 1];    // a[1..N] used
+};
+const VoigtCoef& voigt_coefficients();
+hipError_t launch_voigt(int64_t n, const double* a, const double* x, double* H, hipStream_t s);
+
 // Multilevel atom (nlte.hip); every array is device memory, FP64.
 struct MlArgs {
   const double* pops;     // [rows][nlev] populations the rates are built with
@@ -175,6 +184,13 @@ struct MlArgs {
   const double* ntot;     // [rows]
   const double* Cul;      // [rows][ntr]
   const double* Clu;      // [rows][ntr]
+  // depth-dependent Voigt lines (line_a == nullptr: sigma[k] throughout)
+  const double* nu;       // [nf]
+  const double* line_nu0; // [ntr]
+  const double* line_s;   // [ntr]
+  const double* line_a;   // [ntr]
+  const double* dopp;     // [rows]
+  VoigtCoef vc;
   int64_t rows;
   int32_t nf, nlev, ntr;
 };

@@ -85,7 +85,8 @@ class Continuum(C.Structure):
 class Atom(C.Structure):
     _fields_ = [("nlev", C.c_int32), ("ntr", C.c_int32)] + [
         (n, C.c_void_p) for n in ("lower", "upper", "k0", "k1", "owner", "sigma", "bfac", "W", "G",
-                                  "Bnu", "kc", "sc", "ntot", "Cul", "Clu")]
+                                  "Bnu", "kc", "sc", "ntot", "Cul", "Clu", "nu", "line_nu0",
+                                  "line_s", "line_a", "dopp")]
 
 
 class AliCtl(C.Structure):
@@ -144,6 +145,7 @@ def load_library(path: str = LIB_PATH):
         "pprt_plan_adjoint_workspace_bytes": (I, [P, C.c_int32, C.POINTER(C.c_size_t)]),
         "pprt_plan_set_launch": (I, [P, C.c_int32, C.c_int32]),
         "pprt_measure_peaks": (I, [P, P, C.c_size_t, C.POINTER(Peaks)]),
+        "pprt_voigt": (I, [P, C.c_int64, P, P, P]),
         "pprt_plan_set_operator": (I, [P, C.c_int32, C.c_int32]),
         "pprt_two_level_reset": (I, [P, P]),
         "pprt_plan_get_launch": (I, [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
@@ -224,6 +226,16 @@ class Context:
         s = C.c_uint32(0)
         self._check(self.lib.pprt_sync(self.h, C.byref(s)), "sync")
         return s.value
+
+    def voigt(self, a, x):
+        """pprt_voigt: H(a, x) for device float64 tensors of equal length."""
+        import torch
+        a = a.contiguous(); x = x.contiguous()
+        if a.dtype != torch.float64 or x.dtype != torch.float64 or a.shape != x.shape:
+            raise TypeError("a and x must be float64 tensors of one shape")
+        H = torch.empty_like(x)
+        self._check(self.lib.pprt_voigt(self.h, x.numel(), _ptr(a), _ptr(x), _ptr(H)), "voigt")
+        return H
 
     def measure_peaks(self, scratch_mib: int = 1024) -> dict:
         """pprt_measure_peaks with a scratch buffer of scratch_mib MiB."""
@@ -614,11 +626,17 @@ class DeviceAtom:
                       owner=i32(atom.owner), sigma=f64(atom.sigma), bfac=f64(atom.bfac), W=f64(atom.W),
                       G=f64(atom.Gst), Bnu=f64(atom.Bnu), kc=f64(atom.kc), sc=f64(atom.sc),
                       ntot=f64(atom.ntot), Cul=f64(atom.Cul), Clu=f64(atom.Clu))
+        voigt = getattr(atom, "line_a", None) is not None
+        if voigt:
+            self.t.update(nu=f64(atom.nu), line_nu0=f64(atom.line_nu0), line_s=f64(atom.line_s),
+                          line_a=f64(atom.line_a), dopp=f64(atom.dopp))
         self.tau = f64(atom.tau)
         self.nstar = f64(atom.nstar)
-        self.struct = Atom(self.nlev, self.ntr, *[_ptr(self.t[n]) for n in (
-            "lower", "upper", "k0", "k1", "owner", "sigma", "bfac", "W", "G", "Bnu", "kc", "sc", "ntot",
-            "Cul", "Clu")])
+        names = ["lower", "upper", "k0", "k1", "owner", "sigma", "bfac", "W", "G", "Bnu", "kc", "sc",
+                 "ntot", "Cul", "Clu"]
+        extra = ["nu", "line_nu0", "line_s", "line_a", "dopp"]
+        self.struct = Atom(self.nlev, self.ntr, *[_ptr(self.t[n]) for n in names],
+                           *[_ptr(self.t[n]) if voigt else None for n in extra])
 
 
 @dataclass
