@@ -18,6 +18,10 @@ paper's Papers I-II, Sect. 2):
   shells d and d+1 the optical path is dtau_k = (q_k(d) + q_k(d+1))/2 chi_ref
   (z_d - z_{d+1}), and the source is linear in it (linear short
   characteristics, the same layer weights as in plane-parallel geometry).
+  The path is evaluated as dtau_ref,d (r_d + r_{d+1}) / (z_d + z_{d+1}), the
+  same number without the cancellation of z_d - z_{d+1} in thin shells (a
+  log-tau radial grid with constant reference opacity makes the outer shells
+  ~1e-12 of the radius thick).
 * Inward intensity from I_top at shell 0; on a tangent ray the outward
   intensity starts at the tangent point with the inward value; on a core
   ray the outward intensity starts on the core with the diffusion value
@@ -92,7 +96,6 @@ def formal_solution_sph(r, tau, q, S, nc, lower="diffusion", Bbot=None, Bbot_pre
     S = np.asarray(S, dtype=np.float64)
     if S.ndim == 1:
         S = np.repeat(S[:, None], nf, axis=1)
-    chi_ref = np.diff(tau) / (r[:-1] - r[1:])               # per shell d..d+1
     p, inner = rays(r, nc)
     mu, w = mu_weights(r, p, inner)
     Itop = np.zeros(nf) if Itop is None else np.asarray(Itop, dtype=np.float64)
@@ -102,7 +105,7 @@ def formal_solution_sph(r, tau, q, S, nc, lower="diffusion", Bbot=None, Bbot_pre
     dt_last = 0.5 * (q[-2] + q[-1]) * (tau[-1] - tau[-2])   # radial, for the diffusion value
     for j in range(p.shape[0]):
         m = int(inner[j])
-        z = np.sqrt(np.maximum(0.0, r[: m + 1] ** 2 - p[j] ** 2))
+        z = np.sqrt(np.maximum(0.0, (r[: m + 1] - p[j]) * (r[: m + 1] + p[j])))
         if p[j] == r[m]:
             z[m] = 0.0
         if m == 0:                                          # zero-length ray at the outer shell
@@ -112,7 +115,11 @@ def formal_solution_sph(r, tau, q, S, nc, lower="diffusion", Bbot=None, Bbot_pre
             lamc[0] += wj * 2
             Iem[:, j] = Itop
             continue
-        dtau = 0.5 * (q[:m] + q[1 : m + 1]) * (chi_ref[:m] * (z[:m] - z[1 : m + 1]))[:, None]
+        # chi_ref (z_d - z_{d+1}) = dtau_ref,d (r_d + r_{d+1}) / (z_d + z_{d+1}), since
+        # z_d^2 - z_{d+1}^2 = r_d^2 - r_{d+1}^2: the same path, free of the
+        # cancellation of thin shells
+        path = np.diff(tau)[:m] * (r[:m] + r[1 : m + 1]) / (z[:m] + z[1 : m + 1])
+        dtau = 0.5 * (q[:m] + q[1 : m + 1]) * path[:, None]
         e, psi, al, ga = formal.short_char_weights(dtau)
         Iin = np.zeros((m + 1, nf)); Din = np.zeros((m + 1, nf))
         ain = np.zeros((m + 1, nf)); pin = np.zeros((m + 1, nf))   # d I_in(d) / d S(d), and 1 - it

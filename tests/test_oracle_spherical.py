@@ -1,7 +1,10 @@
 """Pins of the spherical oracle: the mu quadrature at every shell, the exact
 constant state, the closed-form solution for a uniform source and opacity
-(path lengths computed directly, no recursion), Lambda* against brute-force
-unit columns, and the ALI fixed point against a direct solve."""
+(path lengths computed directly, no recursion), the same on the thin shells
+of a log-tau radial grid against a 60-digit evaluation, Lambda* against
+brute-force unit columns, and the ALI fixed point against a direct solve."""
+from decimal import Decimal, localcontext
+
 import numpy as np
 import pytest
 
@@ -67,6 +70,47 @@ def test_uniform_sphere_closed_form():
             Iout = 1 - np.exp(-chi * path_out)
             J[d] += 0.5 * w[d, j] * (Iin + Iout)
     assert np.max(np.abs(out["J"] - J)) < 1e-13
+
+
+def test_thin_shells_against_high_precision():
+    """The paper's line-test sphere (Sect. 3.1): r_out = 2 r_c, tau_std log
+    from 1e-4 to 1e8 at constant continuum opacity, so the outer shells are
+    ~1e-12 r thick.  S = 1, uniform q, nothing incident: J against the same
+    sums in 60-digit decimal arithmetic (paths z_d - z_{d+1} taken directly,
+    I = 1 - exp(-path) per direction).  Forming z_d - z_{d+1} in float64
+    loses ~1e-11 here; the oracle must stay at rounding level."""
+    nd, nc = 40, 5
+    tmin, tmax = 1e-4, 1e8
+    tau = np.geomspace(tmin, tmax, nd)
+    r = 2.0 - (tau - tmin) / (tmax - tmin)
+    r[-1] = 1.0
+    chi = np.array([1e-9, 1e-6, 1e-3])
+    q = np.repeat(chi[None, :], nd, axis=0)
+    out = spherical.formal_solution_sph(r, tau, q, np.ones((nd, 3)), nc, lower="given",
+                                        Bbot=np.zeros(3))
+    p, inner = spherical.rays(r, nc)
+    w = out["w"]
+    J = np.zeros((nd, 3))
+    with localcontext() as ctx:
+        ctx.prec = 60
+        R = [Decimal(float(x)) for x in r]
+        T = [Decimal(float(x)) for x in tau]
+        for j, pj in enumerate(p):
+            m, P = int(inner[j]), Decimal(float(pj))
+            z = [(R[d] * R[d] - P * P).sqrt() for d in range(m + 1)]
+            if pj == r[m]:
+                z[m] = Decimal(0)
+            core = pj < r[-1]
+            seg = [(T[d + 1] - T[d]) / (R[d] - R[d + 1]) * (z[d] - z[d + 1]) for d in range(m)]
+            for k in range(3):
+                cum = [Decimal(0)]
+                for sg in seg:
+                    cum.append(cum[-1] + Decimal(float(chi[k])) * sg)
+                for d in range(m + 1):
+                    t_out = (cum[-1] - cum[d]) if core else (2 * cum[-1] - cum[d])
+                    I = 2 - (-cum[d]).exp() - (-t_out).exp()
+                    J[d, k] += 0.5 * w[d, j] * float(I)
+    assert np.max(np.abs(out["J"] - J) / J) < 1e-13
 
 
 @pytest.mark.parametrize("nd,nf,nc,seed", [(6, 2, 3, 0), (10, 3, 5, 1)])
