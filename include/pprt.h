@@ -374,6 +374,45 @@ pprt_status pprt_plan_nlte_workspace_bytes(const pprt_plan* plan, int32_t nlev, 
 pprt_status pprt_nlte_step(pprt_plan* plan, const pprt_fs_in* in, const pprt_atom* atom,
                            double* pops, double* max_rel, void* workspace);
 
+/* ---- 1D spherical symmetry ----------------------------------------------
+ * The formal solution on impact-parameter rays through spherical shells
+ * (the geometry of the paper's 1D comparison calculations, Sect. 3.1), with
+ * the same linear short-characteristic update per ray segment.  Shells
+ * r_0 > .. > r_{nd-1} = R_core per atmosphere (node 0 outermost, finite,
+ * positive, strictly decreasing: else PPRT_E_INVALID_ARG); the radial
+ * reference optical depth tau (from pprt_fs_in, increasing inward) sets
+ * chi_ref = dtau / dr per shell and q_k = chi_k / chi_ref, so a segment of
+ * a ray with impact parameter p has the optical path (q_k(d) + q_k(d+1))/2
+ * dtau_d (r_d + r_{d+1}) / (z_d + z_{d+1}), z = sqrt(r^2 - p^2).  Rays: n_core core rays with mu at the core
+ * 1 - c/n_core (c = 0..n_core-1) and one tangent ray per shell.  At each
+ * shell J, J - S, H use trapezoid weights in mu over the rays crossing it
+ * (mu from 1 down to 0 at the shell's tangent ray); Lambda*_dd = dJ/dS(d)
+ * exactly, including the round trip of tangent rays through their tangent
+ * point.  Incident intensity Itop and core intensity Ibot (GIVEN) are
+ * isotropic, [nb][nf]; the diffusion core uses B + mu (B - B_prev)/dtau_k
+ * of the last radial layer with mu at the core.  Outputs J, JmS, lstar,
+ * lstar_c, H ([rows][nf]).  r is a host array [rows], read during the call
+ * only.  At most 65535 atmospheres and 1024 core rays per plan. */
+typedef struct pprt_sph_plan pprt_sph_plan;
+pprt_status pprt_sph_plan_create(pprt_ctx* ctx, int32_t nbatch, const int32_t* nd, int32_t nf,
+                                 int32_t precision, int32_t lower_bc, uint32_t outputs,
+                                 const double* r, int32_t n_core, pprt_sph_plan** out);
+void pprt_sph_plan_destroy(pprt_sph_plan* plan);
+pprt_status pprt_sph_plan_info(const pprt_sph_plan* plan, int64_t* rows, int32_t* nrays,
+                               int64_t* ray_shell_pairs);
+pprt_status pprt_sph_formal_solution(pprt_sph_plan* plan, const pprt_fs_in* in, pprt_fs_out* out);
+/* Two-level operator-splitting step on spherical atmospheres: pure line,
+ * diagonal Lambda*, the update of pprt_two_level_ali_step (the paper's
+ * Sect. 3.2.2 line tests, here on the geometry above).  As there, in->Sg,
+ * Bbot and Bbot_prev are ignored: the line source is S [rows] (FP64 state,
+ * updated in place), the diffusion core takes atom->B at the two innermost
+ * shells, and atmospheres with active[b] == 0 are left untouched.
+ * workspace: pprt_sph_plan_workspace_bytes. */
+pprt_status pprt_sph_plan_workspace_bytes(const pprt_sph_plan* plan, size_t* bytes);
+pprt_status pprt_sph_two_level_ali_step(pprt_sph_plan* plan, const pprt_fs_in* in,
+                                        const pprt_two_level* atom, double* S, double* max_rel,
+                                        const int32_t* active, void* workspace);
+
 /* ---- Voigt function ----------------------------------------------------
  * H(a, x) = Re w(x + i a), w the Faddeeva function, for a >= 0, by the
  * rational expansion of Weideman (1994) with N = 40 terms,

@@ -78,7 +78,8 @@ __global__ void k_sg_assemble(const double* __restrict__ S, const T* __restrict_
   Sg[x] = (T)((double)p[x] * S[r] + (double)c[x]);
 }
 
-// Per row: jms = sum_k wphi_k (JmS_k + S^g_k - S_l), olb = sum_k wphi_k ((1-p_k) + p_k Lc_k),
+// Per row: jms = sum_k wphi_k (JmS_k + S^g_k - S_l), olb = sum_k wphi_k ((1-p_k) + p_k Lc_k)
+// (p and S^g NULL: a pure line, p = 1 and S^g = S_l),
 // written as part[row] = (jms, olb, 0, 0) (one frequency group, one hemisphere slot).
 template <typename T>
 __global__ __launch_bounds__(256) void k_profile_reduce(const double* __restrict__ S,
@@ -95,8 +96,10 @@ __global__ __launch_bounds__(256) void k_profile_reduce(const double* __restrict
   for (int k = threadIdx.x; k < nf; k += blockDim.x) {
     const int64_t x = r * nf + k;
     const double wp = (double)wphi[k];
-    const double pk = (double)p[x];
-    js += wp * ((double)JmS[x] + ((double)Sg[x] - Sl));
+    // p == nullptr: a pure line (S^g = S_l, p = 1)
+    const double pk = p ? (double)p[x] : 1.0;
+    const double sgl = p ? ((double)Sg[x] - Sl) : 0.0;
+    js += wp * ((double)JmS[x] + sgl);
     ls += wp * ((1.0 - pk) + pk * (double)Lc[x]);
   }
   red[0][threadIdx.x] = js;

@@ -751,8 +751,6 @@ pprt_status pprt_two_level_ali_step_continuum(pprt_plan* p, const pprt_fs_in* in
   if (!in->tau || !in->q || !ct->pfrac || !ct->sg_const)
     return fail(c, PPRT_E_INVALID_ARG, "tau, q, pfrac and sg_const are required");
   if (!at->eps || !at->B || !at->wphi) return fail(c, PPRT_E_INVALID_ARG, "atom needs eps, B and wphi");
-  if (p->lower_bc == PPRT_BC_DIFFUSION && (!in->Bbot || !in->Bbot_prev))
-    return fail(c, PPRT_E_INVALID_ARG, "diffusion lower boundary needs Bbot and Bbot_prev");
   if (!ws) return fail(c, PPRT_E_WORKSPACE, "workspace required (pprt_plan_continuum_workspace_bytes)");
   if (ct->omega && (p->precision != PPRT_FP64 || !dense_na_supported(p->na)))
     return fail(c, PPRT_E_UNSUPPORTED, "in-layer scattering needs an FP64 plan and na in {1,2,4,8,16}");
@@ -1282,6 +1280,236 @@ pprt_status pprt_voigt(pprt_ctx* c, int64_t n, const double* a, const double* x,
   if (!c) return PPRT_E_INVALID_ARG;
   if (n < 0 || (n > 0 && (!a || !x || !H))) return fail(c, PPRT_E_INVALID_ARG, "a, x and H are required");
   return hip_check(c, launch_voigt(n, a, x, H, c->stream), "Voigt launch");
+}
+
+}  // extern "C"
+
+// ---- 1D spherical symmetry -------------------------------------------------
+
+struct pprt_sph_plan {
+  pprt_ctx* ctx = nullptr;
+  int nb = 0, nf = 0, precision = 0, lower_bc = 0, nc = 0;
+  uint32_t outputs = 0;
+  std::vector<int32_t> nd;
+  std::vector<int64_t> off;
+  int64_t rows = 0;
+  int64_t* d_off = nullptr;
+  int32_t* d_ray0 = nullptr;
+  SphRay* d_rays = nullptr;
+  double* d_tab = nullptr;     // [3][entries]: path factor | half weight | mu
+  int64_t entries = 0;
+  int32_t nrays = 0;
+};
+
+extern "C" {
+
+pprt_status pprt_sph_plan_create(pprt_ctx* c, int32_t nb, const int32_t* nd, int32_t nf, int32_t precision,
+                                 int32_t lower_bc, uint32_t outputs, const double* r, int32_t n_core,
+                                 pprt_sph_plan** out) {
+  if (!c || !out) return PPRT_E_INVALID_ARG;
+  *out = nullptr;
+  if (!nd || !r) return fail(c, PPRT_E_INVALID_ARG, "nd and r are required");
+  if (nb < 1 || nf < 1) return fail(c, PPRT_E_SHAPE, "nbatch and nf must be >= 1");
+  if (precision != PPRT_FP64 && precision != PPRT_FP32) return fail(c, PPRT_E_INVALID_ARG, "unknown precision");
+  if (lower_bc != PPRT_BC_DIFFUSION && lower_bc != PPRT_BC_GIVEN)
+    return fail(c, PPRT_E_INVALID_ARG, "unknown lower boundary");
+  if (n_core < 1 || n_core > 1024) return fail(c, PPRT_E_INVALID_ARG, "n_core must be in 1..1024");
+  if (nb > 65535) return fail(c, PPRT_E_SHAPE, "at most 65535 spherical atmospheres per plan");
+  const uint32_t allowed = PPRT_OUT_J | PPRT_OUT_JMS | PPRT_OUT_LSTAR | PPRT_OUT_LSTAR_C | PPRT_OUT_H;
+  if (outputs & ~allowed) return fail(c, PPRT_E_UNSUPPORTED, "spherical plans give J, JmS, lstar, lstar_c and H");
+  for (int b = 0; b < nb; ++b)
+    if (nd[b] < 2) return fail(c, PPRT_E_SHAPE, "nd[%d] = %d: need at least 2 shells", b, nd[b]);
+  pprt_sph_plan* p = new (std::nothrow) pprt_sph_plan;
+  if (!p) return fail(c, PPRT_E_DEVICE, "out of host memory");
+  p->ctx = c; p->nb = nb; p->nf = nf; p->precision = precision; p->lower_bc = lower_bc;
+  p->nc = n_core; p->outputs = outputs;
+  p->nd.assign(nd, nd + nb);
+  p->off.assign(nb + 1, 0);
+  for (int b = 0; b < nb; ++b) p->off[b + 1] = p->off[b] + nd[b];
+  p->rows = p->off[nb];
+  std::vector<int32_t> ray0(nb + 1, 0);
+  std::vector<SphRay> rays;
+  std::vector<double> pf, hw, muv;
+  for (int b = 0; b < nb; ++b) {
+    const double* rb = r + p->off[b];
+    const int n = nd[b];
+    for (int d = 0; d + 1 < n; ++d)
+      if (!(rb[d] > rb[d + 1]) || !(rb[d + 1] > 0.0) || !std::isfinite(rb[d])) {
+        delete p;
+        return fail(c, PPRT_E_INVALID_ARG, "atmosphere %d: radii must decrease strictly inward and stay positive", b);
+      }
+    const double Rc = rb[n - 1];
+    // impact parameters, ascending: core rays (mu_core = 1 - c/nc), then tangent rays r_{n-1} .. r_0
+    std::vector<double> pp;
+    std::vector<int> inner;
+    for (int ci = 0; ci < n_core; ++ci) {
+      const double mc = 1.0 - (double)ci / n_core;
+      pp.push_back(Rc * std::sqrt(std::max(0.0, 1.0 - mc * mc)));
+      inner.push_back(n - 1);
+    }
+    for (int m = n - 1; m >= 0; --m) {
+      pp.push_back(rb[m]);
+      inner.push_back(m);
+    }
+    const int nr = (int)pp.size();
+    // mu and trapezoid weights in mu per shell over the rays crossing it
+    std::vector<double> mu((size_t)n * nr, 0.0), w((size_t)n * nr, 0.0);
+    for (int d = 0; d < n; ++d) {
+      std::vector<int> hit;
+      for (int j = 0; j < nr; ++j)
+        if (inner[j] >= d) hit.push_back(j);      // p ascending = mu descending
+      for (int j : hit) {
+        const double x = pp[j] / rb[d];
+        mu[(size_t)d * nr + j] = (pp[j] == rb[d]) ? 0.0 : std::sqrt(std::max(0.0, 1.0 - x * x));
+      }
+      for (size_t i = 0; i + 1 < hit.size(); ++i) {
+        const double dm = mu[(size_t)d * nr + hit[i]] - mu[(size_t)d * nr + hit[i + 1]];
+        w[(size_t)d * nr + hit[i]] += 0.5 * dm;
+        w[(size_t)d * nr + hit[i + 1]] += 0.5 * dm;
+      }
+    }
+    ray0[b] = (int32_t)rays.size();
+    for (int j = 0; j < nr; ++j) {
+      const int m = inner[j];
+      SphRay ry{};
+      ry.e0 = (int32_t)pf.size();
+      ry.m = m;
+      ry.core = (m == n - 1 && pp[j] < Rc) ? 1 : 0;
+      std::vector<double> z(m + 1);
+      for (int d = 0; d <= m; ++d) z[d] = std::sqrt(std::max(0.0, (rb[d] - pp[j]) * (rb[d] + pp[j])));
+      if (pp[j] == rb[m]) z[m] = 0.0;
+      ry.mu_core = ry.core ? z[m] / rb[m] : 0.0;
+      for (int d = 0; d <= m; ++d) {
+        // z_d - z_{d+1} = (r_d - r_{d+1}) * path; times chi_ref = dtau_ref / (r_d - r_{d+1})
+        pf.push_back(d < m ? (rb[d] + rb[d + 1]) / (z[d] + z[d + 1]) : 0.0);
+        hw.push_back(0.5 * w[(size_t)d * nr + j]);
+        muv.push_back(mu[(size_t)d * nr + j]);
+      }
+      rays.push_back(ry);
+    }
+    if (pf.size() > (size_t)INT32_MAX) {
+      delete p;
+      return fail(c, PPRT_E_SHAPE, "too many (ray, shell) pairs");
+    }
+  }
+  ray0[nb] = (int32_t)rays.size();
+  p->nrays = (int32_t)rays.size();
+  p->entries = (int64_t)pf.size();
+  std::vector<double> tab(3 * pf.size());
+  std::copy(pf.begin(), pf.end(), tab.begin());
+  std::copy(hw.begin(), hw.end(), tab.begin() + pf.size());
+  std::copy(muv.begin(), muv.end(), tab.begin() + 2 * pf.size());
+  hipError_t e = hipMalloc(&p->d_off, p->off.size() * sizeof(int64_t));
+  if (e == hipSuccess) e = hipMalloc(&p->d_ray0, ray0.size() * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc(&p->d_rays, rays.size() * sizeof(SphRay));
+  if (e == hipSuccess) e = hipMalloc(&p->d_tab, tab.size() * sizeof(double));
+  if (e == hipSuccess) e = hipMemcpy(p->d_off, p->off.data(), p->off.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->d_ray0, ray0.data(), ray0.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->d_rays, rays.data(), rays.size() * sizeof(SphRay), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->d_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    pprt_sph_plan_destroy(p);
+    return hip_check(c, e, "spherical plan metadata");
+  }
+  *out = p;
+  return PPRT_OK;
+}
+
+void pprt_sph_plan_destroy(pprt_sph_plan* p) {
+  if (!p) return;
+  if (p->d_off) (void)hipFree(p->d_off);
+  if (p->d_ray0) (void)hipFree(p->d_ray0);
+  if (p->d_rays) (void)hipFree(p->d_rays);
+  if (p->d_tab) (void)hipFree(p->d_tab);
+  delete p;
+}
+
+pprt_status pprt_sph_plan_info(const pprt_sph_plan* p, int64_t* rows, int32_t* nrays, int64_t* pairs) {
+  if (!p) return PPRT_E_INVALID_ARG;
+  if (rows) *rows = p->rows;
+  if (nrays) *nrays = p->nrays;
+  if (pairs) *pairs = p->entries;
+  return PPRT_OK;
+}
+
+}  // extern "C"
+
+namespace {
+template <typename T>
+pprt_status sph_launch(pprt_sph_plan* p, const pprt_fs_in* in, const double* Sl, const double* Bl,
+                       const int32_t* active, T* J, T* JmS, T* L, T* Lc, T* H) {
+  SphArgs<T> a{};
+  a.off = p->d_off; a.ray0 = p->d_ray0; a.rays = p->d_rays;
+  a.path = p->d_tab; a.hw = p->d_tab + p->entries; a.mu = p->d_tab + 2 * p->entries;
+  a.tau = in->tau; a.q = (const T*)in->q; a.Sg = Sl ? nullptr : (const T*)in->Sg; a.Sl = Sl;
+  a.Itop = (const T*)in->Itop; a.Bbot = (const T*)in->Bbot; a.Bbot_prev = (const T*)in->Bbot_prev;
+  a.Ibot = (const T*)in->Ibot; a.Bl = Bl; a.active = active;
+  a.J = J; a.JmS = JmS; a.lstar = L; a.lstar_c = Lc; a.H = H;
+  a.nf = p->nf; a.lower_bc = p->lower_bc;
+  return hip_check(p->ctx, launch_fs_sph(p->precision, p->nb, p->nf, p->ctx->stream, &a),
+                   "spherical formal-solution launch");
+}
+}  // namespace
+
+extern "C" {
+
+pprt_status pprt_sph_formal_solution(pprt_sph_plan* p, const pprt_fs_in* in, pprt_fs_out* out) {
+  if (!p) return PPRT_E_INVALID_ARG;
+  pprt_ctx* c = p->ctx;
+  if (!in || !out) return fail(c, PPRT_E_INVALID_ARG, "null in/out");
+  if (!in->tau || !in->q || !in->Sg) return fail(c, PPRT_E_INVALID_ARG, "tau, q and Sg are required");
+  if (p->lower_bc == PPRT_BC_DIFFUSION && (!in->Bbot || !in->Bbot_prev))
+    return fail(c, PPRT_E_INVALID_ARG, "diffusion lower boundary needs Bbot and Bbot_prev");
+  const uint32_t o = p->outputs;
+  if (o == 0) return fail(c, PPRT_E_INVALID_ARG, "plan requests no outputs");
+  struct { uint32_t bit; void* ptr; const char* name; } req[] = {
+      {PPRT_OUT_J, out->J, "J"}, {PPRT_OUT_JMS, out->JmS, "JmS"}, {PPRT_OUT_LSTAR, out->lstar, "lstar"},
+      {PPRT_OUT_LSTAR_C, out->lstar_c, "lstar_c"}, {PPRT_OUT_H, out->H, "H"}};
+  for (auto& r : req)
+    if ((o & r.bit) && !r.ptr) return fail(c, PPRT_E_INVALID_ARG, "output %s requested but NULL", r.name);
+  auto pick = [&](uint32_t bit, void* ptr) { return (o & bit) ? ptr : nullptr; };
+  if (p->precision == PPRT_FP64)
+    return sph_launch<double>(p, in, nullptr, nullptr, nullptr, (double*)pick(PPRT_OUT_J, out->J), (double*)pick(PPRT_OUT_JMS, out->JmS),
+                              (double*)pick(PPRT_OUT_LSTAR, out->lstar), (double*)pick(PPRT_OUT_LSTAR_C, out->lstar_c),
+                              (double*)pick(PPRT_OUT_H, out->H));
+  return sph_launch<float>(p, in, nullptr, nullptr, nullptr, (float*)pick(PPRT_OUT_J, out->J), (float*)pick(PPRT_OUT_JMS, out->JmS),
+                           (float*)pick(PPRT_OUT_LSTAR, out->lstar), (float*)pick(PPRT_OUT_LSTAR_C, out->lstar_c),
+                           (float*)pick(PPRT_OUT_H, out->H));
+}
+
+pprt_status pprt_sph_plan_workspace_bytes(const pprt_sph_plan* p, size_t* bytes) {
+  if (!p || !bytes) return PPRT_E_INVALID_ARG;
+  const size_t es = p->precision == PPRT_FP64 ? sizeof(double) : sizeof(float);
+  *bytes = 2 * align256((size_t)p->rows * p->nf * es) + align256((size_t)p->rows * 4 * sizeof(double));
+  return PPRT_OK;
+}
+
+pprt_status pprt_sph_two_level_ali_step(pprt_sph_plan* p, const pprt_fs_in* in, const pprt_two_level* at,
+                                        double* S, double* max_rel, const int32_t* active, void* ws) {
+  if (!p) return PPRT_E_INVALID_ARG;
+  pprt_ctx* c = p->ctx;
+  if (!in || !at || !S || !max_rel) return fail(c, PPRT_E_INVALID_ARG, "null argument");
+  if (!in->tau || !in->q) return fail(c, PPRT_E_INVALID_ARG, "tau and q are required");
+  if (!at->eps || !at->B || !at->wphi) return fail(c, PPRT_E_INVALID_ARG, "atom needs eps, B and wphi");
+  if (!ws) return fail(c, PPRT_E_WORKSPACE, "workspace required (pprt_sph_plan_workspace_bytes)");
+  const size_t es = p->precision == PPRT_FP64 ? sizeof(double) : sizeof(float);
+  const size_t arr = align256((size_t)p->rows * p->nf * es);
+  char* base = (char*)ws;
+  void* JmS = base;
+  void* Lc = base + arr;
+  double* part = (double*)(base + 2 * arr);
+  pprt_status r = p->precision == PPRT_FP64
+                      ? sph_launch<double>(p, in, S, at->B, active, nullptr, (double*)JmS, nullptr, (double*)Lc, nullptr)
+                      : sph_launch<float>(p, in, S, at->B, active, nullptr, (float*)JmS, nullptr, (float*)Lc, nullptr);
+  if (r != PPRT_OK) return r;
+  r = hip_check(c, launch_profile_reduce(p->precision, S, JmS, Lc, nullptr, nullptr, at->wphi, part, p->rows,
+                                         p->nf, c->stream), "profile reduction");
+  if (r != PPRT_OK) return r;
+  AliUpdateArgs u{};
+  u.off = p->d_off; u.part = part; u.eps = at->eps; u.B = at->B; u.S = S; u.max_rel = max_rel;
+  u.active = const_cast<int32_t*>(active); u.iters = nullptr; u.status = c->d_status; u.tol = 0.0;
+  u.nw = 1; u.nb = p->nb; u.part_fp64 = 1;
+  return hip_check(c, launch_ali_update(p->nb, c->stream, u), "ALI update launch");
 }
 
 }  // extern "C"

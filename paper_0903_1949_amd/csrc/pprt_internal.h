@@ -157,6 +157,36 @@ size_t dense_workspace_bytes(int na, int64_t rows, int nf);
 int dense_freqs_per_item(int na);
 hipError_t launch_fs_dense(const DenseLaunch& L, hipStream_t s);
 
+// Spherical formal solution (sph.hip).
+struct SphRay {
+  int32_t e0;      // first (ray, shell) entry
+  int32_t m;       // innermost shell reached
+  int32_t core;    // 1: ends on the core
+  double mu_core;  // mu at the core (core rays)
+};
+template <typename T>
+struct SphArgs {
+  const int64_t* off;       // [nb+1]
+  const int32_t* ray0;      // [nb+1] rays of atmosphere b: ray0[b] .. ray0[b+1]-1
+  const SphRay* rays;
+  const double* path;       // [entries] (r_d + r_{d+1}) / (z_d + z_{d+1}); 0 at the innermost node
+  const double* hw;         // [entries] half trapezoid weight in mu
+  const double* mu;         // [entries]
+  const double* tau;
+  const T* q;
+  const T* Sg;              // [rows][nf] or nullptr (then Sl)
+  const double* Sl;         // [rows] source per row (pure line), when Sg == nullptr
+  const T* Itop;            // [nb][nf] isotropic incident, or nullptr
+  const T* Bbot;            // [nb][nf] diffusion core: B at the two innermost shells,
+  const T* Bbot_prev;       //   or, when Bl is set, Bl at those rows (all frequencies)
+  const double* Bl;         // [rows] or nullptr
+  const T* Ibot;            // [nb][nf] isotropic core intensity (GIVEN)
+  const int32_t* active;    // [nb] or nullptr: skip atmospheres with active[b] == 0
+  T *J, *JmS, *lstar, *lstar_c, *H;
+  int32_t nf, lower_bc;
+};
+hipError_t launch_fs_sph(int precision, int nb, int nf, hipStream_t s, const void* args);
+
 // Weideman's expansion of the Faddeeva function (nlte.hip): N terms.
 constexpr int kVoigtN = 40;
 struct VoigtCoef {

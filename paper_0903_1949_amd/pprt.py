@@ -153,6 +153,14 @@ def load_library(path: str = LIB_PATH):
                                    C.POINTER(TuneReport)]),
         "pprt_emergent_intensity": (I, [P, C.POINTER(FsIn), C.c_int32, P, P]),
         "pprt_formal_solution_vjp": (I, [P, C.POINTER(FsIn), C.c_int32, P, C.POINTER(FsGrad), P]),
+        "pprt_sph_plan_create": (I, [P, C.c_int32, C.POINTER(C.c_int32), C.c_int32, C.c_int32,
+                                     C.c_int32, U32, C.POINTER(D), C.c_int32, C.POINTER(P)]),
+        "pprt_sph_plan_destroy": (None, [P]),
+        "pprt_sph_plan_info": (I, [P, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                                   C.POINTER(C.c_int64)]),
+        "pprt_sph_formal_solution": (I, [P, C.POINTER(FsIn), C.POINTER(FsOut)]),
+        "pprt_sph_plan_workspace_bytes": (I, [P, C.POINTER(C.c_size_t)]),
+        "pprt_sph_two_level_ali_step": (I, [P, C.POINTER(FsIn), C.POINTER(TwoLevel), P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -611,6 +619,106 @@ class Plan:
                                                     _ptr(self.workspace()), int(bool(force)),
                                                     C.byref(rep)), "autotune")
         return {k: getattr(rep, k) for k, _ in TuneReport._fields_}
+
+
+class SphPlan:
+    """Ragged batch of spherical atmospheres (see pprt_sph_plan_create): radii
+    r [rows] (host, decreasing inward per atmosphere), n_core core rays plus
+    one tangent ray per shell."""
+
+    OUTPUTS = {OUT_J: "J", OUT_JMS: "JmS", OUT_LSTAR: "lstar", OUT_LSTAR_C: "lstar_c", OUT_H: "H"}
+
+    def __init__(self, ctx: Context, nd, nf: int, r, n_core: int, precision: int = FP32,
+                 lower_bc: int = BC_DIFFUSION, outputs: int = OUT_JMS | OUT_LSTAR_C):
+        import torch
+        self.ctx, self.lib = ctx, ctx.lib
+        self.nd = np.ascontiguousarray(np.asarray(nd, dtype=np.int32))
+        self.nf, self.precision, self.n_core = int(nf), int(precision), int(n_core)
+        self.lower_bc, self.outputs = int(lower_bc), int(outputs)
+        self._r = np.ascontiguousarray(np.asarray(r, dtype=np.float64))
+        if self._r.shape != (int(self.nd.sum()),):
+            raise ValueError(f"r must have shape ({int(self.nd.sum())},)")
+        h = C.c_void_p()
+        ctx._check(self.lib.pprt_sph_plan_create(
+            ctx.h, int(self.nd.shape[0]), self.nd.ctypes.data_as(C.POINTER(C.c_int32)), self.nf,
+            self.precision, self.lower_bc, self.outputs, self._r.ctypes.data_as(C.POINTER(C.c_double)),
+            self.n_core, C.byref(h)), "sph_plan_create")
+        self.h = h
+        rows, nr, pairs = C.c_int64(), C.c_int32(), C.c_int64()
+        ctx._check(self.lib.pprt_sph_plan_info(h, C.byref(rows), C.byref(nr), C.byref(pairs)),
+                   "sph_plan_info")
+        self.rows, self.nrays, self.pairs = rows.value, nr.value, pairs.value
+        nb = C.c_size_t()
+        ctx._check(self.lib.pprt_sph_plan_workspace_bytes(h, C.byref(nb)), "sph_workspace_bytes")
+        self.workspace_bytes = nb.value
+        self.dtype = torch.float64 if self.precision == FP64 else torch.float32
+        self._ws = None
+
+    @property
+    def nb(self) -> int:
+        return int(self.nd.shape[0])
+
+    def workspace(self):
+        import torch
+        if self._ws is None:
+            self._ws = torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8,
+                                   device=f"cuda:{self.ctx.device}")
+        return self._ws
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pprt_sph_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    _want = Plan._want
+
+    def fs_in(self, tau, q, Sg=None, Bbot=None, Bbot_prev=None, Itop=None, Ibot=None):
+        import torch
+        R, nf, nb, dt = self.rows, self.nf, self.nb, self.dtype
+        self._want(tau, (R,), torch.float64, "tau")
+        self._want(q, (R, nf), dt, "q")
+        if Sg is not None:
+            self._want(Sg, (R, nf), dt, "Sg")
+        for name, t in (("Bbot", Bbot), ("Bbot_prev", Bbot_prev), ("Itop", Itop), ("Ibot", Ibot)):
+            if t is not None:
+                self._want(t, (nb, nf), dt, name)
+        return FsIn(_ptr(tau), _ptr(q), _ptr(Sg), _ptr(Itop), _ptr(Bbot), _ptr(Bbot_prev), _ptr(Ibot))
+
+    def formal_solution(self, tau, q, Sg, Bbot=None, Bbot_prev=None, Itop=None, Ibot=None) -> dict:
+        """pprt_sph_formal_solution: returns a dict of the requested [rows, nf] outputs."""
+        import torch
+        fin = self.fs_in(tau, q, Sg, Bbot, Bbot_prev, Itop, Ibot)
+        out, ptrs = {}, {}
+        for bit, name in self.OUTPUTS.items():
+            if self.outputs & bit:
+                out[name] = torch.empty((self.rows, self.nf), dtype=self.dtype, device=tau.device)
+                ptrs[name] = _ptr(out[name])
+        fo = FsOut(**ptrs)
+        self.ctx._check(self.lib.pprt_sph_formal_solution(self.h, C.byref(fin), C.byref(fo)),
+                        "sph_formal_solution")
+        return out
+
+    def two_level_ali_step(self, tau, q, S, eps, B, wphi, max_rel, active=None, Itop=None, Ibot=None):
+        """pprt_sph_two_level_ali_step: one spherical formal solution + OS update, S in place."""
+        import torch
+        fin = self.fs_in(tau, q, None, None, None, Itop, Ibot)
+        self._want(eps, (self.nb,), torch.float64, "eps")
+        self._want(B, (self.rows,), torch.float64, "B")
+        self._want(wphi, (self.nf,), self.dtype, "wphi")
+        self._want(S, (self.rows,), torch.float64, "S")
+        self._want(max_rel, (self.nb,), torch.float64, "max_rel")
+        if active is not None:
+            self._want(active, (self.nb,), torch.int32, "active")
+        at = TwoLevel(_ptr(eps), _ptr(B), _ptr(wphi))
+        self.ctx._check(self.lib.pprt_sph_two_level_ali_step(
+            self.h, C.byref(fin), C.byref(at), _ptr(S), _ptr(max_rel), _ptr(active),
+            _ptr(self.workspace())), "sph_two_level_ali_step")
 
 
 class DeviceAtom:

@@ -185,6 +185,73 @@ def two_level_batch(nb=512, nd_lo=48, nd_hi=256, na=8, nf=1024, eps_lo=1e-6,
                          meta={"x": x, "seed": seed, "cont_ratio": cont_ratio, "eps_c": eps_c})
 
 
+@dataclass
+class SphericalBatch:
+    """A batch of independent spherically symmetric two-level atmospheres."""
+
+    nd: np.ndarray            # [nb] int32 shells per atmosphere
+    r: np.ndarray             # [sum nd] float64 radii, decreasing inward, r[last] = r_core
+    tau: np.ndarray           # [sum nd] float64 radial reference optical depth
+    q: np.ndarray             # [sum nd, nf] float64 opacity / chi_ref
+    phi: np.ndarray           # [nf]
+    wnu: np.ndarray           # [nf]
+    eps: np.ndarray           # [nb]
+    B: np.ndarray             # [sum nd]
+    n_core: int               # core rays per atmosphere
+    name: str = ""
+
+    @property
+    def nb(self) -> int:
+        return int(self.nd.shape[0])
+
+    @property
+    def nf(self) -> int:
+        return int(self.phi.shape[0])
+
+    @property
+    def off(self) -> np.ndarray:
+        o = np.zeros(self.nb + 1, dtype=np.int64)
+        o[1:] = np.cumsum(self.nd)
+        return o
+
+    def rows(self, b: int) -> slice:
+        o = self.off
+        return slice(int(o[b]), int(o[b + 1]))
+
+
+def spherical_batch(nb=4, nd_lo=24, nd_hi=48, nf=64, n_core=8, r_out=2.0, tau_lo=1e-4,
+                    tau_hi=1e8, eps_lo=1e-6, eps_hi=1e-1, sigma_m=0.5, x_max=5.0,
+                    B_slope=0.0, seed=5) -> SphericalBatch:
+    """Spheres after the paper's test environment (Sect. 3.1): core radius 1,
+    outer radius r_out (2 for its large test case, 1.1 for the small one),
+    radial optical depth log-spaced tau_lo..tau_hi (1e-4..1e8 there) at a
+    constant reference opacity, so r_d = r_out - (tau_d - tau_lo) (r_out - 1) /
+    (tau_hi - tau_lo); a Doppler line with per-node multipliers
+    m ~ lognormal(0, sigma_m), q_k = m phi_k; eps_b log-uniform; B = 1 (the
+    paper's constant Planck function) plus B_slope * (d / (nd - 1)) when a
+    gradient is wanted."""
+    rng = np.random.default_rng(seed)
+    nd = rng.integers(nd_lo, nd_hi + 1, size=nb).astype(np.int32)
+    eps = np.exp(rng.uniform(math.log(eps_lo), math.log(eps_hi), size=nb))
+    x, phi, w = doppler_grid(nf, x_max)
+    rs, taus, ms, Bs = [], [], [], []
+    for b in range(nb):
+        n = int(nd[b])
+        t = log_tau(n, tau_lo, tau_hi)
+        r = r_out - (t - tau_lo) * ((r_out - 1.0) / (tau_hi - tau_lo))
+        r[0], r[-1] = r_out, 1.0
+        rs.append(r)
+        taus.append(t)
+        ms.append(rng.lognormal(0.0, sigma_m, size=n))
+        Bs.append(1.0 + B_slope * np.arange(n) / (n - 1))
+    m = np.concatenate(ms)
+    return SphericalBatch(nd=nd, r=np.concatenate(rs), tau=np.concatenate(taus),
+                          q=m[:, None] * phi[None, :], phi=phi, wnu=w, eps=eps,
+                          B=np.concatenate(Bs), n_core=int(n_core),
+                          name=(f"{nb} spheres r_out={r_out:g} nd {nd_lo}..{nd_hi} nf={nf} "
+                                f"n_core={n_core} seed={seed}"))
+
+
 def random_slab(nd=9, nf=3, seed=0, tau_lo=1e-3, tau_hi=1e2, q_sigma=0.7,
                 s_lo=0.2, s_hi=2.0):
     """Small slab with random opacity ratios and a random positive source per
