@@ -61,6 +61,10 @@ def parse():
     ap.add_argument("--graph-chunk", type=int, default=25,
                     help="ALI iterations per captured graph in the graph-mode timing (0: skip)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_fs_profile_c3a.json"))
+    ap.add_argument("--workload", choices=["c3a", "spherical"], default="c3a",
+                    help="c3a: the plane-parallel batch (default, the headline line); "
+                         "spherical: the same batch shape as spheres (1D spherical symmetry)")
+    ap.add_argument("--sph-cpu-sample", type=int, default=8, help="spheres in the CPU sample")
     return ap.parse_args()
 
 
@@ -103,6 +107,9 @@ def main():
               "shards over atmospheres or frequencies without communication but no multi-GPU "
               "run is part of this build", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "spherical":
+        bench_spherical(args)
+        return
     import torch
     from paper_0903_1949_amd import pprt
     from paper_0903_1949_amd import workloads as W
@@ -253,6 +260,161 @@ def main():
         "fp64_plain": fp64,
         "speedup_vs_fp64_plain": (value / fp64["value"]) if fp64 else None,
         "fp32_vs_fp64": {"S_after_one_step_rel": rel_step, "update_rel": rel_update},
+    }
+    print(json.dumps(line), flush=True)
+
+
+# Spherical sweep, FP32 flops per (ray, shell, frequency) crossing: the
+# 12 of one direction as above, both directions -> 24; plus, per outward
+# segment of a tangent ray, the round trip through its tangent point:
+# gamma (1), E^2 (1), e E^2 gamma (2), psi - that (1), alpha (1), the weighted
+# term to the next node (2), E <- e E (1), accumulation (1) -> 10.
+SPH_FLOPS_PER_POINT = 24.0
+SPH_FLOPS_PER_TANGENT_SEGMENT = 10.0
+
+
+def sph_cpu_baseline(c, S_trial, n_core, nsample):
+    """The spherical oracle (numpy FP64, one thread): one ALI step for
+    `nsample` spheres spread over the shell-count range."""
+    from threadpoolctl import threadpool_limits
+    from oracle import spherical
+    order = np.argsort(c.nd)
+    idx = order[np.linspace(0, c.nb - 1, nsample).astype(int)]
+    pts = 0
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        for b in idx:
+            s = c.rows(int(b))
+            spherical.two_level_ali_sph(c.r[s], c.tau[s], c.q[s], c.phi, c.wnu, float(c.eps[b]),
+                                        c.B[s], n_core, tol=0.0, max_iter=1, S0=S_trial[s])
+            n = int(c.nd[b])
+            pts += (n_core * n + n * (n + 1) // 2) * c.nf
+        dt = time.perf_counter() - t0
+    return {"value": pts / dt, "unit": "pts/s", "cores": 1, "kind": "oracle",
+            "sample": f"one ALI step of {len(idx)} of the {c.nb} spheres (nd {int(c.nd[idx].min())}.."
+                      f"{int(c.nd[idx].max())}, {pts} points), numpy FP64, 1 thread, {dt:.1f} s"}
+
+
+def bench_spherical(args):
+    """One two-level ALI step over 512 spheres: the ray-group sweep with the
+    fused profile quadratures, then the float64 update.  A point is one
+    (ray, shell, frequency) crossing, with both the inward and the outward
+    intensity."""
+    import torch
+    from paper_0903_1949_amd import pprt
+    from paper_0903_1949_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    n_core = 16
+    c = W.spherical_batch(nb=512, nd_lo=48, nd_hi=256, nf=1024, n_core=n_core, r_out=2.0,
+                          tau_lo=1e-4, tau_hi=1e8, eps_lo=1e-6, eps_hi=1e-1, seed=3)
+    nd = c.nd.astype(np.int64)
+    pairs = n_core * nd + nd * (nd + 1) // 2
+    pts = int(pairs.sum()) * c.nf
+    flops = (SPH_FLOPS_PER_POINT * pairs.sum() +
+             SPH_FLOPS_PER_TANGENT_SEGMENT * (nd * (nd - 1) // 2).sum()) * c.nf
+    S_trial = np.empty_like(c.tau)
+    for b in range(c.nb):
+        s = c.rows(b)
+        e = float(c.eps[b])
+        S_trial[s] = 1.0 - (1.0 - math.sqrt(e)) * np.exp(-math.sqrt(3.0 * e) * c.tau[s])
+    ctx = pprt.Context(0)
+    stream = torch.cuda.current_stream()
+
+    def upload(prec):
+        dt = torch.float64 if prec == pprt.FP64 else torch.float32
+        dev = lambda a, d: torch.as_tensor(np.ascontiguousarray(a), dtype=d, device="cuda:0")
+        return dict(tau=dev(c.tau, torch.float64), q=dev(c.q, dt), eps=dev(c.eps, torch.float64),
+                    B=dev(c.B, torch.float64), wphi=dev(c.wnu * c.phi, dt),
+                    S=dev(S_trial, torch.float64))
+
+    t_plan = time.perf_counter()
+    plan = pprt.SphPlan(ctx, c.nd, c.nf, c.r, n_core, precision=pprt.FP32)
+    t_plan = time.perf_counter() - t_plan
+    d = upload(pprt.FP32)
+    S0 = d["S"].clone()
+    mx = torch.zeros(c.nb, dtype=torch.float64, device="cuda:0")
+
+    def step(ev0=None, ev1=None):
+        if ev0 is not None:
+            ev0.record(stream)
+        plan.two_level_moments(d["tau"], d["q"], d["S"], d["eps"], d["B"], d["wphi"])
+        if ev1 is not None:
+            ev1.record(stream)
+        plan.two_level_update(d["S"], d["eps"], d["B"], d["wphi"], mx)
+
+    # FP32 vs FP64 difference of one step from the same S (not timed)
+    step()
+    torch.cuda.synchronize()
+    S32 = d["S"].clone()
+    plan64 = pprt.SphPlan(ctx, c.nd, c.nf, c.r, n_core, precision=pprt.FP64)
+    d64 = upload(pprt.FP64)
+    mx64 = torch.zeros_like(mx)
+    plan64.two_level_ali_step(d64["tau"], d64["q"], d64["S"], d64["eps"], d64["B"], d64["wphi"], mx64)
+    torch.cuda.synchronize()
+    rel_step = float(((S32 - d64["S"]).abs() / d64["S"].abs()).max())
+    d["S"].copy_(S0)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e0, e1 in evs:
+        step(e0, e1)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    k_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
+    value = pts / (wall / args.steps)
+    print(f"[spherical] {args.steps} steps, {ms_per_step:.3f} ms/step, sweep {k_ms:.3f} ms",
+          file=sys.stderr, flush=True)
+
+    fp64 = None
+    if not args.no_fp64:
+        d64["S"].copy_(S0)
+        plan64.two_level_ali_step(d64["tau"], d64["q"], d64["S"], d64["eps"], d64["B"], d64["wphi"], mx64)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.fp64_steps):
+            plan64.two_level_ali_step(d64["tau"], d64["q"], d64["S"], d64["eps"], d64["B"],
+                                      d64["wphi"], mx64)
+        torch.cuda.synchronize()
+        w64 = (time.perf_counter() - t1) / args.fp64_steps
+        fp64 = {"value": pts / w64, "ms_per_step": w64 * 1e3,
+                "desc": "the same step with the FP64 ray-group sweep (series / exp weights)"}
+
+    achieved = flops / (k_ms * 1e-3) / 1e12
+    peaks = ctx.measure_peaks()
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VALU_NONPACKED,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU_NONPACKED, 4),
+                "traffic": None, "kernel": "k_sph_fast<float,8,true>", "kernel_ms": round(k_ms, 5),
+                "flops_per_launch": flops,
+                "flops_per_point": SPH_FLOPS_PER_POINT,
+                "flops_per_tangent_segment": SPH_FLOPS_PER_TANGENT_SEGMENT,
+                "peak_measured": round(peaks["fp32_tflops"], 2),
+                "frac_of_measured": round(achieved / peaks["fp32_tflops"], 4)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = sph_cpu_baseline(c, S_trial, n_core, args.sph_cpu_sample)
+    line = {
+        "metric": "spherical formal-solution ray*shell*freq pts/s, batched FP32",
+        "value": value, "unit": "pts/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "512 two-level spheres (r_out = 2 r_core, tau 1e-4..1e8), nd "
+                               "U{48..256}, 16 core rays + one tangent ray per shell, nf 1024, "
+                               "eps 1e-6..1e-1, seed 3 (one ALI step per step)",
+                   "nbatch": c.nb, "rows": int(nd.sum()), "nf": c.nf, "n_core": n_core,
+                   "points_per_step": pts, "seed": 3, "plan_build_s": round(t_plan, 3),
+                   "group_size": 8},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "fp64": fp64,
+        "speedup_vs_fp64": (value / fp64["value"]) if fp64 else None,
+        "fp32_vs_fp64": {"S_after_one_step_rel": rel_step},
     }
     print(json.dumps(line), flush=True)
 

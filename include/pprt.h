@@ -392,7 +392,10 @@ pprt_status pprt_nlte_step(pprt_plan* plan, const pprt_fs_in* in, const pprt_ato
  * isotropic, [nb][nf]; the diffusion core uses B + mu (B - B_prev)/dtau_k
  * of the last radial layer with mu at the core.  Outputs J, JmS, lstar,
  * lstar_c, H ([rows][nf]).  r is a host array [rows], read during the call
- * only.  At most 65535 atmospheres and 1024 core rays per plan. */
+ * only.  At most 65535 atmospheres, 4096 shells each and 1024 core rays per
+ * plan.  A plan whose outputs are exactly JmS | LSTAR_C (what an ALI step
+ * needs) runs the ray-group sweep; other output sets the per-frequency
+ * sweep over single rays. */
 typedef struct pprt_sph_plan pprt_sph_plan;
 pprt_status pprt_sph_plan_create(pprt_ctx* ctx, int32_t nbatch, const int32_t* nd, int32_t nf,
                                  int32_t precision, int32_t lower_bc, uint32_t outputs,
@@ -412,6 +415,14 @@ pprt_status pprt_sph_plan_workspace_bytes(const pprt_sph_plan* plan, size_t* byt
 pprt_status pprt_sph_two_level_ali_step(pprt_sph_plan* plan, const pprt_fs_in* in,
                                         const pprt_two_level* atom, double* S, double* max_rel,
                                         const int32_t* active, void* workspace);
+/* The two halves of that step: the sweep, which leaves per 64-frequency tile
+ * the profile-weighted sums of J - S and 1 - Lambda* in the workspace, and
+ * the float64 update from them (same arguments as above). */
+pprt_status pprt_sph_two_level_moments(pprt_sph_plan* plan, const pprt_fs_in* in,
+                                       const pprt_two_level* atom, const double* S,
+                                       const int32_t* active, void* workspace);
+pprt_status pprt_sph_two_level_update(pprt_sph_plan* plan, const pprt_two_level* atom, double* S,
+                                      double* max_rel, const int32_t* active, void* workspace);
 
 /* ---- Voigt function ----------------------------------------------------
  * H(a, x) = Re w(x + i a), w the Faddeeva function, for a >= 0, by the

@@ -96,46 +96,6 @@ __device__ __forceinline__ void layer_w(double dt, double inv_dt, double /*c*/, 
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 
-// ---- wave-wide sums (deterministic order) ---------------------------------
-template <int CTRL>
-__device__ __forceinline__ float dpp_f(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
-}
-template <int CTRL>
-__device__ __forceinline__ double dpp_d(double v) {
-  const long long u = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xffffffffll), CTRL, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, 0xf, 0xf, false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ __forceinline__ float readlane(float v, int l) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
-__device__ __forceinline__ double readlane(double v, int l) {
-  const long long u = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffll), l);
-  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// Sum over the 64 lanes of a wave; every lane must be active.  Within each
-// row of 16 lanes: quad swaps, half-row mirror, row mirror; then the four row
-// sums are added in a fixed order.  The result is uniform over the wave.
-__device__ __forceinline__ float wave_sum(float v) {
-  v += dpp_f<0xb1>(v);    // quad_perm [1,0,3,2]
-  v += dpp_f<0x4e>(v);    // quad_perm [2,3,0,1]
-  v += dpp_f<0x141>(v);   // row_half_mirror
-  v += dpp_f<0x140>(v);   // row_mirror
-  return (readlane(v, 0) + readlane(v, 16)) + (readlane(v, 32) + readlane(v, 48));
-}
-__device__ __forceinline__ double wave_sum(double v) {
-  v += dpp_d<0xb1>(v);
-  v += dpp_d<0x4e>(v);
-  v += dpp_d<0x141>(v);
-  v += dpp_d<0x140>(v);
-  return (readlane(v, 0) + readlane(v, 16)) + (readlane(v, 32) + readlane(v, 48));
-}
-
 // Quad-local swaps (lanes 4q..4q+3): partner 1 and partner 2.
 __device__ __forceinline__ float dpp_quad_swap1(float v) { return dpp_f<0xb1>(v); }
 __device__ __forceinline__ float dpp_quad_swap2(float v) { return dpp_f<0x4e>(v); }

@@ -1299,6 +1299,13 @@ struct pprt_sph_plan {
   double* d_tab = nullptr;     // [3][entries]: path factor | half weight | mu
   int64_t entries = 0;
   int32_t nrays = 0;
+  // ray-group sweep (two-level step, and J - S / 1 - Lambda* formal solutions)
+  int G = 0, ntiles = 0, wpb = 0, nblocks = 0, ndmax = 0;
+  int32_t* d_grp0 = nullptr;   // [nb+1]
+  int64_t* d_gtab = nullptr;   // [ngroups]
+  void* d_gt = nullptr;        // group tables, plan precision
+  void* d_muc = nullptr;       // [nb][nc], plan precision
+  SphItem* d_items = nullptr;  // [nblocks * wpb]
 };
 
 extern "C" {
@@ -1315,6 +1322,8 @@ pprt_status pprt_sph_plan_create(pprt_ctx* c, int32_t nb, const int32_t* nd, int
     return fail(c, PPRT_E_INVALID_ARG, "unknown lower boundary");
   if (n_core < 1 || n_core > 1024) return fail(c, PPRT_E_INVALID_ARG, "n_core must be in 1..1024");
   if (nb > 65535) return fail(c, PPRT_E_SHAPE, "at most 65535 spherical atmospheres per plan");
+  for (int b = 0; b < nb; ++b)
+    if (nd[b] > 4096) return fail(c, PPRT_E_SHAPE, "nd[%d] = %d: at most 4096 shells", b, nd[b]);
   const uint32_t allowed = PPRT_OUT_J | PPRT_OUT_JMS | PPRT_OUT_LSTAR | PPRT_OUT_LSTAR_C | PPRT_OUT_H;
   if (outputs & ~allowed) return fail(c, PPRT_E_UNSUPPORTED, "spherical plans give J, JmS, lstar, lstar_c and H");
   for (int b = 0; b < nb; ++b)
@@ -1330,6 +1339,11 @@ pprt_status pprt_sph_plan_create(pprt_ctx* c, int32_t nb, const int32_t* nd, int
   std::vector<int32_t> ray0(nb + 1, 0);
   std::vector<SphRay> rays;
   std::vector<double> pf, hw, muv;
+  const int G = sph_group_size(precision);
+  std::vector<int32_t> grp0(nb + 1, 0);
+  std::vector<int64_t> gtab;
+  std::vector<double> gt, muc;
+  std::vector<int64_t> work(nb, 0);
   for (int b = 0; b < nb; ++b) {
     const double* rb = r + p->off[b];
     const int n = nd[b];
@@ -1386,6 +1400,26 @@ pprt_status pprt_sph_plan_create(pprt_ctx* c, int32_t nb, const int32_t* nd, int
         muv.push_back(mu[(size_t)d * nr + j]);
       }
       rays.push_back(ry);
+      work[b] += m + 1;
+      if (ry.core) muc.push_back(ry.mu_core);
+    }
+    // ray groups: rows d = 0..deepest shell, each [path | 1/path | half weight] x G
+    grp0[b] = (int32_t)gtab.size();
+    for (int j0 = 0; j0 < nr; j0 += G) {
+      const int mx = std::min(n - 1, n_core + n - 1 - j0);
+      gtab.push_back((int64_t)gt.size());
+      const size_t base = gt.size();
+      gt.resize(base + (size_t)(mx + 1) * 3 * G, 0.0);
+      for (int g = 0; g < G && j0 + g < nr; ++g) {
+        const SphRay& ry = rays[ray0[b] + j0 + g];
+        for (int d = 0; d <= ry.m && d <= mx; ++d) {
+          const double pfd = pf[ry.e0 + d];
+          double* row = &gt[base + (size_t)d * 3 * G];
+          row[g] = pfd;
+          row[G + g] = pfd > 0.0 ? 1.0 / pfd : 0.0;
+          row[2 * G + g] = hw[ry.e0 + d];
+        }
+      }
     }
     if (pf.size() > (size_t)INT32_MAX) {
       delete p;
@@ -1393,7 +1427,41 @@ pprt_status pprt_sph_plan_create(pprt_ctx* c, int32_t nb, const int32_t* nd, int
     }
   }
   ray0[nb] = (int32_t)rays.size();
+  grp0[nb] = (int32_t)gtab.size();
   p->nrays = (int32_t)rays.size();
+  // work list of the group sweep: one wave per (sphere, 64-frequency tile),
+  // spheres by decreasing work.  From 16 spheres on, the tiles of a sphere go
+  // to blocks on one XCD (block i runs on XCD i mod 8), so the sphere's ray
+  // tables are read into one L2.
+  p->G = G;
+  p->ntiles = (nf + 63) / 64;
+  p->ndmax = *std::max_element(nd, nd + nb);
+  const size_t es = precision == PPRT_FP64 ? sizeof(double) : sizeof(float);
+  p->wpb = (int)std::max<size_t>(1, std::min<size_t>(4, 65536 / (2 * (size_t)p->ndmax * es)));
+  std::vector<int> order(nb);
+  for (int b = 0; b < nb; ++b) order[b] = b;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
+  const int nbk = (p->ntiles + p->wpb - 1) / p->wpb;       // blocks per sphere
+  std::vector<SphItem> items;
+  if (nb >= 16) {
+    const int noct = (nb + 7) / 8;
+    p->nblocks = 8 * nbk * noct;
+    items.assign((size_t)p->nblocks * p->wpb, SphItem{-1, 0});
+    for (int s_ = 0; s_ < nb; ++s_)
+      for (int blk = 0; blk < nbk; ++blk) {
+        const int64_t pid = 8 * ((int64_t)nbk * (s_ / 8) + blk) + s_ % 8;
+        for (int w_ = 0; w_ < p->wpb; ++w_) {
+          const int t = blk * p->wpb + w_;
+          if (t < p->ntiles) items[pid * p->wpb + w_] = SphItem{order[s_], t};
+        }
+      }
+  } else {
+    p->nblocks = nb * nbk;
+    items.assign((size_t)p->nblocks * p->wpb, SphItem{-1, 0});
+    for (int s_ = 0; s_ < nb; ++s_)
+      for (int t = 0; t < p->ntiles; ++t)
+        items[((size_t)s_ * nbk + t / p->wpb) * p->wpb + t % p->wpb] = SphItem{order[s_], t};
+  }
   p->entries = (int64_t)pf.size();
   std::vector<double> tab(3 * pf.size());
   std::copy(pf.begin(), pf.end(), tab.begin());
@@ -1407,6 +1475,23 @@ pprt_status pprt_sph_plan_create(pprt_ctx* c, int32_t nb, const int32_t* nd, int
   if (e == hipSuccess) e = hipMemcpy(p->d_ray0, ray0.data(), ray0.size() * sizeof(int32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->d_rays, rays.data(), rays.size() * sizeof(SphRay), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->d_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice);
+  // group tables and core mu in the plan precision
+  auto upload_t = [&](const std::vector<double>& v, void** dst) -> hipError_t {
+    hipError_t r = hipMalloc(dst, std::max<size_t>(1, v.size()) * es);
+    if (r != hipSuccess) return r;
+    if (precision == PPRT_FP64) return hipMemcpy(*dst, v.data(), v.size() * es, hipMemcpyHostToDevice);
+    std::vector<float> f(v.begin(), v.end());
+    return hipMemcpy(*dst, f.data(), f.size() * es, hipMemcpyHostToDevice);
+  };
+  if (e == hipSuccess) e = upload_t(gt, &p->d_gt);
+  if (e == hipSuccess) e = upload_t(muc, &p->d_muc);
+  if (e == hipSuccess) e = hipMalloc(&p->d_grp0, grp0.size() * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc(&p->d_gtab, gtab.size() * sizeof(int64_t));
+  if (e == hipSuccess) e = hipMalloc(&p->d_items, items.size() * sizeof(SphItem));
+  if (e == hipSuccess) e = hipMemcpy(p->d_grp0, grp0.data(), grp0.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->d_gtab, gtab.data(), gtab.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_items, items.data(), items.size() * sizeof(SphItem), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     pprt_sph_plan_destroy(p);
     return hip_check(c, e, "spherical plan metadata");
@@ -1421,6 +1506,11 @@ void pprt_sph_plan_destroy(pprt_sph_plan* p) {
   if (p->d_ray0) (void)hipFree(p->d_ray0);
   if (p->d_rays) (void)hipFree(p->d_rays);
   if (p->d_tab) (void)hipFree(p->d_tab);
+  if (p->d_grp0) (void)hipFree(p->d_grp0);
+  if (p->d_gtab) (void)hipFree(p->d_gtab);
+  if (p->d_gt) (void)hipFree(p->d_gt);
+  if (p->d_muc) (void)hipFree(p->d_muc);
+  if (p->d_items) (void)hipFree(p->d_items);
   delete p;
 }
 
@@ -1449,6 +1539,22 @@ pprt_status sph_launch(pprt_sph_plan* p, const pprt_fs_in* in, const double* Sl,
   return hip_check(p->ctx, launch_fs_sph(p->precision, p->nb, p->nf, p->ctx->stream, &a),
                    "spherical formal-solution launch");
 }
+// Ray-group sweep: the columns JmS, Lc (formal solution) or, with wphi and
+// part, the tiles' profile-quadrature partials (two-level step).
+template <typename T>
+pprt_status sph_fast_launch(pprt_sph_plan* p, const pprt_fs_in* in, const double* Sl, const double* Bl,
+                            const int32_t* active, const void* wphi, T* JmS, T* Lc, T* part) {
+  SphFastArgs<T> a{};
+  a.items = p->d_items; a.off = p->d_off; a.grp0 = p->d_grp0; a.gtab = p->d_gtab;
+  a.tab = (const T*)p->d_gt; a.muc = (const T*)p->d_muc;
+  a.tau = in->tau; a.q = (const T*)in->q; a.Sg = Sl ? nullptr : (const T*)in->Sg; a.Sl = Sl;
+  a.Itop = (const T*)in->Itop; a.Bbot = (const T*)in->Bbot; a.Bbot_prev = (const T*)in->Bbot_prev;
+  a.Bl = Bl; a.Ibot = (const T*)in->Ibot; a.active = active; a.wphi = (const T*)wphi;
+  a.JmS = JmS; a.Lc = Lc; a.part = part;
+  a.nf = p->nf; a.ntiles = p->ntiles; a.lower_bc = p->lower_bc; a.n_core = p->nc; a.ndmax = p->ndmax;
+  return hip_check(p->ctx, launch_sph_fast(p->precision, p->nblocks, p->wpb, p->ctx->stream, &a),
+                   "spherical ray-group sweep launch");
+}
 }  // namespace
 
 extern "C" {
@@ -1468,6 +1574,13 @@ pprt_status pprt_sph_formal_solution(pprt_sph_plan* p, const pprt_fs_in* in, ppr
   for (auto& r : req)
     if ((o & r.bit) && !r.ptr) return fail(c, PPRT_E_INVALID_ARG, "output %s requested but NULL", r.name);
   auto pick = [&](uint32_t bit, void* ptr) { return (o & bit) ? ptr : nullptr; };
+  if (o == (PPRT_OUT_JMS | PPRT_OUT_LSTAR_C)) {        // what an ALI step consumes: ray-group sweep
+    if (p->precision == PPRT_FP64)
+      return sph_fast_launch<double>(p, in, nullptr, nullptr, nullptr, nullptr, (double*)out->JmS,
+                                     (double*)out->lstar_c, nullptr);
+    return sph_fast_launch<float>(p, in, nullptr, nullptr, nullptr, nullptr, (float*)out->JmS,
+                                  (float*)out->lstar_c, nullptr);
+  }
   if (p->precision == PPRT_FP64)
     return sph_launch<double>(p, in, nullptr, nullptr, nullptr, (double*)pick(PPRT_OUT_J, out->J), (double*)pick(PPRT_OUT_JMS, out->JmS),
                               (double*)pick(PPRT_OUT_LSTAR, out->lstar), (double*)pick(PPRT_OUT_LSTAR_C, out->lstar_c),
@@ -1480,36 +1593,45 @@ pprt_status pprt_sph_formal_solution(pprt_sph_plan* p, const pprt_fs_in* in, ppr
 pprt_status pprt_sph_plan_workspace_bytes(const pprt_sph_plan* p, size_t* bytes) {
   if (!p || !bytes) return PPRT_E_INVALID_ARG;
   const size_t es = p->precision == PPRT_FP64 ? sizeof(double) : sizeof(float);
-  *bytes = 2 * align256((size_t)p->rows * p->nf * es) + align256((size_t)p->rows * 4 * sizeof(double));
+  *bytes = align256((size_t)p->rows * p->ntiles * 4 * es);
   return PPRT_OK;
+}
+
+pprt_status pprt_sph_two_level_moments(pprt_sph_plan* p, const pprt_fs_in* in, const pprt_two_level* at,
+                                       const double* S, const int32_t* active, void* ws) {
+  if (!p) return PPRT_E_INVALID_ARG;
+  pprt_ctx* c = p->ctx;
+  if (!in || !at || !S) return fail(c, PPRT_E_INVALID_ARG, "null argument");
+  if (!in->tau || !in->q) return fail(c, PPRT_E_INVALID_ARG, "tau and q are required");
+  if (!at->B || !at->wphi) return fail(c, PPRT_E_INVALID_ARG, "atom needs B and wphi");
+  if (!ws) return fail(c, PPRT_E_WORKSPACE, "workspace required (pprt_sph_plan_workspace_bytes)");
+  return p->precision == PPRT_FP64
+             ? sph_fast_launch<double>(p, in, S, at->B, active, at->wphi, nullptr, nullptr, (double*)ws)
+             : sph_fast_launch<float>(p, in, S, at->B, active, at->wphi, nullptr, nullptr, (float*)ws);
+}
+
+pprt_status pprt_sph_two_level_update(pprt_sph_plan* p, const pprt_two_level* at, double* S, double* max_rel,
+                                      const int32_t* active, void* ws) {
+  if (!p) return PPRT_E_INVALID_ARG;
+  pprt_ctx* c = p->ctx;
+  if (!at || !S || !max_rel) return fail(c, PPRT_E_INVALID_ARG, "null argument");
+  if (!at->eps || !at->B) return fail(c, PPRT_E_INVALID_ARG, "atom needs eps and B");
+  if (!ws) return fail(c, PPRT_E_WORKSPACE, "workspace required (pprt_sph_plan_workspace_bytes)");
+  AliUpdateArgs u{};
+  u.off = p->d_off; u.part = ws; u.eps = at->eps; u.B = at->B; u.S = S; u.max_rel = max_rel;
+  u.active = const_cast<int32_t*>(active); u.iters = nullptr; u.status = c->d_status; u.tol = 0.0;
+  u.nw = p->ntiles; u.nb = p->nb; u.part_fp64 = p->precision == PPRT_FP64 ? 1 : 0;
+  return hip_check(c, launch_ali_update(p->nb, c->stream, u), "ALI update launch");
 }
 
 pprt_status pprt_sph_two_level_ali_step(pprt_sph_plan* p, const pprt_fs_in* in, const pprt_two_level* at,
                                         double* S, double* max_rel, const int32_t* active, void* ws) {
   if (!p) return PPRT_E_INVALID_ARG;
-  pprt_ctx* c = p->ctx;
-  if (!in || !at || !S || !max_rel) return fail(c, PPRT_E_INVALID_ARG, "null argument");
-  if (!in->tau || !in->q) return fail(c, PPRT_E_INVALID_ARG, "tau and q are required");
-  if (!at->eps || !at->B || !at->wphi) return fail(c, PPRT_E_INVALID_ARG, "atom needs eps, B and wphi");
-  if (!ws) return fail(c, PPRT_E_WORKSPACE, "workspace required (pprt_sph_plan_workspace_bytes)");
-  const size_t es = p->precision == PPRT_FP64 ? sizeof(double) : sizeof(float);
-  const size_t arr = align256((size_t)p->rows * p->nf * es);
-  char* base = (char*)ws;
-  void* JmS = base;
-  void* Lc = base + arr;
-  double* part = (double*)(base + 2 * arr);
-  pprt_status r = p->precision == PPRT_FP64
-                      ? sph_launch<double>(p, in, S, at->B, active, nullptr, (double*)JmS, nullptr, (double*)Lc, nullptr)
-                      : sph_launch<float>(p, in, S, at->B, active, nullptr, (float*)JmS, nullptr, (float*)Lc, nullptr);
+  if (!max_rel) return fail(p->ctx, PPRT_E_INVALID_ARG, "null argument");
+  if (at && !at->eps) return fail(p->ctx, PPRT_E_INVALID_ARG, "atom needs eps, B and wphi");
+  const pprt_status r = pprt_sph_two_level_moments(p, in, at, S, active, ws);
   if (r != PPRT_OK) return r;
-  r = hip_check(c, launch_profile_reduce(p->precision, S, JmS, Lc, nullptr, nullptr, at->wphi, part, p->rows,
-                                         p->nf, c->stream), "profile reduction");
-  if (r != PPRT_OK) return r;
-  AliUpdateArgs u{};
-  u.off = p->d_off; u.part = part; u.eps = at->eps; u.B = at->B; u.S = S; u.max_rel = max_rel;
-  u.active = const_cast<int32_t*>(active); u.iters = nullptr; u.status = c->d_status; u.tol = 0.0;
-  u.nw = 1; u.nb = p->nb; u.part_fp64 = 1;
-  return hip_check(c, launch_ali_update(p->nb, c->stream, u), "ALI update launch");
+  return pprt_sph_two_level_update(p, at, S, max_rel, active, ws);
 }
 
 }  // extern "C"

@@ -13,6 +13,56 @@ namespace pprt {
 
 constexpr int kMaxNA = 32;
 
+// psi(x) = (1 - e^-x)/x for optically thin layers (0 <= x < 1/4), FP32: a
+// degree-4 polynomial fitted for least maximum relative error on [0, 1/4]
+// (Remez exchange; fitted error 2.5e-9, evaluated in FP32 4.5e-8).
+__device__ __forceinline__ float psi_thin_f32(float x) {
+  float p = fmaf(x, 7.510221563279629e-3f, -4.1488952934741974e-2f);
+  p = fmaf(x, p, 1.6665081679821014e-1f);
+  p = fmaf(x, p, -4.999994933605194e-1f);
+  return fmaf(x, p, 1.0f);
+}
+
+// ---- wave-wide sums (deterministic order) ---------------------------------
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xffffffffll), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float readlane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double readlane(double v, int l) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 64 lanes of a wave; every lane must be active.  Within each
+// row of 16 lanes: quad swaps, half-row mirror, row mirror; then the four row
+// sums are added in a fixed order.  The result is uniform over the wave.
+__device__ __forceinline__ float wave_sum(float v) {
+  v += dpp_f<0xb1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_f<0x4e>(v);    // quad_perm [2,3,0,1]
+  v += dpp_f<0x141>(v);   // row_half_mirror
+  v += dpp_f<0x140>(v);   // row_mirror
+  return (readlane(v, 0) + readlane(v, 16)) + (readlane(v, 32) + readlane(v, 48));
+}
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_d<0xb1>(v);
+  v += dpp_d<0x4e>(v);
+  v += dpp_d<0x141>(v);
+  v += dpp_d<0x140>(v);
+  return (readlane(v, 0) + readlane(v, 16)) + (readlane(v, 32) + readlane(v, 48));
+}
+
 // Angle constants of one plan, passed to kernels by value (kernel-argument
 // segment, read into scalar registers).  All per-angle, uniform over lanes.
 template <typename T>
@@ -186,6 +236,42 @@ struct SphArgs {
   int32_t nf, lower_bc;
 };
 hipError_t launch_fs_sph(int precision, int nb, int nf, hipStream_t s, const void* args);
+
+// Spherical two-level sweep (sph.hip): one wave per (sphere, 64-frequency
+// tile), rays in groups of sph_group_size() held in registers.
+struct SphItem {
+  int32_t b;       // sphere (-1: idle wave)
+  int32_t tile;    // 64-frequency tile
+};
+template <typename T>
+struct SphFastArgs {
+  const SphItem* items;     // [nblocks * waves per block], block order
+  const int64_t* off;       // [nb+1]
+  const int32_t* grp0;      // [nb+1] ray groups of sphere b: grp0[b] .. grp0[b+1]-1
+  const int64_t* gtab;      // [ngroups] start of the group's table in tab
+  const T* tab;             // per group [deepest shell + 1][3][G]: path factor of the
+                            // segment to the next shell inward, its reciprocal, half
+                            // weight in mu (zero where the ray misses the shell)
+  const T* muc;             // [nb][n_core] mu at the core of core ray c
+  const double* tau;
+  const T* q;
+  const T* Sg;              // [rows][nf] source per frequency (formal solution)
+  const double* Sl;         // [rows] line source (two-level step)
+  const T* Itop;            // [nb][nf] or nullptr
+  const T* Bbot;            // [nb][nf] diffusion core (when Bl == nullptr)
+  const T* Bbot_prev;
+  const double* Bl;         // [rows] B per row (two-level step) or nullptr
+  const T* Ibot;            // [nb][nf] given core intensity
+  const int32_t* active;    // [nb] or nullptr
+  const T* wphi;            // [nf] profile weights (two-level step)
+  T* JmS;                   // [rows][nf] J - S (formal solution)
+  T* Lc;                    // [rows][nf] 1 - Lambda* (formal solution)
+  T* part;                  // [rows][ntiles][2][2] (two-level step) or nullptr
+  int32_t nf, ntiles, lower_bc, n_core, ndmax;
+};
+int sph_group_size(int precision);
+size_t sph_fast_lds_bytes(int precision, int wpb, int ndmax);
+hipError_t launch_sph_fast(int precision, int nblocks, int wpb, hipStream_t s, const void* args);
 
 // Weideman's expansion of the Faddeeva function (nlte.hip): N terms.
 constexpr int kVoigtN = 40;

@@ -25,6 +25,9 @@
 // one after another and accumulates J, J - S, H, Lambda* and 1 - Lambda* of
 // every shell it crosses in the output arrays (each lane owns its frequency
 // column, so the read-modify-writes never collide).
+#include <type_traits>
+#include <utility>
+
 #include "pprt_internal.h"
 
 namespace pprt {
@@ -168,7 +171,354 @@ __global__ __launch_bounds__(256) void k_fs_sph(SphArgs<T> a) {
   }
 }
 
+// ---- sweep with rays in register groups ---------------------------------------
+//
+// One wave per (sphere, 64-frequency tile); lane = frequency.  The wave takes
+// the sphere's rays G at a time.  Rays are ordered by impact parameter: the
+// n_core core rays (deepest shell nd-1), then the tangent rays of shells
+// nd-1, nd-2, ..., 0.  Ray g of group j (global index jG + g) therefore crosses
+// shell d exactly when g <= T(d) = n_core + nd - 1 - d - jG, turns at its
+// tangent point when g == T(d), and a whole group is inside every shell with
+// T(d) >= G: each of the group's conditions is one comparison with T(d), and
+// all but the last G shells of a group run without any.
+//
+// Per ray the wave keeps in registers the difference-form intensity
+// D = I - S, the last inward psi (the outward start value of a tangent ray)
+// and the transmission E from the tangent point (the round trip of Lambda*).
+// q and S of a shell are read once per group; the group's geometry row
+// (path factor, its reciprocal, half weight) comes through scalar loads.  Each
+// shell's contribution of the group is added once: to the J - S and
+// 1 - Lambda* columns (formal solution), or, for the two-level step, already
+// summed over the wave's frequencies with the profile weights into the
+// wave's per-shell totals in LDS, which end as the tile's partial sums for the
+// float64 update.
+
+// A load from an address that is uniform over the wave, issued as a scalar load.
+template <typename T>
+__device__ __forceinline__ T sload(const T* p, int64_t i) {
+  return ((const __attribute__((address_space(4))) T*)p)[i];
+}
+
+// f(integral_constant<int, g>) for g = 0..N-1, unrolled in the source so that
+// every per-ray register is a separate value.
+template <typename F, int... I>
+__device__ __forceinline__ void for_rays_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void for_rays(F&& f) {
+  for_rays_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+constexpr float kLog2e = 1.4426950408889634f;
+
+// One segment of the difference-form update D <- e D + psi dS, FP32.
+// Thin (x < 1/4): psi from the fitted polynomial and D + psi (dS - x D), the
+// same update with 1 - e = x psi; thick: e = 2^(-x log2 e) and psi = m - e m,
+// m = 1/x = rq * ip (rq = 1/(qbar dtau_ref), ip = 1/path factor).  The regime
+// is chosen per wave; when the lanes disagree both forms run.
+template <bool NEED_E>
+__device__ __forceinline__ void seg_update(float x, float rq, float ip, float dS, float& D,
+                                           float& ps, float& e) {
+  const unsigned long long act = __ballot(1);
+  const unsigned long long tb = __ballot(x < 0.25f);
+  float Dn, pn, en = 0.0f;
+  if (tb == act) {
+    pn = psi_thin_f32(x);
+    if (NEED_E) en = fmaf(-x, pn, 1.0f);
+    Dn = fmaf(pn, fmaf(-x, D, dS), D);
+  } else if (tb == 0) {
+    en = __builtin_amdgcn_exp2f(-(x * kLog2e));
+    const float m = rq * ip;
+    pn = fmaf(-en, m, m);
+    Dn = fmaf(en, D, pn * dS);
+  } else {
+    const float p1 = psi_thin_f32(x);
+    const float D1 = fmaf(p1, fmaf(-x, D, dS), D);
+    const float e2 = __builtin_amdgcn_exp2f(-(x * kLog2e));
+    const float m = rq * ip;
+    const float p2 = fmaf(-e2, m, m);
+    const float D2 = fmaf(e2, D, p2 * dS);
+    const bool thin = x < 0.25f;
+    pn = thin ? p1 : p2;
+    Dn = thin ? D1 : D2;
+    if (NEED_E) en = thin ? fmaf(-x, p1, 1.0f) : e2;
+  }
+  D = Dn;
+  ps = pn;
+  if (NEED_E) e = en;
+}
+
+// FP64: psi by its series for thin segments (x < 1/4, 13 terms, truncation
+// below 1e-17), else e = exp(-x), psi = (1 - e)/x.
+template <bool NEED_E>
+__device__ __forceinline__ void seg_update(double x, double rq, double ip, double dS, double& D,
+                                           double& ps, double& e) {
+  double pn, en;
+  if (x < 0.25) {
+    // psi = sum_{n=0}^{12} (-x)^n / (n+1)!
+    double p = 1.0 / 6227020800.0;                    // 1/13!
+    p = fma(p, -x, 1.0 / 479001600.0);
+    p = fma(p, -x, 1.0 / 39916800.0);
+    p = fma(p, -x, 1.0 / 3628800.0);
+    p = fma(p, -x, 1.0 / 362880.0);
+    p = fma(p, -x, 1.0 / 40320.0);
+    p = fma(p, -x, 1.0 / 5040.0);
+    p = fma(p, -x, 1.0 / 720.0);
+    p = fma(p, -x, 1.0 / 120.0);
+    p = fma(p, -x, 1.0 / 24.0);
+    p = fma(p, -x, 1.0 / 6.0);
+    p = fma(p, -x, 0.5);
+    pn = fma(p, -x, 1.0);
+    en = fma(-x, pn, 1.0);
+  } else {
+    en = exp(-x);
+    pn = (1.0 - en) * (rq * ip);
+  }
+  D = fma(en, D, pn * dS);
+  ps = pn;
+  e = en;
+}
+
+__device__ __forceinline__ float recip_t(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip_t(double x) { return 1.0 / x; }
+
+template <typename T, int G, bool PART>
+__global__ __launch_bounds__(256) void k_sph_fast(SphFastArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char sph_lds[];
+  const int lane = (int)(threadIdx.x & 63);
+  const int wave = (int)(threadIdx.x >> 6);
+  const SphItem it = a.items[(int64_t)blockIdx.x * (blockDim.x >> 6) + wave];
+  const int b = __builtin_amdgcn_readfirstlane(it.b);
+  if (b < 0) return;
+  if (a.active != nullptr && a.active[b] == 0) return;
+  const int tile = __builtin_amdgcn_readfirstlane(it.tile);
+  const int nf = a.nf;
+  const int k = tile * 64 + lane;
+  const bool ok = k < nf;
+  const int kk = ok ? k : nf - 1;                   // clamped: loads stay in bounds
+  const int64_t o = a.off[b];
+  const int nd = (int)(a.off[b + 1] - o);
+  const int nc = a.n_core;
+  const T* __restrict__ qc = a.q + kk;
+  auto q_at = [&](int d) -> T { return qc[(o + d) * nf]; };
+  auto S_at = [&](int d) -> T { return PART ? T(a.Sl[o + d]) : a.Sg[(o + d) * nf + kk]; };
+  const T wp = PART ? (ok ? a.wphi[kk] : T(0)) : T(0);
+  T* acc = PART ? reinterpret_cast<T*>(sph_lds) + (int64_t)wave * 2 * a.ndmax : nullptr;
+  if (PART) {
+    for (int d = lane; d < 2 * a.ndmax; d += 64) acc[d] = T(0);
+  }
+  // one shell's contribution of the current group
+  auto flush = [&](int d, T vj, T vl, bool store) {
+    if (PART) {
+      const T sj = wave_sum(wp * vj);
+      const T sl = wave_sum(wp * vl);
+      if (lane == 0) {
+        atomicAdd(acc + d, sj);
+        atomicAdd(acc + a.ndmax + d, sl);
+      }
+    } else if (ok) {
+      const int64_t x = (o + d) * nf + kk;
+      if (store) {
+        a.JmS[x] = vj;
+        a.Lc[x] = vl;
+      } else {
+        a.JmS[x] += vj;
+        a.Lc[x] += vl;
+      }
+    }
+  };
+  const T Itop = a.Itop ? a.Itop[(int64_t)b * nf + kk] : T(0);
+  // core intensity I(mu) = Ic0 + mu Ic1
+  T Ic0, Ic1 = T(0);
+  if (a.lower_bc == PPRT_BC_DIFFUSION) {
+    const T Bb = a.Bl ? T(a.Bl[o + nd - 1]) : a.Bbot[(int64_t)b * nf + kk];
+    const T Bp = a.Bl ? T(a.Bl[o + nd - 2]) : a.Bbot_prev[(int64_t)b * nf + kk];
+    const T dtl = T(0.5) * (q_at(nd - 2) + q_at(nd - 1)) * T(a.tau[o + nd - 1] - a.tau[o + nd - 2]);
+    Ic0 = Bb;
+    Ic1 = (Bb - Bp) / dtl;
+  } else {
+    Ic0 = a.Ibot ? a.Ibot[(int64_t)b * nf + kk] : T(0);
+  }
+  const T* muc = a.muc + (int64_t)b * nc;
+  const int gfirst = a.grp0[b], glast = a.grp0[b + 1];
+  for (int gi = gfirst; gi < glast; ++gi) {
+    const int jG = (gi - gfirst) * G;
+    const int Tb = nc + nd - 1 - jG;                // T(d) = Tb - d
+    const int mx = Tb < nd - 1 ? Tb : nd - 1;       // deepest shell of the group
+    const int ncg = nc - jG;                        // rays g < ncg are core rays
+    const bool first = gi == gfirst;                // its core rays reach every shell
+    const T* tb = a.tab + sload(a.gtab, gi);
+    T D[G], E[G], pl[G];
+    T pth[G], ipt[G], hw[G], hwn[G];
+    auto load_row = [&](int d, bool geo, bool wts) {
+      const T* row = tb + (int64_t)d * 3 * G;
+      for_rays<G>([&](auto gc) {
+        constexpr int g = decltype(gc)::value;
+        if (geo) {
+          pth[g] = sload(row, g);
+          ipt[g] = sload(row, G + g);
+        }
+        if (wts) hw[g] = sload(row, 2 * G + g);
+      });
+    };
+    // ---- inward: node 0, then segments d-1 -> d
+    T S0 = S_at(0), q0 = q_at(0);
+    {
+      load_row(0, false, true);
+      T hs = T(0);
+      const T D0 = Itop - S0;
+      for_rays<G>([&](auto gc) {
+        constexpr int g = decltype(gc)::value;
+        hs += hw[g];
+        D[g] = D0;
+        E[g] = T(1);
+        pl[g] = T(1);
+      });
+      flush(0, hs * D0, hs, first);
+    }
+    auto inward = [&](int d, auto cond) {
+      constexpr bool COND = decltype(cond)::value;
+      const T q1 = q_at(d), S1 = S_at(d);
+      const T qa = T(0.5) * (q0 + q1) * T(a.tau[o + d] - a.tau[o + d - 1]);
+      const T rq = recip_t(qa);
+      const T dS = S0 - S1;
+      load_row(d - 1, true, false);
+      load_row(d, false, true);
+      const int Td = Tb - d;
+      T aj = T(0), al = T(0);
+      for_rays<G>([&](auto gc) {
+        constexpr int g = decltype(gc)::value;
+        if (!COND || g <= Td) {
+          T ps, e;
+          seg_update<false>(qa * pth[g], rq, ipt[g], dS, D[g], ps, e);
+          if (COND && g == Td) pl[g] = ps;
+          aj = fma(hw[g], D[g], aj);
+          al = fma(hw[g], ps, al);
+        }
+      });
+      flush(d, aj, al, first);
+      q0 = q1;
+      S0 = S1;
+    };
+    const int dA = Tb - G;                          // T(d) >= G for d <= dA
+    {
+      const int e1 = dA < mx ? dA : mx;
+      int d = 1;
+      for (; d <= e1; ++d) inward(d, std::false_type{});
+      for (; d <= mx; ++d) inward(d, std::true_type{});
+    }
+    // ---- outward: turn at each ray's deepest shell, then segments d+1 -> d.
+    // The round trip of a tangent ray adds e_d E^2 gamma_d to node d and, unless
+    // node d+1 is its tangent node, E^2 alpha_d to node d+1 (taken from
+    // 1 - Lambda*), so node d+1 is added one shell late.
+    T Sn = S0, qn = q0;                              // node mx
+    T nj = T(0), nl = T(0);
+    {
+      load_row(mx, false, true);
+      const int Td = Tb - mx;
+      const T Sm = Sn;
+      for_rays<G>([&](auto gc) {
+        constexpr int g = decltype(gc)::value;
+        if (mx == nd - 1 ? g <= Td : g == Td) {
+          T pn = pl[g];
+          if (g < ncg) {
+            D[g] = Ic0 + muc[jG + g] * Ic1 - Sm;
+            pn = T(1);
+          }
+          nj = fma(hw[g], D[g], nj);
+          nl = fma(hw[g], pn, nl);
+        }
+        hwn[g] = hw[g];
+      });
+    }
+    auto outward = [&](int d, auto cond) {
+      constexpr bool COND = decltype(cond)::value;
+      const T Sd = S_at(d), qd = q_at(d);
+      const T qa = T(0.5) * (qd + qn) * T(a.tau[o + d + 1] - a.tau[o + d]);
+      const T rq = recip_t(qa);
+      const T dS = Sn - Sd;
+      load_row(d, true, true);
+      const int Td = Tb - d;
+      T aj = T(0), al = T(0);
+      for_rays<G>([&](auto gc) {
+        constexpr int g = decltype(gc)::value;
+        if (COND && g == Td) {                        // tangent point (d < nd-1 here)
+          aj = fma(hw[g], D[g], aj);
+          al = fma(hw[g], pl[g], al);
+        } else if (!COND || g < Td) {
+          T ps, e;
+          if (g < ncg) {
+            seg_update<false>(qa * pth[g], rq, ipt[g], dS, D[g], ps, e);
+            al = fma(hw[g], ps, al);
+          } else {
+            seg_update<true>(qa * pth[g], rq, ipt[g], dS, D[g], ps, e);
+            const T E2 = E[g] * E[g];
+            al = fma(hw[g], ps - e * (E2 * (ps - e)), al);
+            if (!COND || g < Td - 1) nl = fma(-hwn[g], E2 * (T(1) - ps), nl);
+            E[g] *= e;
+          }
+          aj = fma(hw[g], D[g], aj);
+        }
+        hwn[g] = hw[g];
+      });
+      flush(d + 1, nj, nl, false);
+      nj = aj;
+      nl = al;
+      Sn = Sd;
+      qn = qd;
+    };
+    {
+      // no condition where T(d+1) >= G (every ray has a segment and the
+      // round-trip term) and d <= nd - 2
+      int dB = dA - 1;
+      if (dB > nd - 2) dB = nd - 2;
+      if (dB < -1) dB = -1;
+      int d = mx - 1;
+      for (; d > dB; --d) outward(d, std::true_type{});
+      for (; d >= 0; --d) outward(d, std::false_type{});
+    }
+    flush(0, nj, nl, false);
+  }
+  if (PART) {
+    for (int d = lane; d < nd; d += 64) {
+      T* pp = a.part + ((o + d) * a.ntiles + tile) * 4;
+      pp[0] = acc[d];
+      pp[1] = acc[a.ndmax + d];
+      pp[2] = T(0);
+      pp[3] = T(0);
+    }
+  }
+}
+
 }  // namespace
+
+int sph_group_size(int precision) { return precision == PPRT_FP64 ? 4 : 8; }
+
+size_t sph_fast_lds_bytes(int precision, int wpb, int ndmax) {
+  return (size_t)wpb * 2 * ndmax * (precision == PPRT_FP64 ? sizeof(double) : sizeof(float));
+}
+
+hipError_t launch_sph_fast(int precision, int nblocks, int wpb, hipStream_t s, const void* args) {
+  if (nblocks <= 0) return hipSuccess;
+  const dim3 grid((unsigned)nblocks), block((unsigned)(64 * wpb));
+  if (precision == PPRT_FP64) {
+    const auto& a = *(const SphFastArgs<double>*)args;
+    if (a.part)
+      hipLaunchKernelGGL((k_sph_fast<double, 4, true>), grid, block,
+                         sph_fast_lds_bytes(precision, wpb, a.ndmax), s, a);
+    else
+      hipLaunchKernelGGL((k_sph_fast<double, 4, false>), grid, block, 0, s, a);
+  } else {
+    const auto& a = *(const SphFastArgs<float>*)args;
+    if (a.part)
+      hipLaunchKernelGGL((k_sph_fast<float, 8, true>), grid, block,
+                         sph_fast_lds_bytes(precision, wpb, a.ndmax), s, a);
+    else
+      hipLaunchKernelGGL((k_sph_fast<float, 8, false>), grid, block, 0, s, a);
+  }
+  return hipGetLastError();
+}
 
 hipError_t launch_fs_sph(int precision, int nb, int nf, hipStream_t s, const void* args) {
   const dim3 grid((unsigned)((nf + 255) / 256), (unsigned)nb);

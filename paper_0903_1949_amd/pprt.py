@@ -161,6 +161,8 @@ def load_library(path: str = LIB_PATH):
         "pprt_sph_formal_solution": (I, [P, C.POINTER(FsIn), C.POINTER(FsOut)]),
         "pprt_sph_plan_workspace_bytes": (I, [P, C.POINTER(C.c_size_t)]),
         "pprt_sph_two_level_ali_step": (I, [P, C.POINTER(FsIn), C.POINTER(TwoLevel), P, P, P, P]),
+        "pprt_sph_two_level_moments": (I, [P, C.POINTER(FsIn), C.POINTER(TwoLevel), P, P, P]),
+        "pprt_sph_two_level_update": (I, [P, C.POINTER(TwoLevel), P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -704,21 +706,42 @@ class SphPlan:
                         "sph_formal_solution")
         return out
 
-    def two_level_ali_step(self, tau, q, S, eps, B, wphi, max_rel, active=None, Itop=None, Ibot=None):
-        """pprt_sph_two_level_ali_step: one spherical formal solution + OS update, S in place."""
+    def _two_level(self, eps, B, wphi, S, active):
         import torch
-        fin = self.fs_in(tau, q, None, None, None, Itop, Ibot)
         self._want(eps, (self.nb,), torch.float64, "eps")
         self._want(B, (self.rows,), torch.float64, "B")
         self._want(wphi, (self.nf,), self.dtype, "wphi")
         self._want(S, (self.rows,), torch.float64, "S")
-        self._want(max_rel, (self.nb,), torch.float64, "max_rel")
         if active is not None:
             self._want(active, (self.nb,), torch.int32, "active")
-        at = TwoLevel(_ptr(eps), _ptr(B), _ptr(wphi))
+        return TwoLevel(_ptr(eps), _ptr(B), _ptr(wphi))
+
+    def two_level_ali_step(self, tau, q, S, eps, B, wphi, max_rel, active=None, Itop=None, Ibot=None):
+        """pprt_sph_two_level_ali_step: one spherical formal solution + OS update, S in place."""
+        import torch
+        fin = self.fs_in(tau, q, None, None, None, Itop, Ibot)
+        at = self._two_level(eps, B, wphi, S, active)
+        self._want(max_rel, (self.nb,), torch.float64, "max_rel")
         self.ctx._check(self.lib.pprt_sph_two_level_ali_step(
             self.h, C.byref(fin), C.byref(at), _ptr(S), _ptr(max_rel), _ptr(active),
             _ptr(self.workspace())), "sph_two_level_ali_step")
+
+    def two_level_moments(self, tau, q, S, eps, B, wphi, active=None, Itop=None, Ibot=None):
+        """pprt_sph_two_level_moments: the sweep half of the step."""
+        fin = self.fs_in(tau, q, None, None, None, Itop, Ibot)
+        at = self._two_level(eps, B, wphi, S, active)
+        self.ctx._check(self.lib.pprt_sph_two_level_moments(
+            self.h, C.byref(fin), C.byref(at), _ptr(S), _ptr(active), _ptr(self.workspace())),
+            "sph_two_level_moments")
+
+    def two_level_update(self, S, eps, B, wphi, max_rel, active=None):
+        """pprt_sph_two_level_update: the float64 update half of the step."""
+        import torch
+        at = self._two_level(eps, B, wphi, S, active)
+        self._want(max_rel, (self.nb,), torch.float64, "max_rel")
+        self.ctx._check(self.lib.pprt_sph_two_level_update(
+            self.h, C.byref(at), _ptr(S), _ptr(max_rel), _ptr(active), _ptr(self.workspace())),
+            "sph_two_level_update")
 
 
 class DeviceAtom:

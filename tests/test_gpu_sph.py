@@ -92,6 +92,57 @@ def test_sph_formal_solution_parity(gpu_ctx, precision, lower, r_out):
             assert e < (TOL_DIFF_FP32 if name in DIFF_KEYS else TOL[precision]), name
 
 
+@pytest.mark.parametrize("precision", [pprt.FP64, pprt.FP32], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("nb,n_core,lower", [(3, 8, pprt.BC_DIFFUSION), (19, 5, pprt.BC_DIFFUSION),
+                                             (4, 3, pprt.BC_GIVEN)], ids=["3sph", "19sph", "given"])
+def test_sph_group_sweep_parity(gpu_ctx, precision, nb, n_core, lower):
+    """J - S and 1 - Lambda* only: the ray-group sweep.  Shell counts from 6
+    (groups entirely within their last G shells) to 40, core-ray counts that
+    are not multiples of the group size, a ragged frequency tile, and with 19
+    spheres the XCD-grouped work list."""
+    c = W.spherical_batch(nb=nb, nd_lo=6, nd_hi=40, nf=150, n_core=n_core, tau_hi=1e8,
+                          B_slope=0.3, seed=13)
+    rng = np.random.default_rng(17)
+    rows, nf = c.tau.shape[0], c.nf
+    Sg = rng.uniform(0.5, 1.5, size=(rows, nf))
+    Itop = rng.uniform(0.0, 0.2, size=(nb, nf))
+    Bb = rng.uniform(1.0, 1.5, size=(nb, nf))
+    Bp = Bb * rng.uniform(0.8, 1.0, size=(nb, nf))
+    dt = torch.float64 if precision == pprt.FP64 else torch.float32
+    plan = pprt.SphPlan(gpu_ctx, c.nd, nf, c.r, c.n_core, precision=precision, lower_bc=lower,
+                        outputs=pprt.OUT_JMS | pprt.OUT_LSTAR_C)
+    kw = dict(Itop=_dev(Itop, dt))
+    if lower == pprt.BC_DIFFUSION:
+        kw.update(Bbot=_dev(Bb, dt), Bbot_prev=_dev(Bp, dt))
+    else:
+        kw.update(Ibot=_dev(Bb, dt))
+    print(f"  {c.name} precision={precision} lower={lower}", flush=True)
+    out = plan.formal_solution(_dev(c.tau, torch.float64), _dev(c.q, dt), _dev(Sg, dt), **kw)
+    torch.cuda.synchronize()
+    got = {k: v.double().cpu().numpy() for k, v in out.items()}
+    q = c.q
+    if precision == pprt.FP32:
+        q, Sg, Itop, Bb, Bp = (r32(x) for x in (q, Sg, Itop, Bb, Bp))
+    worst = {}
+    for b in range(nb):
+        s = c.rows(b)
+        ref = spherical.formal_solution_sph(
+            c.r[s], c.tau[s], q[s], Sg[s], c.n_core,
+            lower="diffusion" if lower == pprt.BC_DIFFUSION else "given",
+            Bbot=Bb[b], Bbot_prev=Bp[b], Itop=Itop[b])
+        worst["lstar_c"] = max(worst.get("lstar_c", 0.0), rel_err(got["lstar_c"][s], ref["lstar_c"]))
+        worst["JmS"] = max(worst.get("JmS", 0.0), rel_err(got["JmS"][s], ref["JmS"]))
+        e = float(np.max(np.abs(got["JmS"][s] - ref["JmS"])) / np.abs(ref["J"]).max())
+        worst["JmS_vs_J"] = max(worst.get("JmS_vs_J", 0.0), e)
+    print("  " + ", ".join(f"{k} {v:.2e}" for k, v in worst.items()), flush=True)
+    if precision == pprt.FP64:
+        assert max(worst.values()) < TOL[precision]
+    else:
+        assert worst["lstar_c"] < TOL[precision]
+        assert worst["JmS"] < TOL_DIFF_FP32
+        assert worst["JmS_vs_J"] < TOL_DIFF_OPERAND_FP32
+
+
 def test_sph_lstar_is_the_brute_force_diagonal(gpu_ctx):
     c = _case(nf=5, nb=1, nd_lo=9, nd_hi=9, n_core=4, seed=2)
     plan = pprt.SphPlan(gpu_ctx, c.nd, c.nf, c.r, c.n_core, precision=pprt.FP64,
@@ -112,9 +163,10 @@ def _ali_inputs(c, dt):
 
 
 @pytest.mark.parametrize("precision", [pprt.FP64, pprt.FP32], ids=["fp64", "fp32"])
-def test_sph_ali_steps_parity(gpu_ctx, precision):
-    c = W.spherical_batch(nb=3, nd_lo=16, nd_hi=28, nf=41, n_core=6, eps_lo=1e-4, eps_hi=1e-1,
-                          tau_hi=1e6, B_slope=0.3, seed=9)
+@pytest.mark.parametrize("nb,nd_lo,nd_hi,nf", [(3, 16, 28, 41), (17, 6, 20, 70)], ids=["3sph", "17sph"])
+def test_sph_ali_steps_parity(gpu_ctx, precision, nb, nd_lo, nd_hi, nf):
+    c = W.spherical_batch(nb=nb, nd_lo=nd_lo, nd_hi=nd_hi, nf=nf, n_core=6, eps_lo=1e-4,
+                          eps_hi=1e-1, tau_hi=1e6, B_slope=0.3, seed=9)
     dt = torch.float64 if precision == pprt.FP64 else torch.float32
     plan = pprt.SphPlan(gpu_ctx, c.nd, c.nf, c.r, c.n_core, precision=precision)
     a = _ali_inputs(c, dt)
