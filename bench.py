@@ -390,7 +390,7 @@ def bench_spherical(args):
     peaks = ctx.measure_peaks()
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VALU_NONPACKED,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU_NONPACKED, 4),
-                "traffic": None, "kernel": "k_sph_fast<float,8,true>", "kernel_ms": round(k_ms, 5),
+                "traffic": None, "kernel": "k_sph_fast<float,16,true>", "kernel_ms": round(k_ms, 5),
                 "flops_per_launch": flops,
                 "flops_per_point": SPH_FLOPS_PER_POINT,
                 "flops_per_tangent_segment": SPH_FLOPS_PER_TANGENT_SEGMENT,
@@ -409,7 +409,7 @@ def bench_spherical(args):
                                "eps 1e-6..1e-1, seed 3 (one ALI step per step)",
                    "nbatch": c.nb, "rows": int(nd.sum()), "nf": c.nf, "n_core": n_core,
                    "points_per_step": pts, "seed": 3, "plan_build_s": round(t_plan, 3),
-                   "group_size": 8},
+                   "group_size": 16},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fp64": fp64,

@@ -392,7 +392,7 @@ pprt_status pprt_nlte_step(pprt_plan* plan, const pprt_fs_in* in, const pprt_ato
  * isotropic, [nb][nf]; the diffusion core uses B + mu (B - B_prev)/dtau_k
  * of the last radial layer with mu at the core.  Outputs J, JmS, lstar,
  * lstar_c, H ([rows][nf]).  r is a host array [rows], read during the call
- * only.  At most 65535 atmospheres, 4096 shells each and 1024 core rays per
+ * only.  At most 65535 atmospheres, 1000 shells each and 1024 core rays per
  * plan.  A plan whose outputs are exactly JmS | LSTAR_C (what an ALI step
  * needs) runs the ray-group sweep; other output sets the per-frequency
  * sweep over single rays. */

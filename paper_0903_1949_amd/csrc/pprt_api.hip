@@ -1304,8 +1304,11 @@ struct pprt_sph_plan {
   int32_t* d_grp0 = nullptr;   // [nb+1]
   int64_t* d_gtab = nullptr;   // [ngroups]
   void* d_gt = nullptr;        // group tables, plan precision
+  void* d_gtx = nullptr;       // per group row: largest / smallest path factor, plan precision
   void* d_muc = nullptr;       // [nb][nc], plan precision
-  SphItem* d_items = nullptr;  // [nblocks * wpb]
+  SphItem* d_items = nullptr;  // [nblocks * wpb]: formal solution, one item per (sphere, tile)
+  SphItem* d_items_part = nullptr;  // [nblocks_part * wpb]: two-level step, chunks of groups
+  int nblocks_part = 0, P = 1;
 };
 
 extern "C" {
@@ -1323,7 +1326,7 @@ pprt_status pprt_sph_plan_create(pprt_ctx* c, int32_t nb, const int32_t* nd, int
   if (n_core < 1 || n_core > 1024) return fail(c, PPRT_E_INVALID_ARG, "n_core must be in 1..1024");
   if (nb > 65535) return fail(c, PPRT_E_SHAPE, "at most 65535 spherical atmospheres per plan");
   for (int b = 0; b < nb; ++b)
-    if (nd[b] > 4096) return fail(c, PPRT_E_SHAPE, "nd[%d] = %d: at most 4096 shells", b, nd[b]);
+    if (nd[b] > 1000) return fail(c, PPRT_E_SHAPE, "nd[%d] = %d: at most 1000 shells", b, nd[b]);
   const uint32_t allowed = PPRT_OUT_J | PPRT_OUT_JMS | PPRT_OUT_LSTAR | PPRT_OUT_LSTAR_C | PPRT_OUT_H;
   if (outputs & ~allowed) return fail(c, PPRT_E_UNSUPPORTED, "spherical plans give J, JmS, lstar, lstar_c and H");
   for (int b = 0; b < nb; ++b)
@@ -1342,8 +1345,9 @@ pprt_status pprt_sph_plan_create(pprt_ctx* c, int32_t nb, const int32_t* nd, int
   const int G = sph_group_size(precision);
   std::vector<int32_t> grp0(nb + 1, 0);
   std::vector<int64_t> gtab;
-  std::vector<double> gt, muc;
+  std::vector<double> gt, gtx, muc;
   std::vector<int64_t> work(nb, 0);
+  std::vector<int64_t> gwork;                  // per group: sum over its rays of shells crossed
   for (int b = 0; b < nb; ++b) {
     const double* rb = r + p->off[b];
     const int n = nd[b];
@@ -1410,8 +1414,12 @@ pprt_status pprt_sph_plan_create(pprt_ctx* c, int32_t nb, const int32_t* nd, int
       gtab.push_back((int64_t)gt.size());
       const size_t base = gt.size();
       gt.resize(base + (size_t)(mx + 1) * 3 * G, 0.0);
+      gwork.push_back(0);
+      const size_t basex = gtx.size();
+      gtx.resize(basex + (size_t)(mx + 1) * 2, 0.0);
       for (int g = 0; g < G && j0 + g < nr; ++g) {
         const SphRay& ry = rays[ray0[b] + j0 + g];
+        gwork.back() += ry.m + 1;
         for (int d = 0; d <= ry.m && d <= mx; ++d) {
           const double pfd = pf[ry.e0 + d];
           double* row = &gt[base + (size_t)d * 3 * G];
@@ -1419,6 +1427,17 @@ pprt_status pprt_sph_plan_create(pprt_ctx* c, int32_t nb, const int32_t* nd, int
           row[G + g] = pfd > 0.0 ? 1.0 / pfd : 0.0;
           row[2 * G + g] = hw[ry.e0 + d];
         }
+      }
+      for (int d = 0; d <= mx; ++d) {
+        const double* row = &gt[base + (size_t)d * 3 * G];
+        double pmax = 0.0, pmin = 0.0;
+        for (int g = 0; g < G; ++g)
+          if (row[g] > 0.0) {
+            pmax = std::max(pmax, row[g]);
+            pmin = pmin > 0.0 ? std::min(pmin, row[g]) : row[g];
+          }
+        gtx[basex + 2 * d] = pmax;
+        gtx[basex + 2 * d + 1] = pmin;
       }
     }
     if (pf.size() > (size_t)INT32_MAX) {
@@ -1429,39 +1448,69 @@ pprt_status pprt_sph_plan_create(pprt_ctx* c, int32_t nb, const int32_t* nd, int
   ray0[nb] = (int32_t)rays.size();
   grp0[nb] = (int32_t)gtab.size();
   p->nrays = (int32_t)rays.size();
-  // work list of the group sweep: one wave per (sphere, 64-frequency tile),
-  // spheres by decreasing work.  From 16 spheres on, the tiles of a sphere go
-  // to blocks on one XCD (block i runs on XCD i mod 8), so the sphere's ray
-  // tables are read into one L2.
+  // Work lists of the group sweep: one wave per (unit, 64-frequency tile).  A
+  // unit is a sphere (formal solution: group 0 stores the columns) or, for the
+  // two-level step of a batch too small to give the GPU 8192 waves, a chunk of
+  // consecutive ray groups: a sphere then takes up to four chunks of about
+  // equal work, in proportion to its work.  Units go by decreasing work; from
+  // 16 units on, the tiles of a unit go to blocks on one XCD (block i runs on
+  // XCD i mod 8), so its ray tables are read into one L2.
   p->G = G;
   p->ntiles = (nf + 63) / 64;
   p->ndmax = *std::max_element(nd, nd + nb);
   const size_t es = precision == PPRT_FP64 ? sizeof(double) : sizeof(float);
-  p->wpb = (int)std::max<size_t>(1, std::min<size_t>(4, 65536 / (2 * (size_t)p->ndmax * es)));
-  std::vector<int> order(nb);
-  for (int b = 0; b < nb; ++b) order[b] = b;
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
-  const int nbk = (p->ntiles + p->wpb - 1) / p->wpb;       // blocks per sphere
-  std::vector<SphItem> items;
-  if (nb >= 16) {
-    const int noct = (nb + 7) / 8;
-    p->nblocks = 8 * nbk * noct;
-    items.assign((size_t)p->nblocks * p->wpb, SphItem{-1, 0});
-    for (int s_ = 0; s_ < nb; ++s_)
-      for (int blk = 0; blk < nbk; ++blk) {
-        const int64_t pid = 8 * ((int64_t)nbk * (s_ / 8) + blk) + s_ % 8;
-        for (int w_ = 0; w_ < p->wpb; ++w_) {
-          const int t = blk * p->wpb + w_;
-          if (t < p->ntiles) items[pid * p->wpb + w_] = SphItem{order[s_], t};
-        }
+  p->wpb = (int)std::max<size_t>(1, std::min<size_t>(4, 65536 / (8 * (size_t)(p->ndmax + 1) * es)));
+  struct Unit { int b, g0, g1, slot, nslot; int64_t w; };
+  const int nbk = (p->ntiles + p->wpb - 1) / p->wpb;       // blocks per unit
+  auto layout = [&](std::vector<Unit> u, int& nblocks) {
+    std::stable_sort(u.begin(), u.end(), [](const Unit& x, const Unit& y) { return x.w > y.w; });
+    const int nu = (int)u.size();
+    std::vector<SphItem> it;
+    const bool xcd = nu >= 16;
+    nblocks = xcd ? 8 * nbk * ((nu + 7) / 8) : nu * nbk;
+    it.assign((size_t)nblocks * p->wpb, SphItem{-1, 0, 0, 0, 0, 1});
+    for (int s_ = 0; s_ < nu; ++s_)
+      for (int t = 0; t < p->ntiles; ++t) {
+        const int blk = t / p->wpb;
+        const int64_t pid = xcd ? 8 * ((int64_t)nbk * (s_ / 8) + blk) + s_ % 8 : (int64_t)s_ * nbk + blk;
+        it[pid * p->wpb + t % p->wpb] = SphItem{u[s_].b, t, u[s_].g0, u[s_].g1, u[s_].slot, u[s_].nslot};
       }
-  } else {
-    p->nblocks = nb * nbk;
-    items.assign((size_t)p->nblocks * p->wpb, SphItem{-1, 0});
-    for (int s_ = 0; s_ < nb; ++s_)
-      for (int t = 0; t < p->ntiles; ++t)
-        items[((size_t)s_ * nbk + t / p->wpb) * p->wpb + t % p->wpb] = SphItem{order[s_], t};
+    return it;
+  };
+  std::vector<Unit> whole, chunks;
+  int64_t wsum = 0;
+  for (int64_t w_ : work) wsum += w_;
+  const int64_t units_wanted = (8192 + p->ntiles - 1) / p->ntiles;
+  const double wchunk = nb >= units_wanted ? 1e300 : std::max(1.0, (double)wsum / (double)units_wanted);
+  p->P = 1;
+  for (int b = 0; b < nb; ++b) {
+    const int ng = grp0[b + 1] - grp0[b];
+    whole.push_back(Unit{b, 0, ng, 0, 1, work[b]});
+    int S = (int)std::lround((double)work[b] / wchunk);
+    S = std::max(1, std::min(std::min(4, ng), S));
+    p->P = std::max(p->P, S);
+    // cut after the first group whose prefix reaches k/S of the work (each chunk non-empty)
+    int g0 = 0;
+    int64_t pre = 0;
+    for (int k = 0; k < S; ++k) {
+      int g1 = g0;
+      int64_t wk = 0;
+      if (k == S - 1) {
+        for (; g1 < ng; ++g1) wk += gwork[grp0[b] + g1];
+      } else {
+        const double target = (double)work[b] * (k + 1) / S;
+        do {
+          wk += gwork[grp0[b] + g1];
+          pre += gwork[grp0[b] + g1];
+          ++g1;
+        } while (g1 < ng - (S - 1 - k) && (double)pre < target);
+      }
+      chunks.push_back(Unit{b, g0, g1, k, S, wk});
+      g0 = g1;
+    }
   }
+  std::vector<SphItem> items = layout(whole, p->nblocks);
+  std::vector<SphItem> items_part = layout(chunks, p->nblocks_part);
   p->entries = (int64_t)pf.size();
   std::vector<double> tab(3 * pf.size());
   std::copy(pf.begin(), pf.end(), tab.begin());
@@ -1484,6 +1533,7 @@ pprt_status pprt_sph_plan_create(pprt_ctx* c, int32_t nb, const int32_t* nd, int
     return hipMemcpy(*dst, f.data(), f.size() * es, hipMemcpyHostToDevice);
   };
   if (e == hipSuccess) e = upload_t(gt, &p->d_gt);
+  if (e == hipSuccess) e = upload_t(gtx, &p->d_gtx);
   if (e == hipSuccess) e = upload_t(muc, &p->d_muc);
   if (e == hipSuccess) e = hipMalloc(&p->d_grp0, grp0.size() * sizeof(int32_t));
   if (e == hipSuccess) e = hipMalloc(&p->d_gtab, gtab.size() * sizeof(int64_t));
@@ -1492,6 +1542,10 @@ pprt_status pprt_sph_plan_create(pprt_ctx* c, int32_t nb, const int32_t* nd, int
   if (e == hipSuccess) e = hipMemcpy(p->d_gtab, gtab.data(), gtab.size() * sizeof(int64_t), hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(p->d_items, items.data(), items.size() * sizeof(SphItem), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&p->d_items_part, items_part.size() * sizeof(SphItem));
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_items_part, items_part.data(), items_part.size() * sizeof(SphItem),
+                  hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     pprt_sph_plan_destroy(p);
     return hip_check(c, e, "spherical plan metadata");
@@ -1509,8 +1563,10 @@ void pprt_sph_plan_destroy(pprt_sph_plan* p) {
   if (p->d_grp0) (void)hipFree(p->d_grp0);
   if (p->d_gtab) (void)hipFree(p->d_gtab);
   if (p->d_gt) (void)hipFree(p->d_gt);
+  if (p->d_gtx) (void)hipFree(p->d_gtx);
   if (p->d_muc) (void)hipFree(p->d_muc);
   if (p->d_items) (void)hipFree(p->d_items);
+  if (p->d_items_part) (void)hipFree(p->d_items_part);
   delete p;
 }
 
@@ -1546,13 +1602,16 @@ pprt_status sph_fast_launch(pprt_sph_plan* p, const pprt_fs_in* in, const double
                             const int32_t* active, const void* wphi, T* JmS, T* Lc, T* part) {
   SphFastArgs<T> a{};
   a.items = p->d_items; a.off = p->d_off; a.grp0 = p->d_grp0; a.gtab = p->d_gtab;
-  a.tab = (const T*)p->d_gt; a.muc = (const T*)p->d_muc;
+  a.tab = (const T*)p->d_gt; a.tabx = (const T*)p->d_gtx; a.muc = (const T*)p->d_muc;
   a.tau = in->tau; a.q = (const T*)in->q; a.Sg = Sl ? nullptr : (const T*)in->Sg; a.Sl = Sl;
   a.Itop = (const T*)in->Itop; a.Bbot = (const T*)in->Bbot; a.Bbot_prev = (const T*)in->Bbot_prev;
   a.Bl = Bl; a.Ibot = (const T*)in->Ibot; a.active = active; a.wphi = (const T*)wphi;
   a.JmS = JmS; a.Lc = Lc; a.part = part;
   a.nf = p->nf; a.ntiles = p->ntiles; a.lower_bc = p->lower_bc; a.n_core = p->nc; a.ndmax = p->ndmax;
-  return hip_check(p->ctx, launch_sph_fast(p->precision, p->nblocks, p->wpb, p->ctx->stream, &a),
+  a.P = p->P;
+  if (part) a.items = p->d_items_part;
+  return hip_check(p->ctx, launch_sph_fast(p->precision, part ? p->nblocks_part : p->nblocks, p->wpb,
+                                           p->ctx->stream, &a),
                    "spherical ray-group sweep launch");
 }
 }  // namespace
@@ -1593,7 +1652,7 @@ pprt_status pprt_sph_formal_solution(pprt_sph_plan* p, const pprt_fs_in* in, ppr
 pprt_status pprt_sph_plan_workspace_bytes(const pprt_sph_plan* p, size_t* bytes) {
   if (!p || !bytes) return PPRT_E_INVALID_ARG;
   const size_t es = p->precision == PPRT_FP64 ? sizeof(double) : sizeof(float);
-  *bytes = align256((size_t)p->rows * p->ntiles * 4 * es);
+  *bytes = align256((size_t)p->rows * p->ntiles * p->P * 4 * es);
   return PPRT_OK;
 }
 
@@ -1620,7 +1679,7 @@ pprt_status pprt_sph_two_level_update(pprt_sph_plan* p, const pprt_two_level* at
   AliUpdateArgs u{};
   u.off = p->d_off; u.part = ws; u.eps = at->eps; u.B = at->B; u.S = S; u.max_rel = max_rel;
   u.active = const_cast<int32_t*>(active); u.iters = nullptr; u.status = c->d_status; u.tol = 0.0;
-  u.nw = p->ntiles; u.nb = p->nb; u.part_fp64 = p->precision == PPRT_FP64 ? 1 : 0;
+  u.nw = p->ntiles * p->P; u.nb = p->nb; u.part_fp64 = p->precision == PPRT_FP64 ? 1 : 0;
   return hip_check(c, launch_ali_update(p->nb, c->stream, u), "ALI update launch");
 }
 

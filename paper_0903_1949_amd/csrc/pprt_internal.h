@@ -45,6 +45,23 @@ __device__ __forceinline__ double readlane(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Sum over each row of 16 lanes (quad swaps, half-row mirror, row mirror);
+// every lane must be active and ends with its row's sum.
+__device__ __forceinline__ float row_sum(float v) {
+  v += dpp_f<0xb1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_f<0x4e>(v);    // quad_perm [2,3,0,1]
+  v += dpp_f<0x141>(v);   // row_half_mirror
+  v += dpp_f<0x140>(v);   // row_mirror
+  return v;
+}
+__device__ __forceinline__ double row_sum(double v) {
+  v += dpp_d<0xb1>(v);
+  v += dpp_d<0x4e>(v);
+  v += dpp_d<0x141>(v);
+  v += dpp_d<0x140>(v);
+  return v;
+}
+
 // Sum over the 64 lanes of a wave; every lane must be active.  Within each
 // row of 16 lanes: quad swaps, half-row mirror, row mirror; then the four row
 // sums are added in a fixed order.  The result is uniform over the wave.
@@ -242,6 +259,9 @@ hipError_t launch_fs_sph(int precision, int nb, int nf, hipStream_t s, const voi
 struct SphItem {
   int32_t b;       // sphere (-1: idle wave)
   int32_t tile;    // 64-frequency tile
+  int32_t g0, g1;  // ray groups g0 .. g1-1 of the sphere
+  int32_t slot;    // partial-sum slot of this chunk of groups (two-level step)
+  int32_t nslot;   // chunks of the sphere (slot 0 clears the slots nslot .. P-1)
 };
 template <typename T>
 struct SphFastArgs {
@@ -252,6 +272,8 @@ struct SphFastArgs {
   const T* tab;             // per group [deepest shell + 1][3][G]: path factor of the
                             // segment to the next shell inward, its reciprocal, half
                             // weight in mu (zero where the ray misses the shell)
+  const T* tabx;            // per group [deepest shell + 1][2]: largest and smallest
+                            // path factor of the group's segments on the row
   const T* muc;             // [nb][n_core] mu at the core of core ray c
   const double* tau;
   const T* q;
@@ -266,8 +288,9 @@ struct SphFastArgs {
   const T* wphi;            // [nf] profile weights (two-level step)
   T* JmS;                   // [rows][nf] J - S (formal solution)
   T* Lc;                    // [rows][nf] 1 - Lambda* (formal solution)
-  T* part;                  // [rows][ntiles][2][2] (two-level step) or nullptr
+  T* part;                  // [rows][ntiles * P][2][2] (two-level step) or nullptr
   int32_t nf, ntiles, lower_bc, n_core, ndmax;
+  int32_t P;                // partial-sum slots per tile
 };
 int sph_group_size(int precision);
 size_t sph_fast_lds_bytes(int precision, int wpb, int ndmax);

@@ -189,9 +189,9 @@ __global__ __launch_bounds__(256) void k_fs_sph(SphArgs<T> a) {
 // (path factor, its reciprocal, half weight) comes through scalar loads.  Each
 // shell's contribution of the group is added once: to the J - S and
 // 1 - Lambda* columns (formal solution), or, for the two-level step, already
-// summed over the wave's frequencies with the profile weights into the
-// wave's per-shell totals in LDS, which end as the tile's partial sums for the
-// float64 update.
+// summed with the profile weights over each 16-lane row of frequencies
+// (DPP) into the wave's per-row, per-shell totals in LDS, which end as the
+// tile's partial sums for the float64 update.
 
 // A load from an address that is uniform over the wave, issued as a scalar load.
 template <typename T>
@@ -280,6 +280,31 @@ __device__ __forceinline__ void seg_update(double x, double rq, double ip, doubl
   e = en;
 }
 
+// The same update with the regime fixed for the whole wave: R = 0 every
+// lane thin, R = 1 every lane thick, R = 2 chosen per ray (as above).  FP64
+// always decides per lane.
+template <int R, bool NEED_E>
+__device__ __forceinline__ void seg_update_r(float x, float rq, float ip, float dS, float& D, float& ps,
+                                             float& e) {
+  if constexpr (R == 0) {
+    ps = psi_thin_f32(x);
+    if (NEED_E) e = fmaf(-x, ps, 1.0f);
+    D = fmaf(ps, fmaf(-x, D, dS), D);
+  } else if constexpr (R == 1) {
+    e = __builtin_amdgcn_exp2f(-(x * kLog2e));
+    const float m = rq * ip;
+    ps = fmaf(-e, m, m);
+    D = fmaf(e, D, ps * dS);
+  } else {
+    seg_update<NEED_E>(x, rq, ip, dS, D, ps, e);
+  }
+}
+template <int R, bool NEED_E>
+__device__ __forceinline__ void seg_update_r(double x, double rq, double ip, double dS, double& D,
+                                             double& ps, double& e) {
+  seg_update<NEED_E>(x, rq, ip, dS, D, ps, e);
+}
+
 __device__ __forceinline__ float recip_t(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double recip_t(double x) { return 1.0 / x; }
 
@@ -304,18 +329,22 @@ __global__ __launch_bounds__(256) void k_sph_fast(SphFastArgs<T> a) {
   auto q_at = [&](int d) -> T { return qc[(o + d) * nf]; };
   auto S_at = [&](int d) -> T { return PART ? T(a.Sl[o + d]) : a.Sg[(o + d) * nf + kk]; };
   const T wp = PART ? (ok ? a.wphi[kk] : T(0)) : T(0);
-  T* acc = PART ? reinterpret_cast<T*>(sph_lds) + (int64_t)wave * 2 * a.ndmax : nullptr;
+  // two-level step: per wave, the profile-weighted sums of each 16-lane row
+  // (4 rows x 2 quantities x ndmax shells, row stride ndmax + 1)
+  const int rs = a.ndmax + 1;
+  T* acc = PART ? reinterpret_cast<T*>(sph_lds) + (int64_t)wave * 8 * rs : nullptr;
   if (PART) {
-    for (int d = lane; d < 2 * a.ndmax; d += 64) acc[d] = T(0);
+    for (int d = lane; d < 8 * rs; d += 64) acc[d] = T(0);
   }
+  const int row = lane >> 4;
   // one shell's contribution of the current group
   auto flush = [&](int d, T vj, T vl, bool store) {
     if (PART) {
-      const T sj = wave_sum(wp * vj);
-      const T sl = wave_sum(wp * vl);
-      if (lane == 0) {
-        atomicAdd(acc + d, sj);
-        atomicAdd(acc + a.ndmax + d, sl);
+      const T sj = row_sum(wp * vj);
+      const T sl = row_sum(wp * vl);
+      if ((lane & 15) == 0) {
+        atomicAdd(acc + row * rs + d, sj);
+        atomicAdd(acc + (4 + row) * rs + d, sl);
       }
     } else if (ok) {
       const int64_t x = (o + d) * nf + kk;
@@ -341,16 +370,33 @@ __global__ __launch_bounds__(256) void k_sph_fast(SphFastArgs<T> a) {
     Ic0 = a.Ibot ? a.Ibot[(int64_t)b * nf + kk] : T(0);
   }
   const T* muc = a.muc + (int64_t)b * nc;
-  const int gfirst = a.grp0[b], glast = a.grp0[b + 1];
-  for (int gi = gfirst; gi < glast; ++gi) {
+  const int gfirst = a.grp0[b];
+  const int gbeg = gfirst + __builtin_amdgcn_readfirstlane(it.g0);
+  const int gend = gfirst + __builtin_amdgcn_readfirstlane(it.g1);
+  for (int gi = gbeg; gi < gend; ++gi) {
     const int jG = (gi - gfirst) * G;
     const int Tb = nc + nd - 1 - jG;                // T(d) = Tb - d
     const int mx = Tb < nd - 1 ? Tb : nd - 1;       // deepest shell of the group
     const int ncg = nc - jG;                        // rays g < ncg are core rays
-    const bool first = gi == gfirst;                // its core rays reach every shell
-    const T* tb = a.tab + sload(a.gtab, gi);
+    const bool first = gi == gfirst;                // its core rays reach every shell (column
+                                                    // mode: one item covers all groups)
+    const int64_t t0 = sload(a.gtab, gi);
+    const T* tb = a.tab + t0;
+    const T* tx = a.tabx + t0 / (3 * G) * 2;        // per row: largest, smallest path factor
     T D[G], E[G], pl[G];
-    T pth[G], ipt[G], hw[G], hwn[G];
+    T pth[G], ipt[G], hw[G];
+    // regime of a shell's segments for the whole group (FP32, every ray with a
+    // segment on row r): 0 all thin, 1 all thick, 2 per ray
+    auto regime = [&](T qa, int r) -> int {
+      if constexpr (sizeof(T) == 8) {
+        return 2;
+      } else {
+        const unsigned long long act = __ballot(1);
+        if (__ballot(qa * sload(tx, 2 * r) < 0.25f) == act) return 0;
+        if (__ballot(qa * sload(tx, 2 * r + 1) >= 0.25f) == act) return 1;
+        return 2;
+      }
+    };
     auto load_row = [&](int d, bool geo, bool wts) {
       const T* row = tb + (int64_t)d * 3 * G;
       for_rays<G>([&](auto gc) {
@@ -387,16 +433,32 @@ __global__ __launch_bounds__(256) void k_sph_fast(SphFastArgs<T> a) {
       load_row(d, false, true);
       const int Td = Tb - d;
       T aj = T(0), al = T(0);
-      for_rays<G>([&](auto gc) {
-        constexpr int g = decltype(gc)::value;
-        if (!COND || g <= Td) {
-          T ps, e;
-          seg_update<false>(qa * pth[g], rq, ipt[g], dS, D[g], ps, e);
-          if (COND && g == Td) pl[g] = ps;
+      auto rays = [&](auto rc) {
+        constexpr int R = decltype(rc)::value;
+        for_rays<G>([&](auto gc) {
+          constexpr int g = decltype(gc)::value;
+          // every ray is computed; one past its deepest shell has zero path and
+          // weight there and keeps its state
+          T ps, e, Dn = D[g];
+          seg_update_r<R, false>(qa * pth[g], rq, ipt[g], dS, Dn, ps, e);
+          if (COND) {
+            D[g] = g <= Td ? Dn : D[g];
+            pl[g] = g == Td ? ps : pl[g];
+          } else {
+            D[g] = Dn;
+          }
           aj = fma(hw[g], D[g], aj);
           al = fma(hw[g], ps, al);
-        }
-      });
+        });
+      };
+      if constexpr (COND) {
+        rays(std::integral_constant<int, 2>{});
+      } else {
+        const int R = regime(qa, d - 1);
+        if (R == 0) rays(std::integral_constant<int, 0>{});
+        else if (R == 1) rays(std::integral_constant<int, 1>{});
+        else rays(std::integral_constant<int, 2>{});
+      }
       flush(d, aj, al, first);
       q0 = q1;
       S0 = S1;
@@ -429,7 +491,6 @@ __global__ __launch_bounds__(256) void k_sph_fast(SphFastArgs<T> a) {
           nj = fma(hw[g], D[g], nj);
           nl = fma(hw[g], pn, nl);
         }
-        hwn[g] = hw[g];
       });
     }
     auto outward = [&](int d, auto cond) {
@@ -439,29 +500,49 @@ __global__ __launch_bounds__(256) void k_sph_fast(SphFastArgs<T> a) {
       const T rq = recip_t(qa);
       const T dS = Sn - Sd;
       load_row(d, true, true);
+      const T* nxt = tb + (int64_t)(d + 1) * 3 * G + 2 * G;   // half weights of node d+1
       const int Td = Tb - d;
       T aj = T(0), al = T(0);
-      for_rays<G>([&](auto gc) {
-        constexpr int g = decltype(gc)::value;
-        if (COND && g == Td) {                        // tangent point (d < nd-1 here)
-          aj = fma(hw[g], D[g], aj);
-          al = fma(hw[g], pl[g], al);
-        } else if (!COND || g < Td) {
-          T ps, e;
-          if (g < ncg) {
-            seg_update<false>(qa * pth[g], rq, ipt[g], dS, D[g], ps, e);
-            al = fma(hw[g], ps, al);
+      // CORE: the group may hold core rays (g < ncg), which have no round trip
+      auto rays = [&](auto rc, auto cc) {
+        constexpr int R = decltype(rc)::value;
+        constexpr bool CORE = decltype(cc)::value;
+        for_rays<G>([&](auto gc) {
+          constexpr int g = decltype(gc)::value;
+          // every ray is computed; in the last shells of the group a ray with
+          // g == T(d) is at its tangent point (it keeps D, adds its last inward
+          // psi) and one with g > T(d) misses the shell (zero weight, keeps its state)
+          const bool seg = !COND || g < Td;
+          T ps, e, Dn = D[g];
+          if (CORE && g < ncg) {
+            seg_update_r<R, false>(qa * pth[g], rq, ipt[g], dS, Dn, ps, e);
+            D[g] = seg ? Dn : D[g];
+            al = fma(hw[g], seg ? ps : pl[g], al);
           } else {
-            seg_update<true>(qa * pth[g], rq, ipt[g], dS, D[g], ps, e);
+            seg_update_r<R, true>(qa * pth[g], rq, ipt[g], dS, Dn, ps, e);
             const T E2 = E[g] * E[g];
-            al = fma(hw[g], ps - e * (E2 * (ps - e)), al);
-            if (!COND || g < Td - 1) nl = fma(-hwn[g], E2 * (T(1) - ps), nl);
-            E[g] *= e;
+            const T u = ps - e * (E2 * (ps - e));
+            D[g] = seg ? Dn : D[g];
+            al = fma(hw[g], seg ? u : pl[g], al);
+            if (!COND || g < Td - 1) nl = fma(-sload(nxt, g), E2 * (T(1) - ps), nl);
+            E[g] = seg ? E[g] * e : E[g];
           }
           aj = fma(hw[g], D[g], aj);
-        }
-        hwn[g] = hw[g];
-      });
+        });
+      };
+      using I0 = std::integral_constant<int, 0>;
+      using I1 = std::integral_constant<int, 1>;
+      using I2 = std::integral_constant<int, 2>;
+      if constexpr (COND) {
+        rays(I2{}, std::true_type{});
+      } else if (ncg > 0) {
+        rays(I2{}, std::true_type{});
+      } else {
+        const int R = regime(qa, d);
+        if (R == 0) rays(I0{}, std::false_type{});
+        else if (R == 1) rays(I1{}, std::false_type{});
+        else rays(I2{}, std::false_type{});
+      }
       flush(d + 1, nj, nl, false);
       nj = aj;
       nl = al;
@@ -481,22 +562,33 @@ __global__ __launch_bounds__(256) void k_sph_fast(SphFastArgs<T> a) {
     flush(0, nj, nl, false);
   }
   if (PART) {
+    // this chunk's slot; the first chunk also clears the slots its sphere leaves unused
+    const int slot = __builtin_amdgcn_readfirstlane(it.slot);
+    const int nslot = __builtin_amdgcn_readfirstlane(it.nslot);
+    const int P = a.P;
     for (int d = lane; d < nd; d += 64) {
-      T* pp = a.part + ((o + d) * a.ntiles + tile) * 4;
-      pp[0] = acc[d];
-      pp[1] = acc[a.ndmax + d];
-      pp[2] = T(0);
-      pp[3] = T(0);
+      T* pp = a.part + ((o + d) * a.ntiles * P + (int64_t)tile * P) * 4;
+      pp[slot * 4 + 0] = (acc[d] + acc[rs + d]) + (acc[2 * rs + d] + acc[3 * rs + d]);
+      pp[slot * 4 + 1] = (acc[4 * rs + d] + acc[5 * rs + d]) + (acc[6 * rs + d] + acc[7 * rs + d]);
+      pp[slot * 4 + 2] = T(0);
+      pp[slot * 4 + 3] = T(0);
+      if (slot == 0)
+        for (int c = nslot; c < P; ++c) {
+          pp[c * 4 + 0] = T(0);
+          pp[c * 4 + 1] = T(0);
+          pp[c * 4 + 2] = T(0);
+          pp[c * 4 + 3] = T(0);
+        }
     }
   }
 }
 
 }  // namespace
 
-int sph_group_size(int precision) { return precision == PPRT_FP64 ? 4 : 8; }
+int sph_group_size(int precision) { return precision == PPRT_FP64 ? 4 : 16; }
 
 size_t sph_fast_lds_bytes(int precision, int wpb, int ndmax) {
-  return (size_t)wpb * 2 * ndmax * (precision == PPRT_FP64 ? sizeof(double) : sizeof(float));
+  return (size_t)wpb * 8 * (ndmax + 1) * (precision == PPRT_FP64 ? sizeof(double) : sizeof(float));
 }
 
 hipError_t launch_sph_fast(int precision, int nblocks, int wpb, hipStream_t s, const void* args) {
@@ -512,10 +604,10 @@ hipError_t launch_sph_fast(int precision, int nblocks, int wpb, hipStream_t s, c
   } else {
     const auto& a = *(const SphFastArgs<float>*)args;
     if (a.part)
-      hipLaunchKernelGGL((k_sph_fast<float, 8, true>), grid, block,
+      hipLaunchKernelGGL((k_sph_fast<float, 16, true>), grid, block,
                          sph_fast_lds_bytes(precision, wpb, a.ndmax), s, a);
     else
-      hipLaunchKernelGGL((k_sph_fast<float, 8, false>), grid, block, 0, s, a);
+      hipLaunchKernelGGL((k_sph_fast<float, 16, false>), grid, block, 0, s, a);
   }
   return hipGetLastError();
 }
