@@ -34,15 +34,22 @@ Ng acceleration (Ng 1974, in the form given by Auer 1987): from the last four
 iterates x0 (newest), x1, x2, x3 and the differences d0 = x0 - x1,
 d1 = x1 - x2, d2 = x2 - x3, the coefficients a, b minimise the weighted norm
 of d0 - a (d0 - d1) - b (d0 - d2) with weights 1/x0^2, and the accelerated
-iterate is (1 - a - b) x0 + a x1 + b x2.  Here it is applied once four
-iterates have accumulated since the start or the last acceleration, and the
-accelerated iterate starts the next group.
+iterate is (1 - a - b) x0 + a x1 + b x2.  The paper gives no schedule (it
+defers the method to its Paper I).  Extrapolation assumes the errors already
+decay geometrically, so here it starts once an un-accelerated step changes S
+by less than NG_START (maximum relative change): that step's old and new
+iterates open the first group.  From then on it is applied whenever four
+iterates have accumulated, and the accelerated iterate starts the next group.
+(Applied from the very first iterates it stalls on some thick atmospheres
+with a small eps, for the diagonal and the tri-diagonal operator alike.)
 """
 from __future__ import annotations
 
 import numpy as np
 
 from . import formal
+
+NG_START = 1e-2
 
 
 def _sg(S_l, pfrac, sg_const, nf):
@@ -175,7 +182,7 @@ def two_level_ali_nonlocal(tau, q, phi, wnu, eps, B, mu, w, tol=1e-8, max_iter=2
     S = B.copy() if S0 is None else np.asarray(S0, dtype=np.float64).copy()
     Bbot = np.full(nf, B[-1])
     Bprev = np.full(nf, B[-2])
-    hist, group = [], [S.copy()]
+    hist, group = [], None
     converged = False
     it = 0
     for it in range(1, max_iter + 1):
@@ -188,10 +195,14 @@ def two_level_ali_nonlocal(tau, q, phi, wnu, eps, B, mu, w, tol=1e-8, max_iter=2
             A -= (1.0 - eps) * (np.diag(Lsub[1:], -1) + np.diag(Lsup[:-1], 1))
         S_new = S + np.linalg.solve(A, rhs)
         if ng:
-            group.append(S_new.copy())
-            if len(group) == 4:
-                S_new = ng_extrapolate(group[3], group[2], group[1], group[0])
-                group = [S_new.copy()]
+            if group is None:
+                if np.max(np.abs(S_new - S) / np.abs(S_new)) < NG_START:
+                    group = [S.copy(), S_new.copy()]
+            else:
+                group.append(S_new.copy())
+                if len(group) == 4:
+                    S_new = ng_extrapolate(group[3], group[2], group[1], group[0])
+                    group = [S_new.copy()]
         rel = float(np.max(np.abs(S_new - S) / np.abs(S_new)))
         hist.append(rel)
         S = S_new

@@ -191,3 +191,25 @@ def test_convergence_ranking_of_the_operators(c1_runs):
     assert it[("tri", False)] < it[("diag", False)] / 4
     assert it[("tri", True)] < it[("tri", False)]
     assert (not runs[("diag", True)]["converged"]) or it[("diag", True)] > it[("tri", False)]
+
+
+def test_ng_waits_for_the_linear_regime():
+    """A thick atmosphere with a small eps (nd 151, eps 1.3e-6, nf 21, na 4)
+    on which Ng extrapolation applied from the first four iterates stalls
+    (the oracle's schedule before this reading: no convergence within 300
+    iterations).  Started once an un-accelerated step changes S by less than
+    1e-2, the tri-diagonal iteration with Ng converges to the direct fixed
+    point in far fewer iterations than without Ng."""
+    b = W.two_level_batch(nb=4, nd_lo=150, nd_hi=230, na=4, nf=21, eps_lo=1e-6, eps_hi=1e-4, seed=5)
+    a = b.atmosphere(2)
+    assert a.nd[0] == 151
+    mu, w = gauss_legendre01(a.na)
+    eps = float(a.eps[0])
+    runs = {ng: ali.two_level_ali_nonlocal(a.tau, a.q, a.phi, a.wnu, eps, a.B, mu, w, tol=1e-10,
+                                           operator="tri", ng=ng, max_iter=1000)
+            for ng in (False, True)}
+    direct = ali.direct_fixed_point(a.tau, a.q, a.phi, a.wnu, eps, a.B, mu, w)
+    for ng, r in runs.items():
+        assert r["converged"], ng
+        assert np.max(np.abs(r["S"] - direct) / direct) < 1e-6, ng
+    assert runs[True]["iterations"] < 0.6 * runs[False]["iterations"]
