@@ -61,9 +61,15 @@ def parse():
     ap.add_argument("--graph-chunk", type=int, default=25,
                     help="ALI iterations per captured graph in the graph-mode timing (0: skip)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_fs_profile_c3a.json"))
-    ap.add_argument("--workload", choices=["c3a", "spherical"], default="c3a",
+    ap.add_argument("--workload", choices=["c3a", "spherical", "nonlocal", "voigt"], default="c3a",
                     help="c3a: the plane-parallel batch (default, the headline line); "
-                         "spherical: the same batch shape as spheres (1D spherical symmetry)")
+                         "spherical: the same batch shape as spheres (1D spherical symmetry); "
+                         "nonlocal: c3a with the tri-diagonal approximate operator and Ng; "
+                         "voigt: the multilevel atom with depth-dependent Voigt lines")
+    ap.add_argument("--voigt-nb", type=int, default=64, help="voigt: atmospheres in the batch")
+    ap.add_argument("--conv-tol", type=float, default=1e-6,
+                    help="nonlocal: tolerance of the convergence comparison")
+    ap.add_argument("--conv-max-iter", type=int, default=4000)
     ap.add_argument("--sph-cpu-sample", type=int, default=8, help="spheres in the CPU sample")
     return ap.parse_args()
 
@@ -109,6 +115,12 @@ def main():
         sys.exit(2)
     if args.workload == "spherical":
         bench_spherical(args)
+        return
+    if args.workload == "nonlocal":
+        bench_nonlocal(args)
+        return
+    if args.workload == "voigt":
+        bench_voigt(args)
         return
     import torch
     from paper_0903_1949_amd import pprt
@@ -415,6 +427,265 @@ def bench_spherical(args):
         "fp64": fp64,
         "speedup_vs_fp64": (value / fp64["value"]) if fp64 else None,
         "fp32_vs_fp64": {"S_after_one_step_rel": rel_step},
+    }
+    print(json.dumps(line), flush=True)
+
+
+# Tri-diagonal sweep, FP32 flops per point: the 24 of the diagonal sweep plus,
+# per angle and hemisphere, alpha (1), gamma (1), gamma + e alpha_prev (2) and
+# the band accumulation (2) -> 36.
+TRI_FLOPS_PER_POINT = 36.0
+
+
+def nonlocal_cpu_baseline(batch, nsample):
+    """The oracle's non-local step (numpy FP64, one thread) on the smallest
+    atmospheres of the batch: the band of Lambda from nd unit-column formal
+    solutions (its definition), one formal solution, the tri-diagonal solve
+    and the Ng bookkeeping."""
+    from threadpoolctl import threadpool_limits
+    from oracle import ali
+    from oracle.quadrature import gauss_legendre01
+    idx = np.argsort(batch.nd)[:nsample]
+    sub = batch.subset(idx)
+    mu, w = gauss_legendre01(sub.na)
+    off = sub.off
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        for b in range(sub.nb):
+            s = slice(off[b], off[b + 1])
+            ali.two_level_ali_nonlocal(sub.tau[s], sub.q[s], sub.phi, sub.wnu, float(sub.eps[b]),
+                                       sub.B[s], mu, w, tol=0.0, max_iter=1, operator="tri", ng=True,
+                                       S0=sub.S_trial[s])
+        dt = time.perf_counter() - t0
+    pts = sub.points
+    return {"value": pts / dt, "unit": "pts/s", "cores": 1, "kind": "oracle",
+            "sample": f"one tri-diagonal ALI step of the {sub.nb} smallest of the 512 atmospheres "
+                      f"(nd {int(sub.nd.min())}..{int(sub.nd.max())}, {pts} points; the band of Lambda "
+                      f"from nd unit-column formal solutions each), numpy FP64, 1 thread, {dt:.1f} s"}
+
+
+def bench_nonlocal(args):
+    """The C3a batch with the tri-diagonal approximate operator and Ng
+    acceleration: one ALI step is the sweep with the band quadratures, then
+    the float64 tri-diagonal solve and Ng.  Also: iterations and wall time to
+    the tolerance with the diagonal and with the tri-diagonal + Ng operator."""
+    import torch
+    from paper_0903_1949_amd import pprt
+    from paper_0903_1949_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    batch = W.two_level_batch(seed=3)
+    pts = batch.points
+    ctx = pprt.Context(0)
+    stream = torch.cuda.current_stream()
+    plan = pprt.Plan(ctx, batch.nd, batch.na, batch.nf, precision=pprt.FP32)
+    plan.set_operator(pprt.LSTAR_TRI, ng=True)
+    db = pprt.upload_two_level(batch, pprt.FP32)
+    tune = None
+    if not args.no_autotune:
+        tune = plan.autotune(db.tau, db.q, db.S, db.eps, db.B, db.wphi, force=True)
+    launch = plan.get_launch()
+    db.S.copy_(db.B)
+    plan.two_level_reset()
+    mx = torch.zeros(batch.nb, dtype=torch.float64, device="cuda:0")
+
+    def step(ev0=None, ev1=None):
+        if ev0 is not None:
+            ev0.record(stream)
+        plan.two_level_moments(db.tau, db.q, db.S, db.eps, db.B, db.wphi)
+        if ev1 is not None:
+            ev1.record(stream)
+        plan.two_level_update(db.S, db.eps, db.B, db.wphi, mx)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for e0, e1 in evs:
+        step(e0, e1)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    k_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
+    value = pts / (wall / args.steps)
+    print(f"[nonlocal] {args.steps} steps, {ms_per_step:.3f} ms/step, sweep {k_ms:.3f} ms",
+          file=sys.stderr, flush=True)
+
+    conv = {"tol": args.conv_tol, "max_iter": args.conv_max_iter, "start": "S = B",
+            "desc": "pprt_two_level_ali in graph mode (chunks of 50 iterations), all 512 "
+                    "atmospheres, until every one changes by less than tol"}
+    for name, op, ng in (("diagonal", pprt.LSTAR_DIAG, False), ("tridiagonal_ng", pprt.LSTAR_TRI, True)):
+        p2 = pprt.Plan(ctx, batch.nd, batch.na, batch.nf, precision=pprt.FP32)
+        p2.set_operator(op, ng=ng)
+        p2.set_launch(*launch)
+        S = db.B.clone()
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        rep = p2.two_level_ali(db.tau, db.q, S, db.eps, db.B, db.wphi, tol=args.conv_tol,
+                               max_iter=args.conv_max_iter, iters_per_sync=50, use_graph=True,
+                               raise_not_converged=False)
+        torch.cuda.synchronize()
+        conv[name] = {"iterations": rep["iterations"], "n_converged": rep["n_converged"],
+                      "max_rel": rep["max_rel"], "seconds": round(time.perf_counter() - tc, 4)}
+        print(f"[nonlocal] {name}: {rep}", file=sys.stderr, flush=True)
+        del p2
+
+    achieved = pts * TRI_FLOPS_PER_POINT / (k_ms * 1e-3) / 1e12
+    peaks = ctx.measure_peaks()
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VALU_NONPACKED,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU_NONPACKED, 4),
+                "traffic": None, "kernel": "k_fs_profile<float,8,true>", "kernel_ms": round(k_ms, 5),
+                "flops_per_point": TRI_FLOPS_PER_POINT,
+                "peak_measured": round(peaks["fp32_tflops"], 2),
+                "frac_of_measured": round(achieved / peaks["fp32_tflops"], 4)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = nonlocal_cpu_baseline(batch, 4)
+    line = {
+        "metric": "formal-solution depth*angle*freq pts/s, batched FP32, tri-diagonal Lambda* + Ng",
+        "value": value, "unit": "pts/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "512 two-level atmospheres, nd U{48..256}, na 8, nf 1024, "
+                               "eps 1e-6..1e-1, seed 3; tri-diagonal approximate operator with "
+                               "Ng acceleration (one ALI step per step)",
+                   "nbatch": batch.nb, "rows": int(batch.nd.sum()), "na": batch.na, "nf": batch.nf,
+                   "points_per_step": pts, "seed": 3,
+                   "launch": {"waves_per_block": launch[0], "persistent_waves_per_cu": launch[1],
+                              "autotune": tune}},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "convergence": conv,
+    }
+    print(json.dumps(line), flush=True)
+
+
+# Multilevel step, FP64 flops.  Voigt function (Weideman, 40 terms): the
+# complex Horner recursion 39 x 7, the Moebius map, the final products and
+# four divisions (counted once each) -> 300 per evaluation; cross-section,
+# opacity, emissivity and source per (row, frequency) -> 20 more.  Dense
+# formal solution (omega > 0): 21 NA^3 per (layer, frequency).
+VOIGT_FLOPS = 300.0
+OPACITY_FLOPS = 20.0
+PEAK_FP64_VALU = 78.6
+
+
+def voigt_cpu_baseline(atom1, mu, w):
+    """The oracle's multilevel iteration (numpy FP64, one thread) for one
+    atmosphere of the batch."""
+    from threadpoolctl import threadpool_limits
+    from oracle import rates
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        rates.nlte_iteration(atom1, atom1.nstar.copy(), mu, w)
+        dt = time.perf_counter() - t0
+    pts = int(atom1.nd.sum()) * atom1.na * atom1.nf
+    return {"value": pts / dt, "unit": "pts/s", "cores": 1, "kind": "oracle",
+            "sample": f"one multilevel iteration of one atmosphere (nd {int(atom1.nd.sum())}, na "
+                      f"{atom1.na}, nf {atom1.nf}, {pts} points), numpy FP64, 1 thread, {dt:.1f} s"}
+
+
+def bench_voigt(args):
+    """One multilevel iteration over a batch of atmospheres whose line
+    profiles depend on depth: opacities and sources from the populations with
+    device Voigt profiles, the omega > 0 formal solution (FP64 dense), the
+    preconditioned rates (Voigt profiles again) and the per-depth FP64 solve.
+    Each stage is also timed on its own with HIP events."""
+    import torch
+    from paper_0903_1949_amd import pprt
+    from paper_0903_1949_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    nb = args.voigt_nb
+    atom = W.multilevel_atom(nbound=6, ncont=5, nd=128, na=8, nline_pts=100, ncont_pts=100,
+                             nb=nb, seed=2, depth_profiles=True)
+    rows, nf, na = int(atom.nd.sum()), atom.nf, atom.na
+    pts = rows * na * nf
+    ctx = pprt.Context(0)
+    stream = torch.cuda.current_stream()
+    plan = pprt.Plan(ctx, atom.nd, na, nf, precision=pprt.FP64, outputs=pprt.OUT_J | pprt.OUT_LSTAR)
+    da = pprt.DeviceAtom(atom)
+    pops = da.nstar.clone()
+    mx = torch.zeros(nb, dtype=torch.float64, device="cuda:0")
+    for _ in range(args.warmup):
+        plan.nlte_step(da.tau, da, pops, mx)
+    torch.cuda.synchronize()
+    steps = args.steps
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.nlte_step(da.tau, da, pops, mx)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / steps
+    value = pts / (wall / steps)
+
+    # the stages one by one, from the same populations
+    off = np.concatenate([[0], np.cumsum(atom.nd)])
+    Bnu = np.asarray(atom.Bnu)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0")
+    Bb, Bp = dev(Bnu[off[1:] - 1]), dev(Bnu[off[1:] - 2])
+
+    def timed(fn, n=5):
+        fn()
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+        out = None
+        for e0, e1 in evs:
+            e0.record(stream)
+            out = fn()
+            e1.record(stream)
+        torch.cuda.synchronize()
+        return float(np.median([e0.elapsed_time(e1) for e0, e1 in evs])), out
+
+    t_op, (q, om, Sg) = timed(lambda: plan.nlte_opacity(da, pops))
+    ws = {}
+    t_fs, fs = timed(lambda: plan.formal_solution_scattering(da.tau, q, Sg, om, Bbot=Bb, Bbot_prev=Bp,
+                                                             workspace=ws.get("w")))
+    ws["w"] = fs["_workspace"]
+    t_ra, (dRlu, dRul, Rsul) = timed(lambda: plan.rates_assemble(da, pops, fs["J"], fs["lstar"]))
+    t_so, _ = timed(lambda: plan.rates_solve(da, pops, dRlu, dRul, Rsul))
+    line_pts = int(np.count_nonzero(np.asarray(atom.line_nu0)[np.asarray(atom.owner)] > 0)) * rows
+    op_flops = line_pts * VOIGT_FLOPS + rows * nf * OPACITY_FLOPS
+    fs_flops = 21.0 * na ** 3 * rows * nf
+    stages = {
+        "opacity_voigt": {"ms": round(t_op, 4), "flops": op_flops,
+                          "tflops": round(op_flops / (t_op * 1e-3) / 1e12, 3),
+                          "line_points": line_pts},
+        "formal_solution_dense": {"ms": round(t_fs, 4), "flops": fs_flops,
+                                  "tflops": round(fs_flops / (t_fs * 1e-3) / 1e12, 3)},
+        "rates_assemble_voigt": {"ms": round(t_ra, 4)},
+        "rates_solve": {"ms": round(t_so, 4)},
+    }
+    print(f"[voigt] {ms_per_step:.3f} ms/step; stages {stages}", file=sys.stderr, flush=True)
+    dom = max(("opacity_voigt", "formal_solution_dense"), key=lambda k: stages[k]["ms"])
+    kern = {"opacity_voigt": "k_ml_opacity", "formal_solution_dense": "k_fs_dense<8>"}[dom]
+    ach = stages[dom]["tflops"]
+    peaks = ctx.measure_peaks()
+    roofline = {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_VALU, "unit": "TFLOP/s",
+                "frac": round(ach / PEAK_FP64_VALU, 4), "traffic": None, "kernel": kern,
+                "kernel_ms": stages[dom]["ms"], "peak_measured": round(peaks["fp64_tflops"], 2),
+                "frac_of_measured": round(ach / peaks["fp64_tflops"], 4)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle.quadrature import gauss_legendre01
+        a1 = W.multilevel_atom(nbound=6, ncont=5, nd=128, na=8, nline_pts=100, ncont_pts=100,
+                               nb=1, seed=2, depth_profiles=True)
+        cpu = voigt_cpu_baseline(a1, *gauss_legendre01(na))
+    line = {
+        "metric": "formal-solution depth*angle*freq pts/s of the multilevel iteration, FP64",
+        "value": value, "unit": "pts/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{nb} atmospheres of the 6+1-level hydrogen-like atom (15 lines, "
+                               "5 continua, depth-dependent Voigt lines), nd 128, na 8, nf 2000, "
+                               "grey scattering continuum eps_c 1e-2, seed 2 (one multilevel "
+                               "iteration per step)",
+                   "nbatch": nb, "rows": rows, "na": na, "nf": nf, "points_per_step": pts, "seed": 2},
+        "roofline": roofline,
+        "stages": stages,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 

@@ -462,8 +462,11 @@ pprt_status pprt_measure_peaks(pprt_ctx* ctx, void* scratch, size_t bytes, pprt_
  *   [I - (1-eps) Lbar*] dS = (1-eps)(Jbar - S) + eps (B - S)
  * (tri-diagonal, diagonally dominant; Thomas elimination).
  * ng = 1 adds Ng acceleration (Ng 1974 in Auer's 1987 form, weights
- * 1/S^2): whenever four iterates have gathered since the first update or
- * the last extrapolation, S is replaced by the extrapolated iterate.
+ * 1/S^2).  It starts once an un-accelerated update changes S by less than
+ * 1e-2 (maximum relative change over the atmosphere; that update's old and
+ * new iterates open the first group); from then on, whenever four iterates
+ * have gathered since the last extrapolation, S is replaced by the
+ * extrapolated iterate.
  * Applies to pprt_two_level_ali_step / _update / _ali (not to the continuum
  * step).  Changes the workspace size: call before
  * pprt_plan_workspace_bytes.  pprt_two_level_ali resets Ng's history at

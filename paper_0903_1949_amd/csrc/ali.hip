@@ -128,9 +128,14 @@ __global__ __launch_bounds__(256) void k_profile_reduce(const double* __restrict
 //     [I - (1-eps) Lbar*] dS = (1-eps)(Jbar - S) + eps (B - S)
 // by Thomas elimination (the matrix is diagonally dominant: the rows of
 // Lambda sum to at most one, so no pivoting is needed).  Ng's extrapolation
-// (in Auer's form, weights 1/x0^2) is applied whenever four iterates have
-// gathered since the first update or the last extrapolation; the group
-// history lives in hist[3][rows] and ng_count[nb].
+// (in Auer's form, weights 1/x0^2) waits until an un-accelerated update
+// changes S by less than kNgStart (maximum relative change), whose old and new
+// iterates open the first group; from then on it is applied whenever four
+// iterates have gathered since the last extrapolation.  The group history
+// lives in hist[3][rows]; ng_count[nb] is 0 while waiting, else the number of
+// iterates in the group.
+constexpr double kNgStart = 1e-2;
+
 __global__ __launch_bounds__(256) void k_ali_update_nl(AliUpdateArgs a, AliNlArgs n) {
   __shared__ double red[5][256];
   __shared__ double ab[3];
@@ -186,8 +191,8 @@ __global__ __launch_bounds__(256) void k_ali_update_nl(AliUpdateArgs a, AliNlArg
   }
   __syncthreads();
   // ---- new iterate (and Ng's group)
-  const int cnt0 = n.ng ? n.ng_count[b] : 0;
-  const int cnt = (n.ng && cnt0 == 0) ? 1 : cnt0;   // the first update opens a group with S_old
+  const int cnt = n.ng ? n.ng_count[b] : 0;
+  const bool waiting = n.ng && cnt == 0;            // the update's S_old, S_new may open a group
   const bool extrap = n.ng && cnt == 3;
   double mx = 0.0;
   bool bad = false;
@@ -196,7 +201,7 @@ __global__ __launch_bounds__(256) void k_ali_update_nl(AliUpdateArgs a, AliNlArg
     const double So = a.S[r];
     const double dS = n.tri ? cf[r * 4 + 3] : cf[r * 4 + 3] / cf[r * 4 + 1];
     const double Sn = So + dS;
-    if (n.ng && cnt0 == 0) n.hist[r] = So;
+    if (waiting) n.hist[r] = So;
     if (extrap) {
       const double x0 = Sn, x1 = n.hist[2 * rows + r], x2 = n.hist[rows + r], x3 = n.hist[r];
       const double d0 = x0 - x1, d1 = x1 - x2, d2 = x2 - x3;
@@ -210,7 +215,7 @@ __global__ __launch_bounds__(256) void k_ali_update_nl(AliUpdateArgs a, AliNlArg
       cf[r * 4 + 0] = Sn;                 // keep x0 for the second pass
       continue;
     }
-    if (n.ng) n.hist[(int64_t)cnt * rows + r] = Sn;
+    if (n.ng) n.hist[(int64_t)(waiting ? 1 : cnt) * rows + r] = Sn;
     double rel = fabs(dS) / fabs(Sn);
     if (!isfinite(Sn) || !isfinite(rel)) {
       bad = true;
@@ -269,7 +274,7 @@ __global__ __launch_bounds__(256) void k_ali_update_nl(AliUpdateArgs a, AliNlArg
     if (a.iters != nullptr) it = (a.iters[b] += 1);
     if (a.active != nullptr && a.tol > 0.0 && m < a.tol) a.active[b] = 0;
     if (a.active != nullptr && a.max_iter > 0 && it >= a.max_iter) a.active[b] = 0;
-    if (n.ng) n.ng_count[b] = extrap ? 1 : cnt + 1;
+    if (n.ng) n.ng_count[b] = extrap ? 1 : waiting ? (m < kNgStart ? 2 : 0) : cnt + 1;
   }
 }
 
