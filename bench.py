@@ -208,14 +208,7 @@ def main():
                          "(includes capture, instantiation and a host check per chunk)"}
 
     achieved_tflops = pts * FLOPS_PER_POINT / (fs_ms * 1e-3) / 1e12
-    traffic = None
-    if os.path.exists(args.traffic_json):
-        try:
-            tj = json.load(open(args.traffic_json))
-            if tj.get("kernel_source_hash") == kernel_hash():
-                traffic = tj.get("bytes_per_launch", {}).get("total")
-        except Exception:
-            traffic = None
+    traffic = measured_traffic(args.traffic_json, "fs_diag.hip")
     peaks = ctx.measure_peaks()
     roofline = {"bound": "alu", "achieved": round(achieved_tflops, 3),
                 "peak": PEAK_FP32_VALU_NONPACKED, "unit": "TFLOP/s",
@@ -400,9 +393,11 @@ def bench_spherical(args):
 
     achieved = flops / (k_ms * 1e-3) / 1e12
     peaks = ctx.measure_peaks()
+    traffic = measured_traffic(os.path.join(ROOT, "profiles", "traffic_sph_fast_512spheres.json"), "sph.hip")
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VALU_NONPACKED,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU_NONPACKED, 4),
-                "traffic": None, "kernel": "k_sph_fast<float,16,true>", "kernel_ms": round(k_ms, 5),
+                "traffic": traffic, "kernel": "k_sph_fast<float,16,true>", "kernel_ms": round(k_ms, 5),
+                "hbm_gbs": round(traffic / (k_ms * 1e-3) / 1e9, 1) if traffic else None,
                 "flops_per_launch": flops,
                 "flops_per_point": SPH_FLOPS_PER_POINT,
                 "flops_per_tangent_segment": SPH_FLOPS_PER_TANGENT_SEGMENT,
@@ -690,12 +685,24 @@ def bench_voigt(args):
     print(json.dumps(line), flush=True)
 
 
-def kernel_hash() -> str:
-    """Hash of the sweep kernel source: traffic counters are only reported
-    while the kernel they were taken on is unchanged."""
+def kernel_hash(name: str = "fs_diag.hip") -> str:
+    """Hash of a kernel source: traffic counters are only reported while the
+    kernel they were taken on is unchanged."""
     import hashlib
-    src = os.path.join(ROOT, "paper_0903_1949_amd", "csrc", "fs_diag.hip")
+    src = os.path.join(ROOT, "paper_0903_1949_amd", "csrc", name)
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(path: str, source: str):
+    """HBM bytes per launch from a committed counter summary, if it was taken
+    on the current kernel source."""
+    try:
+        tj = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if tj.get("kernel_source_hash") != kernel_hash(source):
+        return None
+    return tj.get("bytes_per_launch", {}).get("total")
 
 
 if __name__ == "__main__":
