@@ -34,13 +34,17 @@
 // and element i of every vector), 64/NA frequencies per wave, one wave per
 // block.  Matrix products broadcast the right operand through the group's LDS
 // slab; the LDS operations of one wave execute in order and compiler fences
-// keep the program order.  Intensities travel in difference form
+// keep the program order.  The two passes are two kernels, each limited to
+// 256 registers so that two waves share a SIMD (fewer spills than three); the
+// eigen solutions of pass 1 (rows of V and the roots) stay in the workspace
+// for pass 2, and each root's Newton iteration starts from the same lane's
+// root of the previous layer.  Intensities travel in difference form
 // D = I - S^g (scaled), whose layer sources are +-(S^g(d+1) - S^g(d)) Q with
 // Q = beta_l+ + t sqrt(w), exact because a layer reproduces a constant S^g
 // (beta_c + t sqrt(w) + r sqrt(w) = sqrt(w)); J - S^g and H then keep their
 // relative accuracy where they are small.  Pass 1 (top -> bottom) stores the composite
 // reflection R_d and source Sigma_d of every node in the workspace; pass 2
-// (bottom -> top) recomputes the layer operators, builds the composites R^up,
+// (bottom -> top) rebuilds the layer operators from the kept eigen solutions, builds the composites R^up,
 // Sigma^up of the layers below and emits the node outputs:
 //     I+ = (I - R^up R)^-1 (R^up Sigma + Sigma^up),  I- = R I+ + Sigma,
 // and the same combination of the unit-source responses of the two layers
@@ -221,7 +225,7 @@ struct LaneTab {  // per-lane copies of the angle constants of row i
 // forms the Gu-Eisenstat vector and lane i keeps row i of V and its root.
 template <int NA>
 __device__ void eigen(Grp<NA>& g, const DenseTab<NA>& T, const LaneTab<NA>& L, double om,
-                      double (&V)[NA], double& k_i) {
+                      double (&V)[NA], double& k_i, double& lam_prev) {
   const int i = g.i;
   double lo = 0.0;
 #pragma unroll
@@ -265,7 +269,10 @@ __device__ void eigen(Grp<NA>& g, const DenseTab<NA>& T, const LaneTab<NA>& L, d
     if (i == 0 && sgn > 0.0 && om1 <= 0.0) {
       del = 0.0;                       // omega = 1: the diffusion root is exactly 0
     } else {
-      double x = 0.5 * (xl + xh);
+      // start from the root of the previous layer (same frequency, nearly the
+      // same omega) when it lies in this half of the interval, else mid-way
+      const double xp = sgn * (lam_prev - org);
+      double x = (xp > xl && xp < xh) ? xp : 0.5 * (xl + xh);
       for (int it = 0; it < 200; ++it) {
         double f, df;
         feval(org, sgn, x, f, df);
@@ -286,6 +293,7 @@ __device__ void eigen(Grp<NA>& g, const DenseTab<NA>& T, const LaneTab<NA>& L, d
   g.buf[Slab<NA>::ROOT + 2 * i + 1] = del;
   wsync();
   const double lam = org + del;
+  lam_prev = lam;
   k_i = sqrt(fmax(lam, 0.0));
   if (!(om > 0.0)) {
 #pragma unroll
@@ -408,14 +416,18 @@ struct FsDenseArgs {
   double *J, *JmS, *lstar, *lstar_c, *Iplus, *Iminus, *H, *Iemerg;
   double* wsR;     // [rows][nf][NA][NA]
   double* wsS;     // [rows][nf][NA]
+  double* wsV;     // [rows][nf][NA][NA+1]: eigen solution of layer (d, d+1), row i and root k_i
   int32_t nf;
   int32_t nitems;
   int32_t lower_bc;
   uint32_t outputs;
 };
 
-template <int NA>
-__global__ __launch_bounds__(64) void k_fs_dense(FsDenseArgs<NA> a, DenseTab<NA> T) {
+// PASS 1: the adding recursion down (composites R, Sigma and the layers'
+// eigen solutions into the workspace); PASS 2: the pass up with the outputs.
+// Two kernels, so that each holds only its own pass's registers.
+template <int NA, int PASS>
+__global__ __launch_bounds__(64, 2) void k_fs_dense(FsDenseArgs<NA> a, DenseTab<NA> T) {
   constexpr int F = 64 / NA;
   __shared__ double slab[F * Slab<NA>::SIZE];
   const int lane = (int)threadIdx.x;
@@ -450,12 +462,16 @@ __global__ __launch_bounds__(64) void k_fs_dense(FsDenseArgs<NA> a, DenseTab<NA>
   double* wsS = a.wsS + (row0 * nf + k) * NA + i;           // + node * nf * NA
   const int64_t strideR = (int64_t)nf * NA * NA;
   const int64_t strideS = (int64_t)nf * NA;
+  double* wsV = a.wsV + ((row0 * nf + k) * NA + i) * (NA + 1);   // + layer * nf * NA * (NA + 1)
+  const int64_t strideV = (int64_t)nf * NA * (NA + 1);
 
   double V[NA];
   double kk = 0.0;
   double om_prev = -1.0;
+  double lam_prev = -1.0;     // root of the last eigen solution (none yet)
   LayerOps<NA> op;
 
+  if constexpr (PASS == 1) {
   // ---------------- pass 1: adding recursion, top -> bottom
   double R[NA];
 #pragma unroll
@@ -468,9 +484,12 @@ __global__ __launch_bounds__(64) void k_fs_dense(FsDenseArgs<NA> a, DenseTab<NA>
     wsS[d * strideS] = Sig;
     const double om = layer_omega(d);
     if (om != om_prev) {
-      eigen<NA>(g, T, L, om, V, kk);
+      eigen<NA>(g, T, L, om, V, kk, lam_prev);
       om_prev = om;
     }
+#pragma unroll
+    for (int j = 0; j < NA; ++j) wsV[d * strideV + j] = V[j];
+    wsV[d * strideV + NA] = kk;
     const double Dl = layer_depth(d);
     layer_ops<NA>(g, T, L, V, kk, Dl, op);
     const double dSg = at(a.Sg, row0 + d + 1) - at(a.Sg, row0 + d);
@@ -498,7 +517,7 @@ __global__ __launch_bounds__(64) void k_fs_dense(FsDenseArgs<NA> a, DenseTab<NA>
 #pragma unroll
   for (int j = 0; j < NA; ++j) wsR[(nd - 1) * strideR + j] = R[j];
   wsS[(nd - 1) * strideS] = Sig;
-
+  } else {
   // ---------------- pass 2: bottom -> top, outputs per node
   double Rup[NA];
 #pragma unroll
@@ -522,12 +541,10 @@ __global__ __launch_bounds__(64) void k_fs_dense(FsDenseArgs<NA> a, DenseTab<NA>
   om_prev = -1.0;
   for (int d = nd - 1; d >= 0; --d) {
     const bool has_a = d >= 1;  // layer a = (d-1, d) above node d
-    if (has_a) {
-      const double om = layer_omega(d - 1);
-      if (om != om_prev) {
-        eigen<NA>(g, T, L, om, V, kk);
-        om_prev = om;
-      }
+    if (has_a) {      // the eigen solution of layer a, kept by pass 1
+#pragma unroll
+      for (int j = 0; j < NA; ++j) V[j] = wsV[(d - 1) * strideV + j];
+      kk = wsV[(d - 1) * strideV + NA];
       layer_ops<NA>(g, T, L, V, kk, layer_depth(d - 1), op);
     }
     // ---- emit node d
@@ -607,11 +624,14 @@ __global__ __launch_bounds__(64) void k_fs_dense(FsDenseArgs<NA> a, DenseTab<NA>
       Sup = Sup_n;
     }
   }
+  }
 }
 
 template <int NA>
 hipError_t launch_dense_t(int nitems, hipStream_t s, const void* args, const void* tab) {
-  hipLaunchKernelGGL((k_fs_dense<NA>), dim3(nitems), dim3(64), 0, s,
+  hipLaunchKernelGGL((k_fs_dense<NA, 1>), dim3(nitems), dim3(64), 0, s,
+                     *static_cast<const FsDenseArgs<NA>*>(args), *static_cast<const DenseTab<NA>*>(tab));
+  hipLaunchKernelGGL((k_fs_dense<NA, 2>), dim3(nitems), dim3(64), 0, s,
                      *static_cast<const FsDenseArgs<NA>*>(args), *static_cast<const DenseTab<NA>*>(tab));
   return hipGetLastError();
 }
@@ -636,6 +656,7 @@ hipError_t run_dense(const DenseLaunch& L, hipStream_t s) {
   a.Iminus = L.Iminus; a.H = L.H; a.Iemerg = L.Iemerg;
   a.wsR = L.ws;
   a.wsS = L.ws + (size_t)L.rows * L.nf * NA * NA;
+  a.wsV = a.wsS + (size_t)L.rows * L.nf * NA;
   a.nf = L.nf; a.nitems = L.nitems; a.lower_bc = L.lower_bc; a.outputs = L.outputs;
   DenseTab<NA> T{};
   fill_tab<NA>(T, L.mu, L.w);
@@ -647,7 +668,7 @@ hipError_t run_dense(const DenseLaunch& L, hipStream_t s) {
 bool dense_na_supported(int na) { return na == 1 || na == 2 || na == 4 || na == 8 || na == 16; }
 
 size_t dense_workspace_bytes(int na, int64_t rows, int nf) {
-  return (size_t)rows * nf * (size_t)(na * na + na) * sizeof(double);
+  return (size_t)rows * nf * (size_t)(2 * na * na + 2 * na) * sizeof(double);
 }
 
 int dense_freqs_per_item(int na) { return 64 / na; }
