@@ -136,3 +136,26 @@ def test_nonlocal_graph_replay_equals_eager(gpu_ctx):
         res[graph] = (db.S.clone(), iters.clone(), rep)
     assert torch.equal(res[True][0], res[False][0])
     assert torch.equal(res[True][1], res[False][1])
+
+
+def test_ng_schedule_on_a_thick_small_eps_atmosphere(gpu_ctx):
+    """The oracle's pin atmosphere for the Ng schedule (nd 151, eps 1.3e-6,
+    nf 21, na 4), where Ng applied from the first iterates stalls: the FP64
+    GPU iteration with the tri-diagonal operator and Ng converges to the
+    oracle's fixed point within one Ng cycle of its iteration count."""
+    b = W.two_level_batch(nb=4, nd_lo=150, nd_hi=230, na=4, nf=21, eps_lo=1e-6, eps_hi=1e-4, seed=5)
+    a = b.atmosphere(2)
+    plan = pprt.Plan(gpu_ctx, a.nd, a.na, a.nf, precision=pprt.FP64)
+    plan.set_operator(pprt.LSTAR_TRI, True)
+    db = pprt.upload_two_level(a, pprt.FP64)
+    db.S.copy_(db.B)
+    iters = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    rep = plan.two_level_ali(db.tau, db.q, db.S, db.eps, db.B, db.wphi, tol=1e-10,
+                             max_iter=1000, iters_per_sync=10, iters=iters)
+    ref = ali.two_level_ali_nonlocal(a.tau, a.q, a.phi, a.wnu, float(a.eps[0]), a.B, plan.mu, plan.w,
+                                     tol=1e-10, operator="tri", ng=True, max_iter=1000)
+    e = rel_err(db.S.cpu().numpy(), ref["S"])
+    print(f"  gpu {rep}, oracle {ref['iterations']}, S err {e:.2e}", flush=True)
+    assert rep["n_converged"] == 1 and ref["converged"]
+    assert abs(int(iters.item()) - ref["iterations"]) <= 4
+    assert e < 1e-9

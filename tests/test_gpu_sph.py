@@ -245,3 +245,44 @@ def test_sph_plan_argument_checks(gpu_ctx):
     Sg = _dev(np.ones((c.tau.shape[0], c.nf)), torch.float64)
     with pytest.raises(pprt.PprtError, match="E_INVALID_ARG"):   # diffusion needs Bbot
         plan.formal_solution(_dev(c.tau, torch.float64), _dev(c.q, torch.float64), Sg)
+    big = W.spherical_batch(nb=1, nd_lo=1001, nd_hi=1001, nf=4, n_core=4, seed=1)
+    with pytest.raises(pprt.PprtError, match="E_SHAPE"):          # more shells than the cap
+        pprt.SphPlan(gpu_ctx, big.nd, big.nf, big.r, big.n_core)
+
+
+def _edge_parity(ctx, c, outputs, precision=pprt.FP64):
+    rng = np.random.default_rng(23)
+    rows, nf, nb = c.tau.shape[0], c.nf, c.nb
+    Sg = rng.uniform(0.5, 1.5, size=(rows, nf))
+    Bb = rng.uniform(1.0, 1.5, size=(nb, nf))
+    Bp = Bb * rng.uniform(0.8, 1.0, size=(nb, nf))
+    dt = torch.float64 if precision == pprt.FP64 else torch.float32
+    plan = pprt.SphPlan(ctx, c.nd, nf, c.r, c.n_core, precision=precision, outputs=outputs)
+    out = plan.formal_solution(_dev(c.tau, torch.float64), _dev(c.q, dt), _dev(Sg, dt),
+                               Bbot=_dev(Bb, dt), Bbot_prev=_dev(Bp, dt))
+    torch.cuda.synchronize()
+    worst = {}
+    for b in range(nb):
+        s = c.rows(b)
+        ref = spherical.formal_solution_sph(c.r[s], c.tau[s], c.q[s], Sg[s], c.n_core,
+                                            Bbot=Bb[b], Bbot_prev=Bp[b])
+        for name, t in out.items():
+            worst[name] = max(worst.get(name, 0.0), rel_err(t.double().cpu().numpy()[s], ref[name]))
+    return worst
+
+
+@pytest.mark.parametrize("outputs", [OUTS, pprt.OUT_JMS | pprt.OUT_LSTAR_C], ids=["all", "group"])
+@pytest.mark.parametrize("shape", ["2shells_1core", "1freq", "40core", "400shells"])
+def test_sph_edge_shapes(gpu_ctx, outputs, shape):
+    """Degenerate and large shapes, FP64 against the oracle: two shells and a
+    single core ray (one group, every shell in its last G); one frequency
+    (63 idle lanes of the tile); 40 core rays (three groups hold core rays);
+    400 shells (about 26 ray groups per sphere)."""
+    kw = {"2shells_1core": dict(nb=2, nd_lo=2, nd_hi=2, nf=5, n_core=1),
+          "1freq": dict(nb=3, nd_lo=10, nd_hi=30, nf=1, n_core=6),
+          "40core": dict(nb=2, nd_lo=20, nd_hi=30, nf=7, n_core=40),
+          "400shells": dict(nb=1, nd_lo=400, nd_hi=400, nf=3, n_core=8)}[shape]
+    c = W.spherical_batch(tau_hi=1e8, B_slope=0.3, seed=31, **kw)
+    worst = _edge_parity(gpu_ctx, c, outputs)
+    print(f"  {shape}: " + ", ".join(f"{k} {v:.2e}" for k, v in worst.items()), flush=True)
+    assert max(worst.values()) < 1e-10
