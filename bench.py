@@ -396,7 +396,7 @@ def bench_spherical(args):
     traffic = measured_traffic(os.path.join(ROOT, "profiles", "traffic_sph_fast_512spheres.json"), "sph.hip")
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VALU_NONPACKED,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU_NONPACKED, 4),
-                "traffic": traffic, "kernel": "k_sph_fast<float,16,true>", "kernel_ms": round(k_ms, 5),
+                "traffic": traffic, "kernel": "k_sph_fast<float,10,true>", "kernel_ms": round(k_ms, 5),
                 "hbm_gbs": round(traffic / (k_ms * 1e-3) / 1e9, 1) if traffic else None,
                 "flops_per_launch": flops,
                 "flops_per_point": SPH_FLOPS_PER_POINT,
@@ -416,7 +416,7 @@ def bench_spherical(args):
                                "eps 1e-6..1e-1, seed 3 (one ALI step per step)",
                    "nbatch": c.nb, "rows": int(nd.sum()), "nf": c.nf, "n_core": n_core,
                    "points_per_step": pts, "seed": 3, "plan_build_s": round(t_plan, 3),
-                   "group_size": 16},
+                   "group_size": 10},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fp64": fp64,

@@ -1450,16 +1450,22 @@ pprt_status pprt_sph_plan_create(pprt_ctx* c, int32_t nb, const int32_t* nd, int
   p->nrays = (int32_t)rays.size();
   // Work lists of the group sweep: one wave per (unit, 64-frequency tile).  A
   // unit is a sphere (formal solution: group 0 stores the columns) or, for the
-  // two-level step of a batch too small to give the GPU 8192 waves, a chunk of
-  // consecutive ray groups: a sphere then takes up to four chunks of about
-  // equal work, in proportion to its work.  Units go by decreasing work; from
-  // 16 units on, the tiles of a unit go to blocks on one XCD (block i runs on
-  // XCD i mod 8), so its ray tables are read into one L2.
+  // two-level step, a chunk of consecutive ray groups.  The step aims at
+  // kStepWaves waves: a sphere takes chunks of about equal work in proportion
+  // to its work, at most kMaxChunks (its partial slots).  Sphere costs grow
+  // with the square of the shell count, and whole spheres leave the last
+  // resident waves of a launch on the largest ones: on 512 spheres of 48-256
+  // shells and 16 tiles, the 8192 whole-sphere waves took 8.45 ms and the
+  // chunked step 7.46 ms.  Units go by decreasing work; from 16 units on, the
+  // tiles of a unit go to blocks on one XCD (block i runs on XCD i mod 8), so
+  // its ray tables are read into one L2.
+  constexpr int64_t kStepWaves = 131072;
+  constexpr int kMaxChunks = 8;
   p->G = G;
   p->ntiles = (nf + 63) / 64;
   p->ndmax = *std::max_element(nd, nd + nb);
   const size_t es = precision == PPRT_FP64 ? sizeof(double) : sizeof(float);
-  p->wpb = (int)std::max<size_t>(1, std::min<size_t>(4, 65536 / (8 * (size_t)(p->ndmax + 1) * es)));
+  p->wpb = (int)std::max<size_t>(1, std::min<size_t>(4, 65536 / (2 * (size_t)(p->ndmax + 1) * es)));
   struct Unit { int b, g0, g1, slot, nslot; int64_t w; };
   const int nbk = (p->ntiles + p->wpb - 1) / p->wpb;       // blocks per unit
   auto layout = [&](std::vector<Unit> u, int& nblocks) {
@@ -1480,14 +1486,14 @@ pprt_status pprt_sph_plan_create(pprt_ctx* c, int32_t nb, const int32_t* nd, int
   std::vector<Unit> whole, chunks;
   int64_t wsum = 0;
   for (int64_t w_ : work) wsum += w_;
-  const int64_t units_wanted = (8192 + p->ntiles - 1) / p->ntiles;
+  const int64_t units_wanted = (kStepWaves + p->ntiles - 1) / p->ntiles;
   const double wchunk = nb >= units_wanted ? 1e300 : std::max(1.0, (double)wsum / (double)units_wanted);
   p->P = 1;
   for (int b = 0; b < nb; ++b) {
     const int ng = grp0[b + 1] - grp0[b];
     whole.push_back(Unit{b, 0, ng, 0, 1, work[b]});
     int S = (int)std::lround((double)work[b] / wchunk);
-    S = std::max(1, std::min(std::min(4, ng), S));
+    S = std::max(1, std::min(std::min(kMaxChunks, ng), S));
     p->P = std::max(p->P, S);
     // cut after the first group whose prefix reaches k/S of the work (each chunk non-empty)
     int g0 = 0;
@@ -1652,7 +1658,7 @@ pprt_status pprt_sph_formal_solution(pprt_sph_plan* p, const pprt_fs_in* in, ppr
 pprt_status pprt_sph_plan_workspace_bytes(const pprt_sph_plan* p, size_t* bytes) {
   if (!p || !bytes) return PPRT_E_INVALID_ARG;
   const size_t es = p->precision == PPRT_FP64 ? sizeof(double) : sizeof(float);
-  *bytes = align256((size_t)p->rows * p->ntiles * p->P * 4 * es);
+  *bytes = align256((size_t)p->rows * p->ntiles * ((p->P + 1) / 2) * 4 * es);
   return PPRT_OK;
 }
 
@@ -1679,7 +1685,7 @@ pprt_status pprt_sph_two_level_update(pprt_sph_plan* p, const pprt_two_level* at
   AliUpdateArgs u{};
   u.off = p->d_off; u.part = ws; u.eps = at->eps; u.B = at->B; u.S = S; u.max_rel = max_rel;
   u.active = const_cast<int32_t*>(active); u.iters = nullptr; u.status = c->d_status; u.tol = 0.0;
-  u.nw = p->ntiles * p->P; u.nb = p->nb; u.part_fp64 = p->precision == PPRT_FP64 ? 1 : 0;
+  u.nw = p->ntiles * ((p->P + 1) / 2); u.nb = p->nb; u.part_fp64 = p->precision == PPRT_FP64 ? 1 : 0;
   return hip_check(c, launch_ali_update(p->nb, c->stream, u), "ALI update launch");
 }
 

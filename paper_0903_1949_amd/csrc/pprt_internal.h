@@ -288,9 +288,9 @@ struct SphFastArgs {
   const T* wphi;            // [nf] profile weights (two-level step)
   T* JmS;                   // [rows][nf] J - S (formal solution)
   T* Lc;                    // [rows][nf] 1 - Lambda* (formal solution)
-  T* part;                  // [rows][ntiles * P][2][2] (two-level step) or nullptr
+  T* part;                  // [rows][ntiles][(P + 1) / 2][4]: slot s at 2s, 2s + 1 (two-level step) or nullptr
   int32_t nf, ntiles, lower_bc, n_core, ndmax;
-  int32_t P;                // partial-sum slots per tile
+  int32_t P;                // partial-sum slots (chunks) per tile
 };
 int sph_group_size(int precision);
 size_t sph_fast_lds_bytes(int precision, int wpb, int ndmax);

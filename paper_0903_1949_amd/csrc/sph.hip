@@ -185,13 +185,22 @@ __global__ __launch_bounds__(256) void k_fs_sph(SphArgs<T> a) {
 // Per ray the wave keeps in registers the difference-form intensity
 // D = I - S, the last inward psi (the outward start value of a tangent ray)
 // and the transmission E from the tangent point (the round trip of Lambda*).
-// q and S of a shell are read once per group; the group's geometry row
-// (path factor, its reciprocal, half weight) comes through scalar loads.  Each
-// shell's contribution of the group is added once: to the J - S and
-// 1 - Lambda* columns (formal solution), or, for the two-level step, already
-// summed with the profile weights over each 16-lane row of frequencies
-// (DPP) into the wave's per-row, per-shell totals in LDS, which end as the
-// tile's partial sums for the float64 update.
+// q and S of a shell are read once per group, one segment ahead (with tau and
+// the row's path-factor bounds), so that the loads of the next shell overlap
+// the arithmetic of this one; the group's geometry rows (path factor, its
+// reciprocal, half weight) come through scalar loads issued before the
+// current shell's flush.  Each shell's contribution of the group is added
+// once: to the J - S and 1 - Lambda* columns (formal solution), or, for the
+// two-level step, already summed with the profile weights over each 16-lane
+// row of frequencies (DPP) and added by the four row leaders (LDS atomics)
+// into the wave's per-shell totals in LDS, which end as the tile's partial
+// sums for the float64 update.
+//
+// Group size and occupancy were set by measurement on 512 spheres of 48-256
+// shells: FP32 groups of 10 rays at six waves per SIMD (80 registers, two
+// spilled) took 6.40 ms per two-level sweep, against 6.46 ms for 12 rays and
+// 6.48 ms for 8 rays at their best wave counts, and 7.29 ms for 16 rays at
+// four waves; the FP64 groups of 4 keep four waves.
 
 // A load from an address that is uniform over the wave, issued as a scalar load.
 template <typename T>
@@ -309,7 +318,8 @@ __device__ __forceinline__ float recip_t(float x) { return __builtin_amdgcn_rcpf
 __device__ __forceinline__ double recip_t(double x) { return 1.0 / x; }
 
 template <typename T, int G, bool PART>
-__global__ __launch_bounds__(256) void k_sph_fast(SphFastArgs<T> a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && PART) ? 6 : 4)))
+void k_sph_fast(SphFastArgs<T> a) {
   extern __shared__ __align__(16) unsigned char sph_lds[];
   const int lane = (int)(threadIdx.x & 63);
   const int wave = (int)(threadIdx.x >> 6);
@@ -329,22 +339,21 @@ __global__ __launch_bounds__(256) void k_sph_fast(SphFastArgs<T> a) {
   auto q_at = [&](int d) -> T { return qc[(o + d) * nf]; };
   auto S_at = [&](int d) -> T { return PART ? T(a.Sl[o + d]) : a.Sg[(o + d) * nf + kk]; };
   const T wp = PART ? (ok ? a.wphi[kk] : T(0)) : T(0);
-  // two-level step: per wave, the profile-weighted sums of each 16-lane row
-  // (4 rows x 2 quantities x ndmax shells, row stride ndmax + 1)
+  // two-level step: per wave, the profile-weighted sums over the tile
+  // (2 quantities x ndmax shells, stride ndmax + 1)
   const int rs = a.ndmax + 1;
-  T* acc = PART ? reinterpret_cast<T*>(sph_lds) + (int64_t)wave * 8 * rs : nullptr;
+  T* acc = PART ? reinterpret_cast<T*>(sph_lds) + (int64_t)wave * 2 * rs : nullptr;
   if (PART) {
-    for (int d = lane; d < 8 * rs; d += 64) acc[d] = T(0);
+    for (int d = lane; d < 2 * rs; d += 64) acc[d] = T(0);
   }
-  const int row = lane >> 4;
   // one shell's contribution of the current group
   auto flush = [&](int d, T vj, T vl, bool store) {
     if (PART) {
       const T sj = row_sum(wp * vj);
       const T sl = row_sum(wp * vl);
       if ((lane & 15) == 0) {
-        atomicAdd(acc + row * rs + d, sj);
-        atomicAdd(acc + (4 + row) * rs + d, sl);
+        atomicAdd(acc + d, sj);
+        atomicAdd(acc + rs + d, sl);
       }
     } else if (ok) {
       const int64_t x = (o + d) * nf + kk;
@@ -387,14 +396,26 @@ __global__ __launch_bounds__(256) void k_sph_fast(SphFastArgs<T> a) {
     T pth[G], ipt[G], hw[G];
     // regime of a shell's segments for the whole group (FP32, every ray with a
     // segment on row r): 0 all thin, 1 all thick, 2 per ray
-    auto regime = [&](T qa, int r) -> int {
+    auto regime = [&](T qa, T pmax, T pmin) -> int {
       if constexpr (sizeof(T) == 8) {
         return 2;
       } else {
         const unsigned long long act = __ballot(1);
-        if (__ballot(qa * sload(tx, 2 * r) < 0.25f) == act) return 0;
-        if (__ballot(qa * sload(tx, 2 * r + 1) >= 0.25f) == act) return 1;
+        if (__ballot(qa * pmax < 0.25f) == act) return 0;
+        if (__ballot(qa * pmin >= 0.25f) == act) return 1;
         return 2;
+      }
+    };
+    // the next shell's q, S, tau and regime bounds, loaded one segment ahead
+    T qp, Sp, xmx = T(0), xmn = T(0);
+    double tp;
+    auto prefetch = [&](int d, int r) {
+      qp = q_at(d);
+      Sp = S_at(d);
+      tp = a.tau[o + d];
+      if constexpr (sizeof(T) == 4) {
+        xmx = sload(tx, 2 * r);
+        xmn = sload(tx, 2 * r + 1);
       }
     };
     auto load_row = [&](int d, bool geo, bool wts) {
@@ -410,6 +431,8 @@ __global__ __launch_bounds__(256) void k_sph_fast(SphFastArgs<T> a) {
     };
     // ---- inward: node 0, then segments d-1 -> d
     T S0 = S_at(0), q0 = q_at(0);
+    double tu0 = a.tau[o];
+    prefetch(1, 0);
     {
       load_row(0, false, true);
       T hs = T(0);
@@ -422,15 +445,17 @@ __global__ __launch_bounds__(256) void k_sph_fast(SphFastArgs<T> a) {
         pl[g] = T(1);
       });
       flush(0, hs * D0, hs, first);
+      load_row(0, true, false);
+      load_row(mx > 0 ? 1 : 0, false, true);
     }
     auto inward = [&](int d, auto cond) {
       constexpr bool COND = decltype(cond)::value;
-      const T q1 = q_at(d), S1 = S_at(d);
-      const T qa = T(0.5) * (q0 + q1) * T(a.tau[o + d] - a.tau[o + d - 1]);
+      const T q1 = qp, S1 = Sp, pmax = xmx, pmin = xmn;
+      const double t1 = tp;
+      prefetch(d + 1 < nd ? d + 1 : nd - 1, d < mx ? d : mx);
+      const T qa = T(0.5) * (q0 + q1) * T(t1 - tu0);
       const T rq = recip_t(qa);
       const T dS = S0 - S1;
-      load_row(d - 1, true, false);
-      load_row(d, false, true);
       const int Td = Tb - d;
       T aj = T(0), al = T(0);
       auto rays = [&](auto rc) {
@@ -454,14 +479,18 @@ __global__ __launch_bounds__(256) void k_sph_fast(SphFastArgs<T> a) {
       if constexpr (COND) {
         rays(std::integral_constant<int, 2>{});
       } else {
-        const int R = regime(qa, d - 1);
+        const int R = regime(qa, pmax, pmin);
         if (R == 0) rays(std::integral_constant<int, 0>{});
         else if (R == 1) rays(std::integral_constant<int, 1>{});
         else rays(std::integral_constant<int, 2>{});
       }
+      // the next segment's rows, loaded while this shell is flushed
+      load_row(d, true, false);
+      load_row(d < mx ? d + 1 : mx, false, true);
       flush(d, aj, al, first);
       q0 = q1;
       S0 = S1;
+      tu0 = t1;
     };
     const int dA = Tb - G;                          // T(d) >= G for d <= dA
     {
@@ -475,7 +504,9 @@ __global__ __launch_bounds__(256) void k_sph_fast(SphFastArgs<T> a) {
     // node d+1 is its tangent node, E^2 alpha_d to node d+1 (taken from
     // 1 - Lambda*), so node d+1 is added one shell late.
     T Sn = S0, qn = q0;                              // node mx
+    double tn = tu0;
     T nj = T(0), nl = T(0);
+    prefetch(mx > 0 ? mx - 1 : 0, mx > 0 ? mx - 1 : 0);
     {
       load_row(mx, false, true);
       const int Td = Tb - mx;
@@ -493,13 +524,15 @@ __global__ __launch_bounds__(256) void k_sph_fast(SphFastArgs<T> a) {
         }
       });
     }
+    load_row(mx > 0 ? mx - 1 : 0, true, true);
     auto outward = [&](int d, auto cond) {
       constexpr bool COND = decltype(cond)::value;
-      const T Sd = S_at(d), qd = q_at(d);
-      const T qa = T(0.5) * (qd + qn) * T(a.tau[o + d + 1] - a.tau[o + d]);
+      const T Sd = Sp, qd = qp, pmax = xmx, pmin = xmn;
+      const double td = tp;
+      prefetch(d > 0 ? d - 1 : 0, d > 0 ? d - 1 : 0);
+      const T qa = T(0.5) * (qd + qn) * T(tn - td);
       const T rq = recip_t(qa);
       const T dS = Sn - Sd;
-      load_row(d, true, true);
       const T* nxt = tb + (int64_t)(d + 1) * 3 * G + 2 * G;   // half weights of node d+1
       const int Td = Tb - d;
       T aj = T(0), al = T(0);
@@ -538,16 +571,18 @@ __global__ __launch_bounds__(256) void k_sph_fast(SphFastArgs<T> a) {
       } else if (ncg > 0) {
         rays(I2{}, std::true_type{});
       } else {
-        const int R = regime(qa, d);
+        const int R = regime(qa, pmax, pmin);
         if (R == 0) rays(I0{}, std::false_type{});
         else if (R == 1) rays(I1{}, std::false_type{});
         else rays(I2{}, std::false_type{});
       }
+      load_row(d > 0 ? d - 1 : 0, true, true);
       flush(d + 1, nj, nl, false);
       nj = aj;
       nl = al;
       Sn = Sd;
       qn = qd;
+      tn = td;
     };
     {
       // no condition where T(d+1) >= G (every ray has a segment and the
@@ -562,22 +597,21 @@ __global__ __launch_bounds__(256) void k_sph_fast(SphFastArgs<T> a) {
     flush(0, nj, nl, false);
   }
   if (PART) {
-    // this chunk's slot; the first chunk also clears the slots its sphere leaves unused
+    // this chunk's slot: the (J - S, 1 - Lambda*) pair at 2 slot, 2 slot + 1 of
+    // the tile's (P + 1) / 2 four-value entries (the update adds entry values 0
+    // and 2, and 1 and 3); the first chunk also clears the slots its sphere
+    // leaves unused
     const int slot = __builtin_amdgcn_readfirstlane(it.slot);
     const int nslot = __builtin_amdgcn_readfirstlane(it.nslot);
-    const int P = a.P;
+    const int P2 = 2 * ((a.P + 1) >> 1);
     for (int d = lane; d < nd; d += 64) {
-      T* pp = a.part + ((o + d) * a.ntiles * P + (int64_t)tile * P) * 4;
-      pp[slot * 4 + 0] = (acc[d] + acc[rs + d]) + (acc[2 * rs + d] + acc[3 * rs + d]);
-      pp[slot * 4 + 1] = (acc[4 * rs + d] + acc[5 * rs + d]) + (acc[6 * rs + d] + acc[7 * rs + d]);
-      pp[slot * 4 + 2] = T(0);
-      pp[slot * 4 + 3] = T(0);
+      T* pp = a.part + ((o + d) * a.ntiles + tile) * (int64_t)P2 * 2;
+      pp[slot * 2 + 0] = acc[d];
+      pp[slot * 2 + 1] = acc[rs + d];
       if (slot == 0)
-        for (int c = nslot; c < P; ++c) {
-          pp[c * 4 + 0] = T(0);
-          pp[c * 4 + 1] = T(0);
-          pp[c * 4 + 2] = T(0);
-          pp[c * 4 + 3] = T(0);
+        for (int c = nslot; c < P2; ++c) {
+          pp[c * 2 + 0] = T(0);
+          pp[c * 2 + 1] = T(0);
         }
     }
   }
@@ -585,10 +619,10 @@ __global__ __launch_bounds__(256) void k_sph_fast(SphFastArgs<T> a) {
 
 }  // namespace
 
-int sph_group_size(int precision) { return precision == PPRT_FP64 ? 4 : 16; }
+int sph_group_size(int precision) { return precision == PPRT_FP64 ? 4 : 10; }
 
 size_t sph_fast_lds_bytes(int precision, int wpb, int ndmax) {
-  return (size_t)wpb * 8 * (ndmax + 1) * (precision == PPRT_FP64 ? sizeof(double) : sizeof(float));
+  return (size_t)wpb * 2 * (ndmax + 1) * (precision == PPRT_FP64 ? sizeof(double) : sizeof(float));
 }
 
 hipError_t launch_sph_fast(int precision, int nblocks, int wpb, hipStream_t s, const void* args) {
@@ -604,10 +638,10 @@ hipError_t launch_sph_fast(int precision, int nblocks, int wpb, hipStream_t s, c
   } else {
     const auto& a = *(const SphFastArgs<float>*)args;
     if (a.part)
-      hipLaunchKernelGGL((k_sph_fast<float, 16, true>), grid, block,
+      hipLaunchKernelGGL((k_sph_fast<float, 10, true>), grid, block,
                          sph_fast_lds_bytes(precision, wpb, a.ndmax), s, a);
     else
-      hipLaunchKernelGGL((k_sph_fast<float, 16, false>), grid, block, 0, s, a);
+      hipLaunchKernelGGL((k_sph_fast<float, 10, false>), grid, block, 0, s, a);
   }
   return hipGetLastError();
 }
