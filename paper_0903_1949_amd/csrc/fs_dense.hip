@@ -68,12 +68,18 @@ __device__ __forceinline__ void wsync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// A group's LDS slab.  Matrix rows are RS doubles apart: padded from NA >= 8
+// on, so that the lanes' 16-byte row stores fall on different banks.  The
+// slab stride is 2 (mod 16) doubles, so that the groups of a wave, which
+// read the same offsets of their own slabs, touch disjoint 4-bank spans.
 template <int NA>
 struct Slab {
-  static constexpr int MAT = (NA * NA > 2 * NA + 2) ? NA * NA : 2 * NA + 2;
+  static constexpr int RS = NA >= 8 ? NA + 2 : NA;
+  static constexpr int MAT = (NA * RS > 2 * NA + 2) ? NA * RS : 2 * NA + 2;
   static constexpr int VEC = MAT;            // 4 vector slots of NA
   static constexpr int ROOT = MAT + 4 * NA;  // 2 NA: root origin and offset
-  static constexpr int SIZE = MAT + 6 * NA;
+  static constexpr int USED = MAT + 6 * NA;
+  static constexpr int SIZE = USED + (18 - USED % 16) % 16;
 };
 
 // lane-group toolkit: lane i holds row i
@@ -85,7 +91,7 @@ struct Grp {
   __device__ __forceinline__ void put_mat(const double (&A)[NA]) {
     wsync();
 #pragma unroll
-    for (int j = 0; j < NA; ++j) buf[i * NA + j] = A[j];
+    for (int j = 0; j < NA; ++j) buf[i * Slab<NA>::RS + j] = A[j];
     wsync();
   }
   __device__ __forceinline__ void put_vec(double v, int slot) {
@@ -106,7 +112,7 @@ struct Grp {
     for (int k = 0; k < NA; ++k) {
       const double a = A[k];
 #pragma unroll
-      for (int j = 0; j < NA; ++j) acc[j] = fma(a, buf[k * NA + j], acc[j]);
+      for (int j = 0; j < NA; ++j) acc[j] = fma(a, buf[k * Slab<NA>::RS + j], acc[j]);
     }
 #pragma unroll
     for (int j = 0; j < NA; ++j) C[j] = acc[j];
@@ -219,6 +225,16 @@ struct LaneTab {  // per-lane copies of the angle constants of row i
   int ext;
 };
 
+// 1/x from the hardware reciprocal and two Newton-Raphson steps
+// (r <- r + r (1 - x r)); for finite nonzero normal x, within 1 ulp
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
 // ---- eigen solution of diag(d) - omega z z^T (d ascending) ------------------
 // Lane i finds root i in (d_{i-1}, d_i) (d_{-1} = 0) as org + del, org the
 // nearer end, by bracketed Newton on the secular function; the group then
@@ -242,7 +258,7 @@ __device__ void eigen(Grp<NA>& g, const DenseTab<NA>& T, const LaneTab<NA>& L, d
       if (i == 0 && o == 0.0) {
 #pragma unroll
         for (int j = 0; j < NA; ++j) {
-          const double r = 1.0 / (T.d[j] - sgn * x);
+          const double r = rcp_nr(T.d[j] - sgn * x);
           s = fma(T.w[j], r, s);
           s2 = fma(T.w[j] * T.d[j], r * r, s2);
         }
@@ -251,7 +267,7 @@ __device__ void eigen(Grp<NA>& g, const DenseTab<NA>& T, const LaneTab<NA>& L, d
       } else {
 #pragma unroll
         for (int j = 0; j < NA; ++j) {
-          const double r = 1.0 / ((T.d[j] - o) - sgn * x);
+          const double r = rcp_nr((T.d[j] - o) - sgn * x);
           s = fma(T.z2[j], r, s);
           s2 = fma(T.z2[j] * r, r, s2);
         }
@@ -278,7 +294,15 @@ __device__ void eigen(Grp<NA>& g, const DenseTab<NA>& T, const LaneTab<NA>& L, d
         feval(org, sgn, x, f, df);
         // lam = org + sgn x is too small when f > 0
         if ((f > 0.0) == (sgn > 0.0)) xl = x; else xh = x;
-        double xn = x - f / (df * sgn);
+        double xn = x - f * rcp_nr(df * sgn);
+        // a converged step ends the iteration before the bracket test: at the
+        // root (f == 0, or a step that rounds to nothing) the update above has
+        // just moved a bracket end onto x, and the test would take a bisection
+        // step away from it
+        if (fabs(xn - x) <= 2e-16 * x) {
+          x = xn;
+          break;
+        }
         if (!(xn > xl && xn < xh)) xn = 0.5 * (xl + xh);
         const double step = fabs(xn - x);
         x = xn;
@@ -315,7 +339,7 @@ __device__ void eigen(Grp<NA>& g, const DenseTab<NA>& T, const LaneTab<NA>& L, d
   double nrm = 0.0;
 #pragma unroll
   for (int j = 0; j < NA; ++j) {
-    const double q = g.vec(j, 2) / ((T.d[j] - org) - del);
+    const double q = g.vec(j, 2) * rcp_nr((T.d[j] - org) - del);
     nrm = fma(q, q, nrm);
   }
   g.put_vec(1.0 / sqrt(nrm), 3);
@@ -323,7 +347,7 @@ __device__ void eigen(Grp<NA>& g, const DenseTab<NA>& T, const LaneTab<NA>& L, d
   for (int a = 0; a < NA; ++a) {
     const double oa = g.buf[Slab<NA>::ROOT + 2 * a];
     const double da = g.buf[Slab<NA>::ROOT + 2 * a + 1];
-    V[a] = zh / ((L.d - oa) - da) * g.vec(a, 3);
+    V[a] = zh * rcp_nr((L.d - oa) - da) * g.vec(a, 3);
   }
 }
 
@@ -368,7 +392,7 @@ __device__ void layer_ops(Grp<NA>& g, const DenseTab<NA>& T, const LaneTab<NA>& 
     double st = 0.0, sc = 0.0;
 #pragma unroll
     for (int a = 0; a < NA; ++a) {
-      const double vja = g.buf[j * NA + a];
+      const double vja = g.buf[j * Slab<NA>::RS + a];
       st = fma(vt[a], vja, st);
       sc = fma(vc[a], vja, sc);
     }
