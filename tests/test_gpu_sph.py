@@ -189,6 +189,39 @@ def test_sph_ali_steps_parity(gpu_ctx, precision, nb, nd_lo, nd_hi, nf):
         assert em < (1e-6 if precision == pprt.FP64 else 1e-2)
 
 
+@pytest.mark.parametrize("precision", [pprt.FP64, pprt.FP32], ids=["fp64", "fp32"])
+def test_sph_ali_step_whole_spheres_at_scale(gpu_ctx, precision):
+    """A batch of 8192 small spheres at 16 frequency tiles already gives the
+    two-level step its 131,072 waves: every sphere is one unit with one partial
+    slot per tile (visible in the workspace size), the layout the chunked
+    batches above never reach.  S after one step on a sample of the spheres
+    (the smallest, the largest and 14 drawn at random) against the oracle."""
+    c = W.spherical_batch(nb=8192, nd_lo=3, nd_hi=6, nf=1024, n_core=2, eps_lo=1e-4,
+                          eps_hi=1e-1, tau_hi=1e4, B_slope=0.3, seed=12)
+    dt = torch.float64 if precision == pprt.FP64 else torch.float32
+    es = 8 if precision == pprt.FP64 else 4
+    plan = pprt.SphPlan(gpu_ctx, c.nd, c.nf, c.r, c.n_core, precision=precision)
+    rows = int(c.nd.sum())
+    assert plan.workspace_bytes == (rows * 16 * 4 * es + 255) // 256 * 256
+    a = _ali_inputs(c, dt)
+    S = _dev(c.B, torch.float64)
+    mx = torch.zeros(c.nb, dtype=torch.float64, device="cuda:0")
+    plan.two_level_ali_step(a["tau"], a["q"], S, a["eps"], a["B"], a["wphi"], mx)
+    torch.cuda.synchronize()
+    got = S.cpu().numpy()
+    rng = np.random.default_rng(3)
+    sample = sorted({int(np.argmin(c.nd)), int(np.argmax(c.nd)),
+                     *rng.choice(c.nb, size=14, replace=False).tolist()})
+    tol = 1e-10 if precision == pprt.FP64 else 2e-6
+    for b in sample:
+        s = c.rows(b)
+        ref = spherical.two_level_ali_sph(c.r[s], c.tau[s], c.q[s], c.phi, c.wnu, float(c.eps[b]),
+                                          c.B[s], c.n_core, tol=0.0, max_iter=1)
+        e = float(np.max(np.abs(got[s] / ref["S"] - 1)))
+        print(f"  b={b} nd={c.nd[b]}: S {e:.2e}", flush=True)
+        assert e < tol
+
+
 def test_sph_ali_converges_to_the_oracle(gpu_ctx):
     c = W.spherical_batch(nb=2, nd_lo=14, nd_hi=20, nf=25, n_core=5, eps_lo=1e-2, eps_hi=1e-1,
                           tau_hi=1e4, B_slope=0.3, seed=4)
