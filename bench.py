@@ -222,6 +222,7 @@ def main():
 
     # ---------------- plain FP64 path: one FP64 launch pair per atmosphere
     fp64 = None
+    fp64_batched = None
     if not args.no_fp64:
         off = batch.off
         plans, views = [], []
@@ -243,6 +244,18 @@ def main():
         w64 = (time.perf_counter() - t1) / args.fp64_steps
         fp64 = {"value": pts / w64, "ms_per_step": w64 * 1e3,
                 "desc": "FP64 sweep + update, one launch pair per atmosphere, untuned"}
+        # the batched step itself in FP64: same plan layout, k_fs_profile<double,8>
+        for _ in range(2):
+            plan64.two_level_ali_step(db64.tau, db64.q, db64.S, db64.eps, db64.B, db64.wphi, mx64)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.fp64_steps):
+            plan64.two_level_ali_step(db64.tau, db64.q, db64.S, db64.eps, db64.B, db64.wphi, mx64)
+        torch.cuda.synchronize()
+        wb64 = (time.perf_counter() - t1) / args.fp64_steps
+        fp64_batched = {"value": pts / wb64, "ms_per_step": wb64 * 1e3,
+                        "desc": "the same batched step in FP64 (k_fs_profile<double,8>: exp and "
+                                "expm1 per layer and angle; FP64 partials)"}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -264,6 +277,8 @@ def main():
         "graph_mode": graph,
         "fp64_plain": fp64,
         "speedup_vs_fp64_plain": (value / fp64["value"]) if fp64 else None,
+        "fp64_batched": fp64_batched,
+        "speedup_vs_fp64_batched": (value / fp64_batched["value"]) if fp64_batched else None,
         "fp32_vs_fp64": {"S_after_one_step_rel": rel_step, "update_rel": rel_update},
     }
     print(json.dumps(line), flush=True)
