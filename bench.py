@@ -61,7 +61,7 @@ def parse():
     ap.add_argument("--graph-chunk", type=int, default=25,
                     help="ALI iterations per captured graph in the graph-mode timing (0: skip)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_fs_profile_c3a.json"))
-    ap.add_argument("--workload", choices=["c3a", "spherical", "nonlocal", "voigt"], default="c3a",
+    ap.add_argument("--workload", choices=["c3a", "spherical", "nonlocal", "voigt", "c3b"], default="c3a",
                     help="c3a: the plane-parallel batch (default, the headline line); "
                          "spherical: the same batch shape as spheres (1D spherical symmetry); "
                          "nonlocal: c3a with the tri-diagonal approximate operator and Ng; "
@@ -121,6 +121,9 @@ def main():
         return
     if args.workload == "voigt":
         bench_voigt(args)
+        return
+    if args.workload == "c3b":
+        bench_c3b(args)
         return
     import torch
     from paper_0903_1949_amd import pprt
@@ -580,6 +583,7 @@ def bench_nonlocal(args):
 VOIGT_FLOPS = 300.0
 OPACITY_FLOPS = 20.0
 PEAK_FP64_VALU = 78.6
+DENSE_FLOPS_PER_LAYER = 21.0 * 8 ** 3   # the 21 NA^3 count per (layer, frequency) at NA = 8
 
 
 def voigt_cpu_baseline(atom1, mu, w):
@@ -595,6 +599,105 @@ def voigt_cpu_baseline(atom1, mu, w):
     return {"value": pts / dt, "unit": "pts/s", "cores": 1, "kind": "oracle",
             "sample": f"one multilevel iteration of one atmosphere (nd {int(atom1.nd.sum())}, na "
                       f"{atom1.na}, nf {atom1.nf}, {pts} points), numpy FP64, 1 thread, {dt:.1f} s"}
+
+
+def c3b_cpu_baseline(batch, mu, w, nsample=2):
+    """The oracle's two-level step with the scattering continuum (dense
+    formal solution, numpy FP64, one thread) on the smallest atmospheres."""
+    from threadpoolctl import threadpool_limits
+    from oracle import ali, dense
+    order = np.argsort(batch.nd, kind="stable")[:nsample]
+    off = batch.off
+    pts = 0
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        for b in order:
+            s = slice(int(off[b]), int(off[b + 1]))
+            ali.two_level_ali(batch.tau[s], batch.q[s], batch.phi, batch.wnu, float(batch.eps[b]),
+                              batch.B[s], mu, w, tol=1e-300, max_iter=1, S0=batch.S_trial[s],
+                              pfrac=batch.pfrac[s], sg_const=batch.sg_const[s],
+                              fs=dense.formal_solution_dense, fs_kwargs={"omega": batch.omega[s]})
+            pts += int(batch.nd[b]) * batch.na * batch.nf
+        dt = time.perf_counter() - t0
+    return {"value": pts / dt, "unit": "pts/s", "cores": 1, "kind": "oracle",
+            "sample": f"one step of the {nsample} smallest of the {batch.nb} atmospheres (nd "
+                      f"{int(batch.nd[order].min())}..{int(batch.nd[order].max())}, {pts} points), "
+                      f"numpy FP64, 1 thread, {dt:.1f} s"}
+
+
+def bench_c3b(args):
+    """The two-level step of the C3a batch with a grey coherent scattering
+    continuum inside the layers (chi_c/chi_l = 1e-3 per unit tau, eps_c =
+    1e-4): S^g assembly, the omega > 0 dense formal solution (FP64) at every
+    point, the profile quadratures and the FP64 update."""
+    import torch
+    from paper_0903_1949_amd import pprt
+    from paper_0903_1949_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    batch = W.two_level_batch(seed=3, cont_ratio=1e-3, eps_c=1e-4)
+    rows, nf, na = int(batch.nd.sum()), batch.nf, batch.na
+    pts = rows * na * nf
+    ctx = pprt.Context(0)
+    plan = pprt.Plan(ctx, batch.nd, na, nf, precision=pprt.FP64)
+    db = pprt.upload_two_level(batch, pprt.FP64)
+    d = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0")
+    pf, sc, om = d(batch.pfrac), d(batch.sg_const), d(batch.omega)
+    mx = torch.zeros(batch.nb, dtype=torch.float64, device="cuda:0")
+    stream = torch.cuda.current_stream()
+
+    def step(e0=None, e1=None):
+        if e0 is not None:
+            e0.record(stream)
+        plan.two_level_ali_step_continuum(db.tau, db.q, db.S, db.eps, db.B, db.wphi, pf, sc, om,
+                                          db.Bbot, db.Bbot_prev, mx)
+        if e1 is not None:
+            e1.record(stream)
+
+    steps, warmup = max(1, min(args.steps, 5)), max(1, min(args.warmup, 2))
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    print(f"c3b: {warmup} warm-up steps done", file=sys.stderr, flush=True)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    t0 = time.perf_counter()
+    for e0, e1 in evs:
+        step(e0, e1)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
+    flops = rows * nf * DENSE_FLOPS_PER_LAYER
+    achieved = flops / (step_ms * 1e-3) / 1e12
+    cpu = None if args.no_cpu_baseline else c3b_cpu_baseline(batch, plan.mu, plan.w)
+    line = {
+        "metric": "formal-solution depth*angle*freq pts/s of the two-level step with coherent "
+                  "continuum scattering, FP64 dense",
+        "value": pts / (wall / steps), "unit": "pts/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": wall * 1e3 / steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "512 two-level atmospheres of the headline batch (nd U{48..256}, na 8, "
+                               "nf 1024, seed 3) with a grey coherent continuum (r_c 1e-3, eps_c 1e-4): "
+                               "omega > 0 at every point (one ALI step per step)",
+                   "nbatch": batch.nb, "rows": rows, "na": na, "nf": nf, "points_per_step": pts,
+                   "workspace_gb": round(plan_continuum_workspace_gb(plan), 1)},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_VALU,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_VALU, 4), "traffic": None,
+                     "kernel": "k_fs_dense<8> (the whole step's event time, an upper bound on the "
+                               "dense passes' own)",
+                     "kernel_ms": round(step_ms, 3), "flops_per_layer_and_freq": DENSE_FLOPS_PER_LAYER,
+                     "peak_note": "FP64 vector, 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz"},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def plan_continuum_workspace_gb(plan):
+    import ctypes as C
+    nbytes = C.c_size_t()
+    plan.ctx._check(plan.lib.pprt_plan_continuum_workspace_bytes(plan.h, C.byref(nbytes)),
+                    "continuum_workspace_bytes")
+    return nbytes.value / 1e9
 
 
 def bench_voigt(args):
