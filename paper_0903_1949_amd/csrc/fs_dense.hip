@@ -560,6 +560,10 @@ __global__ __launch_bounds__(64, 2) void k_fs_dense(FsDenseArgs<NA> a, DenseTab<
     }
     (void)rl;
   }
+  // the unit-source responses behind Lambda* (plain form) and 1 - Lambda*
+  // (difference form) are formed only for the outputs that are wanted
+  const bool wd = (o & PPRT_OUT_LSTAR) != 0;
+  const bool we = (o & PPRT_OUT_LSTAR_C) != 0;
   double dSu = 0.0;           // dSigma^up of the node being emitted (layer below)
   double eSu = -L.sw;         // its difference-form counterpart (lower boundary: -1)
   om_prev = -1.0;
@@ -586,8 +590,9 @@ __global__ __launch_bounds__(64, 2) void k_fs_dense(FsDenseArgs<NA> a, DenseTab<
     // unit response: layer above (S^g 0 -> 1) through R_{d-1}, G_{d-1}; in
     // plain form (dS, for Lambda*) and in difference form (eS, sources +-Q
     // and -1 at a boundary, for 1 - Lambda* with full relative accuracy)
+    // (each response only when its output is wanted: wd, we are uniform)
     double dS = 0.0, eS = -L.sw;
-    if (has_a) {
+    if (has_a && (wd || we)) {
       double Rm[NA], Y[NA];
 #pragma unroll
       for (int j = 0; j < NA; ++j) Rm[j] = wsR[(d - 1) * strideR + j];
@@ -595,18 +600,25 @@ __global__ __launch_bounds__(64, 2) void k_fs_dense(FsDenseArgs<NA> a, DenseTab<
 #pragma unroll
       for (int j = 0; j < NA; ++j) Y[j] = ((j == i) ? 1.0 : 0.0) - Y[j];
       double y1 = op.blp, y2 = op.qv;
-      g.solve2(Y, y1, y2);                            // G_{d-1} (dbeta+_a, Q_a)
-      dS = g.mv(op.t, g.mv(Rm, y1)) + op.blm;
-      eS = g.mv(op.t, g.mv(Rm, y2)) - op.qv;
+      if (wd && we) g.solve2(Y, y1, y2);              // G_{d-1} (dbeta+_a, Q_a)
+      else if (wd) y1 = g.solve(Y, y1);
+      else y2 = g.solve(Y, y2);
+      if (wd) dS = g.mv(op.t, g.mv(Rm, y1)) + op.blm;
+      if (we) eS = g.mv(op.t, g.mv(Rm, y2)) - op.qv;
     }
-    const double dIp = g.mv(Xi, g.mv(Rup, dS) + dSu);
-    const double dIm = g.mv(Rd, dIp) + dS;
-    const double eDp = g.mv(Xi, g.mv(Rup, eS) + eSu);
-    const double eDm = g.mv(Rd, eDp) + eS;
     // Ip, Im are the scaled differences D+- = sqrt(w) (I+- - S^g)
     const double JmSn = 0.5 * g.sum(L.sw * (Ip + Im));
-    const double Ln = 0.5 * g.sum(L.sw * (dIp + dIm));
-    const double Lcn = -0.5 * g.sum(L.sw * (eDp + eDm));
+    double Ln = 0.0, Lcn = 0.0;
+    if (wd) {
+      const double dIp = g.mv(Xi, g.mv(Rup, dS) + dSu);
+      const double dIm = g.mv(Rd, dIp) + dS;
+      Ln = 0.5 * g.sum(L.sw * (dIp + dIm));
+    }
+    if (we) {
+      const double eDp = g.mv(Xi, g.mv(Rup, eS) + eSu);
+      const double eDm = g.mv(Rd, eDp) + eS;
+      Lcn = -0.5 * g.sum(L.sw * (eDp + eDm));
+    }
     const double Hn = 0.5 * g.sum(L.swmu * (Ip - Im));
     {
       const int64_t x = (row0 + d) * nf + k;
@@ -638,8 +650,8 @@ __global__ __launch_bounds__(64, 2) void k_fs_dense(FsDenseArgs<NA> a, DenseTab<
       const double Sup_n = g.mv(op.t, Sup + w1) + bp;
       // unit response of layer a seen from node d-1 (S^g 1 -> 0)
       const double dbm = op.bc - op.blm, dbp = op.bc - op.blp;
-      dSu = g.mv(op.t, g.mv(RG, dbm)) + dbp;
-      eSu = g.mv(op.t, g.mv(RG, op.qv)) - op.qv;
+      if (wd) dSu = g.mv(op.t, g.mv(RG, dbm)) + dbp;
+      if (we) eSu = g.mv(op.t, g.mv(RG, op.qv)) - op.qv;
       double RGt[NA], tRGt[NA];
       g.mul(RGt, RG, op.t);
       g.mul(tRGt, op.t, RGt);
