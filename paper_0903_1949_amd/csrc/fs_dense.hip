@@ -191,6 +191,64 @@ struct Grp {
     }
     wsync();
   }
+  // y1, y2, y3 with A y = b1, b2, b3; A is destroyed
+  __device__ __forceinline__ void solve3(double (&A)[NA], double& b1, double& b2, double& b3) {
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+      wsync();
+      if (i == k) {
+        const double p = 1.0 / A[k];
+#pragma unroll
+        for (int j = 0; j < NA; ++j) {
+          A[j] *= p;
+          buf[j] = A[j];
+        }
+        b1 *= p;
+        b2 *= p;
+        b3 *= p;
+        buf[NA] = b1;
+        buf[NA + 1] = b2;
+        buf[NA + 2] = b3;
+      }
+      wsync();
+      if (i != k) {
+        const double f = A[k];
+#pragma unroll
+        for (int j = 0; j < NA; ++j) A[j] = fma(-f, buf[j], A[j]);
+        b1 = fma(-f, buf[NA], b1);
+        b2 = fma(-f, buf[NA + 1], b2);
+        b3 = fma(-f, buf[NA + 2], b3);
+      }
+    }
+    wsync();
+  }
+  // X <- A^-1 X (X holds the right-hand side's rows on entry); A is destroyed
+  __device__ __forceinline__ void solve_mat(double (&X)[NA], double (&A)[NA]) {
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+      wsync();
+      if (i == k) {
+        const double p = 1.0 / A[k];
+#pragma unroll
+        for (int j = 0; j < NA; ++j) {
+          A[j] *= p;
+          X[j] *= p;
+          buf[j] = A[j];
+          buf[NA + j] = X[j];
+        }
+      }
+      wsync();
+      if (i != k) {
+        const double f = A[k];
+#pragma unroll
+        for (int j = 0; j < NA; ++j) {
+          A[j] = fma(-f, buf[j], A[j]);
+          X[j] = fma(-f, buf[NA + j], X[j]);
+        }
+      }
+    }
+    wsync();
+  }
   // y with A y = b (b_i in this lane); A is destroyed
   __device__ __forceinline__ double solve(double (&A)[NA], double b) {
 #pragma unroll
@@ -380,33 +438,44 @@ __device__ void layer_ops(Grp<NA>& g, const DenseTab<NA>& T, const LaneTab<NA>& 
   g.put_vec(cx, 3);
   // Q_T = V diag(tx) V^T and Q_C' = V diag(cx) V^T: broadcast V
   g.put_mat(V);
-  double AT[NA], AC[NA];
-  double vt[NA], vc[NA];
+  // one matrix at a time (fewer live registers): Q_T, then M + Q_T and its
+  // inverse, then D M + Q_C' and its inverse (the first inversion's pivot
+  // rows overwrite the slab's matrix region, so V is put there again)
+  double QT[NA], FT[NA], FC[NA];
+  {
+    double vt[NA];
 #pragma unroll
-  for (int a = 0; a < NA; ++a) {
-    vt[a] = V[a] * g.vec(a, 2);
-    vc[a] = V[a] * g.vec(a, 3);
-  }
+    for (int a = 0; a < NA; ++a) vt[a] = V[a] * g.vec(a, 2);
 #pragma unroll
-  for (int j = 0; j < NA; ++j) {
-    double st = 0.0, sc = 0.0;
+    for (int j = 0; j < NA; ++j) {
+      double st = 0.0;
 #pragma unroll
-    for (int a = 0; a < NA; ++a) {
-      const double vja = g.buf[j * Slab<NA>::RS + a];
-      st = fma(vt[a], vja, st);
-      sc = fma(vc[a], vja, sc);
+      for (int a = 0; a < NA; ++a) st = fma(vt[a], g.buf[j * Slab<NA>::RS + a], st);
+      QT[j] = st;
     }
-    AT[j] = st;
-    AC[j] = sc;
   }
-  double QT[NA];
+  {
+    double AT[NA];
 #pragma unroll
-  for (int j = 0; j < NA; ++j) QT[j] = AT[j];
-  AT[i] += L.m;                 // M + Q_T      (lane-dependent diagonal)
-  AC[i] += Dl * L.m;            // D M + Q_C'
-  double FT[NA], FC[NA];
-  g.inv(FT, AT);
-  g.inv(FC, AC);
+    for (int j = 0; j < NA; ++j) AT[j] = QT[j];
+    AT[i] += L.m;               // M + Q_T      (lane-dependent diagonal)
+    g.inv(FT, AT);
+  }
+  g.put_mat(V);
+  {
+    double vc[NA], AC[NA];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) vc[a] = V[a] * g.vec(a, 3);
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      double sc = 0.0;
+#pragma unroll
+      for (int a = 0; a < NA; ++a) sc = fma(vc[a], g.buf[j * Slab<NA>::RS + a], sc);
+      AC[j] = sc;
+    }
+    AC[i] += Dl * L.m;          // D M + Q_C'
+    g.inv(FC, AC);
+  }
   double tw = 0.0, rw = 0.0, fw = 0.0, qv = 0.0;
 #pragma unroll
   for (int j = 0; j < NA; ++j) {
@@ -580,13 +649,6 @@ __global__ __launch_bounds__(64, 2) void k_fs_dense(FsDenseArgs<NA> a, DenseTab<
 #pragma unroll
     for (int j = 0; j < NA; ++j) Rd[j] = wsR[d * strideR + j];
     const double Sd = wsS[d * strideS];
-    double X[NA], Xi[NA];
-    g.mul(X, Rup, Rd);
-#pragma unroll
-    for (int j = 0; j < NA; ++j) X[j] = ((j == i) ? 1.0 : 0.0) - X[j];
-    g.inv(Xi, X);
-    const double Ip = g.mv(Xi, g.mv(Rup, Sd) + Sup);
-    const double Im = g.mv(Rd, Ip) + Sd;
     // unit response: layer above (S^g 0 -> 1) through R_{d-1}, G_{d-1}; in
     // plain form (dS, for Lambda*) and in difference form (eS, sources +-Q
     // and -1 at a boundary, for 1 - Lambda* with full relative accuracy)
@@ -606,16 +668,26 @@ __global__ __launch_bounds__(64, 2) void k_fs_dense(FsDenseArgs<NA> a, DenseTab<
       if (wd) dS = g.mv(op.t, g.mv(Rm, y1)) + op.blm;
       if (we) eS = g.mv(op.t, g.mv(Rm, y2)) - op.qv;
     }
+    // I+ and the two responses from one elimination on I - R^up R_d
+    double Ip = g.mv(Rup, Sd) + Sup;
+    double dIp = wd ? g.mv(Rup, dS) + dSu : 0.0;
+    double eDp = we ? g.mv(Rup, eS) + eSu : 0.0;
+    {
+      double X[NA];
+      g.mul(X, Rup, Rd);
+#pragma unroll
+      for (int j = 0; j < NA; ++j) X[j] = ((j == i) ? 1.0 : 0.0) - X[j];
+      g.solve3(X, Ip, dIp, eDp);
+    }
+    const double Im = g.mv(Rd, Ip) + Sd;
     // Ip, Im are the scaled differences D+- = sqrt(w) (I+- - S^g)
     const double JmSn = 0.5 * g.sum(L.sw * (Ip + Im));
     double Ln = 0.0, Lcn = 0.0;
     if (wd) {
-      const double dIp = g.mv(Xi, g.mv(Rup, dS) + dSu);
       const double dIm = g.mv(Rd, dIp) + dS;
       Ln = 0.5 * g.sum(L.sw * (dIp + dIm));
     }
     if (we) {
-      const double eDp = g.mv(Xi, g.mv(Rup, eS) + eSu);
       const double eDm = g.mv(Rd, eDp) + eS;
       Lcn = -0.5 * g.sum(L.sw * (eDp + eDm));
     }
@@ -640,12 +712,15 @@ __global__ __launch_bounds__(64, 2) void k_fs_dense(FsDenseArgs<NA> a, DenseTab<
       const double dSg = at(a.Sg, row0 + d) - at(a.Sg, row0 + d - 1);
       const double bp = dSg * op.qv;
       const double bm = -dSg * op.qv;
-      double Y[NA], Gu[NA], RG[NA];
-      g.mul(Y, op.r, Rup);
+      // R^up G^up = R^up (I - r R^up)^-1 = (I - R^up r)^-1 R^up
+      double Y[NA], RG[NA];
+      g.mul(Y, Rup, op.r);
 #pragma unroll
-      for (int j = 0; j < NA; ++j) Y[j] = ((j == i) ? 1.0 : 0.0) - Y[j];
-      g.inv(Gu, Y);                                  // (I - r R^up)^-1
-      g.mul(RG, Rup, Gu);                            // R^up G^up
+      for (int j = 0; j < NA; ++j) {
+        Y[j] = ((j == i) ? 1.0 : 0.0) - Y[j];
+        RG[j] = Rup[j];
+      }
+      g.solve_mat(RG, Y);
       const double w1 = g.mv(RG, g.mv(op.r, Sup) + bm);
       const double Sup_n = g.mv(op.t, Sup + w1) + bp;
       // unit response of layer a seen from node d-1 (S^g 1 -> 0)
