@@ -82,6 +82,16 @@ struct Slab {
   static constexpr int SIZE = USED + (18 - USED % 16) % 16;
 };
 
+// 1/x from the hardware reciprocal and two Newton-Raphson steps
+// (r <- r + r (1 - x r)); for finite nonzero normal x, within 1 ulp
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
 // lane-group toolkit: lane i holds row i
 template <int NA>
 struct Grp {
@@ -142,7 +152,7 @@ struct Grp {
     for (int k = 0; k < NA; ++k) {
       wsync();
       if (i == k) {
-        const double p = 1.0 / A[k];
+        const double p = rcp_nr(A[k]);
 #pragma unroll
         for (int j = 0; j < NA; ++j) {
           A[j] *= p;
@@ -169,7 +179,7 @@ struct Grp {
     for (int k = 0; k < NA; ++k) {
       wsync();
       if (i == k) {
-        const double p = 1.0 / A[k];
+        const double p = rcp_nr(A[k]);
 #pragma unroll
         for (int j = 0; j < NA; ++j) {
           A[j] *= p;
@@ -197,7 +207,7 @@ struct Grp {
     for (int k = 0; k < NA; ++k) {
       wsync();
       if (i == k) {
-        const double p = 1.0 / A[k];
+        const double p = rcp_nr(A[k]);
 #pragma unroll
         for (int j = 0; j < NA; ++j) {
           A[j] *= p;
@@ -228,7 +238,7 @@ struct Grp {
     for (int k = 0; k < NA; ++k) {
       wsync();
       if (i == k) {
-        const double p = 1.0 / A[k];
+        const double p = rcp_nr(A[k]);
 #pragma unroll
         for (int j = 0; j < NA; ++j) {
           A[j] *= p;
@@ -255,7 +265,7 @@ struct Grp {
     for (int k = 0; k < NA; ++k) {
       wsync();
       if (i == k) {
-        const double p = 1.0 / A[k];
+        const double p = rcp_nr(A[k]);
 #pragma unroll
         for (int j = 0; j < NA; ++j) {
           A[j] *= p;
@@ -283,15 +293,6 @@ struct LaneTab {  // per-lane copies of the angle constants of row i
   int ext;
 };
 
-// 1/x from the hardware reciprocal and two Newton-Raphson steps
-// (r <- r + r (1 - x r)); for finite nonzero normal x, within 1 ulp
-__device__ __forceinline__ double rcp_nr(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
-}
 
 // ---- eigen solution of diag(d) - omega z z^T (d ascending) ------------------
 // Lane i finds root i in (d_{i-1}, d_i) (d_{-1} = 0) as org + del, org the
