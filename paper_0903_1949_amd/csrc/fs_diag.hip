@@ -37,30 +37,37 @@ namespace {
 // (wave, layer, angle) triples in line-formation atmospheres), otherwise both
 // run and each lane selects its own.
 template <bool AG>
+__device__ __forceinline__ void layer_w_thin(float D, float& e_, float& ps_, float& al_, float& ga_) {
+  ps_ = fmaf(D, fmaf(D, fmaf(D, fmaf(D, fmaf(D, -1.f / 720.f, 1.f / 120.f), -1.f / 24.f),
+                             1.f / 6.f), -0.5f), 1.f);
+  e_ = fmaf(-D, ps_, 1.f);
+  if (AG) {
+    al_ = D * fmaf(-D, fmaf(-D, fmaf(-D, fmaf(-D, fmaf(-D, 1.f / 5040.f, 1.f / 720.f),
+                                               1.f / 120.f), 1.f / 24.f), 1.f / 6.f), 0.5f);
+    ga_ = fmaf(D, ps_, -al_);
+  }
+}
+template <bool AG>
+__device__ __forceinline__ void layer_w_thick(float dt, float inv_dt, float c, float mu, float& e_,
+                                              float& ps_, float& al_, float& ga_) {
+  e_ = __builtin_amdgcn_exp2f(-(dt * c));        // v_exp_f32; c = log2(e)/mu
+  const float m = mu * inv_dt;
+  ps_ = fmaf(-e_, m, m);
+  if (AG) {
+    al_ = 1.f - ps_;
+    ga_ = ps_ - e_;
+  }
+}
+template <bool AG>
 __device__ __forceinline__ void layer_w(float dt, float inv_dt, float c, float rmu, float mu,
                                         float& e, float& ps, float& al, float& ga) {
   const float D = dt * rmu;
   const bool thin = D < 0.25f;
   const unsigned long long act = __ballot(1);
   const unsigned long long tb = __ballot(thin);
-  auto thin_w = [&](float& e_, float& ps_, float& al_, float& ga_) {
-    ps_ = fmaf(D, fmaf(D, fmaf(D, fmaf(D, fmaf(D, -1.f / 720.f, 1.f / 120.f), -1.f / 24.f),
-                               1.f / 6.f), -0.5f), 1.f);
-    e_ = fmaf(-D, ps_, 1.f);
-    if (AG) {
-      al_ = D * fmaf(-D, fmaf(-D, fmaf(-D, fmaf(-D, fmaf(-D, 1.f / 5040.f, 1.f / 720.f),
-                                                 1.f / 120.f), 1.f / 24.f), 1.f / 6.f), 0.5f);
-      ga_ = fmaf(D, ps_, -al_);
-    }
-  };
+  auto thin_w = [&](float& e_, float& ps_, float& al_, float& ga_) { layer_w_thin<AG>(D, e_, ps_, al_, ga_); };
   auto thick_w = [&](float& e_, float& ps_, float& al_, float& ga_) {
-    e_ = __builtin_amdgcn_exp2f(-(dt * c));      // v_exp_f32; c = log2(e)/mu
-    const float m = mu * inv_dt;
-    ps_ = fmaf(-e_, m, m);
-    if (AG) {
-      al_ = 1.f - ps_;
-      ga_ = ps_ - e_;
-    }
+    layer_w_thick<AG>(dt, inv_dt, c, mu, e_, ps_, al_, ga_);
   };
   if (tb == act) {
     thin_w(e, ps, al, ga);
@@ -507,16 +514,39 @@ __device__ __forceinline__ void profile_sweep(const FsProfileArgs<T>& a, const A
     T ls = T(0), band = T(0);
     if (TRI) {
       // with the neighbour coupling: the layer's alpha, gamma and e per angle
-      // (accurate series for thin layers), band = 1/2 sum w (gamma + e alpha_prev)
+      // (accurate series for thin layers), band = 1/2 sum w (gamma + e alpha_prev).
+      // FP32 decides the regime once per layer when every angle agrees in
+      // every lane (the thresholds of sweep_layer), else per angle.
       const T inv = recip(dt);
+      if constexpr (std::is_same<T, float>::value) {
+        auto layer = [&](auto rc) {
+          constexpr int R = decltype(rc)::value;
 #pragma unroll
-      for (int i = 0; i < NA; ++i) {
-        T e, ps, al, ga;
-        layer_w<true>(dt, inv, ang.c[i], ang.rmu[i], ang.mu[i], e, ps, al, ga);
-        D[i] = e * D[i] + ps * dS;
-        ls += ang.hw[i] * ps;
-        band += ang.hw[i] * (ga + e * aprev[i]);
-        aprev[i] = al;
+          for (int i = 0; i < NA; ++i) {
+            float e, ps, al, ga;
+            if constexpr (R == 0) layer_w_thin<true>(dt * ang.rmu[i], e, ps, al, ga);
+            else if constexpr (R == 1) layer_w_thick<true>(dt, inv, ang.c[i], ang.mu[i], e, ps, al, ga);
+            else layer_w<true>(dt, inv, ang.c[i], ang.rmu[i], ang.mu[i], e, ps, al, ga);
+            D[i] = e * D[i] + ps * dS;
+            ls += ang.hw[i] * ps;
+            band += ang.hw[i] * (ga + e * aprev[i]);
+            aprev[i] = al;
+          }
+        };
+        const unsigned long long act = __ballot(1);
+        if (__ballot(dt < ang.dt_all_thin) == act) layer(std::integral_constant<int, 0>{});
+        else if (__ballot(dt >= ang.dt_all_thick) == act) layer(std::integral_constant<int, 1>{});
+        else layer(std::integral_constant<int, 2>{});
+      } else {
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+          T e, ps, al, ga;
+          layer_w<true>(dt, inv, ang.c[i], ang.rmu[i], ang.mu[i], e, ps, al, ga);
+          D[i] = e * D[i] + ps * dS;
+          ls += ang.hw[i] * ps;
+          band += ang.hw[i] * (ga + e * aprev[i]);
+          aprev[i] = al;
+        }
       }
     } else {
       sweep_layer(ang, dt, dS, D, ls);
