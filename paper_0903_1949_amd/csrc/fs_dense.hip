@@ -259,6 +259,37 @@ struct Grp {
     }
     wsync();
   }
+  // X <- A^-1 X and b <- A^-1 b (X and b hold the right-hand sides on entry);
+  // A is destroyed
+  __device__ __forceinline__ void solve_mat_v(double (&X)[NA], double (&A)[NA], double& b) {
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+      wsync();
+      if (i == k) {
+        const double p = rcp_nr(A[k]);
+#pragma unroll
+        for (int j = 0; j < NA; ++j) {
+          A[j] *= p;
+          X[j] *= p;
+          buf[j] = A[j];
+          buf[NA + j] = X[j];
+        }
+        b *= p;
+        buf[2 * NA] = b;
+      }
+      wsync();
+      if (i != k) {
+        const double f = A[k];
+#pragma unroll
+        for (int j = 0; j < NA; ++j) {
+          A[j] = fma(-f, buf[j], A[j]);
+          X[j] = fma(-f, buf[NA + j], X[j]);
+        }
+        b = fma(-f, buf[2 * NA], b);
+      }
+    }
+    wsync();
+  }
   // y with A y = b (b_i in this lane); A is destroyed
   __device__ __forceinline__ double solve(double (&A)[NA], double b) {
 #pragma unroll
@@ -589,15 +620,17 @@ __global__ __launch_bounds__(64, 2) void k_fs_dense(FsDenseArgs<NA> a, DenseTab<
     const double dSg = at(a.Sg, row0 + d + 1) - at(a.Sg, row0 + d);
     const double bp = dSg * op.qv;        // difference-form layer sources
     const double bm = -dSg * op.qv;
-    // G = (I - r R)^-1, P = G t, u = G (r Sigma + beta+)
-    double X[NA], G[NA], P[NA];
+    // G = (I - r R)^-1: P = G t and u = G (r Sigma + beta+) from one
+    // elimination on I - r R with t and r Sigma + beta+ as right-hand sides
+    double X[NA], P[NA];
     g.mul(X, op.r, R);
 #pragma unroll
-    for (int j = 0; j < NA; ++j) X[j] = ((j == i) ? 1.0 : 0.0) - X[j];
-    g.inv(G, X);
-    g.mul(P, G, op.t);
-    const double v = g.mv(op.r, Sig) + bp;
-    const double u = g.mv(G, v);
+    for (int j = 0; j < NA; ++j) {
+      X[j] = ((j == i) ? 1.0 : 0.0) - X[j];
+      P[j] = op.t[j];
+    }
+    double u = g.mv(op.r, Sig) + bp;
+    g.solve_mat_v(P, X, u);
     // Sigma_{d+1} = t (Sigma + R u) + beta-,  R_{d+1} = r + t R P
     const double Ru = g.mv(R, u);
     const double Sig_n = g.mv(op.t, Sig + Ru) + bm;
