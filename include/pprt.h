@@ -190,8 +190,10 @@ pprt_status pprt_formal_solution(pprt_plan* plan, const pprt_fs_in* in, pprt_fs_
  * gets I+-, J, J - S^g, H and the exact diagonal Lambda*_dd = dJ(d)/dS^g(d)
  * with 1 - Lambda*.  FP64 plans only, na in {1, 2, 4, 8, 16}
  * (E_UNSUPPORTED otherwise).  Needs a workspace of
- * pprt_plan_scattering_workspace_bytes() (it holds the composite reflection
- * and source of every node and frequency between the two passes); omega = 0
+ * pprt_plan_scattering_workspace_bytes(): 8 (2 na^2 + 4 na) bytes per node
+ * and frequency, the composite reflection and source of every node, each
+ * layer's eigen solution and two of its unit-source responses, kept between
+ * the top-down and the bottom-up pass; omega = 0
  * everywhere reproduces pprt_formal_solution to rounding. */
 pprt_status pprt_plan_scattering_workspace_bytes(const pprt_plan* plan, size_t* bytes);
 pprt_status pprt_formal_solution_scattering(pprt_plan* plan, const pprt_fs_in* in,

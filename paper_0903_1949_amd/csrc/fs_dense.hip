@@ -75,7 +75,7 @@ __device__ __forceinline__ void wsync() {
 template <int NA>
 struct Slab {
   static constexpr int RS = NA >= 8 ? NA + 2 : NA;
-  static constexpr int MAT = (NA * RS > 2 * NA + 2) ? NA * RS : 2 * NA + 2;
+  static constexpr int MAT = (NA * RS > 2 * NA + 3) ? NA * RS : 2 * NA + 3;
   static constexpr int VEC = MAT;            // 4 vector slots of NA
   static constexpr int ROOT = MAT + 4 * NA;  // 2 NA: root origin and offset
   static constexpr int USED = MAT + 6 * NA;
@@ -259,9 +259,10 @@ struct Grp {
     }
     wsync();
   }
-  // X <- A^-1 X and b <- A^-1 b (X and b hold the right-hand sides on entry);
-  // A is destroyed
-  __device__ __forceinline__ void solve_mat_v(double (&X)[NA], double (&A)[NA], double& b) {
+  // X <- A^-1 X and b0, b1, b2 <- A^-1 b0, b1, b2 (right-hand sides on
+  // entry); A is destroyed
+  __device__ __forceinline__ void solve_mat_v3(double (&X)[NA], double (&A)[NA], double& b0,
+                                               double& b1, double& b2) {
 #pragma unroll
     for (int k = 0; k < NA; ++k) {
       wsync();
@@ -274,8 +275,12 @@ struct Grp {
           buf[j] = A[j];
           buf[NA + j] = X[j];
         }
-        b *= p;
-        buf[2 * NA] = b;
+        b0 *= p;
+        b1 *= p;
+        b2 *= p;
+        buf[2 * NA] = b0;
+        buf[2 * NA + 1] = b1;
+        buf[2 * NA + 2] = b2;
       }
       wsync();
       if (i != k) {
@@ -285,7 +290,9 @@ struct Grp {
           A[j] = fma(-f, buf[j], A[j]);
           X[j] = fma(-f, buf[NA + j], X[j]);
         }
-        b = fma(-f, buf[2 * NA], b);
+        b0 = fma(-f, buf[2 * NA], b0);
+        b1 = fma(-f, buf[2 * NA + 1], b1);
+        b2 = fma(-f, buf[2 * NA + 2], b2);
       }
     }
     wsync();
@@ -542,6 +549,7 @@ struct FsDenseArgs {
   double* wsR;     // [rows][nf][NA][NA]
   double* wsS;     // [rows][nf][NA]
   double* wsV;     // [rows][nf][NA][NA+1]: eigen solution of layer (d, d+1), row i and root k_i
+  double* wsZ;     // [rows][nf][NA][2]: R_d G_d beta+ and R_d G_d Q of layer (d, d+1), element i
   int32_t nf;
   int32_t nitems;
   int32_t lower_bc;
@@ -589,6 +597,12 @@ __global__ __launch_bounds__(64, 2) void k_fs_dense(FsDenseArgs<NA> a, DenseTab<
   const int64_t strideS = (int64_t)nf * NA;
   double* wsV = a.wsV + ((row0 * nf + k) * NA + i) * (NA + 1);   // + layer * nf * NA * (NA + 1)
   const int64_t strideV = (int64_t)nf * NA * (NA + 1);
+  double* wsZ = a.wsZ + ((row0 * nf + k) * NA + i) * 2;          // + layer * nf * NA * 2
+  const int64_t strideZ = (int64_t)nf * NA * 2;
+  // the unit-source responses behind Lambda* (plain form) and 1 - Lambda*
+  // (difference form) are formed only for the outputs that are wanted
+  const bool wd = (o & PPRT_OUT_LSTAR) != 0;
+  const bool we = (o & PPRT_OUT_LSTAR_C) != 0;
 
   double V[NA];
   double kk = 0.0;
@@ -620,8 +634,8 @@ __global__ __launch_bounds__(64, 2) void k_fs_dense(FsDenseArgs<NA> a, DenseTab<
     const double dSg = at(a.Sg, row0 + d + 1) - at(a.Sg, row0 + d);
     const double bp = dSg * op.qv;        // difference-form layer sources
     const double bm = -dSg * op.qv;
-    // G = (I - r R)^-1: P = G t and u = G (r Sigma + beta+) from one
-    // elimination on I - r R with t and r Sigma + beta+ as right-hand sides
+    // G = (I - r R)^-1: P = G t, u = G (r Sigma + beta+), and for pass 2's
+    // unit responses G beta_l+ and G Q, from one elimination on I - r R
     double X[NA], P[NA];
     g.mul(X, op.r, R);
 #pragma unroll
@@ -630,7 +644,10 @@ __global__ __launch_bounds__(64, 2) void k_fs_dense(FsDenseArgs<NA> a, DenseTab<
       P[j] = op.t[j];
     }
     double u = g.mv(op.r, Sig) + bp;
-    g.solve_mat_v(P, X, u);
+    double y1 = op.blp, y2 = op.qv;
+    g.solve_mat_v3(P, X, u, y1, y2);
+    if (wd) wsZ[d * strideZ] = g.mv(R, y1);
+    if (we) wsZ[d * strideZ + 1] = g.mv(R, y2);
     // Sigma_{d+1} = t (Sigma + R u) + beta-,  R_{d+1} = r + t R P
     const double Ru = g.mv(R, u);
     const double Sig_n = g.mv(op.t, Sig + Ru) + bm;
@@ -663,10 +680,6 @@ __global__ __launch_bounds__(64, 2) void k_fs_dense(FsDenseArgs<NA> a, DenseTab<
     }
     (void)rl;
   }
-  // the unit-source responses behind Lambda* (plain form) and 1 - Lambda*
-  // (difference form) are formed only for the outputs that are wanted
-  const bool wd = (o & PPRT_OUT_LSTAR) != 0;
-  const bool we = (o & PPRT_OUT_LSTAR_C) != 0;
   double dSu = 0.0;           // dSigma^up of the node being emitted (layer below)
   double eSu = -L.sw;         // its difference-form counterpart (lower boundary: -1)
   om_prev = -1.0;
@@ -688,19 +701,9 @@ __global__ __launch_bounds__(64, 2) void k_fs_dense(FsDenseArgs<NA> a, DenseTab<
     // and -1 at a boundary, for 1 - Lambda* with full relative accuracy)
     // (each response only when its output is wanted: wd, we are uniform)
     double dS = 0.0, eS = -L.sw;
-    if (has_a && (wd || we)) {
-      double Rm[NA], Y[NA];
-#pragma unroll
-      for (int j = 0; j < NA; ++j) Rm[j] = wsR[(d - 1) * strideR + j];
-      g.mul(Y, op.r, Rm);
-#pragma unroll
-      for (int j = 0; j < NA; ++j) Y[j] = ((j == i) ? 1.0 : 0.0) - Y[j];
-      double y1 = op.blp, y2 = op.qv;
-      if (wd && we) g.solve2(Y, y1, y2);              // G_{d-1} (dbeta+_a, Q_a)
-      else if (wd) y1 = g.solve(Y, y1);
-      else y2 = g.solve(Y, y2);
-      if (wd) dS = g.mv(op.t, g.mv(Rm, y1)) + op.blm;
-      if (we) eS = g.mv(op.t, g.mv(Rm, y2)) - op.qv;
+    if (has_a) {      // R_{d-1} G_{d-1} (dbeta+_a, Q_a), kept by pass 1
+      if (wd) dS = g.mv(op.t, wsZ[(d - 1) * strideZ]) + op.blm;
+      if (we) eS = g.mv(op.t, wsZ[(d - 1) * strideZ + 1]) - op.qv;
     }
     // I+ and the two responses from one elimination on I - R^up R_d
     double Ip = g.mv(Rup, Sd) + Sup;
@@ -802,6 +805,7 @@ hipError_t run_dense(const DenseLaunch& L, hipStream_t s) {
   a.wsR = L.ws;
   a.wsS = L.ws + (size_t)L.rows * L.nf * NA * NA;
   a.wsV = a.wsS + (size_t)L.rows * L.nf * NA;
+  a.wsZ = a.wsV + (size_t)L.rows * L.nf * NA * (NA + 1);
   a.nf = L.nf; a.nitems = L.nitems; a.lower_bc = L.lower_bc; a.outputs = L.outputs;
   DenseTab<NA> T{};
   fill_tab<NA>(T, L.mu, L.w);
@@ -813,7 +817,7 @@ hipError_t run_dense(const DenseLaunch& L, hipStream_t s) {
 bool dense_na_supported(int na) { return na == 1 || na == 2 || na == 4 || na == 8 || na == 16; }
 
 size_t dense_workspace_bytes(int na, int64_t rows, int nf) {
-  return (size_t)rows * nf * (size_t)(2 * na * na + 2 * na) * sizeof(double);
+  return (size_t)rows * nf * (size_t)(2 * na * na + 4 * na) * sizeof(double);
 }
 
 int dense_freqs_per_item(int na) { return 64 / na; }
