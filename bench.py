@@ -62,7 +62,7 @@ def parse():
     ap.add_argument("--graph-chunk", type=int, default=25,
                     help="ALI iterations per captured graph in the graph-mode timing (0: skip)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_fs_profile_c3a.json"))
-    ap.add_argument("--workload", choices=["c3a", "spherical", "nonlocal", "voigt", "c3b"], default="c3a",
+    ap.add_argument("--workload", choices=["c3a", "spherical", "nonlocal", "voigt", "c3b", "adjoint"], default="c3a",
                     help="c3a: the plane-parallel batch (default, the headline line); "
                          "spherical: the same batch shape as spheres (1D spherical symmetry); "
                          "nonlocal: c3a with the tri-diagonal approximate operator and Ng; "
@@ -125,6 +125,9 @@ def main():
         return
     if args.workload == "c3b":
         bench_c3b(args)
+        return
+    if args.workload == "adjoint":
+        bench_adjoint(args)
         return
     import torch
     from paper_0903_1949_amd import pprt
@@ -691,6 +694,91 @@ def bench_c3b(args):
                                "dense passes' own)",
                      "kernel_ms": round(step_ms, 3), "flops_per_layer_and_freq": DENSE_FLOPS_PER_LAYER,
                      "peak_note": "FP64 vector, 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz"},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+ADJ_FLOPS_PER_POINT = 48.0   # forward 12; reverse 2 x 12 (segment recompute) + 12 (adjoint)
+
+
+def bench_adjoint(args):
+    """Gradient of the emergent-spectrum loss L = sum I+(tau_1)^2 on the C4
+    case (nd 256, na 16, nf 4096, FP32): the forward emergent intensity with
+    layer checkpoints every 16 nodes and the hand-written vector-Jacobian
+    product (dL/dq, dL/dS per depth and frequency), through the C ABI."""
+    import torch
+    from paper_0903_1949_amd import pprt
+    from paper_0903_1949_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    g = W.gradient_case()
+    nd, na, nf = g.tau.shape[0], g.na, g.B.shape[1]
+    pts = nd * na * nf
+    ctx = pprt.Context(0)
+    plan = pprt.Plan(ctx, [nd], na, nf, precision=pprt.FP32)
+    d = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda:0")
+    tau = d(g.tau, torch.float64)
+    q = d(np.outer(g.c, g.f), torch.float32)
+    B = d(g.B, torch.float32)
+    Bb, Bp = B[-1:].contiguous(), B[-2:-1].contiguous()
+    K = 16
+    ws = torch.empty(max(plan.adjoint_workspace_bytes(K), 256), dtype=torch.uint8, device="cuda:0")
+    stream = torch.cuda.current_stream()
+
+    def step(e0=None, e1=None, e2=None):
+        if e0 is not None:
+            e0.record(stream)
+        I, _ = plan.emergent_intensity(tau, q, B, Bb, Bp, checkpoint_interval=K, workspace=ws)
+        if e1 is not None:
+            e1.record(stream)
+        gI = 2.0 * I
+        plan.formal_solution_vjp(tau, q, B, gI, ws, Bb, Bp, checkpoint_interval=K)
+        if e2 is not None:
+            e2.record(stream)
+
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    steps = args.steps
+    evs = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for e0, e1, e2 in evs:
+        step(e0, e1, e2)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    fwd_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1, _ in evs]))
+    tot_ms = float(np.mean([e0.elapsed_time(e2) for e0, _, e2 in evs]))
+    achieved = pts * ADJ_FLOPS_PER_POINT / (tot_ms * 1e-3) / 1e12
+    cpu = None
+    if not args.no_cpu_baseline:
+        from threadpoolctl import threadpool_limits
+        from oracle import grad
+        ks = slice(0, nf)
+        with threadpool_limits(limits=1):
+            t1 = time.perf_counter()
+            grad.emergent_intensity(g.tau, np.outer(g.c, g.f)[:, ks], g.B[:, ks], plan.mu,
+                                    Bbot=g.B[-1, ks], Bbot_prev=g.B[-2, ks])
+            dt = time.perf_counter() - t1
+        cpu = {"value": pts / dt, "unit": "pts/s", "cores": 1, "kind": "oracle",
+               "sample": f"the oracle's FP64 forward emergent intensity at all {nf} frequencies "
+                         f"({pts} points, {dt:.1f} s, numpy, 1 thread); it differentiates by complex "
+                         "step, one complex forward per parameter depth, and has no adjoint"}
+    line = {
+        "metric": "formal-solution depth*angle*freq pts/s of the emergent-spectrum gradient (forward + VJP), FP32",
+        "value": pts / (wall / steps), "unit": "pts/s", "n_gpus": 1, "steps": steps,
+        "warmup": max(1, args.warmup), "ms_per_step": wall * 1e3 / steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "one atmosphere, nd 256, tau 1e-4..1e4, na 16, nf 4096 (nu 1.5e14..3e15 Hz), "
+                               "lognormal per-depth opacity, B_nu of a grey Eddington T(tau), seed 4; "
+                               "loss sum of I+(tau_1)^2, checkpoints every 16 nodes",
+                   "nd": nd, "na": na, "nf": nf, "points_per_step": pts, "checkpoint_interval": K},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VALU_NONPACKED,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU_NONPACKED, 4),
+                     "traffic": None, "kernel": "k_emergent + k_emergent_vjp (forward + VJP launches)",
+                     "kernel_ms": round(tot_ms, 4), "forward_ms": round(fwd_ms, 4),
+                     "flops_per_point": ADJ_FLOPS_PER_POINT,
+                     "note": "a single atmosphere: 4096 x 16 lanes, one wave per SIMD; latency-bound"},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
