@@ -262,8 +262,8 @@ def main():
         torch.cuda.synchronize()
         wb64 = (time.perf_counter() - t1) / args.fp64_steps
         fp64_batched = {"value": pts / wb64, "ms_per_step": wb64 * 1e3,
-                        "desc": "the same batched step in FP64 (k_fs_profile<double,8>: exp and "
-                                "expm1 per layer and angle; FP64 partials)"}
+                        "desc": "the same batched step in FP64 (k_fs_profile<double,8>: series for "
+                                "thin layers, exp for thick ones; FP64 partials)"}
 
     cpu = None
     if not args.no_cpu_baseline:
