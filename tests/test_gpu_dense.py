@@ -137,6 +137,18 @@ def test_continuum_batch_slice(gpu_ctx):
         assert e < 1e-9, (k, e)
 
 
+def test_scattering_rejects_unsupported_angle_counts(gpu_ctx):
+    """The dense path takes na in {1, 2, 4, 8, 16}; 32 angles (64 x 64 layer
+    operators) and odd counts are refused before any launch."""
+    for na in (32, 3):
+        plan = pprt.Plan(gpu_ctx, [4], na, 3, precision=pprt.FP64, outputs=pprt.OUT_J)
+        z = torch.zeros((4, 3), dtype=torch.float64, device="cuda:0")
+        one = torch.ones((1, 3), dtype=torch.float64, device="cuda:0")
+        with pytest.raises(pprt.PprtError, match="E_UNSUPPORTED"):
+            plan.formal_solution_scattering(_dev(np.logspace(-2, 1, 4)), z + 1, z, z,
+                                            Bbot=one, Bbot_prev=one)
+
+
 def test_scattering_rejects_fp32_plan(gpu_ctx):
     plan = pprt.Plan(gpu_ctx, [4], 4, 3, precision=pprt.FP32, outputs=pprt.OUT_J)
     z = torch.zeros((4, 3), dtype=torch.float32, device="cuda:0")
