@@ -33,6 +33,24 @@ def rel_err(a, b, floor=1e-4):
     return float(np.max(np.abs(a - b) / den))
 
 
+def switch_slab(na, nf=5):
+    """One two-level slab of unit opacity whose layers put Delta = dtau/mu
+    just below and just above 1/4 (relative offsets 1e-3, 1e-6, 1e-9) for
+    every angle in turn: the switch between the thin-layer series and the
+    exponential in the sweeps.  Synthetic; returns a workloads.TwoLevelBatch."""
+    from oracle.quadrature import gauss_legendre01
+    from paper_0903_1949_amd import workloads as W
+    mu, _ = gauss_legendre01(na)
+    offsets = [s * f for f in (1e-3, 1e-6, 1e-9) for s in (-1.0, 1.0)]
+    steps = [0.25 * m * (1.0 + o) for m in mu for o in offsets]
+    tau = 1e-3 + np.concatenate([[0.0], np.cumsum(steps)])
+    nd = tau.shape[0]
+    _, phi, wnu = W.doppler_grid(nf)
+    return W.TwoLevelBatch(nd=np.array([nd], np.int32), tau=tau, q=np.ones((nd, nf)), phi=phi,
+                           wnu=wnu, eps=np.array([1e-3]), B=1.0 + 0.5 * tau / tau[-1],
+                           S_trial=1.0 - 0.7 * np.exp(-3.0 * tau), na=na)
+
+
 @pytest.fixture(scope="session")
 def gpu_ctx():
     """libpprt context on cuda:0.  GPU tests fail (not skip) without a device:

@@ -9,7 +9,7 @@ import torch
 from oracle import ali
 from paper_0903_1949_amd import pprt
 from paper_0903_1949_amd import workloads as W
-from tests.conftest import rel_err
+from tests.conftest import rel_err, switch_slab
 from tests.test_gpu_fs import _random_batch, r32
 
 pytestmark = pytest.mark.gpu
@@ -69,6 +69,35 @@ def test_nonlocal_steps_match_oracle(gpu_ctx, prec, tol, ng):
         worst = max(worst, rel_err(db.S[s].cpu().numpy(), ref["S"]))
     print(f"  tri ng={ng} prec={prec}: S after 4 steps {worst:.2e}", flush=True)
     assert worst < tol
+
+
+@pytest.mark.parametrize("prec,tol", [(pprt.FP64, 1e-10), (pprt.FP32, 2e-6)])
+@pytest.mark.parametrize("na", [4, 8])
+def test_tri_steps_across_the_thin_thick_switch(gpu_ctx, na, prec, tol):
+    """The tri-diagonal sweep's alpha, gamma and e per angle switch from their
+    series to the exponential at Delta = 1/4 (in FP32 decided once per layer
+    when every angle agrees): two steps on a slab whose layers put Delta
+    within 1e-9..1e-3 of 1/4 for every angle, against the oracle."""
+    batch = switch_slab(na)
+    db = pprt.upload_two_level(batch, prec)
+    plan = pprt.Plan(gpu_ctx, batch.nd, na, batch.nf, precision=prec)
+    plan.set_operator(pprt.LSTAR_TRI, False)
+    plan.two_level_reset()
+    db.S.copy_(db.B)
+    mx = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    for _ in range(2):
+        plan.two_level_ali_step(db.tau, db.q, db.S, db.eps, db.B, db.wphi, mx)
+    torch.cuda.synchronize()
+    # the device holds the profile weights w phi rounded to the plan precision
+    wnu = batch.wnu
+    if prec == pprt.FP32:
+        wnu = (batch.wnu * batch.phi).astype(np.float32).astype(np.float64) / batch.phi
+    ref = ali.two_level_ali_nonlocal(batch.tau, batch.q, batch.phi, wnu,
+                                     float(batch.eps[0]), batch.B, plan.mu, plan.w,
+                                     tol=1e-300, max_iter=2, operator="tri", ng=False)
+    e = rel_err(db.S.cpu().numpy(), ref["S"])
+    print(f"  tri na={na} prec={prec}: S after 2 steps {e:.2e}", flush=True)
+    assert e < tol
 
 
 @pytest.mark.parametrize("ng", [False, True])
