@@ -498,18 +498,20 @@ pprt_status pprt_plan_get_launch(const pprt_plan* plan, int32_t* waves_per_block
 typedef struct pprt_tune_report {
   int32_t waves_per_block;          /* chosen                                  */
   int32_t persistent_waves_per_cu;  /* chosen (0 = one wave per item)          */
-  float best_ms;                    /* mean time of the chosen shape           */
-  float default_ms;                 /* mean time of the plan's default shape   */
+  float best_ms;                    /* time of the chosen shape (best round)   */
+  float default_ms;                 /* time of the plan's default shape        */
   int32_t candidates;               /* shapes measured                         */
   int32_t from_cache;               /* 1: taken from the in-process cache      */
 } pprt_tune_report;
 
 /* Time every launch shape (4 block sizes x {per-item, persistent at 8, 16,
- * 32 waves per CU}) on the caller's inputs with HIP events (one warm-up and
- * three timed launches each, moments only; S is read, not changed; the
- * workspace's moment area is overwritten), keep the fastest in the plan and
- * in an in-process cache keyed by device, precision, na, nf and the depth
- * counts.  A later plan of the same shape takes the cached choice without
+ * 32 waves per CU}) on the caller's inputs with HIP events (three rounds
+ * over all shapes, each one warm-up and three timed launches per shape,
+ * moments only; S is read, not changed; the workspace's moment area is
+ * overwritten), keep each shape's best round, and choose the fastest shape
+ * when it beats the plan's default by more than 1% (else the default); the
+ * choice goes into the plan and an in-process cache keyed by device,
+ * precision, na, nf and the depth counts.  A later plan of the same shape takes the cached choice without
  * measuring unless flags has PPRT_TUNE_FORCE.  Synchronises the stream. */
 pprt_status pprt_plan_autotune(pprt_plan* plan, const pprt_fs_in* in, const pprt_two_level* atom,
                                const double* S, void* workspace, int32_t flags,

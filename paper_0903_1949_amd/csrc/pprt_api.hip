@@ -1190,29 +1190,53 @@ pprt_status pprt_plan_autotune(pprt_plan* p, const pprt_fs_in* in, const pprt_tw
   r = hip_check(c, hipEventCreate(&e0), "event");
   if (r == PPRT_OK) r = hip_check(c, hipEventCreate(&e1), "event");
   TuneChoice best{default_wpb, 0, 1e30f, 0.f, 0};
-  const int reps = 3;
-  for (int wpb : wpbs) {
-    for (int wpc : wpcs) {
-      if (r != PPRT_OK) break;
-      r = pprt_plan_set_launch(p, wpb, wpc);
-      if (r != PPRT_OK) break;
-      r = ali_moments_impl(p, in, at, S, nullptr, ws);       // warm-up
-      if (r == PPRT_OK) r = hip_check(c, hipEventRecord(e0, c->stream), "event record");
-      for (int k = 0; k < reps && r == PPRT_OK; ++k) r = ali_moments_impl(p, in, at, S, nullptr, ws);
-      if (r == PPRT_OK) r = hip_check(c, hipEventRecord(e1, c->stream), "event record");
-      if (r == PPRT_OK) r = hip_check(c, hipEventSynchronize(e1), "event sync");
-      float ms = 0.f;
-      if (r == PPRT_OK) r = hip_check(c, hipEventElapsedTime(&ms, e0, e1), "event time");
-      if (r != PPRT_OK) break;
-      ms /= reps;
-      ++best.candidates;
-      if (wpb == default_wpb && wpc == 0) best.default_ms = ms;
-      if (ms < best.best_ms) {
-        best.best_ms = ms;
-        best.wpb = wpb;
-        best.wpc = wpc;
+  // Three interleaved rounds over all shapes, each shape keeping its best
+  // round (a transient slowdown or a clock ramp does not decide the choice),
+  // and a shape other than the default only when it is more than 1% faster.
+  const int reps = 3, rounds = 3;
+  constexpr int ncand = 16;
+  float tbest[ncand];
+  for (float& t : tbest) t = 1e30f;
+  for (int rd = 0; rd < rounds && r == PPRT_OK; ++rd) {
+    int ci = 0;
+    for (int wpb : wpbs) {
+      for (int wpc : wpcs) {
+        if (r != PPRT_OK) break;
+        r = pprt_plan_set_launch(p, wpb, wpc);
+        if (r != PPRT_OK) break;
+        r = ali_moments_impl(p, in, at, S, nullptr, ws);       // warm-up
+        if (r == PPRT_OK) r = hip_check(c, hipEventRecord(e0, c->stream), "event record");
+        for (int k = 0; k < reps && r == PPRT_OK; ++k) r = ali_moments_impl(p, in, at, S, nullptr, ws);
+        if (r == PPRT_OK) r = hip_check(c, hipEventRecord(e1, c->stream), "event record");
+        if (r == PPRT_OK) r = hip_check(c, hipEventSynchronize(e1), "event sync");
+        float ms = 0.f;
+        if (r == PPRT_OK) r = hip_check(c, hipEventElapsedTime(&ms, e0, e1), "event time");
+        if (r != PPRT_OK) break;
+        ms /= reps;
+        if (ms < tbest[ci]) tbest[ci] = ms;
+        ++ci;
       }
     }
+  }
+  if (r == PPRT_OK) {
+    int ci = 0;
+    for (int wpb : wpbs)
+      for (int wpc : wpcs) {
+        if (wpb == default_wpb && wpc == 0) best.default_ms = tbest[ci];
+        ++ci;
+      }
+    best.candidates = ncand;
+    best.best_ms = best.default_ms;
+    ci = 0;
+    for (int wpb : wpbs)
+      for (int wpc : wpcs) {
+        if (tbest[ci] < 0.99f * best.default_ms && tbest[ci] < best.best_ms) {
+          best.best_ms = tbest[ci];
+          best.wpb = wpb;
+          best.wpc = wpc;
+        }
+        ++ci;
+      }
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
