@@ -34,7 +34,10 @@
 // and element i of every vector), 64/NA frequencies per wave, one wave per
 // block.  Matrix products broadcast the right operand through the group's LDS
 // slab; the LDS operations of one wave execute in order and compiler fences
-// keep the program order.  The two passes are two kernels, each limited to
+// keep the program order.  The Gauss-Jordan eliminations instead take each
+// pivot row from its lane through the cross-lane permute and scale no row
+// until the end (fewer instructions than a pivot lane that scales and stores
+// its row while the other lanes wait).  The two passes are two kernels, each limited to
 // 256 registers so that two waves share a SIMD (fewer spills than three); the
 // eigen solutions of pass 1 (rows of V and the roots) stay in the workspace
 // for pass 2, and each root's Newton iteration starts from the same lane's
@@ -97,6 +100,7 @@ template <int NA>
 struct Grp {
   double* buf;
   int i;
+  int b4;   // 4 x the group's first lane (permute address)
 
   __device__ __forceinline__ void put_mat(const double (&A)[NA]) {
     wsync();
@@ -143,185 +147,74 @@ struct Grp {
     for (int j = 0; j < NA; ++j) acc += vec(j, 1);
     return acc;
   }
-  // X = A^-1 by Gauss-Jordan without pivoting; A is destroyed.  Used on
-  // symmetric positive definite matrices and on I - (reflection products).
-  __device__ __forceinline__ void inv(double (&X)[NA], double (&A)[NA]) {
-#pragma unroll
-    for (int j = 0; j < NA; ++j) X[j] = (j == i) ? 1.0 : 0.0;
-#pragma unroll
-    for (int k = 0; k < NA; ++k) {
-      wsync();
-      if (i == k) {
-        const double p = rcp_nr(A[k]);
-#pragma unroll
-        for (int j = 0; j < NA; ++j) {
-          A[j] *= p;
-          X[j] *= p;
-          buf[j] = A[j];
-          buf[NA + j] = X[j];
-        }
-      }
-      wsync();
-      if (i != k) {
-        const double f = A[k];
-#pragma unroll
-        for (int j = 0; j < NA; ++j) {
-          A[j] = fma(-f, buf[j], A[j]);
-          X[j] = fma(-f, buf[NA + j], X[j]);
-        }
-      }
-    }
-    wsync();
+  // Gauss-Jordan elimination without pivoting on the rows [A | X | v] held
+  // by the group's lanes (A is destroyed).  Step k takes row k from lane k
+  // through the cross-lane permute (no LDS memory, no divergent pivot lane)
+  // and subtracts A_ik / A_kk times it from every other row; the pivot row is
+  // not scaled, so column k of A and the columns left of it are final after
+  // step k and are not updated again.  Lane i divides its right-hand sides by
+  // its own pivot at the end.  XM: 0 no matrix right-hand side, 1 X holds one
+  // on entry, 2 X starts as the identity (X = A^-1 on exit; row k of X has
+  // no entries right of column k at step k).
+  __device__ __forceinline__ double from_lane(double v, int k) const {
+    const int a = b4 + 4 * k;
+    const int lo = __builtin_amdgcn_ds_bpermute(a, __double2loint(v));
+    const int hi = __builtin_amdgcn_ds_bpermute(a, __double2hiint(v));
+    return __hiloint2double(hi, lo);
   }
-  // y1, y2 with A y = b1, A y = b2; A is destroyed
-  __device__ __forceinline__ void solve2(double (&A)[NA], double& b1, double& b2) {
+  template <int XM, int NB>
+  __device__ __forceinline__ void gj(double (&A)[NA], double (&X)[NA], double (&v)[NB > 0 ? NB : 1]) {
+    if constexpr (XM == 2) {
+#pragma unroll
+      for (int j = 0; j < NA; ++j) X[j] = (j == i) ? 1.0 : 0.0;
+    }
+    double own = 1.0;
 #pragma unroll
     for (int k = 0; k < NA; ++k) {
-      wsync();
-      if (i == k) {
-        const double p = rcp_nr(A[k]);
+      const double piv = from_lane(A[k], k);
+      const double c = (i == k) ? 0.0 : A[k] * rcp_nr(piv);
+      own = (i == k) ? piv : own;
 #pragma unroll
-        for (int j = 0; j < NA; ++j) {
-          A[j] *= p;
-          buf[j] = A[j];
-        }
-        b1 *= p;
-        b2 *= p;
-        buf[NA] = b1;
-        buf[NA + 1] = b2;
-      }
-      wsync();
-      if (i != k) {
-        const double f = A[k];
+      for (int j = k + 1; j < NA; ++j) A[j] = fma(-c, from_lane(A[j], k), A[j]);
+      if constexpr (XM != 0) {
 #pragma unroll
-        for (int j = 0; j < NA; ++j) A[j] = fma(-f, buf[j], A[j]);
-        b1 = fma(-f, buf[NA], b1);
-        b2 = fma(-f, buf[NA + 1], b2);
+        for (int j = 0; j < (XM == 2 ? k + 1 : NA); ++j) X[j] = fma(-c, from_lane(X[j], k), X[j]);
       }
+#pragma unroll
+      for (int m = 0; m < NB; ++m) v[m] = fma(-c, from_lane(v[m], k), v[m]);
     }
-    wsync();
+    const double r = rcp_nr(own);
+    if constexpr (XM != 0) {
+#pragma unroll
+      for (int j = 0; j < NA; ++j) X[j] *= r;
+    }
+#pragma unroll
+    for (int m = 0; m < NB; ++m) v[m] *= r;
+  }
+  // X = A^-1; A is destroyed.  Used on symmetric positive definite matrices
+  // and on I - (reflection products).
+  __device__ __forceinline__ void inv(double (&X)[NA], double (&A)[NA]) {
+    double v[1];
+    gj<2, 0>(A, X, v);
   }
   // y1, y2, y3 with A y = b1, b2, b3; A is destroyed
   __device__ __forceinline__ void solve3(double (&A)[NA], double& b1, double& b2, double& b3) {
-#pragma unroll
-    for (int k = 0; k < NA; ++k) {
-      wsync();
-      if (i == k) {
-        const double p = rcp_nr(A[k]);
-#pragma unroll
-        for (int j = 0; j < NA; ++j) {
-          A[j] *= p;
-          buf[j] = A[j];
-        }
-        b1 *= p;
-        b2 *= p;
-        b3 *= p;
-        buf[NA] = b1;
-        buf[NA + 1] = b2;
-        buf[NA + 2] = b3;
-      }
-      wsync();
-      if (i != k) {
-        const double f = A[k];
-#pragma unroll
-        for (int j = 0; j < NA; ++j) A[j] = fma(-f, buf[j], A[j]);
-        b1 = fma(-f, buf[NA], b1);
-        b2 = fma(-f, buf[NA + 1], b2);
-        b3 = fma(-f, buf[NA + 2], b3);
-      }
-    }
-    wsync();
+    double v[3] = {b1, b2, b3};
+    gj<0, 3>(A, A, v);
+    b1 = v[0]; b2 = v[1]; b3 = v[2];
   }
   // X <- A^-1 X (X holds the right-hand side's rows on entry); A is destroyed
   __device__ __forceinline__ void solve_mat(double (&X)[NA], double (&A)[NA]) {
-#pragma unroll
-    for (int k = 0; k < NA; ++k) {
-      wsync();
-      if (i == k) {
-        const double p = rcp_nr(A[k]);
-#pragma unroll
-        for (int j = 0; j < NA; ++j) {
-          A[j] *= p;
-          X[j] *= p;
-          buf[j] = A[j];
-          buf[NA + j] = X[j];
-        }
-      }
-      wsync();
-      if (i != k) {
-        const double f = A[k];
-#pragma unroll
-        for (int j = 0; j < NA; ++j) {
-          A[j] = fma(-f, buf[j], A[j]);
-          X[j] = fma(-f, buf[NA + j], X[j]);
-        }
-      }
-    }
-    wsync();
+    double v[1];
+    gj<1, 0>(A, X, v);
   }
   // X <- A^-1 X and b0, b1, b2 <- A^-1 b0, b1, b2 (right-hand sides on
   // entry); A is destroyed
   __device__ __forceinline__ void solve_mat_v3(double (&X)[NA], double (&A)[NA], double& b0,
                                                double& b1, double& b2) {
-#pragma unroll
-    for (int k = 0; k < NA; ++k) {
-      wsync();
-      if (i == k) {
-        const double p = rcp_nr(A[k]);
-#pragma unroll
-        for (int j = 0; j < NA; ++j) {
-          A[j] *= p;
-          X[j] *= p;
-          buf[j] = A[j];
-          buf[NA + j] = X[j];
-        }
-        b0 *= p;
-        b1 *= p;
-        b2 *= p;
-        buf[2 * NA] = b0;
-        buf[2 * NA + 1] = b1;
-        buf[2 * NA + 2] = b2;
-      }
-      wsync();
-      if (i != k) {
-        const double f = A[k];
-#pragma unroll
-        for (int j = 0; j < NA; ++j) {
-          A[j] = fma(-f, buf[j], A[j]);
-          X[j] = fma(-f, buf[NA + j], X[j]);
-        }
-        b0 = fma(-f, buf[2 * NA], b0);
-        b1 = fma(-f, buf[2 * NA + 1], b1);
-        b2 = fma(-f, buf[2 * NA + 2], b2);
-      }
-    }
-    wsync();
-  }
-  // y with A y = b (b_i in this lane); A is destroyed
-  __device__ __forceinline__ double solve(double (&A)[NA], double b) {
-#pragma unroll
-    for (int k = 0; k < NA; ++k) {
-      wsync();
-      if (i == k) {
-        const double p = rcp_nr(A[k]);
-#pragma unroll
-        for (int j = 0; j < NA; ++j) {
-          A[j] *= p;
-          buf[j] = A[j];
-        }
-        b *= p;
-        buf[NA] = b;
-      }
-      wsync();
-      if (i != k) {
-        const double f = A[k];
-#pragma unroll
-        for (int j = 0; j < NA; ++j) A[j] = fma(-f, buf[j], A[j]);
-        b = fma(-f, buf[NA], b);
-      }
-    }
-    wsync();
-    return b;
+    double v[3] = {b0, b1, b2};
+    gj<1, 3>(A, X, v);
+    b0 = v[0]; b1 = v[1]; b2 = v[2];
   }
 };
 
@@ -574,7 +467,7 @@ __global__ __launch_bounds__(64, 2) void k_fs_dense(FsDenseArgs<NA> a, DenseTab<
   const int k = it.g * F + grp;
   if (k >= nf) return;   // a whole group: groups never talk to each other
   const int64_t row0 = a.off[b];
-  Grp<NA> g{slab + grp * Slab<NA>::SIZE, lane % NA};
+  Grp<NA> g{slab + grp * Slab<NA>::SIZE, lane % NA, 4 * (lane - lane % NA)};
   const int i = g.i;
   LaneTab<NA> L{};
 #pragma unroll
