@@ -76,6 +76,27 @@ def test_scattering_parity(gpu_ctx, nds, nf, na):
         assert e < 1e-10, (k, e)
 
 
+@pytest.mark.parametrize("na", [8, 16])
+def test_scattering_parity_extreme_layers(gpu_ctx, na):
+    """Layer optical depths from 3e-6 to 1e5 (pivots of D M + Q_C' near 1e6 in
+    the eliminations) and albedos up to 0.9999, where 1 - Lambda* falls to 1e-4."""
+    nds, nf = [9, 5], 5
+    print(f"[case] extreme layers nds={nds} nf={nf} na={na}", flush=True)
+    rng = np.random.default_rng(41 + na)
+    parts = [W.random_slab(nd, nf, seed=41 + nd, tau_lo=1e-7, tau_hi=1e5) for nd in nds]
+    c = dict(tau=np.concatenate([p[0] for p in parts]), q=np.concatenate([p[1] for p in parts]),
+             S=np.concatenate([p[2] for p in parts]),
+             om=rng.uniform(0.9, 0.9999, size=(sum(nds), nf)),
+             Bb=np.stack([p[3] for p in parts]), Bp=np.stack([p[4] for p in parts]),
+             Itop=rng.uniform(0, 0.3, size=(len(nds), nf, na)), Ibot=None)
+    plan, got = _gpu(gpu_ctx, nds, na, nf, c, pprt.BC_DIFFUSION)
+    ref = _oracle(nds, c, plan.mu, plan.w, pprt.BC_DIFFUSION)
+    errs = {k: rel_err(got[k], ref[k]) for k in KEYS}
+    print("  errors:", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for k, e in errs.items():
+        assert e < 1e-10, (k, e)
+
+
 def test_scattering_parity_given_lower_boundary(gpu_ctx):
     nds, nf, na = [9, 4], 10, 4
     c = _case(nds, nf, na, 17, bc=pprt.BC_GIVEN)
