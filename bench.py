@@ -35,9 +35,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Algorithmic FP32 work of the sweep per point (FMA = 2 flops, exp = 1):
-# per hemisphere and angle: Delta (1), exp (1), 1 - e (1), times mu/dtau (2),
-# D = e D + psi dS (3), J and Lambda* accumulations (4)  -> 12, both hemispheres 24.
+# Algorithmic work of the moments-mode sweep per point, fixed before measuring:
+# bytes: q (or dtau) and S read, J - S and 1 - Lambda* written, 4 B each per
+# (depth, frequency) in FP32 = 16 B per (d, k) = 16 / na B per point (2 B at na = 8);
+# flops: per direction about 1 exp + 18 FP32 flops -> 36 flops + 2 exp per point.
+# attainable = min(HBM / bytes, FP32 peak / flops) = min(4.0e12, 4.37e12) pts/s: HBM.
+BYTES_PER_DK = 16.0
+FLOPS_PER_POINT_ALG = 36.0
+# What the fused kernel itself executes (FMA = 2 flops, exp = 1): per hemisphere
+# and angle Delta (1), exp (1), 1 - e (1), times mu/dtau (2), D = e D + psi dS (3),
+# J and Lambda* accumulations (4) -> 12, both hemispheres 24; and it moves only
+# q once per (d, k) plus per-row data: about 0.5 B per point.
 FLOPS_PER_POINT = 24.0
 PEAK_FP32_VALU_NONPACKED = 78.6   # TFLOP/s: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 PEAK_FP32_VALU_PUBLISHED = 157.3  # TFLOP/s: the published FP32 vector figure (packed FP32, two FMAs per lane)
@@ -47,12 +55,17 @@ PEAK_HBM = 8000.0                 # GB/s
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=256, help="atmospheres in the CPU sample")
+    ap.add_argument("--cpu-sample", type=int, default=64,
+                    help="atmospheres in the single-thread CPU sample")
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="worker processes of the all-core oracle run (0: the host's CPU share, at most 16)")
+    ap.add_argument("--stat-replays", type=int, default=50,
+                    help="graph replays behind the median / p10 / p90 step and kernel times")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (read + write) 5 times and "
                          "exit: the reference for scaling FETCH_SIZE / WRITE_SIZE counters")
@@ -75,7 +88,7 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(batch, nsample):
+def cpu_baseline_one_thread(batch, nsample):
     """The oracle (numpy FP64, single thread) on a bounded sample of the same
     workload: every step of one ALI iteration for `nsample` atmospheres
     spread over the depth-count range."""
@@ -102,9 +115,147 @@ def cpu_baseline(batch, nsample):
         ali.batch_two_level_update(sub.nd, S, sub.B, sub.eps, jms, olb)
         dt = time.perf_counter() - t0
     pts = sub.points
-    return {"value": pts / dt, "unit": "pts/s", "cores": 1, "kind": "oracle",
+    return {"value": pts / dt, "unit": "pts/s", "cores": 1,
             "sample": f"one ALI step of {sub.nb} of the 512 atmospheres (nd {int(sub.nd.min())}.."
                       f"{int(sub.nd.max())}, {pts} points), numpy FP64, 1 thread, {dt:.1f} s"}
+
+
+_CPU_BATCH = None
+
+
+def _cpu_worker_init(seed):
+    """Oracle worker (separate process): the same seeded workload, one thread."""
+    global _CPU_BATCH
+    from threadpoolctl import threadpool_limits
+    from paper_0903_1949_amd import workloads as W
+    threadpool_limits(limits=1)
+    _CPU_BATCH = W.two_level_batch(seed=seed)
+
+
+def _cpu_worker(idx):
+    """Profile moments of the oracle's formal solution for atmospheres idx."""
+    from oracle import ali, formal
+    from oracle.quadrature import gauss_legendre01
+    bt = _CPU_BATCH
+    mu, w = gauss_legendre01(bt.na)
+    off = bt.off
+    t0 = time.perf_counter()
+    res = []
+    for b in idx:
+        s = slice(off[b], off[b + 1])
+        S = bt.S_trial[s]
+        out = formal.formal_solution(bt.tau[s], bt.q[s], S, mu, w, lower="diffusion",
+                                     Bbot=np.full(bt.nf, bt.B[s][-1]),
+                                     Bbot_prev=np.full(bt.nf, bt.B[s][-2]))
+        jms, olb = ali.profile_moments(out, S, np.broadcast_to(S[:, None], out["J"].shape),
+                                       bt.phi, bt.wnu)
+        res.append((int(b), jms, olb))
+    return res, time.perf_counter() - t0
+
+
+def cpu_share():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_allcore(batch, seed, nworkers):
+    """The oracle on every atmosphere of the batch, spread over `nworkers`
+    processes (one thread each, atmospheres dealt longest first), then the
+    float64 update: one full ALI step of the workload on the host cores."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    from oracle import ali
+    order = [int(b) for b in np.argsort(-batch.nd, kind="stable")]
+    chunks = [order[i::nworkers * 4] for i in range(nworkers * 4)]
+    with ProcessPoolExecutor(nworkers, mp_context=mp.get_context("spawn"),
+                             initializer=_cpu_worker_init, initargs=(seed,)) as ex:
+        list(ex.map(_cpu_worker, [[] for _ in range(nworkers)]))       # workers up and initialised
+        t0 = time.perf_counter()
+        parts = list(ex.map(_cpu_worker, chunks))
+        jms = np.zeros(batch.tau.shape[0])
+        olb = np.zeros_like(jms)
+        off = batch.off
+        for res, _ in parts:
+            for b, j, o in res:
+                jms[off[b]:off[b + 1]] = j
+                olb[off[b]:off[b + 1]] = o
+        ali.batch_two_level_update(batch.nd, batch.S_trial.copy(), batch.B, batch.eps, jms, olb)
+        dt = time.perf_counter() - t0
+    busy = sum(t for _, t in parts)
+    return {"value": batch.points / dt, "unit": "pts/s", "cores": nworkers, "kind": "oracle",
+            "sample": f"one ALI step of all {batch.nb} atmospheres ({batch.points} points), numpy FP64 "
+                      f"oracle in {nworkers} processes of one thread each, {dt:.1f} s wall "
+                      f"({busy:.1f} s of worker time)",
+            "nproc": os.cpu_count(), "cpu_model": cpu_model()}
+
+
+def graph_of(ctx, fn):
+    """Capture the library launches made by fn() (on a side stream bound to
+    the context) in a torch CUDA graph; fn runs once eagerly first."""
+    import torch
+    main = torch.cuda.current_stream()
+    side = torch.cuda.Stream()
+    side.wait_stream(main)
+    with torch.cuda.stream(side):
+        ctx.set_stream(side)
+        fn()
+    main.wait_stream(side)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        ctx.set_stream(side)
+        fn()
+    ctx.set_stream(main)
+    torch.cuda.synchronize()
+    return g
+
+
+def replay_times(g, n, stream):
+    """n back-to-back replays of graph g with an event between each: wall
+    time and per-replay milliseconds (the GPU never waits for the host)."""
+    import torch
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs[0].record(stream)
+    for i in range(n):
+        g.replay()
+        evs[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(n)])
+
+
+def launch_times(fn, n, stream):
+    """n back-to-back eager launches of fn with events between them: the
+    average (first to last event / n) and the per-launch milliseconds."""
+    import torch
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
+    torch.cuda.synchronize()
+    evs[0].record(stream)
+    for i in range(n):
+        fn()
+        evs[i + 1].record(stream)
+    torch.cuda.synchronize()
+    per = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(n)])
+    return evs[0].elapsed_time(evs[n]) / n, per
+
+
+def stats_ms(per):
+    return {"median": round(float(np.median(per)), 5), "p10": round(float(np.percentile(per, 10)), 5),
+            "p90": round(float(np.percentile(per, 90)), 5), "n": int(per.size)}
 
 
 def main():
@@ -148,55 +299,36 @@ def main():
     ctx = pprt.Context(0)
     stream = torch.cuda.current_stream()
 
-    # ---------------- batched FP32 path
+    # ---------------- batched FP32 path: one ALI step captured in a hipGraph
     plan = pprt.Plan(ctx, batch.nd, batch.na, batch.nf, precision=pprt.FP32,
                      waves_per_block=args.waves_per_block)
     db = pprt.upload_two_level(batch, pprt.FP32)
     db.S.copy_(db.B)
     S0 = db.S.clone()
     mx = torch.zeros(batch.nb, dtype=torch.float64, device="cuda:0")
-    tune = None
-    if not args.no_autotune and not args.waves_per_block:
-        tune = plan.autotune(db.tau, db.q, db.S, db.eps, db.B, db.wphi, force=True)
-    launch = plan.get_launch()
 
-    def step(ev0=None, ev1=None):
-        if ev0 is not None:
-            ev0.record(stream)
+    def moments():
         plan.two_level_moments(db.tau, db.q, db.S, db.eps, db.B, db.wphi)
-        if ev1 is not None:
-            ev1.record(stream)
+
+    def step():
+        moments()
         plan.two_level_update(db.S, db.eps, db.B, db.wphi, mx)
 
-    # FP32 vs FP64 difference of one step from the same S (not timed)
-    step()
-    torch.cuda.synchronize()
-    S_fp32_one = db.S.clone()
-    plan64 = pprt.Plan(ctx, batch.nd, batch.na, batch.nf, precision=pprt.FP64)
-    db64 = pprt.upload_two_level(batch, pprt.FP64)
-    db64.S.copy_(S0)
-    mx64 = torch.zeros_like(mx)
-    plan64.two_level_ali_step(db64.tau, db64.q, db64.S, db64.eps, db64.B, db64.wphi, mx64)
-    torch.cuda.synchronize()
-    d32 = (S_fp32_one - S0).double()
-    d64 = (db64.S - S0)
-    rel_step = float(((S_fp32_one - db64.S).abs() / db64.S.abs()).max())
-    rel_update = float(((d32 - d64).abs() / torch.clamp(d64.abs(), min=1e-4 * float(d64.abs().max()))).max())
-
+    tune = None
+    if not args.no_autotune and not args.waves_per_block:
+        # the tuner's ~200 launches also bring the clocks up right before timing
+        tune = plan.autotune(db.tau, db.q, db.S, db.eps, db.B, db.wphi, force=True)
+    launch = plan.get_launch()
+    g = graph_of(ctx, step)
     for _ in range(args.warmup):
-        step()
+        g.replay()
     torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for e0, e1 in evs:
-        step(e0, e1)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    wall, per_step = replay_times(g, args.steps, stream)
     ms_per_step = wall * 1e3 / args.steps
-    fs_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
     value = pts / (wall / args.steps)
+    if args.steps < args.stat_replays:
+        _, per_step = replay_times(g, args.stat_replays, stream)
+    k_avg, per_k = launch_times(moments, args.stat_replays, stream)
 
     # ---------------- the same iterations through pprt_two_level_ali in graph mode
     graph = None
@@ -214,19 +346,48 @@ def main():
                  "desc": "pprt_two_level_ali, chunks of iterations captured once and replayed "
                          "(includes capture, instantiation and a host check per chunk)"}
 
-    achieved_tflops = pts * FLOPS_PER_POINT / (fs_ms * 1e-3) / 1e12
+    # FP32 vs FP64 difference of one step from the same S (not timed)
+    db.S.copy_(S0)
+    step()
+    torch.cuda.synchronize()
+    S_fp32_one = db.S.clone()
+    plan64 = pprt.Plan(ctx, batch.nd, batch.na, batch.nf, precision=pprt.FP64)
+    db64 = pprt.upload_two_level(batch, pprt.FP64)
+    db64.S.copy_(S0)
+    mx64 = torch.zeros_like(mx)
+    plan64.two_level_ali_step(db64.tau, db64.q, db64.S, db64.eps, db64.B, db64.wphi, mx64)
+    torch.cuda.synchronize()
+    d32 = (S_fp32_one - S0).double()
+    d64 = (db64.S - S0)
+    rel_step = float(((S_fp32_one - db64.S).abs() / db64.S.abs()).max())
+    rel_update = float(((d32 - d64).abs() / torch.clamp(d64.abs(), min=1e-4 * float(d64.abs().max()))).max())
+
+    # ---------------- roofline of the sweep kernel (moments mode)
+    k_s = k_avg * 1e-3
+    bytes_per_pt = BYTES_PER_DK / batch.na
+    pts_per_s = pts / k_s
+    attain_hbm = PEAK_HBM * 1e9 / bytes_per_pt
+    attain_alu = PEAK_FP32_VALU_PUBLISHED * 1e12 / FLOPS_PER_POINT_ALG
+    attainable = min(attain_hbm, attain_alu)
+    gbs = pts * bytes_per_pt / k_s / 1e9
     traffic = measured_traffic(args.traffic_json, "fs_diag.hip")
     peaks = ctx.measure_peaks()
-    roofline = {"bound": "alu", "achieved": round(achieved_tflops, 3),
-                "peak": PEAK_FP32_VALU_NONPACKED, "unit": "TFLOP/s",
-                "frac": round(achieved_tflops / PEAK_FP32_VALU_NONPACKED, 4), "traffic": traffic,
-                "kernel": "k_fs_profile<float,8>", "kernel_ms": round(fs_ms, 5),
-                "flops_per_point": FLOPS_PER_POINT,
-                "peak_measured": round(peaks["fp32_tflops"], 2),
-                "frac_of_measured": round(achieved_tflops / peaks["fp32_tflops"], 4),
-                "frac_of_published_packed": round(achieved_tflops / PEAK_FP32_VALU_PUBLISHED, 4),
-                "hbm_gbs": round(traffic / (fs_ms * 1e-3) / 1e9, 1) if traffic else None,
-                "copy_gbs_measured": round(peaks["copy_gbs"], 1)}
+    roofline = {"bound": "hbm" if attain_hbm <= attain_alu else "alu",
+                "achieved": round(gbs, 1), "peak": PEAK_HBM, "unit": "GB/s",
+                "frac": round(pts_per_s / attainable, 4), "traffic": traffic,
+                "kernel": "k_fs_profile<float,8>", "kernel_ms": round(k_avg, 5),
+                "kernel_ms_stats": stats_ms(per_k),
+                "bytes_per_point": bytes_per_pt, "flops_per_point": FLOPS_PER_POINT_ALG,
+                "attainable_pts_per_s": attainable, "achieved_pts_per_s": pts_per_s,
+                "alu_frac_published": round(pts_per_s * FLOPS_PER_POINT_ALG / (PEAK_FP32_VALU_PUBLISHED * 1e12), 4),
+                "alu_frac_nonpacked": round(pts_per_s * FLOPS_PER_POINT_ALG / (PEAK_FP32_VALU_NONPACKED * 1e12), 4),
+                "kernel_own_work": {
+                    "flops_per_point": FLOPS_PER_POINT,
+                    "tflops": round(pts_per_s * FLOPS_PER_POINT / 1e12, 3),
+                    "frac_of_nonpacked_valu": round(pts_per_s * FLOPS_PER_POINT / (PEAK_FP32_VALU_NONPACKED * 1e12), 4),
+                    "hbm_gbs_measured": round(traffic / k_s / 1e9, 1) if traffic else None},
+                "peak_measured": {"fp32_tflops": round(peaks["fp32_tflops"], 2),
+                                  "copy_gbs": round(peaks["copy_gbs"], 1)}}
 
     # ---------------- plain FP64 path: one FP64 launch pair per atmosphere
     fp64 = None
@@ -253,21 +414,22 @@ def main():
         fp64 = {"value": pts / w64, "ms_per_step": w64 * 1e3,
                 "desc": "FP64 sweep + update, one launch pair per atmosphere, untuned"}
         # the batched step itself in FP64: same plan layout, k_fs_profile<double,8>
-        for _ in range(2):
+        def step64b():
             plan64.two_level_ali_step(db64.tau, db64.q, db64.S, db64.eps, db64.B, db64.wphi, mx64)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(args.fp64_steps):
-            plan64.two_level_ali_step(db64.tau, db64.q, db64.S, db64.eps, db64.B, db64.wphi, mx64)
-        torch.cuda.synchronize()
-        wb64 = (time.perf_counter() - t1) / args.fp64_steps
-        fp64_batched = {"value": pts / wb64, "ms_per_step": wb64 * 1e3,
+        g64 = graph_of(ctx, step64b)
+        for _ in range(3):
+            g64.replay()
+        w, per64 = replay_times(g64, max(args.fp64_steps, 10), stream)
+        fp64_batched = {"value": pts / float(np.median(per64) * 1e-3),
+                        "ms_per_step": stats_ms(per64)["median"], "step_ms_stats": stats_ms(per64),
                         "desc": "the same batched step in FP64 (k_fs_profile<double,8>: series for "
-                                "thin layers, exp for thick ones; FP64 partials)"}
+                                "thin layers, exp for thick ones; FP64 partials), graph replays"}
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(batch, args.cpu_sample)
+        nw = args.cpu_workers or cpu_share()
+        cpu = cpu_baseline_allcore(batch, 3, nw)
+        cpu["one_thread"] = cpu_baseline_one_thread(batch, args.cpu_sample)
 
     line = {
         "metric": "formal-solution depth*angle*freq pts/s, batched FP32 (plain FP64 beside it)",
@@ -275,11 +437,13 @@ def main():
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "512 two-level atmospheres, nd U{48..256}, na 8, nf 1024, "
-                               "eps 1e-6..1e-1, seed 3 (one ALI step per step)",
+                               "eps 1e-6..1e-1, seed 3 (one ALI step per step: sweep + moments "
+                               "+ FP64 update, captured once in a hipGraph and replayed)",
                    "nbatch": batch.nb, "rows": int(batch.nd.sum()), "na": batch.na,
                    "nf": batch.nf, "points_per_step": pts, "seed": 3,
                    "launch": {"waves_per_block": launch[0], "persistent_waves_per_cu": launch[1],
                               "autotune": tune}},
+        "step_ms_stats": stats_ms(per_step),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "graph_mode": graph,

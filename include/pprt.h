@@ -68,8 +68,9 @@ typedef enum pprt_status {
 } pprt_status;
 
 /* device status bits (pprt_sync) */
-#define PPRT_DEV_NONFINITE 0x1u
-#define PPRT_DEV_SINGULAR  0x2u
+#define PPRT_DEV_NONFINITE 0x1u  /* a kernel produced NaN/Inf                     */
+#define PPRT_DEV_SINGULAR  0x2u  /* a per-depth rate system had no usable pivot   */
+#define PPRT_DEV_BADINDEX  0x4u  /* a model-atom table entry was out of range     */
 
 typedef enum pprt_precision { PPRT_FP64 = 0, PPRT_FP32 = 1 } pprt_precision;
 typedef enum pprt_lower_bc { PPRT_BC_DIFFUSION = 0, PPRT_BC_GIVEN = 1 } pprt_lower_bc;
@@ -115,8 +116,26 @@ pprt_status pprt_set_stream(pprt_ctx* ctx, void* hip_stream);
 /* Message of the last host-side error on this context ("" if none). */
 const char* pprt_last_error(const pprt_ctx* ctx);
 /* Wait for the context stream, then return and clear the device status
- * word (PPRT_DEV_* bits).  E_NONFINITE if the NONFINITE bit was set. */
+ * word (PPRT_DEV_* bits).  E_NONFINITE if the NONFINITE bit was set, else
+ * E_SINGULAR for SINGULAR, else E_INVALID_ARG for BADINDEX. */
 pprt_status pprt_sync(pprt_ctx* ctx, uint32_t* device_status);
+
+/* Validation mode.  PPRT_VALIDATE_INPUTS: before launching, the compute
+ * calls copy their inputs to the host (on the context stream, then
+ * synchronise) and scan them: tau strictly increasing per atmosphere
+ * (E_INVALID_ARG) and finite, q > 0 (E_INVALID_ARG), every source,
+ * boundary and albedo array finite (E_NONFINITE).  Off by default: the scan
+ * reads every input array once per call. */
+#define PPRT_VALIDATE_INPUTS 0x1u
+pprt_status pprt_set_validation(pprt_ctx* ctx, uint32_t flags);
+
+/* The same scans on host arrays, without a device.  pprt_check_tau: tau
+ * [sum nd] (host) finite and strictly increasing inside each atmosphere
+ * (E_NONFINITE / E_INVALID_ARG, E_SHAPE for nd < 2).  pprt_check_finite:
+ * n values of the given precision (host) finite, else E_NONFINITE.  msg
+ * (host, len bytes, may be NULL) receives the reason. */
+pprt_status pprt_check_tau(int32_t nbatch, const int32_t* nd, const double* tau, char* msg, size_t len);
+pprt_status pprt_check_finite(int32_t precision, int64_t n, const void* x, char* msg, size_t len);
 
 /* ------------------------------------------------------------------ plan */
 
@@ -216,6 +235,10 @@ typedef struct pprt_ali_ctl {
   int32_t use_graph;     /* 1: capture the iterations_per_sync launches between
                             checks once in a hipGraph (on a private stream at
                             the default priority) and replay it; same results */
+  int32_t resume;        /* 0: start afresh (iteration counts, convergence
+                            flags and Ng history reset); 1: continue from the
+                            state in the workspace, e.g. after
+                            pprt_ali_state_import; max_iter caps the total */
 } pprt_ali_ctl;
 
 typedef struct pprt_ali_report {
@@ -332,11 +355,14 @@ typedef struct pprt_atom {
   const double* dopp;        /* [rows] Doppler width relative to the line centre    */
 } pprt_atom;
 
-/* Host validation of the atom's tables (copies the int32 tables to the
- * host): level and window indices in range, windows inside [0, nf), every
- * frequency owned by the transition whose window holds it.  E_INVALID_ARG /
- * E_SHAPE with a message otherwise.  The compute calls below validate the
- * first time they see a given set of table pointers. */
+/* Host validation of the atom (copies the tables to the host on the
+ * context stream, then synchronises): level and window indices in range,
+ * windows inside [0, nf), every frequency owned by the transition whose
+ * window holds it (E_INVALID_ARG / E_SHAPE), and the rate-matrix pattern of
+ * pprt_atom_check_host (E_SINGULAR).  The compute calls below re-read and
+ * check the index tables on every call (a table rewritten in place is seen);
+ * their kernels also test every index they use and raise PPRT_DEV_BADINDEX
+ * instead of reading outside an array. */
 pprt_status pprt_atom_check(pprt_plan* plan, const pprt_atom* atom);
 
 /* Opacity and source assembly from populations pops [rows][nlev]:
@@ -367,6 +393,17 @@ pprt_status pprt_rates_solve(pprt_plan* plan, const pprt_atom* atom, const doubl
 pprt_status pprt_plan_nlte_workspace_bytes(const pprt_plan* plan, int32_t nlev, int32_t ntr,
                                            size_t* bytes);
 
+/* Host-only form of pprt_atom_check on host copies of the tables (no
+ * device): index tables as above, plus the rate-matrix pattern: a level all
+ * of whose transitions have zero collision rates (both ways) and a zero
+ * cross-section over the window at some depth row makes the statistical
+ * equilibrium singular there (its row and column are empty): E_SINGULAR.
+ * Reads lower, upper, k0, k1, owner, sigma, Cul, Clu [rows][ntr] and, with
+ * Voigt lines (line_a != NULL), line_nu0 and line_s; the other fields are
+ * ignored.  pprt_atom_check runs the same checks on the device tables. */
+pprt_status pprt_atom_check_host(const pprt_atom* atom_host, int64_t rows, int32_t nf, char* msg,
+                                 size_t len);
+
 /* One accelerated-Lambda iteration of the multilevel atom: opacities from
  * pops, formal solution with in-layer continuum scattering (FP64 plans,
  * na in {1,2,4,8,16}), rate assembly and the per-depth solve; pops
@@ -375,6 +412,23 @@ pprt_status pprt_plan_nlte_workspace_bytes(const pprt_plan* plan, int32_t nlev, 
  * diffusion lower boundary takes B from atom->Bnu. */
 pprt_status pprt_nlte_step(pprt_plan* plan, const pprt_fs_in* in, const pprt_atom* atom,
                            double* pops, double* max_rel, void* workspace);
+
+/* The multilevel operator-splitting loop (Sect. 2; the convergence test of
+ * Sect. 3.2.1 on the populations): from pops (device [rows][nlev], float64,
+ * in/out) repeat pprt_nlte_step until every atmosphere's maximum relative
+ * population change is below ctl->tol or ctl->max_iter steps were taken.
+ * An atmosphere stops (its populations are frozen) at its own convergence;
+ * `iters` (device int32 [nb], may be NULL) receives the per-atmosphere
+ * counts.  The atom is validated once, tables and rate-matrix pattern
+ * (pprt_atom_check).  Synchronises every ctl->iters_per_sync steps;
+ * ctl->use_graph and ctl->resume must be 0.  Returns E_SINGULAR if a
+ * per-depth system had no usable pivot (those rows keep their previous
+ * populations), E_NONFINITE for NaN/Inf, E_NOT_CONVERGED at the cap; the
+ * report is filled in every case that reaches the loop.  Workspace:
+ * pprt_plan_nlte_workspace_bytes. */
+pprt_status pprt_nlte_solve(pprt_plan* plan, const pprt_fs_in* in, const pprt_atom* atom,
+                            const pprt_ali_ctl* ctl, double* pops, int32_t* iters,
+                            pprt_ali_report* report, void* workspace);
 
 /* ---- 1D spherical symmetry ----------------------------------------------
  * The formal solution on impact-parameter rays through spherical shells
@@ -478,6 +532,23 @@ pprt_status pprt_measure_peaks(pprt_ctx* ctx, void* scratch, size_t bytes, pprt_
 #define PPRT_LSTAR_TRI 1
 pprt_status pprt_plan_set_operator(pprt_plan* plan, int32_t lstar, int32_t ng);
 pprt_status pprt_two_level_reset(pprt_plan* plan, void* workspace);
+
+/* ---- Checkpoint / resume of the two-level ALI ----------------------------
+ * The state of an operator-splitting iteration is the source function S and
+ * what the workspace carries between steps: per-atmosphere iteration counts
+ * and convergence flags (pprt_two_level_ali) and Ng's group history and
+ * counter.  pprt_ali_state_export writes it into a caller-owned host buffer
+ * of pprt_ali_state_bytes() bytes (a header fingerprints the batch shape,
+ * precision and operator); pprt_ali_state_import restores it into S and a
+ * workspace of a plan of the same shape and operator (E_SHAPE /
+ * E_INVALID_ARG otherwise), so that stepping on (pprt_two_level_ali_step,
+ * or pprt_two_level_ali with ctl->resume = 1) continues bit for bit as
+ * the uninterrupted iteration would.  Both synchronise the context stream. */
+pprt_status pprt_ali_state_bytes(const pprt_plan* plan, size_t* bytes);
+pprt_status pprt_ali_state_export(pprt_plan* plan, const double* S, const void* workspace, void* host,
+                                  size_t bytes);
+pprt_status pprt_ali_state_import(pprt_plan* plan, const void* host, size_t bytes, double* S,
+                                  void* workspace);
 
 /* ---- Launch shape of the batched two-level sweep, and its autotuner ------
  * The batched sweep of pprt_two_level_moments / _ali_step / _ali runs one

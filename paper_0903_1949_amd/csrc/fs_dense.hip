@@ -445,6 +445,7 @@ struct FsDenseArgs {
   double* wsS;     // [rows][nf][NA]
   double* wsV;     // [rows][nf][NA][NA+1]: eigen solution of layer (d, d+1), row i and root k_i
   double* wsZ;     // [rows][nf][NA][2]: R_d G_d beta+ and R_d G_d Q of layer (d, d+1), element i
+  uint32_t* status; // device status word: NONFINITE when an output is not finite
   int32_t nf;
   int32_t nitems;
   int32_t lower_bc;
@@ -558,6 +559,7 @@ __global__ __launch_bounds__(64, 2) void k_fs_dense(FsDenseArgs<NA> a, DenseTab<
   wsS[(nd - 1) * strideS] = Sig;
   } else {
   // ---------------- pass 2: bottom -> top, outputs per node
+  bool nonfinite = false;
   double Rup[NA];
 #pragma unroll
   for (int j = 0; j < NA; ++j) Rup[j] = 0.0;
@@ -624,6 +626,8 @@ __global__ __launch_bounds__(64, 2) void k_fs_dense(FsDenseArgs<NA> a, DenseTab<
       Lcn = -0.5 * g.sum(L.sw * (eDp + eDm));
     }
     const double Hn = 0.5 * g.sum(L.swmu * (Ip - Im));
+    // a zero or non-finite pivot in any elimination ends up here
+    nonfinite |= !isfinite(Ip + Im + Ln + Lcn);
     {
       const int64_t x = (row0 + d) * nf + k;
       const double S = a.Sg[x];
@@ -667,6 +671,7 @@ __global__ __launch_bounds__(64, 2) void k_fs_dense(FsDenseArgs<NA> a, DenseTab<
       Sup = Sup_n;
     }
   }
+  if (nonfinite && a.status) atomicOr(a.status, PPRT_DEV_NONFINITE);
   }
 }
 
@@ -702,6 +707,7 @@ hipError_t run_dense(const DenseLaunch& L, hipStream_t s) {
   a.wsV = a.wsS + (size_t)L.rows * L.nf * NA;
   a.wsZ = a.wsV + (size_t)L.rows * L.nf * NA * (NA + 1);
   a.nf = L.nf; a.nitems = L.nitems; a.lower_bc = L.lower_bc; a.outputs = L.outputs;
+  a.status = L.status;
   DenseTab<NA> T{};
   fill_tab<NA>(T, L.mu, L.w);
   return launch_dense_t<NA>(L.nitems, s, &a, &T);

@@ -58,6 +58,12 @@ __device__ __forceinline__ double cross_section(const MlArgs& a, int64_t r, int 
   return a.sigma[k];
 }
 
+// level indices of transition t inside [0, nlev) with lower < upper
+__device__ __forceinline__ bool level_pair_ok(const MlArgs& a, int t) {
+  const int l = a.lower[t], u = a.upper[t];
+  return l >= 0 && u < a.nlev && l < u;
+}
+
 __global__ void k_voigt(VoigtCoef vc, int64_t n, const double* __restrict__ av,
                         const double* __restrict__ xv, double* __restrict__ H) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -71,6 +77,12 @@ __global__ void k_ml_opacity(MlArgs a, double* __restrict__ q, double* __restric
   const int64_t r = x / a.nf;
   const int k = (int)(x - r * a.nf);
   const int t = a.owner[k];
+  // the host validates the tables; a table rewritten since then cannot
+  // make this kernel read out of bounds
+  if (t < 0 || t >= a.ntr || !level_pair_ok(a, t)) {
+    if (a.status) atomicOr(a.status, PPRT_DEV_BADINDEX);
+    return;
+  }
   const double nl = a.pops[r * a.nlev + a.lower[t]];
   const double nu = a.pops[r * a.nlev + a.upper[t]];
   const double G = a.G[x], s = cross_section(a, r, k, t);
@@ -91,6 +103,10 @@ __global__ __launch_bounds__(64) void k_ml_rates(MlArgs a, const double* __restr
   const int64_t r = blockIdx.x;
   const int t = blockIdx.y;
   const int lane = threadIdx.x;
+  if (!level_pair_ok(a, t) || a.k0[t] < 0 || a.k1[t] > a.nf) {
+    if (lane == 0 && a.status) atomicOr(a.status, PPRT_DEV_BADINDEX);
+    return;
+  }
   const double nl = a.pops[r * a.nlev + a.lower[t]];
   const double nu = a.pops[r * a.nlev + a.upper[t]];
   double s1 = 0.0, s2 = 0.0, s3 = 0.0;
@@ -135,10 +151,15 @@ __global__ __launch_bounds__(128) void k_ml_solve(MlArgs a, const int64_t* __res
                                                   const double* __restrict__ Rsul,
                                                   double* __restrict__ pops_new,
                                                   double* __restrict__ max_rel,
-                                                  uint32_t* __restrict__ status) {
+                                                  uint32_t* __restrict__ status, MlSolveCtl ctl) {
   __shared__ double red[128];
   const int b = blockIdx.x;
   const int n = a.nlev;
+  if (ctl.active != nullptr && ctl.active[b] == 0) {   // converged: keep the populations
+    for (int64_t x = off[b] * n + threadIdx.x; x < off[b + 1] * n; x += blockDim.x)
+      pops_new[x] = a.pops[x];
+    return;
+  }
   double mx = 0.0;
   uint32_t bad = 0;
   for (int64_t r = off[b] + threadIdx.x; r < off[b + 1]; r += blockDim.x) {
@@ -151,6 +172,7 @@ __global__ __launch_bounds__(128) void k_ml_solve(MlArgs a, const int64_t* __res
     // A[i][j] += rate j -> i ; A[i][i] -= rates out of i
     for (int t = 0; t < a.ntr; ++t) {
       const int l = a.lower[t], u = a.upper[t];
+      if (!(l >= 0 && u < n && l < u)) { bad |= PPRT_DEV_BADINDEX; continue; }
       const int64_t y = r * a.ntr + t;
       const double Plu = dRlu[y] + a.Clu[y];
       const double Pul = Rsul[y] + dRul[y] + a.Cul[y];
@@ -167,13 +189,16 @@ __global__ __launch_bounds__(128) void k_ml_solve(MlArgs a, const int64_t* __res
       sc[j] = a.pops[r * n + j];
       for (int i = 0; i < n; ++i) A[i][j] *= sc[j];
     }
-    // LU with partial pivoting, forward/back substitution
+    // LU with partial pivoting, forward/back substitution.  A column with
+    // no nonzero (or no finite) pivot makes the system singular: the row
+    // keeps its old populations and the SINGULAR bit is raised.
+    bool singular = false;
     for (int c = 0; c < n; ++c) {
       int p = c;
       double best = fabs(A[c][c]);
       for (int i = c + 1; i < n; ++i)
         if (fabs(A[i][c]) > best) { best = fabs(A[i][c]); p = i; }
-      if (!(best > 0.0)) { bad |= PPRT_DEV_SINGULAR; break; }
+      if (!(best > 0.0) || !isfinite(best)) { singular = true; break; }
       if (p != c) {
         for (int j = 0; j < n; ++j) { const double tmp = A[c][j]; A[c][j] = A[p][j]; A[p][j] = tmp; }
         const double tmp = x[c]; x[c] = x[p]; x[p] = tmp;
@@ -186,6 +211,11 @@ __global__ __launch_bounds__(128) void k_ml_solve(MlArgs a, const int64_t* __res
           x[i] = fma(-f, x[c], x[i]);
         }
       }
+    }
+    if (singular) {
+      bad |= PPRT_DEV_SINGULAR;
+      for (int i = 0; i < n; ++i) pops_new[r * n + i] = a.pops[r * n + i];
+      continue;
     }
     for (int c = n - 1; c >= 0; --c) {
       double s = x[c];
@@ -208,7 +238,14 @@ __global__ __launch_bounds__(128) void k_ml_solve(MlArgs a, const int64_t* __res
     if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
     __syncthreads();
   }
-  if (threadIdx.x == 0 && max_rel) max_rel[b] = red[0];
+  if (threadIdx.x == 0) {
+    if (max_rel) max_rel[b] = red[0];
+    if (ctl.iters != nullptr) {
+      const int it = (ctl.iters[b] += 1);
+      if (ctl.active != nullptr && (red[0] < ctl.tol || (ctl.max_iter > 0 && it >= ctl.max_iter)))
+        ctl.active[b] = 0;
+    }
+  }
 }
 
 __global__ void k_gather_bottom(const double* __restrict__ Bnu, const int64_t* __restrict__ off,
@@ -243,10 +280,10 @@ hipError_t launch_ml_rates(const MlArgs& a, const double* J, const double* L, do
 
 hipError_t launch_ml_solve(const MlArgs& a, const int64_t* off, int nb, const double* dRlu,
                            const double* dRul, const double* Rsul, double* pops_new, double* max_rel,
-                           uint32_t* status, hipStream_t s) {
+                           uint32_t* status, hipStream_t s, const MlSolveCtl& ctl) {
   if (nb == 0) return hipSuccess;
   hipLaunchKernelGGL(k_ml_solve, dim3(nb), dim3(128), 0, s, a, off, dRlu, dRul, Rsul, pops_new,
-                     max_rel, status);
+                     max_rel, status, ctl);
   return hipGetLastError();
 }
 

@@ -21,6 +21,7 @@ struct pprt_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   uint32_t* d_status = nullptr;   // device status word
+  uint32_t validate = 0;          // PPRT_VALIDATE_* flags
   std::string err;
 };
 
@@ -49,9 +50,6 @@ struct pprt_plan {
   std::vector<double> mu, w;
   Angles<float> af{};
   Angles<double> ad{};
-  // last atom tables that passed pprt_atom_check
-  const void* checked_atom[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-  int checked_nlev = 0, checked_ntr = 0;
   // workspace layout of the ALI calls
   size_t ws_part = 0, ws_maxrel = 0, ws_active = 0, ws_iters = 0, ws_bytes = 0;
   // two-level operator: tri-diagonal Lambda* and/or Ng acceleration
@@ -260,6 +258,80 @@ pprt_status adj_common_checks(pprt_plan* p, const pprt_fs_in* in, int K, void* w
   return ensure_ck_off(p, K);
 }
 
+// ---- host-side input checks (shared by the host-only entry points and the
+// context's validation mode)
+pprt_status tau_check(int nb, const int32_t* nd, const double* tau, char* msg, size_t len) {
+  int64_t r = 0;
+  for (int b = 0; b < nb; ++b) {
+    for (int d = 0; d < nd[b]; ++d, ++r) {
+      if (!std::isfinite(tau[r]))
+        return shape_fail(msg, len, PPRT_E_NONFINITE, "tau of atmosphere %d, node %d is not finite", b, d);
+      if (d > 0 && !(tau[r] > tau[r - 1]))
+        return shape_fail(msg, len, PPRT_E_INVALID_ARG,
+                          "tau of atmosphere %d is not strictly increasing at node %d (%.17g after %.17g)",
+                          b, d, tau[r], tau[r - 1]);
+    }
+  }
+  return PPRT_OK;
+}
+
+template <typename T>
+pprt_status finite_check(const T* x, int64_t n, const char* name, bool positive, char* msg, size_t len) {
+  for (int64_t i = 0; i < n; ++i) {
+    if (!std::isfinite((double)x[i]))
+      return shape_fail(msg, len, PPRT_E_NONFINITE, "%s[%lld] is not finite", name, (long long)i);
+    if (positive && !(x[i] > T(0)))
+      return shape_fail(msg, len, PPRT_E_INVALID_ARG, "%s[%lld] = %g must be > 0", name, (long long)i,
+                        (double)x[i]);
+  }
+  return PPRT_OK;
+}
+
+// Validation mode: copy a device array to the host on the context stream
+// (ordered after the caller's writes) and scan it.
+pprt_status validate_array(pprt_ctx* c, const void* dev, int64_t n, int es, const char* name,
+                           bool positive) {
+  if (!dev || n <= 0) return PPRT_OK;
+  std::vector<unsigned char> h((size_t)n * es);
+  hipError_t e = hipMemcpyAsync(h.data(), dev, h.size(), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  pprt_status r = hip_check(c, e, "validation read");
+  if (r != PPRT_OK) return r;
+  char msg[256];
+  r = es == 8 ? finite_check((const double*)h.data(), n, name, positive, msg, sizeof msg)
+              : finite_check((const float*)h.data(), n, name, positive, msg, sizeof msg);
+  return r == PPRT_OK ? r : fail(c, r, "%s", msg);
+}
+
+pprt_status validate_tau(pprt_ctx* c, int nb, const int32_t* nd, int64_t rows, const double* tau) {
+  std::vector<double> h(rows);
+  hipError_t e = hipMemcpyAsync(h.data(), tau, rows * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  pprt_status r = hip_check(c, e, "validation read");
+  if (r != PPRT_OK) return r;
+  char msg[256];
+  r = tau_check(nb, nd, h.data(), msg, sizeof msg);
+  return r == PPRT_OK ? r : fail(c, r, "%s", msg);
+}
+
+// The inputs of a plane-parallel call: tau monotone and finite, q > 0, the
+// sources and boundary data finite.  Sl: a float64 [rows] source (or NULL).
+pprt_status validate_fs_in(pprt_plan* p, const pprt_fs_in* in, const double* Sl) {
+  pprt_ctx* c = p->ctx;
+  if (!(c->validate & PPRT_VALIDATE_INPUTS) || !in) return PPRT_OK;
+  const int es = p->precision == PPRT_FP64 ? 8 : 4;
+  const int64_t rf = p->rows * (int64_t)p->nf, bf = (int64_t)p->nb * p->nf;
+  pprt_status r = validate_tau(c, p->nb, p->nd.data(), p->rows, in->tau);
+  if (r == PPRT_OK) r = validate_array(c, in->q, rf, es, "q", true);
+  if (r == PPRT_OK) r = validate_array(c, in->Sg, rf, es, "Sg", false);
+  if (r == PPRT_OK) r = validate_array(c, Sl, p->rows, 8, "S", false);
+  if (r == PPRT_OK) r = validate_array(c, in->Itop, bf * p->na, es, "Itop", false);
+  if (r == PPRT_OK) r = validate_array(c, in->Ibot, bf * p->na, es, "Ibot", false);
+  if (r == PPRT_OK) r = validate_array(c, in->Bbot, bf, es, "Bbot", false);
+  if (r == PPRT_OK) r = validate_array(c, in->Bbot_prev, bf, es, "Bbot_prev", false);
+  return r;
+}
+
 }  // namespace
 
 extern "C" {
@@ -327,7 +399,33 @@ pprt_status pprt_sync(pprt_ctx* c, uint32_t* device_status) {
   if (r != PPRT_OK) return r;
   if (device_status) *device_status = st;
   if (st & PPRT_DEV_NONFINITE) return fail(c, PPRT_E_NONFINITE, "device reported non-finite values");
+  if (st & PPRT_DEV_SINGULAR) return fail(c, PPRT_E_SINGULAR, "a per-depth rate system was singular");
+  if (st & PPRT_DEV_BADINDEX)
+    return fail(c, PPRT_E_INVALID_ARG, "a model-atom table entry was out of range on the device");
   return PPRT_OK;
+}
+
+pprt_status pprt_set_validation(pprt_ctx* c, uint32_t flags) {
+  if (!c) return PPRT_E_INVALID_ARG;
+  if (flags & ~PPRT_VALIDATE_INPUTS) return fail(c, PPRT_E_INVALID_ARG, "unknown validation flags 0x%x", flags);
+  c->validate = flags;
+  return PPRT_OK;
+}
+
+pprt_status pprt_check_tau(int32_t nbatch, const int32_t* nd, const double* tau, char* msg, size_t len) {
+  if (msg && len) msg[0] = 0;
+  if (nbatch < 1 || !nd || !tau) return shape_fail(msg, len, PPRT_E_INVALID_ARG, "need nbatch >= 1, nd and tau");
+  for (int b = 0; b < nbatch; ++b)
+    if (nd[b] < 2) return shape_fail(msg, len, PPRT_E_SHAPE, "nd[%d] = %d: need at least 2 nodes", b, nd[b]);
+  return tau_check(nbatch, nd, tau, msg, len);
+}
+
+pprt_status pprt_check_finite(int32_t precision, int64_t n, const void* x, char* msg, size_t len) {
+  if (msg && len) msg[0] = 0;
+  if (n < 0 || (n > 0 && !x)) return shape_fail(msg, len, PPRT_E_INVALID_ARG, "need n >= 0 and x");
+  if (precision == PPRT_FP64) return finite_check((const double*)x, n, "x", false, msg, len);
+  if (precision == PPRT_FP32) return finite_check((const float*)x, n, "x", false, msg, len);
+  return shape_fail(msg, len, PPRT_E_INVALID_ARG, "unknown precision %d", precision);
 }
 
 pprt_status pprt_shape_check(const pprt_shape* sh, char* msg, size_t msg_len) {
@@ -509,6 +607,10 @@ pprt_status pprt_formal_solution(pprt_plan* p, const pprt_fs_in* in, pprt_fs_out
       {PPRT_OUT_LSTAR_SUB, out->lstar_sub, "lstar_sub"}, {PPRT_OUT_LSTAR_SUP, out->lstar_sup, "lstar_sup"}};
   for (auto& r : req)
     if ((o & r.bit) && !r.ptr) return fail(c, PPRT_E_INVALID_ARG, "output %s requested but NULL", r.name);
+  {
+    const pprt_status v = validate_fs_in(p, in, nullptr);
+    if (v != PPRT_OK) return v;
+  }
 
   hipError_t e;
   if (p->precision == PPRT_FP64) {
@@ -570,7 +672,14 @@ pprt_status pprt_formal_solution_scattering(pprt_plan* p, const pprt_fs_in* in, 
       {PPRT_OUT_H, out->H, "H"}, {PPRT_OUT_IEMERG, out->Iemerg, "Iemerg"}};
   for (auto& r : req)
     if ((o & r.bit) && !r.ptr) return fail(c, PPRT_E_INVALID_ARG, "output %s requested but NULL", r.name);
+  {
+    pprt_status v = validate_fs_in(p, in, nullptr);
+    if (v == PPRT_OK && (c->validate & PPRT_VALIDATE_INPUTS))
+      v = validate_array(c, omega, p->rows * (int64_t)p->nf, 8, "omega", false);
+    if (v != PPRT_OK) return v;
+  }
   DenseLaunch L{};
+  L.status = c->d_status;
   L.items = p->d_items_dense; L.off = p->d_off; L.tau = in->tau; L.q = (const double*)in->q;
   L.Sg = (const double*)in->Sg; L.omega = (const double*)omega; L.Itop = (const double*)in->Itop;
   L.Bbot = (const double*)in->Bbot; L.Bbot_prev = (const double*)in->Bbot_prev;
@@ -691,7 +800,12 @@ static pprt_status check_ali_args(pprt_plan* p, const pprt_fs_in* in, const pprt
   if (!in->tau || !in->q) return fail(c, PPRT_E_INVALID_ARG, "tau and q are required");
   if (!at->eps || !at->B || !at->wphi) return fail(c, PPRT_E_INVALID_ARG, "atom needs eps, B and wphi");
   if (!ws) return fail(c, PPRT_E_WORKSPACE, "workspace of %zu bytes required", p->ws_bytes);
-  return PPRT_OK;
+  pprt_status r = validate_fs_in(p, in, S);
+  if (r == PPRT_OK && (c->validate & PPRT_VALIDATE_INPUTS)) {
+    r = validate_array(c, at->B, p->rows, 8, "B", false);
+    if (r == PPRT_OK) r = validate_array(c, at->eps, p->nb, 8, "eps", false);
+  }
+  return r;
 }
 
 pprt_status pprt_two_level_ali_step(pprt_plan* p, const pprt_fs_in* in, const pprt_two_level* at,
@@ -754,6 +868,17 @@ pprt_status pprt_two_level_ali_step_continuum(pprt_plan* p, const pprt_fs_in* in
   if (!ws) return fail(c, PPRT_E_WORKSPACE, "workspace required (pprt_plan_continuum_workspace_bytes)");
   if (ct->omega && (p->precision != PPRT_FP64 || !dense_na_supported(p->na)))
     return fail(c, PPRT_E_UNSUPPORTED, "in-layer scattering needs an FP64 plan and na in {1,2,4,8,16}");
+  {
+    pprt_status v = validate_fs_in(p, in, S);
+    if (v == PPRT_OK && (c->validate & PPRT_VALIDATE_INPUTS)) {
+      const int es = p->precision == PPRT_FP64 ? 8 : 4;
+      const int64_t rf = p->rows * (int64_t)p->nf;
+      v = validate_array(c, ct->pfrac, rf, es, "pfrac", true);
+      if (v == PPRT_OK) v = validate_array(c, ct->sg_const, rf, es, "sg_const", false);
+      if (v == PPRT_OK) v = validate_array(c, ct->omega, rf, es, "omega", false);
+    }
+    if (v != PPRT_OK) return v;
+  }
   size_t off[6];
   continuum_layout(p, off);
   char* base = (char*)ws;
@@ -767,6 +892,7 @@ pprt_status pprt_two_level_ali_step_continuum(pprt_plan* p, const pprt_fs_in* in
   hipError_t e;
   if (ct->omega) {
     DenseLaunch L{};
+    L.status = c->d_status;
     L.items = p->d_items_dense; L.off = p->d_off; L.tau = in->tau; L.q = (const double*)in->q;
     L.Sg = (const double*)Sg; L.omega = (const double*)ct->omega; L.Itop = (const double*)in->Itop;
     L.Bbot = (const double*)in->Bbot; L.Bbot_prev = (const double*)in->Bbot_prev;
@@ -818,17 +944,27 @@ pprt_status pprt_two_level_ali(pprt_plan* p, const pprt_fs_in* in, const pprt_tw
   double* maxrel = (double*)(base + p->ws_maxrel);
   int32_t* active = (int32_t*)(base + p->ws_active);
   int32_t* its = (int32_t*)(base + p->ws_iters);
-  r = hip_check(c, launch_fill_i32(active, 1, p->nb, c->stream), "fill");
-  if (r != PPRT_OK) return r;
-  r = hip_check(c, launch_fill_i32(its, 0, p->nb, c->stream), "fill");
-  if (r != PPRT_OK) return r;
-  if (p->use_ng) {
-    r = hip_check(c, launch_fill_i32((int32_t*)(base + p->ws_ngc), 0, p->nb, c->stream), "fill");
-    if (r != PPRT_OK) return r;
-  }
   std::vector<int32_t> h_active(p->nb), h_iters(p->nb);
   std::vector<double> h_max(p->nb);
   int done_iters = 0;
+  if (ctl->resume) {
+    // continue from the state in the workspace (pprt_ali_state_import): the
+    // per-atmosphere counts go on from where they were; max_iter caps them
+    r = hip_check(c, hipMemcpyAsync(h_iters.data(), its, p->nb * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                    c->stream), "iters read");
+    if (r == PPRT_OK) r = hip_check(c, hipStreamSynchronize(c->stream), "sync");
+    if (r != PPRT_OK) return r;
+    done_iters = *std::min_element(h_iters.begin(), h_iters.end());
+  } else {
+    r = hip_check(c, launch_fill_i32(active, 1, p->nb, c->stream), "fill");
+    if (r != PPRT_OK) return r;
+    r = hip_check(c, launch_fill_i32(its, 0, p->nb, c->stream), "fill");
+    if (r != PPRT_OK) return r;
+    if (p->use_ng) {
+      r = hip_check(c, launch_fill_i32((int32_t*)(base + p->ws_ngc), 0, p->nb, c->stream), "fill");
+      if (r != PPRT_OK) return r;
+    }
+  }
   bool all_done = false;
   // Graph mode: the iterations between host checks are captured once (on a
   // private stream at the default priority) and replayed on the context
@@ -888,6 +1024,7 @@ static MlArgs ml_args(const pprt_plan* p, const pprt_atom* at, const double* pop
   a.owner = at->owner; a.sigma = at->sigma; a.bfac = at->bfac; a.W = at->W; a.G = at->G;
   a.Bnu = at->Bnu; a.kc = at->kc; a.sc = at->sc; a.ntot = at->ntot; a.Cul = at->Cul; a.Clu = at->Clu;
   a.rows = p->rows; a.nf = p->nf; a.nlev = at->nlev; a.ntr = at->ntr;
+  a.status = p->ctx->d_status;
   if (at->line_a) {
     a.nu = at->nu; a.line_nu0 = at->line_nu0; a.line_s = at->line_s; a.line_a = at->line_a;
     a.dopp = at->dopp;
@@ -896,8 +1033,25 @@ static MlArgs ml_args(const pprt_plan* p, const pprt_atom* at, const double* pop
   return a;
 }
 
-pprt_status pprt_atom_check(pprt_plan* p, const pprt_atom* at) {
-  if (!p) return PPRT_E_INVALID_ARG;
+}  // extern "C"
+
+namespace {
+
+// Host copies of an atom's tables, read on the context stream so that they
+// are ordered after whatever the caller queued there (then synchronised).
+struct AtomHost {
+  std::vector<int32_t> lo, up, k0, k1, own;
+  std::vector<double> sigma, line_nu0, line_s, Cul, Clu;
+};
+
+template <typename T>
+hipError_t read_async(std::vector<T>& v, const void* src, size_t n, hipStream_t s) {
+  v.resize(n);
+  if (n == 0) return hipSuccess;
+  return hipMemcpyAsync(v.data(), src, n * sizeof(T), hipMemcpyDeviceToHost, s);
+}
+
+pprt_status atom_required(pprt_plan* p, const pprt_atom* at) {
   pprt_ctx* c = p->ctx;
   if (!at) return fail(c, PPRT_E_INVALID_ARG, "null atom");
   if (at->nlev < 2 || at->nlev > ml_max_levels())
@@ -907,48 +1061,149 @@ pprt_status pprt_atom_check(pprt_plan* p, const pprt_atom* at) {
                        at->G, at->Bnu, at->kc, at->sc, at->ntot, at->Cul, at->Clu};
   for (const void* ptr : req)
     if (!ptr) return fail(c, PPRT_E_INVALID_ARG, "atom arrays must all be given");
-  {
-    const void* vo[] = {at->nu, at->line_nu0, at->line_s, at->line_a, at->dopp};
-    int given = 0;
-    for (const void* ptr : vo) given += ptr != nullptr;
-    if (at->line_a ? given != 5 : given != 0)
-      return fail(c, PPRT_E_INVALID_ARG, "Voigt lines need nu, line_nu0, line_s, line_a and dopp together");
-  }
-  if (p->checked_atom[0] == at->lower && p->checked_atom[1] == at->upper &&
-      p->checked_atom[2] == at->k0 && p->checked_atom[3] == at->k1 &&
-      p->checked_atom[4] == at->owner && p->checked_nlev == at->nlev && p->checked_ntr == at->ntr)
-    return PPRT_OK;
-  std::vector<int32_t> lo(at->ntr), up(at->ntr), k0(at->ntr), k1(at->ntr), own(p->nf);
-  hipError_t e = hipSuccess;
-  if (e == hipSuccess) e = hipMemcpy(lo.data(), at->lower, at->ntr * 4, hipMemcpyDeviceToHost);
-  if (e == hipSuccess) e = hipMemcpy(up.data(), at->upper, at->ntr * 4, hipMemcpyDeviceToHost);
-  if (e == hipSuccess) e = hipMemcpy(k0.data(), at->k0, at->ntr * 4, hipMemcpyDeviceToHost);
-  if (e == hipSuccess) e = hipMemcpy(k1.data(), at->k1, at->ntr * 4, hipMemcpyDeviceToHost);
-  if (e == hipSuccess) e = hipMemcpy(own.data(), at->owner, (size_t)p->nf * 4, hipMemcpyDeviceToHost);
-  pprt_status r = hip_check(c, e, "atom table read");
-  if (r != PPRT_OK) return r;
-  for (int t = 0; t < at->ntr; ++t) {
-    if (lo[t] < 0 || up[t] >= at->nlev || !(lo[t] < up[t]))
-      return fail(c, PPRT_E_INVALID_ARG, "transition %d: need 0 <= lower < upper < nlev", t);
-    if (k0[t] < 0 || k1[t] > p->nf || !(k0[t] < k1[t]))
-      return fail(c, PPRT_E_INVALID_ARG, "transition %d: window [%d, %d) outside [0, %d)", t, k0[t],
-                  k1[t], p->nf);
-    for (int k = k0[t]; k < k1[t]; ++k)
-      if (own[k] != t) return fail(c, PPRT_E_INVALID_ARG, "frequency %d lies in window %d but owner says %d", k, t, own[k]);
-  }
-  for (int k = 0; k < p->nf; ++k)
-    if (own[k] < 0 || own[k] >= at->ntr)
-      return fail(c, PPRT_E_INVALID_ARG, "frequency %d has no owning transition", k);
-  p->checked_atom[0] = at->lower; p->checked_atom[1] = at->upper; p->checked_atom[2] = at->k0;
-  p->checked_atom[3] = at->k1; p->checked_atom[4] = at->owner;
-  p->checked_nlev = at->nlev; p->checked_ntr = at->ntr;
+  const void* vo[] = {at->nu, at->line_nu0, at->line_s, at->line_a, at->dopp};
+  int given = 0;
+  for (const void* ptr : vo) given += ptr != nullptr;
+  if (at->line_a ? given != 5 : given != 0)
+    return fail(c, PPRT_E_INVALID_ARG, "Voigt lines need nu, line_nu0, line_s, line_a and dopp together");
   return PPRT_OK;
+}
+
+// Index tables (and, with `pattern`, the rate data the singularity
+// pre-check needs) copied to the host, stream-ordered.
+pprt_status atom_read(pprt_plan* p, const pprt_atom* at, bool pattern, AtomHost& h) {
+  pprt_ctx* c = p->ctx;
+  const hipStream_t s = c->stream;
+  hipError_t e = hipSuccess;
+  const size_t nt = (size_t)at->ntr;
+  if (e == hipSuccess) e = read_async(h.lo, at->lower, nt, s);
+  if (e == hipSuccess) e = read_async(h.up, at->upper, nt, s);
+  if (e == hipSuccess) e = read_async(h.k0, at->k0, nt, s);
+  if (e == hipSuccess) e = read_async(h.k1, at->k1, nt, s);
+  if (e == hipSuccess) e = read_async(h.own, at->owner, (size_t)p->nf, s);
+  if (pattern) {
+    if (e == hipSuccess) e = read_async(h.sigma, at->sigma, (size_t)p->nf, s);
+    if (e == hipSuccess) e = read_async(h.Cul, at->Cul, (size_t)p->rows * nt, s);
+    if (e == hipSuccess) e = read_async(h.Clu, at->Clu, (size_t)p->rows * nt, s);
+    if (at->line_a) {
+      if (e == hipSuccess) e = read_async(h.line_nu0, at->line_nu0, nt, s);
+      if (e == hipSuccess) e = read_async(h.line_s, at->line_s, nt, s);
+    }
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return hip_check(c, e, "atom table read");
+}
+
+}  // namespace
+
+// Host-side checks shared by pprt_atom_check and pprt_atom_check_host.
+static pprt_status check_atom_tables(int nlev, int ntr, int nf, const int32_t* lo, const int32_t* up,
+                                     const int32_t* k0, const int32_t* k1, const int32_t* own,
+                                     char* msg, size_t len) {
+  for (int t = 0; t < ntr; ++t) {
+    if (lo[t] < 0 || up[t] >= nlev || !(lo[t] < up[t]))
+      return shape_fail(msg, len, PPRT_E_INVALID_ARG, "transition %d: need 0 <= lower < upper < nlev", t);
+    if (k0[t] < 0 || k1[t] > nf || !(k0[t] < k1[t]))
+      return shape_fail(msg, len, PPRT_E_INVALID_ARG, "transition %d: window [%d, %d) outside [0, %d)", t,
+                        k0[t], k1[t], nf);
+    for (int k = k0[t]; k < k1[t]; ++k)
+      if (own[k] != t)
+        return shape_fail(msg, len, PPRT_E_INVALID_ARG, "frequency %d lies in window %d but owner says %d",
+                          k, t, own[k]);
+  }
+  for (int k = 0; k < nf; ++k)
+    if (own[k] < 0 || own[k] >= ntr)
+      return shape_fail(msg, len, PPRT_E_INVALID_ARG, "frequency %d has no owning transition", k);
+  return PPRT_OK;
+}
+
+// Rate-matrix pattern: a level none of whose transitions can carry a rate at
+// some depth (zero collision rates both ways and a zero cross-section over
+// the window) leaves its statistical-equilibrium row and column empty, so the
+// system is singular there whatever the radiation field.
+static pprt_status check_rate_pattern(int nlev, int ntr, int nf, int64_t rows, const int32_t* lo,
+                                      const int32_t* up, const int32_t* k0, const int32_t* k1,
+                                      const double* sigma, const double* line_nu0, const double* line_s,
+                                      const double* Cul, const double* Clu, char* msg, size_t len) {
+  std::vector<char> rad(ntr, 0);
+  for (int t = 0; t < ntr; ++t) {
+    if (line_nu0 && line_nu0[t] > 0.0) {
+      rad[t] = line_s[t] != 0.0;
+    } else {
+      for (int k = k0[t]; k < k1[t] && !rad[t]; ++k) rad[t] = sigma[k] != 0.0;
+    }
+  }
+  std::vector<char> live(nlev);
+  for (int64_t r = 0; r < rows; ++r) {
+    std::fill(live.begin(), live.end(), 0);
+    for (int t = 0; t < ntr; ++t) {
+      const int64_t y = r * ntr + t;
+      if (rad[t] || Cul[y] != 0.0 || Clu[y] != 0.0) live[lo[t]] = live[up[t]] = 1;
+    }
+    for (int j = 0; j < nlev; ++j)
+      if (!live[j])
+        return shape_fail(msg, len, PPRT_E_SINGULAR,
+                          "level %d has no nonzero rate at row %lld: the rate equations are singular", j,
+                          (long long)r);
+  }
+  return PPRT_OK;
+}
+
+// Tables only (every multilevel compute call): keeps kernels inside their arrays.
+static pprt_status atom_tables_ok(pprt_plan* p, const pprt_atom* at) {
+  pprt_status r = atom_required(p, at);
+  if (r != PPRT_OK) return r;
+  AtomHost h;
+  r = atom_read(p, at, false, h);
+  if (r != PPRT_OK) return r;
+  char msg[256];
+  r = check_atom_tables(at->nlev, at->ntr, p->nf, h.lo.data(), h.up.data(), h.k0.data(), h.k1.data(),
+                        h.own.data(), msg, sizeof msg);
+  return r == PPRT_OK ? r : fail(p->ctx, r, "%s", msg);
+}
+
+extern "C" {
+
+pprt_status pprt_atom_check(pprt_plan* p, const pprt_atom* at) {
+  if (!p) return PPRT_E_INVALID_ARG;
+  pprt_status r = atom_required(p, at);
+  if (r != PPRT_OK) return r;
+  AtomHost h;
+  r = atom_read(p, at, true, h);
+  if (r != PPRT_OK) return r;
+  char msg[256];
+  r = check_atom_tables(at->nlev, at->ntr, p->nf, h.lo.data(), h.up.data(), h.k0.data(), h.k1.data(),
+                        h.own.data(), msg, sizeof msg);
+  if (r == PPRT_OK)
+    r = check_rate_pattern(at->nlev, at->ntr, p->nf, p->rows, h.lo.data(), h.up.data(), h.k0.data(),
+                           h.k1.data(), h.sigma.data(), at->line_a ? h.line_nu0.data() : nullptr,
+                           at->line_a ? h.line_s.data() : nullptr, h.Cul.data(), h.Clu.data(), msg,
+                           sizeof msg);
+  return r == PPRT_OK ? r : fail(p->ctx, r, "%s", msg);
+}
+
+pprt_status pprt_atom_check_host(const pprt_atom* at, int64_t rows, int32_t nf, char* msg, size_t len) {
+  if (msg && len) msg[0] = 0;
+  if (!at) return shape_fail(msg, len, PPRT_E_INVALID_ARG, "null atom");
+  if (at->nlev < 2 || at->nlev > ml_max_levels())
+    return shape_fail(msg, len, PPRT_E_SHAPE, "nlev must be in 2..%d (got %d)", ml_max_levels(), at->nlev);
+  if (at->ntr < 1 || nf < 1 || rows < 1) return shape_fail(msg, len, PPRT_E_SHAPE, "need ntr, nf, rows >= 1");
+  if (!at->lower || !at->upper || !at->k0 || !at->k1 || !at->owner || !at->sigma || !at->Cul || !at->Clu)
+    return shape_fail(msg, len, PPRT_E_INVALID_ARG, "lower, upper, k0, k1, owner, sigma, Cul and Clu are required");
+  if (at->line_a && (!at->line_nu0 || !at->line_s))
+    return shape_fail(msg, len, PPRT_E_INVALID_ARG, "Voigt lines need line_nu0 and line_s");
+  pprt_status r = check_atom_tables(at->nlev, at->ntr, nf, at->lower, at->upper, at->k0, at->k1, at->owner,
+                                    msg, len);
+  if (r != PPRT_OK) return r;
+  return check_rate_pattern(at->nlev, at->ntr, nf, rows, at->lower, at->upper, at->k0, at->k1, at->sigma,
+                            at->line_a ? at->line_nu0 : nullptr, at->line_a ? at->line_s : nullptr,
+                            at->Cul, at->Clu, msg, len);
 }
 
 pprt_status pprt_nlte_opacity(pprt_plan* p, const pprt_atom* at, const double* pops, double* q,
                               double* omega, double* Sg) {
   if (!p) return PPRT_E_INVALID_ARG;
-  pprt_status r = pprt_atom_check(p, at);
+  pprt_status r = atom_tables_ok(p, at);
   if (r != PPRT_OK) return r;
   if (!pops || !q || !omega || !Sg) return fail(p->ctx, PPRT_E_INVALID_ARG, "null array");
   return hip_check(p->ctx, launch_ml_opacity(ml_args(p, at, pops), q, omega, Sg, p->ctx->stream),
@@ -959,7 +1214,7 @@ pprt_status pprt_rates_assemble(pprt_plan* p, const pprt_atom* at, const double*
                                 const double* J, const double* lstar, double* dRlu, double* dRul,
                                 double* Rsul) {
   if (!p) return PPRT_E_INVALID_ARG;
-  pprt_status r = pprt_atom_check(p, at);
+  pprt_status r = atom_tables_ok(p, at);
   if (r != PPRT_OK) return r;
   if (!pops_old || !J || !lstar || !dRlu || !dRul || !Rsul)
     return fail(p->ctx, PPRT_E_INVALID_ARG, "null array");
@@ -971,7 +1226,7 @@ pprt_status pprt_rates_solve(pprt_plan* p, const pprt_atom* at, const double* po
                              const double* dRlu, const double* dRul, const double* Rsul,
                              double* pops_new, double* max_rel) {
   if (!p) return PPRT_E_INVALID_ARG;
-  pprt_status r = pprt_atom_check(p, at);
+  pprt_status r = atom_tables_ok(p, at);
   if (r != PPRT_OK) return r;
   if (!pops_old || !dRlu || !dRul || !Rsul || !pops_new)
     return fail(p->ctx, PPRT_E_INVALID_ARG, "null array");
@@ -982,63 +1237,69 @@ pprt_status pprt_rates_solve(pprt_plan* p, const pprt_atom* at, const double* po
 }
 
 // nlte workspace: [q | om | Sg | J | L (rows*nf) | Bb | Bp (nb*nf) | dRlu | dRul | Rsul (rows*ntr)
-//                  | pops_new (rows*nlev) | dense ws]
-static void nlte_layout(const pprt_plan* p, int nlev, int ntr, size_t off[12]) {
+//                  | pops_new (rows*nlev) | max_rel (nb) | active | iters (nb int32) | dense ws]
+enum { NL_Q, NL_OM, NL_SG, NL_J, NL_L, NL_BB, NL_BP, NL_DRLU, NL_DRUL, NL_RSUL, NL_PN, NL_MAXREL,
+       NL_ACTIVE, NL_ITERS, NL_DENSE, NL_END };
+static void nlte_layout(const pprt_plan* p, int nlev, int ntr, size_t off[NL_END + 1]) {
   const size_t rf = align256((size_t)p->rows * p->nf * sizeof(double));
   const size_t bf = align256((size_t)p->nb * p->nf * sizeof(double));
   const size_t rt = align256((size_t)p->rows * ntr * sizeof(double));
   const size_t rl = align256((size_t)p->rows * nlev * sizeof(double));
+  const size_t sz[NL_END] = {rf, rf, rf, rf, rf, bf, bf, rt, rt, rt, rl,
+                             align256((size_t)p->nb * sizeof(double)),
+                             align256((size_t)p->nb * sizeof(int32_t)),
+                             align256((size_t)p->nb * sizeof(int32_t)),
+                             align256(dense_workspace_bytes(p->na, p->rows, p->nf))};
   off[0] = 0;
-  for (int i = 1; i <= 5; ++i) off[i] = off[i - 1] + rf;
-  off[6] = off[5] + bf;
-  off[7] = off[6] + bf;
-  off[8] = off[7] + rt;
-  off[9] = off[8] + rt;
-  off[10] = off[9] + rt;
-  off[11] = off[10] + rl + align256(dense_workspace_bytes(p->na, p->rows, p->nf));
+  for (int i = 0; i < NL_END; ++i) off[i + 1] = off[i] + sz[i];
 }
 
 pprt_status pprt_plan_nlte_workspace_bytes(const pprt_plan* p, int32_t nlev, int32_t ntr, size_t* bytes) {
   if (!p || !bytes || nlev < 2 || ntr < 1) return PPRT_E_INVALID_ARG;
-  size_t off[12];
+  size_t off[NL_END + 1];
   nlte_layout(p, nlev, ntr, off);
-  *bytes = off[11];
+  *bytes = off[NL_END];
   return PPRT_OK;
 }
 
-pprt_status pprt_nlte_step(pprt_plan* p, const pprt_fs_in* in, const pprt_atom* at, double* pops,
-                           double* max_rel, void* ws) {
-  if (!p) return PPRT_E_INVALID_ARG;
+}  // extern "C"
+
+static pprt_status nlte_common_checks(pprt_plan* p, const pprt_fs_in* in, const double* pops, void* ws) {
   pprt_ctx* c = p->ctx;
   if (p->precision != PPRT_FP64 || !dense_na_supported(p->na))
     return fail(c, PPRT_E_UNSUPPORTED, "multilevel step needs an FP64 plan and na in {1,2,4,8,16}");
   if (p->lower_bc != PPRT_BC_DIFFUSION)
     return fail(c, PPRT_E_UNSUPPORTED, "multilevel step uses the diffusion lower boundary");
-  if (!in || !in->tau || !pops || !max_rel) return fail(c, PPRT_E_INVALID_ARG, "null argument");
+  if (!in || !in->tau || !pops) return fail(c, PPRT_E_INVALID_ARG, "null argument");
   if (!ws) return fail(c, PPRT_E_WORKSPACE, "workspace required (pprt_plan_nlte_workspace_bytes)");
-  pprt_status r = pprt_atom_check(p, at);
-  if (r != PPRT_OK) return r;
-  size_t off[12];
+  if (c->validate & PPRT_VALIDATE_INPUTS) {
+    pprt_status v = validate_tau(c, p->nb, p->nd.data(), p->rows, in->tau);
+    if (v == PPRT_OK) v = validate_array(c, in->Itop, (int64_t)p->nb * p->nf * p->na, 8, "Itop", false);
+    if (v != PPRT_OK) return v;
+  }
+  return PPRT_OK;
+}
+
+// One iteration: opacities from pops, the scattering formal solution, the
+// preconditioned rates and the per-depth solve; pops is overwritten only by
+// the new populations of rows whose system was solvable.
+static pprt_status nlte_step_impl(pprt_plan* p, const pprt_fs_in* in, const pprt_atom* at, double* pops,
+                                  double* max_rel, void* ws, const MlSolveCtl& ctl) {
+  pprt_ctx* c = p->ctx;
+  size_t off[NL_END + 1];
   nlte_layout(p, at->nlev, at->ntr, off);
   char* base = (char*)ws;
-  double* q = (double*)(base + off[0]);
-  double* om = (double*)(base + off[1]);
-  double* Sg = (double*)(base + off[2]);
-  double* J = (double*)(base + off[3]);
-  double* Ls = (double*)(base + off[4]);
-  double* Bb = (double*)(base + off[5]);
-  double* Bp = (double*)(base + off[6]);
-  double* dRlu = (double*)(base + off[7]);
-  double* dRul = (double*)(base + off[8]);
-  double* Rsul = (double*)(base + off[9]);
-  double* pn = (double*)(base + off[10]);
-  double* dws = (double*)(base + off[10] + align256((size_t)p->rows * at->nlev * sizeof(double)));
+  auto arr = [&](int slot) { return (double*)(base + off[slot]); };
+  double *q = arr(NL_Q), *om = arr(NL_OM), *Sg = arr(NL_SG), *J = arr(NL_J), *Ls = arr(NL_L);
+  double *Bb = arr(NL_BB), *Bp = arr(NL_BP), *dRlu = arr(NL_DRLU), *dRul = arr(NL_DRUL);
+  double *Rsul = arr(NL_RSUL), *pn = arr(NL_PN), *dws = arr(NL_DENSE);
   const MlArgs a = ml_args(p, at, pops);
-  r = hip_check(c, launch_ml_opacity(a, q, om, Sg, c->stream), "opacity launch");
+  pprt_status r = hip_check(c, launch_ml_opacity(a, q, om, Sg, c->stream), "opacity launch");
   if (r != PPRT_OK) return r;
   r = hip_check(c, launch_gather_bottom(at->Bnu, p->d_off, p->nb, p->nf, Bb, Bp, c->stream), "gather");
   if (r != PPRT_OK) return r;
   DenseLaunch L{};
+  L.status = c->d_status;
   L.items = p->d_items_dense; L.off = p->d_off; L.tau = in->tau; L.q = q; L.Sg = Sg; L.omega = om;
   L.Itop = (const double*)in->Itop; L.Bbot = Bb; L.Bbot_prev = Bp; L.Ibot = nullptr;
   L.J = J; L.lstar = Ls; L.ws = dws; L.rows = p->rows; L.nf = p->nf; L.na = p->na;
@@ -1049,10 +1310,93 @@ pprt_status pprt_nlte_step(pprt_plan* p, const pprt_fs_in* in, const pprt_atom* 
   r = hip_check(c, launch_ml_rates(a, J, Ls, dRlu, dRul, Rsul, c->stream), "rate assembly launch");
   if (r != PPRT_OK) return r;
   r = hip_check(c, launch_ml_solve(a, p->d_off, p->nb, dRlu, dRul, Rsul, pn, max_rel, c->d_status,
-                                   c->stream), "rate solve launch");
+                                   c->stream, ctl), "rate solve launch");
   if (r != PPRT_OK) return r;
   return hip_check(c, hipMemcpyAsync(pops, pn, (size_t)p->rows * at->nlev * sizeof(double),
                                      hipMemcpyDeviceToDevice, c->stream), "population copy");
+}
+
+extern "C" {
+
+pprt_status pprt_nlte_step(pprt_plan* p, const pprt_fs_in* in, const pprt_atom* at, double* pops,
+                           double* max_rel, void* ws) {
+  if (!p) return PPRT_E_INVALID_ARG;
+  pprt_status r = nlte_common_checks(p, in, pops, ws);
+  if (r != PPRT_OK) return r;
+  if (!max_rel) return fail(p->ctx, PPRT_E_INVALID_ARG, "max_rel is required");
+  r = atom_tables_ok(p, at);
+  if (r != PPRT_OK) return r;
+  return nlte_step_impl(p, in, at, pops, max_rel, ws, MlSolveCtl{});
+}
+
+pprt_status pprt_nlte_solve(pprt_plan* p, const pprt_fs_in* in, const pprt_atom* at,
+                            const pprt_ali_ctl* ctl, double* pops, int32_t* iters,
+                            pprt_ali_report* rep, void* ws) {
+  if (!p) return PPRT_E_INVALID_ARG;
+  pprt_ctx* c = p->ctx;
+  pprt_status r = nlte_common_checks(p, in, pops, ws);
+  if (r != PPRT_OK) return r;
+  if (!ctl || !(ctl->tol > 0.0) || ctl->max_iter < 1 || ctl->iters_per_sync < 1)
+    return fail(c, PPRT_E_INVALID_ARG, "ctl needs tol > 0, max_iter >= 1, iters_per_sync >= 1");
+  if (ctl->use_graph || ctl->resume)
+    return fail(c, PPRT_E_UNSUPPORTED, "the multilevel loop has no graph or resume mode");
+  r = pprt_atom_check(p, at);   // tables and the rate-matrix pattern, once
+  if (r != PPRT_OK) return r;
+  size_t off[NL_END + 1];
+  nlte_layout(p, at->nlev, at->ntr, off);
+  char* base = (char*)ws;
+  double* maxrel = (double*)(base + off[NL_MAXREL]);
+  int32_t* active = (int32_t*)(base + off[NL_ACTIVE]);
+  int32_t* its = (int32_t*)(base + off[NL_ITERS]);
+  r = hip_check(c, launch_fill_i32(active, 1, p->nb, c->stream), "fill");
+  if (r != PPRT_OK) return r;
+  r = hip_check(c, launch_fill_i32(its, 0, p->nb, c->stream), "fill");
+  if (r != PPRT_OK) return r;
+  MlSolveCtl sc{active, its, ctl->tol, ctl->max_iter};
+  std::vector<int32_t> h_active(p->nb), h_iters(p->nb);
+  std::vector<double> h_max(p->nb);
+  int done = 0;
+  uint32_t st = 0;
+  while (done < ctl->max_iter) {
+    const int m = std::min(ctl->iters_per_sync, ctl->max_iter - done);
+    for (int j = 0; j < m; ++j) {
+      r = nlte_step_impl(p, in, at, pops, maxrel, ws, sc);
+      if (r != PPRT_OK) return r;
+    }
+    done += m;
+    r = hip_check(c, hipMemcpyAsync(h_active.data(), active, p->nb * sizeof(int32_t),
+                                    hipMemcpyDeviceToHost, c->stream), "flag read");
+    if (r != PPRT_OK) return r;
+    r = hip_check(c, hipMemcpyAsync(&st, c->d_status, sizeof st, hipMemcpyDeviceToHost, c->stream),
+                  "status read");
+    if (r != PPRT_OK) return r;
+    r = hip_check(c, hipStreamSynchronize(c->stream), "sync");
+    if (r != PPRT_OK) return r;
+    if (st & (PPRT_DEV_SINGULAR | PPRT_DEV_NONFINITE | PPRT_DEV_BADINDEX)) break;
+    if (std::all_of(h_active.begin(), h_active.end(), [](int32_t v) { return v == 0; })) break;
+  }
+  r = hip_check(c, hipMemcpyAsync(h_iters.data(), its, p->nb * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                  c->stream), "iters");
+  if (r == PPRT_OK)
+    r = hip_check(c, hipMemcpyAsync(h_max.data(), maxrel, p->nb * sizeof(double), hipMemcpyDeviceToHost,
+                                    c->stream), "maxrel");
+  if (r == PPRT_OK && iters)
+    r = hip_check(c, hipMemcpyAsync(iters, its, p->nb * sizeof(int32_t), hipMemcpyDeviceToDevice, c->stream),
+                  "iters copy");
+  if (r == PPRT_OK) r = hip_check(c, hipStreamSynchronize(c->stream), "sync");
+  if (r != PPRT_OK) return r;
+  const int32_t n_conv =
+      (int32_t)std::count_if(h_max.begin(), h_max.end(), [&](double v) { return v < ctl->tol; });
+  if (rep) {
+    rep->iterations = *std::max_element(h_iters.begin(), h_iters.end());
+    rep->n_converged = n_conv;
+    rep->max_rel = *std::max_element(h_max.begin(), h_max.end());
+  }
+  r = pprt_sync(c, &st);   // clears the status word; E_NONFINITE / E_SINGULAR / E_INVALID_ARG
+  if (r != PPRT_OK) return r;
+  if (n_conv < p->nb)
+    return fail(c, PPRT_E_NOT_CONVERGED, "multilevel ALI not converged after %d iterations", done);
+  return PPRT_OK;
 }
 
 pprt_status pprt_plan_adjoint_workspace_bytes(const pprt_plan* p, int32_t K, size_t* bytes) {
@@ -1285,6 +1629,110 @@ pprt_status pprt_two_level_reset(pprt_plan* p, void* ws) {
   if (!p->use_ng) return PPRT_OK;
   return hip_check(p->ctx, launch_fill_i32((int32_t*)((char*)ws + p->ws_ngc), 0, p->nb, p->ctx->stream),
                    "Ng reset");
+}
+
+// ---- ALI state: host image of S and of the iteration state in the workspace
+namespace {
+struct AliStateHeader {
+  char magic[8];          // "PPRTALI1"
+  int32_t nb, na, nf, precision, lstar_tri, use_ng;
+  int64_t rows;
+  uint64_t nd_hash;       // FNV-1a of nd[]
+};
+uint64_t nd_hash(const std::vector<int32_t>& nd) {
+  uint64_t h = 1469598103934665603ull;
+  for (int32_t v : nd)
+    for (int k = 0; k < 4; ++k) {
+      h ^= (uint64_t)((v >> (8 * k)) & 0xff);
+      h *= 1099511628211ull;
+    }
+  return h;
+}
+// [header | S (rows f64) | iters, active (nb i32 each) | Ng: hist (3 rows f64), ng_count (nb i32)]
+struct AliStateLayout {
+  size_t S, iters, active, hist, ngc, total;
+};
+AliStateLayout ali_state_layout(const pprt_plan* p) {
+  AliStateLayout L{};
+  L.S = sizeof(AliStateHeader);
+  L.iters = L.S + (size_t)p->rows * sizeof(double);
+  L.active = L.iters + (size_t)p->nb * sizeof(int32_t);
+  L.hist = L.active + (size_t)p->nb * sizeof(int32_t);
+  L.ngc = L.hist + (p->use_ng ? (size_t)p->rows * 3 * sizeof(double) : 0);
+  L.total = L.ngc + (p->use_ng ? (size_t)p->nb * sizeof(int32_t) : 0);
+  return L;
+}
+}  // namespace
+
+pprt_status pprt_ali_state_bytes(const pprt_plan* p, size_t* bytes) {
+  if (!p || !bytes) return PPRT_E_INVALID_ARG;
+  *bytes = ali_state_layout(p).total;
+  return PPRT_OK;
+}
+
+pprt_status pprt_ali_state_export(pprt_plan* p, const double* S, const void* ws, void* host, size_t bytes) {
+  if (!p) return PPRT_E_INVALID_ARG;
+  pprt_ctx* c = p->ctx;
+  const AliStateLayout L = ali_state_layout(p);
+  if (!S || !ws || !host) return fail(c, PPRT_E_INVALID_ARG, "S, workspace and host buffer are required");
+  if (bytes < L.total) return fail(c, PPRT_E_WORKSPACE, "state image needs %zu bytes (got %zu)", L.total, bytes);
+  unsigned char* h = (unsigned char*)host;
+  AliStateHeader hd{};
+  std::memcpy(hd.magic, "PPRTALI1", 8);
+  hd.nb = p->nb; hd.na = p->na; hd.nf = p->nf; hd.precision = p->precision;
+  hd.lstar_tri = p->lstar_tri; hd.use_ng = p->use_ng; hd.rows = p->rows; hd.nd_hash = nd_hash(p->nd);
+  std::memcpy(h, &hd, sizeof hd);
+  const char* base = (const char*)ws;
+  const hipStream_t st = c->stream;
+  hipError_t e = hipMemcpyAsync(h + L.S, S, (size_t)p->rows * sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h + L.iters, base + p->ws_iters, p->nb * sizeof(int32_t), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h + L.active, base + p->ws_active, p->nb * sizeof(int32_t), hipMemcpyDeviceToHost, st);
+  if (p->use_ng) {
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(h + L.hist, base + p->ws_hist, (size_t)p->rows * 3 * sizeof(double),
+                         hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(h + L.ngc, base + p->ws_ngc, p->nb * sizeof(int32_t), hipMemcpyDeviceToHost, st);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return hip_check(c, e, "state export");
+}
+
+pprt_status pprt_ali_state_import(pprt_plan* p, const void* host, size_t bytes, double* S, void* ws) {
+  if (!p) return PPRT_E_INVALID_ARG;
+  pprt_ctx* c = p->ctx;
+  const AliStateLayout L = ali_state_layout(p);
+  if (!S || !ws || !host) return fail(c, PPRT_E_INVALID_ARG, "S, workspace and host buffer are required");
+  if (bytes < sizeof(AliStateHeader)) return fail(c, PPRT_E_INVALID_ARG, "state image too short");
+  const unsigned char* h = (const unsigned char*)host;
+  AliStateHeader hd{};
+  std::memcpy(&hd, h, sizeof hd);
+  if (std::memcmp(hd.magic, "PPRTALI1", 8) != 0) return fail(c, PPRT_E_INVALID_ARG, "not an ALI state image");
+  if (hd.nb != p->nb || hd.na != p->na || hd.nf != p->nf || hd.rows != p->rows ||
+      hd.nd_hash != nd_hash(p->nd))
+    return fail(c, PPRT_E_SHAPE, "state image was written for another batch shape");
+  if (hd.precision != p->precision || hd.lstar_tri != p->lstar_tri || hd.use_ng != p->use_ng)
+    return fail(c, PPRT_E_INVALID_ARG, "state image was written with another precision or operator");
+  if (bytes < L.total) return fail(c, PPRT_E_INVALID_ARG, "state image truncated (%zu of %zu bytes)", bytes, L.total);
+  char* base = (char*)ws;
+  const hipStream_t st = c->stream;
+  hipError_t e = hipMemcpyAsync(S, h + L.S, (size_t)p->rows * sizeof(double), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(base + p->ws_iters, h + L.iters, p->nb * sizeof(int32_t), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(base + p->ws_active, h + L.active, p->nb * sizeof(int32_t), hipMemcpyHostToDevice, st);
+  if (p->use_ng) {
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(base + p->ws_hist, h + L.hist, (size_t)p->rows * 3 * sizeof(double),
+                         hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(base + p->ws_ngc, h + L.ngc, p->nb * sizeof(int32_t), hipMemcpyHostToDevice, st);
+  }
+  // the caller may free the image when this returns
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return hip_check(c, e, "state import");
 }
 
 pprt_status pprt_measure_peaks(pprt_ctx* c, void* scratch, size_t bytes, pprt_peaks* out) {

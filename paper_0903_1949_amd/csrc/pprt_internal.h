@@ -213,6 +213,7 @@ struct DenseLaunch {
   const double* Ibot;
   double *J, *JmS, *lstar, *lstar_c, *Iplus, *Iminus, *H, *Iemerg;
   double* ws;
+  uint32_t* status;   // device status word (NONFINITE), may be NULL
   int64_t rows;
   int32_t nf, na, nitems, lower_bc;
   uint32_t outputs;
@@ -323,6 +324,7 @@ struct MlArgs {
   const double* ntot;     // [rows]
   const double* Cul;      // [rows][ntr]
   const double* Clu;      // [rows][ntr]
+  uint32_t* status;       // device status word: BADINDEX for a table entry out of range
   // depth-dependent Voigt lines (line_a == nullptr: sigma[k] throughout)
   const double* nu;       // [nf]
   const double* line_nu0; // [ntr]
@@ -337,9 +339,19 @@ int ml_max_levels();
 hipError_t launch_ml_opacity(const MlArgs& a, double* q, double* om, double* Sg, hipStream_t s);
 hipError_t launch_ml_rates(const MlArgs& a, const double* J, const double* L, double* dRlu,
                            double* dRul, double* Rsul, hipStream_t s);
+// Convergence bookkeeping of the multilevel loop (all NULL / 0: one plain solve).
+// Atmospheres with active[b] == 0 keep their populations; after each solve
+// iters[b] is incremented and active[b] cleared once max_rel < tol or the
+// count reaches max_iter.
+struct MlSolveCtl {
+  int32_t* active;
+  int32_t* iters;
+  double tol;
+  int32_t max_iter;
+};
 hipError_t launch_ml_solve(const MlArgs& a, const int64_t* off, int nb, const double* dRlu,
                            const double* dRul, const double* Rsul, double* pops_new, double* max_rel,
-                           uint32_t* status, hipStream_t s);
+                           uint32_t* status, hipStream_t s, const MlSolveCtl& ctl = MlSolveCtl{});
 hipError_t launch_gather_bottom(const double* Bnu, const int64_t* off, int nb, int nf, double* Bb,
                                 double* Bp, hipStream_t s);
 

@@ -91,7 +91,7 @@ class Atom(C.Structure):
 
 class AliCtl(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("iters_per_sync", C.c_int32),
-                ("use_graph", C.c_int32)]
+                ("use_graph", C.c_int32), ("resume", C.c_int32)]
 
 
 class AliReport(C.Structure):
@@ -163,6 +163,15 @@ def load_library(path: str = LIB_PATH):
         "pprt_sph_two_level_ali_step": (I, [P, C.POINTER(FsIn), C.POINTER(TwoLevel), P, P, P, P]),
         "pprt_sph_two_level_moments": (I, [P, C.POINTER(FsIn), C.POINTER(TwoLevel), P, P, P]),
         "pprt_sph_two_level_update": (I, [P, C.POINTER(TwoLevel), P, P, P, P]),
+        "pprt_set_validation": (I, [P, U32]),
+        "pprt_check_tau": (I, [C.c_int32, C.POINTER(C.c_int32), C.POINTER(D), C.c_char_p, C.c_size_t]),
+        "pprt_check_finite": (I, [C.c_int32, C.c_int64, P, C.c_char_p, C.c_size_t]),
+        "pprt_atom_check_host": (I, [C.POINTER(Atom), C.c_int64, C.c_int32, C.c_char_p, C.c_size_t]),
+        "pprt_nlte_solve": (I, [P, C.POINTER(FsIn), C.POINTER(Atom), C.POINTER(AliCtl), P, P,
+                                C.POINTER(AliReport), P]),
+        "pprt_ali_state_bytes": (I, [P, C.POINTER(C.c_size_t)]),
+        "pprt_ali_state_export": (I, [P, P, P, P, C.c_size_t]),
+        "pprt_ali_state_import": (I, [P, P, C.c_size_t, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -203,6 +212,52 @@ def shape_check(nd, na, nf, precision=FP32, lower_bc=BC_DIFFUSION, outputs=OUT_J
     return STATUS.get(st, st), buf.value.decode()
 
 
+def check_tau(nd, tau):
+    """Host-only pprt_check_tau: (status name, message)."""
+    lib = load_library()
+    ndv = np.ascontiguousarray(np.asarray(nd, dtype=np.int32))
+    tv = np.ascontiguousarray(np.asarray(tau, dtype=np.float64))
+    buf = C.create_string_buffer(256)
+    st = lib.pprt_check_tau(int(ndv.shape[0]), ndv.ctypes.data_as(C.POINTER(C.c_int32)),
+                            tv.ctypes.data_as(C.POINTER(C.c_double)), buf, 256)
+    return STATUS.get(st, st), buf.value.decode()
+
+
+def check_finite(x):
+    """Host-only pprt_check_finite on a float32 or float64 numpy array."""
+    lib = load_library()
+    x = np.ascontiguousarray(x)
+    if x.dtype not in (np.float32, np.float64):
+        raise TypeError("float32 or float64 array expected")
+    buf = C.create_string_buffer(256)
+    st = lib.pprt_check_finite(FP64 if x.dtype == np.float64 else FP32, int(x.size),
+                               C.c_void_p(x.ctypes.data), buf, 256)
+    return STATUS.get(st, st), buf.value.decode()
+
+
+def atom_check_host(atom, rows=None):
+    """Host-only pprt_atom_check_host on a workloads.MultiLevelAtom (its
+    index tables, cross-sections and collision rates): (status, message)."""
+    lib = load_library()
+    keep = {"lower": np.ascontiguousarray(atom.lo, dtype=np.int32),
+            "upper": np.ascontiguousarray(atom.up, dtype=np.int32),
+            "k0": np.ascontiguousarray(atom.k0, dtype=np.int32),
+            "k1": np.ascontiguousarray(atom.k1, dtype=np.int32),
+            "owner": np.ascontiguousarray(atom.owner, dtype=np.int32),
+            "sigma": np.ascontiguousarray(atom.sigma, dtype=np.float64),
+            "Cul": np.ascontiguousarray(atom.Cul, dtype=np.float64),
+            "Clu": np.ascontiguousarray(atom.Clu, dtype=np.float64)}
+    if getattr(atom, "line_a", None) is not None:
+        keep.update(line_nu0=np.ascontiguousarray(atom.line_nu0, dtype=np.float64),
+                    line_s=np.ascontiguousarray(atom.line_s, dtype=np.float64),
+                    line_a=np.ascontiguousarray(atom.line_a, dtype=np.float64))
+    a = Atom(int(atom.nl), int(atom.nt), **{k: C.c_void_p(v.ctypes.data) for k, v in keep.items()})
+    rows = int(keep["Cul"].shape[0]) if rows is None else int(rows)
+    buf = C.create_string_buffer(256)
+    st = lib.pprt_atom_check_host(C.byref(a), rows, int(keep["owner"].shape[0]), buf, 256)
+    return STATUS.get(st, st), buf.value.decode()
+
+
 def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
@@ -236,6 +291,10 @@ class Context:
         s = C.c_uint32(0)
         self._check(self.lib.pprt_sync(self.h, C.byref(s)), "sync")
         return s.value
+
+    def set_validation(self, on: bool = True):
+        """pprt_set_validation: host scan of every input before each launch."""
+        self._check(self.lib.pprt_set_validation(self.h, 1 if on else 0), "set_validation")
 
     def voigt(self, a, x):
         """pprt_voigt: H(a, x) for device float64 tensors of equal length."""
@@ -503,9 +562,19 @@ class Plan:
             _ptr(workspace)), "two_level_ali_step_continuum")
 
     # ------------------------------------------------------ multilevel
+    def _want_atom(self, atom):
+        if not isinstance(getattr(atom, "struct", None), Atom):
+            raise TypeError("atom must be a DeviceAtom")
+        if atom.rows != self.rows or atom.nf != self.nf:
+            raise ValueError(f"atom was built for {atom.rows} rows and {atom.nf} frequencies, "
+                             f"the plan has {self.rows} and {self.nf}")
+        return atom
+
     def nlte_opacity(self, atom, pops):
         import torch
         R, nf = self.rows, self.nf
+        self._want_atom(atom)
+        self._want(pops, (R, atom.nlev), torch.float64, "pops")
         q = torch.empty((R, nf), dtype=torch.float64, device=pops.device)
         om = torch.empty_like(q)
         Sg = torch.empty_like(q)
@@ -515,6 +584,10 @@ class Plan:
 
     def rates_assemble(self, atom, pops_old, J, lstar):
         import torch
+        self._want_atom(atom)
+        self._want(pops_old, (self.rows, atom.nlev), torch.float64, "pops_old")
+        self._want(J, (self.rows, self.nf), torch.float64, "J")
+        self._want(lstar, (self.rows, self.nf), torch.float64, "lstar")
         shp = (self.rows, atom.ntr)
         out = [torch.empty(shp, dtype=torch.float64, device=pops_old.device) for _ in range(3)]
         self.ctx._check(self.lib.pprt_rates_assemble(
@@ -524,6 +597,10 @@ class Plan:
 
     def rates_solve(self, atom, pops_old, dRlu, dRul, Rsul):
         import torch
+        self._want_atom(atom)
+        self._want(pops_old, (self.rows, atom.nlev), torch.float64, "pops_old")
+        for name, t in (("dRlu", dRlu), ("dRul", dRul), ("Rsul", Rsul)):
+            self._want(t, (self.rows, atom.ntr), torch.float64, name)
         pn = torch.empty_like(pops_old)
         mx = torch.empty(self.nb, dtype=torch.float64, device=pops_old.device)
         self.ctx._check(self.lib.pprt_rates_solve(
@@ -531,19 +608,69 @@ class Plan:
             _ptr(mx)), "rates_solve")
         return pn, mx
 
-    def nlte_step(self, tau, atom, pops, max_rel, Itop=None):
+    def _nlte_args(self, tau, atom, pops, Itop):
         import torch
+        self._want_atom(atom)
         self._want(tau, (self.rows,), torch.float64, "tau")
         self._want(pops, (self.rows, atom.nlev), torch.float64, "pops")
-        self._want(max_rel, (self.nb,), torch.float64, "max_rel")
+        if Itop is not None:
+            self._want(Itop, (self.nb, self.nf, self.na), torch.float64, "Itop")
         fin = FsIn(_ptr(tau), None, None, _ptr(Itop), None, None, None)
         nbytes = C.c_size_t()
         self.ctx._check(self.lib.pprt_plan_nlte_workspace_bytes(self.h, atom.nlev, atom.ntr,
                                                                 C.byref(nbytes)), "nlte_workspace_bytes")
         if getattr(self, "_nws", None) is None or self._nws.numel() < nbytes.value:
             self._nws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=tau.device)
+        return fin
+
+    def nlte_step(self, tau, atom, pops, max_rel, Itop=None):
+        import torch
+        fin = self._nlte_args(tau, atom, pops, Itop)
+        self._want(max_rel, (self.nb,), torch.float64, "max_rel")
         self.ctx._check(self.lib.pprt_nlte_step(self.h, C.byref(fin), C.byref(atom.struct), _ptr(pops),
                                                 _ptr(max_rel), _ptr(self._nws)), "nlte_step")
+
+    def nlte_solve(self, tau, atom, pops, tol=1e-8, max_iter=200, iters_per_sync=8, iters=None,
+                   Itop=None, raise_not_converged=True):
+        """pprt_nlte_solve: the multilevel loop to tolerance; pops in place.
+        Returns the report dict."""
+        import torch
+        fin = self._nlte_args(tau, atom, pops, Itop)
+        if iters is not None:
+            self._want(iters, (self.nb,), torch.int32, "iters")
+        ctl = AliCtl(float(tol), int(max_iter), int(iters_per_sync), 0, 0)
+        rep = AliReport()
+        st = self.lib.pprt_nlte_solve(self.h, C.byref(fin), C.byref(atom.struct), C.byref(ctl),
+                                      _ptr(pops), _ptr(iters), C.byref(rep), _ptr(self._nws))
+        report = {"iterations": rep.iterations, "n_converged": rep.n_converged,
+                  "max_rel": rep.max_rel, "status": STATUS.get(st, st)}
+        if st == 6 and not raise_not_converged:
+            return report
+        self.ctx._check(st, "nlte_solve")
+        return report
+
+    # ------------------------------------------------ ALI checkpoint / resume
+    def ali_state_export(self, S) -> np.ndarray:
+        """pprt_ali_state_export: a host byte image of S and the iteration
+        state held in this plan's workspace."""
+        import torch
+        self._want(S, (self.rows,), torch.float64, "S")
+        n = C.c_size_t()
+        self.ctx._check(self.lib.pprt_ali_state_bytes(self.h, C.byref(n)), "ali_state_bytes")
+        buf = np.zeros(n.value, dtype=np.uint8)
+        self.ctx._check(self.lib.pprt_ali_state_export(self.h, _ptr(S), _ptr(self.workspace()),
+                                                       C.c_void_p(buf.ctypes.data), n.value),
+                        "ali_state_export")
+        return buf
+
+    def ali_state_import(self, image, S):
+        """pprt_ali_state_import: restore S and this plan's workspace state."""
+        import torch
+        self._want(S, (self.rows,), torch.float64, "S")
+        image = np.ascontiguousarray(image, dtype=np.uint8)
+        self.ctx._check(self.lib.pprt_ali_state_import(self.h, C.c_void_p(image.ctypes.data),
+                                                       int(image.size), _ptr(S), _ptr(self.workspace())),
+                        "ali_state_import")
 
     def two_level_moments(self, tau, q, S, eps, B, wphi, active=None, Itop=None, Ibot=None):
         """pprt_two_level_moments: the formal-solution half of an ALI step."""
@@ -567,7 +694,7 @@ class Plan:
 
     def two_level_ali(self, tau, q, S, eps, B, wphi, tol=1e-8, max_iter=20000,
                       iters_per_sync=64, use_graph=False, iters=None, Itop=None, Ibot=None,
-                      raise_not_converged=True):
+                      raise_not_converged=True, resume=False):
         """pprt_two_level_ali: iterate to convergence; returns the report dict."""
         import torch
         fin = self.fs_in(tau, q, None, None, None, Itop, Ibot)
@@ -575,7 +702,8 @@ class Plan:
         self._want(S, (self.rows,), torch.float64, "S")
         if iters is not None:
             self._want(iters, (self.nb,), torch.int32, "iters")
-        ctl = AliCtl(float(tol), int(max_iter), int(iters_per_sync), int(bool(use_graph)))
+        ctl = AliCtl(float(tol), int(max_iter), int(iters_per_sync), int(bool(use_graph)),
+                     int(bool(resume)))
         rep = AliReport()
         st = self.lib.pprt_two_level_ali(self.h, C.byref(fin), C.byref(at), C.byref(ctl), _ptr(S),
                                          _ptr(iters), C.byref(rep), _ptr(self.workspace()))
@@ -763,6 +891,7 @@ class DeviceAtom:
                           line_a=f64(atom.line_a), dopp=f64(atom.dopp))
         self.tau = f64(atom.tau)
         self.nstar = f64(atom.nstar)
+        self.rows, self.nf = int(self.t["G"].shape[0]), int(self.t["owner"].shape[0])
         names = ["lower", "upper", "k0", "k1", "owner", "sigma", "bfac", "W", "G", "Bnu", "kc", "sc",
                  "ntot", "Cul", "Clu"]
         extra = ["nu", "line_nu0", "line_s", "line_a", "dopp"]
