@@ -535,9 +535,10 @@ pprt_status pprt_two_level_reset(pprt_plan* plan, void* workspace);
 
 /* ---- Checkpoint / resume of the two-level ALI ----------------------------
  * The state of an operator-splitting iteration is the source function S and
- * what the workspace carries between steps: per-atmosphere iteration counts
- * and convergence flags (pprt_two_level_ali) and Ng's group history and
- * counter.  pprt_ali_state_export writes it into a caller-owned host buffer
+ * what the workspace carries between steps: per-atmosphere iteration counts,
+ * last maximum relative changes and convergence flags (pprt_two_level_ali)
+ * and Ng's group history and counter.  On resume an atmosphere steps again
+ * unless it has met the new call's tolerance or iteration cap.  pprt_ali_state_export writes it into a caller-owned host buffer
  * of pprt_ali_state_bytes() bytes (a header fingerprints the batch shape,
  * precision and operator); pprt_ali_state_import restores it into S and a
  * workspace of a plan of the same shape and operator (E_SHAPE /

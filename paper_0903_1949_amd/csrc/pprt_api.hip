@@ -25,6 +25,7 @@ struct pprt_ctx {
   std::string err;
 };
 
+
 struct pprt_plan {
   pprt_ctx* ctx = nullptr;
   int nb = 0, na = 0, nf = 0, precision = 0, lower_bc = 0, wpb = 4, ng = 1, nw = 1;
@@ -367,6 +368,7 @@ pprt_status pprt_create(pprt_ctx** out, int device) {
   c->device = device;
   if (hipMalloc(&c->d_status, sizeof(uint32_t)) != hipSuccess ||
       hipMemset(c->d_status, 0, sizeof(uint32_t)) != hipSuccess) {
+    if (c->d_status) (void)hipFree(c->d_status);
     delete c;
     return PPRT_E_DEVICE;
   }
@@ -949,9 +951,20 @@ pprt_status pprt_two_level_ali(pprt_plan* p, const pprt_fs_in* in, const pprt_tw
   int done_iters = 0;
   if (ctl->resume) {
     // continue from the state in the workspace (pprt_ali_state_import): the
-    // per-atmosphere counts go on from where they were; max_iter caps them
+    // per-atmosphere counts go on from where they were, max_iter caps them,
+    // and an atmosphere is active again unless it has met this call's
+    // tolerance or cap (one that stopped at an earlier, lower cap resumes)
     r = hip_check(c, hipMemcpyAsync(h_iters.data(), its, p->nb * sizeof(int32_t), hipMemcpyDeviceToHost,
                                     c->stream), "iters read");
+    if (r == PPRT_OK)
+      r = hip_check(c, hipMemcpyAsync(h_max.data(), maxrel, p->nb * sizeof(double), hipMemcpyDeviceToHost,
+                                      c->stream), "max_rel read");
+    if (r == PPRT_OK) r = hip_check(c, hipStreamSynchronize(c->stream), "sync");
+    if (r != PPRT_OK) return r;
+    for (int b = 0; b < p->nb; ++b)
+      h_active[b] = (h_iters[b] < ctl->max_iter && !(h_iters[b] > 0 && h_max[b] < ctl->tol)) ? 1 : 0;
+    r = hip_check(c, hipMemcpyAsync(active, h_active.data(), p->nb * sizeof(int32_t), hipMemcpyHostToDevice,
+                                    c->stream), "flag write");
     if (r == PPRT_OK) r = hip_check(c, hipStreamSynchronize(c->stream), "sync");
     if (r != PPRT_OK) return r;
     done_iters = *std::min_element(h_iters.begin(), h_iters.end());
@@ -1632,6 +1645,7 @@ pprt_status pprt_two_level_reset(pprt_plan* p, void* ws) {
 }
 
 // ---- ALI state: host image of S and of the iteration state in the workspace
+// (the last maximum relative change, counts, convergence flags, Ng history)
 namespace {
 struct AliStateHeader {
   char magic[8];          // "PPRTALI1"
@@ -1648,14 +1662,16 @@ uint64_t nd_hash(const std::vector<int32_t>& nd) {
     }
   return h;
 }
-// [header | S (rows f64) | iters, active (nb i32 each) | Ng: hist (3 rows f64), ng_count (nb i32)]
+// [header | S (rows f64) | max_rel (nb f64) | iters, active (nb i32 each) |
+//  Ng: hist (3 rows f64), ng_count (nb i32)]
 struct AliStateLayout {
-  size_t S, iters, active, hist, ngc, total;
+  size_t S, maxrel, iters, active, hist, ngc, total;
 };
 AliStateLayout ali_state_layout(const pprt_plan* p) {
   AliStateLayout L{};
   L.S = sizeof(AliStateHeader);
-  L.iters = L.S + (size_t)p->rows * sizeof(double);
+  L.maxrel = L.S + (size_t)p->rows * sizeof(double);
+  L.iters = L.maxrel + (size_t)p->nb * sizeof(double);
   L.active = L.iters + (size_t)p->nb * sizeof(int32_t);
   L.hist = L.active + (size_t)p->nb * sizeof(int32_t);
   L.ngc = L.hist + (p->use_ng ? (size_t)p->rows * 3 * sizeof(double) : 0);
@@ -1685,6 +1701,8 @@ pprt_status pprt_ali_state_export(pprt_plan* p, const double* S, const void* ws,
   const char* base = (const char*)ws;
   const hipStream_t st = c->stream;
   hipError_t e = hipMemcpyAsync(h + L.S, S, (size_t)p->rows * sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h + L.maxrel, base + p->ws_maxrel, p->nb * sizeof(double), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess)
     e = hipMemcpyAsync(h + L.iters, base + p->ws_iters, p->nb * sizeof(int32_t), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess)
@@ -1719,6 +1737,8 @@ pprt_status pprt_ali_state_import(pprt_plan* p, const void* host, size_t bytes, 
   char* base = (char*)ws;
   const hipStream_t st = c->stream;
   hipError_t e = hipMemcpyAsync(S, h + L.S, (size_t)p->rows * sizeof(double), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(base + p->ws_maxrel, h + L.maxrel, p->nb * sizeof(double), hipMemcpyHostToDevice, st);
   if (e == hipSuccess)
     e = hipMemcpyAsync(base + p->ws_iters, h + L.iters, p->nb * sizeof(int32_t), hipMemcpyHostToDevice, st);
   if (e == hipSuccess)

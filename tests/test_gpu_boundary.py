@@ -29,18 +29,33 @@ def small_atom():
     return W.multilevel_atom(nbound=3, ncont=2, nd=16, na=4, nline_pts=10, ncont_pts=6, seed=11)
 
 
-def test_nlte_solve_matches_oracle_loop(gpu_ctx, small_atom):
+def _count_slack(ref, tol):
+    """0 when the oracle's last two changes sit clearly on either side of
+    tol (10%), else 1: the populations of the two sides agree to ~1e-9
+    relative, so a change that lands within rounding of tol may cross it one
+    iteration earlier or later."""
+    h = ref["max_rel"]
+    k = ref["iterations"]
+    clear = h[k - 1] < 0.9 * tol and (k < 2 or h[k - 2] > 1.1 * tol)
+    return 0 if clear else 1
+
+
+@pytest.mark.parametrize("tol", [1e-7, 1e-9])
+def test_nlte_solve_matches_oracle_loop(gpu_ctx, small_atom, tol):
     a = small_atom
     plan = _mplan(gpu_ctx, a)
     da = pprt.DeviceAtom(a)
     pops = da.nstar.clone()
     iters = torch.zeros(1, dtype=torch.int32, device="cuda:0")
-    rep = plan.nlte_solve(da.tau, da, pops, tol=1e-9, max_iter=400, iters_per_sync=16, iters=iters)
-    ref = rates.nlte_solve(a, plan.mu, plan.w, tol=1e-9, max_iter=400)
+    rep = plan.nlte_solve(da.tau, da, pops, tol=tol, max_iter=400, iters_per_sync=16, iters=iters)
+    ref = rates.nlte_solve(a, plan.mu, plan.w, tol=tol, max_iter=400)
     e = float(np.max(np.abs(pops.cpu().numpy() / ref["pops"] - 1)))
-    print(f"  gpu {rep['iterations']} iterations, oracle {ref['iterations']}, rel err {e:.2e}", flush=True)
+    slack = _count_slack(ref, tol)
+    print(f"  tol {tol:.0e}: gpu {rep['iterations']} iterations, oracle {ref['iterations']} "
+          f"(last changes {ref['max_rel'][-2:]}, slack {slack}), rel err {e:.2e}", flush=True)
     assert rep["status"] == "OK" and rep["n_converged"] == 1
-    assert int(iters.item()) == rep["iterations"] == ref["iterations"]
+    assert int(iters.item()) == rep["iterations"]
+    assert abs(rep["iterations"] - ref["iterations"]) <= slack
     assert e < 1e-8
 
 
@@ -70,7 +85,7 @@ def test_nlte_solve_batch_freezes_converged_atmospheres(gpu_ctx):
         e = float(np.max(np.abs(got[s] / ref["pops"] - 1)))
         print(f"  atmosphere {b}: gpu {int(iters[b])} oracle {ref['iterations']} rel err {e:.2e}", flush=True)
         counts.append(ref["iterations"])
-        assert int(iters[b]) == ref["iterations"]
+        assert abs(int(iters[b]) - ref["iterations"]) <= _count_slack(ref, 1e-7)
         assert e < 1e-8
     assert len(set(counts)) > 1      # the atmospheres really stopped at different steps
 
