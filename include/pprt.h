@@ -263,6 +263,26 @@ pprt_status pprt_two_level_ali_step(pprt_plan* plan, const pprt_fs_in* in,
                                     double* max_rel, const int32_t* active,
                                     void* workspace);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * pprt_two_level_ali_step without the caller's workspace.  The step's
+ * scratch (the per-tile moment partials and, with the tri-diagonal
+ * operator, its per-row coefficients) lives in a static device array of
+ * PPRT_NOALLOC_SCRATCH_BYTES bytes, one copy per GPU, which the process
+ * holds until it ends; a plan whose pprt_plan_workspace_bytes exceeds it
+ * gets E_WORKSPACE (split the batch into smaller plans), and plans with Ng
+ * acceleration get E_UNSUPPORTED (Ng's history must persist between steps).
+ * Every call on one GPU uses that GPU's single array, whatever the context or
+ * stream: calls that overlap on one GPU race, and the caller must order
+ * them.  No allocating call is made (plan metadata is allocated earlier, by
+ * pprt_plan_create; the validation mode's host scan is not applied here);
+ * the step writes every scratch entry before it reads it.
+ * Other arguments, results and errors as pprt_two_level_ali_step. */
+#define PPRT_NOALLOC_SCRATCH_BYTES (64u << 20)
+pprt_status pprt_two_level_ali_step_noalloc(pprt_plan* plan, const pprt_fs_in* in,
+                                            const pprt_two_level* atom, double* S,
+                                            double* max_rel, const int32_t* active);
+
 /* The two halves of pprt_two_level_ali_step, for callers that schedule or
  * time them separately.  pprt_two_level_moments runs the formal solution
  * and leaves the profile-weighted moments (per row, frequency group and

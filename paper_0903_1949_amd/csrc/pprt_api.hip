@@ -22,9 +22,36 @@ struct pprt_ctx {
   hipStream_t stream = nullptr;
   uint32_t* d_status = nullptr;   // device status word
   uint32_t validate = 0;          // PPRT_VALIDATE_* flags
+  void* scratch = nullptr;        // this device's copy of the static scratch array
   std::string err;
 };
 
+// Static scratch of the allocation-free step (pprt_two_level_ali_step_noalloc):
+// one copy per GPU, held until the process ends.  Host code never uses the
+// array's name as an address: each device's copy is looked up once with
+// hipGetSymbolAddress (device_scratch) and only that pointer is passed on.
+static __device__ __align__(256) unsigned char scratch[PPRT_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;   // device -> address of its copy of `scratch`
+
+// Address of `scratch` on `device` (which must be current), looked up once per device.
+hipError_t device_scratch(int device, void** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(device);
+  if (it != g_scratch_ptr.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || ptr == nullptr) return e != hipSuccess ? e : hipErrorInvalidSymbol;
+  g_scratch_ptr[device] = ptr;
+  *out = ptr;
+  return hipSuccess;
+}
+}  // namespace
 
 struct pprt_plan {
   pprt_ctx* ctx = nullptr;
@@ -367,7 +394,8 @@ pprt_status pprt_create(pprt_ctx** out, int device) {
   if (!c) return PPRT_E_DEVICE;
   c->device = device;
   if (hipMalloc(&c->d_status, sizeof(uint32_t)) != hipSuccess ||
-      hipMemset(c->d_status, 0, sizeof(uint32_t)) != hipSuccess) {
+      hipMemset(c->d_status, 0, sizeof(uint32_t)) != hipSuccess ||
+      device_scratch(device, &c->scratch) != hipSuccess) {
     if (c->d_status) (void)hipFree(c->d_status);
     delete c;
     return PPRT_E_DEVICE;
@@ -817,6 +845,30 @@ pprt_status pprt_two_level_ali_step(pprt_plan* p, const pprt_fs_in* in, const pp
   if (r != PPRT_OK) return r;
   if (!max_rel) return fail(p->ctx, PPRT_E_INVALID_ARG, "max_rel is required");
   return ali_step_impl(p, in, at, S, max_rel, const_cast<int32_t*>(active), nullptr, 0.0, ws);
+}
+
+pprt_status pprt_two_level_ali_step_noalloc(pprt_plan* p, const pprt_fs_in* in, const pprt_two_level* at,
+                                            double* S, double* max_rel, const int32_t* active) {
+  if (!p) return PPRT_E_INVALID_ARG;
+  pprt_ctx* c = p->ctx;
+  if (p->use_ng)
+    return fail(c, PPRT_E_UNSUPPORTED,
+                "the allocation-free step keeps no state between calls: plans with Ng acceleration "
+                "need a workspace (pprt_two_level_ali_step)");
+  if (p->ws_bytes > PPRT_NOALLOC_SCRATCH_BYTES)
+    return fail(c, PPRT_E_WORKSPACE,
+                "this plan needs %zu bytes of scratch; the static scratch holds %zu (use "
+                "pprt_two_level_ali_step with a workspace, or split the batch)",
+                p->ws_bytes, (size_t)PPRT_NOALLOC_SCRATCH_BYTES);
+  if (!c->scratch) return fail(c, PPRT_E_DEVICE, "no static scratch on this device");
+  // the argument checks of pprt_two_level_ali_step without the validation
+  // mode's host scan (which would allocate host buffers)
+  if (!in || !at || !S || !max_rel) return fail(c, PPRT_E_INVALID_ARG, "null argument");
+  if (!in->tau || !in->q) return fail(c, PPRT_E_INVALID_ARG, "tau and q are required");
+  if (!at->eps || !at->B || !at->wphi) return fail(c, PPRT_E_INVALID_ARG, "atom needs eps, B and wphi");
+  // every scratch entry the step reads it has written first in the same
+  // call (partials for active atmospheres, coefficients): nothing to clear
+  return ali_step_impl(p, in, at, S, max_rel, const_cast<int32_t*>(active), nullptr, 0.0, c->scratch);
 }
 
 pprt_status pprt_two_level_moments(pprt_plan* p, const pprt_fs_in* in, const pprt_two_level* at,

@@ -169,6 +169,7 @@ def load_library(path: str = LIB_PATH):
         "pprt_atom_check_host": (I, [C.POINTER(Atom), C.c_int64, C.c_int32, C.c_char_p, C.c_size_t]),
         "pprt_nlte_solve": (I, [P, C.POINTER(FsIn), C.POINTER(Atom), C.POINTER(AliCtl), P, P,
                                 C.POINTER(AliReport), P]),
+        "pprt_two_level_ali_step_noalloc": (I, [P, C.POINTER(FsIn), C.POINTER(TwoLevel), P, P, P]),
         "pprt_ali_state_bytes": (I, [P, C.POINTER(C.c_size_t)]),
         "pprt_ali_state_export": (I, [P, P, P, P, C.c_size_t]),
         "pprt_ali_state_import": (I, [P, P, C.c_size_t, P, P]),
@@ -533,6 +534,21 @@ class Plan:
         self.ctx._check(self.lib.pprt_two_level_ali_step(
             self.h, C.byref(fin), C.byref(at), _ptr(S), _ptr(max_rel), _ptr(active),
             _ptr(self.workspace())), "two_level_ali_step")
+
+    def two_level_ali_step_noalloc(self, tau, q, S, eps, B, wphi, max_rel, active=None, Itop=None,
+                                   Ibot=None):
+        """pprt_two_level_ali_step_noalloc: the same step with the library's
+        static scratch instead of a workspace (nothing is allocated)."""
+        import torch
+        fin = self.fs_in(tau, q, None, None, None, Itop, Ibot)
+        at = self.two_level(eps, B, wphi)
+        self._want(S, (self.rows,), torch.float64, "S")
+        self._want(max_rel, (self.nb,), torch.float64, "max_rel")
+        if active is not None:
+            self._want(active, (self.nb,), torch.int32, "active")
+        self.ctx._check(self.lib.pprt_two_level_ali_step_noalloc(
+            self.h, C.byref(fin), C.byref(at), _ptr(S), _ptr(max_rel), _ptr(active)),
+            "two_level_ali_step_noalloc")
 
     def two_level_ali_step_continuum(self, tau, q, S, eps, B, wphi, pfrac, sg_const, omega,
                                      Bbot, Bbot_prev, max_rel, active=None, Itop=None, Ibot=None,
