@@ -66,8 +66,6 @@ def parse():
                     help="worker processes of the all-core oracle run (0: the host's CPU share, at most 16)")
     ap.add_argument("--stat-replays", type=int, default=50,
                     help="launches behind the median / p10 / p90 step and kernel times")
-    ap.add_argument("--graph-steps", type=int, default=10,
-                    help="ALI steps captured in one hipGraph for the timed region")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (read + write) 5 times and "
                          "exit: the reference for scaling FETCH_SIZE / WRITE_SIZE counters")
@@ -204,42 +202,6 @@ def cpu_baseline_allcore(batch, seed, nworkers):
             "nproc": os.cpu_count(), "cpu_model": cpu_model()}
 
 
-def graph_of(ctx, fn):
-    """Capture the library launches made by fn() (on a side stream bound to
-    the context) in a torch CUDA graph; fn runs once eagerly first."""
-    import torch
-    main = torch.cuda.current_stream()
-    side = torch.cuda.Stream()
-    side.wait_stream(main)
-    with torch.cuda.stream(side):
-        ctx.set_stream(side)
-        fn()
-    main.wait_stream(side)
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g, stream=side):
-        ctx.set_stream(side)
-        fn()
-    ctx.set_stream(main)
-    torch.cuda.synchronize()
-    return g
-
-
-def replay_times(g, n, stream):
-    """n back-to-back replays of graph g with an event between each: wall
-    time and per-replay milliseconds (the GPU never waits for the host)."""
-    import torch
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    evs[0].record(stream)
-    for i in range(n):
-        g.replay()
-        evs[i + 1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    return wall, np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(n)])
-
-
 def launch_times(fn, n, stream):
     """n back-to-back eager launches of fn with events between them: the
     average (first to last event / n) and the per-launch milliseconds."""
@@ -321,20 +283,20 @@ def main():
         # the tuner's ~200 launches also bring the clocks up right before timing
         tune = plan.autotune(db.tau, db.q, db.S, db.eps, db.B, db.wphi, force=True)
     launch = plan.get_launch()
-    # The timed steps replay hipGraphs: one of args.graph_steps steps (the
-    # host launches one replay per several milliseconds of GPU work, so the
-    # GPU never waits for it) and one of a single step for the remainder.
-    G = max(1, args.graph_steps)
-    gG = graph_of(ctx, lambda: [step() for _ in range(G)])
-    g1 = graph_of(ctx, step)
+    # The timed steps are one launch of the library's persistent step graph
+    # (pprt_two_level_graph_create: the K steps captured once), after the
+    # warm-up steps launched as a graph of one step.
+    G = max(1, min(args.steps, 4096))
+    gG = plan.two_level_graph(db.tau, db.q, db.S, db.eps, db.B, db.wphi, mx, steps=G)
+    g1 = plan.two_level_graph(db.tau, db.q, db.S, db.eps, db.B, db.wphi, mx, steps=1)
     for _ in range(args.warmup):
-        g1.replay()
+        g1.launch()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps // G):
-        gG.replay()
+        gG.launch()
     for _ in range(args.steps % G):
-        g1.replay()
+        g1.launch()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = wall * 1e3 / args.steps
@@ -430,14 +392,13 @@ def main():
         # the batched step itself in FP64: same plan layout, k_fs_profile<double,8>
         def step64b():
             plan64.two_level_ali_step(db64.tau, db64.q, db64.S, db64.eps, db64.B, db64.wphi, mx64)
-        g64 = graph_of(ctx, step64b)
         for _ in range(3):
-            g64.replay()
-        w, per64 = replay_times(g64, max(args.fp64_steps, 10), stream)
+            step64b()
+        _, per64 = launch_times(step64b, max(args.fp64_steps, 10), stream)
         fp64_batched = {"value": pts / float(np.median(per64) * 1e-3),
                         "ms_per_step": stats_ms(per64)["median"], "step_ms_stats": stats_ms(per64),
                         "desc": "the same batched step in FP64 (k_fs_profile<double,8>: series for "
-                                "thin layers, exp for thick ones; FP64 partials), graph replays"}
+                                "thin layers, exp for thick ones; FP64 partials)"}
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -283,6 +283,23 @@ pprt_status pprt_two_level_ali_step_noalloc(pprt_plan* plan, const pprt_fs_in* i
                                             const pprt_two_level* atom, double* S,
                                             double* max_rel, const int32_t* active);
 
+/* A persistent step graph (the batched configuration's "one hipGraph
+ * launch"): `steps` consecutive pprt_two_level_ali_step calls on exactly
+ * these arguments are captured once into a hipGraph (on a private stream at
+ * the default priority) and instantiated; each pprt_graph_launch replays
+ * them on the context stream current at launch time, asynchronously, with
+ * the same results as the eager calls.  The pointers are baked into the
+ * graph: every array and the workspace must stay allocated, at the same
+ * addresses, until pprt_graph_destroy, and the plan must outlive the graph.
+ * Launches of one graph, like the steps, must be ordered on one stream. */
+typedef struct pprt_graph pprt_graph;
+pprt_status pprt_two_level_graph_create(pprt_plan* plan, const pprt_fs_in* in,
+                                        const pprt_two_level* atom, double* S, double* max_rel,
+                                        const int32_t* active, void* workspace, int32_t steps,
+                                        pprt_graph** out);
+pprt_status pprt_graph_launch(pprt_graph* graph);
+void pprt_graph_destroy(pprt_graph* graph);
+
 /* The two halves of pprt_two_level_ali_step, for callers that schedule or
  * time them separately.  pprt_two_level_moments runs the formal solution
  * and leaves the profile-weighted moments (per row, frequency group and

@@ -307,22 +307,26 @@ struct ProfileLayout {
 };
 
 // One layer of the difference-form sweep for all angles, with the
-// Lambda*-complement sum ls += sum_i (w_i/2) psi_i.
+// Lambda*-complement sum ls += sum_i wh_i psi_i (wh_i: the lane's weight of
+// angle i, w_i/2 times its frequency's profile weight).
 //
-// FP32.  Optically thin (Delta < 1/4): psi from a degree-4 polynomial fitted
-// to (1 - e^-Delta)/Delta on [0, 1/4] for least maximum relative error
-// (Remez exchange; fitted error 2.5e-9, below FP32 rounding; evaluated in
-// FP32 the error is 4.5e-8), and the update written without e, using
-// 1 - e = Delta psi:
-//     D <- D + psi (dS - Delta D)        (= e D + psi dS).
-// Thick: e = 2^(-dtau c) (v_exp_f32), psi = m - e m, m = mu / dtau.
-// Because Delta_i = dtau / mu_i, the wave decides once per layer: all angles
-// thin when dtau < min_i(mu_i)/4 in every lane, all thick when
-// dtau >= max_i(mu_i)/4 in every lane, otherwise per angle (and per lane when
-// the lanes disagree).  The reciprocal of dtau is formed only for thick work.
+// FP32.  Every angle takes the same update,
+//     D <- D + psi (dS - Delta D)        (= e D + psi dS, as 1 - e = Delta psi),
+// and only psi is formed by regime.  Optically thin (Delta < 1/4): psi from a
+// degree-4 polynomial fitted to (1 - e^-Delta)/Delta on [0, 1/4] for least
+// maximum relative error (Remez exchange; fitted error 2.5e-9, below FP32
+// rounding; evaluated in FP32 the error is 4.5e-8).  Thick: psi = m - e m,
+// e = 2^(-dtau c) (v_exp_f32), m = mu / dtau; there 1 - Delta psi equals e up
+// to an absolute rounding error of order 1e-7, i.e. the transmitted term keeps
+// a relative accuracy of order 1e-7 of D, like e D itself.  Because
+// Delta_i = dtau / mu_i, the wave decides once per layer: all angles thin when
+// dtau < min_i(mu_i)/4 in every lane, all thick when dtau >= max_i(mu_i)/4 in
+// every lane, otherwise per angle (and per lane when the lanes disagree).  The
+// branches produce only psi, so the intensities are updated in place after
+// they join (no register copies of the NA intensities at the join).
 template <int NA>
-__device__ __forceinline__ void sweep_layer(const Angles<float>& ang, float dt, float dS,
-                                            float (&D)[NA], float& ls) {
+__device__ __forceinline__ void sweep_layer(const Angles<float>& ang, const float (&wh)[NA], float dt,
+                                            float dS, float (&D)[NA], float& ls) {
   constexpr float kThin = 0.25f;
   auto psi_poly = [](float x) {
     float p = fmaf(x, 7.510221563279629e-3f, -4.1488952934741974e-2f);
@@ -330,64 +334,52 @@ __device__ __forceinline__ void sweep_layer(const Angles<float>& ang, float dt, 
     p = fmaf(x, p, -4.999994933605194e-1f);
     return fmaf(x, p, 1.0f);
   };
+  auto psi_exp = [&](int i, float inv) {
+    const float e = __builtin_amdgcn_exp2f(-(dt * ang.c[i]));
+    const float m = ang.mu[i] * inv;
+    return fmaf(-e, m, m);
+  };
+  float ps[NA], x[NA];
+#pragma unroll
+  for (int i = 0; i < NA; ++i) x[i] = dt * ang.rmu[i];     // Delta_i
   const unsigned long long act = __ballot(1);
   const bool all_thin = __ballot(dt < ang.dt_all_thin) == act;
-  const bool all_thick = !all_thin && __ballot(dt >= ang.dt_all_thick) == act;
   if (all_thin) {
 #pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      const float x = dt * ang.rmu[i];
-      const float ps = psi_poly(x);
-      D[i] = fmaf(ps, fmaf(-x, D[i], dS), D[i]);
-      ls = fmaf(ang.hw[i], ps, ls);
-    }
-    return;
-  }
-  const float inv = recip(dt);
-  if (all_thick) {
+    for (int i = 0; i < NA; ++i) ps[i] = psi_poly(x[i]);
+  } else {
+    const float inv = recip(dt);
+    if (__ballot(dt >= ang.dt_all_thick) == act) {
 #pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      const float e = __builtin_amdgcn_exp2f(-(dt * ang.c[i]));
-      const float m = ang.mu[i] * inv;
-      const float ps = fmaf(-e, m, m);
-      D[i] = fmaf(e, D[i], ps * dS);
-      ls = fmaf(ang.hw[i], ps, ls);
+      for (int i = 0; i < NA; ++i) ps[i] = psi_exp(i, inv);
+    } else {
+#pragma unroll
+      for (int i = 0; i < NA; ++i) {
+        const bool thin = x[i] < kThin;
+        const unsigned long long tb = __ballot(thin);
+        if (tb == act) {
+          ps[i] = psi_poly(x[i]);
+        } else if (tb == 0) {
+          ps[i] = psi_exp(i, inv);
+        } else {
+          const float p1 = psi_poly(x[i]);
+          const float p2 = psi_exp(i, inv);
+          ps[i] = thin ? p1 : p2;
+        }
+      }
     }
-    return;
   }
 #pragma unroll
   for (int i = 0; i < NA; ++i) {
-    const float x = dt * ang.rmu[i];
-    const bool thin = x < kThin;
-    const unsigned long long tb = __ballot(thin);
-    float ps, Dn;
-    if (tb == act) {
-      ps = psi_poly(x);
-      Dn = fmaf(ps, fmaf(-x, D[i], dS), D[i]);
-    } else if (tb == 0) {
-      const float e = __builtin_amdgcn_exp2f(-(dt * ang.c[i]));
-      const float m = ang.mu[i] * inv;
-      ps = fmaf(-e, m, m);
-      Dn = fmaf(e, D[i], ps * dS);
-    } else {
-      const float p1 = psi_poly(x);
-      const float D1 = fmaf(p1, fmaf(-x, D[i], dS), D[i]);
-      const float e = __builtin_amdgcn_exp2f(-(dt * ang.c[i]));
-      const float m = ang.mu[i] * inv;
-      const float p2 = fmaf(-e, m, m);
-      const float D2 = fmaf(e, D[i], p2 * dS);
-      ps = thin ? p1 : p2;
-      Dn = thin ? D1 : D2;
-    }
-    D[i] = Dn;
-    ls = fmaf(ang.hw[i], ps, ls);
+    D[i] = fmaf(ps[i], fmaf(-x[i], D[i], dS), D[i]);
+    ls = fmaf(wh[i], ps[i], ls);
   }
 }
 
 // FP64: the series below 1/4, the closed form above (as described in the loop).
 template <int NA>
-__device__ __forceinline__ void sweep_layer(const Angles<double>& ang, double dt, double dS,
-                                            double (&D)[NA], double& ls) {
+__device__ __forceinline__ void sweep_layer(const Angles<double>& ang, const double (&wh)[NA], double dt,
+                                            double dS, double (&D)[NA], double& ls) {
   const double inv = recip(dt);
 #pragma unroll
   for (int i = 0; i < NA; ++i) {
@@ -416,7 +408,7 @@ __device__ __forceinline__ void sweep_layer(const Angles<double>& ang, double dt
       ps = (1.0 - e) * (ang.mu[i] * inv);
     }
     D[i] = e * D[i] + ps * dS;
-    ls += ang.hw[i] * ps;
+    ls += wh[i] * ps;
   }
 }
 
@@ -431,19 +423,31 @@ __device__ __forceinline__ void profile_sweep(const FsProfileArgs<T>& a, const A
   const int kk = k < nf ? k : nf - 1;         // clamped: loads stay in bounds
   const int64_t row0 = a.off[b];
   const T wp = k < nf ? a.wphi[kk] : T(0);
-  const T* __restrict__ qcol = a.q + kk;
+  T wh[NA];                                   // the lane's weights: profile x angle
+#pragma unroll
+  for (int i = 0; i < NA; ++i) wh[i] = wp * ang.hw[i];
+  // q of node `row` for this lane: a uniform row base plus the lane's column
+  auto qat = [&](int64_t row) { return a.q[row * nf + kk]; };
+  // S, B and the per-row differences are read-only for the whole launch and
+  // their index is uniform over the wave: reading them through the constant
+  // address space makes them scalar loads, kept in scalar registers
+  using cdouble = const __attribute__((address_space(4))) double;
+  using cT = const __attribute__((address_space(4))) T;
+  cdouble* const Sc = (cdouble*)a.S;
+  cdouble* const Bc = (cdouble*)a.B;
+  cT* const dtr = (cT*)a.dtr;     // T(tau[r+1] - tau[r]) / 2
+  cT* const dSr = (cT*)a.dSr;     // T(S[r+1] - S[r])
 
   T D[NA];
   int d = UP ? nd - 1 : 0;
-  T qn = qcol[(row0 + d) * nf];
-  double Sn = a.S[row0 + d];
-  double tn = a.tau[row0 + d];
+  T qn = qat(row0 + d);
+  double Sn = Sc[row0 + d];
   if (UP) {
-    const T qa = qcol[(row0 + d - 1) * nf];
-    const T dt = T(0.5) * (qa + qn) * T(tn - a.tau[row0 + d - 1]);
+    const T qa = qat(row0 + d - 1);
+    const T dt = (qa + qn) * dtr[row0 + d - 1];
     if (a.lower_bc == PPRT_BC_DIFFUSION) {
-      const double Bb = a.B[row0 + d];
-      const double Bp = a.B[row0 + d - 1];
+      const double Bb = Bc[row0 + d];
+      const double Bp = Bc[row0 + d - 1];
       const T g = T(Bb - Bp) / dt;
       const T base = T(Bb - Sn);
 #pragma unroll
@@ -493,18 +497,18 @@ __device__ __forceinline__ void profile_sweep(const FsProfileArgs<T>& a, const A
   };
   auto park = [&](int j, T jsum, T lsum, T band) {
     const int slot = j % CHN;
-    slab[(NQ * slot + 0) * 64 + lane] = wp * jsum;
-    slab[(NQ * slot + 1) * 64 + lane] = wp * lsum;
+    slab[(NQ * slot + 0) * 64 + lane] = jsum;        // weighted already
+    slab[(NQ * slot + 1) * 64 + lane] = lsum;
     if (TRI) slab[(NQ * slot + 2) * 64 + lane] = wp * band;
   };
   auto node_sum = [&]() {
     T js = T(0);
 #pragma unroll
-    for (int i = 0; i < NA; ++i) js += ang.hw[i] * D[i];
+    for (int i = 0; i < NA; ++i) js += wh[i] * D[i];
     return js;
   };
 
-  park(0, node_sum(), ang.hwsum, T(0));
+  park(0, node_sum(), wp * ang.hwsum, T(0));
   int j0 = 0;
   // TRI: alpha of the previous layer in sweep order, per angle (0 before the
   // first layer: the boundary node's intensity does not depend on S)
@@ -513,26 +517,24 @@ __device__ __forceinline__ void profile_sweep(const FsProfileArgs<T>& a, const A
   for (int i = 0; i < (TRI ? NA : 1); ++i) aprev[i] = T(0);
   // prefetch the next node of the sweep
   int dn = UP ? nd - 2 : 1;
-  T qf = qcol[(row0 + dn) * nf];
-  double Sf = a.S[row0 + dn];
-  double tf = a.tau[row0 + dn];
+  T qf = qat(row0 + dn);
   for (int j = 1; j < nd; ++j) {
     if (j % CHN == 0) {
       flush(j0, CHN);
       j0 = j;
     }
     const T qd = qf;
-    const double Sd = Sf;
-    const double td = tf;
+    // the layer between this node and its predecessor in sweep order spans
+    // rows l, l+1: its reference depth and the source change across it
+    const int64_t l = row0 + (UP ? nd - 1 - j : j - 1);
+    const T dtl = dtr[l];
+    const T dSl = dSr[l];
     if (j + 1 < nd) {
       dn = UP ? nd - 2 - j : j + 1;
-      qf = qcol[(row0 + dn) * nf];
-      Sf = a.S[row0 + dn];
-      tf = a.tau[row0 + dn];
+      qf = qat(row0 + dn);
     }
-    // layer between this node and its predecessor in sweep order
-    const T dt = T(0.5) * (qd + qn) * T(UP ? (tn - td) : (td - tn));
-    const T dS = T(Sn - Sd);
+    const T dt = (qd + qn) * dtl;             // dtl = half the reference depth
+    const T dS = UP ? dSl : -dSl;
     T ls = T(0), band = T(0);
     if (TRI) {
       // with the neighbour coupling: the layer's alpha, gamma and e per angle
@@ -550,7 +552,7 @@ __device__ __forceinline__ void profile_sweep(const FsProfileArgs<T>& a, const A
             else if constexpr (R == 1) layer_w_thick<true>(dt, inv, ang.c[i], ang.mu[i], e, ps, al, ga);
             else layer_w<true>(dt, inv, ang.c[i], ang.rmu[i], ang.mu[i], e, ps, al, ga);
             D[i] = e * D[i] + ps * dS;
-            ls += ang.hw[i] * ps;
+            ls += wh[i] * ps;
             band += ang.hw[i] * (ga + e * aprev[i]);
             aprev[i] = al;
           }
@@ -565,16 +567,16 @@ __device__ __forceinline__ void profile_sweep(const FsProfileArgs<T>& a, const A
           T e, ps, al, ga;
           layer_w<true>(dt, inv, ang.c[i], ang.rmu[i], ang.mu[i], e, ps, al, ga);
           D[i] = e * D[i] + ps * dS;
-          ls += ang.hw[i] * ps;
+          ls += wh[i] * ps;
           band += ang.hw[i] * (ga + e * aprev[i]);
           aprev[i] = al;
         }
       }
     } else {
-      sweep_layer(ang, dt, dS, D, ls);
+      sweep_layer(ang, wh, dt, dS, D, ls);
     }
     park(j, node_sum(), ls, band);
-    qn = qd; Sn = Sd; tn = td;
+    qn = qd;
   }
   flush(j0, nd - j0);
 }
@@ -582,7 +584,9 @@ __device__ __forceinline__ void profile_sweep(const FsProfileArgs<T>& a, const A
 template <typename T, int NA, bool TRI>
 __global__ __launch_bounds__(512) void k_fs_profile(FsProfileArgs<T> a, Angles<T> ang) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  const int wave = (int)(threadIdx.x >> 6);
+  // the wave index is uniform over the wave: say so, so that the item, the
+  // atmosphere's offsets and its per-row data are loaded and kept as scalars
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   T* slab = reinterpret_cast<T*>(lds_raw) +
             (size_t)wave * (ProfileLayout<TRI>::NQ * ProfileLayout<TRI>::CHN * 64);
   if (a.queue == nullptr) {
@@ -611,6 +615,22 @@ __global__ __launch_bounds__(512) void k_fs_profile(FsProfileArgs<T> a, Angles<T
     else
       profile_sweep<T, NA, false, TRI>(a, ang, it, slab);
   }
+}
+
+// Per-row differences for the batched sweep, rounded once to T:
+//     dtr[r] = T(tau[r+1] - tau[r]) / 2,   dSr[r] = T(S[r+1] - S[r])
+// (the last row has no successor: 0; rows that straddle two atmospheres are
+// never read).  The halving is exact, so a layer's optical depth
+// (q_d + q_{d+1}) dtr is the same number as 1/2 (q_d + q_{d+1}) T(dtau).
+template <typename T>
+__global__ __launch_bounds__(256) void k_row_diffs(const double* __restrict__ tau,
+                                                   const double* __restrict__ S, int64_t rows,
+                                                   T* __restrict__ dtr, T* __restrict__ dSr) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  const bool last = r + 1 >= rows;
+  dtr[r] = last ? T(0) : T(0.5) * T(tau[r + 1] - tau[r]);
+  dSr[r] = last ? T(0) : T(S[r + 1] - S[r]);
 }
 
 template <typename T, int NA>
@@ -674,6 +694,17 @@ hipError_t launch_fs_full(int precision, int na, int wpb, int nitems, hipStream_
   if (nitems == 0) return hipSuccess;
   return precision == PPRT_FP64 ? dispatch_full<double>(na, wpb, nitems, s, args, angles)
                                 : dispatch_full<float>(na, wpb, nitems, s, args, angles);
+}
+
+hipError_t launch_row_diffs(int precision, const double* tau, const double* S, int64_t rows, void* dtr,
+                            void* dSr, hipStream_t s) {
+  if (rows == 0) return hipSuccess;
+  const dim3 grid((unsigned)((rows + 255) / 256));
+  if (precision == PPRT_FP64)
+    hipLaunchKernelGGL(k_row_diffs<double>, grid, dim3(256), 0, s, tau, S, rows, (double*)dtr, (double*)dSr);
+  else
+    hipLaunchKernelGGL(k_row_diffs<float>, grid, dim3(256), 0, s, tau, S, rows, (float*)dtr, (float*)dSr);
+  return hipGetLastError();
 }
 
 hipError_t launch_fs_profile(int precision, int na, int wpb, int nitems, int nblocks, bool tri,

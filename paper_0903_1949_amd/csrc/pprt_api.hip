@@ -79,7 +79,7 @@ struct pprt_plan {
   Angles<float> af{};
   Angles<double> ad{};
   // workspace layout of the ALI calls
-  size_t ws_part = 0, ws_maxrel = 0, ws_active = 0, ws_iters = 0, ws_bytes = 0;
+  size_t ws_part = 0, ws_rowd = 0, ws_maxrel = 0, ws_active = 0, ws_iters = 0, ws_bytes = 0;
   // two-level operator: tri-diagonal Lambda* and/or Ng acceleration
   int lstar_tri = 0, use_ng = 0;
   size_t ws_coef = 0, ws_hist = 0, ws_ngc = 0;
@@ -214,6 +214,8 @@ void layout_ali_workspace(pprt_plan* p) {
   size_t o = 0;
   p->ws_part = o;
   o = align256(o + (size_t)p->rows * p->nw * 2 * nqp * es);
+  p->ws_rowd = o;                       // per-row tau and S differences of the sweep
+  o = align256(o + (size_t)p->rows * 2 * es);
   p->ws_maxrel = o;
   o = align256(o + (size_t)p->nb * sizeof(double));
   p->ws_active = o;
@@ -726,17 +728,23 @@ static pprt_status ali_moments_impl(pprt_plan* p, const pprt_fs_in* in, const pp
                                     const double* S, const int32_t* active, void* ws) {
   pprt_ctx* c = p->ctx;
   void* part = (char*)ws + p->ws_part;
+  const size_t es = p->precision == PPRT_FP64 ? sizeof(double) : sizeof(float);
+  char* dtr = (char*)ws + p->ws_rowd;
+  char* dSr = dtr + (size_t)p->rows * es;
   hipError_t e;
   if (p->prof_blocks) {   // zero the work counter with a kernel (safe inside a captured graph)
     e = launch_fill_i32(p->d_queue, 0, 1, c->stream);
     if (e != hipSuccess) return hip_check(c, e, "work counter reset");
   }
+  e = launch_row_diffs(p->precision, in->tau, S, p->rows, dtr, dSr, c->stream);
+  if (e != hipSuccess) return hip_check(c, e, "row differences");
 
   if (p->precision == PPRT_FP64) {
     FsProfileArgs<double> a{};
     a.items = p->d_items_prof; a.off = p->d_off; a.tau = in->tau; a.q = (const double*)in->q;
     a.S = S; a.B = at->B; a.Itop = (const double*)in->Itop; a.Ibot = (const double*)in->Ibot;
     a.wphi = (const double*)at->wphi; a.active = active; a.part = (double*)part;
+    a.dtr = (const double*)dtr; a.dSr = (const double*)dSr;
     a.queue = p->prof_blocks ? p->d_queue : nullptr;
     a.nf = p->nf; a.nw = p->nw; a.nitems = p->n_prof; a.lower_bc = p->lower_bc;
     e = launch_fs_profile(p->precision, p->na, p->wpb, p->n_prof, p->prof_blocks, p->lstar_tri != 0,
@@ -746,6 +754,7 @@ static pprt_status ali_moments_impl(pprt_plan* p, const pprt_fs_in* in, const pp
     a.items = p->d_items_prof; a.off = p->d_off; a.tau = in->tau; a.q = (const float*)in->q;
     a.S = S; a.B = at->B; a.Itop = (const float*)in->Itop; a.Ibot = (const float*)in->Ibot;
     a.wphi = (const float*)at->wphi; a.active = active; a.part = (float*)part;
+    a.dtr = (const float*)dtr; a.dSr = (const float*)dSr;
     a.queue = p->prof_blocks ? p->d_queue : nullptr;
     a.nf = p->nf; a.nw = p->nw; a.nitems = p->n_prof; a.lower_bc = p->lower_bc;
     e = launch_fs_profile(p->precision, p->na, p->wpb, p->n_prof, p->prof_blocks, p->lstar_tri != 0,
@@ -823,6 +832,11 @@ static pprt_status capture_ali_chunk(pprt_plan* p, const pprt_fs_in* in, const p
   return hip_check(c, hipGraphInstantiate(&gc.exec, gc.graph, nullptr, nullptr, 0), "graph instantiate");
 }
 
+struct pprt_graph {
+  pprt_plan* plan = nullptr;
+  GraphChunk chunk;
+};
+
 static pprt_status check_ali_args(pprt_plan* p, const pprt_fs_in* in, const pprt_two_level* at,
                                   const double* S, void* ws) {
   pprt_ctx* c = p->ctx;
@@ -870,6 +884,38 @@ pprt_status pprt_two_level_ali_step_noalloc(pprt_plan* p, const pprt_fs_in* in, 
   // call (partials for active atmospheres, coefficients): nothing to clear
   return ali_step_impl(p, in, at, S, max_rel, const_cast<int32_t*>(active), nullptr, 0.0, c->scratch);
 }
+
+pprt_status pprt_two_level_graph_create(pprt_plan* p, const pprt_fs_in* in, const pprt_two_level* at,
+                                        double* S, double* max_rel, const int32_t* active, void* ws,
+                                        int32_t steps, pprt_graph** out) {
+  if (!p) return PPRT_E_INVALID_ARG;
+  pprt_ctx* c = p->ctx;
+  if (!out) return fail(c, PPRT_E_INVALID_ARG, "null output handle");
+  *out = nullptr;
+  pprt_status r = check_ali_args(p, in, at, S, ws);
+  if (r != PPRT_OK) return r;
+  if (!max_rel) return fail(c, PPRT_E_INVALID_ARG, "max_rel is required");
+  if (steps < 1 || steps > 4096) return fail(c, PPRT_E_INVALID_ARG, "steps must be in 1..4096 (got %d)", steps);
+  pprt_graph* g = new (std::nothrow) pprt_graph;
+  if (!g) return fail(c, PPRT_E_DEVICE, "out of host memory");
+  g->plan = p;
+  r = capture_ali_chunk(p, in, at, S, max_rel, const_cast<int32_t*>(active), nullptr, 0.0, 0, steps, ws,
+                        g->chunk);
+  if (r != PPRT_OK) {
+    delete g;
+    return r;
+  }
+  *out = g;
+  return PPRT_OK;
+}
+
+pprt_status pprt_graph_launch(pprt_graph* g) {
+  if (!g || !g->plan || !g->chunk.exec) return PPRT_E_INVALID_ARG;
+  pprt_ctx* c = g->plan->ctx;
+  return hip_check(c, hipGraphLaunch(g->chunk.exec, c->stream), "graph launch");
+}
+
+void pprt_graph_destroy(pprt_graph* g) { delete g; }
 
 pprt_status pprt_two_level_moments(pprt_plan* p, const pprt_fs_in* in, const pprt_two_level* at,
                                    const double* S, const int32_t* active, void* ws) {

@@ -137,6 +137,8 @@ struct FsProfileArgs {
   const int32_t* active;    // [nb] or nullptr
   int32_t* queue;           // persistent launch: work counter (zeroed before launch); else nullptr
   T* part;                  // [rows][nw][2 dir][2 or 4] per-wave profile moments
+  const T* dtr;             // [rows] T(tau[r+1] - tau[r]) / 2 (launch_row_diffs)
+  const T* dSr;             // [rows] T(S[r+1] - S[r])
   int32_t nf;
   int32_t nw;               // waves across the frequency range, ceil(nf/64)
   int32_t nitems;           // one item per wave: (b, 64-frequency tile, dir)
@@ -362,6 +364,8 @@ hipError_t launch_fs_full(int precision, int na, int wpb, int nitems, hipStream_
 // blocks whose waves take items from args.queue.
 // tri: also reduce the tri-diagonal band (part[] then has 4 entries per
 // (row, tile, hemisphere): J-S, 1-Lambda*, band, unused).
+hipError_t launch_row_diffs(int precision, const double* tau, const double* S, int64_t rows, void* dtr,
+                            void* dSr, hipStream_t s);
 hipError_t launch_fs_profile(int precision, int na, int wpb, int nitems, int nblocks, bool tri,
                              hipStream_t s, const void* args, const void* angles);
 hipError_t launch_ali_update(int nb, hipStream_t s, const AliUpdateArgs& a);

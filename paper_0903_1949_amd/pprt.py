@@ -170,6 +170,10 @@ def load_library(path: str = LIB_PATH):
         "pprt_nlte_solve": (I, [P, C.POINTER(FsIn), C.POINTER(Atom), C.POINTER(AliCtl), P, P,
                                 C.POINTER(AliReport), P]),
         "pprt_two_level_ali_step_noalloc": (I, [P, C.POINTER(FsIn), C.POINTER(TwoLevel), P, P, P]),
+        "pprt_two_level_graph_create": (I, [P, C.POINTER(FsIn), C.POINTER(TwoLevel), P, P, P, P,
+                                            C.c_int32, C.POINTER(P)]),
+        "pprt_graph_launch": (I, [P]),
+        "pprt_graph_destroy": (None, [P]),
         "pprt_ali_state_bytes": (I, [P, C.POINTER(C.c_size_t)]),
         "pprt_ali_state_export": (I, [P, P, P, P, C.c_size_t]),
         "pprt_ali_state_import": (I, [P, P, C.c_size_t, P, P]),
@@ -535,6 +539,25 @@ class Plan:
             self.h, C.byref(fin), C.byref(at), _ptr(S), _ptr(max_rel), _ptr(active),
             _ptr(self.workspace())), "two_level_ali_step")
 
+    def two_level_graph(self, tau, q, S, eps, B, wphi, max_rel, steps=1, active=None, Itop=None,
+                        Ibot=None):
+        """pprt_two_level_graph_create: `steps` ALI steps captured once; the
+        returned StepGraph replays them with .launch().  Keeps the tensors
+        alive for the graph's lifetime."""
+        import torch
+        fin = self.fs_in(tau, q, None, None, None, Itop, Ibot)
+        at = self.two_level(eps, B, wphi)
+        self._want(S, (self.rows,), torch.float64, "S")
+        self._want(max_rel, (self.nb,), torch.float64, "max_rel")
+        if active is not None:
+            self._want(active, (self.nb,), torch.int32, "active")
+        ws = self.workspace()
+        h = C.c_void_p()
+        self.ctx._check(self.lib.pprt_two_level_graph_create(
+            self.h, C.byref(fin), C.byref(at), _ptr(S), _ptr(max_rel), _ptr(active), _ptr(ws),
+            int(steps), C.byref(h)), "two_level_graph_create")
+        return StepGraph(self, h, (tau, q, S, eps, B, wphi, max_rel, active, Itop, Ibot, ws))
+
     def two_level_ali_step_noalloc(self, tau, q, S, eps, B, wphi, max_rel, active=None, Itop=None,
                                    Ibot=None):
         """pprt_two_level_ali_step_noalloc: the same step with the library's
@@ -765,6 +788,27 @@ class Plan:
                                                     _ptr(self.workspace()), int(bool(force)),
                                                     C.byref(rep)), "autotune")
         return {k: getattr(rep, k) for k, _ in TuneReport._fields_}
+
+
+class StepGraph:
+    """A captured sequence of ALI steps (pprt_two_level_graph_create)."""
+
+    def __init__(self, plan, h, keep):
+        self.plan, self.h, self._keep = plan, h, keep
+
+    def launch(self):
+        self.plan.ctx._check(self.plan.lib.pprt_graph_launch(self.h), "graph_launch")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.plan.lib.pprt_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class SphPlan:

@@ -263,3 +263,29 @@ def test_ali_state_refuses_other_shapes(gpu_ctx):
         p3.ali_state_import(image, d1.S)
     with pytest.raises(pprt.PprtError, match="E_INVALID_ARG"):
         p1.ali_state_import(image[:100], d1.S)
+
+
+@pytest.mark.parametrize("prec", [pprt.FP32, pprt.FP64])
+def test_step_graph_replays_equal_eager_steps(gpu_ctx, prec):
+    """pprt_two_level_graph_create / pprt_graph_launch: every replay, with
+    eager work and a synchronisation between replays, equals the eager
+    steps bit for bit (one-step and three-step graphs)."""
+    batch = W.two_level_batch(nb=7, nd_lo=20, nd_hi=90, na=8, nf=200, seed=41)
+    plan = pprt.Plan(gpu_ctx, batch.nd, batch.na, batch.nf, precision=prec)
+    db = pprt.upload_two_level(batch, prec)
+    ref = pprt.upload_two_level(batch, prec)
+    mx = torch.zeros(batch.nb, dtype=torch.float64, device="cuda:0")
+    mx_ref = torch.zeros_like(mx)
+    g1 = plan.two_level_graph(db.tau, db.q, db.S, db.eps, db.B, db.wphi, mx, steps=1)
+    g3 = plan.two_level_graph(db.tau, db.q, db.S, db.eps, db.B, db.wphi, mx, steps=3)
+    for rep in range(3):
+        g1.launch()
+        plan.two_level_ali_step(ref.tau, ref.q, ref.S, ref.eps, ref.B, ref.wphi, mx_ref)
+        torch.cuda.synchronize()
+        assert torch.equal(db.S, ref.S) and torch.equal(mx, mx_ref), rep
+        g3.launch()
+        for _ in range(3):
+            plan.two_level_ali_step(ref.tau, ref.q, ref.S, ref.eps, ref.B, ref.wphi, mx_ref)
+        torch.cuda.synchronize()
+        assert torch.equal(db.S, ref.S) and torch.equal(mx, mx_ref), rep
+    g1.close(); g3.close()

@@ -10,26 +10,32 @@ import torch
 from oracle import formal
 from paper_0903_1949_amd import pprt
 from paper_0903_1949_amd import workloads as W
-from tests.conftest import rel_err
+from tests.conftest import rel_err, rel_err_terms
 
 pytestmark = pytest.mark.gpu
 
 TOL = {pprt.FP64: 1e-10, pprt.FP32: 1e-5}
 KEYS = ["J", "JmS", "lstar", "lstar_c", "Iplus", "Iminus", "H"]
-# J - S and H are small differences of O(S) hemisphere moments in the
-# diffusion regime (D+ + D- cancels to second order).  In FP32 their error is
-# set by the 1e-7 relative rounding of e and psi times |D|, not by |J - S|, so
-# in the per-array metric they reach ~1e-4; they are also checked against the
-# scale of the operands (|J|), where they must stay at FP32 rounding level.
+# J - S = 1/2 sum_i w_i (D+_i + D-_i) and H = 1/2 sum_i w_i mu_i (D+_i - D-_i)
+# are sums whose terms cancel: in the diffusion regime D+ + D- is second
+# order in the source gradient.  Their contract is relative to the magnitude
+# of their terms, 1/2 sum_i w_i (|D+_i| + |D-_i|) (times mu_i for H), element
+# by element: 1e-5 in FP32, 1e-10 in FP64 (tests.conftest.rel_err_terms).
+# The per-array metric, which measures them against their own (possibly
+# cancelled) value, is printed beside it.
 DIFF_KEYS = ("JmS", "H")
-TOL_DIFF_FP32 = 1e-3
-TOL_DIFF_OPERAND_FP32 = 2e-6
 
 
 def tolerance(prec, key):
-    if prec == pprt.FP32 and key in DIFF_KEYS:
-        return TOL_DIFF_FP32
     return TOL[prec]
+
+
+def term_magnitudes(ref, S, mu, w):
+    """1/2 sum_i w_i (|D+| + |D-|) and the same with mu_i: the size of the
+    terms that J - S and H sum, from the oracle's intensities (D = I - S)."""
+    Dp = np.abs(ref["Iplus"] - S[..., None])
+    Dm = np.abs(ref["Iminus"] - S[..., None])
+    return {"JmS": 0.5 * (Dp + Dm) @ w, "H": 0.5 * (Dp + Dm) @ (w * mu)}
 
 
 def r32(a):
@@ -82,19 +88,18 @@ def _run(ctx, nds, nf, na, prec, bc, seed, wpb=0):
     ref = _oracle(nds, tau, q, S, Bb, Bp, Itop, Ibot, plan.mu, plan.w, bc)
     got = {k: out[k].double().cpu().numpy() for k in KEYS + ["Iemerg"]}
     errs = {k: rel_err(got[k], ref[k]) for k in KEYS + ["Iemerg"]}
-    scale = np.abs(ref["J"]).max()
+    mag = term_magnitudes(ref, S, plan.mu, plan.w)
     for k in DIFF_KEYS:
-        errs[k + "_vs_J"] = float(np.max(np.abs(got[k] - ref[k])) / scale)
+        errs[k + "_vs_terms"] = rel_err_terms(got[k], ref[k], mag[k], scale=S)
     print("  errors:", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
     return errs
 
 
 def _assert(errs, prec):
     for k, e in errs.items():
-        if k.endswith("_vs_J"):
-            assert e < (TOL_DIFF_OPERAND_FP32 if prec == pprt.FP32 else TOL[prec]), (k, e)
-        else:
-            assert e < tolerance(prec, k), (k, e)
+        if k in DIFF_KEYS:
+            continue          # reported; the contract is the _vs_terms metric
+        assert e < TOL[prec], (k, e)
 
 
 @pytest.mark.parametrize("prec", [pprt.FP64, pprt.FP32])
@@ -153,12 +158,21 @@ def test_c3a_full_size_sampled(gpu_ctx):
             int(np.argmin(batch.eps)), int(np.argmax(batch.eps))]
     for b in pick:
         s = slice(off[b], off[b + 1])
-        ref = formal.formal_solution(batch.tau[s], r32(batch.q[s]), r32(batch.S_trial[s]), plan.mu,
+        S32 = np.repeat(r32(batch.S_trial[s])[:, None], batch.nf, axis=1)
+        ref = formal.formal_solution(batch.tau[s], r32(batch.q[s]), S32, plan.mu,
                                      plan.w, lower="diffusion", Bbot=np.full(batch.nf, batch.B[last[b]]),
                                      Bbot_prev=np.full(batch.nf, batch.B[last[b] - 1]))
+        mag = term_magnitudes(ref, S32, plan.mu, plan.w)
         for k in ("JmS", "lstar_c", "H"):
-            e = rel_err(out[k][s].double().cpu().numpy(), ref[k])
-            print(f"  b={b} nd={batch.nd[b]} {k}: {e:.2e}", flush=True)
-            assert e < tolerance(pprt.FP32, k), (b, k, e)
+            g = out[k][s].double().cpu().numpy()
+            e = rel_err(g, ref[k])
+            if k in DIFF_KEYS:
+                et = rel_err_terms(g, ref[k], mag[k], scale=S32)
+                print(f"  b={b} nd={batch.nd[b]} {k}: {e:.2e} (per array), {et:.2e} (of its terms)",
+                      flush=True)
+                assert et < TOL[pprt.FP32], (b, k, et)
+            else:
+                print(f"  b={b} nd={batch.nd[b]} {k}: {e:.2e}", flush=True)
+                assert e < TOL[pprt.FP32], (b, k, e)
         e = rel_err(out["Iemerg"][b].double().cpu().numpy(), ref["Iemerg"])
         assert e < 1e-5, (b, "Iemerg", e)

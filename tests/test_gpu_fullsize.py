@@ -14,12 +14,9 @@ import torch
 from oracle import ali, dense, formal, rates
 from paper_0903_1949_amd import pprt
 from paper_0903_1949_amd import workloads as W
-from tests.conftest import rel_err
+from tests.conftest import U64, rate_magnitudes, rel_err, skeel
 
 pytestmark = pytest.mark.gpu
-
-U64 = 2.0 ** -53
-
 
 def r32(a):
     return np.asarray(a, dtype=np.float32).astype(np.float64)
@@ -113,30 +110,6 @@ def test_c3b_step_full_batch(gpu_ctx):
         assert e < 1e-10 and e_d < 1e-10
 
 
-def _rate_magnitudes(a, pops, J, lstar):
-    o = rates.opacities(a, pops)
-    sig = rates.cross_sections(a)
-    G = a.Gst
-    U = a.bfac[None, :] * G * sig
-    p = o["chi_t"] / o["kappa"]
-    dJmag = np.abs(J) + np.abs(lstar * o["eta_t"] / o["kappa"])
-    W = a.W[None, :]
-    rows = pops.shape[0]
-    m = [np.zeros((rows, a.nt)) for _ in range(3)]
-    for t in range(a.nt):
-        sl = slice(int(a.k0[t]), int(a.k1[t]))
-        m[0][:, t] = np.sum(np.abs(W[:, sl] * sig[:, sl]) * dJmag[:, sl], axis=1)
-        m[1][:, t] = np.sum(np.abs(W[:, sl] * G[:, sl] * sig[:, sl]) * dJmag[:, sl], axis=1)
-        m[2][:, t] = np.sum(np.abs(W[:, sl] * U[:, sl]) * (1.0 + np.abs(p[:, sl] * lstar[:, sl])), axis=1)
-    return m
-
-
-def skeel(As, x):
-    """Componentwise condition of As x = b: (|As^-1| |As| |x|)_i / |x_i|."""
-    inv = np.linalg.inv(As)
-    return (np.abs(inv) @ (np.abs(As) @ np.abs(x))) / np.abs(x)
-
-
 @pytest.fixture(scope="module")
 def c2():
     return W.multilevel_atom()
@@ -173,7 +146,7 @@ def test_c2_multilevel_iteration_full_config(gpu_ctx, c2):
     # terms cancel where J is close to Lambda* S: their rounding is set by
     # the magnitude of the terms, sum W sigma (|J| + |Lambda* eta/kappa|)
     # (with G for [dR_ul], and sum W U (1 + p Lambda*) for [R*_ul])
-    mag = _rate_magnitudes(a, pops0, fs_ref["J"], fs_ref["lstar"])
+    mag = rate_magnitudes(a, pops0, fs_ref["J"], fs_ref["lstar"])
     e_rt_mag = [float(np.max(np.abs(g.cpu().numpy() - r) / m)) for g, r, m in zip(dR, r_ref, mag)]
     # stage 4: the solve from the oracle's rates, bound per row by the condition
     pn, _ = plan.rates_solve(da, d(pops0), *[d(r) for r in r_ref])
