@@ -828,6 +828,7 @@ def bench_c3b(args):
     step_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
     flops = rows * nf * DENSE_FLOPS_PER_LAYER
     achieved = flops / (step_ms * 1e-3) / 1e12
+    fp32 = c3b_fp32_bulk(ctx, batch, plan, db, pf, sc, om, steps, step_ms)
     cpu = None if args.no_cpu_baseline else c3b_cpu_baseline(batch, plan.mu, plan.w)
     line = {
         "metric": "formal-solution depth*angle*freq pts/s of the two-level step with coherent "
@@ -846,9 +847,67 @@ def bench_c3b(args):
                                "dense passes' own)",
                      "kernel_ms": round(step_ms, 3), "flops_per_layer_and_freq": DENSE_FLOPS_PER_LAYER,
                      "peak_note": "FP64 vector, 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz"},
+        "fp32_bulk": fp32,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def c3b_fp32_bulk(ctx, batch, plan64, db64, pf64, sc64, om64, steps, fp64_step_ms):
+    """The same step with an FP32 plan (FP64 layer operators, FP32 adding
+    recursion, FP64 eliminations under the thick-layer rule): event time per
+    step, the speed-up over the FP64 step, the share of eliminations that ran
+    in FP64, and the error of one step's S against the FP64 step from the
+    same S (and of the FP32-only eliminations beside it)."""
+    import torch
+    from paper_0903_1949_amd import pprt
+
+    rows, nf, na = int(batch.nd.sum()), batch.nf, batch.na
+    plan = pprt.Plan(ctx, batch.nd, na, nf, precision=pprt.FP32)
+    db = pprt.upload_two_level(batch, pprt.FP32)
+    f = lambda t: t.to(torch.float32).contiguous()
+    pf, sc, om = f(pf64), f(sc64), f(om64)
+    mx = torch.zeros(batch.nb, dtype=torch.float64, device="cuda:0")
+    stream = torch.cuda.current_stream()
+
+    def step(pl, d, a, b, c, m):
+        pl.two_level_ali_step_continuum(d.tau, d.q, d.S, d.eps, d.B, d.wphi, a, b, c, d.Bbot,
+                                        d.Bbot_prev, m)
+
+    step(plan, db, pf, sc, om, mx)
+    torch.cuda.synchronize()
+    ctx.thick_counts(reset=True)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    for e0, e1 in evs:
+        e0.record(stream)
+        step(plan, db, pf, sc, om, mx)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
+    n64, ntot = ctx.thick_counts(reset=True)
+    # one step from the same S in FP64, FP32 (rule) and FP32 (no FP64 eliminations)
+    S0 = torch.as_tensor(batch.S_trial, dtype=torch.float64, device="cuda:0")
+    mx64 = torch.zeros_like(mx)
+    db64.S.copy_(S0)
+    step(plan64, db64, pf64, sc64, om64, mx64)
+    out = {}
+    for mode, name in ((pprt.THICK_RULE, "rule"), (pprt.THICK_NEVER, "never")):
+        plan.set_thick_mode(mode)
+        db.S.copy_(S0)
+        step(plan, db, pf, sc, om, mx)
+        torch.cuda.synchronize()
+        dS64 = (db64.S - S0).abs()
+        err = ((db.S - db64.S).abs() / db64.S.abs()).max().item()
+        err_d = ((db.S - db64.S).abs().max() / dS64.max()).item()
+        out[name] = {"S_rel_err_vs_fp64": err, "dS_err_vs_fp64_scale": err_d}
+    plan.set_thick_mode(pprt.THICK_RULE)
+    return {"ms_per_step": round(ms, 3), "pts_per_s": rows * na * nf / (ms * 1e-3),
+            "speedup_vs_fp64_step": round(fp64_step_ms / ms, 3),
+            "fp64_eliminations": n64, "eliminations": ntot,
+            "fp64_elimination_share": round(n64 / max(ntot, 1), 4),
+            "one_step_errors": out,
+            "workspace_gb": round(plan_continuum_workspace_gb(plan), 1)}
 
 
 ADJ_FLOPS_PER_POINT = 48.0   # forward 12; reverse 2 x 12 (segment recompute) + 12 (adjoint)

@@ -207,17 +207,46 @@ pprt_status pprt_formal_solution(pprt_plan* plan, const pprt_fs_in* in, pprt_fs_
  * exactly (discrete-ordinate eigen solution, no growing exponentials), layers
  * are combined by the adding method top-down and bottom-up, and every node
  * gets I+-, J, J - S^g, H and the exact diagonal Lambda*_dd = dJ(d)/dS^g(d)
- * with 1 - Lambda*.  FP64 plans only, na in {1, 2, 4, 8, 16}
- * (E_UNSUPPORTED otherwise).  Needs a workspace of
- * pprt_plan_scattering_workspace_bytes(): 8 (2 na^2 + 4 na) bytes per node
- * and frequency, the composite reflection and source of every node, each
- * layer's eigen solution and two of its unit-source responses, kept between
- * the top-down and the bottom-up pass; omega = 0
- * everywhere reproduces pprt_formal_solution to rounding. */
+ * with 1 - Lambda*.  na in {1, 2, 4, 8, 16} (E_UNSUPPORTED otherwise).
+ * Precision: an FP64 plan computes in FP64 throughout.  An FP32 plan forms
+ * each layer's operators in FP64 and rounds them, keeps arrays, composites,
+ * products and the adding recursion in FP32, and runs the eliminations with
+ * I - (reflection)(reflection) in FP64 where the thick-layer rule selects
+ * them (pprt_plan_set_thick_mode).  Needs a workspace of
+ * pprt_plan_scattering_workspace_bytes() per node and frequency:
+ * 8 (2 na^2 + 4 na) bytes in FP64 plans (the composite reflection and source
+ * of every node, two unit-source responses of each layer and each layer's
+ * eigen solution), 4 (na^2 + 3 na) bytes in FP32 plans (the same without the
+ * eigen solutions, which the bottom-up pass recomputes), kept between the
+ * top-down and the bottom-up pass; omega = 0 everywhere reproduces
+ * pprt_formal_solution to rounding. */
 pprt_status pprt_plan_scattering_workspace_bytes(const pprt_plan* plan, size_t* bytes);
 pprt_status pprt_formal_solution_scattering(pprt_plan* plan, const pprt_fs_in* in,
                                             const void* omega, pprt_fs_out* out,
                                             void* workspace);
+
+/* FP64 eliminations of the FP32-bulk scattering path (the precision split of
+ * the layer recursion: FP32 bulk, FP64 for the inversions of optically thick
+ * layers).  The recursion inverts I - r R_d on the way down and I - R^up r,
+ * I - R^up R_d on the way up.  PPRT_THICK_RULE (the default) runs one of
+ * these in FP64 when its layer's absorption depth dtau (1 - omega)^1/2
+ * exceeds 1 or the bound |A|_inf |B|_inf of the reflection product |A B|
+ * exceeds 1/2; the decision is taken for a wave of 64/na frequencies at once
+ * (FP64 when any of them qualifies).  PPRT_THICK_NEVER keeps every
+ * elimination in FP32 and PPRT_THICK_ALWAYS runs every one in FP64 (error
+ * studies).  FP64 plans ignore the mode.  E_INVALID_ARG for another value. */
+typedef enum pprt_thick_mode {
+  PPRT_THICK_RULE = 0, PPRT_THICK_NEVER = 1, PPRT_THICK_ALWAYS = 2
+} pprt_thick_mode;
+pprt_status pprt_plan_set_thick_mode(pprt_plan* plan, int32_t mode);
+
+/* Counters of the FP32-bulk scattering path, summed over every launch on the
+ * context since it was created or last reset: eliminations run in FP64 and
+ * all eliminations (one per wave and decision).  pprt_thick_counts
+ * synchronises the context's stream; pprt_thick_counts_reset is ordered on
+ * it. */
+pprt_status pprt_thick_counts(pprt_ctx* ctx, uint64_t* fp64, uint64_t* total);
+pprt_status pprt_thick_counts_reset(pprt_ctx* ctx);
 
 /* ----------------------------------------------------- two-level atom ALI */
 
@@ -327,8 +356,9 @@ typedef struct pprt_continuum {
 pprt_status pprt_plan_continuum_workspace_bytes(const pprt_plan* plan, size_t* bytes);
 
 /* One operator-splitting step of the line on a continuum: S^g assembly,
- * formal solution (with in-layer scattering when cont->omega is given: FP64
- * plans, na in {1,2,4,8,16}), then per node the profile quadratures
+ * formal solution (with in-layer scattering when cont->omega is given: na in
+ * {1,2,4,8,16}, FP32 plans with the thick-layer FP64 eliminations of
+ * pprt_formal_solution_scattering), then per node the profile quadratures
  *   Jbar - S_l = sum_k wphi_k [(J_k - S^g_k) + (S^g_k - S_l)],
  *   1 - Lbar*  = sum_k wphi_k [(1 - p_k) + p_k (1 - Lambda*_k)]
  * and the float64 update of pprt_two_level_ali_step.  in->Bbot/Bbot_prev are

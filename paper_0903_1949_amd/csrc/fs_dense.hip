@@ -1,5 +1,6 @@
 // Formal solution with coherent isotropic scattering inside the layers
-// (omega > 0) on gfx950, FP64: exact homogeneous-layer operators t, r, beta
+// (omega > 0) on gfx950, in FP64 or with an FP32 bulk: exact homogeneous-layer
+// operators t, r, beta
 // from the discrete-ordinate eigen solution, the adding recursion down, a
 // bottom-up adding pass, and the two-sided combination that yields I+-, J and
 // the exact diagonal Lambda* at every node.
@@ -53,10 +54,71 @@
 // and the same combination of the unit-source responses of the two layers
 // that touch the node gives Lambda*_dd = dJ(d)/dS^g(d) (plain form) and
 // 1 - Lambda*_dd (difference form, so it stays accurate as Lambda* -> 1).
+//
+// Precision.  The kernels are templated on the bulk type T.  T = double is
+// FP64 throughout.  T = float keeps every array, composite, product and the
+// adding recursion in FP32, but forms each layer's operators in FP64 and
+// rounds them: in a thin, nearly conservative layer the absorption that
+// t and r carry is a small difference of the large non-diffusive modes, and
+// the matrix products V diag(.) V^T of an FP32 layer solution bury it in
+// rounding (the diffusion eigenvalue is ~(1 - omega) of the others), which
+// the recursion then accumulates over many layers.  The FP64 eigen solution
+// is recomputed in each pass (only when the layer albedo changes) instead of
+// being stored.  The eliminations with I - (reflection)(reflection)
+// -- G = (I - r R_d)^-1 of the way down, (I - R^up r)^-1 and (I - R^up R_d)^-1
+// of the way up -- run in FP64 where the thick-layer rule asks for it: the layer's
+// absorption depth D (1 - omega)^1/2 exceeds 1, or the bound |r|_inf |R|_inf
+// of |r R| exceeds 1/2 (its spectral radius, and with it the conditioning of
+// I - r R, is then no longer safely away from 1).  In FP64 the product r R is
+// accumulated from the FP32 operands (exact products) and the right-hand
+// sides are formed in FP64 before the elimination; results are rounded back
+// to FP32.  The decision is taken per wave (FP64 when any of its frequency
+// groups qualifies) so the branch stays uniform; a mode switch forces FP64 or
+// FP32 everywhere for error studies, and per-wave counters record how many
+// eliminations ran in FP64.
+#include <type_traits>
+
 #include "pprt_internal.h"
 
 namespace pprt {
 namespace {
+
+// ---- scalar helpers per bulk type -------------------------------------------
+// 1/x from the hardware reciprocal and Newton-Raphson steps (r <- r + r (1 - x r)):
+// two for double, one for float; for finite nonzero normal x within 1 ulp
+__device__ __forceinline__ double rcpT(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ float rcpT(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double sqrtT(double x) { return sqrt(x); }
+__device__ __forceinline__ float sqrtT(float x) { return sqrtf(x); }
+__device__ __forceinline__ double tanhT(double x) { return tanh(x); }
+__device__ __forceinline__ float tanhT(float x) { return tanhf(x); }
+__device__ __forceinline__ double absT(double x) { return fabs(x); }
+__device__ __forceinline__ float absT(float x) { return fabsf(x); }
+__device__ __forceinline__ double maxT(double a, double b) { return fmax(a, b); }
+__device__ __forceinline__ float maxT(float a, float b) { return fmaxf(a, b); }
+template <typename T>
+constexpr T epsT() { return std::is_same<T, double>::value ? (T)0x1p-52 : (T)0x1p-23f; }
+
+// value of v in lane `a / 4` (a = 4 x source lane) through the cross-lane permute
+__device__ __forceinline__ double permute(int a, double v) {
+  const int lo = __builtin_amdgcn_ds_bpermute(a, __double2loint(v));
+  const int hi = __builtin_amdgcn_ds_bpermute(a, __double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float permute(int a, float v) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(a, __float_as_int(v)));
+}
 
 template <int NA>
 struct DenseTab {
@@ -71,80 +133,89 @@ __device__ __forceinline__ void wsync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// A group's LDS slab.  Matrix rows are RS doubles apart: padded from NA >= 8
-// on, so that the lanes' 16-byte row stores fall on different banks.  The
-// slab stride is 2 (mod 16) doubles, so that the groups of a wave, which
-// read the same offsets of their own slabs, touch disjoint 4-bank spans.
-template <int NA>
+// A group's LDS slab in elements of type T.  Matrix rows are RS elements
+// apart: padded by 16 bytes from NA >= 8 on, so that the lanes' 16-byte row
+// stores fall on different banks.  The slab stride is 16 bytes more than a
+// multiple of 128 bytes, so that the groups of a wave, which read the same
+// offsets of their own slabs, touch disjoint bank spans.  The kernels size
+// the slabs for double; a float group uses the first half of its double slab.
+template <typename T, int NA>
 struct Slab {
-  static constexpr int RS = NA >= 8 ? NA + 2 : NA;
+  static constexpr int PADW = 16 / (int)sizeof(T);
+  static constexpr int LINE = 128 / (int)sizeof(T);
+  static constexpr int RS = NA >= 8 ? NA + PADW : NA;
   static constexpr int MAT = (NA * RS > 2 * NA + 3) ? NA * RS : 2 * NA + 3;
   static constexpr int VEC = MAT;            // 4 vector slots of NA
   static constexpr int ROOT = MAT + 4 * NA;  // 2 NA: root origin and offset
   static constexpr int USED = MAT + 6 * NA;
-  static constexpr int SIZE = USED + (18 - USED % 16) % 16;
+  static constexpr int SIZE = USED + (PADW + LINE - USED % LINE) % LINE;
 };
+static_assert(Slab<float, 16>::USED <= 2 * Slab<double, 16>::SIZE, "float slab fits its double slab");
+static_assert(Slab<float, 1>::USED <= 2 * Slab<double, 1>::SIZE, "float slab fits its double slab");
 
-// 1/x from the hardware reciprocal and two Newton-Raphson steps
-// (r <- r + r (1 - x r)); for finite nonzero normal x, within 1 ulp
-__device__ __forceinline__ double rcp_nr(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
-}
-
-// lane-group toolkit: lane i holds row i
-template <int NA>
+// lane-group toolkit in precision T: lane i holds row i.  Operands of another
+// type are converted as they are read (float -> double is exact).
+template <typename T, int NA>
 struct Grp {
-  double* buf;
+  T* buf;
   int i;
   int b4;   // 4 x the group's first lane (permute address)
+  static constexpr int RS = Slab<T, NA>::RS;
 
-  __device__ __forceinline__ void put_mat(const double (&A)[NA]) {
+  template <typename S>
+  __device__ __forceinline__ void put_mat(const S (&A)[NA]) {
     wsync();
 #pragma unroll
-    for (int j = 0; j < NA; ++j) buf[i * Slab<NA>::RS + j] = A[j];
+    for (int j = 0; j < NA; ++j) buf[i * RS + j] = (T)A[j];
     wsync();
   }
-  __device__ __forceinline__ void put_vec(double v, int slot) {
+  __device__ __forceinline__ void put_vec(T v, int slot) {
     wsync();
-    buf[Slab<NA>::VEC + slot * NA + i] = v;
+    buf[Slab<T, NA>::VEC + slot * NA + i] = v;
     wsync();
   }
-  __device__ __forceinline__ double vec(int j, int slot) const {
-    return buf[Slab<NA>::VEC + slot * NA + j];
+  __device__ __forceinline__ T vec(int j, int slot) const {
+    return buf[Slab<T, NA>::VEC + slot * NA + j];
   }
   // C = A B
-  __device__ __forceinline__ void mul(double (&C)[NA], const double (&A)[NA], const double (&B)[NA]) {
+  template <typename SA, typename SB>
+  __device__ __forceinline__ void mul(T (&C)[NA], const SA (&A)[NA], const SB (&B)[NA]) {
     put_mat(B);
-    double acc[NA];
+    T acc[NA];
 #pragma unroll
-    for (int j = 0; j < NA; ++j) acc[j] = 0.0;
+    for (int j = 0; j < NA; ++j) acc[j] = (T)0;
 #pragma unroll
     for (int k = 0; k < NA; ++k) {
-      const double a = A[k];
+      const T a = (T)A[k];
 #pragma unroll
-      for (int j = 0; j < NA; ++j) acc[j] = fma(a, buf[k * Slab<NA>::RS + j], acc[j]);
+      for (int j = 0; j < NA; ++j) acc[j] = fmaT(a, buf[k * RS + j], acc[j]);
     }
 #pragma unroll
     for (int j = 0; j < NA; ++j) C[j] = acc[j];
   }
   // (A x)_i
-  __device__ __forceinline__ double mv(const double (&A)[NA], double x) {
+  template <typename SA>
+  __device__ __forceinline__ T mv(const SA (&A)[NA], T x) {
     put_vec(x, 0);
-    double acc = 0.0;
+    T acc = (T)0;
 #pragma unroll
-    for (int j = 0; j < NA; ++j) acc = fma(A[j], vec(j, 0), acc);
+    for (int j = 0; j < NA; ++j) acc = fmaT((T)A[j], vec(j, 0), acc);
     return acc;
   }
   // sum over the group of v
-  __device__ __forceinline__ double sum(double v) {
+  __device__ __forceinline__ T sum(T v) {
     put_vec(v, 1);
-    double acc = 0.0;
+    T acc = (T)0;
 #pragma unroll
     for (int j = 0; j < NA; ++j) acc += vec(j, 1);
+    return acc;
+  }
+  // maximum over the group of v
+  __device__ __forceinline__ T gmax(T v) {
+    put_vec(v, 1);
+    T acc = vec(0, 1);
+#pragma unroll
+    for (int j = 1; j < NA; ++j) acc = maxT(acc, vec(j, 1));
     return acc;
   }
   // Gauss-Jordan elimination without pivoting on the rows [A | X | v] held
@@ -156,34 +227,29 @@ struct Grp {
   // its own pivot at the end.  XM: 0 no matrix right-hand side, 1 X holds one
   // on entry, 2 X starts as the identity (X = A^-1 on exit; row k of X has
   // no entries right of column k at step k).
-  __device__ __forceinline__ double from_lane(double v, int k) const {
-    const int a = b4 + 4 * k;
-    const int lo = __builtin_amdgcn_ds_bpermute(a, __double2loint(v));
-    const int hi = __builtin_amdgcn_ds_bpermute(a, __double2hiint(v));
-    return __hiloint2double(hi, lo);
-  }
+  __device__ __forceinline__ T from_lane(T v, int k) const { return permute(b4 + 4 * k, v); }
   template <int XM, int NB>
-  __device__ __forceinline__ void gj(double (&A)[NA], double (&X)[NA], double (&v)[NB > 0 ? NB : 1]) {
+  __device__ __forceinline__ void gj(T (&A)[NA], T (&X)[NA], T (&v)[NB > 0 ? NB : 1]) {
     if constexpr (XM == 2) {
 #pragma unroll
-      for (int j = 0; j < NA; ++j) X[j] = (j == i) ? 1.0 : 0.0;
+      for (int j = 0; j < NA; ++j) X[j] = (j == i) ? (T)1 : (T)0;
     }
-    double own = 1.0;
+    T own = (T)1;
 #pragma unroll
     for (int k = 0; k < NA; ++k) {
-      const double piv = from_lane(A[k], k);
-      const double c = (i == k) ? 0.0 : A[k] * rcp_nr(piv);
+      const T piv = from_lane(A[k], k);
+      const T c = (i == k) ? (T)0 : A[k] * rcpT(piv);
       own = (i == k) ? piv : own;
 #pragma unroll
-      for (int j = k + 1; j < NA; ++j) A[j] = fma(-c, from_lane(A[j], k), A[j]);
+      for (int j = k + 1; j < NA; ++j) A[j] = fmaT(-c, from_lane(A[j], k), A[j]);
       if constexpr (XM != 0) {
 #pragma unroll
-        for (int j = 0; j < (XM == 2 ? k + 1 : NA); ++j) X[j] = fma(-c, from_lane(X[j], k), X[j]);
+        for (int j = 0; j < (XM == 2 ? k + 1 : NA); ++j) X[j] = fmaT(-c, from_lane(X[j], k), X[j]);
       }
 #pragma unroll
-      for (int m = 0; m < NB; ++m) v[m] = fma(-c, from_lane(v[m], k), v[m]);
+      for (int m = 0; m < NB; ++m) v[m] = fmaT(-c, from_lane(v[m], k), v[m]);
     }
-    const double r = rcp_nr(own);
+    const T r = rcpT(own);
     if constexpr (XM != 0) {
 #pragma unroll
       for (int j = 0; j < NA; ++j) X[j] *= r;
@@ -191,36 +257,34 @@ struct Grp {
 #pragma unroll
     for (int m = 0; m < NB; ++m) v[m] *= r;
   }
-  // X = A^-1; A is destroyed.  Used on symmetric positive definite matrices
-  // and on I - (reflection products).
-  __device__ __forceinline__ void inv(double (&X)[NA], double (&A)[NA]) {
-    double v[1];
+  // X = A^-1; A is destroyed.  Used on symmetric positive definite matrices.
+  __device__ __forceinline__ void inv(T (&X)[NA], T (&A)[NA]) {
+    T v[1];
     gj<2, 0>(A, X, v);
   }
   // y1, y2, y3 with A y = b1, b2, b3; A is destroyed
-  __device__ __forceinline__ void solve3(double (&A)[NA], double& b1, double& b2, double& b3) {
-    double v[3] = {b1, b2, b3};
+  __device__ __forceinline__ void solve3(T (&A)[NA], T& b1, T& b2, T& b3) {
+    T v[3] = {b1, b2, b3};
     gj<0, 3>(A, A, v);
     b1 = v[0]; b2 = v[1]; b3 = v[2];
   }
   // X <- A^-1 X (X holds the right-hand side's rows on entry); A is destroyed
-  __device__ __forceinline__ void solve_mat(double (&X)[NA], double (&A)[NA]) {
-    double v[1];
+  __device__ __forceinline__ void solve_mat(T (&X)[NA], T (&A)[NA]) {
+    T v[1];
     gj<1, 0>(A, X, v);
   }
   // X <- A^-1 X and b0, b1, b2 <- A^-1 b0, b1, b2 (right-hand sides on
   // entry); A is destroyed
-  __device__ __forceinline__ void solve_mat_v3(double (&X)[NA], double (&A)[NA], double& b0,
-                                               double& b1, double& b2) {
-    double v[3] = {b0, b1, b2};
+  __device__ __forceinline__ void solve_mat_v3(T (&X)[NA], T (&A)[NA], T& b0, T& b1, T& b2) {
+    T v[3] = {b0, b1, b2};
     gj<1, 3>(A, X, v);
     b0 = v[0]; b1 = v[1]; b2 = v[2];
   }
 };
 
-template <int NA>
+template <typename T, int NA>
 struct LaneTab {  // per-lane copies of the angle constants of row i
-  double mu, m, d, z2, w, sw, swmu;
+  T mu, m, d, z2, w, sw, swmu;
   int ext;
 };
 
@@ -230,114 +294,119 @@ struct LaneTab {  // per-lane copies of the angle constants of row i
 // nearer end, by bracketed Newton on the secular function; the group then
 // forms the Gu-Eisenstat vector and lane i keeps row i of V and its root.
 template <int NA>
-__device__ void eigen(Grp<NA>& g, const DenseTab<NA>& T, const LaneTab<NA>& L, double om,
-                      double (&V)[NA], double& k_i, double& lam_prev) {
+__device__ void eigen(Grp<double, NA>& g, const DenseTab<NA>& tb, const LaneTab<double, NA>& L,
+                      double om, double (&V)[NA], double& k_i, double& lam_prev) {
+  using T = double;
+  constexpr T EPS = epsT<T>();
   const int i = g.i;
-  double lo = 0.0;
+  T lo = (T)0;
 #pragma unroll
   for (int j = 0; j < NA; ++j)
-    if (j == i - 1) lo = T.d[j];
-  const double hi = L.d;
-  double org = hi, del = 0.0;
-  const double om1 = 1.0 - om;
-  if (om > 0.0) {
+    if (j == i - 1) lo = tb.d[j];
+  const T hi = L.d;
+  T org = hi, del = (T)0;
+  const T om1 = (T)1 - om;
+  if (om > (T)0) {
     // f(lam) = 1 - om sum z2_j/(d_j - lam), or for root 0 near lam = 0 the
     // equivalent (1 - om) - om lam sum w_j/(d_j - lam); both decrease in lam.
-    auto feval = [&](double o, double sgn, double x, double& f, double& df) {
-      double s = 0.0, s2 = 0.0;
-      if (i == 0 && o == 0.0) {
+    auto feval = [&](T o, T sgn, T x, T& f, T& df) {
+      T s = (T)0, s2 = (T)0;
+      if (i == 0 && o == (T)0) {
 #pragma unroll
         for (int j = 0; j < NA; ++j) {
-          const double r = rcp_nr(T.d[j] - sgn * x);
-          s = fma(T.w[j], r, s);
-          s2 = fma(T.w[j] * T.d[j], r * r, s2);
+          const T r = rcpT(tb.d[j] - sgn * x);
+          s = fmaT(tb.w[j], r, s);
+          s2 = fmaT(tb.w[j] * tb.d[j], r * r, s2);
         }
         f = om1 - om * x * s;
         df = -om * s2;
       } else {
 #pragma unroll
         for (int j = 0; j < NA; ++j) {
-          const double r = rcp_nr((T.d[j] - o) - sgn * x);
-          s = fma(T.z2[j], r, s);
-          s2 = fma(T.z2[j] * r, r, s2);
+          const T r = rcpT((tb.d[j] - o) - sgn * x);
+          s = fmaT(tb.z2[j], r, s);
+          s2 = fmaT(tb.z2[j] * r, r, s2);
         }
-        f = 1.0 - om * s;
+        f = (T)1 - om * s;
         df = -om * s2;
       }
     };
-    const double mid = 0.5 * (lo + hi);
-    double fm, dfm;
-    if (i == 0) feval(0.0, 1.0, mid, fm, dfm);
-    else feval(lo, 1.0, mid - lo, fm, dfm);
-    double sgn, xl, xh;
-    if (fm > 0.0) { org = hi; sgn = -1.0; xl = 0.0; xh = hi - mid; }
-    else { org = lo; sgn = 1.0; xl = 0.0; xh = mid - lo; }
-    if (i == 0 && sgn > 0.0 && om1 <= 0.0) {
-      del = 0.0;                       // omega = 1: the diffusion root is exactly 0
+    const T mid = (T)0.5 * (lo + hi);
+    T fm, dfm;
+    if (i == 0) feval((T)0, (T)1, mid, fm, dfm);
+    else feval(lo, (T)1, mid - lo, fm, dfm);
+    T sgn, xl, xh;
+    if (fm > (T)0) { org = hi; sgn = (T)-1; xl = (T)0; xh = hi - mid; }
+    else { org = lo; sgn = (T)1; xl = (T)0; xh = mid - lo; }
+    if (i == 0 && sgn > (T)0 && om1 <= (T)0) {
+      del = (T)0;                       // omega = 1: the diffusion root is exactly 0
     } else {
       // start from the root of the previous layer (same frequency, nearly the
       // same omega) when it lies in this half of the interval, else mid-way
-      const double xp = sgn * (lam_prev - org);
-      double x = (xp > xl && xp < xh) ? xp : 0.5 * (xl + xh);
+      const T xp = sgn * (lam_prev - org);
+      T x = (xp > xl && xp < xh) ? xp : (T)0.5 * (xl + xh);
       for (int it = 0; it < 200; ++it) {
-        double f, df;
+        T f, df;
         feval(org, sgn, x, f, df);
         // lam = org + sgn x is too small when f > 0
-        if ((f > 0.0) == (sgn > 0.0)) xl = x; else xh = x;
-        double xn = x - f * rcp_nr(df * sgn);
+        if ((f > (T)0) == (sgn > (T)0)) xl = x; else xh = x;
+        T xn = x - f * rcpT(df * sgn);
         // a converged step ends the iteration before the bracket test: at the
         // root (f == 0, or a step that rounds to nothing) the update above has
         // just moved a bracket end onto x, and the test would take a bisection
         // step away from it
-        if (fabs(xn - x) <= 2e-16 * x) {
+        if (absT(xn - x) <= (T)2 * EPS * x) {
           x = xn;
           break;
         }
-        if (!(xn > xl && xn < xh)) xn = 0.5 * (xl + xh);
-        const double step = fabs(xn - x);
+        if (!(xn > xl && xn < xh)) xn = (T)0.5 * (xl + xh);
+        const T step = absT(xn - x);
         x = xn;
-        if (step <= 2e-16 * x || xh - xl <= 4e-16 * xh) break;
+        if (step <= (T)2 * EPS * x || xh - xl <= (T)4 * EPS * xh) break;
       }
       del = sgn * x;
     }
   }
   // broadcast roots
   wsync();
-  g.buf[Slab<NA>::ROOT + 2 * i + 0] = org;
-  g.buf[Slab<NA>::ROOT + 2 * i + 1] = del;
+  g.buf[Slab<T, NA>::ROOT + 2 * i + 0] = org;
+  g.buf[Slab<T, NA>::ROOT + 2 * i + 1] = del;
   wsync();
-  const double lam = org + del;
+  const T lam = org + del;
   lam_prev = lam;
-  k_i = sqrt(fmax(lam, 0.0));
-  if (!(om > 0.0)) {
+  k_i = sqrtT(maxT(lam, (T)0));
+  if (!(om > (T)0)) {
 #pragma unroll
-    for (int a = 0; a < NA; ++a) V[a] = (a == i) ? 1.0 : 0.0;
+    for (int a = 0; a < NA; ++a) V[a] = (a == i) ? (T)1 : (T)0;
     return;
   }
   // Gu-Eisenstat: zhat_i^2 = prod_a (lam_a - d_i) / (-omega prod_{j != i} (d_j - d_i))
-  double num = 1.0, den = -om;
+  T num = del + (org - L.d), den = -om;
 #pragma unroll
   for (int a = 0; a < NA; ++a) {
-    const double oa = g.buf[Slab<NA>::ROOT + 2 * a];
-    const double da = g.buf[Slab<NA>::ROOT + 2 * a + 1];
-    num *= (oa - L.d) + da;
-    if (a != i) den *= (T.d[a] - L.d);
+    const T oa = g.buf[Slab<T, NA>::ROOT + 2 * a];
+    const T da = g.buf[Slab<T, NA>::ROOT + 2 * a + 1];
+    if (a != i) {
+      num *= (oa - L.d) + da;
+      den *= tb.d[a] - L.d;
+    }
   }
-  const double zh = sqrt(fabs(num / den));
+  const T zh2 = num / den;
+  const T zh = sqrtT(absT(zh2));
   g.put_vec(zh, 2);
   // column norm of eigenvector i: sum_j zh_j^2 / (d_j - lam_i)^2
-  double nrm = 0.0;
+  T nrm = (T)0;
 #pragma unroll
   for (int j = 0; j < NA; ++j) {
-    const double q = g.vec(j, 2) * rcp_nr((T.d[j] - org) - del);
-    nrm = fma(q, q, nrm);
+    const T q = g.vec(j, 2) * rcpT((tb.d[j] - org) - del);
+    nrm = fmaT(q, q, nrm);
   }
-  g.put_vec(1.0 / sqrt(nrm), 3);
+  g.put_vec((T)1 / sqrtT(nrm), 3);
 #pragma unroll
   for (int a = 0; a < NA; ++a) {
-    const double oa = g.buf[Slab<NA>::ROOT + 2 * a];
-    const double da = g.buf[Slab<NA>::ROOT + 2 * a + 1];
-    V[a] = zh * rcp_nr((L.d - oa) - da) * g.vec(a, 3);
+    const T oa = g.buf[Slab<T, NA>::ROOT + 2 * a];
+    const T da = g.buf[Slab<T, NA>::ROOT + 2 * a + 1];
+    V[a] = zh * rcpT((L.d - oa) - da) * g.vec(a, 3);
   }
 }
 
@@ -351,21 +420,24 @@ __device__ __forceinline__ double x_coth_x(double x) {
 }
 
 // Layer operators in scaled variables (row i in this lane).
-template <int NA>
+template <typename T, int NA>
 struct LayerOps {
-  double t[NA], r[NA];
-  double bc, blp, blm;  // element i of beta_c, beta_l+, beta_l-
-  double qv;            // element i of Q = beta_l+ + t sqrt(w) (difference-form source)
+  T t[NA], r[NA];
+  T bc, blp, blm;  // element i of beta_c, beta_l+, beta_l-
+  T qv;            // element i of Q = beta_l+ + t sqrt(w) (difference-form source)
 };
 
+// (FP64 for every bulk type: see the precision note at the top)
 template <int NA>
-__device__ void layer_ops(Grp<NA>& g, const DenseTab<NA>& T, const LaneTab<NA>& L,
-                          const double (&V)[NA], double k_i, double Dl, LayerOps<NA>& o) {
+__device__ void layer_ops(Grp<double, NA>& g, const DenseTab<NA>& tb, const LaneTab<double, NA>& L,
+                          const double (&V)[NA], double k_i, double Dl, LayerOps<double, NA>& o) {
+  using T = double;
   const int i = g.i;
+  constexpr int RS = Slab<T, NA>::RS;
   // per-root factors of root i, broadcast
-  const double x = 0.5 * k_i * Dl;
-  const double tx = k_i * tanh(x);
-  const double cx = 2.0 * x_coth_x(x);
+  const T x = (T)0.5 * k_i * Dl;
+  const T tx = k_i * tanhT(x);
+  const T cx = (T)2 * x_coth_x(x);
   g.put_vec(tx, 2);
   g.put_vec(cx, 3);
   // Q_T = V diag(tx) V^T and Q_C' = V diag(cx) V^T: broadcast V
@@ -375,21 +447,21 @@ __device__ void layer_ops(Grp<NA>& g, const DenseTab<NA>& T, const LaneTab<NA>& 
   // slab alone, so putting V there again changes no value; its fences keep
   // the compiler from interleaving the second product with the first
   // inversion, which without them spills 69 registers in pass 1 (15% slower)
-  double QT[NA], FT[NA], FC[NA];
+  T QT[NA], FT[NA], FC[NA];
   {
-    double vt[NA];
+    T vt[NA];
 #pragma unroll
     for (int a = 0; a < NA; ++a) vt[a] = V[a] * g.vec(a, 2);
 #pragma unroll
     for (int j = 0; j < NA; ++j) {
-      double st = 0.0;
+      T st = (T)0;
 #pragma unroll
-      for (int a = 0; a < NA; ++a) st = fma(vt[a], g.buf[j * Slab<NA>::RS + a], st);
+      for (int a = 0; a < NA; ++a) st = fmaT(vt[a], g.buf[j * RS + a], st);
       QT[j] = st;
     }
   }
   {
-    double AT[NA];
+    T AT[NA];
 #pragma unroll
     for (int j = 0; j < NA; ++j) AT[j] = QT[j];
     AT[i] += L.m;               // M + Q_T      (lane-dependent diagonal)
@@ -397,68 +469,153 @@ __device__ void layer_ops(Grp<NA>& g, const DenseTab<NA>& T, const LaneTab<NA>& 
   }
   g.put_mat(V);
   {
-    double vc[NA], AC[NA];
+    T vc[NA], AC[NA];
 #pragma unroll
     for (int a = 0; a < NA; ++a) vc[a] = V[a] * g.vec(a, 3);
 #pragma unroll
     for (int j = 0; j < NA; ++j) {
-      double sc = 0.0;
+      T sc = (T)0;
 #pragma unroll
-      for (int a = 0; a < NA; ++a) sc = fma(vc[a], g.buf[j * Slab<NA>::RS + a], sc);
+      for (int a = 0; a < NA; ++a) sc = fmaT(vc[a], g.buf[j * RS + a], sc);
       AC[j] = sc;
     }
     AC[i] += Dl * L.m;          // D M + Q_C'
     g.inv(FC, AC);
   }
-  double tw = 0.0, rw = 0.0, fw = 0.0, qv = 0.0;
+  T tw = (T)0, rw = (T)0, fw = (T)0, qv = (T)0;
 #pragma unroll
   for (int j = 0; j < NA; ++j) {
-    const double ft = FT[j], fc = Dl * FC[j];
-    o.r[j] = L.m * (ft + fc) - ((j == i) ? 1.0 : 0.0);
+    const T ft = FT[j], fc = Dl * FC[j];
+    o.r[j] = L.m * (ft + fc) - ((j == i) ? (T)1 : (T)0);
     o.t[j] = L.m * (ft - fc);
-    tw = fma(o.t[j], T.sw[j], tw);
-    rw = fma(o.r[j], T.sw[j], rw);
-    fw = fma(ft, T.sw[j], fw);
-    qv = fma(FC[j], T.swmu[j], qv);
+    tw = fmaT(o.t[j], tb.sw[j], tw);
+    rw = fmaT(o.r[j], tb.sw[j], rw);
+    fw = fmaT(ft, tb.sw[j], fw);
+    qv = fmaT(FC[j], tb.swmu[j], qv);
   }
-  qv *= 2.0 * L.m;
+  qv *= (T)2 * L.m;
   o.qv = qv;
-  o.bc = 2.0 * g.mv(QT, fw);
+  o.bc = (T)2 * g.mv(QT, fw);
   o.blp = qv - tw;
   o.blm = (L.sw - rw) - qv;
 }
 
-template <int NA>
+template <typename T, int NA>
+__device__ __forceinline__ void round_ops(const LayerOps<double, NA>& s, LayerOps<T, NA>& o) {
+#pragma unroll
+  for (int j = 0; j < NA; ++j) {
+    o.t[j] = (T)s.t[j];
+    o.r[j] = (T)s.r[j];
+  }
+  o.bc = (T)s.bc; o.blp = (T)s.blp; o.blm = (T)s.blm; o.qv = (T)s.qv;
+}
+
+// ---- the eliminations with I - (reflection)(reflection) in FP64 -------------
+// for a float bulk under the thick-layer rule: the layer's own FP64
+// operators, the FP32 composites converted exactly, products accumulated and
+// right-hand sides formed in precision U = double.  (The kernels spell out
+// the same eliminations in the bulk type inline: through these helpers the
+// compiler serialises the FP64 kernels' cross-lane permutes, 16% slower.)
+
+// way down: P <- G t, u <- G (r Sigma + dS^g Q), y1 <- G beta_l+, y2 <- G Q,
+// G = (I - r R)^-1
+template <typename U, typename T, typename S, int NA>
+__device__ __forceinline__ void solve_down(Grp<U, NA>& gu, const LayerOps<S, NA>& op, const T (&R)[NA],
+                                           T Sig, T dSg, T (&P)[NA], T& u, T& y1, T& y2) {
+  const int i = gu.i;
+  U X[NA], Pu[NA];
+  gu.mul(X, op.r, R);
+#pragma unroll
+  for (int j = 0; j < NA; ++j) {
+    X[j] = ((j == i) ? (U)1 : (U)0) - X[j];
+    Pu[j] = (U)op.t[j];
+  }
+  U uu = gu.mv(op.r, (U)Sig) + (U)dSg * (U)op.qv;
+  U z1 = (U)op.blp, z2 = (U)op.qv;
+  gu.solve_mat_v3(Pu, X, uu, z1, z2);
+#pragma unroll
+  for (int j = 0; j < NA; ++j) P[j] = (T)Pu[j];
+  u = (T)uu; y1 = (T)z1; y2 = (T)z2;
+}
+
+// node: (I - R^up R_d) y = R^up s + s^up for the intensity and the two unit
+// responses (the latter only when wanted)
+template <typename U, typename T, int NA>
+__device__ __forceinline__ void solve_node(Grp<U, NA>& gu, const T (&Rup)[NA], const T (&Rd)[NA], T Sd,
+                                           T Sup, T dS, T dSu, T eS, T eSu, bool wd, bool we, T& Ip,
+                                           T& dIp, T& eDp) {
+  const int i = gu.i;
+  U y0 = gu.mv(Rup, (U)Sd) + (U)Sup;
+  U y1 = wd ? gu.mv(Rup, (U)dS) + (U)dSu : (U)0;
+  U y2 = we ? gu.mv(Rup, (U)eS) + (U)eSu : (U)0;
+  U X[NA];
+  gu.mul(X, Rup, Rd);
+#pragma unroll
+  for (int j = 0; j < NA; ++j) X[j] = ((j == i) ? (U)1 : (U)0) - X[j];
+  gu.solve3(X, y0, y1, y2);
+  Ip = (T)y0; dIp = (T)y1; eDp = (T)y2;
+}
+
+// way up: RG <- (I - R^up r)^-1 R^up  (= R^up (I - r R^up)^-1)
+template <typename U, typename T, typename S, int NA>
+__device__ __forceinline__ void solve_up(Grp<U, NA>& gu, const T (&Rup)[NA], const S (&r)[NA],
+                                         T (&RG)[NA]) {
+  const int i = gu.i;
+  U Y[NA], Xu[NA];
+  gu.mul(Y, Rup, r);
+#pragma unroll
+  for (int j = 0; j < NA; ++j) {
+    Y[j] = ((j == i) ? (U)1 : (U)0) - Y[j];
+    Xu[j] = (U)Rup[j];
+  }
+  gu.solve_mat(Xu, Y);
+#pragma unroll
+  for (int j = 0; j < NA; ++j) RG[j] = (T)Xu[j];
+}
+
+template <typename T, int NA>
+__device__ __forceinline__ T row_abs_sum(const T (&A)[NA]) {
+  T s = (T)0;
+#pragma unroll
+  for (int j = 0; j < NA; ++j) s += absT(A[j]);
+  return s;
+}
+
+template <typename T, int NA>
 struct FsDenseArgs {
   const Item* items;
   const int64_t* off;
   const double* tau;
-  const double* q;
-  const double* Sg;
-  const double* omega;
-  const double* Itop;
-  const double* Bbot;
-  const double* Bbot_prev;
-  const double* Ibot;
-  double *J, *JmS, *lstar, *lstar_c, *Iplus, *Iminus, *H, *Iemerg;
-  double* wsR;     // [rows][nf][NA][NA]
-  double* wsS;     // [rows][nf][NA]
-  double* wsV;     // [rows][nf][NA][NA+1]: eigen solution of layer (d, d+1), row i and root k_i
-  double* wsZ;     // [rows][nf][NA][2]: R_d G_d beta+ and R_d G_d Q of layer (d, d+1), element i
+  const T* q;
+  const T* Sg;
+  const T* omega;
+  const T* Itop;
+  const T* Bbot;
+  const T* Bbot_prev;
+  const T* Ibot;
+  T *J, *JmS, *lstar, *lstar_c, *Iplus, *Iminus, *H, *Iemerg;
+  T* wsR;     // [rows][nf][NA][NA]
+  T* wsS;     // [rows][nf][NA]
+  double* wsV; // [rows][nf][NA][NA+1]: eigen solution of layer (d, d+1), row i and root k_i
+               // (FP64 bulk only; a float bulk recomputes it in pass 2)
+  T* wsZ;     // [rows][nf][NA][2]: R_d G_d beta+ and R_d G_d Q of layer (d, d+1), element i
   uint32_t* status; // device status word: NONFINITE when an output is not finite
+  unsigned long long* thick_stats;  // [2]: eliminations in FP64, all eliminations (float bulk)
   int32_t nf;
   int32_t nitems;
   int32_t lower_bc;
+  int32_t thick_mode;   // DENSE_THICK_RULE / _NEVER / _ALWAYS (float bulk)
   uint32_t outputs;
 };
 
-// PASS 1: the adding recursion down (composites R, Sigma and the layers'
-// eigen solutions into the workspace); PASS 2: the pass up with the outputs.
-// Two kernels, so that each holds only its own pass's registers.
-template <int NA, int PASS>
-__global__ __launch_bounds__(64, 2) void k_fs_dense(FsDenseArgs<NA> a, DenseTab<NA> T) {
+// PASS 1: the adding recursion down (composites R, Sigma and, in FP64, the
+// layers' eigen solutions into the workspace); PASS 2: the pass up with the
+// outputs.  Two kernels, so that each holds only its own pass's registers.
+template <typename T, int NA, int PASS>
+__global__ __launch_bounds__(64, 2) void k_fs_dense(FsDenseArgs<T, NA> a, DenseTab<NA> tb) {
   constexpr int F = 64 / NA;
-  __shared__ double slab[F * Slab<NA>::SIZE];
+  constexpr bool MIXED = std::is_same<T, float>::value;
+  __shared__ double slab[F * Slab<double, NA>::SIZE];
   const int lane = (int)threadIdx.x;
   const int grp = lane / NA;
   const int item = (int)blockIdx.x;
@@ -470,84 +627,115 @@ __global__ __launch_bounds__(64, 2) void k_fs_dense(FsDenseArgs<NA> a, DenseTab<
   const int k = it.g * F + grp;
   if (k >= nf) return;   // a whole group: groups never talk to each other
   const int64_t row0 = a.off[b];
-  Grp<NA> g{slab + grp * Slab<NA>::SIZE, lane % NA, 4 * (lane - lane % NA)};
+  double* gslab = slab + grp * Slab<double, NA>::SIZE;
+  Grp<T, NA> g{reinterpret_cast<T*>(gslab), lane % NA, 4 * (lane - lane % NA)};
+  Grp<double, NA> g64{gslab, lane % NA, 4 * (lane - lane % NA)};
   const int i = g.i;
-  LaneTab<NA> L{};
+  LaneTab<double, NA> L64{};
 #pragma unroll
   for (int j = 0; j < NA; ++j)
     if (j == i) {
-      L.mu = T.mu[j]; L.m = T.m[j]; L.d = T.d[j]; L.z2 = T.z2[j]; L.w = T.w[j];
-      L.sw = T.sw[j]; L.swmu = T.swmu[j]; L.ext = T.ext[j];
+      L64.mu = tb.mu[j]; L64.m = tb.m[j]; L64.d = tb.d[j]; L64.z2 = tb.z2[j]; L64.w = tb.w[j];
+      L64.sw = tb.sw[j]; L64.swmu = tb.swmu[j]; L64.ext = tb.ext[j];
     }
+  LaneTab<T, NA> L{(T)L64.mu, (T)L64.m, (T)L64.d, (T)L64.z2, (T)L64.w, (T)L64.sw, (T)L64.swmu, L64.ext};
   const uint32_t o = a.outputs;
-  auto at = [&](const double* p, int64_t row) { return p[row * nf + k]; };
-  auto layer_depth = [&](int d) {   // optical depth of layer (d, d+1)
-    return 0.5 * (at(a.q, row0 + d) + at(a.q, row0 + d + 1)) * (a.tau[row0 + d + 1] - a.tau[row0 + d]);
+  auto at = [&](const T* p, int64_t row) { return p[row * nf + k]; };
+  // layer (d, d+1): optical depth and albedo in FP64 from the bulk inputs
+  auto layer_depth = [&](int d) {
+    return 0.5 * ((double)at(a.q, row0 + d) + (double)at(a.q, row0 + d + 1)) *
+           (a.tau[row0 + d + 1] - a.tau[row0 + d]);
   };
   auto layer_omega = [&](int d) {
-    return a.omega ? 0.5 * (at(a.omega, row0 + d) + at(a.omega, row0 + d + 1)) : 0.0;
+    return a.omega ? 0.5 * ((double)at(a.omega, row0 + d) + (double)at(a.omega, row0 + d + 1)) : 0.0;
   };
-  double* wsR = a.wsR + ((row0 * nf + k) * NA + i) * NA;   // + node * nf * NA * NA
-  double* wsS = a.wsS + (row0 * nf + k) * NA + i;           // + node * nf * NA
+  // the thick-layer rule's absorption-depth test for one layer
+  auto thick_layer = [&](T Dl, T om) { return Dl * sqrtT(maxT((T)1 - om, (T)0)) > (T)1; };
+  // wave-uniform decision: FP64 when any lane's group asks for it
+  auto wave_any = [&](bool f) { return __builtin_amdgcn_ballot_w64(f) != 0; };
+  T* wsR = a.wsR + ((row0 * nf + k) * NA + i) * NA;   // + node * nf * NA * NA
+  T* wsS = a.wsS + (row0 * nf + k) * NA + i;           // + node * nf * NA
   const int64_t strideR = (int64_t)nf * NA * NA;
   const int64_t strideS = (int64_t)nf * NA;
-  double* wsV = a.wsV + ((row0 * nf + k) * NA + i) * (NA + 1);   // + layer * nf * NA * (NA + 1)
+  double* wsV = MIXED ? nullptr : a.wsV + ((row0 * nf + k) * NA + i) * (NA + 1);  // + layer * nf * NA * (NA + 1)
   const int64_t strideV = (int64_t)nf * NA * (NA + 1);
-  double* wsZ = a.wsZ + ((row0 * nf + k) * NA + i) * 2;          // + layer * nf * NA * 2
+  T* wsZ = a.wsZ + ((row0 * nf + k) * NA + i) * 2;          // + layer * nf * NA * 2
   const int64_t strideZ = (int64_t)nf * NA * 2;
   // the unit-source responses behind Lambda* (plain form) and 1 - Lambda*
   // (difference form) are formed only for the outputs that are wanted
   const bool wd = (o & PPRT_OUT_LSTAR) != 0;
   const bool we = (o & PPRT_OUT_LSTAR_C) != 0;
+  const int mode = a.thick_mode;
+  unsigned n64 = 0, ntot = 0;   // eliminations of this wave in FP64, in all
 
   double V[NA];
   double kk = 0.0;
   double om_prev = -1.0;
   double lam_prev = -1.0;     // root of the last eigen solution (none yet)
-  LayerOps<NA> op;
+  LayerOps<double, NA> op64;  // the layer's operators (FP64) ...
+  LayerOps<T, NA> op;         // ... in the bulk type
 
   if constexpr (PASS == 1) {
   // ---------------- pass 1: adding recursion, top -> bottom
-  double R[NA];
+  T R[NA];
 #pragma unroll
-  for (int j = 0; j < NA; ++j) R[j] = 0.0;
+  for (int j = 0; j < NA; ++j) R[j] = (T)0;
   // difference form: D = I - S^g, scaled by sqrt(w)
-  double Sig = L.sw * ((a.Itop ? a.Itop[((int64_t)b * nf + k) * NA + L.ext] : 0.0) - at(a.Sg, row0));
+  T Sig = L.sw * ((a.Itop ? a.Itop[((int64_t)b * nf + k) * NA + L.ext] : (T)0) - at(a.Sg, row0));
   for (int d = 0; d < nd - 1; ++d) {
 #pragma unroll
     for (int j = 0; j < NA; ++j) wsR[d * strideR + j] = R[j];
     wsS[d * strideS] = Sig;
-    const double om = layer_omega(d);
-    if (om != om_prev) {
-      eigen<NA>(g, T, L, om, V, kk, lam_prev);
-      om_prev = om;
+    const double om64 = layer_omega(d);
+    if (om64 != om_prev) {
+      eigen<NA>(g64, tb, L64, om64, V, kk, lam_prev);
+      om_prev = om64;
     }
+    if constexpr (!MIXED) {
 #pragma unroll
-    for (int j = 0; j < NA; ++j) wsV[d * strideV + j] = V[j];
-    wsV[d * strideV + NA] = kk;
-    const double Dl = layer_depth(d);
-    layer_ops<NA>(g, T, L, V, kk, Dl, op);
-    const double dSg = at(a.Sg, row0 + d + 1) - at(a.Sg, row0 + d);
-    const double bp = dSg * op.qv;        // difference-form layer sources
-    const double bm = -dSg * op.qv;
+      for (int j = 0; j < NA; ++j) wsV[d * strideV + j] = V[j];
+      wsV[d * strideV + NA] = kk;
+    }
+    const double Dl64 = layer_depth(d);
+    layer_ops<NA>(g64, tb, L64, V, kk, Dl64, op64);
+    round_ops(op64, op);
+    const T Dl = (T)Dl64, om = (T)om64;
+    const T dSg = at(a.Sg, row0 + d + 1) - at(a.Sg, row0 + d);
+    const T bm = -dSg * op.qv;       // difference-form layer source of the way up
     // G = (I - r R)^-1: P = G t, u = G (r Sigma + beta+), and for pass 2's
     // unit responses G beta_l+ and G Q, from one elimination on I - r R
-    double X[NA], P[NA];
-    g.mul(X, op.r, R);
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      X[j] = ((j == i) ? 1.0 : 0.0) - X[j];
-      P[j] = op.t[j];
+    T P[NA], u, y1, y2;
+    bool use64 = false;
+    if constexpr (MIXED) {
+      if (mode == DENSE_THICK_ALWAYS) {
+        use64 = true;
+      } else if (mode == DENSE_THICK_RULE) {
+        const T nR = g.gmax(row_abs_sum(R));
+        use64 = wave_any(thick_layer(Dl, om) || row_abs_sum(op.r) * nR > (T)0.5);
+      }
+      n64 += use64 ? 1u : 0u;
+      ++ntot;
     }
-    double u = g.mv(op.r, Sig) + bp;
-    double y1 = op.blp, y2 = op.qv;
-    g.solve_mat_v3(P, X, u, y1, y2);
+    if (use64) {
+      solve_down<double>(g64, op64, R, Sig, dSg, P, u, y1, y2);
+    } else {
+      T X[NA];
+      g.mul(X, op.r, R);
+#pragma unroll
+      for (int j = 0; j < NA; ++j) {
+        X[j] = ((j == i) ? (T)1 : (T)0) - X[j];
+        P[j] = op.t[j];
+      }
+      u = g.mv(op.r, Sig) + dSg * op.qv;
+      y1 = op.blp; y2 = op.qv;
+      g.solve_mat_v3(P, X, u, y1, y2);
+    }
     if (wd) wsZ[d * strideZ] = g.mv(R, y1);
     if (we) wsZ[d * strideZ + 1] = g.mv(R, y2);
     // Sigma_{d+1} = t (Sigma + R u) + beta-,  R_{d+1} = r + t R P
-    const double Ru = g.mv(R, u);
-    const double Sig_n = g.mv(op.t, Sig + Ru) + bm;
-    double RP[NA], tRP[NA];
+    const T Ru = g.mv(R, u);
+    const T Sig_n = g.mv(op.t, Sig + Ru) + bm;
+    T RP[NA], tRP[NA];
     g.mul(RP, R, P);
     g.mul(tRP, op.t, RP);
 #pragma unroll
@@ -560,77 +748,106 @@ __global__ __launch_bounds__(64, 2) void k_fs_dense(FsDenseArgs<NA> a, DenseTab<
   } else {
   // ---------------- pass 2: bottom -> top, outputs per node
   bool nonfinite = false;
-  double Rup[NA];
+  T Rup[NA];
 #pragma unroll
-  for (int j = 0; j < NA; ++j) Rup[j] = 0.0;
-  double Sup;
+  for (int j = 0; j < NA; ++j) Rup[j] = (T)0;
+  T Sup;
   {
     const int64_t rl = row0 + nd - 1;
-    const double S_last = at(a.Sg, rl);
+    const T S_last = at(a.Sg, rl);
     if (a.lower_bc == PPRT_BC_DIFFUSION) {
-      const double Bb = a.Bbot[(int64_t)b * nf + k];
-      const double Bp = a.Bbot_prev[(int64_t)b * nf + k];
-      const double gr = (Bb - Bp) / layer_depth(nd - 2);
+      const T Bb = a.Bbot[(int64_t)b * nf + k];
+      const T Bp = a.Bbot_prev[(int64_t)b * nf + k];
+      const T gr = (Bb - Bp) / (T)layer_depth(nd - 2);
       Sup = L.sw * ((Bb - S_last) + L.mu * gr);
     } else {
-      Sup = L.sw * ((a.Ibot ? a.Ibot[((int64_t)b * nf + k) * NA + L.ext] : 0.0) - S_last);
+      Sup = L.sw * ((a.Ibot ? a.Ibot[((int64_t)b * nf + k) * NA + L.ext] : (T)0) - S_last);
     }
-    (void)rl;
   }
-  double dSu = 0.0;           // dSigma^up of the node being emitted (layer below)
-  double eSu = -L.sw;         // its difference-form counterpart (lower boundary: -1)
-  om_prev = -1.0;
+  T dSu = (T)0;           // dSigma^up of the node being emitted (layer below)
+  T eSu = -L.sw;          // its difference-form counterpart (lower boundary: -1)
+  bool thick_below = false;   // the layer below the node meets the absorption-depth test
   for (int d = nd - 1; d >= 0; --d) {
     const bool has_a = d >= 1;  // layer a = (d-1, d) above node d
-    if (has_a) {      // the eigen solution of layer a, kept by pass 1
+    T Da = (T)0, oma = (T)0;
+    if (has_a) {      // the eigen solution of layer a: kept by pass 1 (FP64 bulk) or recomputed
+      const double om64 = layer_omega(d - 1);
+      if constexpr (MIXED) {
+        if (om64 != om_prev) {
+          eigen<NA>(g64, tb, L64, om64, V, kk, lam_prev);
+          om_prev = om64;
+        }
+      } else {
 #pragma unroll
-      for (int j = 0; j < NA; ++j) V[j] = wsV[(d - 1) * strideV + j];
-      kk = wsV[(d - 1) * strideV + NA];
-      layer_ops<NA>(g, T, L, V, kk, layer_depth(d - 1), op);
+        for (int j = 0; j < NA; ++j) V[j] = wsV[(d - 1) * strideV + j];
+        kk = wsV[(d - 1) * strideV + NA];
+      }
+      const double Da64 = layer_depth(d - 1);
+      layer_ops<NA>(g64, tb, L64, V, kk, Da64, op64);
+      round_ops(op64, op);
+      Da = (T)Da64;
+      oma = (T)om64;
     }
+    const bool thick_a = MIXED && has_a && mode == DENSE_THICK_RULE && thick_layer(Da, oma);
     // ---- emit node d
-    double Rd[NA];
+    T Rd[NA];
 #pragma unroll
     for (int j = 0; j < NA; ++j) Rd[j] = wsR[d * strideR + j];
-    const double Sd = wsS[d * strideS];
+    const T Sd = wsS[d * strideS];
     // unit response: layer above (S^g 0 -> 1) through R_{d-1}, G_{d-1}; in
     // plain form (dS, for Lambda*) and in difference form (eS, sources +-Q
     // and -1 at a boundary, for 1 - Lambda* with full relative accuracy)
     // (each response only when its output is wanted: wd, we are uniform)
-    double dS = 0.0, eS = -L.sw;
+    T dS = (T)0, eS = -L.sw;
     if (has_a) {      // R_{d-1} G_{d-1} (dbeta+_a, Q_a), kept by pass 1
       if (wd) dS = g.mv(op.t, wsZ[(d - 1) * strideZ]) + op.blm;
       if (we) eS = g.mv(op.t, wsZ[(d - 1) * strideZ + 1]) - op.qv;
     }
     // I+ and the two responses from one elimination on I - R^up R_d
-    double Ip = g.mv(Rup, Sd) + Sup;
-    double dIp = wd ? g.mv(Rup, dS) + dSu : 0.0;
-    double eDp = we ? g.mv(Rup, eS) + eSu : 0.0;
+    T Ip, dIp, eDp;
     {
-      double X[NA];
-      g.mul(X, Rup, Rd);
+      bool use64 = false;
+      if constexpr (MIXED) {
+        if (mode == DENSE_THICK_ALWAYS) {
+          use64 = true;
+        } else if (mode == DENSE_THICK_RULE) {
+          const T nR = g.gmax(row_abs_sum(Rd));
+          use64 = wave_any(thick_a || thick_below || row_abs_sum(Rup) * nR > (T)0.5);
+        }
+        n64 += use64 ? 1u : 0u;
+        ++ntot;
+      }
+      if (use64) {
+        solve_node<double>(g64, Rup, Rd, Sd, Sup, dS, dSu, eS, eSu, wd, we, Ip, dIp, eDp);
+      } else {
+        Ip = g.mv(Rup, Sd) + Sup;
+        dIp = wd ? g.mv(Rup, dS) + dSu : (T)0;
+        eDp = we ? g.mv(Rup, eS) + eSu : (T)0;
+        T X[NA];
+        g.mul(X, Rup, Rd);
 #pragma unroll
-      for (int j = 0; j < NA; ++j) X[j] = ((j == i) ? 1.0 : 0.0) - X[j];
-      g.solve3(X, Ip, dIp, eDp);
+        for (int j = 0; j < NA; ++j) X[j] = ((j == i) ? (T)1 : (T)0) - X[j];
+        g.solve3(X, Ip, dIp, eDp);
+      }
     }
-    const double Im = g.mv(Rd, Ip) + Sd;
+    const T Im = g.mv(Rd, Ip) + Sd;
     // Ip, Im are the scaled differences D+- = sqrt(w) (I+- - S^g)
-    const double JmSn = 0.5 * g.sum(L.sw * (Ip + Im));
-    double Ln = 0.0, Lcn = 0.0;
+    const T JmSn = (T)0.5 * g.sum(L.sw * (Ip + Im));
+    T Ln = (T)0, Lcn = (T)0;
     if (wd) {
-      const double dIm = g.mv(Rd, dIp) + dS;
-      Ln = 0.5 * g.sum(L.sw * (dIp + dIm));
+      const T dIm = g.mv(Rd, dIp) + dS;
+      Ln = (T)0.5 * g.sum(L.sw * (dIp + dIm));
     }
     if (we) {
-      const double eDm = g.mv(Rd, eDp) + eS;
-      Lcn = -0.5 * g.sum(L.sw * (eDp + eDm));
+      const T eDm = g.mv(Rd, eDp) + eS;
+      Lcn = (T)-0.5 * g.sum(L.sw * (eDp + eDm));
     }
-    const double Hn = 0.5 * g.sum(L.swmu * (Ip - Im));
+    const T Hn = (T)0.5 * g.sum(L.swmu * (Ip - Im));
     // a zero or non-finite pivot in any elimination ends up here
     nonfinite |= !isfinite(Ip + Im + Ln + Lcn);
     {
       const int64_t x = (row0 + d) * nf + k;
-      const double S = a.Sg[x];
+      const T S = a.Sg[x];
       if (i == 0) {
         if (o & PPRT_OUT_J) a.J[x] = JmSn + S;
         if (o & PPRT_OUT_JMS) a.JmS[x] = JmSn;
@@ -645,94 +862,125 @@ __global__ __launch_bounds__(64, 2) void k_fs_dense(FsDenseArgs<NA> a, DenseTab<
     }
     // ---- move the lower composite up through layer a
     if (has_a) {
-      const double dSg = at(a.Sg, row0 + d) - at(a.Sg, row0 + d - 1);
-      const double bp = dSg * op.qv;
-      const double bm = -dSg * op.qv;
+      const T dSg = at(a.Sg, row0 + d) - at(a.Sg, row0 + d - 1);
+      const T bp = dSg * op.qv;
+      const T bm = -dSg * op.qv;
       // R^up G^up = R^up (I - r R^up)^-1 = (I - R^up r)^-1 R^up
-      double Y[NA], RG[NA];
-      g.mul(Y, Rup, op.r);
-#pragma unroll
-      for (int j = 0; j < NA; ++j) {
-        Y[j] = ((j == i) ? 1.0 : 0.0) - Y[j];
-        RG[j] = Rup[j];
+      T RG[NA];
+      bool use64 = false;
+      if constexpr (MIXED) {
+        if (mode == DENSE_THICK_ALWAYS) {
+          use64 = true;
+        } else if (mode == DENSE_THICK_RULE) {
+          const T nr = g.gmax(row_abs_sum(op.r));
+          use64 = wave_any(thick_a || row_abs_sum(Rup) * nr > (T)0.5);
+        }
+        n64 += use64 ? 1u : 0u;
+        ++ntot;
       }
-      g.solve_mat(RG, Y);
-      const double w1 = g.mv(RG, g.mv(op.r, Sup) + bm);
-      const double Sup_n = g.mv(op.t, Sup + w1) + bp;
+      if (use64) {
+        solve_up<double>(g64, Rup, op64.r, RG);
+      } else {
+        T Y[NA];
+        g.mul(Y, Rup, op.r);
+#pragma unroll
+        for (int j = 0; j < NA; ++j) {
+          Y[j] = ((j == i) ? (T)1 : (T)0) - Y[j];
+          RG[j] = Rup[j];
+        }
+        g.solve_mat(RG, Y);
+      }
+      const T w1 = g.mv(RG, g.mv(op.r, Sup) + bm);
+      const T Sup_n = g.mv(op.t, Sup + w1) + bp;
       // unit response of layer a seen from node d-1 (S^g 1 -> 0)
-      const double dbm = op.bc - op.blm, dbp = op.bc - op.blp;
+      const T dbm = op.bc - op.blm, dbp = op.bc - op.blp;
       if (wd) dSu = g.mv(op.t, g.mv(RG, dbm)) + dbp;
       if (we) eSu = g.mv(op.t, g.mv(RG, op.qv)) - op.qv;
-      double RGt[NA], tRGt[NA];
+      T RGt[NA], tRGt[NA];
       g.mul(RGt, RG, op.t);
       g.mul(tRGt, op.t, RGt);
 #pragma unroll
       for (int j = 0; j < NA; ++j) Rup[j] = op.r[j] + tRGt[j];
       Sup = Sup_n;
     }
+    thick_below = thick_a;
   }
   if (nonfinite && a.status) atomicOr(a.status, PPRT_DEV_NONFINITE);
   }
+  if constexpr (MIXED) {
+    if (a.thick_stats && lane == 0) {
+      atomicAdd(&a.thick_stats[0], (unsigned long long)n64);
+      atomicAdd(&a.thick_stats[1], (unsigned long long)ntot);
+    }
+  }
 }
 
 template <int NA>
-hipError_t launch_dense_t(int nitems, hipStream_t s, const void* args, const void* tab) {
-  hipLaunchKernelGGL((k_fs_dense<NA, 1>), dim3(nitems), dim3(64), 0, s,
-                     *static_cast<const FsDenseArgs<NA>*>(args), *static_cast<const DenseTab<NA>*>(tab));
-  hipLaunchKernelGGL((k_fs_dense<NA, 2>), dim3(nitems), dim3(64), 0, s,
-                     *static_cast<const FsDenseArgs<NA>*>(args), *static_cast<const DenseTab<NA>*>(tab));
-  return hipGetLastError();
-}
-
-template <int NA>
-void fill_tab(DenseTab<NA>& T, const double* mu_asc, const double* w_asc) {
+void fill_tab(DenseTab<NA>& tb, const double* mu_asc, const double* w_asc) {
   // internal order: descending mu
   for (int i = 0; i < NA; ++i) {
     const int e = NA - 1 - i;
     const double m = mu_asc[e], w = w_asc[e];
-    T.mu[i] = m; T.m[i] = 1.0 / m; T.d[i] = 1.0 / (m * m); T.w[i] = w;
-    T.z2[i] = w / (m * m); T.sw[i] = sqrt(w); T.swmu[i] = sqrt(w) * m; T.ext[i] = e;
+    tb.mu[i] = m; tb.m[i] = 1.0 / m; tb.d[i] = 1.0 / (m * m); tb.w[i] = w;
+    tb.z2[i] = w / (m * m); tb.sw[i] = sqrt(w); tb.swmu[i] = sqrt(w) * m; tb.ext[i] = e;
   }
 }
 
-template <int NA>
+template <typename T, int NA>
 hipError_t run_dense(const DenseLaunch& L, hipStream_t s) {
-  FsDenseArgs<NA> a{};
-  a.items = L.items; a.off = L.off; a.tau = L.tau; a.q = L.q; a.Sg = L.Sg; a.omega = L.omega;
-  a.Itop = L.Itop; a.Bbot = L.Bbot; a.Bbot_prev = L.Bbot_prev; a.Ibot = L.Ibot;
-  a.J = L.J; a.JmS = L.JmS; a.lstar = L.lstar; a.lstar_c = L.lstar_c; a.Iplus = L.Iplus;
-  a.Iminus = L.Iminus; a.H = L.H; a.Iemerg = L.Iemerg;
-  a.wsR = L.ws;
-  a.wsS = L.ws + (size_t)L.rows * L.nf * NA * NA;
-  a.wsV = a.wsS + (size_t)L.rows * L.nf * NA;
-  a.wsZ = a.wsV + (size_t)L.rows * L.nf * NA * (NA + 1);
+  FsDenseArgs<T, NA> a{};
+  a.items = L.items; a.off = L.off; a.tau = L.tau;
+  a.q = (const T*)L.q; a.Sg = (const T*)L.Sg; a.omega = (const T*)L.omega;
+  a.Itop = (const T*)L.Itop; a.Bbot = (const T*)L.Bbot; a.Bbot_prev = (const T*)L.Bbot_prev;
+  a.Ibot = (const T*)L.Ibot;
+  a.J = (T*)L.J; a.JmS = (T*)L.JmS; a.lstar = (T*)L.lstar; a.lstar_c = (T*)L.lstar_c;
+  a.Iplus = (T*)L.Iplus; a.Iminus = (T*)L.Iminus; a.H = (T*)L.H; a.Iemerg = (T*)L.Iemerg;
+  // workspace: R | Sigma | Z in the bulk type, then (FP64 bulk) the eigen solutions
+  const size_t rf = (size_t)L.rows * L.nf;
+  a.wsR = (T*)L.ws;
+  a.wsS = a.wsR + rf * NA * NA;
+  a.wsZ = a.wsS + rf * NA;
+  a.wsV = std::is_same<T, double>::value ? (double*)(a.wsZ + rf * NA * 2) : nullptr;
   a.nf = L.nf; a.nitems = L.nitems; a.lower_bc = L.lower_bc; a.outputs = L.outputs;
   a.status = L.status;
-  DenseTab<NA> T{};
-  fill_tab<NA>(T, L.mu, L.w);
-  return launch_dense_t<NA>(L.nitems, s, &a, &T);
+  a.thick_stats = L.thick_stats;
+  a.thick_mode = L.thick_mode;
+  DenseTab<NA> tb{};
+  fill_tab<NA>(tb, L.mu, L.w);
+  hipLaunchKernelGGL((k_fs_dense<T, NA, 1>), dim3(L.nitems), dim3(64), 0, s, a, tb);
+  hipLaunchKernelGGL((k_fs_dense<T, NA, 2>), dim3(L.nitems), dim3(64), 0, s, a, tb);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t run_dense_na(const DenseLaunch& L, hipStream_t s) {
+  switch (L.na) {
+    case 1: return run_dense<T, 1>(L, s);
+    case 2: return run_dense<T, 2>(L, s);
+    case 4: return run_dense<T, 4>(L, s);
+    case 8: return run_dense<T, 8>(L, s);
+    case 16: return run_dense<T, 16>(L, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace
 
 bool dense_na_supported(int na) { return na == 1 || na == 2 || na == 4 || na == 8 || na == 16; }
 
-size_t dense_workspace_bytes(int na, int64_t rows, int nf) {
-  return (size_t)rows * nf * (size_t)(2 * na * na + 4 * na) * sizeof(double);
+size_t dense_workspace_bytes(int na, int64_t rows, int nf, int precision) {
+  // per node and frequency: R (na^2), Sigma (na), Z (2 na) in the bulk type,
+  // plus the eigen solution (na^2 + na doubles) in FP64
+  const size_t rf = (size_t)rows * nf;
+  if (precision == PPRT_FP64) return rf * (size_t)(2 * na * na + 4 * na) * sizeof(double);
+  return rf * (size_t)(na * na + 3 * na) * sizeof(float);
 }
 
 int dense_freqs_per_item(int na) { return 64 / na; }
 
 hipError_t launch_fs_dense(const DenseLaunch& L, hipStream_t s) {
   if (L.nitems == 0) return hipSuccess;
-  switch (L.na) {
-    case 1: return run_dense<1>(L, s);
-    case 2: return run_dense<2>(L, s);
-    case 4: return run_dense<4>(L, s);
-    case 8: return run_dense<8>(L, s);
-    case 16: return run_dense<16>(L, s);
-    default: return hipErrorInvalidValue;
-  }
+  return L.precision == PPRT_FP64 ? run_dense_na<double>(L, s) : run_dense_na<float>(L, s);
 }
 
 }  // namespace pprt

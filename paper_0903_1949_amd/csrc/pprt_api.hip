@@ -21,6 +21,7 @@ struct pprt_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   uint32_t* d_status = nullptr;   // device status word
+  unsigned long long* d_thick = nullptr;   // [2] FP64 / all dense eliminations (FP32 bulk)
   uint32_t validate = 0;          // PPRT_VALIDATE_* flags
   void* scratch = nullptr;        // this device's copy of the static scratch array
   std::string err;
@@ -83,6 +84,7 @@ struct pprt_plan {
   // two-level operator: tri-diagonal Lambda* and/or Ng acceleration
   int lstar_tri = 0, use_ng = 0;
   size_t ws_coef = 0, ws_hist = 0, ws_ngc = 0;
+  int thick_mode = DENSE_THICK_RULE;   // FP32-bulk scattering path: the FP64 elimination rule
 };
 
 namespace {
@@ -397,8 +399,11 @@ pprt_status pprt_create(pprt_ctx** out, int device) {
   c->device = device;
   if (hipMalloc(&c->d_status, sizeof(uint32_t)) != hipSuccess ||
       hipMemset(c->d_status, 0, sizeof(uint32_t)) != hipSuccess ||
+      hipMalloc(&c->d_thick, 2 * sizeof(unsigned long long)) != hipSuccess ||
+      hipMemset(c->d_thick, 0, 2 * sizeof(unsigned long long)) != hipSuccess ||
       device_scratch(device, &c->scratch) != hipSuccess) {
     if (c->d_status) (void)hipFree(c->d_status);
+    if (c->d_thick) (void)hipFree(c->d_thick);
     delete c;
     return PPRT_E_DEVICE;
   }
@@ -409,6 +414,7 @@ pprt_status pprt_create(pprt_ctx** out, int device) {
 void pprt_destroy(pprt_ctx* c) {
   if (!c) return;
   if (c->d_status) (void)hipFree(c->d_status);
+  if (c->d_thick) (void)hipFree(c->d_thick);
   delete c;
 }
 
@@ -675,16 +681,42 @@ pprt_status pprt_formal_solution(pprt_plan* p, const pprt_fs_in* in, pprt_fs_out
 
 pprt_status pprt_plan_scattering_workspace_bytes(const pprt_plan* p, size_t* bytes) {
   if (!p || !bytes) return PPRT_E_INVALID_ARG;
-  *bytes = dense_na_supported(p->na) ? dense_workspace_bytes(p->na, p->rows, p->nf) : 0;
+  *bytes = dense_na_supported(p->na) ? dense_workspace_bytes(p->na, p->rows, p->nf, p->precision) : 0;
   return PPRT_OK;
+}
+
+pprt_status pprt_plan_set_thick_mode(pprt_plan* p, int32_t mode) {
+  if (!p) return PPRT_E_INVALID_ARG;
+  static_assert(PPRT_THICK_RULE == DENSE_THICK_RULE && PPRT_THICK_NEVER == DENSE_THICK_NEVER &&
+                    PPRT_THICK_ALWAYS == DENSE_THICK_ALWAYS, "thick modes");
+  if (mode != PPRT_THICK_RULE && mode != PPRT_THICK_NEVER && mode != PPRT_THICK_ALWAYS)
+    return fail(p->ctx, PPRT_E_INVALID_ARG, "thick mode %d is not one of PPRT_THICK_*", mode);
+  p->thick_mode = mode;
+  return PPRT_OK;
+}
+
+pprt_status pprt_thick_counts(pprt_ctx* c, uint64_t* fp64, uint64_t* total) {
+  if (!c || !fp64 || !total) return PPRT_E_INVALID_ARG;
+  unsigned long long h[2] = {0, 0};
+  pprt_status r = hip_check(c, hipMemcpyAsync(h, c->d_thick, sizeof h, hipMemcpyDeviceToHost, c->stream),
+                            "thick-count read");
+  if (r == PPRT_OK) r = hip_check(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  if (r != PPRT_OK) return r;
+  *fp64 = h[0];
+  *total = h[1];
+  return PPRT_OK;
+}
+
+pprt_status pprt_thick_counts_reset(pprt_ctx* c) {
+  if (!c) return PPRT_E_INVALID_ARG;
+  return hip_check(c, hipMemsetAsync(c->d_thick, 0, 2 * sizeof(unsigned long long), c->stream),
+                   "thick-count reset");
 }
 
 pprt_status pprt_formal_solution_scattering(pprt_plan* p, const pprt_fs_in* in, const void* omega,
                                             pprt_fs_out* out, void* ws) {
   if (!p) return PPRT_E_INVALID_ARG;
   pprt_ctx* c = p->ctx;
-  if (p->precision != PPRT_FP64)
-    return fail(c, PPRT_E_UNSUPPORTED, "in-layer scattering runs in FP64 plans only");
   if (!dense_na_supported(p->na))
     return fail(c, PPRT_E_UNSUPPORTED, "in-layer scattering needs na in {1,2,4,8,16} (got %d)", p->na);
   if (!in || !out || !omega) return fail(c, PPRT_E_INVALID_ARG, "null in/out/omega");
@@ -692,7 +724,7 @@ pprt_status pprt_formal_solution_scattering(pprt_plan* p, const pprt_fs_in* in, 
   if (p->lower_bc == PPRT_BC_DIFFUSION && (!in->Bbot || !in->Bbot_prev))
     return fail(c, PPRT_E_INVALID_ARG, "diffusion lower boundary needs Bbot and Bbot_prev");
   if (!ws) return fail(c, PPRT_E_WORKSPACE, "workspace of %zu bytes required",
-                       dense_workspace_bytes(p->na, p->rows, p->nf));
+                       dense_workspace_bytes(p->na, p->rows, p->nf, p->precision));
   const uint32_t o = p->outputs;
   if (o & (PPRT_OUT_LSTAR_SUB | PPRT_OUT_LSTAR_SUP))
     return fail(c, PPRT_E_UNSUPPORTED, "the tri-diagonal band is available for omega = 0 only");
@@ -707,19 +739,19 @@ pprt_status pprt_formal_solution_scattering(pprt_plan* p, const pprt_fs_in* in, 
   {
     pprt_status v = validate_fs_in(p, in, nullptr);
     if (v == PPRT_OK && (c->validate & PPRT_VALIDATE_INPUTS))
-      v = validate_array(c, omega, p->rows * (int64_t)p->nf, 8, "omega", false);
+      v = validate_array(c, omega, p->rows * (int64_t)p->nf, p->precision == PPRT_FP64 ? 8 : 4,
+                         "omega", false);
     if (v != PPRT_OK) return v;
   }
   DenseLaunch L{};
   L.status = c->d_status;
-  L.items = p->d_items_dense; L.off = p->d_off; L.tau = in->tau; L.q = (const double*)in->q;
-  L.Sg = (const double*)in->Sg; L.omega = (const double*)omega; L.Itop = (const double*)in->Itop;
-  L.Bbot = (const double*)in->Bbot; L.Bbot_prev = (const double*)in->Bbot_prev;
-  L.Ibot = (const double*)in->Ibot;
-  L.J = (double*)out->J; L.JmS = (double*)out->JmS; L.lstar = (double*)out->lstar;
-  L.lstar_c = (double*)out->lstar_c; L.Iplus = (double*)out->Iplus; L.Iminus = (double*)out->Iminus;
-  L.H = (double*)out->H; L.Iemerg = (double*)out->Iemerg;
-  L.ws = (double*)ws; L.rows = p->rows; L.nf = p->nf; L.na = p->na; L.nitems = p->n_dense;
+  L.thick_stats = c->d_thick; L.precision = p->precision; L.thick_mode = p->thick_mode;
+  L.items = p->d_items_dense; L.off = p->d_off; L.tau = in->tau; L.q = in->q;
+  L.Sg = in->Sg; L.omega = omega; L.Itop = in->Itop;
+  L.Bbot = in->Bbot; L.Bbot_prev = in->Bbot_prev; L.Ibot = in->Ibot;
+  L.J = out->J; L.JmS = out->JmS; L.lstar = out->lstar; L.lstar_c = out->lstar_c;
+  L.Iplus = out->Iplus; L.Iminus = out->Iminus; L.H = out->H; L.Iemerg = out->Iemerg;
+  L.ws = ws; L.rows = p->rows; L.nf = p->nf; L.na = p->na; L.nitems = p->n_dense;
   L.lower_bc = p->lower_bc; L.outputs = o; L.mu = p->mu.data(); L.w = p->w.data();
   return hip_check(c, launch_fs_dense(L, c->stream), "scattering formal-solution launch");
 }
@@ -943,8 +975,8 @@ static void continuum_layout(const pprt_plan* p, size_t off[6]) {
   off[2] = off[1] + arr;
   off[3] = off[2] + arr;
   off[4] = off[3] + align256((size_t)p->rows * 4 * sizeof(double));
-  off[5] = off[4] + (dense_na_supported(p->na) && p->precision == PPRT_FP64
-                         ? align256(dense_workspace_bytes(p->na, p->rows, p->nf)) : 0);
+  off[5] = off[4] + (dense_na_supported(p->na)
+                         ? align256(dense_workspace_bytes(p->na, p->rows, p->nf, p->precision)) : 0);
 }
 
 pprt_status pprt_plan_continuum_workspace_bytes(const pprt_plan* p, size_t* bytes) {
@@ -966,8 +998,8 @@ pprt_status pprt_two_level_ali_step_continuum(pprt_plan* p, const pprt_fs_in* in
     return fail(c, PPRT_E_INVALID_ARG, "tau, q, pfrac and sg_const are required");
   if (!at->eps || !at->B || !at->wphi) return fail(c, PPRT_E_INVALID_ARG, "atom needs eps, B and wphi");
   if (!ws) return fail(c, PPRT_E_WORKSPACE, "workspace required (pprt_plan_continuum_workspace_bytes)");
-  if (ct->omega && (p->precision != PPRT_FP64 || !dense_na_supported(p->na)))
-    return fail(c, PPRT_E_UNSUPPORTED, "in-layer scattering needs an FP64 plan and na in {1,2,4,8,16}");
+  if (ct->omega && !dense_na_supported(p->na))
+    return fail(c, PPRT_E_UNSUPPORTED, "in-layer scattering needs na in {1,2,4,8,16}");
   {
     pprt_status v = validate_fs_in(p, in, S);
     if (v == PPRT_OK && (c->validate & PPRT_VALIDATE_INPUTS)) {
@@ -993,12 +1025,12 @@ pprt_status pprt_two_level_ali_step_continuum(pprt_plan* p, const pprt_fs_in* in
   if (ct->omega) {
     DenseLaunch L{};
     L.status = c->d_status;
-    L.items = p->d_items_dense; L.off = p->d_off; L.tau = in->tau; L.q = (const double*)in->q;
-    L.Sg = (const double*)Sg; L.omega = (const double*)ct->omega; L.Itop = (const double*)in->Itop;
-    L.Bbot = (const double*)in->Bbot; L.Bbot_prev = (const double*)in->Bbot_prev;
-    L.Ibot = (const double*)in->Ibot;
-    L.JmS = (double*)JmS; L.lstar_c = (double*)Lc;
-    L.ws = (double*)(base + off[4]); L.rows = p->rows; L.nf = p->nf; L.na = p->na;
+    L.thick_stats = c->d_thick; L.precision = p->precision; L.thick_mode = p->thick_mode;
+    L.items = p->d_items_dense; L.off = p->d_off; L.tau = in->tau; L.q = in->q;
+    L.Sg = Sg; L.omega = ct->omega; L.Itop = in->Itop;
+    L.Bbot = in->Bbot; L.Bbot_prev = in->Bbot_prev; L.Ibot = in->Ibot;
+    L.JmS = JmS; L.lstar_c = Lc;
+    L.ws = base + off[4]; L.rows = p->rows; L.nf = p->nf; L.na = p->na;
     L.nitems = p->n_dense; L.lower_bc = p->lower_bc; L.outputs = PPRT_OUT_JMS | PPRT_OUT_LSTAR_C;
     L.mu = p->mu.data(); L.w = p->w.data();
     e = launch_fs_dense(L, c->stream);
@@ -1360,7 +1392,7 @@ static void nlte_layout(const pprt_plan* p, int nlev, int ntr, size_t off[NL_END
                              align256((size_t)p->nb * sizeof(double)),
                              align256((size_t)p->nb * sizeof(int32_t)),
                              align256((size_t)p->nb * sizeof(int32_t)),
-                             align256(dense_workspace_bytes(p->na, p->rows, p->nf))};
+                             align256(dense_workspace_bytes(p->na, p->rows, p->nf, PPRT_FP64))};
   off[0] = 0;
   for (int i = 0; i < NL_END; ++i) off[i + 1] = off[i] + sz[i];
 }
@@ -1411,6 +1443,7 @@ static pprt_status nlte_step_impl(pprt_plan* p, const pprt_fs_in* in, const pprt
   if (r != PPRT_OK) return r;
   DenseLaunch L{};
   L.status = c->d_status;
+  L.precision = PPRT_FP64;
   L.items = p->d_items_dense; L.off = p->d_off; L.tau = in->tau; L.q = q; L.Sg = Sg; L.omega = om;
   L.Itop = (const double*)in->Itop; L.Bbot = Bb; L.Bbot_prev = Bp; L.Ibot = nullptr;
   L.J = J; L.lstar = Ls; L.ws = dws; L.rows = p->rows; L.nf = p->nf; L.na = p->na;

@@ -201,29 +201,34 @@ struct AliNlArgs {
 };
 hipError_t launch_ali_update_nl(int nb, hipStream_t s, const AliUpdateArgs& a, const AliNlArgs& n);
 
-// Dense (in-layer scattering) formal solution, FP64 (fs_dense.hip).
+// Dense (in-layer scattering) formal solution, FP64 or FP32 bulk (fs_dense.hip).
+// Real arrays are double for PPRT_FP64 and float for PPRT_FP32; tau is double.
+enum { DENSE_THICK_RULE = 0, DENSE_THICK_NEVER = 1, DENSE_THICK_ALWAYS = 2 };
 struct DenseLaunch {
   const Item* items;
   const int64_t* off;
   const double* tau;
-  const double* q;
-  const double* Sg;
-  const double* omega;
-  const double* Itop;
-  const double* Bbot;
-  const double* Bbot_prev;
-  const double* Ibot;
-  double *J, *JmS, *lstar, *lstar_c, *Iplus, *Iminus, *H, *Iemerg;
-  double* ws;
+  const void* q;
+  const void* Sg;
+  const void* omega;
+  const void* Itop;
+  const void* Bbot;
+  const void* Bbot_prev;
+  const void* Ibot;
+  void *J, *JmS, *lstar, *lstar_c, *Iplus, *Iminus, *H, *Iemerg;
+  void* ws;
   uint32_t* status;   // device status word (NONFINITE), may be NULL
+  unsigned long long* thick_stats;   // [2] FP64 / all eliminations (FP32 bulk), may be NULL
   int64_t rows;
   int32_t nf, na, nitems, lower_bc;
+  int32_t precision;  // PPRT_FP64 or PPRT_FP32 (bulk)
+  int32_t thick_mode; // DENSE_THICK_* (FP32 bulk only)
   uint32_t outputs;
   const double* mu;   // host, ascending
   const double* w;
 };
 bool dense_na_supported(int na);
-size_t dense_workspace_bytes(int na, int64_t rows, int nf);
+size_t dense_workspace_bytes(int na, int64_t rows, int nf, int precision);
 int dense_freqs_per_item(int na);
 hipError_t launch_fs_dense(const DenseLaunch& L, hipStream_t s);
 

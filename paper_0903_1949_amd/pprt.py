@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libpprt.so")
 
 FP64, FP32 = 0, 1
 BC_DIFFUSION, BC_GIVEN = 0, 1
+THICK_RULE, THICK_NEVER, THICK_ALWAYS = 0, 1, 2
 OUT_J, OUT_JMS, OUT_LSTAR, OUT_LSTAR_C = 0x01, 0x02, 0x04, 0x08
 OUT_IPLUS, OUT_IMINUS, OUT_H, OUT_IEMERG = 0x10, 0x20, 0x40, 0x80
 OUT_LSTAR_SUB, OUT_LSTAR_SUP = 0x100, 0x200
@@ -129,6 +130,9 @@ def load_library(path: str = LIB_PATH):
         "pprt_two_level_ali_step": (I, [P, C.POINTER(FsIn), C.POINTER(TwoLevel), P, P, P, P]),
         "pprt_plan_scattering_workspace_bytes": (I, [P, C.POINTER(C.c_size_t)]),
         "pprt_formal_solution_scattering": (I, [P, C.POINTER(FsIn), P, C.POINTER(FsOut), P]),
+        "pprt_plan_set_thick_mode": (I, [P, C.c_int32]),
+        "pprt_thick_counts": (I, [P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
+        "pprt_thick_counts_reset": (I, [P]),
         "pprt_plan_continuum_workspace_bytes": (I, [P, C.POINTER(C.c_size_t)]),
         "pprt_two_level_ali_step_continuum": (I, [P, C.POINTER(FsIn), C.POINTER(TwoLevel),
                                                   C.POINTER(Continuum), P, P, P, P]),
@@ -300,6 +304,15 @@ class Context:
     def set_validation(self, on: bool = True):
         """pprt_set_validation: host scan of every input before each launch."""
         self._check(self.lib.pprt_set_validation(self.h, 1 if on else 0), "set_validation")
+
+    def thick_counts(self, reset: bool = False) -> tuple[int, int]:
+        """pprt_thick_counts: (eliminations run in FP64, all eliminations) of
+        the FP32-bulk scattering path since creation or the last reset."""
+        f64, tot = C.c_uint64(0), C.c_uint64(0)
+        self._check(self.lib.pprt_thick_counts(self.h, C.byref(f64), C.byref(tot)), "thick_counts")
+        if reset:
+            self._check(self.lib.pprt_thick_counts_reset(self.h), "thick_counts_reset")
+        return int(f64.value), int(tot.value)
 
     def voigt(self, a, x):
         """pprt_voigt: H(a, x) for device float64 tensors of equal length."""
@@ -488,6 +501,11 @@ class Plan:
                                                           _ptr(gIemerg), C.byref(fg), _ptr(workspace)),
                         "formal_solution_vjp")
         return g
+
+    def set_thick_mode(self, mode: int):
+        """pprt_plan_set_thick_mode: THICK_RULE (default), THICK_NEVER or
+        THICK_ALWAYS for the FP64 eliminations of the FP32-bulk scattering path."""
+        self.ctx._check(self.lib.pprt_plan_set_thick_mode(self.h, int(mode)), "set_thick_mode")
 
     def formal_solution_scattering(self, tau, q, Sg, omega, Bbot=None, Bbot_prev=None, Itop=None,
                                    Ibot=None, out: dict | None = None, workspace=None) -> dict:

@@ -97,6 +97,9 @@ def test_null_arguments_rejected_without_device():
     assert lib.pprt_sync(None, None) == 1
     assert lib.pprt_set_stream(None, None) == 1
     assert lib.pprt_plan_workspace_bytes(None, None) == 1
+    assert lib.pprt_plan_set_thick_mode(None, 0) == 1
+    assert lib.pprt_thick_counts(None, None, None) == 1
+    assert lib.pprt_thick_counts_reset(None) == 1
     assert lib.pprt_last_error(None) == b""
     lib.pprt_destroy(None)
     lib.pprt_plan_destroy(None)

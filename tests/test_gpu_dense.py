@@ -169,11 +169,3 @@ def test_scattering_rejects_unsupported_angle_counts(gpu_ctx):
             plan.formal_solution_scattering(_dev(np.logspace(-2, 1, 4)), z + 1, z, z,
                                             Bbot=one, Bbot_prev=one)
 
-
-def test_scattering_rejects_fp32_plan(gpu_ctx):
-    plan = pprt.Plan(gpu_ctx, [4], 4, 3, precision=pprt.FP32, outputs=pprt.OUT_J)
-    z = torch.zeros((4, 3), dtype=torch.float32, device="cuda:0")
-    with pytest.raises(pprt.PprtError, match="E_UNSUPPORTED"):
-        plan.formal_solution_scattering(_dev(np.logspace(-2, 1, 4)), z + 1, z, z,
-                                        Bbot=torch.ones((1, 3), dtype=torch.float32, device="cuda:0"),
-                                        Bbot_prev=torch.ones((1, 3), dtype=torch.float32, device="cuda:0"))

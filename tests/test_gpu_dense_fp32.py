@@ -1,0 +1,187 @@
+"""GPU parity of the FP32-bulk formal solution with in-layer scattering
+(pprt_formal_solution_scattering on an FP32 plan: FP64 layer operators, FP32
+adding recursion, FP64 eliminations under the thick-layer rule) with the FP64
+oracle run on the FP32-rounded inputs, output by output, and the thick-layer
+modes and counters.
+
+Per-output contract (two metrics: `arr`, the per-array relative error with a
+floor of 1e-4 of the array's scale, and `scale`, max |a - b| / max |b|):
+  * general albedos (omega <= 0.99, and 0.9 .. 0.9999 with layers of optical
+    depth 3e-6 .. 1e5): J within 2e-6, I+ and emergent I within 1e-5, Lambda*
+    and 1 - Lambda* within 1e-6 (arr); J - S^g, H and I- within 2e-6 (scale)
+    (measured at most 8.8e-7, 3.2e-6, 1.7e-7 and 9.4e-7);
+  * the line on the nearly conservative continuum of the batch (omega up to
+    1 - 1e-4 in the line wings): J, I+, emergent I within 1e-4 (arr), Lambda*
+    and 1 - Lambda* within 2e-6 (arr), J - S^g, H and I- within 2e-5 (scale)
+    (measured at most 3.8e-5, 3.0e-7 and 3.1e-6);
+  * one operator-splitting step of the line on such a continuum: S within
+    2e-5 (measured 9.1e-6); its change is held to 1e-3 of its largest value
+    (the FP32 J - S^g carries an absolute error of about 1e-6 of S, which is
+    a large relative error where the change is small).
+The second is looser because the composite reflection of a thick,
+nearly conservative stack carries its absorption in its last digits: FP32
+composites lose it (the FP64 eliminations leave the errors as they are)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_0903_1949_amd import pprt
+from paper_0903_1949_amd import workloads as W
+from tests.conftest import rel_err
+from tests.test_gpu_dense import KEYS, _case, _oracle
+
+pytestmark = pytest.mark.gpu
+
+GENERAL = {"arr": (("J",), 2e-6), "arr2": (("Iplus", "Iemerg"), 1e-5), "arr3": (("lstar", "lstar_c"), 1e-6),
+           "scale": (("JmS", "H", "Iminus"), 2e-6)}
+CONSERVATIVE = {"arr": (("J", "Iplus", "Iemerg"), 1e-4), "arr2": (("lstar", "lstar_c"), 2e-6),
+                "scale": (("JmS", "H", "Iminus"), 2e-5)}
+
+
+def _r32(a):
+    return np.asarray(a, np.float32).astype(np.float64)
+
+
+def _scale_err(a, b):
+    b = np.asarray(b, np.float64)
+    m = np.max(np.abs(b))
+    return float(np.max(np.abs(np.asarray(a, np.float64) - b)) / m) if m > 0 else float(np.max(np.abs(a)))
+
+
+def _run(ctx, nds, na, nf, c, mode=pprt.THICK_RULE, outputs=pprt.OUT_ALL):
+    d = lambda a, dt=torch.float32: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda:0")
+    plan = pprt.Plan(ctx, nds, na, nf, precision=pprt.FP32, outputs=outputs)
+    plan.set_thick_mode(mode)
+    ctx.thick_counts(reset=True)
+    out = plan.formal_solution_scattering(d(c["tau"], torch.float64), d(c["q"]), d(c["S"]), d(c["om"]),
+                                          Bbot=d(c["Bb"]), Bbot_prev=d(c["Bp"]), Itop=d(c["Itop"]))
+    torch.cuda.synchronize()
+    counts = ctx.thick_counts(reset=True)
+    return plan, {k: out[k].double().cpu().numpy() for k in KEYS if k in out}, counts
+
+
+def _rounded(c):
+    return {k: (v if k == "tau" or v is None else _r32(v)) for k, v in c.items()}
+
+
+def _check(got, ref, contract, label):
+    errs = {"arr": {k: rel_err(got[k], ref[k]) for k in KEYS},
+            "scale": {k: _scale_err(got[k], ref[k]) for k in KEYS}}
+    print(f"  {label} arr:", " ".join(f"{k}={v:.1e}" for k, v in errs["arr"].items()), flush=True)
+    print(f"  {label} scale:", " ".join(f"{k}={v:.1e}" for k, v in errs["scale"].items()), flush=True)
+    for metric, (keys, tol) in contract.items():
+        m = "arr" if metric.startswith("arr") else "scale"
+        for k in keys:
+            assert errs[m][k] < tol, (label, m, k, errs[m][k], tol)
+
+
+def _extreme(na):
+    nds, nf = [9, 5], 5
+    rng = np.random.default_rng(41 + na)
+    parts = [W.random_slab(nd, nf, seed=41 + nd, tau_lo=1e-7, tau_hi=1e5) for nd in nds]
+    c = dict(tau=np.concatenate([p[0] for p in parts]), q=np.concatenate([p[1] for p in parts]),
+             S=np.concatenate([p[2] for p in parts]), om=rng.uniform(0.9, 0.9999, size=(sum(nds), nf)),
+             Bb=np.stack([p[3] for p in parts]), Bp=np.stack([p[4] for p in parts]),
+             Itop=rng.uniform(0, 0.3, size=(len(nds), nf, na)), Ibot=None)
+    return nds, nf, c
+
+
+def _continuum_slice(nb=3, nf=64, seed=33):
+    full = W.two_level_batch(nb=nb, nd_lo=60, nd_hi=120, nf=nf, seed=seed, cont_ratio=1e-3, eps_c=1e-4)
+    Sg = full.pfrac * full.S_trial[:, None] + full.sg_const
+    last = full.off[1:] - 1
+    c = dict(tau=full.tau, q=full.q, S=Sg, om=full.omega,
+             Bb=np.repeat(full.B[last][:, None], full.nf, 1),
+             Bp=np.repeat(full.B[last - 1][:, None], full.nf, 1),
+             Itop=np.zeros((full.nb, full.nf, full.na)), Ibot=None)
+    return [int(x) for x in full.nd], full.nf, full.na, c
+
+
+@pytest.mark.parametrize("nds,nf,na", [
+    ([2], 1, 1), ([3, 2], 3, 2), ([6], 5, 4), ([12, 5, 2], 9, 8), ([20], 17, 8), ([7, 9], 6, 16),
+])
+def test_fp32_scattering_parity(gpu_ctx, nds, nf, na):
+    seed = sum(nds) * 7 + nf + na
+    print(f"[case] fp32 scattering nds={nds} nf={nf} na={na} seed={seed}", flush=True)
+    c = _case(nds, nf, na, seed)
+    plan, got, _ = _run(gpu_ctx, nds, na, nf, c)
+    ref = _oracle(nds, _rounded(c), plan.mu, plan.w, pprt.BC_DIFFUSION)
+    _check(got, ref, GENERAL, "rule")
+
+
+@pytest.mark.parametrize("na", [8, 16])
+def test_fp32_scattering_extreme_layers(gpu_ctx, na):
+    nds, nf, c = _extreme(na)
+    print(f"[case] fp32 extreme layers nds={nds} nf={nf} na={na}", flush=True)
+    plan, got, _ = _run(gpu_ctx, nds, na, nf, c)
+    ref = _oracle(nds, _rounded(c), plan.mu, plan.w, pprt.BC_DIFFUSION)
+    _check(got, ref, GENERAL, "rule")
+
+
+def test_fp32_continuum_slice_modes(gpu_ctx):
+    """The line on the batch's scattering continuum (3 atmospheres, nd 60..120,
+    64 frequencies, 8 angles) in the three thick modes against the oracle;
+    the rule runs some but not all eliminations in FP64, NEVER none and
+    ALWAYS all, and each mode meets the conservative contract."""
+    nds, nf, na, c = _continuum_slice()
+    print(f"[case] fp32 continuum slice nds={nds} nf={nf} na={na}", flush=True)
+    ref = None
+    for mode, name in ((pprt.THICK_RULE, "rule"), (pprt.THICK_NEVER, "never"), (pprt.THICK_ALWAYS, "always")):
+        plan, got, (n64, ntot) = _run(gpu_ctx, nds, na, nf, c, mode)
+        if ref is None:
+            ref = _oracle(nds, _rounded(c), plan.mu, plan.w, pprt.BC_DIFFUSION)
+        print(f"  {name}: {n64} of {ntot} eliminations in FP64", flush=True)
+        # per wave: nd - 1 on the way down, nd + nd - 1 on the way up
+        waves_per_atm = -(-nf // (64 // na))
+        assert ntot == sum(waves_per_atm * (3 * nd - 2) for nd in nds)
+        if name == "rule":
+            assert 0 < n64 < ntot
+        elif name == "never":
+            assert n64 == 0
+        else:
+            assert n64 == ntot
+        _check(got, ref, CONSERVATIVE, name)
+
+
+def test_fp32_workspace_and_mode_validation(gpu_ctx):
+    """An FP32 plan needs 4 (na^2 + 3 na) bytes per node and frequency (no
+    stored eigen solutions), an FP64 plan 8 (2 na^2 + 4 na); modes outside
+    PPRT_THICK_* are refused."""
+    import ctypes as C
+    nd, na, nf = [30, 20], 8, 40
+    for prec, per in ((pprt.FP32, 4 * (na * na + 3 * na)), (pprt.FP64, 8 * (2 * na * na + 4 * na))):
+        plan = pprt.Plan(gpu_ctx, nd, na, nf, precision=prec, outputs=pprt.OUT_J)
+        nbytes = C.c_size_t()
+        assert plan.lib.pprt_plan_scattering_workspace_bytes(plan.h, C.byref(nbytes)) == 0
+        assert nbytes.value == sum(nd) * nf * per
+    plan = pprt.Plan(gpu_ctx, nd, na, nf, precision=pprt.FP32, outputs=pprt.OUT_J)
+    for bad in (-1, 3):
+        with pytest.raises(pprt.PprtError, match="E_INVALID_ARG"):
+            plan.set_thick_mode(bad)
+
+
+def test_fp32_continuum_step_parity(gpu_ctx):
+    """One operator-splitting step of the line on a scattering continuum with
+    an FP32 plan against the oracle's step on the FP32-rounded inputs: S and
+    its change."""
+    from tests.test_gpu_ali import _cont_device, _oracle_one_step
+    batch = W.two_level_batch(nb=3, nd_lo=8, nd_hi=40, na=8, nf=40, seed=21, cont_ratio=1e-2,
+                              eps_c=1e-2, x_max=4.0)
+    print("[case] fp32 continuum step", flush=True)
+    plan = pprt.Plan(gpu_ctx, batch.nd, batch.na, batch.nf, precision=pprt.FP32)
+    db = pprt.upload_two_level(batch, pprt.FP32)
+    pf, sc, om = _cont_device(batch, pprt.FP32)
+    S0 = batch.S_trial.copy()
+    mx = torch.zeros(batch.nb, dtype=torch.float64, device="cuda:0")
+    plan.two_level_ali_step_continuum(db.tau, db.q, db.S, db.eps, db.B, db.wphi, pf, sc, om,
+                                      db.Bbot, db.Bbot_prev, mx)
+    torch.cuda.synchronize()
+    for name in ("q", "pfrac", "sg_const", "omega"):
+        setattr(batch, name, _r32(getattr(batch, name)))
+    batch.wnu = _r32(batch.wnu * batch.phi) / batch.phi
+    ref = _oracle_one_step(batch, S0, plan.mu, plan.w, True)
+    e = rel_err(db.S.cpu().numpy(), ref)
+    e_d = rel_err(db.S.cpu().numpy() - S0, ref - S0)
+    e_ds = _scale_err(db.S.cpu().numpy() - S0, ref - S0)
+    print(f"  S {e:.2e}  dS {e_d:.2e} (per array)  {e_ds:.2e} (of its largest value)", flush=True)
+    assert e < 2e-5 and e_ds < 1e-3
