@@ -41,4 +41,8 @@ dense       omega > 0: exact layer operators by matrix exponential + doubling,
             adding recursion, dense Lambda*.
 rates       multilevel preconditioned rates and statistical equilibrium.
 grad        gradients of the emergent spectrum (complex step, central FD).
+spherical   1D spherical symmetry along impact-parameter rays.
+sph3d       3D full characteristics on a spherical voxel grid: the walk,
+            the characteristics of each direction, J, the flux vector, the
+            3^3-neighbour Lambda* and the grey operator-splitting step.
 """
