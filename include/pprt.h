@@ -696,6 +696,89 @@ pprt_status pprt_formal_solution_vjp(pprt_plan* plan, const pprt_fs_in* in,
                                      int32_t checkpoint_interval, const void* gIemerg,
                                      const pprt_fs_grad* grad, void* workspace);
 
+/* ------------------------- 3D full characteristics, spherical voxel grid */
+
+/* The paper's own method (Sect. 2: characteristics tracked through the grid
+ * from boundary to boundary, stepping voxel to neighbouring voxel, every
+ * voxel crossed by at least one per solid angle; Sect. 3.1: the spherical
+ * grid regular in theta_c and phi_c, I = 0 incident outside and I_core
+ * leaving the inner sphere; Sect. 3.2.1: the 3^3-neighbour Lambda*).
+ * Voxel (i, j, k): r[i] <= r < r[i+1], theta_c in [j pi/nt, (j+1) pi/nt),
+ * phi_c in [2 pi k/np, 2 pi (k+1)/np); index v = (i nt + j) np + k.  Opacity
+ * chi and source S are constant inside a voxel, per frequency.  Directions:
+ * mu at n_mu Gauss-Legendre nodes on (-1, 1) times n_phi azimuths (offset by
+ * half a step), weights summing to one.  Per direction the characteristics
+ * are a square lattice of parallel lines with spacing h across the direction
+ * (each started on the outer sphere, plus one leaving the inner sphere where
+ * a line meets it) and one through the centre of every voxel that no line
+ * crossed.  J_v is the path-length weighted mean of the segment-mean
+ * intensities S + (I_in - S)(1 - e^-D)/D over the characteristics that
+ * cross v, summed over directions with their weights. */
+typedef struct pprt_vox_grid {
+  int32_t nr, nt, np;    /* 1 <= nr <= 1023, 2 <= nt <= 1023, 3 <= np <= 1023  */
+  const double* r;       /* host [nr + 1], ascending by at least 1e-12 r[nr] per
+                            shell (the walk takes crossings within 1e-13 r[nr]
+                            of the current point as the surface just crossed),
+                            r[0] > 0                                            */
+} pprt_vox_grid;
+
+typedef struct pprt_vox_plan pprt_vox_plan;
+
+typedef struct pprt_vox_info {
+  int64_t nvox, ndir, nrays, nsegments;
+  int64_t ncoverage;     /* coverage characteristics (voxels no lattice line crossed) */
+  double spacing;        /* lattice spacing h                                   */
+  size_t device_bytes;   /* geometry held on the device                         */
+} pprt_vox_info;
+
+/* Builds the characteristics of every direction on the host (FP64, threaded
+ * over directions) and uploads them: per segment the packed voxel index, the
+ * path length and the mean weight (8 + 2 es bytes, es = 8 in FP64 and 4 in
+ * FP32 plans).  spacing <= 0 takes r[0] pi / (2 nt) (half an inner boundary
+ * face).  nf >= 1 frequencies.  E_INVALID_ARG for a bad grid or count,
+ * E_SHAPE when the characteristics would exceed 2^31 segments. */
+pprt_status pprt_vox_plan_create(pprt_ctx* ctx, const pprt_vox_grid* grid, int32_t n_mu, int32_t n_phi,
+                                 double spacing, int32_t nf, int32_t precision, pprt_vox_plan** out);
+pprt_status pprt_vox_plan_info(const pprt_vox_plan* plan, pprt_vox_info* info);
+/* The same characteristics on the host only (no device, no context): call
+ * with NULL arrays for the counts, then with arrays of those sizes (host):
+ * ray_seg0 [nrays + 1], ray_dir [nrays], ray_core [nrays] (1: starts on the
+ * inner sphere), seg_ijk [nseg] (i << 20 | j << 10 | k), seg_ell [nseg],
+ * seg_wn [nseg] (direction weight over the direction's path length in the
+ * voxel; 0 where a coverage characteristic does not enter the mean).
+ * E_WORKSPACE if the arrays were sized for other counts. */
+pprt_status pprt_vox_geometry_host(const pprt_vox_grid* grid, int32_t n_mu, int32_t n_phi, double spacing,
+                                   int64_t* nrays, int64_t* nseg, int64_t* ray_seg0, int32_t* ray_dir,
+                                   uint8_t* ray_core, uint32_t* seg_ijk, double* seg_ell, double* seg_wn);
+/* Directions [ndir][3] and weights [ndir] into host arrays. */
+pprt_status pprt_vox_directions(const pprt_vox_plan* plan, double* dirs, double* w);
+void pprt_vox_plan_destroy(pprt_vox_plan* plan);
+
+/* Formal solution: chi, S real [nvox][nf] (device); I_out, I_core real [nf]
+ * (device, NULL = 0) entering at the outer and leaving the inner sphere.
+ * Outputs (device, float64, overwritten): J [nvox][nf]; flux [nvox][3][nf]
+ * (Cartesian components of sum w n I_bar, NULL = not computed); lstar
+ * [nvox][27][nf] (NULL = not computed): Lambda*_{v,u} = dJ_v/dS_u for
+ * u = (i+di, j+dj, k+dk), slot (di+1) 9 + (dj+1) 3 + (dk+1), phi periodic,
+ * zero for neighbours beyond a radial boundary or a pole, followed along each
+ * characteristic through its last 8 distinct voxels.  FP64 atomic
+ * accumulation: results agree between runs to rounding, not bit for bit.
+ * Asynchronous on the context's stream. */
+pprt_status pprt_vox_formal_solution(pprt_vox_plan* plan, const void* chi, const void* S, const void* I_out,
+                                     const void* I_core, double* J, double* flux, double* lstar);
+
+/* Grey two-level operator-splitting step on every voxel and frequency with
+ * the diagonal of Lambda* (the local operator of Sect. 3.2.1):
+ *   S <- S + ((1 - eps) J + eps B - S) / (1 - (1 - eps) Lambda*_vv),
+ * S, B float64 [nvox][nf] (device; S in/out), eps float64 [nvox] (device),
+ * max_rel float64 [1] (device) <- max |dS| / |S_new|.  The workspace
+ * (pprt_vox_ali_workspace_bytes) holds J, Lambda*_vv and, in FP32 plans, S
+ * rounded to the bulk type.  Asynchronous. */
+pprt_status pprt_vox_ali_workspace_bytes(const pprt_vox_plan* plan, size_t* bytes);
+pprt_status pprt_vox_ali_step(pprt_vox_plan* plan, const void* chi, double* S, const double* B,
+                              const double* eps, const void* I_out, const void* I_core, double* max_rel,
+                              void* workspace);
+
 #ifdef __cplusplus
 }
 #endif

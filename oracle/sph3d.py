@@ -40,7 +40,8 @@ to its Papers I-II; the reading taken here:
   one among the current voxel's two spheres, two cones theta = const (the
   plane z = 0 at theta = pi/2; none on the axis) and two half-planes
   phi = const; the crossed surface names the neighbour (one index up or
-  down, phi periodic).  A line that passes the z axis (within 1e-9 of the
+  down, phi periodic); crossings closer than 1e-13 of the outer radius to the
+  current point are the surface just crossed.  A line that passes the z axis (within 1e-9 of the
   outer radius) inside a pole voxel meets all half-planes there at once; it
   goes on in the pole voxel of the direction's own azimuth.  A segment is the
   part of the line inside one voxel, of length ell.
@@ -199,7 +200,7 @@ def walk(g: Grid, p0, n, ijk, tol=None, max_steps=None):
     contains p0) to its end, and how it ends ("out" or "core")."""
     p0 = np.asarray(p0, dtype=np.float64)
     n = np.asarray(n, dtype=np.float64)
-    tol = 1e-12 * g.r[-1] if tol is None else tol
+    tol = 1e-13 * g.r[-1] if tol is None else tol
     max_steps = 8 * (g.nr + g.nt + g.np_) + 64 if max_steps is None else max_steps
     ax_tol = 1e-9 * g.r[-1]
     i, j, k = ijk

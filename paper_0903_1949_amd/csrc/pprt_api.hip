@@ -11,6 +11,7 @@
 #include <new>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "pprt_internal.h"
@@ -2320,6 +2321,265 @@ pprt_status pprt_sph_two_level_ali_step(pprt_sph_plan* p, const pprt_fs_in* in, 
   const pprt_status r = pprt_sph_two_level_moments(p, in, at, S, active, ws);
   if (r != PPRT_OK) return r;
   return pprt_sph_two_level_update(p, at, S, max_rel, active, ws);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------- 3D voxels
+struct pprt_vox_plan {
+  pprt_ctx* ctx = nullptr;
+  int nr = 0, nt = 0, np = 0, ndir = 0, nf = 0, precision = 0;
+  int64_t nvox = 0, nrays = 0, nseg = 0, nfill = 0;
+  double spacing = 0.0;
+  size_t dev_bytes = 0;
+  std::vector<double> dirs, w;
+  int64_t* d_seg0 = nullptr;
+  int32_t* d_dir = nullptr;
+  uint8_t* d_core = nullptr;
+  uint32_t* d_ijk = nullptr;
+  void* d_ell = nullptr;
+  void* d_wn = nullptr;
+  double* d_dirs = nullptr;
+};
+
+namespace {
+
+void vox_free(pprt_vox_plan* p) {
+  void* ptrs[] = {p->d_seg0, p->d_dir, p->d_core, p->d_ijk, p->d_ell, p->d_wn, p->d_dirs};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+}
+
+template <typename T>
+hipError_t vox_upload_real(const std::vector<double>& src, void** dst) {
+  hipError_t e = hipMalloc(dst, src.size() * sizeof(T) + 16);
+  if (e != hipSuccess) return e;
+  const size_t chunk = (size_t)1 << 24;
+  std::vector<T> tmp;
+  for (size_t o = 0; o < src.size(); o += chunk) {
+    const size_t n = std::min(chunk, src.size() - o);
+    tmp.resize(n);
+    for (size_t q = 0; q < n; ++q) tmp[q] = (T)src[o + q];
+    e = hipMemcpy((T*)*dst + o, tmp.data(), n * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <typename T>
+void vox_args(const pprt_vox_plan* p, const void* chi, const void* S, const void* I_out, const void* I_core,
+              double* J, double* flux, double* lstar, VoxArgs<T>& a) {
+  a.ray_seg0 = p->d_seg0; a.ray_dir = p->d_dir; a.ray_core = p->d_core; a.seg_ijk = p->d_ijk;
+  a.seg_ell = (const T*)p->d_ell; a.seg_wn = (const T*)p->d_wn; a.dirs = p->d_dirs;
+  a.chi = (const T*)chi; a.S = (const T*)S; a.I_out = (const T*)I_out; a.I_core = (const T*)I_core;
+  a.J = J; a.flux = flux; a.lstar = lstar;
+  a.nrays = p->nrays; a.nf = p->nf; a.nt = p->nt; a.np = p->np;
+  int g = 1;
+  while (g < p->nf && g < 64) g <<= 1;
+  a.group = g;
+  a.nfb = (p->nf + 63) / 64;
+}
+
+pprt_status vox_fs_launch(pprt_vox_plan* p, const void* chi, const void* S, const void* I_out,
+                          const void* I_core, double* J, double* flux, double* lstar, int mode) {
+  pprt_ctx* c = p->ctx;
+  const int64_t nvf = p->nvox * p->nf;
+  hipError_t e = launch_vox_zero(J, nvf, c->stream);
+  if (e == hipSuccess && flux) e = launch_vox_zero(flux, 3 * nvf, c->stream);
+  if (e == hipSuccess && lstar) e = launch_vox_zero(lstar, (mode == 1 ? 27 : 1) * nvf, c->stream);
+  if (e != hipSuccess) return hip_check(c, e, "voxel output clear");
+  if (p->precision == PPRT_FP64) {
+    VoxArgs<double> a{};
+    vox_args(p, chi, S, I_out, I_core, J, flux, lstar, a);
+    e = launch_vox_fs(PPRT_FP64, &a, mode, c->stream);
+  } else {
+    VoxArgs<float> a{};
+    vox_args(p, chi, S, I_out, I_core, J, flux, lstar, a);
+    e = launch_vox_fs(PPRT_FP32, &a, mode, c->stream);
+  }
+  return hip_check(c, e, "voxel formal-solution launch");
+}
+
+void vox_ali_layout(const pprt_vox_plan* p, size_t off[4]) {
+  const size_t nvf = (size_t)p->nvox * p->nf;
+  off[0] = 0;
+  off[1] = align256(nvf * sizeof(double));
+  off[2] = off[1] + align256(nvf * sizeof(double));
+  off[3] = off[2] + (p->precision == PPRT_FP64 ? 0 : align256(nvf * sizeof(float)));
+}
+
+}  // namespace
+
+extern "C" {
+
+pprt_status pprt_vox_plan_create(pprt_ctx* c, const pprt_vox_grid* grid, int32_t n_mu, int32_t n_phi,
+                                 double spacing, int32_t nf, int32_t precision, pprt_vox_plan** out) {
+  if (!c || !grid || !out) return PPRT_E_INVALID_ARG;
+  *out = nullptr;
+  if (!grid->r || grid->nr < 1 || grid->nr > 1023 || grid->nt < 2 || grid->nt > 1023 || grid->np < 3 ||
+      grid->np > 1023)
+    return fail(c, PPRT_E_INVALID_ARG, "voxel grid needs 1 <= nr <= 1023, 2 <= nt <= 1023, 3 <= np <= 1023");
+  if (!(grid->r[0] > 0.0)) return fail(c, PPRT_E_INVALID_ARG, "r[0] must be positive");
+  for (int i = 0; i < grid->nr; ++i)
+    if (!(grid->r[i + 1] - grid->r[i] >= 1e-12 * grid->r[grid->nr]))
+      return fail(c, PPRT_E_INVALID_ARG, "r must ascend by at least 1e-12 of the outer radius per shell");
+  if (n_mu < 1 || n_mu > 64 || n_phi < 1 || n_phi > 4096)
+    return fail(c, PPRT_E_INVALID_ARG, "need 1 <= n_mu <= 64 and 1 <= n_phi <= 4096");
+  if (nf < 1) return fail(c, PPRT_E_INVALID_ARG, "nf must be >= 1");
+  if (precision != PPRT_FP64 && precision != PPRT_FP32)
+    return fail(c, PPRT_E_INVALID_ARG, "precision must be PPRT_FP64 or PPRT_FP32");
+  const double h = spacing > 0.0 ? spacing : grid->r[0] * 3.14159265358979323846 / (2.0 * grid->nt);
+  // rough size: lattice lines of all directions times the radial depth crossed
+  const double R = grid->r[grid->nr];
+  const double est = (double)n_mu * n_phi * 3.14159265358979323846 * (R / h) * (R / h) *
+                     (1.0 + 2.0 * (grid->nr + grid->nt + grid->np)) / 4.0;
+  if (est > 2.0e9)
+    return fail(c, PPRT_E_SHAPE, "about %.3g segments: more than the plan supports (coarser spacing or fewer "
+                "directions)", est);
+  VoxGeom geo;
+  std::string err;
+  const int nth = (int)std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency()));
+  if (!vox_build_geometry(grid->r, grid->nr, grid->nt, grid->np, n_mu, n_phi, h, nth, geo, err))
+    return fail(c, PPRT_E_INVALID_ARG, "%s", err.c_str());
+  const int64_t nseg = (int64_t)geo.seg_ijk.size();
+  if (nseg >= ((int64_t)1 << 31)) return fail(c, PPRT_E_SHAPE, "%lld segments: more than 2^31", (long long)nseg);
+  pprt_vox_plan* p = new (std::nothrow) pprt_vox_plan;
+  if (!p) return fail(c, PPRT_E_DEVICE, "out of host memory");
+  p->ctx = c; p->nr = grid->nr; p->nt = grid->nt; p->np = grid->np; p->ndir = geo.ndir; p->nf = nf;
+  p->precision = precision; p->nvox = (int64_t)grid->nr * grid->nt * grid->np;
+  p->nrays = (int64_t)geo.ray_dir.size(); p->nseg = nseg; p->nfill = geo.nfill; p->spacing = h;
+  p->dirs = geo.dirs; p->w = geo.w;
+  const size_t es = precision == PPRT_FP64 ? sizeof(double) : sizeof(float);
+  hipError_t e = hipSetDevice(c->device);
+  auto up = [&](void** d, const void* src, size_t bytes) {
+    if (e != hipSuccess) return;
+    e = hipMalloc(d, bytes + 16);
+    if (e == hipSuccess && bytes) e = hipMemcpy(*d, src, bytes, hipMemcpyHostToDevice);
+  };
+  up((void**)&p->d_seg0, geo.ray_seg0.data(), geo.ray_seg0.size() * sizeof(int64_t));
+  up((void**)&p->d_dir, geo.ray_dir.data(), geo.ray_dir.size() * sizeof(int32_t));
+  up((void**)&p->d_core, geo.ray_core.data(), geo.ray_core.size());
+  up((void**)&p->d_ijk, geo.seg_ijk.data(), geo.seg_ijk.size() * sizeof(uint32_t));
+  up((void**)&p->d_dirs, geo.dirs.data(), geo.dirs.size() * sizeof(double));
+  if (e == hipSuccess)
+    e = precision == PPRT_FP64 ? vox_upload_real<double>(geo.seg_ell, &p->d_ell)
+                               : vox_upload_real<float>(geo.seg_ell, &p->d_ell);
+  if (e == hipSuccess)
+    e = precision == PPRT_FP64 ? vox_upload_real<double>(geo.seg_wn, &p->d_wn)
+                               : vox_upload_real<float>(geo.seg_wn, &p->d_wn);
+  if (e != hipSuccess) {
+    vox_free(p);
+    delete p;
+    return hip_check(c, e, "voxel plan upload");
+  }
+  p->dev_bytes = geo.ray_seg0.size() * 8 + geo.ray_dir.size() * 4 + geo.ray_core.size() + nseg * (4 + 2 * es) +
+                 geo.dirs.size() * 8;
+  *out = p;
+  return PPRT_OK;
+}
+
+pprt_status pprt_vox_geometry_host(const pprt_vox_grid* grid, int32_t n_mu, int32_t n_phi, double spacing,
+                                   int64_t* nrays, int64_t* nseg, int64_t* ray_seg0, int32_t* ray_dir,
+                                   uint8_t* ray_core, uint32_t* seg_ijk, double* seg_ell, double* seg_wn) {
+  if (!grid || !grid->r || !nrays || !nseg) return PPRT_E_INVALID_ARG;
+  if (grid->nr < 1 || grid->nr > 1023 || grid->nt < 2 || grid->nt > 1023 || grid->np < 3 || grid->np > 1023 ||
+      !(grid->r[0] > 0.0) || n_mu < 1 || n_mu > 64 || n_phi < 1 || n_phi > 4096)
+    return PPRT_E_INVALID_ARG;
+  for (int i = 0; i < grid->nr; ++i)
+    if (!(grid->r[i + 1] - grid->r[i] >= 1e-12 * grid->r[grid->nr])) return PPRT_E_INVALID_ARG;
+  const double h = spacing > 0.0 ? spacing : grid->r[0] * 3.14159265358979323846 / (2.0 * grid->nt);
+  VoxGeom geo;
+  std::string err;
+  const int nth = (int)std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency()));
+  if (!vox_build_geometry(grid->r, grid->nr, grid->nt, grid->np, n_mu, n_phi, h, nth, geo, err))
+    return PPRT_E_INVALID_ARG;
+  const int64_t R = (int64_t)geo.ray_dir.size(), Sg = (int64_t)geo.seg_ijk.size();
+  const bool fill = ray_seg0 || ray_dir || ray_core || seg_ijk || seg_ell || seg_wn;
+  if (fill) {
+    if (*nrays != R || *nseg != Sg) return PPRT_E_WORKSPACE;
+    if (ray_seg0) std::copy(geo.ray_seg0.begin(), geo.ray_seg0.end(), ray_seg0);
+    if (ray_dir) std::copy(geo.ray_dir.begin(), geo.ray_dir.end(), ray_dir);
+    if (ray_core) std::copy(geo.ray_core.begin(), geo.ray_core.end(), ray_core);
+    if (seg_ijk) std::copy(geo.seg_ijk.begin(), geo.seg_ijk.end(), seg_ijk);
+    if (seg_ell) std::copy(geo.seg_ell.begin(), geo.seg_ell.end(), seg_ell);
+    if (seg_wn) std::copy(geo.seg_wn.begin(), geo.seg_wn.end(), seg_wn);
+  }
+  *nrays = R;
+  *nseg = Sg;
+  return PPRT_OK;
+}
+
+pprt_status pprt_vox_plan_info(const pprt_vox_plan* p, pprt_vox_info* info) {
+  if (!p || !info) return PPRT_E_INVALID_ARG;
+  info->nvox = p->nvox; info->ndir = p->ndir; info->nrays = p->nrays; info->nsegments = p->nseg;
+  info->ncoverage = p->nfill; info->spacing = p->spacing; info->device_bytes = p->dev_bytes;
+  return PPRT_OK;
+}
+
+pprt_status pprt_vox_directions(const pprt_vox_plan* p, double* dirs, double* w) {
+  if (!p || !dirs || !w) return PPRT_E_INVALID_ARG;
+  std::copy(p->dirs.begin(), p->dirs.end(), dirs);
+  std::copy(p->w.begin(), p->w.end(), w);
+  return PPRT_OK;
+}
+
+void pprt_vox_plan_destroy(pprt_vox_plan* p) {
+  if (!p) return;
+  vox_free(p);
+  delete p;
+}
+
+pprt_status pprt_vox_formal_solution(pprt_vox_plan* p, const void* chi, const void* S, const void* I_out,
+                                     const void* I_core, double* J, double* flux, double* lstar) {
+  if (!p) return PPRT_E_INVALID_ARG;
+  pprt_ctx* c = p->ctx;
+  if (!chi || !S || !J) return fail(c, PPRT_E_INVALID_ARG, "chi, S and J are required");
+  if (c->validate & PPRT_VALIDATE_INPUTS) {
+    const int es = p->precision == PPRT_FP64 ? 8 : 4;
+    const int64_t nvf = p->nvox * p->nf;
+    pprt_status v = validate_array(c, chi, nvf, es, "chi", true);
+    if (v == PPRT_OK) v = validate_array(c, S, nvf, es, "S", false);
+    if (v == PPRT_OK) v = validate_array(c, I_out, p->nf, es, "I_out", false);
+    if (v == PPRT_OK) v = validate_array(c, I_core, p->nf, es, "I_core", false);
+    if (v != PPRT_OK) return v;
+  }
+  return vox_fs_launch(p, chi, S, I_out, I_core, J, flux, lstar, lstar ? 1 : 0);
+}
+
+pprt_status pprt_vox_ali_workspace_bytes(const pprt_vox_plan* p, size_t* bytes) {
+  if (!p || !bytes) return PPRT_E_INVALID_ARG;
+  size_t off[4];
+  vox_ali_layout(p, off);
+  *bytes = off[3];
+  return PPRT_OK;
+}
+
+pprt_status pprt_vox_ali_step(pprt_vox_plan* p, const void* chi, double* S, const double* B,
+                              const double* eps, const void* I_out, const void* I_core, double* max_rel,
+                              void* ws) {
+  if (!p) return PPRT_E_INVALID_ARG;
+  pprt_ctx* c = p->ctx;
+  if (!chi || !S || !B || !eps || !max_rel) return fail(c, PPRT_E_INVALID_ARG, "null argument");
+  if (!ws) return fail(c, PPRT_E_WORKSPACE, "workspace required (pprt_vox_ali_workspace_bytes)");
+  size_t off[4];
+  vox_ali_layout(p, off);
+  char* base = (char*)ws;
+  double* J = (double*)(base + off[0]);
+  double* Ld = (double*)(base + off[1]);
+  const int64_t nvf = p->nvox * p->nf;
+  const void* Sb = S;
+  if (p->precision != PPRT_FP64) {
+    void* St = base + off[2];
+    pprt_status r = hip_check(c, launch_vox_to_bulk(p->precision, S, St, nvf, c->stream), "S rounding");
+    if (r != PPRT_OK) return r;
+    Sb = St;
+  }
+  pprt_status r = vox_fs_launch(p, chi, Sb, I_out, I_core, J, nullptr, Ld, 2);
+  if (r != PPRT_OK) return r;
+  r = hip_check(c, launch_vox_zero(max_rel, 1, c->stream), "max_rel clear");
+  if (r != PPRT_OK) return r;
+  return hip_check(c, launch_vox_ali(J, Ld, S, B, eps, p->nvox, p->nf, (unsigned long long*)max_rel, c->stream),
+                   "voxel update launch");
 }
 
 }  // extern "C"

@@ -375,6 +375,46 @@ hipError_t launch_fs_profile(int precision, int na, int wpb, int nitems, int nbl
                              hipStream_t s, const void* args, const void* angles);
 hipError_t launch_ali_update(int nb, hipStream_t s, const AliUpdateArgs& a);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+
+// 3D full characteristics on a spherical voxel grid (vox3d.hip).
+struct VoxGeom {                   // plan-time geometry (host, FP64)
+  int nr = 0, nt = 0, np = 0, ndir = 0;
+  int64_t nfill = 0;               // coverage characteristics
+  std::vector<double> dirs, w;     // [ndir][3], [ndir]
+  std::vector<int64_t> ray_seg0;   // [nrays + 1]
+  std::vector<int32_t> ray_dir;    // [nrays]
+  std::vector<uint8_t> ray_core;   // [nrays] 1: starts on the inner sphere
+  std::vector<uint32_t> seg_ijk;   // [nseg] i << 20 | j << 10 | k
+  std::vector<double> seg_ell;     // [nseg] path length in the voxel
+  std::vector<double> seg_wn;      // [nseg] w / (direction's path length in the voxel), 0 off the mean
+};
+bool vox_build_geometry(const double* r, int nr, int nt, int np, int n_mu, int n_phi, double h, int nthreads,
+                        VoxGeom& out, std::string& err);
+template <typename T>
+struct VoxArgs {
+  const int64_t* ray_seg0;
+  const int32_t* ray_dir;
+  const uint8_t* ray_core;
+  const uint32_t* seg_ijk;
+  const T* seg_ell;
+  const T* seg_wn;
+  const double* dirs;       // [ndir][3]
+  const T* chi;             // [nvox][nf]
+  const T* S;               // [nvox][nf]
+  const T* I_out;           // [nf] or NULL (0)
+  const T* I_core;          // [nf] or NULL (0)
+  double* J;                // [nvox][nf], accumulated (zeroed by the caller)
+  double* flux;             // [nvox][3][nf] Cartesian, or NULL
+  double* lstar;            // [nvox][27][nf] (band) or [nvox][nf] (diagonal), or NULL
+  int64_t nrays;
+  int32_t nf, nfb, group, nt, np;
+};
+hipError_t launch_vox_zero(double* p, int64_t n, hipStream_t s);
+hipError_t launch_vox_fs(int precision, const void* args, int mode, hipStream_t s);
+hipError_t launch_vox_to_bulk(int precision, const double* src, void* dst, int64_t n, hipStream_t s);
+hipError_t launch_vox_ali(const double* J, const double* Ld, double* S, const double* B, const double* eps,
+                          int64_t nvox, int nf, unsigned long long* maxrel_bits, hipStream_t s);
+
 hipError_t launch_sg_assemble(int precision, const double* S, const void* p, const void* c, void* Sg,
                               int64_t rows, int nf, hipStream_t s);
 hipError_t launch_profile_reduce(int precision, const double* S, const void* JmS, const void* Lc,

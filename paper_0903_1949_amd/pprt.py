@@ -34,6 +34,15 @@ STATUS = {0: "OK", 1: "E_INVALID_ARG", 2: "E_SHAPE", 3: "E_DEVICE", 4: "E_WORKSP
           9: "E_LAUNCH"}
 
 
+class VoxGrid(C.Structure):
+    _fields_ = [("nr", C.c_int32), ("nt", C.c_int32), ("np", C.c_int32), ("r", C.POINTER(C.c_double))]
+
+
+class VoxInfo(C.Structure):
+    _fields_ = [("nvox", C.c_int64), ("ndir", C.c_int64), ("nrays", C.c_int64), ("nsegments", C.c_int64),
+                ("ncoverage", C.c_int64), ("spacing", C.c_double), ("device_bytes", C.c_size_t)]
+
+
 class PprtError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{STATUS.get(code, code)}: {msg}")
@@ -157,6 +166,16 @@ def load_library(path: str = LIB_PATH):
                                    C.POINTER(TuneReport)]),
         "pprt_emergent_intensity": (I, [P, C.POINTER(FsIn), C.c_int32, P, P]),
         "pprt_formal_solution_vjp": (I, [P, C.POINTER(FsIn), C.c_int32, P, C.POINTER(FsGrad), P]),
+        "pprt_vox_plan_create": (I, [P, C.POINTER(VoxGrid), C.c_int32, C.c_int32, D, C.c_int32, C.c_int32,
+                                     C.POINTER(P)]),
+        "pprt_vox_plan_info": (I, [P, C.POINTER(VoxInfo)]),
+        "pprt_vox_directions": (I, [P, C.POINTER(D), C.POINTER(D)]),
+        "pprt_vox_plan_destroy": (None, [P]),
+        "pprt_vox_geometry_host": (I, [C.POINTER(VoxGrid), C.c_int32, C.c_int32, D, C.POINTER(C.c_int64),
+                                       C.POINTER(C.c_int64), P, P, P, P, P, P]),
+        "pprt_vox_formal_solution": (I, [P, P, P, P, P, P, P, P]),
+        "pprt_vox_ali_workspace_bytes": (I, [P, C.POINTER(C.c_size_t)]),
+        "pprt_vox_ali_step": (I, [P, P, P, P, P, P, P, P, P]),
         "pprt_sph_plan_create": (I, [P, C.c_int32, C.POINTER(C.c_int32), C.c_int32, C.c_int32,
                                      C.c_int32, U32, C.POINTER(D), C.c_int32, C.POINTER(P)]),
         "pprt_sph_plan_destroy": (None, [P]),
@@ -1004,3 +1023,123 @@ def upload_two_level(batch, precision: int, device="cuda:0") -> DeviceBatch:
         tau=t(batch.tau, torch.float64), q=t(batch.q, dt), S=t(batch.S_trial, torch.float64),
         B=t(batch.B, torch.float64), eps=t(batch.eps, torch.float64),
         wphi=t(batch.wnu * batch.phi, dt), Bbot=t(Bb, dt), Bbot_prev=t(Bp, dt))
+
+
+def _vox_grid(r, nt, np_):
+    r = np.ascontiguousarray(np.asarray(r, dtype=np.float64))
+    return VoxGrid(int(r.shape[0] - 1), int(nt), int(np_), r.ctypes.data_as(C.POINTER(C.c_double))), r
+
+
+def vox_geometry_host(r, nt, np_, n_mu, n_phi, spacing=0.0):
+    """pprt_vox_geometry_host: the characteristics the voxel plan builds, on
+    the host only.  Returns a dict of numpy arrays (ray_seg0, ray_dir,
+    ray_core, seg_ijk, seg_ell, seg_wn)."""
+    lib = load_library()
+    g, keep = _vox_grid(r, nt, np_)
+    nr_, ns_ = C.c_int64(), C.c_int64()
+    st = lib.pprt_vox_geometry_host(C.byref(g), int(n_mu), int(n_phi), float(spacing), C.byref(nr_), C.byref(ns_),
+                                    None, None, None, None, None, None)
+    if st != 0:
+        raise PprtError(st, "vox_geometry_host")
+    out = {"ray_seg0": np.zeros(nr_.value + 1, np.int64), "ray_dir": np.zeros(nr_.value, np.int32),
+           "ray_core": np.zeros(nr_.value, np.uint8), "seg_ijk": np.zeros(ns_.value, np.uint32),
+           "seg_ell": np.zeros(ns_.value), "seg_wn": np.zeros(ns_.value)}
+    st = lib.pprt_vox_geometry_host(C.byref(g), int(n_mu), int(n_phi), float(spacing), C.byref(nr_), C.byref(ns_),
+                                    *(out[k].ctypes.data for k in ("ray_seg0", "ray_dir", "ray_core", "seg_ijk",
+                                                                   "seg_ell", "seg_wn")))
+    if st != 0:
+        raise PprtError(st, "vox_geometry_host")
+    del keep
+    return out
+
+
+class VoxPlan:
+    """3D full characteristics on a spherical voxel grid (pprt_vox_plan_create):
+    radial edges r [nr + 1] (host), nt x np angular voxels, n_mu x n_phi
+    directions, lattice spacing (<= 0: default), nf frequencies."""
+
+    def __init__(self, ctx: Context, r, nt: int, np_: int, n_mu: int, n_phi: int, nf: int,
+                 precision: int = FP32, spacing: float = 0.0):
+        import torch
+        self.ctx, self.lib = ctx, ctx.lib
+        g, self._r = _vox_grid(r, nt, np_)
+        self.nr, self.nt, self.np_ = g.nr, g.nt, g.np
+        self.nf, self.precision = int(nf), int(precision)
+        h = C.c_void_p()
+        ctx._check(self.lib.pprt_vox_plan_create(ctx.h, C.byref(g), int(n_mu), int(n_phi), float(spacing), self.nf,
+                                                 self.precision, C.byref(h)), "vox_plan_create")
+        self.h = h
+        info = VoxInfo()
+        ctx._check(self.lib.pprt_vox_plan_info(h, C.byref(info)), "vox_plan_info")
+        self.info = {k: getattr(info, k) for k, _ in VoxInfo._fields_}
+        self.nvox, self.ndir = int(info.nvox), int(info.ndir)
+        d = np.zeros((self.ndir, 3))
+        w = np.zeros(self.ndir)
+        ctx._check(self.lib.pprt_vox_directions(h, d.ctypes.data_as(C.POINTER(C.c_double)),
+                                                w.ctypes.data_as(C.POINTER(C.c_double))), "vox_directions")
+        self.dirs, self.w = d, w
+        nb = C.c_size_t()
+        ctx._check(self.lib.pprt_vox_ali_workspace_bytes(h, C.byref(nb)), "vox_ali_workspace_bytes")
+        self.ali_workspace_bytes = nb.value
+        self.dtype = torch.float64 if self.precision == FP64 else torch.float32
+        self._ws = None
+
+    _want = Plan._want
+
+    def formal_solution(self, chi, S, I_out=None, I_core=None, flux=False, lstar=False, out=None):
+        """J [nvox, nf] (float64) and, if asked, the flux [nvox, 3, nf]
+        (Cartesian) and Lambda* [nvox, 27, nf]."""
+        import torch
+        V, nf, dt = self.nvox, self.nf, self.dtype
+        self._want(chi, (V, nf), dt, "chi")
+        self._want(S, (V, nf), dt, "S")
+        if I_out is not None:
+            self._want(I_out, (nf,), dt, "I_out")
+        if I_core is not None:
+            self._want(I_core, (nf,), dt, "I_core")
+        dev = chi.device
+        out = dict(out or {})
+        out.setdefault("J", torch.empty((V, nf), dtype=torch.float64, device=dev))
+        self._want(out["J"], (V, nf), torch.float64, "J")
+        if flux:
+            out.setdefault("flux", torch.empty((V, 3, nf), dtype=torch.float64, device=dev))
+            self._want(out["flux"], (V, 3, nf), torch.float64, "flux")
+        if lstar:
+            out.setdefault("lstar", torch.empty((V, 27, nf), dtype=torch.float64, device=dev))
+            self._want(out["lstar"], (V, 27, nf), torch.float64, "lstar")
+        self.ctx._check(self.lib.pprt_vox_formal_solution(
+            self.h, _ptr(chi), _ptr(S), _ptr(I_out), _ptr(I_core), _ptr(out["J"]),
+            _ptr(out.get("flux") if flux else None), _ptr(out.get("lstar") if lstar else None)),
+            "vox_formal_solution")
+        return out
+
+    def ali_step(self, chi, S, B, eps, max_rel, I_out=None, I_core=None, workspace=None):
+        """pprt_vox_ali_step: S (float64 [nvox, nf]) in place; max_rel float64 [1]."""
+        import torch
+        V, nf, dt = self.nvox, self.nf, self.dtype
+        self._want(chi, (V, nf), dt, "chi")
+        self._want(S, (V, nf), torch.float64, "S")
+        self._want(B, (V, nf), torch.float64, "B")
+        self._want(eps, (V,), torch.float64, "eps")
+        self._want(max_rel, (1,), torch.float64, "max_rel")
+        if I_out is not None:
+            self._want(I_out, (nf,), dt, "I_out")
+        if I_core is not None:
+            self._want(I_core, (nf,), dt, "I_core")
+        if workspace is None:
+            if self._ws is None:
+                self._ws = torch.empty(max(self.ali_workspace_bytes, 256), dtype=torch.uint8, device=S.device)
+            workspace = self._ws
+        self.ctx._check(self.lib.pprt_vox_ali_step(self.h, _ptr(chi), _ptr(S), _ptr(B), _ptr(eps), _ptr(I_out),
+                                                   _ptr(I_core), _ptr(max_rel), _ptr(workspace)), "vox_ali_step")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pprt_vox_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -521,3 +521,59 @@ def gradient_case(nd=256, na=16, nf=4096, tau_lo=1e-4, tau_hi=1e4, teff=5800.0,
     B = nu[None, :] ** 3 / np.expm1(x)
     B = B / B.max()
     return GradientCase(tau=tau, c=c, f=f, B=B, nu=nu, na=na)
+
+
+@dataclass
+class VoxelSphere:
+    """A sphere on a 3D spherical voxel grid (r, theta_c, phi_c): radial edges
+    r [nr + 1], opacity chi [nvox, nf] and thermal source B [nvox, nf] per
+    voxel (voxel v = (i nt + j) np + k), scattering eps [nvox]."""
+    r: np.ndarray
+    nt: int
+    np_: int
+    chi: np.ndarray
+    B: np.ndarray
+    eps: np.ndarray
+
+    @property
+    def nvox(self):
+        return self.chi.shape[0]
+
+    @property
+    def nf(self):
+        return self.chi.shape[1]
+
+
+def voxel_sphere(nr=65, nt=33, np_=65, nf=32, r_in=1.0, r_out=2.0, tau_min=1e-4, tau_max=1e8,
+                 continuum="r6", line_ratio=0.0, eps=1e-4, B=1.0, lumpy=0.0, seed=0):
+    """The test sphere of the paper's Sect. 3.1 on a voxel grid.  Radial
+    edges logarithmic in the reference optical depth from tau_max at r_in to
+    tau_min at the last inner edge (0 at r_out); the reference opacity per
+    shell is the mean over the shell, dtau/dr, of chi = C / r^6 ("r6",
+    C fixed by the tau range) or of a constant ("const").  nf frequencies
+    across a Doppler line: chi_k = chi_ref (1 + line_ratio phi_k) with phi
+    normalised to peak 1 (line_ratio 0: grey).  lumpy > 0 multiplies each
+    voxel's opacity by a seeded lognormal factor of that sigma (a 3D
+    structure).  B constant, eps per voxel."""
+    if continuum == "r6":
+        C = 5.0 * tau_max / (r_in ** -5 - r_out ** -5)
+        taus = np.logspace(np.log10(tau_max), np.log10(tau_min), nr)
+        r = np.concatenate([(5.0 * taus / C + r_out ** -5) ** -0.2, [r_out]])
+        r[0] = r_in
+    else:
+        taus = np.logspace(np.log10(tau_max), np.log10(tau_min), nr)
+        chi0 = tau_max / (r_out - r_in)
+        r = np.concatenate([r_out - taus / chi0, [r_out]])
+        r[0] = r_in
+    tau_e = np.concatenate([taus, [0.0]])
+    chi_shell = (tau_e[:-1] - tau_e[1:]) / (r[1:] - r[:-1])
+    x = doppler_grid(nf)[0]
+    phi = np.exp(-x * x)
+    prof = 1.0 + line_ratio * phi
+    nvox = nr * nt * np_
+    chi = np.repeat(chi_shell, nt * np_)[:, None] * prof[None, :]
+    if lumpy > 0.0:
+        rng = np.random.default_rng(seed)
+        chi = chi * rng.lognormal(0.0, lumpy, size=(nvox, 1))
+    return VoxelSphere(r=r, nt=nt, np_=np_, chi=chi, B=np.full((nvox, nf), float(B)),
+                       eps=np.full(nvox, float(eps)))
