@@ -564,12 +564,17 @@ pprt_status pprt_voigt(pprt_ctx* ctx, int64_t n, const double* a, const double* 
  * with HIP events on the context stream (best of four launches).  `scratch`
  * is caller-owned device memory: at least n_CU * 16 * 256 * 8 bytes; the
  * copy is measured (half the buffer copied to the other half) when it holds
- * at least 128 MiB, else copy_gbs = 0.  Synchronises the stream. */
+ * at least 128 MiB, else copy_gbs = 0.  The atomic rates (coalesced adds of
+ * rows of 32 values at hashed rows of an array of up to 139425 rows, the
+ * pattern of the 3D formal solution) need 32 x 8 x 1024 bytes, else 0.
+ * Synchronises the stream. */
 typedef struct pprt_peaks {
   double fp32_tflops;
   double fp64_tflops;
   double exp2_trate;     /* 1e12 exp2 per second */
   double copy_gbs;
+  double atomic_f64_gadds;   /* 1e9 FP64 atomic adds per second */
+  double atomic_f32_gadds;   /* 1e9 FP32 atomic adds per second */
 } pprt_peaks;
 pprt_status pprt_measure_peaks(pprt_ctx* ctx, void* scratch, size_t bytes, pprt_peaks* out);
 
@@ -761,9 +766,12 @@ void pprt_vox_plan_destroy(pprt_vox_plan* plan);
  * [nvox][27][nf] (NULL = not computed): Lambda*_{v,u} = dJ_v/dS_u for
  * u = (i+di, j+dj, k+dk), slot (di+1) 9 + (dj+1) 3 + (dk+1), phi periodic,
  * zero for neighbours beyond a radial boundary or a pole, followed along each
- * characteristic through its last 8 distinct voxels.  FP64 atomic
- * accumulation: results agree between runs to rounding, not bit for bit.
- * Asynchronous on the context's stream. */
+ * characteristic through its last 8 distinct voxels.  Accumulation by
+ * atomic adds: FP64 plans and the Lambda* band in FP64; in FP32 plans J (and
+ * the flux in FP64) as FP32 sums over blocks of 64 directions added into
+ * the FP64 output.  Results agree between runs to rounding, not bit for bit.
+ * The plan holds 2 x 4 nvox nf bytes of block sums in FP32 plans.
+ * Asynchronous on the context's stream; calls on one plan must not overlap. */
 pprt_status pprt_vox_formal_solution(pprt_vox_plan* plan, const void* chi, const void* S, const void* I_out,
                                      const void* I_core, double* J, double* flux, double* lstar);
 

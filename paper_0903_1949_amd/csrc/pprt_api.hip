@@ -1896,8 +1896,11 @@ pprt_status pprt_measure_peaks(pprt_ctx* c, void* scratch, size_t bytes, pprt_pe
   if (r != PPRT_OK) return r;
   if (bytes < (size_t)ncu * 16 * 256 * sizeof(double))
     return fail(c, PPRT_E_WORKSPACE, "scratch must hold at least %zu bytes", (size_t)ncu * 16 * 256 * sizeof(double));
-  return hip_check(c, measure_peaks(ncu, scratch, bytes, c->stream, &out->fp32_tflops, &out->fp64_tflops,
-                                    &out->exp2_trate, &out->copy_gbs), "peak kernels");
+  r = hip_check(c, measure_peaks(ncu, scratch, bytes, c->stream, &out->fp32_tflops, &out->fp64_tflops,
+                                 &out->exp2_trate, &out->copy_gbs), "peak kernels");
+  if (r != PPRT_OK) return r;
+  return hip_check(c, measure_atomic_rates(ncu, scratch, bytes, c->stream, &out->atomic_f64_gadds,
+                                           &out->atomic_f32_gadds), "atomic rate kernels");
 }
 
 pprt_status pprt_voigt(pprt_ctx* c, int64_t n, const double* a, const double* x, double* H) {
@@ -2333,6 +2336,8 @@ struct pprt_vox_plan {
   double spacing = 0.0;
   size_t dev_bytes = 0;
   std::vector<double> dirs, w;
+  std::vector<int64_t> dir_ray0;   // [ndir + 1] first characteristic of each direction
+  float* d_part = nullptr;         // FP32 plans: block sums of J and Lambda*_vv [2][nvox][nf]
   int64_t* d_seg0 = nullptr;
   int32_t* d_dir = nullptr;
   uint8_t* d_core = nullptr;
@@ -2344,8 +2349,10 @@ struct pprt_vox_plan {
 
 namespace {
 
+constexpr int kVoxDirBlock = 64;   // directions per FP32 partial sum (FP32 plans)
+
 void vox_free(pprt_vox_plan* p) {
-  void* ptrs[] = {p->d_seg0, p->d_dir, p->d_core, p->d_ijk, p->d_ell, p->d_wn, p->d_dirs};
+  void* ptrs[] = {p->d_seg0, p->d_dir, p->d_core, p->d_ijk, p->d_ell, p->d_wn, p->d_dirs, p->d_part};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
 }
@@ -2366,14 +2373,14 @@ hipError_t vox_upload_real(const std::vector<double>& src, void** dst) {
   return hipSuccess;
 }
 
-template <typename T>
+template <typename T, typename A>
 void vox_args(const pprt_vox_plan* p, const void* chi, const void* S, const void* I_out, const void* I_core,
-              double* J, double* flux, double* lstar, VoxArgs<T>& a) {
+              A* J, double* flux, A* lstar, int64_t ray0, int64_t ray1, VoxArgs<T, A>& a) {
   a.ray_seg0 = p->d_seg0; a.ray_dir = p->d_dir; a.ray_core = p->d_core; a.seg_ijk = p->d_ijk;
   a.seg_ell = (const T*)p->d_ell; a.seg_wn = (const T*)p->d_wn; a.dirs = p->d_dirs;
   a.chi = (const T*)chi; a.S = (const T*)S; a.I_out = (const T*)I_out; a.I_core = (const T*)I_core;
   a.J = J; a.flux = flux; a.lstar = lstar;
-  a.nrays = p->nrays; a.nf = p->nf; a.nt = p->nt; a.np = p->np;
+  a.ray0 = ray0; a.nrays = ray1 - ray0; a.nf = p->nf; a.nt = p->nt; a.np = p->np;
   int g = 1;
   while (g < p->nf && g < 64) g <<= 1;
   a.group = g;
@@ -2389,13 +2396,27 @@ pprt_status vox_fs_launch(pprt_vox_plan* p, const void* chi, const void* S, cons
   if (e == hipSuccess && lstar) e = launch_vox_zero(lstar, (mode == 1 ? 27 : 1) * nvf, c->stream);
   if (e != hipSuccess) return hip_check(c, e, "voxel output clear");
   if (p->precision == PPRT_FP64) {
-    VoxArgs<double> a{};
-    vox_args(p, chi, S, I_out, I_core, J, flux, lstar, a);
-    e = launch_vox_fs(PPRT_FP64, &a, mode, c->stream);
+    VoxArgs<double, double> a{};
+    vox_args(p, chi, S, I_out, I_core, J, flux, lstar, 0, p->nrays, a);
+    e = launch_vox_fs(PPRT_FP64, false, &a, mode, c->stream);
+  } else if (mode == 1) {             // the full band: FP64 accumulation
+    VoxArgs<float, double> a{};
+    vox_args(p, chi, S, I_out, I_core, J, flux, lstar, 0, p->nrays, a);
+    e = launch_vox_fs(PPRT_FP32, false, &a, mode, c->stream);
   } else {
-    VoxArgs<float> a{};
-    vox_args(p, chi, S, I_out, I_core, J, flux, lstar, a);
-    e = launch_vox_fs(PPRT_FP32, &a, mode, c->stream);
+    // FP32 sums over blocks of kVoxDirBlock directions, each added into the FP64 outputs
+    float* pJ = p->d_part;
+    float* pL = p->d_part + nvf;
+    for (int d0 = 0; d0 < p->ndir && e == hipSuccess; d0 += kVoxDirBlock) {
+      const int d1 = std::min(p->ndir, d0 + kVoxDirBlock);
+      e = launch_vox_zero32(pJ, (mode == 2 ? 2 : 1) * nvf, c->stream);
+      VoxArgs<float, float> a{};
+      vox_args(p, chi, S, I_out, I_core, pJ, flux, mode == 2 ? pL : (float*)nullptr, p->dir_ray0[d0],
+               p->dir_ray0[d1], a);
+      if (e == hipSuccess) e = launch_vox_fs(PPRT_FP32, true, &a, mode, c->stream);
+      if (e == hipSuccess) e = launch_vox_flush(pJ, J, nvf, c->stream);
+      if (e == hipSuccess && mode == 2) e = launch_vox_flush(pL, lstar, nvf, c->stream);
+    }
   }
   return hip_check(c, e, "voxel formal-solution launch");
 }
@@ -2449,18 +2470,23 @@ pprt_status pprt_vox_plan_create(pprt_ctx* c, const pprt_vox_grid* grid, int32_t
   p->precision = precision; p->nvox = (int64_t)grid->nr * grid->nt * grid->np;
   p->nrays = (int64_t)geo.ray_dir.size(); p->nseg = nseg; p->nfill = geo.nfill; p->spacing = h;
   p->dirs = geo.dirs; p->w = geo.w;
+  p->dir_ray0.assign(geo.ndir + 1, p->nrays);
+  for (int64_t q = p->nrays - 1; q >= 0; --q) p->dir_ray0[geo.ray_dir[q]] = q;
+  for (int d = geo.ndir - 1; d >= 0; --d)       // a direction without characteristics starts where the next does
+    if (p->dir_ray0[d] > p->dir_ray0[d + 1]) p->dir_ray0[d] = p->dir_ray0[d + 1];
   const size_t es = precision == PPRT_FP64 ? sizeof(double) : sizeof(float);
   hipError_t e = hipSetDevice(c->device);
   auto up = [&](void** d, const void* src, size_t bytes) {
     if (e != hipSuccess) return;
     e = hipMalloc(d, bytes + 16);
-    if (e == hipSuccess && bytes) e = hipMemcpy(*d, src, bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess && bytes && src) e = hipMemcpy(*d, src, bytes, hipMemcpyHostToDevice);
   };
   up((void**)&p->d_seg0, geo.ray_seg0.data(), geo.ray_seg0.size() * sizeof(int64_t));
   up((void**)&p->d_dir, geo.ray_dir.data(), geo.ray_dir.size() * sizeof(int32_t));
   up((void**)&p->d_core, geo.ray_core.data(), geo.ray_core.size());
   up((void**)&p->d_ijk, geo.seg_ijk.data(), geo.seg_ijk.size() * sizeof(uint32_t));
   up((void**)&p->d_dirs, geo.dirs.data(), geo.dirs.size() * sizeof(double));
+  if (precision == PPRT_FP32) up((void**)&p->d_part, nullptr, 2 * (size_t)p->nvox * nf * sizeof(float));
   if (e == hipSuccess)
     e = precision == PPRT_FP64 ? vox_upload_real<double>(geo.seg_ell, &p->d_ell)
                                : vox_upload_real<float>(geo.seg_ell, &p->d_ell);
@@ -2473,7 +2499,7 @@ pprt_status pprt_vox_plan_create(pprt_ctx* c, const pprt_vox_grid* grid, int32_t
     return hip_check(c, e, "voxel plan upload");
   }
   p->dev_bytes = geo.ray_seg0.size() * 8 + geo.ray_dir.size() * 4 + geo.ray_core.size() + nseg * (4 + 2 * es) +
-                 geo.dirs.size() * 8;
+                 geo.dirs.size() * 8 + (precision == PPRT_FP32 ? 2 * (size_t)p->nvox * nf * sizeof(float) : 0);
   *out = p;
   return PPRT_OK;
 }

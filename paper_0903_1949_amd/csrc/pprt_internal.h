@@ -390,7 +390,7 @@ struct VoxGeom {                   // plan-time geometry (host, FP64)
 };
 bool vox_build_geometry(const double* r, int nr, int nt, int np, int n_mu, int n_phi, double h, int nthreads,
                         VoxGeom& out, std::string& err);
-template <typename T>
+template <typename T, typename A = double>   // A: accumulator type of J and Lambda*
 struct VoxArgs {
   const int64_t* ray_seg0;
   const int32_t* ray_dir;
@@ -403,14 +403,18 @@ struct VoxArgs {
   const T* S;               // [nvox][nf]
   const T* I_out;           // [nf] or NULL (0)
   const T* I_core;          // [nf] or NULL (0)
-  double* J;                // [nvox][nf], accumulated (zeroed by the caller)
+  A* J;                     // [nvox][nf], accumulated (zeroed by the caller)
   double* flux;             // [nvox][3][nf] Cartesian, or NULL
-  double* lstar;            // [nvox][27][nf] (band) or [nvox][nf] (diagonal), or NULL
-  int64_t nrays;
+  A* lstar;                 // [nvox][27][nf] (band) or [nvox][nf] (diagonal), or NULL
+  int64_t ray0;             // first characteristic of this launch
+  int64_t nrays;            // characteristics of this launch
   int32_t nf, nfb, group, nt, np;
 };
 hipError_t launch_vox_zero(double* p, int64_t n, hipStream_t s);
-hipError_t launch_vox_fs(int precision, const void* args, int mode, hipStream_t s);
+hipError_t launch_vox_fs(int precision, bool acc32, const void* args, int mode, hipStream_t s);
+hipError_t launch_vox_zero32(float* p, int64_t n, hipStream_t s);
+// dst[i] += src[i] (FP32 partial sums into the FP64 outputs)
+hipError_t launch_vox_flush(const float* src, double* dst, int64_t n, hipStream_t s);
 hipError_t launch_vox_to_bulk(int precision, const double* src, void* dst, int64_t n, hipStream_t s);
 hipError_t launch_vox_ali(const double* J, const double* Ld, double* S, const double* B, const double* eps,
                           int64_t nvox, int nf, unsigned long long* maxrel_bits, hipStream_t s);
@@ -426,5 +430,7 @@ bool na_supported(int na);
 // Measured peaks (peaks.hip): FP32 / FP64 FMA TFLOP/s, exp2 Texp/s, copy GB/s.
 hipError_t measure_peaks(int n_cu, void* scratch, size_t bytes, hipStream_t s, double* fp32,
                          double* fp64, double* exp_rate, double* copy_gbs);
+hipError_t measure_atomic_rates(int n_cu, void* scratch, size_t bytes, hipStream_t s, double* f64_gadds,
+                                double* f32_gadds);
 
 }  // namespace pprt

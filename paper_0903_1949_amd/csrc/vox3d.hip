@@ -44,7 +44,13 @@
 // segment stream of a characteristic is read once for all its frequencies;
 // chi and S are read as rows over frequency (the voxel's row stays in L2
 // across the characteristics of nearby directions).  J, the flux and
-// Lambda* accumulate in FP64 with the hardware's atomic add.
+// Lambda* accumulate with the hardware's atomic add, one per segment and
+// frequency; that add rate bounds the kernel (about 1.9e11 FP64 or 3.3e11
+// FP32 adds per second on the whole chip for rows of 32 to 64 values).
+// FP32 plans therefore accumulate J (and the diagonal of Lambda* in the
+// operator-splitting step) in FP32 over blocks of 64 directions and add
+// each block's sums into the FP64 outputs; FP64 plans and the full band
+// accumulate in FP64 directly.
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -383,16 +389,21 @@ __device__ __forceinline__ float exp_neg(float D) { return expf(-D); }
 
 constexpr int kWin = 8;   // Lambda* window: distinct voxels followed per characteristic
 
-template <typename T, int MODE>   // MODE 0: J (+flux); 1: J + Lambda* band; 2: J + Lambda*_vv only
-__global__ __launch_bounds__(256) void k_vox_fs(VoxArgs<T> a) {
+// MODE 0: J (+flux); 1: J + Lambda* band; 2: J + Lambda*_vv only.  The
+// segments are taken P at a time: their records, then their voxels' chi and
+// S rows, are loaded together before the sequential update, so each batch
+// waits for two memory round trips instead of two per segment.
+template <typename T, typename A, int MODE, int P>
+__global__ __launch_bounds__(256) void k_vox_fs(VoxArgs<T, A> a) {
   const int lane = (int)(threadIdx.x & 63);
   const int wave = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
   const int G = a.group;                     // lanes per characteristic
   const int per_wave = 64 / G;
   const int fb = wave % a.nfb;               // frequency block
-  const int64_t ray = (int64_t)(wave / a.nfb) * per_wave + lane / G;
+  const int64_t rl = (int64_t)(wave / a.nfb) * per_wave + lane / G;
   const int kf = fb * 64 + lane % G;
-  if (ray >= a.nrays || kf >= a.nf) return;
+  if (rl >= a.nrays || kf >= a.nf) return;
+  const int64_t ray = a.ray0 + rl;
   const int nf = a.nf;
   const int64_t s0 = a.ray_seg0[ray], s1 = a.ray_seg0[ray + 1];
   const int d = a.ray_dir[ray];
@@ -406,72 +417,97 @@ __global__ __launch_bounds__(256) void k_vox_fs(VoxArgs<T> a) {
 #pragma unroll
     for (int q = 0; q < kWin; ++q) { wid[q] = 0xffffffffu; wder[q] = (T)0; wage[q] = -1; }
   }
-  for (int64_t s = s0; s < s1; ++s) {
-    const uint32_t ijk = a.seg_ijk[s];
-    const T ell = a.seg_ell[s];
-    const T wn = a.seg_wn[s];
-    const int v = vox_index(ijk, a.nt, a.np);
-    const T chi = a.chi[(int64_t)v * nf + kf];
-    const T S = a.S[(int64_t)v * nf + kf];
-    const T D = chi * ell;
-    const T e = exp_neg(D);
-    const T ps = psi_d(D);
-    const T Ib = S + (I - S) * ps;
-    const double f = (double)wn * (double)ell;
-    if (f != 0.0) {
-      unsafeAtomicAdd(a.J + (int64_t)v * nf + kf, f * (double)Ib);
-      if (a.flux) {
-        double* F = a.flux + (int64_t)v * 3 * nf + kf;
-        unsafeAtomicAdd(F, f * (double)Ib * nx);
-        unsafeAtomicAdd(F + nf, f * (double)Ib * ny);
-        unsafeAtomicAdd(F + 2 * nf, f * (double)Ib * nz);
-      }
-    }
-    if constexpr (MODE != 0) {
-      // dI_bar/dS_u = psi dI_in/dS_u (+ 1 - psi for u = v); dI_out/dS_u = e dI_in/dS_u (+ 1 - e);
-      // MODE 2 accumulates the diagonal (u = v) alone
-      int self = -1;
+  for (int64_t sb = s0; sb < s1; sb += P) {
+    const int n = (int)(s1 - sb < P ? s1 - sb : P);
+    uint32_t ijkq[P];
+    T ellq[P], wnq[P], chiq[P], Sq[P];
+    int vq[P];
 #pragma unroll
-      for (int q = 0; q < kWin; ++q) {
-        if (wage[q] >= 0) {
-          if (wid[q] == ijk) self = q;
-          const int slot = MODE == 1 ? nbr_slot(ijk, wid[q], a.np) : (wid[q] == ijk ? 13 : -1);
-          if (slot >= 0 && f != 0.0) {
-            const T dv = ps * wder[q] + (wid[q] == ijk ? (T)1 - ps : (T)0);
-            double* Lp = MODE == 1 ? a.lstar + ((int64_t)v * 27 + slot) * nf + kf : a.lstar + (int64_t)v * nf + kf;
-            unsafeAtomicAdd(Lp, f * (double)dv);
+    for (int q = 0; q < P; ++q)
+      if (q < n) {
+        ijkq[q] = a.seg_ijk[sb + q];
+        ellq[q] = a.seg_ell[sb + q];
+        wnq[q] = a.seg_wn[sb + q];
+      }
+#pragma unroll
+    for (int q = 0; q < P; ++q)
+      if (q < n) {
+        vq[q] = vox_index(ijkq[q], a.nt, a.np);
+        chiq[q] = a.chi[(int64_t)vq[q] * nf + kf];
+        Sq[q] = a.S[(int64_t)vq[q] * nf + kf];
+      }
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      if (q >= n) break;
+      const uint32_t ijk = ijkq[q];
+      const T ell = ellq[q];
+      const int v = vq[q];
+      const T S = Sq[q];
+      const T D = chiq[q] * ell;
+      const T e = exp_neg(D);
+      const T ps = psi_d(D);
+      const T Ib = S + (I - S) * ps;
+      const double f = (double)wnq[q] * (double)ell;
+      if (f != 0.0) {
+        unsafeAtomicAdd(a.J + (int64_t)v * nf + kf, (A)(f * (double)Ib));
+        if (a.flux) {
+          double* F = a.flux + (int64_t)v * 3 * nf + kf;
+          unsafeAtomicAdd(F, f * (double)Ib * nx);
+          unsafeAtomicAdd(F + nf, f * (double)Ib * ny);
+          unsafeAtomicAdd(F + 2 * nf, f * (double)Ib * nz);
+        }
+      }
+      if constexpr (MODE != 0) {
+        // dI_bar/dS_u = psi dI_in/dS_u (+ 1 - psi for u = v); dI_out/dS_u = e dI_in/dS_u (+ 1 - e);
+        // MODE 2 accumulates the diagonal (u = v) alone
+        int self = -1;
+#pragma unroll
+        for (int w = 0; w < kWin; ++w) {
+          if (wage[w] >= 0) {
+            if (wid[w] == ijk) self = w;
+            const int slot = MODE == 1 ? nbr_slot(ijk, wid[w], a.np) : (wid[w] == ijk ? 13 : -1);
+            if (slot >= 0 && f != 0.0) {
+              const T dv = ps * wder[w] + (wid[w] == ijk ? (T)1 - ps : (T)0);
+              A* Lp = MODE == 1 ? a.lstar + ((int64_t)v * 27 + slot) * nf + kf : a.lstar + (int64_t)v * nf + kf;
+              unsafeAtomicAdd(Lp, (A)(f * (double)dv));
+            }
           }
         }
-      }
-      if (self < 0 && f != 0.0) {
-        double* Lp = MODE == 1 ? a.lstar + ((int64_t)v * 27 + 13) * nf + kf : a.lstar + (int64_t)v * nf + kf;
-        unsafeAtomicAdd(Lp, f * (double)((T)1 - ps));
-      }
-      // carry the window: attenuate, then (re)enter v as the most recent
-      int oldest = 0, oldest_age = 0x7fffffff;
-#pragma unroll
-      for (int q = 0; q < kWin; ++q) {
-        wder[q] *= e;
-        if (wage[q] < oldest_age) { oldest_age = wage[q]; oldest = q; }
-      }
-      const int age = (int)(s - s0);
-      const int q0 = self >= 0 ? self : oldest;
-#pragma unroll
-      for (int q = 0; q < kWin; ++q)
-        if (q == q0) {
-          wder[q] = (self >= 0 ? wder[q] : (T)0) + ((T)1 - e);
-          wid[q] = ijk;
-          wage[q] = age;
+        if (self < 0 && f != 0.0) {
+          A* Lp = MODE == 1 ? a.lstar + ((int64_t)v * 27 + 13) * nf + kf : a.lstar + (int64_t)v * nf + kf;
+          unsafeAtomicAdd(Lp, (A)(f * (double)((T)1 - ps)));
         }
+        // carry the window: attenuate, then (re)enter v as the most recent
+        int oldest = 0, oldest_age = 0x7fffffff;
+#pragma unroll
+        for (int w = 0; w < kWin; ++w) {
+          wder[w] *= e;
+          if (wage[w] < oldest_age) { oldest_age = wage[w]; oldest = w; }
+        }
+        const int age = (int)(sb + q - s0);
+        const int w0 = self >= 0 ? self : oldest;
+#pragma unroll
+        for (int w = 0; w < kWin; ++w)
+          if (w == w0) {
+            wder[w] = (self >= 0 ? wder[w] : (T)0) + ((T)1 - e);
+            wid[w] = ijk;
+            wage[w] = age;
+          }
+      }
+      I = S + (I - S) * e;
     }
-    I = S + (I - S) * e;
   }
 }
 
 template <typename T>
-__global__ void k_vox_fill(double* p, int64_t n) {
+__global__ void k_vox_fill(T* p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0.0;
+  if (i < n) p[i] = (T)0;
+}
+
+__global__ void k_vox_flush(const float* src, double* dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] += (double)src[i];
 }
 
 // grey two-level operator splitting per voxel and frequency:
@@ -499,15 +535,16 @@ __global__ void k_to_bulk(const double* src, T* dst, int64_t n) {
   if (i < n) dst[i] = (T)src[i];
 }
 
-template <typename T>
-hipError_t run_vox_fs(const VoxArgs<T>& a, int mode, hipStream_t s) {
+template <typename T, typename A>
+hipError_t run_vox_fs(const VoxArgs<T, A>& a, int mode, hipStream_t s) {
   const int64_t per_wave = 64 / a.group;
   const int64_t waves = ((a.nrays + per_wave - 1) / per_wave) * a.nfb;
   const int64_t blocks = (waves + 3) / 4;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  if (mode == 1) hipLaunchKernelGGL((k_vox_fs<T, 1>), dim3((unsigned)blocks), dim3(256), 0, s, a);
-  else if (mode == 2) hipLaunchKernelGGL((k_vox_fs<T, 2>), dim3((unsigned)blocks), dim3(256), 0, s, a);
-  else hipLaunchKernelGGL((k_vox_fs<T, 0>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+  if (blocks == 0) return hipSuccess;
+  if (mode == 1) hipLaunchKernelGGL((k_vox_fs<T, A, 1, 4>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+  else if (mode == 2) hipLaunchKernelGGL((k_vox_fs<T, A, 2, 4>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((k_vox_fs<T, A, 0, 8>), dim3((unsigned)blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -519,9 +556,22 @@ hipError_t launch_vox_zero(double* p, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_vox_fs(int precision, const void* args, int mode, hipStream_t s) {
-  return precision == PPRT_FP64 ? run_vox_fs(*static_cast<const VoxArgs<double>*>(args), mode, s)
-                                : run_vox_fs(*static_cast<const VoxArgs<float>*>(args), mode, s);
+hipError_t launch_vox_zero32(float* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_vox_fill<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_vox_flush(const float* src, double* dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_vox_flush, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_vox_fs(int precision, bool acc32, const void* args, int mode, hipStream_t s) {
+  if (precision == PPRT_FP64) return run_vox_fs(*static_cast<const VoxArgs<double, double>*>(args), mode, s);
+  if (acc32) return run_vox_fs(*static_cast<const VoxArgs<float, float>*>(args), mode, s);
+  return run_vox_fs(*static_cast<const VoxArgs<float, double>*>(args), mode, s);
 }
 
 hipError_t launch_vox_to_bulk(int precision, const double* src, void* dst, int64_t n, hipStream_t s) {

@@ -81,7 +81,8 @@ class TuneReport(C.Structure):
 
 class Peaks(C.Structure):
     _fields_ = [("fp32_tflops", C.c_double), ("fp64_tflops", C.c_double),
-                ("exp2_trate", C.c_double), ("copy_gbs", C.c_double)]
+                ("exp2_trate", C.c_double), ("copy_gbs", C.c_double),
+                ("atomic_f64_gadds", C.c_double), ("atomic_f32_gadds", C.c_double)]
 
 
 class TwoLevel(C.Structure):
