@@ -207,16 +207,20 @@ pprt_status pprt_formal_solution(pprt_plan* plan, const pprt_fs_in* in, pprt_fs_
  * exactly (discrete-ordinate eigen solution, no growing exponentials), layers
  * are combined by the adding method top-down and bottom-up, and every node
  * gets I+-, J, J - S^g, H and the exact diagonal Lambda*_dd = dJ(d)/dS^g(d)
- * with 1 - Lambda*.  na in {1, 2, 4, 8, 16} (E_UNSUPPORTED otherwise).
+ * with 1 - Lambda*.  na in {1, 2, 4, 8, 16}, and 32 in FP64 plans
+ * (E_UNSUPPORTED otherwise); FP64 plans with na = 32 run on the matrix cores
+ * (one frequency per wave, 16 x 16 FP64 tiles), the others on the vector
+ * units (na lanes per frequency, one row of each operator per lane).
  * Precision: an FP64 plan computes in FP64 throughout.  An FP32 plan forms
  * each layer's operators in FP64 and rounds them, keeps arrays, composites,
  * products and the adding recursion in FP32, and runs the eliminations with
  * I - (reflection)(reflection) in FP64 where the thick-layer rule selects
  * them (pprt_plan_set_thick_mode).  Needs a workspace of
  * pprt_plan_scattering_workspace_bytes() per node and frequency:
- * 8 (2 na^2 + 4 na) bytes in FP64 plans (the composite reflection and source
- * of every node, two unit-source responses of each layer and each layer's
- * eigen solution), 4 (na^2 + 3 na) bytes in FP32 plans (the same without the
+ * 8 (2 na^2 + 4 na) bytes in FP64 plans with na <= 16 (the composite
+ * reflection and source of every node, two unit-source responses of each
+ * layer and each layer's eigen solution), 8 (na^2 + 3 na) bytes in FP64 plans
+ * with na = 32 and 4 (na^2 + 3 na) bytes in FP32 plans (the same without the
  * eigen solutions, which the bottom-up pass recomputes), kept between the
  * top-down and the bottom-up pass; omega = 0 everywhere reproduces
  * pprt_formal_solution to rounding. */
@@ -473,7 +477,7 @@ pprt_status pprt_atom_check_host(const pprt_atom* atom_host, int64_t rows, int32
 
 /* One accelerated-Lambda iteration of the multilevel atom: opacities from
  * pops, formal solution with in-layer continuum scattering (FP64 plans,
- * na in {1,2,4,8,16}), rate assembly and the per-depth solve; pops
+ * na in {1,2,4,8,16,32}), rate assembly and the per-depth solve; pops
  * [rows][nlev] is replaced by the new populations and max_rel [nb] gets the
  * largest relative change.  in->tau (and in->Itop, NULL = 0) are used; the
  * diffusion lower boundary takes B from atom->Bnu. */

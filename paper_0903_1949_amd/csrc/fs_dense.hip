@@ -966,20 +966,27 @@ hipError_t run_dense_na(const DenseLaunch& L, hipStream_t s) {
 
 }  // namespace
 
-bool dense_na_supported(int na) { return na == 1 || na == 2 || na == 4 || na == 8 || na == 16; }
+bool dense_na_supported(int na) { return na == 1 || na == 2 || na == 4 || na == 8 || na == 16 || na == 32; }
 
 size_t dense_workspace_bytes(int na, int64_t rows, int nf, int precision) {
   // per node and frequency: R (na^2), Sigma (na), Z (2 na) in the bulk type,
-  // plus the eigen solution (na^2 + na doubles) in FP64
+  // plus (lane-per-row FP64 kernels) the eigen solution (na^2 + na doubles)
   const size_t rf = (size_t)rows * nf;
+  if (precision == PPRT_FP64 && dense_mfma_na(na)) return dense_mfma_workspace_bytes(na, rows, nf);
   if (precision == PPRT_FP64) return rf * (size_t)(2 * na * na + 4 * na) * sizeof(double);
   return rf * (size_t)(na * na + 3 * na) * sizeof(float);
 }
 
-int dense_freqs_per_item(int na) { return 64 / na; }
+// frequencies per wave: one on the matrix cores, else 64 / na lane groups
+int dense_freqs_per_item(int na, int precision) {
+  if (precision == PPRT_FP64 && dense_mfma_na(na)) return 1;
+  return na <= 64 ? 64 / na : 1;
+}
 
 hipError_t launch_fs_dense(const DenseLaunch& L, hipStream_t s) {
   if (L.nitems == 0) return hipSuccess;
+  if (L.precision == PPRT_FP64 && dense_mfma_na(L.na)) return launch_fs_dense_mfma(L, s);
+  if (L.na > 16) return hipErrorInvalidValue;
   return L.precision == PPRT_FP64 ? run_dense_na<double>(L, s) : run_dense_na<float>(L, s);
 }
 

@@ -63,6 +63,7 @@ def _gpu(ctx, nds, na, nf, c, bc):
 
 @pytest.mark.parametrize("nds,nf,na", [
     ([2], 1, 1), ([3, 2], 3, 2), ([6], 5, 4), ([12, 5, 2], 9, 8), ([20], 17, 8), ([7, 9], 6, 16),
+    ([7, 9], 6, 32), ([2, 13, 3], 3, 32),
 ])
 def test_scattering_parity(gpu_ctx, nds, nf, na):
     seed = sum(nds) * 7 + nf + na
@@ -76,7 +77,7 @@ def test_scattering_parity(gpu_ctx, nds, nf, na):
         assert e < 1e-10, (k, e)
 
 
-@pytest.mark.parametrize("na", [8, 16])
+@pytest.mark.parametrize("na", [8, 16, 32])
 def test_scattering_parity_extreme_layers(gpu_ctx, na):
     """Layer optical depths from 3e-6 to 1e5 (pivots of D M + Q_C' near 1e6 in
     the eliminations) and albedos up to 0.9999, where 1 - Lambda* falls to 1e-4."""
@@ -97,8 +98,10 @@ def test_scattering_parity_extreme_layers(gpu_ctx, na):
         assert e < 1e-10, (k, e)
 
 
-def test_scattering_parity_given_lower_boundary(gpu_ctx):
-    nds, nf, na = [9, 4], 10, 4
+@pytest.mark.parametrize("na", [4, 32])
+def test_scattering_parity_given_lower_boundary(gpu_ctx, na):
+    nds, nf = [9, 4], 10
+    print(f"[case] given lower boundary nds={nds} nf={nf} na={na}", flush=True)
     c = _case(nds, nf, na, 17, bc=pprt.BC_GIVEN)
     plan, got = _gpu(gpu_ctx, nds, na, nf, c, pprt.BC_GIVEN)
     ref = _oracle(nds, c, plan.mu, plan.w, pprt.BC_GIVEN)
@@ -107,8 +110,10 @@ def test_scattering_parity_given_lower_boundary(gpu_ctx):
         assert e < 1e-10, (k, e)
 
 
-def test_scattering_with_zero_albedo_equals_diagonal_path(gpu_ctx):
-    nds, nf, na = [15, 6], 33, 8
+@pytest.mark.parametrize("na", [8, 32])
+def test_scattering_with_zero_albedo_equals_diagonal_path(gpu_ctx, na):
+    nds, nf = [15, 6], 33
+    print(f"[case] zero albedo nds={nds} nf={nf} na={na}", flush=True)
     c = _case(nds, nf, na, 5)
     c["om"] = np.zeros_like(c["om"])
     plan, got = _gpu(gpu_ctx, nds, na, nf, c, pprt.BC_DIFFUSION)
@@ -120,11 +125,12 @@ def test_scattering_with_zero_albedo_equals_diagonal_path(gpu_ctx):
         assert e < 1e-11, (k, e)
 
 
-@pytest.mark.parametrize("omega", [0.5, 0.99, 0.9999])
-def test_semi_infinite_h_function_on_gpu(gpu_ctx, omega):
+@pytest.mark.parametrize("na,omega", [(8, 0.5), (8, 0.99), (8, 0.9999), (32, 0.99), (32, 0.9999)])
+def test_semi_infinite_h_function_on_gpu(gpu_ctx, na, omega):
     """Constant thermal source B, thick isotropically scattering slab: the
     emergent intensity is B sqrt(1-omega) H(mu) (discrete H-function)."""
-    na, nf = 8, 1
+    nf = 1
+    print(f"[case] semi-infinite na={na} omega={omega}", flush=True)
     tau = np.concatenate([[1e-9], np.logspace(-6, 6, 60)])
     nd = tau.shape[0]
     B = 1.3
@@ -159,13 +165,16 @@ def test_continuum_batch_slice(gpu_ctx):
 
 
 def test_scattering_rejects_unsupported_angle_counts(gpu_ctx):
-    """The dense path takes na in {1, 2, 4, 8, 16}; 32 angles (64 x 64 layer
-    operators) and odd counts are refused before any launch."""
-    for na in (32, 3):
-        plan = pprt.Plan(gpu_ctx, [4], na, 3, precision=pprt.FP64, outputs=pprt.OUT_J)
-        z = torch.zeros((4, 3), dtype=torch.float64, device="cuda:0")
-        one = torch.ones((1, 3), dtype=torch.float64, device="cuda:0")
+    """The dense path takes na in {1, 2, 4, 8, 16, 32} in FP64 and up to 16 in
+    FP32: odd counts, and 32 angles in an FP32 plan, are refused before any
+    launch; more than 32 angles are refused when the plan is made."""
+    for na, prec in ((3, pprt.FP64), (32, pprt.FP32)):
+        dt = torch.float64 if prec == pprt.FP64 else torch.float32
+        plan = pprt.Plan(gpu_ctx, [4], na, 3, precision=prec, outputs=pprt.OUT_J)
+        z = torch.zeros((4, 3), dtype=dt, device="cuda:0")
+        one = torch.ones((1, 3), dtype=dt, device="cuda:0")
         with pytest.raises(pprt.PprtError, match="E_UNSUPPORTED"):
             plan.formal_solution_scattering(_dev(np.logspace(-2, 1, 4)), z + 1, z, z,
                                             Bbot=one, Bbot_prev=one)
-
+    with pytest.raises(pprt.PprtError, match="E_SHAPE"):
+        pprt.Plan(gpu_ctx, [4], 64, 3, precision=pprt.FP64, outputs=pprt.OUT_J)
