@@ -77,13 +77,15 @@ def parse():
     ap.add_argument("--graph-chunk", type=int, default=25,
                     help="ALI iterations per captured graph in the graph-mode timing (0: skip)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_fs_profile_c3a.json"))
-    ap.add_argument("--workload", choices=["c3a", "spherical", "nonlocal", "voigt", "c3b", "adjoint", "vox3d"],
+    ap.add_argument("--workload", choices=["c3a", "spherical", "nonlocal", "voigt", "c3b", "adjoint", "vox3d",
+                                           "c5"],
                     default="c3a",
                     help="c3a: the plane-parallel batch (default, the headline line); "
                          "spherical: the same batch shape as spheres (1D spherical symmetry); "
                          "nonlocal: c3a with the tri-diagonal approximate operator and Ng; "
                          "voigt: the multilevel atom with depth-dependent Voigt lines")
     ap.add_argument("--voigt-nb", type=int, default=64, help="voigt: atmospheres in the batch")
+    ap.add_argument("--c5-steps", type=int, default=3, help="c5: timed multilevel iterations")
     ap.add_argument("--conv-tol", type=float, default=1e-6,
                     help="nonlocal: tolerance of the convergence comparison")
     ap.add_argument("--conv-max-iter", type=int, default=4000)
@@ -241,6 +243,8 @@ def main():
     if args.workload == "voigt":
         bench_voigt(args)
         return
+    if args.workload == "c5":
+        return bench_c5(args)
     if args.workload == "vox3d":
         bench_vox3d(args)
         return
@@ -746,6 +750,7 @@ def bench_nonlocal(args):
 VOIGT_FLOPS = 300.0
 OPACITY_FLOPS = 20.0
 PEAK_FP64_VALU = 78.6
+PEAK_FP64_MFMA = 78.6    # TFLOP/s: dense FP64 matrix-core peak (the same as the FP64 vector rate)
 DENSE_FLOPS_PER_LAYER = 21.0 * 8 ** 3   # the 21 NA^3 count per (layer, frequency) at NA = 8
 
 
@@ -1225,6 +1230,140 @@ def bench_voigt(args):
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def bench_c5(args):
+    """The large angle-coupled case: one multilevel iteration of the 20-level
+    atom (100 depth-dependent Voigt lines, 4 continua) on 512 depths, 32
+    angles per hemisphere (the 64 x 64 block layer operators on the FP64
+    matrix cores) and 16384 frequencies: opacities, the omega > 0 formal
+    solution, the preconditioned rates and the 20-level FP64 solve per depth.
+    Each stage is also timed on its own with HIP events."""
+    import torch
+    from paper_0903_1949_amd import pprt
+    from paper_0903_1949_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    atom = W.c5_atom()
+    rows, nf, na = int(atom.nd.sum()), atom.nf, atom.na
+    pts = rows * na * nf
+    ctx = pprt.Context(0)
+    stream = torch.cuda.current_stream()
+    plan = pprt.Plan(ctx, atom.nd, na, nf, precision=pprt.FP64, outputs=pprt.OUT_J | pprt.OUT_LSTAR)
+    da = pprt.DeviceAtom(atom)
+    pops = da.nstar.clone()
+    mx = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0")
+    Bnu = np.asarray(atom.Bnu)
+    Bb, Bp = dev(Bnu[-1:]), dev(Bnu[-2:-1])
+
+    def timed(fn, n=3):
+        fn()
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+        out = None
+        for e0, e1 in evs:
+            e0.record(stream)
+            out = fn()
+            e1.record(stream)
+        torch.cuda.synchronize()
+        return float(np.median([e0.elapsed_time(e1) for e0, e1 in evs])), out
+
+    # the stages one by one from the LTE populations (the formal solution's
+    # workspace is released before the iterations allocate their own)
+    t_op, (q, om, Sg) = timed(lambda: plan.nlte_opacity(da, pops))
+    ws = {}
+    t_fs, fs = timed(lambda: plan.formal_solution_scattering(da.tau, q, Sg, om, Bbot=Bb, Bbot_prev=Bp,
+                                                             workspace=ws.get("w")))
+    ws["w"] = fs["_workspace"]
+    ws_gb = ws["w"].numel() * ws["w"].element_size() / 1e9
+    t_ra, (dRlu, dRul, Rsul) = timed(lambda: plan.rates_assemble(da, pops, fs["J"], fs["lstar"]))
+    t_so, _ = timed(lambda: plan.rates_solve(da, pops, dRlu, dRul, Rsul))
+    J64, L64 = fs["J"].clone(), fs["lstar"].clone()
+    del fs, ws, dRlu, dRul, Rsul
+    torch.cuda.empty_cache()
+    # the same formal solution on an FP32 plan (FP32 arrays and workspace,
+    # FP64 arithmetic): time and per-output error against the FP64 stage
+    plan32 = pprt.Plan(ctx, atom.nd, na, nf, precision=pprt.FP32, outputs=pprt.OUT_J | pprt.OUT_LSTAR)
+    q32, Sg32, om32, Bb32, Bp32 = (x.float() for x in (q, Sg, om, Bb, Bp))
+    ws32 = {}
+    t_fs32, fs32 = timed(lambda: plan32.formal_solution_scattering(da.tau, q32, Sg32, om32, Bbot=Bb32,
+                                                                   Bbot_prev=Bp32, workspace=ws32.get("w")))
+    ws32["w"] = fs32["_workspace"]
+
+    def arr_err(a, b):
+        return float(((a.double() - b).abs() / torch.maximum(b.abs(), 1e-4 * b.abs().max())).max())
+
+    fp32_leg = {"ms": round(t_fs32, 2), "J_err": arr_err(fs32["J"], J64), "lstar_err": arr_err(fs32["lstar"], L64),
+                "workspace_gb": round(ws32["w"].numel() * ws32["w"].element_size() / 1e9, 1),
+                "metric": "max |FP32 - FP64| / max(|FP64|, 1e-4 max |FP64|), inputs rounded to FP32"}
+    del fs32, ws32, plan32, q32, Sg32, om32, J64, L64, q, om, Sg
+    torch.cuda.empty_cache()
+    print(f"[c5] stages: opacity {t_op:.2f} ms, formal solution {t_fs:.1f} ms (FP32 plan {t_fs32:.1f} ms), "
+          f"rates {t_ra:.2f} ms, solve {t_so:.2f} ms", file=sys.stderr, flush=True)
+
+    warmup, steps = min(args.warmup, 2), args.c5_steps      # about a second per iteration
+    for _ in range(warmup):
+        plan.nlte_step(da.tau, da, pops, mx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.nlte_step(da.tau, da, pops, mx)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / steps
+    value = pts / (wall / steps)
+    fs_flops = 21.0 * na ** 3 * (rows - 1) * nf
+    stages = {
+        "opacity_voigt": {"ms": round(t_op, 3)},
+        "formal_solution_dense": {"ms": round(t_fs, 2), "flops": fs_flops,
+                                  "tflops": round(fs_flops / (t_fs * 1e-3) / 1e12, 3),
+                                  "workspace_gb": round(ws_gb, 1)},
+        "rates_assemble_voigt": {"ms": round(t_ra, 3)},
+        "rates_solve_20_levels": {"ms": round(t_so, 3)},
+        "formal_solution_fp32_plan": fp32_leg,
+    }
+    ach = stages["formal_solution_dense"]["tflops"]
+    roofline = {"bound": "mfma", "achieved": ach, "peak": PEAK_FP64_MFMA, "unit": "TFLOP/s",
+                "frac": round(ach / PEAK_FP64_MFMA, 4), "traffic": None,
+                "kernel": "k_fs_dense_mfma<2,1> + <2,2>", "kernel_ms": stages["formal_solution_dense"]["ms"],
+                "flops_per_unit": "21 NA^3 per (layer, frequency)"}
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle.quadrature import gauss_legendre01
+        cpu = c5_cpu_baseline(W.c5_atom(nd=24, nline_pts=5, ncont_pts=4), *gauss_legendre01(na))
+    line = {
+        "metric": "formal-solution depth*angle*freq pts/s of the multilevel iteration, FP64",
+        "value": value, "unit": "pts/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "20-level hydrogen-like atom (100 depth-dependent Voigt lines, damping "
+                               "log-uniform 1e-4..1e-1, 4 continua), nd 512, tau 1e-6..1e2, na 32 "
+                               "(64 x 64 block layer operators), nf 16384, grey scattering continuum "
+                               "eps_c 1e-2, seed 5 (one multilevel iteration per step)",
+                   "rows": rows, "na": na, "nf": nf, "levels": int(atom.nl), "transitions": int(atom.nt),
+                   "points_per_step": pts, "seed": 5},
+        "roofline": roofline,
+        "stages": stages,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def c5_cpu_baseline(atom1, mu, w):
+    """The oracle's multilevel iteration (numpy FP64, one thread) for the
+    same atom on a reduced grid."""
+    from threadpoolctl import threadpool_limits
+    from oracle import rates
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        rates.nlte_iteration(atom1, atom1.nstar.copy(), mu, w)
+        dt = time.perf_counter() - t0
+    pts = int(atom1.nd.sum()) * atom1.na * atom1.nf
+    return {"value": pts / dt, "unit": "pts/s", "cores": 1, "kind": "oracle",
+            "sample": f"one multilevel iteration of the same 20-level atom on a reduced grid (nd "
+                      f"{int(atom1.nd.sum())}, na {atom1.na}, nf {atom1.nf}: 5 points per line, 4 per "
+                      f"continuum; {pts} points), numpy FP64, 1 thread, {dt:.1f} s"}
 
 
 def kernel_hash(name: str = "fs_diag.hip") -> str:

@@ -207,15 +207,18 @@ pprt_status pprt_formal_solution(pprt_plan* plan, const pprt_fs_in* in, pprt_fs_
  * exactly (discrete-ordinate eigen solution, no growing exponentials), layers
  * are combined by the adding method top-down and bottom-up, and every node
  * gets I+-, J, J - S^g, H and the exact diagonal Lambda*_dd = dJ(d)/dS^g(d)
- * with 1 - Lambda*.  na in {1, 2, 4, 8, 16}, and 32 in FP64 plans
- * (E_UNSUPPORTED otherwise); FP64 plans with na = 32 run on the matrix cores
- * (one frequency per wave, 16 x 16 FP64 tiles), the others on the vector
- * units (na lanes per frequency, one row of each operator per lane).
- * Precision: an FP64 plan computes in FP64 throughout.  An FP32 plan forms
- * each layer's operators in FP64 and rounds them, keeps arrays, composites,
- * products and the adding recursion in FP32, and runs the eliminations with
- * I - (reflection)(reflection) in FP64 where the thick-layer rule selects
- * them (pprt_plan_set_thick_mode).  Needs a workspace of
+ * with 1 - Lambda*.  na in {1, 2, 4, 8, 16, 32} (E_UNSUPPORTED otherwise);
+ * plans with na = 32 run on the matrix cores (one frequency per wave, 16 x 16
+ * FP64 tiles), the others on the vector units (na lanes per frequency, one
+ * row of each operator per lane).
+ * Precision: an FP64 plan computes in FP64 throughout.  An FP32 plan with
+ * na <= 16 forms each layer's operators in FP64 and rounds them, keeps
+ * arrays, composites, products and the adding recursion in FP32, and runs
+ * the eliminations with I - (reflection)(reflection) in FP64 where the
+ * thick-layer rule selects them (pprt_plan_set_thick_mode).  An FP32 plan
+ * with na = 32 keeps its arrays and the workspace in FP32 and computes in
+ * FP64: every elimination is FP64 (pprt_thick_counts counts them all) and
+ * the thick modes change nothing.  Needs a workspace of
  * pprt_plan_scattering_workspace_bytes() per node and frequency:
  * 8 (2 na^2 + 4 na) bytes in FP64 plans with na <= 16 (the composite
  * reflection and source of every node, two unit-source responses of each
@@ -361,7 +364,7 @@ pprt_status pprt_plan_continuum_workspace_bytes(const pprt_plan* plan, size_t* b
 
 /* One operator-splitting step of the line on a continuum: S^g assembly,
  * formal solution (with in-layer scattering when cont->omega is given: na in
- * {1,2,4,8,16}, FP32 plans with the thick-layer FP64 eliminations of
+ * {1,2,4,8,16,32}, FP32 plans with the FP64 eliminations of
  * pprt_formal_solution_scattering), then per node the profile quadratures
  *   Jbar - S_l = sum_k wphi_k [(J_k - S^g_k) + (S^g_k - S_l)],
  *   1 - Lbar*  = sum_k wphi_k [(1 - p_k) + p_k (1 - Lambda*_k)]

@@ -972,20 +972,20 @@ size_t dense_workspace_bytes(int na, int64_t rows, int nf, int precision) {
   // per node and frequency: R (na^2), Sigma (na), Z (2 na) in the bulk type,
   // plus (lane-per-row FP64 kernels) the eigen solution (na^2 + na doubles)
   const size_t rf = (size_t)rows * nf;
-  if (precision == PPRT_FP64 && dense_mfma_na(na)) return dense_mfma_workspace_bytes(na, rows, nf);
+  if (dense_mfma_na(na)) return dense_mfma_workspace_bytes(na, rows, nf, precision);
   if (precision == PPRT_FP64) return rf * (size_t)(2 * na * na + 4 * na) * sizeof(double);
   return rf * (size_t)(na * na + 3 * na) * sizeof(float);
 }
 
 // frequencies per wave: one on the matrix cores, else 64 / na lane groups
 int dense_freqs_per_item(int na, int precision) {
-  if (precision == PPRT_FP64 && dense_mfma_na(na)) return 1;
+  if (dense_mfma_na(na)) return 1;
   return na <= 64 ? 64 / na : 1;
 }
 
 hipError_t launch_fs_dense(const DenseLaunch& L, hipStream_t s) {
   if (L.nitems == 0) return hipSuccess;
-  if (L.precision == PPRT_FP64 && dense_mfma_na(L.na)) return launch_fs_dense_mfma(L, s);
+  if (dense_mfma_na(L.na)) return launch_fs_dense_mfma(L, s);
   if (L.na > 16) return hipErrorInvalidValue;
   return L.precision == PPRT_FP64 ? run_dense_na<double>(L, s) : run_dense_na<float>(L, s);
 }

@@ -569,29 +569,32 @@ __device__ __forceinline__ void set_identity_minus(const W<T>& w, Mat<T>& X) {
         X.t[ti][tj][q] = ((ti == tj && (w.g + 4 * q) == w.c) ? 1.0 : 0.0) - X.t[ti][tj][q];
 }
 
-template <int T>
+// S: the plan's storage type (inputs, outputs and the workspace); the
+// arithmetic is FP64 for both
+template <typename S>
 struct MfArgs {
   const Item* items;
   const int64_t* off;
   const double* tau;
-  const double* q;
-  const double* Sg;
-  const double* omega;
-  const double* Itop;
-  const double* Bbot;
-  const double* Bbot_prev;
-  const double* Ibot;
-  double *J, *JmS, *lstar, *lstar_c, *Iplus, *Iminus, *H, *Iemerg;
-  double* wsR;     // [rows][nf][NA][NA]
-  double* wsS;     // [rows][nf][NA]
-  double* wsZ;     // [rows][nf][NA][2]
+  const S* q;
+  const S* Sg;
+  const S* omega;
+  const S* Itop;
+  const S* Bbot;
+  const S* Bbot_prev;
+  const S* Ibot;
+  S *J, *JmS, *lstar, *lstar_c, *Iplus, *Iminus, *H, *Iemerg;
+  S* wsR;          // [rows][nf][NA][NA]
+  S* wsS;          // [rows][nf][NA]
+  S* wsZ;          // [rows][nf][NA][2]
   uint32_t* status;
+  unsigned long long* thick_stats;   // FP32 plans: [FP64 eliminations, all eliminations]
   int32_t nf, nitems, lower_bc;
   uint32_t outputs;
 };
 
-template <int T, int PASS>
-__global__ __launch_bounds__(64) void k_fs_dense_mfma(MfArgs<T> a, MfTab<16 * T> tb) {
+template <int T, int PASS, typename S>
+__global__ __launch_bounds__(64) void k_fs_dense_mfma(MfArgs<S> a, MfTab<16 * T> tb) {
   constexpr int NA = 16 * T;
   __shared__ double slab[Lay<T>::SIZE];
   const int lane = (int)threadIdx.x;
@@ -620,7 +623,7 @@ __global__ __launch_bounds__(64) void k_fs_dense_mfma(MfArgs<T> a, MfTab<16 * T>
   const double mu_l = tab(w, Lay<T>::TMU);
   const int ext = NA - 1 - lane;
   const uint32_t o = a.outputs;
-  auto at = [&](const double* p, int64_t row) { return p[row * nf + k]; };
+  auto at = [&](const S* p, int64_t row) { return (double)p[row * nf + k]; };
   auto layer_depth = [&](int d) {
     return 0.5 * (at(a.q, row0 + d) + at(a.q, row0 + d + 1)) * (a.tau[row0 + d + 1] - a.tau[row0 + d]);
   };
@@ -628,29 +631,29 @@ __global__ __launch_bounds__(64) void k_fs_dense_mfma(MfArgs<T> a, MfTab<16 * T>
     return a.omega ? 0.5 * (at(a.omega, row0 + d) + at(a.omega, row0 + d + 1)) : 0.0;
   };
   const int64_t strideR = (int64_t)nf * NA * NA, strideS = (int64_t)nf * NA, strideZ = (int64_t)nf * NA * 2;
-  double* wsR = a.wsR + (row0 * nf + k) * NA * NA;
-  double* wsS = a.wsS + (row0 * nf + k) * NA;
-  double* wsZ = a.wsZ + (row0 * nf + k) * NA * 2;
+  S* wsR = a.wsR + (row0 * nf + k) * NA * NA;
+  S* wsS = a.wsS + (row0 * nf + k) * NA;
+  S* wsZ = a.wsZ + (row0 * nf + k) * NA * 2;
   const bool wd = (o & PPRT_OUT_LSTAR) != 0;
   const bool we = (o & PPRT_OUT_LSTAR_C) != 0;
   double lam_prev = -1.0, om_prev = -1.0;
   Ops<T> op;
 
-  auto save_mat = [&](double* dst, const Mat<T>& M) {
+  auto save_mat = [&](S* dst, const Mat<T>& M) {
 #pragma unroll
     for (int ti = 0; ti < T; ++ti)
 #pragma unroll
       for (int tj = 0; tj < T; ++tj)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) dst[(16 * ti + w.g + 4 * q) * NA + 16 * tj + w.c] = M.t[ti][tj][q];
+        for (int q = 0; q < 4; ++q) dst[(16 * ti + w.g + 4 * q) * NA + 16 * tj + w.c] = (S)M.t[ti][tj][q];
   };
-  auto load_mat = [&](const double* src, Mat<T>& M) {
+  auto load_mat = [&](const S* src, Mat<T>& M) {
 #pragma unroll
     for (int ti = 0; ti < T; ++ti)
 #pragma unroll
       for (int tj = 0; tj < T; ++tj)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) M.t[ti][tj][q] = src[(16 * ti + w.g + 4 * q) * NA + 16 * tj + w.c];
+        for (int q = 0; q < 4; ++q) M.t[ti][tj][q] = (double)src[(16 * ti + w.g + 4 * q) * NA + 16 * tj + w.c];
   };
 
   if constexpr (PASS == 1) {
@@ -662,12 +665,12 @@ __global__ __launch_bounds__(64) void k_fs_dense_mfma(MfArgs<T> a, MfTab<16 * T>
       for (int tj = 0; tj < T; ++tj) R.t[ti][tj] = v4d{0.0, 0.0, 0.0, 0.0};
     double Sig = 0.0;
     if (act) {
-      const double It = a.Itop ? a.Itop[((int64_t)b * nf + k) * NA + ext] : 0.0;
+      const double It = a.Itop ? (double)a.Itop[((int64_t)b * nf + k) * NA + ext] : 0.0;
       Sig = sw_l * (It - at(a.Sg, row0));
     }
     for (int d = 0; d < nd - 1; ++d) {
       save_mat(wsR + d * strideR, R);
-      if (act) wsS[d * strideS + lane] = Sig;
+      if (act) wsS[d * strideS + lane] = (S)Sig;
       layer<T>(w, layer_omega(d), layer_depth(d), lam_prev, om_prev, op);
       const double dSg = at(a.Sg, row0 + d + 1) - at(a.Sg, row0 + d);
       // G = (I - r R)^-1: P = G t, u = G (r Sigma + dS^g Q) and the unit
@@ -697,11 +700,11 @@ __global__ __launch_bounds__(64) void k_fs_dense_mfma(MfArgs<T> a, MfTab<16 * T>
       cols_out(w, xc, uu, y1, y2);
       if (wd) {
         const double z = mv(w, R, y1);
-        if (act) wsZ[d * strideZ + 2 * lane] = z;
+        if (act) wsZ[d * strideZ + 2 * lane] = (S)z;
       }
       if (we) {
         const double z = mv(w, R, y2);
-        if (act) wsZ[d * strideZ + 2 * lane + 1] = z;
+        if (act) wsZ[d * strideZ + 2 * lane + 1] = (S)z;
       }
       // Sigma_{d+1} = t (Sigma + R u) - dS^g Q,  R_{d+1} = r + t R P
       const double Ru = mv(w, R, uu);
@@ -715,7 +718,11 @@ __global__ __launch_bounds__(64) void k_fs_dense_mfma(MfArgs<T> a, MfTab<16 * T>
         for (int tj = 0; tj < T; ++tj) R.t[ti][tj] = op.r.t[ti][tj] + tRP.t[ti][tj];
     }
     save_mat(wsR + (nd - 1) * strideR, R);
-    if (act) wsS[(nd - 1) * strideS + lane] = Sig;
+    if (act) wsS[(nd - 1) * strideS + lane] = (S)Sig;
+    if (sizeof(S) == 4 && a.thick_stats && lane == 0) {   // every elimination here is FP64
+      atomicAdd(&a.thick_stats[0], (unsigned long long)(nd - 1));
+      atomicAdd(&a.thick_stats[1], (unsigned long long)(nd - 1));
+    }
   } else {
     // ---- pass 2: bottom -> top, outputs per node
     bool nonfinite = false;
@@ -728,12 +735,12 @@ __global__ __launch_bounds__(64) void k_fs_dense_mfma(MfArgs<T> a, MfTab<16 * T>
     if (act) {
       const double S_last = at(a.Sg, row0 + nd - 1);
       if (a.lower_bc == PPRT_BC_DIFFUSION) {
-        const double Bb = a.Bbot[(int64_t)b * nf + k];
-        const double Bp = a.Bbot_prev[(int64_t)b * nf + k];
+        const double Bb = (double)a.Bbot[(int64_t)b * nf + k];
+        const double Bp = (double)a.Bbot_prev[(int64_t)b * nf + k];
         const double gr = (Bb - Bp) / layer_depth(nd - 2);
         Sup = sw_l * ((Bb - S_last) + mu_l * gr);
       } else {
-        const double Ib = a.Ibot ? a.Ibot[((int64_t)b * nf + k) * NA + ext] : 0.0;
+        const double Ib = a.Ibot ? (double)a.Ibot[((int64_t)b * nf + k) * NA + ext] : 0.0;
         Sup = sw_l * (Ib - S_last);
       }
     }
@@ -742,13 +749,13 @@ __global__ __launch_bounds__(64) void k_fs_dense_mfma(MfArgs<T> a, MfTab<16 * T>
       if (has_a) layer<T>(w, layer_omega(d - 1), layer_depth(d - 1), lam_prev, om_prev, op);
       Mat<T> Rd;
       load_mat(wsR + d * strideR, Rd);
-      const double Sd = act ? wsS[d * strideS + lane] : 0.0;
+      const double Sd = act ? (double)wsS[d * strideS + lane] : 0.0;
       // unit responses of the layer above (plain form for Lambda*, difference
       // form for 1 - Lambda*), from R_{d-1} G_{d-1} (beta_l+, Q) of pass 1
       double dS = 0.0, eS = -sw_l;
       if (has_a) {
-        if (wd) dS = mv(w, op.t, act ? wsZ[(d - 1) * strideZ + 2 * lane] : 0.0) + op.blm;
-        if (we) eS = mv(w, op.t, act ? wsZ[(d - 1) * strideZ + 2 * lane + 1] : 0.0) - op.qv;
+        if (wd) dS = mv(w, op.t, act ? (double)wsZ[(d - 1) * strideZ + 2 * lane] : 0.0) + op.blm;
+        if (we) eS = mv(w, op.t, act ? (double)wsZ[(d - 1) * strideZ + 2 * lane + 1] : 0.0) - op.qv;
       }
       // I+ and the two responses from one elimination on I - R^up R_d
       double Ip = mv(w, Rup, Sd) + Sup;
@@ -779,18 +786,18 @@ __global__ __launch_bounds__(64) void k_fs_dense_mfma(MfArgs<T> a, MfTab<16 * T>
       nonfinite |= !isfinite(JmSn + Hn + Ln + Lcn);
       {
         const int64_t x = (row0 + d) * nf + k;
-        const double S = a.Sg[x];
+        const double Sx = (double)a.Sg[x];
         if (lane == 0) {
-          if (o & PPRT_OUT_J) a.J[x] = JmSn + S;
-          if (o & PPRT_OUT_JMS) a.JmS[x] = JmSn;
-          if (o & PPRT_OUT_LSTAR) a.lstar[x] = Ln;
-          if (o & PPRT_OUT_LSTAR_C) a.lstar_c[x] = Lcn;
-          if (o & PPRT_OUT_H) a.H[x] = Hn;
+          if (o & PPRT_OUT_J) a.J[x] = (S)(JmSn + Sx);
+          if (o & PPRT_OUT_JMS) a.JmS[x] = (S)JmSn;
+          if (o & PPRT_OUT_LSTAR) a.lstar[x] = (S)Ln;
+          if (o & PPRT_OUT_LSTAR_C) a.lstar_c[x] = (S)Lcn;
+          if (o & PPRT_OUT_H) a.H[x] = (S)Hn;
         }
         if (act) {
-          if (o & PPRT_OUT_IPLUS) a.Iplus[x * NA + ext] = Ip / sw_l + S;
-          if (o & PPRT_OUT_IMINUS) a.Iminus[x * NA + ext] = Im / sw_l + S;
-          if (d == 0 && (o & PPRT_OUT_IEMERG)) a.Iemerg[((int64_t)b * nf + k) * NA + ext] = Ip / sw_l + S;
+          if (o & PPRT_OUT_IPLUS) a.Iplus[x * NA + ext] = (S)(Ip / sw_l + Sx);
+          if (o & PPRT_OUT_IMINUS) a.Iminus[x * NA + ext] = (S)(Im / sw_l + Sx);
+          if (d == 0 && (o & PPRT_OUT_IEMERG)) a.Iemerg[((int64_t)b * nf + k) * NA + ext] = (S)(Ip / sw_l + Sx);
         }
       }
       // move the lower composite up through layer a = d - 1
@@ -827,24 +834,29 @@ __global__ __launch_bounds__(64) void k_fs_dense_mfma(MfArgs<T> a, MfTab<16 * T>
       }
     }
     if (nonfinite && a.status && lane == 0) atomicOr(a.status, PPRT_DEV_NONFINITE);
+    if (sizeof(S) == 4 && a.thick_stats && lane == 0) {
+      atomicAdd(&a.thick_stats[0], (unsigned long long)(2 * nd - 1));
+      atomicAdd(&a.thick_stats[1], (unsigned long long)(2 * nd - 1));
+    }
   }
 }
 
-template <int T>
+template <int T, typename S>
 hipError_t run_mfma(const DenseLaunch& L, hipStream_t s) {
   constexpr int NA = 16 * T;
-  MfArgs<T> a{};
+  MfArgs<S> a{};
   a.items = L.items; a.off = L.off; a.tau = L.tau;
-  a.q = (const double*)L.q; a.Sg = (const double*)L.Sg; a.omega = (const double*)L.omega;
-  a.Itop = (const double*)L.Itop; a.Bbot = (const double*)L.Bbot; a.Bbot_prev = (const double*)L.Bbot_prev;
-  a.Ibot = (const double*)L.Ibot;
-  a.J = (double*)L.J; a.JmS = (double*)L.JmS; a.lstar = (double*)L.lstar; a.lstar_c = (double*)L.lstar_c;
-  a.Iplus = (double*)L.Iplus; a.Iminus = (double*)L.Iminus; a.H = (double*)L.H; a.Iemerg = (double*)L.Iemerg;
+  a.q = (const S*)L.q; a.Sg = (const S*)L.Sg; a.omega = (const S*)L.omega;
+  a.Itop = (const S*)L.Itop; a.Bbot = (const S*)L.Bbot; a.Bbot_prev = (const S*)L.Bbot_prev;
+  a.Ibot = (const S*)L.Ibot;
+  a.J = (S*)L.J; a.JmS = (S*)L.JmS; a.lstar = (S*)L.lstar; a.lstar_c = (S*)L.lstar_c;
+  a.Iplus = (S*)L.Iplus; a.Iminus = (S*)L.Iminus; a.H = (S*)L.H; a.Iemerg = (S*)L.Iemerg;
   const size_t rf = (size_t)L.rows * L.nf;
-  a.wsR = (double*)L.ws;
+  a.wsR = (S*)L.ws;
   a.wsS = a.wsR + rf * NA * NA;
   a.wsZ = a.wsS + rf * NA;
   a.status = L.status;
+  a.thick_stats = L.thick_stats;
   a.nf = L.nf; a.nitems = L.nitems; a.lower_bc = L.lower_bc; a.outputs = L.outputs;
   MfTab<NA> tb{};
   for (int i = 0; i < NA; ++i) {
@@ -853,8 +865,8 @@ hipError_t run_mfma(const DenseLaunch& L, hipStream_t s) {
     tb.mu[i] = m; tb.m[i] = 1.0 / m; tb.d[i] = 1.0 / (m * m); tb.w[i] = wt;
     tb.z2[i] = wt / (m * m); tb.sw[i] = sqrt(wt); tb.swmu[i] = sqrt(wt) * m;
   }
-  hipLaunchKernelGGL((k_fs_dense_mfma<T, 1>), dim3(L.nitems), dim3(64), 0, s, a, tb);
-  hipLaunchKernelGGL((k_fs_dense_mfma<T, 2>), dim3(L.nitems), dim3(64), 0, s, a, tb);
+  hipLaunchKernelGGL((k_fs_dense_mfma<T, 1, S>), dim3(L.nitems), dim3(64), 0, s, a, tb);
+  hipLaunchKernelGGL((k_fs_dense_mfma<T, 2, S>), dim3(L.nitems), dim3(64), 0, s, a, tb);
   return hipGetLastError();
 }
 
@@ -862,13 +874,13 @@ hipError_t run_mfma(const DenseLaunch& L, hipStream_t s) {
 
 bool dense_mfma_na(int na) { return na == 32; }
 
-size_t dense_mfma_workspace_bytes(int na, int64_t rows, int nf) {
-  return (size_t)rows * nf * (size_t)(na * na + 3 * na) * sizeof(double);
+size_t dense_mfma_workspace_bytes(int na, int64_t rows, int nf, int precision) {
+  return (size_t)rows * nf * (size_t)(na * na + 3 * na) * (precision == PPRT_FP64 ? sizeof(double) : sizeof(float));
 }
 
 hipError_t launch_fs_dense_mfma(const DenseLaunch& L, hipStream_t s) {
   if (L.nitems == 0) return hipSuccess;
-  if (L.na == 32) return run_mfma<2>(L, s);
+  if (L.na == 32) return L.precision == PPRT_FP64 ? run_mfma<2, double>(L, s) : run_mfma<2, float>(L, s);
   return hipErrorInvalidValue;
 }
 

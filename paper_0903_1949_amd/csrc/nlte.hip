@@ -143,106 +143,206 @@ __global__ __launch_bounds__(64) void k_ml_rates(MlArgs a, const double* __restr
 }
 
 constexpr int kMaxLev = 32;
+constexpr int kSolveWaves = 4;            // waves per block (one block per atmosphere)
+constexpr int kSolveLd = kMaxLev + 1;     // LDS row stride of the assembled matrix
 
-// one block per atmosphere; each thread solves the systems of its rows
-__global__ __launch_bounds__(128) void k_ml_solve(MlArgs a, const int64_t* __restrict__ off,
-                                                  const double* __restrict__ dRlu,
-                                                  const double* __restrict__ dRul,
-                                                  const double* __restrict__ Rsul,
-                                                  double* __restrict__ pops_new,
-                                                  double* __restrict__ max_rel,
-                                                  uint32_t* __restrict__ status, MlSolveCtl ctl) {
-  __shared__ double red[128];
+// value of v in lane l (l uniform)
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const long long bits = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(bits & 0xffffffffll), l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(bits >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Statistical equilibrium per depth: one wave per depth row.  Lane i
+// assembles row i of the rate matrix in the wave's LDS (in transition order,
+// so the sums are the same on every run), then keeps it in registers (static
+// column indices: no private memory) for an LU factorisation with partial
+// pivoting in which the pivot rows stay in their lanes: each step picks the
+// largest remaining |A_ic| by a wave reduction (ties to the lowest row) and
+// reads the pivot row from its lane; one step of iterative refinement
+// follows.  Unknowns are n_i / n_i^old (columns scaled by the previous
+// populations), row 0 is number conservation.
+__global__ __launch_bounds__(64 * kSolveWaves) void k_ml_solve(
+    MlArgs a, const int64_t* __restrict__ off, const double* __restrict__ dRlu,
+    const double* __restrict__ dRul, const double* __restrict__ Rsul, double* __restrict__ pops_new,
+    double* __restrict__ max_rel, uint32_t* __restrict__ status, MlSolveCtl ctl) {
+  __shared__ double Ms[kSolveWaves][kMaxLev * kSolveLd];
+  __shared__ double red[kSolveWaves];
   const int b = blockIdx.x;
   const int n = a.nlev;
+  const int lane = (int)(threadIdx.x & 63);
+  const int wv = (int)(threadIdx.x >> 6);
   if (ctl.active != nullptr && ctl.active[b] == 0) {   // converged: keep the populations
     for (int64_t x = off[b] * n + threadIdx.x; x < off[b + 1] * n; x += blockDim.x)
       pops_new[x] = a.pops[x];
     return;
   }
+  double* M = Ms[wv];
   double mx = 0.0;
   uint32_t bad = 0;
-  for (int64_t r = off[b] + threadIdx.x; r < off[b + 1]; r += blockDim.x) {
-    double A[kMaxLev][kMaxLev];
-    double x[kMaxLev];
-    for (int i = 0; i < n; ++i) {
-      x[i] = 0.0;
-      for (int j = 0; j < n; ++j) A[i][j] = 0.0;
-    }
-    // A[i][j] += rate j -> i ; A[i][i] -= rates out of i
+  for (int64_t r = off[b] + wv; r < off[b + 1]; r += kSolveWaves) {
+    // the previous row's reads of the slab are done
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // ---- assembly: A[i][j] += rate j -> i, A[i][i] -= rates out of i
+    if (lane < n)
+      for (int j = 0; j < n; ++j) M[lane * kSolveLd + j] = 0.0;
     for (int t = 0; t < a.ntr; ++t) {
       const int l = a.lower[t], u = a.upper[t];
       if (!(l >= 0 && u < n && l < u)) { bad |= PPRT_DEV_BADINDEX; continue; }
       const int64_t y = r * a.ntr + t;
       const double Plu = dRlu[y] + a.Clu[y];
       const double Pul = Rsul[y] + dRul[y] + a.Cul[y];
-      A[u][l] += Plu;
-      A[l][l] -= Plu;
-      A[l][u] += Pul;
-      A[u][u] -= Pul;
-    }
-    for (int j = 0; j < n; ++j) A[0][j] = 1.0;   // number conservation
-    x[0] = a.ntot[r];
-    // unknowns n_i / n_i^old: scale the columns by the previous populations
-    double sc[kMaxLev];
-    for (int j = 0; j < n; ++j) {
-      sc[j] = a.pops[r * n + j];
-      for (int i = 0; i < n; ++i) A[i][j] *= sc[j];
-    }
-    // LU with partial pivoting, forward/back substitution.  A column with
-    // no nonzero (or no finite) pivot makes the system singular: the row
-    // keeps its old populations and the SINGULAR bit is raised.
-    bool singular = false;
-    for (int c = 0; c < n; ++c) {
-      int p = c;
-      double best = fabs(A[c][c]);
-      for (int i = c + 1; i < n; ++i)
-        if (fabs(A[i][c]) > best) { best = fabs(A[i][c]); p = i; }
-      if (!(best > 0.0) || !isfinite(best)) { singular = true; break; }
-      if (p != c) {
-        for (int j = 0; j < n; ++j) { const double tmp = A[c][j]; A[c][j] = A[p][j]; A[p][j] = tmp; }
-        const double tmp = x[c]; x[c] = x[p]; x[p] = tmp;
+      if (lane == u) {
+        M[u * kSolveLd + l] += Plu;
+        M[u * kSolveLd + u] -= Pul;
+      } else if (lane == l) {
+        M[l * kSolveLd + l] -= Plu;
+        M[l * kSolveLd + u] += Pul;
       }
-      const double inv = 1.0 / A[c][c];
-      for (int i = c + 1; i < n; ++i) {
-        const double f = A[i][c] * inv;
-        if (f != 0.0) {
-          for (int j = c; j < n; ++j) A[i][j] = fma(-f, A[c][j], A[i][j]);
-          x[i] = fma(-f, x[c], x[i]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // ---- row `lane` into registers, columns scaled by the old populations
+    double row[kMaxLev];
+    double x = (lane == 0) ? a.ntot[r] : 0.0;
+#pragma unroll
+    for (int j = 0; j < kMaxLev; ++j) {
+      double v = 0.0;
+      if (j < n) {
+        v = (lane == 0) ? 1.0 : (lane < n ? M[lane * kSolveLd + j] : 0.0);   // row 0: conservation
+        v *= a.pops[r * n + j];
+      }
+      row[j] = v;
+    }
+    bool used = lane >= n;
+    int mystep = kMaxLev;                // the step at which this lane's row is the pivot
+    int pos[kMaxLev];
+    bool singular = false;
+#pragma unroll
+    for (int c = 0; c < kMaxLev; ++c) {
+      pos[c] = 0;
+      if (c < n && !singular) {
+        // pivot: the largest |A_ic| over the rows not yet used (a NaN counts
+        // as infinite, which makes the system singular)
+        double v = -1.0;
+        if (!used) {
+          v = fabs(row[c]);
+          if (v != v) v = INFINITY;
+        }
+        int bl = lane;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+          const double ov = __shfl_xor(v, o);
+          const int ol = __shfl_xor(bl, o);
+          if (ov > v || (ov == v && ol < bl)) { v = ov; bl = ol; }
+        }
+        const int p = __builtin_amdgcn_readfirstlane(bl);
+        // v is the same in every lane after the reduction
+        if (!(v > 0.0) || !isfinite(v)) {
+          singular = true;
+        } else {
+          pos[c] = p;
+          const double inv = 1.0 / lane_value(row[c], p);
+          const double xp = lane_value(x, p);
+          const bool upd = !used && lane != p;
+          const double f = upd ? row[c] * inv : 0.0;
+#pragma unroll
+          for (int j = c + 1; j < kMaxLev; ++j) {
+            const double pj = lane_value(row[j], p);
+            if (upd) row[j] = fma(-f, pj, row[j]);
+          }
+          if (upd) x = fma(-f, xp, x);
+          if (lane == p) { used = true; mystep = c; }
         }
       }
     }
     if (singular) {
       bad |= PPRT_DEV_SINGULAR;
-      for (int i = 0; i < n; ++i) pops_new[r * n + i] = a.pops[r * n + i];
+      if (lane < n) pops_new[r * n + lane] = a.pops[r * n + lane];
       continue;
     }
-    for (int c = n - 1; c >= 0; --c) {
-      double s = x[c];
-      for (int j = c + 1; j < n; ++j) s = fma(-A[c][j], x[j], s);
-      x[c] = s / A[c][c];
+    // ---- back substitution on the pivot rows (uniform values)
+    double sol[kMaxLev];
+#pragma unroll
+    for (int c = kMaxLev - 1; c >= 0; --c) {
+      sol[c] = 0.0;
+      if (c < n) {
+        const int p = pos[c];
+        double sacc = lane_value(x, p);
+#pragma unroll
+        for (int j = c + 1; j < kMaxLev; ++j)
+          if (j < n) sacc = fma(-lane_value(row[j], p), sol[j], sacc);
+        sol[c] = sacc / lane_value(row[c], p);
+      }
     }
-    for (int i = 0; i < n; ++i) x[i] *= sc[i];
-    for (int i = 0; i < n; ++i) {
-      const double old = a.pops[r * n + i];
-      const double rel = fabs(x[i] - old) / fabs(x[i]);
-      if (!isfinite(x[i])) bad |= PPRT_DEV_NONFINITE;
+    // ---- one step of iterative refinement in FP64: the residual of the
+    // scaled system from the assembled matrix (still in the slab), then the
+    // correction from the same factors (partial pivoting alone leaves
+    // componentwise backward errors of several n u on these systems, whose
+    // columns span many decades; one step brings them to rounding level)
+    double d = 0.0;
+    if (lane < n) {
+      d = (lane == 0) ? a.ntot[r] : 0.0;
+#pragma unroll
+      for (int j = 0; j < kMaxLev; ++j)
+        if (j < n) {
+          const double aij = (lane == 0) ? 1.0 : M[lane * kSolveLd + j];
+          d = fma(-(aij * a.pops[r * n + j]), sol[j], d);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < kMaxLev; ++c) {
+      if (c < n) {
+        const int p = pos[c];
+        const double inv = 1.0 / lane_value(row[c], p);
+        const double dp = lane_value(d, p);
+        if (mystep > c) d = fma(-(row[c] * inv), dp, d);
+      }
+    }
+    double corr[kMaxLev];
+#pragma unroll
+    for (int c = kMaxLev - 1; c >= 0; --c) {
+      corr[c] = 0.0;
+      if (c < n) {
+        const int p = pos[c];
+        double sacc = lane_value(d, p);
+#pragma unroll
+        for (int j = c + 1; j < kMaxLev; ++j)
+          if (j < n) sacc = fma(-lane_value(row[j], p), corr[j], sacc);
+        corr[c] = sacc / lane_value(row[c], p);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kMaxLev; ++c) sol[c] += corr[c];
+    double mine = 0.0;
+#pragma unroll
+    for (int j = 0; j < kMaxLev; ++j)
+      if (j == lane) mine = sol[j];
+    if (lane < n) {
+      const double old = a.pops[r * n + lane];
+      const double xi = mine * old;
+      const double rel = fabs(xi - old) / fabs(xi);
+      if (!isfinite(xi)) bad |= PPRT_DEV_NONFINITE;
       mx = fmax(mx, isfinite(rel) ? rel : INFINITY);
-      pops_new[r * n + i] = x[i];
+      pops_new[r * n + lane] = xi;
     }
   }
   if (bad && status) atomicOr(status, bad);
-  red[threadIdx.x] = mx;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+  if (lane == 0) red[wv] = mx;
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
-    __syncthreads();
-  }
   if (threadIdx.x == 0) {
-    if (max_rel) max_rel[b] = red[0];
+    double m = red[0];
+    for (int w = 1; w < kSolveWaves; ++w) m = fmax(m, red[w]);
+    if (max_rel) max_rel[b] = m;
     if (ctl.iters != nullptr) {
       const int it = (ctl.iters[b] += 1);
-      if (ctl.active != nullptr && (red[0] < ctl.tol || (ctl.max_iter > 0 && it >= ctl.max_iter)))
+      if (ctl.active != nullptr && (m < ctl.tol || (ctl.max_iter > 0 && it >= ctl.max_iter)))
         ctl.active[b] = 0;
     }
   }
@@ -282,7 +382,7 @@ hipError_t launch_ml_solve(const MlArgs& a, const int64_t* off, int nb, const do
                            const double* dRul, const double* Rsul, double* pops_new, double* max_rel,
                            uint32_t* status, hipStream_t s, const MlSolveCtl& ctl) {
   if (nb == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ml_solve, dim3(nb), dim3(128), 0, s, a, off, dRlu, dRul, Rsul, pops_new,
+  hipLaunchKernelGGL(k_ml_solve, dim3(nb), dim3(64 * kSolveWaves), 0, s, a, off, dRlu, dRul, Rsul, pops_new,
                      max_rel, status, ctl);
   return hipGetLastError();
 }

@@ -718,9 +718,8 @@ pprt_status pprt_formal_solution_scattering(pprt_plan* p, const pprt_fs_in* in, 
                                             pprt_fs_out* out, void* ws) {
   if (!p) return PPRT_E_INVALID_ARG;
   pprt_ctx* c = p->ctx;
-  if (!dense_na_supported(p->na) || (p->na > 16 && p->precision != PPRT_FP64))
-    return fail(c, PPRT_E_UNSUPPORTED, "in-layer scattering needs na in {1,2,4,8,16}, or 32 in an FP64 plan "
-                "(got %d)", p->na);
+  if (!dense_na_supported(p->na))
+    return fail(c, PPRT_E_UNSUPPORTED, "in-layer scattering needs na in {1,2,4,8,16,32} (got %d)", p->na);
   if (!in || !out || !omega) return fail(c, PPRT_E_INVALID_ARG, "null in/out/omega");
   if (!in->tau || !in->q || !in->Sg) return fail(c, PPRT_E_INVALID_ARG, "tau, q and Sg are required");
   if (p->lower_bc == PPRT_BC_DIFFUSION && (!in->Bbot || !in->Bbot_prev))
@@ -1000,8 +999,8 @@ pprt_status pprt_two_level_ali_step_continuum(pprt_plan* p, const pprt_fs_in* in
     return fail(c, PPRT_E_INVALID_ARG, "tau, q, pfrac and sg_const are required");
   if (!at->eps || !at->B || !at->wphi) return fail(c, PPRT_E_INVALID_ARG, "atom needs eps, B and wphi");
   if (!ws) return fail(c, PPRT_E_WORKSPACE, "workspace required (pprt_plan_continuum_workspace_bytes)");
-  if (ct->omega && (!dense_na_supported(p->na) || (p->na > 16 && p->precision != PPRT_FP64)))
-    return fail(c, PPRT_E_UNSUPPORTED, "in-layer scattering needs na in {1,2,4,8,16}, or 32 in an FP64 plan");
+  if (ct->omega && !dense_na_supported(p->na))
+    return fail(c, PPRT_E_UNSUPPORTED, "in-layer scattering needs na in {1,2,4,8,16,32}");
   {
     pprt_status v = validate_fs_in(p, in, S);
     if (v == PPRT_OK && (c->validate & PPRT_VALIDATE_INPUTS)) {

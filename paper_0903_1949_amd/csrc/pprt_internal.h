@@ -230,9 +230,9 @@ struct DenseLaunch {
 bool dense_na_supported(int na);
 size_t dense_workspace_bytes(int na, int64_t rows, int nf, int precision);
 int dense_freqs_per_item(int na, int precision);
-// NA = 16 and 32 in FP64 plans: the matrix-core kernels (fs_dense_mfma.hip)
+// NA = 32: the matrix-core kernels (fs_dense_mfma.hip), FP64 arithmetic for both storage types
 bool dense_mfma_na(int na);
-size_t dense_mfma_workspace_bytes(int na, int64_t rows, int nf);
+size_t dense_mfma_workspace_bytes(int na, int64_t rows, int nf, int precision);
 hipError_t launch_fs_dense_mfma(const DenseLaunch& L, hipStream_t s);
 hipError_t launch_fs_dense(const DenseLaunch& L, hipStream_t s);
 

@@ -345,7 +345,8 @@ _SAHA = 2.0706e-16          # (h^2 / (2 pi m_e k))^(3/2) in cm^3 K^(3/2), hydrog
 def multilevel_atom(nbound=6, ncont=5, nd=128, na=8, nline_pts=100, ncont_pts=100,
                     tau_lo=1e-6, tau_hi=1e2, teff=5800.0, eps_c=1e-2, strength_lo=1e-2,
                     strength_hi=1e4, a_lo=1e-3, a_hi=1e-2, x_max=50.0, coll_scale=1e-3,
-                    line_pairs=None, nb=1, seed=2, depth_profiles=False) -> MultiLevelAtom:
+                    line_pairs=None, nb=1, seed=2, depth_profiles=False,
+                    damping_log=False) -> MultiLevelAtom:
     """Hydrogen-like atom with `nbound` bound levels (E_i = 1 - 1/i^2,
     g_i = 2 i^2) and a continuum level, all bound-bound pairs as lines (or
     `line_pairs`) and bound-free continua from levels 1..ncont, on a grey
@@ -353,7 +354,7 @@ def multilevel_atom(nbound=6, ncont=5, nd=128, na=8, nline_pts=100, ncont_pts=10
 
     Line strengths: LTE line-centre chi_l / chi_c at tau_ref = 1,
     log-uniform on [strength_lo, strength_hi]; Voigt damping a uniform on
-    [a_lo, a_hi]; each line sampled by nline_pts points symmetric about the
+    [a_lo, a_hi] (log-uniform with damping_log=True); each line sampled by nline_pts points symmetric about the
     centre and concentrated in the core (x = x_max sinh-spaced).  Continua:
     hydrogenic nu^-3 cross-sections from the edge to 4x the edge on
     ncont_pts log-spaced points, strength at the edge log-uniform in
@@ -406,7 +407,8 @@ def multilevel_atom(nbound=6, ncont=5, nd=128, na=8, nline_pts=100, ncont_pts=10
     strengths = np.exp(rng.uniform(math.log(strength_lo), math.log(strength_hi), size=nt))
     line_nu0 = np.zeros(nt)
     line_s = np.zeros(nt)
-    damp = rng.uniform(a_lo, a_hi, size=nt)
+    damp = (np.exp(rng.uniform(math.log(a_lo), math.log(a_hi), size=nt)) if damping_log
+            else rng.uniform(a_lo, a_hi, size=nt))
     cstr = np.exp(rng.uniform(math.log(0.1), math.log(10.0), size=nt))
     for t in range(nt):
         l, u = int(lo[t]), int(up[t])
@@ -484,6 +486,29 @@ def multilevel_atom(nbound=6, ncont=5, nd=128, na=8, nline_pts=100, ncont_pts=10
         line_nu0=line_nu0 if depth_profiles else None, line_s=line_s if depth_profiles else None,
         line_a=np.where(kind == 0, damp, 0.0) if depth_profiles else None,
         dopp=rep(dopp) if depth_profiles else None)
+
+
+def c5_atom(nd=512, na=32, nline_pts=160, ncont=4, ncont_pts=96, nlines=100, nb=1,
+            seed=5) -> MultiLevelAtom:
+    """The large angle-coupled case: a 20-level hydrogen-like atom (19 bound
+    levels and the continuum) with `nlines` lines, all 18 Delta n = 1 pairs
+    plus seeded other pairs, and bound-free continua from the lowest `ncont`
+    levels; nd depths, tau_ref 1e-6..1e2; na angles per hemisphere;
+    nf = nlines * nline_pts + ncont * ncont_pts frequencies (16384 at the
+    defaults); depth-dependent Voigt lines with damping log-uniform on
+    [1e-4, 1e-1] and strengths log-uniform on [1e-2, 1e4]; grey background
+    with eps_c = 1e-2."""
+    nbound = 19
+    adj = [(i, i + 1) for i in range(nbound - 1)]
+    rest = [(i, j) for i in range(nbound) for j in range(i + 2, nbound)]
+    rng = np.random.default_rng(seed + 1000)
+    pick = rng.choice(len(rest), size=nlines - len(adj), replace=False)
+    pairs = sorted(adj + [rest[k] for k in pick])
+    return multilevel_atom(nbound=nbound, ncont=ncont, nd=nd, na=na, nline_pts=nline_pts,
+                           ncont_pts=ncont_pts, tau_lo=1e-6, tau_hi=1e2, eps_c=1e-2,
+                           strength_lo=1e-2, strength_hi=1e4, a_lo=1e-4, a_hi=1e-1,
+                           line_pairs=pairs, nb=nb, seed=seed, depth_profiles=True,
+                           damping_log=True)
 
 
 def _trapz_weights(x):

@@ -165,10 +165,10 @@ def test_continuum_batch_slice(gpu_ctx):
 
 
 def test_scattering_rejects_unsupported_angle_counts(gpu_ctx):
-    """The dense path takes na in {1, 2, 4, 8, 16, 32} in FP64 and up to 16 in
-    FP32: odd counts, and 32 angles in an FP32 plan, are refused before any
-    launch; more than 32 angles are refused when the plan is made."""
-    for na, prec in ((3, pprt.FP64), (32, pprt.FP32)):
+    """The dense path takes na in {1, 2, 4, 8, 16, 32}: odd counts are refused
+    before any launch, in either precision; more than 32 angles are refused
+    when the plan is made."""
+    for na, prec in ((3, pprt.FP64), (3, pprt.FP32)):
         dt = torch.float64 if prec == pprt.FP64 else torch.float32
         plan = pprt.Plan(gpu_ctx, [4], na, 3, precision=prec, outputs=pprt.OUT_J)
         z = torch.zeros((4, 3), dtype=dt, device="cuda:0")

@@ -1,8 +1,9 @@
 """GPU parity of the FP32-bulk formal solution with in-layer scattering
 (pprt_formal_solution_scattering on an FP32 plan: FP64 layer operators, FP32
-adding recursion, FP64 eliminations under the thick-layer rule) with the FP64
-oracle run on the FP32-rounded inputs, output by output, and the thick-layer
-modes and counters.
+adding recursion, FP64 eliminations under the thick-layer rule; at 32 angles
+FP32 arrays and workspace with FP64 arithmetic) with the FP64 oracle run on
+the FP32-rounded inputs, output by output, and the thick-layer modes and
+counters.
 
 Per-output contract (two metrics: `arr`, the per-array relative error with a
 floor of 1e-4 of the array's scale, and `scale`, max |a - b| / max |b|):
@@ -99,6 +100,7 @@ def _continuum_slice(nb=3, nf=64, seed=33):
 
 @pytest.mark.parametrize("nds,nf,na", [
     ([2], 1, 1), ([3, 2], 3, 2), ([6], 5, 4), ([12, 5, 2], 9, 8), ([20], 17, 8), ([7, 9], 6, 16),
+    ([7, 9], 6, 32),
 ])
 def test_fp32_scattering_parity(gpu_ctx, nds, nf, na):
     seed = sum(nds) * 7 + nf + na
@@ -109,13 +111,16 @@ def test_fp32_scattering_parity(gpu_ctx, nds, nf, na):
     _check(got, ref, GENERAL, "rule")
 
 
-@pytest.mark.parametrize("na", [8, 16])
+@pytest.mark.parametrize("na", [8, 16, 32])
 def test_fp32_scattering_extreme_layers(gpu_ctx, na):
     nds, nf, c = _extreme(na)
     print(f"[case] fp32 extreme layers nds={nds} nf={nf} na={na}", flush=True)
-    plan, got, _ = _run(gpu_ctx, nds, na, nf, c)
+    plan, got, (n64, ntot) = _run(gpu_ctx, nds, na, nf, c)
     ref = _oracle(nds, _rounded(c), plan.mu, plan.w, pprt.BC_DIFFUSION)
     _check(got, ref, GENERAL, "rule")
+    if na == 32:
+        # one wave per frequency, every elimination in FP64: nd - 1 down, 2 nd - 1 up
+        assert n64 == ntot == sum(nf * (3 * nd - 2) for nd in nds)
 
 
 def test_fp32_continuum_slice_modes(gpu_ctx):
@@ -145,11 +150,12 @@ def test_fp32_continuum_slice_modes(gpu_ctx):
 
 def test_fp32_workspace_and_mode_validation(gpu_ctx):
     """An FP32 plan needs 4 (na^2 + 3 na) bytes per node and frequency (no
-    stored eigen solutions), an FP64 plan 8 (2 na^2 + 4 na); modes outside
-    PPRT_THICK_* are refused."""
+    stored eigen solutions), an FP64 plan 8 (2 na^2 + 4 na) up to 16 angles
+    and 8 (na^2 + 3 na) at 32; modes outside PPRT_THICK_* are refused."""
     import ctypes as C
-    nd, na, nf = [30, 20], 8, 40
-    for prec, per in ((pprt.FP32, 4 * (na * na + 3 * na)), (pprt.FP64, 8 * (2 * na * na + 4 * na))):
+    nd, nf = [30, 20], 40
+    for na, prec, per in ((8, pprt.FP32, 4 * (8 * 8 + 3 * 8)), (8, pprt.FP64, 8 * (2 * 8 * 8 + 4 * 8)),
+                          (32, pprt.FP32, 4 * (32 * 32 + 3 * 32)), (32, pprt.FP64, 8 * (32 * 32 + 3 * 32))):
         plan = pprt.Plan(gpu_ctx, nd, na, nf, precision=prec, outputs=pprt.OUT_J)
         nbytes = C.c_size_t()
         assert plan.lib.pprt_plan_scattering_workspace_bytes(plan.h, C.byref(nbytes)) == 0

@@ -80,6 +80,32 @@ def test_rate_assembly_and_solve_parity(gpu_ctx, atom):
     assert np.allclose(mx.cpu().numpy(), mref, rtol=1e-8)
 
 
+@pytest.mark.parametrize("nbound", [19, 31])
+def test_rate_solve_many_levels(gpu_ctx, nbound):
+    """The statistical-equilibrium solve at 20 and 32 levels (the largest
+    atom the library takes): hydrogen-like levels, the Delta n = 1 lines and
+    three continua, against the oracle's solve of the same rates."""
+    pairs = [(i, i + 1) for i in range(nbound - 1)]
+    a = W.multilevel_atom(nbound=nbound, ncont=3, nd=12, na=4, nline_pts=5, ncont_pts=3,
+                          line_pairs=pairs, seed=13, nb=2)
+    print(f"[case] rate solve levels={a.nl} transitions={a.nt}", flush=True)
+    plan = _plan(gpu_ctx, a)
+    da = pprt.DeviceAtom(a)
+    rng = np.random.default_rng(2)
+    rows = a.tau.shape[0]
+    pops = a.nstar * rng.uniform(0.5, 2.0, size=a.nstar.shape)
+    J = rng.uniform(0.1, 2.0, size=(rows, a.nf)) * a.Bnu
+    L = rng.uniform(0.0, 1.0, size=(rows, a.nf))
+    ref = rates.preconditioned_rates(a, pops, J, L)
+    pn, mx = plan.rates_solve(da, _dev(pops), *[_dev(r) for r in ref])
+    torch.cuda.synchronize()
+    got = pn.cpu().numpy()
+    ratio, worst, bw_ratio = population_error_ratio(a, pops, ref, got, 0.0, J, L)
+    print(f"  worst rel err {worst:.2e}, err / condition bound {ratio:.2e}, backward error / bound "
+          f"{bw_ratio:.2e}", flush=True)
+    assert ratio < 1.0 and bw_ratio < 1.0
+
+
 def test_nlte_iteration_parity(gpu_ctx, atom):
     plan = _plan(gpu_ctx, atom)
     da = pprt.DeviceAtom(atom)

@@ -201,8 +201,11 @@ def test_two_level_with_continuum_ali_fixed_point():
 def test_dense_lstar_complement_keeps_relative_accuracy():
     """Thick layers: 1 - Lambda* is tiny and must keep its relative accuracy.
     With omega = 0 it equals the short-characteristic complement
-    1/2 sum w (psi_above + psi_below) exactly; with omega > 0 it must sit
-    between the omega = 0 value scaled by (1 - omega) and the omega = 0 value."""
+    1/2 sum w (psi_above + psi_below) exactly.  With omega > 0 scattering
+    keeps a photon longer from thermalising, so the complement grows
+    monotonically with omega, and nodes with equal layers on both sides get
+    the same value (both computed through the tiny complement itself, not as
+    1 minus a number near 1)."""
     mu, w = gauss_legendre01(4)
     tau = np.array([1.0, 2e4, 4e4, 6e4, 8e4])
     nd = tau.shape[0]
@@ -211,3 +214,10 @@ def test_dense_lstar_complement_keeps_relative_accuracy():
     f0 = formal.formal_solution(tau, q, np.ones(nd), mu, w, lower="given")
     assert np.max(np.abs(o0["lstar_c"][1:-1] / f0["lstar_c"][1:-1] - 1)) < 1e-12
     assert f0["lstar_c"][2, 0] < 1e-4
+    prev = o0["lstar_c"][1:-1, 0]
+    for om in (0.1, 0.5, 0.9, 0.99, 0.9999):
+        c = dense.formal_solution_dense(tau, q, np.ones(nd), mu, w, omega=np.full((nd, 1), om),
+                                        lower="given")["lstar_c"][1:-1, 0]
+        assert np.all(c > prev)
+        assert abs(c[2] / c[1] - 1) < 1e-10      # nodes 2 and 3: equal layers (2e4) on both sides
+        prev = c
