@@ -668,7 +668,7 @@ pprt_status pprt_plan_autotune(pprt_plan* plan, const pprt_fs_in* in, const pprt
                                const double* S, void* workspace, int32_t flags,
                                pprt_tune_report* report);
 
-/* ---- Gradients of the emergent spectrum (omega = 0) ----------------------
+/* ---- Gradients of the emergent spectrum (omega = 0; omega > 0 below) -----
  * The emergent intensity I+(tau_1, mu_i, nu_k) of the plane-parallel formal
  * solution without in-layer scattering (Sect. 3.2 comparison calculation,
  * linear source between nodes) and the vector-Jacobian product of that map:
@@ -707,6 +707,26 @@ pprt_status pprt_emergent_intensity(pprt_plan* plan, const pprt_fs_in* in,
 pprt_status pprt_formal_solution_vjp(pprt_plan* plan, const pprt_fs_in* in,
                                      int32_t checkpoint_interval, const void* gIemerg,
                                      const pprt_fs_grad* grad, void* workspace);
+
+/* ---- Gradients of the emergent spectrum with in-layer scattering --------
+ * The vector-Jacobian product of the emergent intensity Iemerg (I+ at node
+ * 0, [b][nf][na]) of pprt_formal_solution_scattering: given g = dL/dIemerg,
+ * the derivatives of L with respect to every q and S^g entry and to the
+ * lower-boundary data (grad->dBbot, dBbot_prev for DIFFUSION, grad->dIbot for
+ * GIVEN, each NULL = not written).  omega and Itop are held fixed.  The
+ * adjoint is hand-written: the call reruns the bottom-up adding recursion of
+ * the layers below every node (composite reflection R^up and source S^up,
+ * kept in the workspace with each layer's eigen solution) and then sweeps it
+ * backwards from the top, with the derivatives of each layer's t, r and
+ * difference-form source in its optical depth taken from the eigen form.
+ * FP64 plans with na in {1, 2, 4, 8, 16} (E_UNSUPPORTED otherwise); in, omega
+ * and gIemerg as for the forward call, device memory; workspace of
+ * pprt_plan_scattering_vjp_workspace_bytes() = 8 (2 na^2 + 2 na) bytes per
+ * node and frequency.  Every dq and dSg entry is overwritten.  Asynchronous. */
+pprt_status pprt_plan_scattering_vjp_workspace_bytes(const pprt_plan* plan, size_t* bytes);
+pprt_status pprt_formal_solution_scattering_vjp(pprt_plan* plan, const pprt_fs_in* in,
+                                                const void* omega, const void* gIemerg,
+                                                const pprt_fs_grad* grad, void* workspace);
 
 /* ------------------------- 3D full characteristics, spherical voxel grid */
 

@@ -1,5 +1,6 @@
 """torch.autograd binding of the emergent intensity and its hand-written
-adjoint (pprt_emergent_intensity / pprt_formal_solution_vjp).
+adjoint (pprt_emergent_intensity / pprt_formal_solution_vjp; with in-layer
+scattering pprt_formal_solution_scattering / pprt_formal_solution_scattering_vjp).
 
 Both directions run in libpprt's kernels; this module only marshals tensors.
 The forward keeps layer checkpoints in a workspace tensor saved for the
@@ -48,3 +49,43 @@ def emergent_intensity(plan: pprt.Plan, tau, q, Sg, Bbot=None, Bbot_prev=None, I
                        checkpoint_interval: int = 16):
     """Differentiable emergent intensity [nb, nf, na]."""
     return EmergentIntensity.apply(plan, checkpoint_interval, tau, q, Sg, Bbot, Bbot_prev, Ibot)
+
+
+class EmergentIntensityScattering(torch.autograd.Function):
+    """Iemerg[b, k, i] of the formal solution with in-layer scattering (FP64
+    plans that request PPRT_OUT_IEMERG, na <= 16), differentiable in q, Sg,
+    Bbot and Bbot_prev (diffusion lower boundary) or q, Sg and Ibot; omega and
+    Itop are held fixed.  The backward pass reruns the bottom-up recursion
+    inside pprt_formal_solution_scattering_vjp, so nothing but the inputs is
+    saved."""
+
+    @staticmethod
+    def forward(ctx, plan: pprt.Plan, tau, q, Sg, omega, Bbot, Bbot_prev, Ibot, Itop):
+        if not plan.outputs & pprt.OUT_IEMERG:
+            raise ValueError("the plan must request OUT_IEMERG")
+        diff = plan.lower_bc == pprt.BC_DIFFUSION
+        q, Sg, omega = q.contiguous(), Sg.contiguous(), omega.contiguous()
+        out = plan.formal_solution_scattering(tau, q, Sg, omega, Bbot=Bbot if diff else None,
+                                              Bbot_prev=Bbot_prev if diff else None, Itop=Itop,
+                                              Ibot=None if diff else Ibot)
+        ctx.plan = plan
+        ctx.save_for_backward(tau, q, Sg, omega, Bbot, Bbot_prev, Ibot, Itop)
+        return out["Iemerg"]
+
+    @staticmethod
+    def backward(ctx, gI):
+        tau, q, Sg, omega, Bbot, Bbot_prev, Ibot, Itop = ctx.saved_tensors
+        plan = ctx.plan
+        diff = plan.lower_bc == pprt.BC_DIFFUSION
+        g = plan.formal_solution_scattering_vjp(tau, q, Sg, omega, gI.contiguous(),
+                                                Bbot=Bbot if diff else None,
+                                                Bbot_prev=Bbot_prev if diff else None, Itop=Itop,
+                                                Ibot=None if diff else Ibot)
+        return (None, None, g["dq"], g["dSg"], None, g.get("dBbot"), g.get("dBbot_prev"),
+                g.get("dIbot"), None)
+
+
+def emergent_intensity_scattering(plan: pprt.Plan, tau, q, Sg, omega, Bbot=None, Bbot_prev=None,
+                                  Ibot=None, Itop=None):
+    """Differentiable emergent intensity [nb, nf, na] with in-layer scattering."""
+    return EmergentIntensityScattering.apply(plan, tau, q, Sg, omega, Bbot, Bbot_prev, Ibot, Itop)

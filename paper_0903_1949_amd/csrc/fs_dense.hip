@@ -202,6 +202,29 @@ struct Grp {
     for (int j = 0; j < NA; ++j) acc = fmaT((T)A[j], vec(j, 0), acc);
     return acc;
   }
+  // (A^T x)_i
+  __device__ __forceinline__ T mvT(const T (&A)[NA], T x) {
+    put_mat(A);
+    put_vec(x, 0);
+    T acc = (T)0;
+#pragma unroll
+    for (int j = 0; j < NA; ++j) acc = fmaT(buf[j * RS + i], vec(j, 0), acc);
+    return acc;
+  }
+  // C = A^T
+  __device__ __forceinline__ void transpose(T (&C)[NA], const T (&A)[NA]) {
+    put_mat(A);
+#pragma unroll
+    for (int j = 0; j < NA; ++j) C[j] = buf[j * RS + i];
+  }
+  // sum over the group's rows of column i of A
+  __device__ __forceinline__ T colsum(const T (&A)[NA]) {
+    put_mat(A);
+    T acc = (T)0;
+#pragma unroll
+    for (int a = 0; a < NA; ++a) acc += buf[a * RS + i];
+    return acc;
+  }
   // sum over the group of v
   __device__ __forceinline__ T sum(T v) {
     put_vec(v, 1);
@@ -964,6 +987,391 @@ hipError_t run_dense_na(const DenseLaunch& L, hipStream_t s) {
   }
 }
 
+// ---- reverse mode of the emergent intensity (omega > 0, FP64) --------------
+// The emergent I+ at node 0 depends only on the composite of the layers below
+// each node, built bottom-up:
+//     R^up_{d-1} = r + t RG t,      RG = (I - R^up_d r)^-1 R^up_d,
+//     S^up_{d-1} = t (S^up_d + RG (r S^up_d - dS^g Q)) + dS^g Q,
+//     D+(0) = R^up_0 Sigma_0 + S^up_0,  Iemerg = D+(0) / sqrt(w) + S^g(0)
+// (layer a = d - 1, dS^g = S^g(d) - S^g(a), Sigma_0 = sqrt(w) (Itop - S^g(0)),
+// and at the bottom R^up = 0, S^up = sqrt(w) (Bbot - S^g + mu (Bbot - Bbot_prev)/D)
+// or sqrt(w) (Ibot - S^g)).  k_dense_up runs that recursion and keeps R^up,
+// S^up of every node and each layer's eigen solution; k_dense_vjp runs it
+// backwards from g = dL/dIemerg, top-down, with the cotangents of R^up and
+// S^up, and takes the derivative of t, r and Q in the layer optical depth D
+// from the eigen form (V, k fixed by the albedo): with x = k D / 2,
+//     dQ_T/dD = V diag(k^2/2 sech^2 x) V^T,   dQ_C'/dD = V diag(k (coth x - x csch^2 x)) V^T,
+//     dF_T = -F_T dQ_T F_T,   dF_C' = -F_C' (M + dQ_C') F_C',
+//     dr = M (dF_T + F_C' + D dF_C'),   dt = M (dF_T - F_C' - D dF_C'),   dQ = 2 M dF_C' sqrt(w) mu.
+// D = (q(a) + q(a+1)) (tau(a+1) - tau(a)) / 2 gives dL/dq; the S^g differences
+// and the boundary terms give dL/dS^g and dL/dBbot, dL/dBbot_prev or dL/dIbot.
+
+// the layer's t, r and Q (in o) with the rows of F_T and F_C' and the root's
+// derivative factors d(k tanh x)/dD and d(2 x coth x)/dD
+template <int NA>
+__device__ void layer_ops_grad(Grp<double, NA>& g, const LaneTab<double, NA>& L, const double (&V)[NA],
+                               double k_i, double Dl, LayerOps<double, NA>& o, double (&FT)[NA],
+                               double (&FC)[NA], double& dtx, double& dcx) {
+  const int i = g.i;
+  constexpr int RS = Slab<double, NA>::RS;
+  const double x = 0.5 * k_i * Dl;
+  const double th = tanh(x);
+  g.put_vec(k_i * th, 2);
+  g.put_vec(2.0 * x_coth_x(x), 3);
+  dtx = 0.5 * k_i * k_i * (1.0 - th * th);
+  if (x < 0.05) {
+    const double x2 = x * x;
+    dcx = k_i * x * (2.0 / 3.0 + x2 * (-4.0 / 45.0 + x2 * (4.0 / 315.0)));
+  } else {
+    const double sh = sinh(x);
+    dcx = k_i * (1.0 / th - x / (sh * sh));
+  }
+  double A[NA];
+  g.put_mat(V);
+  {
+    double vt[NA];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) vt[a] = V[a] * g.vec(a, 2);
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      double st = 0.0;
+#pragma unroll
+      for (int a = 0; a < NA; ++a) st = fma(vt[a], g.buf[j * RS + a], st);
+      A[j] = st;
+    }
+  }
+  A[i] += L.m;                  // M + Q_T
+  g.inv(FT, A);
+  g.put_mat(V);
+  {
+    double vc[NA];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) vc[a] = V[a] * g.vec(a, 3);
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      double st = 0.0;
+#pragma unroll
+      for (int a = 0; a < NA; ++a) st = fma(vc[a], g.buf[j * RS + a], st);
+      A[j] = st;
+    }
+  }
+  A[i] += Dl * L.m;             // D M + Q_C'
+  g.inv(FC, A);
+#pragma unroll
+  for (int j = 0; j < NA; ++j) {
+    const double ft = FT[j], fc = Dl * FC[j];
+    o.r[j] = L.m * (ft + fc) - ((j == i) ? 1.0 : 0.0);
+    o.t[j] = L.m * (ft - fc);
+  }
+  g.put_vec(L.swmu, 1);
+  double qv = 0.0;
+#pragma unroll
+  for (int j = 0; j < NA; ++j) qv = fma(FC[j], g.vec(j, 1), qv);
+  o.qv = 2.0 * L.m * qv;
+}
+
+template <int NA>
+struct DenseVjpArgs {
+  const Item* items;
+  const int64_t* off;
+  const double *tau, *q, *Sg, *omega, *Itop, *Bbot, *Bbot_prev, *Ibot, *gI;
+  double *dq, *dSg, *dBbot, *dBbot_prev, *dIbot;
+  double* wsR;   // [rows][nf][NA][NA]: R^up of each node
+  double* wsS;   // [rows][nf][NA]: S^up of each node
+  double* wsV;   // [rows][nf][NA][NA+1]: eigen solution of layer (d, d+1), row i and root k_i
+  uint32_t* status;
+  int32_t nf, nitems, lower_bc;
+};
+
+// the lane-group set-up shared by the two kernels
+#define PPRT_DENSE_GROUP_SETUP                                                              \
+  constexpr int F = 64 / NA;                                                                \
+  __shared__ double slab[F * Slab<double, NA>::SIZE];                                        \
+  const int lane = (int)threadIdx.x;                                                        \
+  const int grp = lane / NA;                                                                \
+  const int item = (int)blockIdx.x;                                                         \
+  if (item >= a.nitems) return;                                                             \
+  const Item it = a.items[item];                                                            \
+  const int b = it.b;                                                                       \
+  const int nd = it.nd;                                                                     \
+  const int nf = a.nf;                                                                      \
+  const int k = it.g * F + grp;                                                             \
+  if (k >= nf) return;                                                                      \
+  const int64_t row0 = a.off[b];                                                            \
+  Grp<double, NA> g{slab + grp * Slab<double, NA>::SIZE, lane % NA, 4 * (lane - lane % NA)}; \
+  const int i = g.i;                                                                        \
+  LaneTab<double, NA> L{};                                                                  \
+  _Pragma("unroll") for (int j = 0; j < NA; ++j) if (j == i) {                              \
+    L.mu = tb.mu[j]; L.m = tb.m[j]; L.d = tb.d[j]; L.z2 = tb.z2[j]; L.w = tb.w[j];          \
+    L.sw = tb.sw[j]; L.swmu = tb.swmu[j]; L.ext = tb.ext[j];                                \
+  }                                                                                         \
+  auto at = [&](const double* p, int64_t row) { return p[row * nf + k]; };                  \
+  auto layer_depth = [&](int d) {                                                           \
+    return 0.5 * (at(a.q, row0 + d) + at(a.q, row0 + d + 1)) * (a.tau[row0 + d + 1] - a.tau[row0 + d]); \
+  };                                                                                        \
+  auto layer_omega = [&](int d) {                                                           \
+    return a.omega ? 0.5 * (at(a.omega, row0 + d) + at(a.omega, row0 + d + 1)) : 0.0;      \
+  };                                                                                        \
+  double* wsR = a.wsR + ((row0 * nf + k) * NA + i) * NA;                                    \
+  double* wsS = a.wsS + (row0 * nf + k) * NA + i;                                           \
+  double* wsV = a.wsV + ((row0 * nf + k) * NA + i) * (NA + 1);                              \
+  const int64_t strideR = (int64_t)nf * NA * NA;                                            \
+  const int64_t strideS = (int64_t)nf * NA;                                                 \
+  const int64_t strideV = (int64_t)nf * NA * (NA + 1);
+
+// the bottom-up composites R^up, S^up of every node, and the eigen solutions
+template <int NA>
+__global__ __launch_bounds__(64, 1) void k_dense_up(DenseVjpArgs<NA> a, DenseTab<NA> tb) {
+  PPRT_DENSE_GROUP_SETUP
+  double Rup[NA];
+#pragma unroll
+  for (int j = 0; j < NA; ++j) Rup[j] = 0.0;
+  double Sup;
+  {
+    const double S_last = at(a.Sg, row0 + nd - 1);
+    if (a.lower_bc == PPRT_BC_DIFFUSION) {
+      const double Bb = a.Bbot[(int64_t)b * nf + k], Bp = a.Bbot_prev[(int64_t)b * nf + k];
+      Sup = L.sw * ((Bb - S_last) + L.mu * (Bb - Bp) / layer_depth(nd - 2));
+    } else {
+      const double Ib = a.Ibot ? a.Ibot[((int64_t)b * nf + k) * NA + L.ext] : 0.0;
+      Sup = L.sw * (Ib - S_last);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NA; ++j) wsR[(nd - 1) * strideR + j] = 0.0;
+  wsS[(nd - 1) * strideS] = Sup;
+  double V[NA], kk = 0.0, om_prev = -1.0, lam_prev = -1.0;
+  LayerOps<double, NA> op;
+  for (int d = nd - 1; d >= 1; --d) {
+    const int la = d - 1;
+    const double om = layer_omega(la);
+    if (om != om_prev) {
+      eigen<NA>(g, tb, L, om, V, kk, lam_prev);
+      om_prev = om;
+    }
+#pragma unroll
+    for (int j = 0; j < NA; ++j) wsV[la * strideV + j] = V[j];
+    wsV[la * strideV + NA] = kk;
+    layer_ops<NA>(g, tb, L, V, kk, layer_depth(la), op);
+    const double dSg = at(a.Sg, row0 + d) - at(a.Sg, row0 + la);
+    double X[NA], RG[NA];
+    g.mul(X, Rup, op.r);
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      X[j] = ((j == i) ? 1.0 : 0.0) - X[j];
+      RG[j] = Rup[j];
+    }
+    g.solve_mat(RG, X);                                  // RG = (I - R^up r)^-1 R^up
+    const double w1 = g.mv(RG, g.mv(op.r, Sup) - dSg * op.qv);
+    Sup = g.mv(op.t, Sup + w1) + dSg * op.qv;
+    double RGt[NA], tRGt[NA];
+    g.mul(RGt, RG, op.t);
+    g.mul(tRGt, op.t, RGt);
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      Rup[j] = op.r[j] + tRGt[j];
+      wsR[la * strideR + j] = Rup[j];
+    }
+    wsS[la * strideS] = Sup;
+  }
+}
+
+// reverse sweep, top-down: dL/dq, dL/dS^g and the boundary derivatives
+template <int NA>
+__global__ __launch_bounds__(64, 1) void k_dense_vjp(DenseVjpArgs<NA> a, DenseTab<NA> tb) {
+  PPRT_DENSE_GROUP_SETUP
+  (void)layer_omega;                  // the albedo enters through the stored eigen solutions
+  const int64_t bk = (int64_t)b * nf + k;
+  bool nonfinite = false;
+  double Rb[NA], Sb;
+  double dS_node, dq_node = 0.0;    // node being finished: its dL/dS^g and dL/dq so far
+  {
+    const double gI = a.gI[bk * NA + L.ext];
+    const double S0 = at(a.Sg, row0);
+    const double Sig0 = L.sw * ((a.Itop ? a.Itop[bk * NA + L.ext] : 0.0) - S0);
+    double Rup[NA];
+#pragma unroll
+    for (int j = 0; j < NA; ++j) Rup[j] = wsR[j];
+    const double Ipb = gI / L.sw;                       // D+(0) = R^up_0 Sigma_0 + S^up_0
+    dS_node = g.sum(gI);
+    g.put_vec(Sig0, 1);
+#pragma unroll
+    for (int j = 0; j < NA; ++j) Rb[j] = Ipb * g.vec(j, 1);
+    dS_node -= g.sum(L.sw * g.mvT(Rup, Ipb));
+    Sb = Ipb;
+  }
+  for (int d = 1; d < nd; ++d) {
+    const int la = d - 1;
+    double Rup[NA], V[NA];
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      Rup[j] = wsR[d * strideR + j];
+      V[j] = wsV[la * strideV + j];
+    }
+    const double Sup = wsS[d * strideS];
+    const double kk = wsV[la * strideV + NA];
+    const double Dl = layer_depth(la);
+    LayerOps<double, NA> op;
+    double FT[NA], FC[NA], dtx, dcx;
+    layer_ops_grad<NA>(g, L, V, kk, Dl, op, FT, FC, dtx, dcx);
+    const double dSg = at(a.Sg, row0 + d) - at(a.Sg, row0 + la);
+    // forward quantities of the step
+    double G[NA], RG[NA], T1[NA], T2[NA];
+    g.mul(T1, Rup, op.r);
+#pragma unroll
+    for (int j = 0; j < NA; ++j) T1[j] = ((j == i) ? 1.0 : 0.0) - T1[j];
+    g.inv(G, T1);                                        // G = (I - R^up r)^-1
+    g.mul(RG, G, Rup);
+    const double v = g.mv(op.r, Sup) - dSg * op.qv;
+    const double u = Sup + g.mv(RG, v);
+    // S^up' = t u + dS^g Q
+    double tb_[NA], rb[NA], RGb[NA];
+    g.put_vec(u, 1);
+#pragma unroll
+    for (int j = 0; j < NA; ++j) tb_[j] = Sb * g.vec(j, 1);
+    const double ub = g.mvT(op.t, Sb);
+    double dSgb = g.sum(op.qv * Sb);
+    double qvb = dSg * Sb;
+    double Supb = ub;
+    // u = S^up + RG v
+    g.put_vec(v, 1);
+#pragma unroll
+    for (int j = 0; j < NA; ++j) RGb[j] = ub * g.vec(j, 1);
+    const double vb = g.mvT(RG, ub);
+    // v = r S^up - dS^g Q
+    g.put_vec(Sup, 1);
+#pragma unroll
+    for (int j = 0; j < NA; ++j) rb[j] = vb * g.vec(j, 1) + Rb[j];   // + the R^up' = r + ... term
+    Supb += g.mvT(op.r, vb);
+    dSgb -= g.sum(op.qv * vb);
+    qvb -= dSg * vb;
+    // R^up' = r + t RG t: t gets Rb (RG t)^T + (t RG)^T Rb, RG gets t^T Rb t^T
+    g.mul(T1, RG, op.t);
+    g.transpose(T2, T1);
+    g.mul(T1, Rb, T2);
+#pragma unroll
+    for (int j = 0; j < NA; ++j) tb_[j] += T1[j];
+    g.mul(T1, op.t, RG);
+    g.transpose(T2, T1);
+    g.mul(T1, T2, Rb);
+#pragma unroll
+    for (int j = 0; j < NA; ++j) tb_[j] += T1[j];
+    double tT[NA];
+    g.transpose(tT, op.t);
+    g.mul(T1, tT, Rb);
+    g.mul(T2, T1, tT);
+#pragma unroll
+    for (int j = 0; j < NA; ++j) RGb[j] += T2[j];
+    // RG = G R^up: R^up gets G^T RGb (I + r RG)^T, r gets RG^T RGb RG^T
+    double Rupb[NA];
+    g.mul(T1, op.r, RG);
+#pragma unroll
+    for (int j = 0; j < NA; ++j) T1[j] += (j == i) ? 1.0 : 0.0;
+    g.transpose(T2, T1);                                 // (I + r RG)^T
+    g.transpose(T1, G);
+    g.mul(Rupb, T1, RGb);
+    g.mul(T1, Rupb, T2);
+#pragma unroll
+    for (int j = 0; j < NA; ++j) Rupb[j] = T1[j];
+    g.transpose(T2, RG);
+    g.mul(T1, T2, RGb);
+    g.mul(RG, T1, T2);                                   // RG no longer needed: RG^T RGb RG^T
+#pragma unroll
+    for (int j = 0; j < NA; ++j) rb[j] += RG[j];
+    // the layer optical depth: <tb, dt> + <rb, dr> + <Qb, dQ>
+    double part = 0.0;
+    {
+      double AT[NA], AC[NA];
+#pragma unroll
+      for (int j = 0; j < NA; ++j) {
+        AT[j] = L.m * (tb_[j] + rb[j]);
+        AC[j] = L.m * (rb[j] - tb_[j]);
+        part = fma(AC[j], FC[j], part);                  // <A_C, F_C'>
+      }
+      g.mul(T1, FT, AT);
+      g.mul(T2, T1, FT);                                 // B_T = F_T A_T F_T
+      g.mul(T1, T2, V);
+#pragma unroll
+      for (int j = 0; j < NA; ++j) T1[j] *= V[j];
+      part -= dtx * g.colsum(T1);                        // - sum_j dtx_j (V^T B_T V)_jj
+      const double c = g.mv(FC, L.swmu);                 // F_C' sqrt(w) mu
+      const double y = g.mv(FC, 2.0 * L.m * qvb);        // F_C' (2 M Qb)
+      g.mul(T1, FC, AC);
+      g.mul(T2, T1, FC);
+      g.put_vec(c, 1);
+#pragma unroll
+      for (int j = 0; j < NA; ++j) T2[j] = Dl * T2[j] + y * g.vec(j, 1);   // B_C
+      double bcd = 0.0;
+#pragma unroll
+      for (int j = 0; j < NA; ++j)
+        if (j == i) bcd = T2[j];
+      part -= L.m * bcd;                                 // - <B_C, M>
+      g.mul(T1, T2, V);
+#pragma unroll
+      for (int j = 0; j < NA; ++j) T1[j] *= V[j];
+      part -= dcx * g.colsum(T1);                        // - sum_j dcx_j (V^T B_C V)_jj
+    }
+    const double Dlb = g.sum(part);
+    const double h = 0.5 * (a.tau[row0 + d] - a.tau[row0 + la]);
+    // node la is finished (layer la - 1 below it came first)
+    dq_node += h * Dlb;
+    dS_node -= dSgb;
+    nonfinite |= !isfinite(dq_node + dS_node);
+    if (i == 0) {
+      a.dq[(row0 + la) * nf + k] = dq_node;
+      a.dSg[(row0 + la) * nf + k] = dS_node;
+    }
+    dq_node = h * Dlb;
+    dS_node = dSgb;
+    Sb = Supb;
+#pragma unroll
+    for (int j = 0; j < NA; ++j) Rb[j] = Rupb[j];
+  }
+  // the lower boundary
+  dS_node -= g.sum(L.sw * Sb);
+  if (a.lower_bc == PPRT_BC_DIFFUSION) {
+    const double Dl = layer_depth(nd - 2);
+    const double Bb = a.Bbot[bk], Bp = a.Bbot_prev[bk];
+    const double swSb = g.sum(L.sw * Sb), swmuSb = g.sum(L.swmu * Sb);
+    const double Dlb = -swmuSb * (Bb - Bp) / (Dl * Dl);
+    const double h = 0.5 * (a.tau[row0 + nd - 1] - a.tau[row0 + nd - 2]);
+    dq_node += h * Dlb;
+    if (i == 0) {
+      a.dq[(row0 + nd - 2) * nf + k] += h * Dlb;       // the last layer's depth also sets the gradient
+      if (a.dBbot) a.dBbot[bk] = swSb + swmuSb / Dl;
+      if (a.dBbot_prev) a.dBbot_prev[bk] = -swmuSb / Dl;
+    }
+  } else if (a.dIbot) {
+    a.dIbot[bk * NA + L.ext] = L.sw * Sb;
+  }
+  nonfinite |= !isfinite(dq_node + dS_node);
+  if (i == 0) {
+    a.dq[(row0 + nd - 1) * nf + k] = dq_node;
+    a.dSg[(row0 + nd - 1) * nf + k] = dS_node;
+  }
+  if (nonfinite && a.status && i == 0) atomicOr(a.status, PPRT_DEV_NONFINITE);
+}
+#undef PPRT_DENSE_GROUP_SETUP
+
+template <int NA>
+hipError_t run_dense_vjp(const DenseVjpLaunch& L, hipStream_t s) {
+  DenseVjpArgs<NA> a{};
+  a.items = L.items; a.off = L.off; a.tau = L.tau; a.q = L.q; a.Sg = L.Sg; a.omega = L.omega;
+  a.Itop = L.Itop; a.Bbot = L.Bbot; a.Bbot_prev = L.Bbot_prev; a.Ibot = L.Ibot; a.gI = L.gI;
+  a.dq = L.dq; a.dSg = L.dSg; a.dBbot = L.dBbot; a.dBbot_prev = L.dBbot_prev; a.dIbot = L.dIbot;
+  const size_t rf = (size_t)L.rows * L.nf;
+  a.wsR = (double*)L.ws;
+  a.wsS = a.wsR + rf * NA * NA;
+  a.wsV = a.wsS + rf * NA;
+  a.status = L.status;
+  a.nf = L.nf; a.nitems = L.nitems; a.lower_bc = L.lower_bc;
+  DenseTab<NA> tb{};
+  fill_tab<NA>(tb, L.mu, L.w);
+  hipLaunchKernelGGL((k_dense_up<NA>), dim3(L.nitems), dim3(64), 0, s, a, tb);
+  hipLaunchKernelGGL((k_dense_vjp<NA>), dim3(L.nitems), dim3(64), 0, s, a, tb);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 bool dense_na_supported(int na) { return na == 1 || na == 2 || na == 4 || na == 8 || na == 16 || na == 32; }
@@ -981,6 +1389,23 @@ size_t dense_workspace_bytes(int na, int64_t rows, int nf, int precision) {
 int dense_freqs_per_item(int na, int precision) {
   if (dense_mfma_na(na)) return 1;
   return na <= 64 ? 64 / na : 1;
+}
+
+size_t dense_vjp_workspace_bytes(int na, int64_t rows, int nf) {
+  // R^up (na^2) and S^up (na) of every node, the eigen solution (na^2 + na) of every layer
+  return (size_t)rows * nf * (size_t)(2 * na * na + 2 * na) * sizeof(double);
+}
+
+hipError_t launch_dense_vjp(const DenseVjpLaunch& L, hipStream_t s) {
+  if (L.nitems == 0) return hipSuccess;
+  switch (L.na) {
+    case 1: return run_dense_vjp<1>(L, s);
+    case 2: return run_dense_vjp<2>(L, s);
+    case 4: return run_dense_vjp<4>(L, s);
+    case 8: return run_dense_vjp<8>(L, s);
+    case 16: return run_dense_vjp<16>(L, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_fs_dense(const DenseLaunch& L, hipStream_t s) {

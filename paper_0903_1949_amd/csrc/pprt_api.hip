@@ -1605,6 +1605,48 @@ pprt_status pprt_formal_solution_vjp(pprt_plan* p, const pprt_fs_in* in, int32_t
   return hip_check(c, e, "adjoint launch");
 }
 
+// ---- reverse mode of the emergent intensity with in-layer scattering ------
+
+pprt_status pprt_plan_scattering_vjp_workspace_bytes(const pprt_plan* p, size_t* bytes) {
+  if (!p || !bytes) return PPRT_E_INVALID_ARG;
+  *bytes = dense_vjp_workspace_bytes(p->na, p->rows, p->nf);
+  return PPRT_OK;
+}
+
+pprt_status pprt_formal_solution_scattering_vjp(pprt_plan* p, const pprt_fs_in* in, const void* omega,
+                                                const void* gIemerg, const pprt_fs_grad* g, void* ws) {
+  if (!p) return PPRT_E_INVALID_ARG;
+  pprt_ctx* c = p->ctx;
+  if (p->precision != PPRT_FP64 || !(p->na == 1 || p->na == 2 || p->na == 4 || p->na == 8 || p->na == 16))
+    return fail(c, PPRT_E_UNSUPPORTED, "the scattering VJP needs an FP64 plan with na in {1,2,4,8,16} "
+                "(got %s, na %d)", p->precision == PPRT_FP64 ? "FP64" : "FP32", p->na);
+  if (!in || !omega || !gIemerg || !g || !g->dq || !g->dSg)
+    return fail(c, PPRT_E_INVALID_ARG, "in, omega, gIemerg, grad->dq and grad->dSg are required");
+  if (!in->tau || !in->q || !in->Sg) return fail(c, PPRT_E_INVALID_ARG, "tau, q and Sg are required");
+  if (p->lower_bc == PPRT_BC_DIFFUSION && (!in->Bbot || !in->Bbot_prev))
+    return fail(c, PPRT_E_INVALID_ARG, "diffusion lower boundary needs Bbot and Bbot_prev");
+  if (!ws) return fail(c, PPRT_E_WORKSPACE, "workspace of %zu bytes required",
+                       dense_vjp_workspace_bytes(p->na, p->rows, p->nf));
+  {
+    pprt_status v = validate_fs_in(p, in, nullptr);
+    if (v == PPRT_OK && (c->validate & PPRT_VALIDATE_INPUTS))
+      v = validate_array(c, omega, p->rows * (int64_t)p->nf, 8, "omega", false);
+    if (v != PPRT_OK) return v;
+  }
+  DenseVjpLaunch L{};
+  L.items = p->d_items_dense; L.off = p->d_off; L.tau = in->tau;
+  L.q = (const double*)in->q; L.Sg = (const double*)in->Sg; L.omega = (const double*)omega;
+  L.Itop = (const double*)in->Itop; L.Bbot = (const double*)in->Bbot;
+  L.Bbot_prev = (const double*)in->Bbot_prev; L.Ibot = (const double*)in->Ibot;
+  L.gI = (const double*)gIemerg;
+  L.dq = (double*)g->dq; L.dSg = (double*)g->dSg; L.dBbot = (double*)g->dBbot;
+  L.dBbot_prev = (double*)g->dBbot_prev; L.dIbot = (double*)g->dIbot;
+  L.ws = ws; L.status = c->d_status;
+  L.rows = p->rows; L.nf = p->nf; L.na = p->na; L.nitems = p->n_dense; L.lower_bc = p->lower_bc;
+  L.mu = p->mu.data(); L.w = p->w.data();
+  return hip_check(c, launch_dense_vjp(L, c->stream), "scattering VJP launch");
+}
+
 // ---- launch shape of the batched sweep and its autotuner -----------------
 
 pprt_status pprt_plan_set_launch(pprt_plan* p, int32_t wpb, int32_t persistent_waves_per_cu) {

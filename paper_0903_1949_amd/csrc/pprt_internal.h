@@ -235,6 +235,22 @@ bool dense_mfma_na(int na);
 size_t dense_mfma_workspace_bytes(int na, int64_t rows, int nf, int precision);
 hipError_t launch_fs_dense_mfma(const DenseLaunch& L, hipStream_t s);
 hipError_t launch_fs_dense(const DenseLaunch& L, hipStream_t s);
+// Reverse mode of the emergent intensity with in-layer scattering (FP64, na <= 16)
+struct DenseVjpLaunch {
+  const Item* items;
+  const int64_t* off;
+  const double *tau, *q, *Sg, *omega, *Itop, *Bbot, *Bbot_prev, *Ibot, *gI;
+  double *dq, *dSg, *dBbot, *dBbot_prev, *dIbot;
+  void* ws;
+  uint32_t* status;
+  int64_t rows;
+  int32_t nf, na, nitems, lower_bc;
+  const double* mu;   // host, ascending
+  const double* w;
+};
+size_t dense_vjp_workspace_bytes(int na, int64_t rows, int nf);
+hipError_t launch_dense_vjp(const DenseVjpLaunch& L, hipStream_t s);
+
 
 // Spherical formal solution (sph.hip).
 struct SphRay {

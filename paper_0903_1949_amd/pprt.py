@@ -167,6 +167,8 @@ def load_library(path: str = LIB_PATH):
                                    C.POINTER(TuneReport)]),
         "pprt_emergent_intensity": (I, [P, C.POINTER(FsIn), C.c_int32, P, P]),
         "pprt_formal_solution_vjp": (I, [P, C.POINTER(FsIn), C.c_int32, P, C.POINTER(FsGrad), P]),
+        "pprt_plan_scattering_vjp_workspace_bytes": (I, [P, C.POINTER(C.c_size_t)]),
+        "pprt_formal_solution_scattering_vjp": (I, [P, C.POINTER(FsIn), P, P, C.POINTER(FsGrad), P]),
         "pprt_vox_plan_create": (I, [P, C.POINTER(VoxGrid), C.c_int32, C.c_int32, D, C.c_int32, C.c_int32,
                                      C.POINTER(P)]),
         "pprt_vox_plan_info": (I, [P, C.POINTER(VoxInfo)]),
@@ -520,6 +522,37 @@ class Plan:
         self.ctx._check(self.lib.pprt_formal_solution_vjp(self.h, C.byref(fin), int(checkpoint_interval),
                                                           _ptr(gIemerg), C.byref(fg), _ptr(workspace)),
                         "formal_solution_vjp")
+        return g
+
+    def formal_solution_scattering_vjp(self, tau, q, Sg, omega, gIemerg, Bbot=None, Bbot_prev=None,
+                                       Itop=None, Ibot=None, workspace=None) -> dict:
+        """pprt_formal_solution_scattering_vjp: dL/dq, dL/dSg and the lower-boundary
+        adjoints of the emergent intensity with in-layer scattering (omega and
+        Itop held fixed).  The returned dict keeps the workspace under
+        "_workspace" for reuse."""
+        import torch
+        fin = self.fs_in(tau, q, Sg, Bbot, Bbot_prev, Itop, Ibot)
+        self._want(omega, (self.rows, self.nf), self.dtype, "omega")
+        self._want(gIemerg, (self.nb, self.nf, self.na), self.dtype, "gIemerg")
+        R, nf, na, nb, dt, dev = self.rows, self.nf, self.na, self.nb, self.dtype, tau.device
+        if workspace is None:
+            nbytes = C.c_size_t()
+            self.ctx._check(self.lib.pprt_plan_scattering_vjp_workspace_bytes(self.h, C.byref(nbytes)),
+                            "scattering_vjp_workspace_bytes")
+            workspace = torch.empty(max(int(nbytes.value), 1), dtype=torch.uint8, device=dev)
+        g = {"dq": torch.empty((R, nf), dtype=dt, device=dev),
+             "dSg": torch.empty((R, nf), dtype=dt, device=dev)}
+        if self.lower_bc == BC_DIFFUSION:
+            g["dBbot"] = torch.empty((nb, nf), dtype=dt, device=dev)
+            g["dBbot_prev"] = torch.empty((nb, nf), dtype=dt, device=dev)
+        else:
+            g["dIbot"] = torch.empty((nb, nf, na), dtype=dt, device=dev)
+        fg = FsGrad(**{k: _ptr(v) for k, v in g.items()})
+        self.ctx._check(self.lib.pprt_formal_solution_scattering_vjp(self.h, C.byref(fin), _ptr(omega),
+                                                                     _ptr(gIemerg), C.byref(fg),
+                                                                     _ptr(workspace)),
+                        "formal_solution_scattering_vjp")
+        g["_workspace"] = workspace
         return g
 
     def set_thick_mode(self, mode: int):

@@ -100,6 +100,8 @@ def test_null_arguments_rejected_without_device():
     assert lib.pprt_plan_set_thick_mode(None, 0) == 1
     assert lib.pprt_thick_counts(None, None, None) == 1
     assert lib.pprt_thick_counts_reset(None) == 1
+    assert lib.pprt_plan_scattering_vjp_workspace_bytes(None, None) == 1
+    assert lib.pprt_formal_solution_scattering_vjp(None, None, None, None, None, None) == 1
     assert lib.pprt_last_error(None) == b""
     lib.pprt_destroy(None)
     lib.pprt_plan_destroy(None)
