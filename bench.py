@@ -1087,6 +1087,40 @@ def bench_adjoint(args):
     fwd_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1, _ in evs]))
     tot_ms = float(np.mean([e0.elapsed_time(e2) for e0, _, e2 in evs]))
     achieved = pts * ADJ_FLOPS_PER_POINT / (tot_ms * 1e-3) / 1e12
+
+    # the same atmosphere with a grey coherent scatterer (albedo 0.5 at every
+    # node), FP64: the forward with in-layer scattering and its hand-written VJP
+    plan64 = pprt.Plan(ctx, [nd], na, nf, precision=pprt.FP64, outputs=pprt.OUT_IEMERG)
+    q64, B64 = q.double(), B.double()
+    om64 = torch.full_like(q64, 0.5)
+    Bb64, Bp64 = B64[-1:].contiguous(), B64[-2:-1].contiguous()
+    wsd, wsv = {}, {}
+
+    def dense_step(e0=None, e1=None, e2=None):
+        if e0 is not None:
+            e0.record(stream)
+        out = plan64.formal_solution_scattering(tau, q64, B64, om64, Bbot=Bb64, Bbot_prev=Bp64,
+                                                workspace=wsd.get("w"))
+        wsd["w"] = out["_workspace"]
+        if e1 is not None:
+            e1.record(stream)
+        gv = plan64.formal_solution_scattering_vjp(tau, q64, B64, om64, 2.0 * out["Iemerg"], Bbot=Bb64,
+                                                   Bbot_prev=Bp64, workspace=wsv.get("w"))
+        wsv["w"] = gv["_workspace"]
+        if e2 is not None:
+            e2.record(stream)
+
+    dense_step()
+    torch.cuda.synchronize()
+    devs = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(3)]
+    for e0, e1, e2 in devs:
+        dense_step(e0, e1, e2)
+    torch.cuda.synchronize()
+    dense_leg = {"forward_ms": round(float(np.median([e0.elapsed_time(e1) for e0, e1, _ in devs])), 3),
+                 "vjp_ms": round(float(np.median([e1.elapsed_time(e2) for _, e1, e2 in devs])), 3),
+                 "what": "albedo 0.5 at every node, FP64: pprt_formal_solution_scattering (Iemerg) and "
+                         "pprt_formal_solution_scattering_vjp (dL/dq, dL/dS^g)"}
+    del wsd, wsv
     cpu = None
     if not args.no_cpu_baseline:
         from threadpoolctl import threadpool_limits
@@ -1116,6 +1150,7 @@ def bench_adjoint(args):
                      "kernel_ms": round(tot_ms, 4), "forward_ms": round(fwd_ms, 4),
                      "flops_per_point": ADJ_FLOPS_PER_POINT,
                      "note": "a single atmosphere: 4096 x 16 lanes, one wave per SIMD; latency-bound"},
+        "with_scattering": dense_leg,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
