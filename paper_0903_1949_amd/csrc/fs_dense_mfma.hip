@@ -217,8 +217,8 @@ __device__ void gj(const W<T>& w, Mat<T>& A, v4d (&X)[T][TX]) {
   double* br = w.s + Lay<T>::BR;
   double* bc = w.s + Lay<T>::BC;
 #pragma unroll
-  for (int tb = 0; tb < T; ++tb)         // the block's tile (static: tiles stay in registers)
-#pragma unroll 1
+  for (int tb = 0; tb < T; ++tb)         // the block's tile and register, both static: the tiles
+#pragma unroll                           // stay in (accumulation) registers, read and written in place
   for (int qb = 0; qb < 4; ++qb) {       // block rows 4 b + g: tile row tb, register qb
     const int b = 4 * tb + qb;
     wsync();
@@ -227,12 +227,12 @@ __device__ void gj(const W<T>& w, Mat<T>& A, v4d (&X)[T][TX]) {
 #pragma unroll
     for (int tj = 0; tj < T; ++tj) {
       const v4d a = A.t[tb][tj];
-      br[w.g * LW + 16 * tj + w.c] = qb == 0 ? a[0] : qb == 1 ? a[1] : qb == 2 ? a[2] : a[3];
+      br[w.g * LW + 16 * tj + w.c] = a[qb];
     }
 #pragma unroll
     for (int tj = 0; tj < TX; ++tj) {
       const v4d a = X[tb][tj];
-      br[w.g * LW + 16 * (T + tj) + w.c] = qb == 0 ? a[0] : qb == 1 ? a[1] : qb == 2 ? a[2] : a[3];
+      br[w.g * LW + 16 * (T + tj) + w.c] = a[qb];
     }
     if ((w.c >> 2) == qb) {
 #pragma unroll
@@ -263,8 +263,9 @@ __device__ void gj(const W<T>& w, Mat<T>& A, v4d (&X)[T][TX]) {
           for (int j = 0; j < 4; ++j) M[i][j] = fma(-f, M[kk][j], M[i][j]);
         }
     }
-    // P^-1 to LDS (lane 4 i + j < 16 writes element (i, j)), after every lane
-    // has read the pivot block
+    // P^-1 to LDS (lane 4 i + j < 16 writes element (i, j); a store from one
+    // lane of all sixteen measured slower), after every lane has read the
+    // pivot block
     double piv = 0.0;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
