@@ -222,9 +222,11 @@ pprt_status pprt_formal_solution(pprt_plan* plan, const pprt_fs_in* in, pprt_fs_
  * pprt_plan_scattering_workspace_bytes() per node and frequency:
  * 8 (2 na^2 + 4 na) bytes in FP64 plans with na <= 16 (the composite
  * reflection and source of every node, two unit-source responses of each
- * layer and each layer's eigen solution), 8 (na^2 + 3 na) bytes in FP64 plans
- * with na = 32 and 4 (na^2 + 3 na) bytes in FP32 plans (the same without the
- * eigen solutions, which the bottom-up pass recomputes), kept between the
+ * layer and each layer's eigen solution), 4 (na^2 + 3 na) bytes in FP32 plans
+ * with na <= 16 (the same without the eigen solutions, which the bottom-up
+ * pass recomputes), and with na = 32 8 or 4 (na^2 + 3 na) bytes (FP64 or FP32
+ * plans) plus 16 na bytes for the secular-equation roots of every layer,
+ * solved apart before the recursion, kept between the
  * top-down and the bottom-up pass; omega = 0 everywhere reproduces
  * pprt_formal_solution to rounding. */
 pprt_status pprt_plan_scattering_workspace_bytes(const pprt_plan* plan, size_t* bytes);

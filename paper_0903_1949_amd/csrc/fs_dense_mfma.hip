@@ -25,14 +25,18 @@
 //   M + Q_T and D M + Q_C' (symmetric positive definite) or
 //   I - (reflection)(reflection)), by blocks of four columns: the block's
 //   four rows and four columns go to LDS, every lane inverts the 4 x 4 pivot
-//   block, and one rank-4 update W -= C (P^-1 B) per tile pair runs on the
-//   matrix cores (the block rows take C = P - I, so they become P^-1 B).
+//   block, the other rows take one rank-4 update W -= C (P^-1 B) per tile
+//   pair on the matrix cores, and the block rows are set to P^-1 B (the loop
+//   over blocks is unrolled, so every tile and register index is static).
 // * Mat-vec products: the vector goes through the slab, each lane multiplies
 //   its tile elements and the sixteen lanes of a row group reduce by
 //   cross-lane shuffles; sums over angles reduce across the wave.
-// * The eigen solution (one root per lane) is recomputed in the pass up
-//   instead of stored; the workspace keeps R, Sigma and two unit-source
-//   responses per node: 8 (NA^2 + 3 NA) bytes per node and frequency.
+// * The secular-equation roots of every layer are solved apart, before the
+//   recursion, by k_mf_roots (one thread per frequency and root, at full
+//   occupancy) and kept in the workspace; both passes rebuild the
+//   eigenvectors from them.  The workspace keeps R, Sigma and two unit-source
+//   responses per node in the plan's type and the roots in FP64:
+//   (NA^2 + 3 NA) reals + 16 NA bytes per node and frequency.
 #include "pprt_internal.h"
 
 namespace pprt {
@@ -428,22 +432,24 @@ __device__ __forceinline__ double row_m(const W<T>& w, int ti, int q) {
 
 // eigen solution (V in the slab's A0 area, row-major) and the layer operators
 template <int T>
-__device__ void layer(const W<T>& w, double om, double Dl, double& lam_prev, double& om_prev, Ops<T>& o) {
+__device__ void layer(const W<T>& w, double om, double Dl, const double* roots, double& om_prev, Ops<T>& o) {
   constexpr int NA = 16 * T;
   constexpr int LA = Lay<T>::LA;
   double* s = w.s;
   const int i = w.lane;
   if (om != om_prev) {
+    // the layer's roots (origin and offset, from k_mf_roots)
     double org = 0.0, del = 0.0;
-    if (i < NA)
-      secular_root<NA>(i, om, lam_prev, s + Lay<T>::TD, s + Lay<T>::TZ2, s + Lay<T>::TW, org, del);
+    if (i < NA) {
+      org = roots[2 * i];
+      del = roots[2 * i + 1];
+    }
     wsync();
     if (i < NA) {
       s[Lay<T>::RT + 2 * i] = org;
       s[Lay<T>::RT + 2 * i + 1] = del;
     }
     wsync();
-    if (i < NA) lam_prev = org + del;
     // Gu-Eisenstat zhat_i, then the column norms
     if (i < NA && om > 0.0) {
       const double dl = s[Lay<T>::TD + i];
@@ -588,11 +594,54 @@ struct MfArgs {
   S* wsR;          // [rows][nf][NA][NA]
   S* wsS;          // [rows][nf][NA]
   S* wsZ;          // [rows][nf][NA][2]
+  double* wsRT;    // [rows][nf][NA][2]: the secular-equation roots (origin, offset) of layer (d, d+1)
   uint32_t* status;
   unsigned long long* thick_stats;   // FP32 plans: [FP64 eliminations, all eliminations]
   int32_t nf, nitems, lower_bc;
   uint32_t outputs;
 };
+
+// The secular-equation roots of every layer, apart from the formal solution:
+// one thread per (frequency, root), two frequencies per wave, each thread
+// walking down its column and starting every layer's Newton iteration from
+// its own root of the layer above (the albedo changes with depth in a real
+// atmosphere, and inside the one-wave-per-SIMD formal solution these
+// iterations were a third of its instructions).  A layer whose albedo equals
+// the one above keeps its roots.
+template <int T, typename S>
+__global__ __launch_bounds__(64) void k_mf_roots(MfArgs<S> a, MfTab<16 * T> tb) {
+  constexpr int NA = 16 * T;
+  static_assert(64 % NA == 0, "whole columns per wave");
+  __shared__ double td[NA], tz2[NA], tw[NA];
+  const int t = (int)threadIdx.x;
+  if (t < NA) {
+    td[t] = tb.d[t];
+    tz2[t] = tb.z2[t];
+    tw[t] = tb.w[t];
+  }
+  __syncthreads();
+  const int item = (int)blockIdx.x * (64 / NA) + t / NA;
+  const int i = t % NA;
+  if (item >= a.nitems) return;
+  const Item it = a.items[item];
+  const int nd = it.nd, nf = a.nf, k = it.g;
+  if (k >= nf) return;
+  const int64_t row0 = a.off[it.b];
+  double* out = a.wsRT + ((row0 * nf + k) * NA + i) * 2;
+  const int64_t stride = (int64_t)nf * NA * 2;
+  double om_prev = -1.0, lam_prev = -1.0, org = 0.0, del = 0.0;
+  for (int d = 0; d < nd - 1; ++d) {
+    const double om = a.omega ? 0.5 * ((double)a.omega[(row0 + d) * nf + k] + (double)a.omega[(row0 + d + 1) * nf + k])
+                              : 0.0;
+    if (om != om_prev) {
+      secular_root<NA>(i, om, lam_prev, td, tz2, tw, org, del);
+      lam_prev = org + del;
+      om_prev = om;
+    }
+    out[d * stride] = org;
+    out[d * stride + 1] = del;
+  }
+}
 
 template <int T, int PASS, typename S>
 __global__ __launch_bounds__(64) void k_fs_dense_mfma(MfArgs<S> a, MfTab<16 * T> tb) {
@@ -637,7 +686,9 @@ __global__ __launch_bounds__(64) void k_fs_dense_mfma(MfArgs<S> a, MfTab<16 * T>
   S* wsZ = a.wsZ + (row0 * nf + k) * NA * 2;
   const bool wd = (o & PPRT_OUT_LSTAR) != 0;
   const bool we = (o & PPRT_OUT_LSTAR_C) != 0;
-  double lam_prev = -1.0, om_prev = -1.0;
+  double om_prev = -1.0;
+  const double* wsRT = a.wsRT + (row0 * nf + k) * NA * 2;   // + layer * nf * NA * 2
+  const int64_t strideRT = (int64_t)nf * NA * 2;
   Ops<T> op;
 
   auto save_mat = [&](S* dst, const Mat<T>& M) {
@@ -672,7 +723,7 @@ __global__ __launch_bounds__(64) void k_fs_dense_mfma(MfArgs<S> a, MfTab<16 * T>
     for (int d = 0; d < nd - 1; ++d) {
       save_mat(wsR + d * strideR, R);
       if (act) wsS[d * strideS + lane] = (S)Sig;
-      layer<T>(w, layer_omega(d), layer_depth(d), lam_prev, om_prev, op);
+      layer<T>(w, layer_omega(d), layer_depth(d), wsRT + d * strideRT, om_prev, op);
       const double dSg = at(a.Sg, row0 + d + 1) - at(a.Sg, row0 + d);
       // G = (I - r R)^-1: P = G t, u = G (r Sigma + dS^g Q) and the unit
       // responses G beta_l+ and G Q, from one elimination on I - r R
@@ -747,7 +798,7 @@ __global__ __launch_bounds__(64) void k_fs_dense_mfma(MfArgs<S> a, MfTab<16 * T>
     }
     for (int d = nd - 1; d >= 0; --d) {
       const bool has_a = d >= 1;
-      if (has_a) layer<T>(w, layer_omega(d - 1), layer_depth(d - 1), lam_prev, om_prev, op);
+      if (has_a) layer<T>(w, layer_omega(d - 1), layer_depth(d - 1), wsRT + (d - 1) * strideRT, om_prev, op);
       Mat<T> Rd;
       load_mat(wsR + d * strideR, Rd);
       const double Sd = act ? (double)wsS[d * strideS + lane] : 0.0;
@@ -856,6 +907,7 @@ hipError_t run_mfma(const DenseLaunch& L, hipStream_t s) {
   a.wsR = (S*)L.ws;
   a.wsS = a.wsR + rf * NA * NA;
   a.wsZ = a.wsS + rf * NA;
+  a.wsRT = (double*)(a.wsZ + rf * NA * 2);
   a.status = L.status;
   a.thick_stats = L.thick_stats;
   a.nf = L.nf; a.nitems = L.nitems; a.lower_bc = L.lower_bc; a.outputs = L.outputs;
@@ -866,6 +918,7 @@ hipError_t run_mfma(const DenseLaunch& L, hipStream_t s) {
     tb.mu[i] = m; tb.m[i] = 1.0 / m; tb.d[i] = 1.0 / (m * m); tb.w[i] = wt;
     tb.z2[i] = wt / (m * m); tb.sw[i] = sqrt(wt); tb.swmu[i] = sqrt(wt) * m;
   }
+  hipLaunchKernelGGL((k_mf_roots<T, S>), dim3((L.nitems + 64 / NA - 1) / (64 / NA)), dim3(64), 0, s, a, tb);
   hipLaunchKernelGGL((k_fs_dense_mfma<T, 1, S>), dim3(L.nitems), dim3(64), 0, s, a, tb);
   hipLaunchKernelGGL((k_fs_dense_mfma<T, 2, S>), dim3(L.nitems), dim3(64), 0, s, a, tb);
   return hipGetLastError();
@@ -876,7 +929,11 @@ hipError_t run_mfma(const DenseLaunch& L, hipStream_t s) {
 bool dense_mfma_na(int na) { return na == 32; }
 
 size_t dense_mfma_workspace_bytes(int na, int64_t rows, int nf, int precision) {
-  return (size_t)rows * nf * (size_t)(na * na + 3 * na) * (precision == PPRT_FP64 ? sizeof(double) : sizeof(float));
+  // R, Sigma and the two unit-source responses in the plan's type, then the
+  // roots of every layer (origin and offset) in FP64
+  const size_t rf = (size_t)rows * nf;
+  return rf * (size_t)(na * na + 3 * na) * (precision == PPRT_FP64 ? sizeof(double) : sizeof(float)) +
+         rf * (size_t)(2 * na) * sizeof(double);
 }
 
 hipError_t launch_fs_dense_mfma(const DenseLaunch& L, hipStream_t s) {
