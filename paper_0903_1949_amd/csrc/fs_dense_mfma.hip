@@ -3,7 +3,7 @@
 // problem) on the FP64 matrix cores of gfx950.  The code is written for
 // NA = 16 T; only T = 2 is built: at NA = 16 the lane-per-row kernel of
 // fs_dense.hip, whose 16 x 16 operators fit one lane's registers row by row,
-// is faster (36 against 51 ms on a 64-atmosphere, 256-frequency batch).
+// is faster (36 against 48 ms on a 64-atmosphere, 256-frequency batch).
 //
 // The method is that of fs_dense.hip (the same homogeneous-layer operators
 // t, r, beta from the discrete-ordinate eigen solution, the adding recursion
