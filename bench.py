@@ -86,6 +86,8 @@ def parse():
                          "voigt: the multilevel atom with depth-dependent Voigt lines")
     ap.add_argument("--voigt-nb", type=int, default=64, help="voigt: atmospheres in the batch")
     ap.add_argument("--c5-steps", type=int, default=3, help="c5: timed multilevel iterations")
+    ap.add_argument("--adj-k", type=int, default=16, choices=[1, 8, 16, 32],
+                    help="adjoint: layer checkpoint interval")
     ap.add_argument("--conv-tol", type=float, default=1e-6,
                     help="nonlocal: tolerance of the convergence comparison")
     ap.add_argument("--conv-max-iter", type=int, default=4000)
@@ -1059,7 +1061,7 @@ def bench_adjoint(args):
     q = d(np.outer(g.c, g.f), torch.float32)
     B = d(g.B, torch.float32)
     Bb, Bp = B[-1:].contiguous(), B[-2:-1].contiguous()
-    K = 16
+    K = args.adj_k
     ws = torch.empty(max(plan.adjoint_workspace_bytes(K), 256), dtype=torch.uint8, device="cuda:0")
     stream = torch.cuda.current_stream()
 
@@ -1142,7 +1144,7 @@ def bench_adjoint(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "one atmosphere, nd 256, tau 1e-4..1e4, na 16, nf 4096 (nu 1.5e14..3e15 Hz), "
                                "lognormal per-depth opacity, B_nu of a grey Eddington T(tau), seed 4; "
-                               "loss sum of I+(tau_1)^2, checkpoints every 16 nodes",
+                               f"loss sum of I+(tau_1)^2, checkpoints every {K} nodes",
                    "nd": nd, "na": na, "nf": nf, "points_per_step": pts, "checkpoint_interval": K},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VALU_NONPACKED,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU_NONPACKED, 4),

@@ -4,7 +4,8 @@ block layer operators, on the matrix cores) and 16384 frequencies.
 
 * The scattering formal solution over the whole frequency grid, compared
   with the oracle at 64 seeded frequencies (line cores and wings of
-  strong and weak lines, continua), all depths and angles.
+  strong and weak lines, continua), all depths and angles; the same on an
+  FP32 plan at 16 frequencies against the oracle on FP32-rounded inputs.
 * Rate assembly and the 20-level statistical-equilibrium solve at full size
   on seeded radiation fields, against the oracle.
 * One full multilevel iteration of the same atom on a reduced grid (10
@@ -74,6 +75,38 @@ def test_c5_formal_solution_full_grid_sampled(gpu_ctx, c5):
     for k, e in errs.items():
         assert e < 1e-10, (k, e)
     assert np.isfinite(got["J"]).all() and np.isfinite(got["lstar"]).all()
+
+
+def test_c5_formal_solution_fp32_plan_full_grid_sampled(gpu_ctx, c5):
+    """The same formal solution on an FP32 plan (FP32 arrays and workspace,
+    FP64 arithmetic at 32 angles) against the oracle on the FP32-rounded
+    inputs at 16 sampled frequencies: the FP32 contract of the dense path
+    (J 2e-6, Lambda* 1e-6 per array; J - S^g and H 2e-6 of their scale)."""
+    a = c5
+    rows, nf, na = a.tau.shape[0], a.nf, a.na
+    print(f"[case] C5 formal solution, FP32 plan, rows={rows} nf={nf} na={na}", flush=True)
+    op = rates.opacities(a, a.nstar)
+    r32 = lambda x: np.asarray(x, np.float32).astype(np.float64)
+    q, Sg, om = r32(op["q"]), r32(op["Sg"]), r32(op["omega"])
+    Bb, Bp = r32(a.Bnu[-1:, :]), r32(a.Bnu[-2:-1, :])
+    ks = _sample_frequencies(a, n=16, seed=6)
+    plan = pprt.Plan(gpu_ctx, a.nd, na, nf, precision=pprt.FP32,
+                     outputs=pprt.OUT_J | pprt.OUT_JMS | pprt.OUT_LSTAR | pprt.OUT_H)
+    f32 = lambda x: torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float32, device="cuda:0")
+    out = plan.formal_solution_scattering(_dev(a.tau), f32(q), f32(Sg), f32(om), Bbot=f32(Bb), Bbot_prev=f32(Bp))
+    torch.cuda.synchronize()
+    kt = torch.as_tensor(ks, device="cuda:0")
+    got = {k: out[k].index_select(1, kt).double().cpu().numpy() for k in ("J", "JmS", "lstar", "H")}
+    del out
+    torch.cuda.empty_cache()
+    ref = dense.formal_solution_dense(a.tau, q[:, ks], Sg[:, ks], plan.mu, plan.w, omega=om[:, ks],
+                                      lower="diffusion", Bbot=Bb[0, ks], Bbot_prev=Bp[0, ks])
+    scale = lambda g, r: float(np.max(np.abs(g - r)) / np.max(np.abs(r)))
+    errs = {"J": rel_err(got["J"], ref["J"]), "lstar": rel_err(got["lstar"], ref["lstar"]),
+            "JmS": scale(got["JmS"], ref["JmS"]), "H": scale(got["H"], ref["H"])}
+    print(f"  frequencies {ks.tolist()}; errors:", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    assert errs["J"] < 2e-6 and errs["lstar"] < 1e-6
+    assert errs["JmS"] < 2e-6 and errs["H"] < 2e-6
 
 
 def test_c5_rates_and_solve_full_size(gpu_ctx, c5):
