@@ -90,8 +90,7 @@ struct Lay {
   static constexpr int TMU = TD + NA;               // NA: mu
   static constexpr int TZ2 = TMU + NA;              // NA: w d
   static constexpr int TW = TZ2 + NA;               // NA: w
-  static constexpr int PI = TW + NA;                // 16: inverse of the pivot block
-  static constexpr int SIZE = PI + 16;
+  static constexpr int SIZE = TW + NA;
   // vector slots: 0 mat-vec input, 1 mat-vec output, 2..4 right-hand-side
   // columns, 5 sqrt(w), 6 sqrt(w) mu, 7 spare
 };
@@ -245,45 +244,40 @@ __device__ void gj(const W<T>& w, Mat<T>& A, v4d (&X)[T][TX]) {
         for (int q = 0; q < 4; ++q) bc[(16 * ti + w.g + 4 * q) * 5 + (w.c & 3)] = A.t[ti][tb][q];
     }
     wsync();
-    // the 4 x 4 pivot block and its inverse (every lane)
-    // in-place Gauss-Jordan inverse of the pivot block (every lane)
-    double M[4][4];
+    // row g of P^-1 for this lane (the only row its B operands need): the
+    // solution of P^T y = e_g from an LU factorisation of the 4 x 4 pivot
+    // block P without pivoting (every lane factorises; no LDS round trip)
+    double M[4][4], rk[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) M[i][j] = br[i * LW + 4 * b + j];
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
-      const double rp = rcp_nr(M[kk][kk]);
-      M[kk][kk] = 1.0;
+      rk[kk] = rcp_nr(M[kk][kk]);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) M[kk][j] *= rp;
+      for (int i = kk + 1; i < 4; ++i) {
+        M[i][kk] *= rk[kk];                              // L below the diagonal
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-        if (i != kk) {
-          const double f = M[i][kk];
-          M[i][kk] = 0.0;
-#pragma unroll
-          for (int j = 0; j < 4; ++j) M[i][j] = fma(-f, M[kk][j], M[i][j]);
-        }
+        for (int j = kk + 1; j < 4; ++j) M[i][j] = fma(-M[i][kk], M[kk][j], M[i][j]);   // U on and above
+      }
     }
-    // P^-1 to LDS (lane 4 i + j < 16 writes element (i, j); a store from one
-    // lane of all sixteen measured slower), after every lane has read the
-    // pivot block
-    double piv = 0.0;
+    double z[4], pr[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int m = 0; m < 4; ++m) {                        // U^T z = e_g
+      double acc = (w.g == m) ? 1.0 : 0.0;
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (w.lane == 4 * i + j) piv = M[i][j];
-    double* pis = w.s + Lay<T>::PI;
-    wsync();
-    if (w.lane < 16) pis[w.lane] = piv;
-    wsync();
-    // B operands: rows of P^-1 [block rows]; lane l takes row g, column 16 tj + c
-    double pr[4];
+      for (int p = 0; p < m; ++p) acc = fma(-M[p][m], z[p], acc);
+      z[m] = acc * rk[m];
+    }
 #pragma unroll
-    for (int m = 0; m < 4; ++m) pr[m] = pis[4 * w.g + m];
+    for (int m = 3; m >= 0; --m) {                       // L^T y = z
+      double acc = z[m];
+#pragma unroll
+      for (int p = m + 1; p < 4; ++p) acc = fma(-M[p][m], pr[p], acc);
+      pr[m] = acc;
+    }
+    // B operands: row g of P^-1 [block rows], columns 16 tj + c
     double bop[TT];
 #pragma unroll
     for (int tj = 0; tj < TT; ++tj) {
