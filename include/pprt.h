@@ -225,8 +225,9 @@ pprt_status pprt_formal_solution(pprt_plan* plan, const pprt_fs_in* in, pprt_fs_
  * layer and each layer's eigen solution), 4 (na^2 + 3 na) bytes in FP32 plans
  * with na <= 16 (the same without the eigen solutions, which the bottom-up
  * pass recomputes), and with na = 32 8 or 4 (na^2 + 3 na) bytes (FP64 or FP32
- * plans) plus 16 na bytes for the secular-equation roots of every layer,
- * solved apart before the recursion, kept between the
+ * plans) plus 32 na bytes for each layer's eigen data (secular-equation
+ * roots, Gu-Eisenstat vector, column norms), solved apart before the
+ * recursion, kept between the
  * top-down and the bottom-up pass; omega = 0 everywhere reproduces
  * pprt_formal_solution to rounding. */
 pprt_status pprt_plan_scattering_workspace_bytes(const pprt_plan* plan, size_t* bytes);

@@ -31,12 +31,13 @@
 // * Mat-vec products: the vector goes through the slab, each lane multiplies
 //   its tile elements and the sixteen lanes of a row group reduce by
 //   cross-lane shuffles; sums over angles reduce across the wave.
-// * The secular-equation roots of every layer are solved apart, before the
+// * The eigen data of every layer (secular-equation roots, the Gu-Eisenstat
+//   vector zhat and the column norms) are solved apart, before the
 //   recursion, by k_mf_roots (one thread per frequency and root, at full
-//   occupancy) and kept in the workspace; both passes rebuild the
+//   occupancy) and kept in the workspace; both passes assemble the
 //   eigenvectors from them.  The workspace keeps R, Sigma and two unit-source
-//   responses per node in the plan's type and the roots in FP64:
-//   (NA^2 + 3 NA) reals + 16 NA bytes per node and frequency.
+//   responses per node in the plan's type and the eigen data in FP64:
+//   (NA^2 + 3 NA) reals + 32 NA bytes per node and frequency.
 #include "pprt_internal.h"
 
 namespace pprt {
@@ -432,39 +433,14 @@ __device__ void layer(const W<T>& w, double om, double Dl, const double* roots, 
   double* s = w.s;
   const int i = w.lane;
   if (om != om_prev) {
-    // the layer's roots (origin and offset, from k_mf_roots)
-    double org = 0.0, del = 0.0;
-    if (i < NA) {
-      org = roots[2 * i];
-      del = roots[2 * i + 1];
-    }
+    // the layer's roots (origin and offset), Gu-Eisenstat zhat and column
+    // norms, from k_mf_roots
     wsync();
     if (i < NA) {
-      s[Lay<T>::RT + 2 * i] = org;
-      s[Lay<T>::RT + 2 * i + 1] = del;
-    }
-    wsync();
-    // Gu-Eisenstat zhat_i, then the column norms
-    if (i < NA && om > 0.0) {
-      const double dl = s[Lay<T>::TD + i];
-      double num = del + (org - dl), den = -om;
-#pragma unroll
-      for (int a = 0; a < NA; ++a)
-        if (a != i) {
-          num *= (s[Lay<T>::RT + 2 * a] - dl) + s[Lay<T>::RT + 2 * a + 1];
-          den *= s[Lay<T>::TD + a] - dl;
-        }
-      s[Lay<T>::ZH + i] = sqrt(fabs(num / den));
-    }
-    wsync();
-    if (i < NA && om > 0.0) {
-      double nrm = 0.0;
-#pragma unroll
-      for (int j = 0; j < NA; ++j) {
-        const double q = s[Lay<T>::ZH + j] * rcp_nr((s[Lay<T>::TD + j] - org) - del);
-        nrm = fma(q, q, nrm);
-      }
-      s[Lay<T>::NR + i] = 1.0 / sqrt(nrm);
+      s[Lay<T>::RT + 2 * i] = roots[4 * i];
+      s[Lay<T>::RT + 2 * i + 1] = roots[4 * i + 1];
+      s[Lay<T>::ZH + i] = roots[4 * i + 2];
+      s[Lay<T>::NR + i] = roots[4 * i + 3];
     }
     om_prev = om;
   }
@@ -588,25 +564,29 @@ struct MfArgs {
   S* wsR;          // [rows][nf][NA][NA]
   S* wsS;          // [rows][nf][NA]
   S* wsZ;          // [rows][nf][NA][2]
-  double* wsRT;    // [rows][nf][NA][2]: the secular-equation roots (origin, offset) of layer (d, d+1)
+  double* wsRT;    // [rows][nf][NA][4]: layer (d, d+1): root origin and offset, zhat, column norm
   uint32_t* status;
   unsigned long long* thick_stats;   // FP32 plans: [FP64 eliminations, all eliminations]
   int32_t nf, nitems, lower_bc;
   uint32_t outputs;
 };
 
-// The secular-equation roots of every layer, apart from the formal solution:
-// one thread per (frequency, root), two frequencies per wave, each thread
-// walking down its column and starting every layer's Newton iteration from
-// its own root of the layer above (the albedo changes with depth in a real
+// The eigen solutions of every layer, apart from the formal solution: one
+// thread per (frequency, root), two frequencies per wave, each thread walking
+// down its column and starting every layer's Newton iteration from its own
+// root of the layer above (the albedo changes with depth in a real
 // atmosphere, and inside the one-wave-per-SIMD formal solution these
-// iterations were a third of its instructions).  A layer whose albedo equals
-// the one above keeps its roots.
+// iterations were a third of its instructions).  The 32 threads of a column
+// then share their roots through LDS for the Gu-Eisenstat zhat_i and the
+// column norms, so that the formal solution only assembles V.  A layer whose
+// albedo equals the one above keeps its values.
 template <int T, typename S>
 __global__ __launch_bounds__(64) void k_mf_roots(MfArgs<S> a, MfTab<16 * T> tb) {
   constexpr int NA = 16 * T;
+  constexpr int C = 64 / NA;            // columns per wave
   static_assert(64 % NA == 0, "whole columns per wave");
   __shared__ double td[NA], tz2[NA], tw[NA];
+  __shared__ double rt[C][2 * NA], zh[C][NA];
   const int t = (int)threadIdx.x;
   if (t < NA) {
     td[t] = tb.d[t];
@@ -614,26 +594,64 @@ __global__ __launch_bounds__(64) void k_mf_roots(MfArgs<S> a, MfTab<16 * T> tb) 
     tw[t] = tb.w[t];
   }
   __syncthreads();
-  const int item = (int)blockIdx.x * (64 / NA) + t / NA;
+  const int col = t / NA;
+  const int item = (int)blockIdx.x * C + col;
   const int i = t % NA;
   if (item >= a.nitems) return;
   const Item it = a.items[item];
   const int nd = it.nd, nf = a.nf, k = it.g;
   if (k >= nf) return;
   const int64_t row0 = a.off[it.b];
-  double* out = a.wsRT + ((row0 * nf + k) * NA + i) * 2;
-  const int64_t stride = (int64_t)nf * NA * 2;
-  double om_prev = -1.0, lam_prev = -1.0, org = 0.0, del = 0.0;
+  double* out = a.wsRT + ((row0 * nf + k) * NA + i) * 4;
+  const int64_t stride = (int64_t)nf * NA * 4;
+  double om_prev = -1.0, lam_prev = -1.0, org = 0.0, del = 0.0, zhat = 0.0, nrm = 1.0;
   for (int d = 0; d < nd - 1; ++d) {
     const double om = a.omega ? 0.5 * ((double)a.omega[(row0 + d) * nf + k] + (double)a.omega[(row0 + d + 1) * nf + k])
                               : 0.0;
-    if (om != om_prev) {
+    const bool fresh = om != om_prev;
+    if (fresh) {
       secular_root<NA>(i, om, lam_prev, td, tz2, tw, org, del);
       lam_prev = org + del;
+    }
+    // (the LDS exchanges stay in this column's own slots; the fences keep
+    // each lane's stores ahead of the other lanes' loads in the wave)
+    wsync();
+    rt[col][2 * i] = org;
+    rt[col][2 * i + 1] = del;
+    wsync();
+    if (fresh && om > 0.0) {
+      const double dl = td[i];
+      double num = del + (org - dl), den = -om;
+#pragma unroll 8
+      for (int b2 = 0; b2 < NA; ++b2)
+        if (b2 != i) {
+          num *= (rt[col][2 * b2] - dl) + rt[col][2 * b2 + 1];
+          den *= td[b2] - dl;
+        }
+      zhat = sqrt(fabs(num / den));
+    }
+    wsync();
+    zh[col][i] = zhat;
+    wsync();
+    if (fresh) {
+      if (om > 0.0) {
+        double q2 = 0.0;
+#pragma unroll 8
+        for (int j = 0; j < NA; ++j) {
+          const double q = zh[col][j] * rcp_nr((td[j] - org) - del);
+          q2 = fma(q, q, q2);
+        }
+        nrm = 1.0 / sqrt(q2);
+      } else {
+        zhat = 0.0;
+        nrm = 1.0;
+      }
       om_prev = om;
     }
     out[d * stride] = org;
     out[d * stride + 1] = del;
+    out[d * stride + 2] = zhat;
+    out[d * stride + 3] = nrm;
   }
 }
 
@@ -681,8 +699,8 @@ __global__ __launch_bounds__(64) void k_fs_dense_mfma(MfArgs<S> a, MfTab<16 * T>
   const bool wd = (o & PPRT_OUT_LSTAR) != 0;
   const bool we = (o & PPRT_OUT_LSTAR_C) != 0;
   double om_prev = -1.0;
-  const double* wsRT = a.wsRT + (row0 * nf + k) * NA * 2;   // + layer * nf * NA * 2
-  const int64_t strideRT = (int64_t)nf * NA * 2;
+  const double* wsRT = a.wsRT + (row0 * nf + k) * NA * 4;   // + layer * nf * NA * 4
+  const int64_t strideRT = (int64_t)nf * NA * 4;
   Ops<T> op;
 
   auto save_mat = [&](S* dst, const Mat<T>& M) {
@@ -923,11 +941,11 @@ hipError_t run_mfma(const DenseLaunch& L, hipStream_t s) {
 bool dense_mfma_na(int na) { return na == 32; }
 
 size_t dense_mfma_workspace_bytes(int na, int64_t rows, int nf, int precision) {
-  // R, Sigma and the two unit-source responses in the plan's type, then the
-  // roots of every layer (origin and offset) in FP64
+  // R, Sigma and the two unit-source responses in the plan's type, then per
+  // layer and root the origin, offset, zhat and column norm in FP64
   const size_t rf = (size_t)rows * nf;
   return rf * (size_t)(na * na + 3 * na) * (precision == PPRT_FP64 ? sizeof(double) : sizeof(float)) +
-         rf * (size_t)(2 * na) * sizeof(double);
+         rf * (size_t)(4 * na) * sizeof(double);
 }
 
 hipError_t launch_fs_dense_mfma(const DenseLaunch& L, hipStream_t s) {
