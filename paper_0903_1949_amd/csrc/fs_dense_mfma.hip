@@ -29,8 +29,8 @@
 //   pair on the matrix cores, and the block rows are set to P^-1 B (the loop
 //   over blocks is unrolled, so every tile and register index is static).
 // * Mat-vec products: the vector goes through the slab, each lane multiplies
-//   its tile elements and the sixteen lanes of a row group reduce by
-//   cross-lane shuffles; sums over angles reduce across the wave.
+//   its tile elements and the sixteen lanes of a row group reduce by DPP
+//   row sums; sums over angles reduce across the wave.
 // * The eigen data of every layer (secular-equation roots, the Gu-Eisenstat
 //   vector zhat and the column norms) are solved apart, before the
 //   recursion, by k_mf_roots (one thread per frequency and root, at full
@@ -180,11 +180,7 @@ __device__ __forceinline__ double mv_slot(const W<T>& w, const Mat<T>& A, int in
       double p = 0.0;
 #pragma unroll
       for (int tj = 0; tj < T; ++tj) p = fma(A.t[ti][tj][q], xc[tj], p);
-      p += __shfl_xor(p, 8, 16);
-      p += __shfl_xor(p, 4, 16);
-      p += __shfl_xor(p, 2, 16);
-      p += __shfl_xor(p, 1, 16);
-      y[ti][q] = p;
+      y[ti][q] = row_sum(p);       // the sixteen lanes of the row group (DPP)
     }
   wsync();
   if (w.c == 0) {
@@ -204,13 +200,8 @@ __device__ __forceinline__ double mv(const W<T>& w, const Mat<T>& A, double x) {
   return mv_slot(w, A, 0);
 }
 
-// sum over angles of a x (compact)
-__device__ __forceinline__ double dot(double a, double x) {
-  double p = a * x;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o);
-  return p;
-}
+// sum over angles of a x (compact; DPP row sums, then the four rows)
+__device__ __forceinline__ double dot(double a, double x) { return wave_sum(a * x); }
 
 // Gauss-Jordan without pivoting on the augmented tiles [A | X] (TX column
 // tiles of right-hand sides): on exit A = I and X = A^-1 X.
