@@ -1220,9 +1220,8 @@ def bench_voigt(args):
 
     t_op, (q, om, Sg) = timed(lambda: plan.nlte_opacity(da, pops))
     ws = {}
-    t_fs, fs = timed(lambda: plan.formal_solution_scattering(da.tau, q, Sg, om, Bbot=Bb, Bbot_prev=Bp,
-                                                             workspace=ws.get("w")))
-    ws["w"] = fs["_workspace"]
+    t_fs, fs = timed(lambda: fs_reusing(ws, lambda w: plan.formal_solution_scattering(
+        da.tau, q, Sg, om, Bbot=Bb, Bbot_prev=Bp, workspace=w)))
     t_ra, (dRlu, dRul, Rsul) = timed(lambda: plan.rates_assemble(da, pops, fs["J"], fs["lstar"]))
     t_so, _ = timed(lambda: plan.rates_solve(da, pops, dRlu, dRul, Rsul))
     line_pts = int(np.count_nonzero(np.asarray(atom.line_nu0)[np.asarray(atom.owner)] > 0)) * rows
@@ -1310,9 +1309,8 @@ def bench_c5(args):
     # workspace is released before the iterations allocate their own)
     t_op, (q, om, Sg) = timed(lambda: plan.nlte_opacity(da, pops))
     ws = {}
-    t_fs, fs = timed(lambda: plan.formal_solution_scattering(da.tau, q, Sg, om, Bbot=Bb, Bbot_prev=Bp,
-                                                             workspace=ws.get("w")))
-    ws["w"] = fs["_workspace"]
+    t_fs, fs = timed(lambda: fs_reusing(ws, lambda w: plan.formal_solution_scattering(
+        da.tau, q, Sg, om, Bbot=Bb, Bbot_prev=Bp, workspace=w)))
     ws_gb = ws["w"].numel() * ws["w"].element_size() / 1e9
     t_ra, (dRlu, dRul, Rsul) = timed(lambda: plan.rates_assemble(da, pops, fs["J"], fs["lstar"]))
     t_so, _ = timed(lambda: plan.rates_solve(da, pops, dRlu, dRul, Rsul))
@@ -1324,9 +1322,8 @@ def bench_c5(args):
     plan32 = pprt.Plan(ctx, atom.nd, na, nf, precision=pprt.FP32, outputs=pprt.OUT_J | pprt.OUT_LSTAR)
     q32, Sg32, om32, Bb32, Bp32 = (x.float() for x in (q, Sg, om, Bb, Bp))
     ws32 = {}
-    t_fs32, fs32 = timed(lambda: plan32.formal_solution_scattering(da.tau, q32, Sg32, om32, Bbot=Bb32,
-                                                                   Bbot_prev=Bp32, workspace=ws32.get("w")))
-    ws32["w"] = fs32["_workspace"]
+    t_fs32, fs32 = timed(lambda: fs_reusing(ws32, lambda w: plan32.formal_solution_scattering(
+        da.tau, q32, Sg32, om32, Bbot=Bb32, Bbot_prev=Bp32, workspace=w)))
 
     def arr_err(a, b):
         return float(((a.double() - b).abs() / torch.maximum(b.abs(), 1e-4 * b.abs().max())).max())
@@ -1409,6 +1406,16 @@ def kernel_hash(name: str = "fs_diag.hip") -> str:
     import hashlib
     src = os.path.join(ROOT, "paper_0903_1949_amd", "csrc", name)
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def fs_reusing(ws: dict, call):
+    """call(workspace) for a formal solution that returns its workspace under
+    "_workspace": the first call allocates it, later calls reuse it (a second
+    allocation while the first result is alive would double the footprint;
+    the 32-angle FP64 case needs 214 GiB)."""
+    out = call(ws.get("w"))
+    ws["w"] = out["_workspace"]
+    return out
 
 
 def measured_traffic(path: str, source: str):

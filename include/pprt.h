@@ -227,7 +227,9 @@ pprt_status pprt_formal_solution(pprt_plan* plan, const pprt_fs_in* in, pprt_fs_
  * pass recomputes), and with na = 32 8 or 4 (na^2 + 3 na) bytes (FP64 or FP32
  * plans) plus 32 na bytes for each layer's eigen data (secular-equation
  * roots, Gu-Eisenstat vector, column norms), solved apart before the
- * recursion, kept between the
+ * recursion, and in FP64 plans 8 (2 na^2 + 4 na) bytes more for each
+ * layer's t, r and source vectors, which the bottom-up pass reads instead
+ * of forming them again (FP32 plans form them again); all kept between the
  * top-down and the bottom-up pass; omega = 0 everywhere reproduces
  * pprt_formal_solution to rounding. */
 pprt_status pprt_plan_scattering_workspace_bytes(const pprt_plan* plan, size_t* bytes);

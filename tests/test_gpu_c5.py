@@ -46,10 +46,21 @@ def _sample_frequencies(atom, n=64, seed=5):
     return np.array(sorted(ks))
 
 
+def _release_device_memory():
+    """Return cached device memory before a workspace of a good part of the
+    card is allocated (an FP64 plan on the full grid needs 230 GB)."""
+    import gc
+    gc.collect()
+    torch.cuda.empty_cache()
+    free, total = torch.cuda.mem_get_info()
+    print(f"  device memory: {free / 1e9:.1f} GB free of {total / 1e9:.1f} GB", flush=True)
+
+
 def test_c5_formal_solution_full_grid_sampled(gpu_ctx, c5):
     a = c5
     rows, nf, na = a.tau.shape[0], a.nf, a.na
     print(f"[case] C5 formal solution rows={rows} nf={nf} na={na}", flush=True)
+    _release_device_memory()
     op = rates.opacities(a, a.nstar)          # the inputs of both sides
     ks = _sample_frequencies(a)
     plan = pprt.Plan(gpu_ctx, a.nd, na, nf, precision=pprt.FP64,
@@ -85,6 +96,7 @@ def test_c5_formal_solution_fp32_plan_full_grid_sampled(gpu_ctx, c5):
     a = c5
     rows, nf, na = a.tau.shape[0], a.nf, a.na
     print(f"[case] C5 formal solution, FP32 plan, rows={rows} nf={nf} na={na}", flush=True)
+    _release_device_memory()
     op = rates.opacities(a, a.nstar)
     r32 = lambda x: np.asarray(x, np.float32).astype(np.float64)
     q, Sg, om = r32(op["q"]), r32(op["Sg"]), r32(op["omega"])

@@ -160,8 +160,9 @@ def test_continuum_batch_slice(gpu_ctx):
     ref = _oracle(list(full.nd), c, plan.mu, plan.w, pprt.BC_DIFFUSION)
     errs = {k: rel_err(got[k], ref[k]) for k in KEYS}
     print("  errors:", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    # the FP64 contract (measured: 6.9e-11 for I-, the rest below 3.1e-11)
     for k, e in errs.items():
-        assert e < 1e-9, (k, e)
+        assert e < 1e-10, (k, e)
 
 
 def test_scattering_rejects_unsupported_angle_counts(gpu_ctx):
