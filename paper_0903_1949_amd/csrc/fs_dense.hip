@@ -1176,11 +1176,47 @@ __global__ __launch_bounds__(64, 1) void k_dense_up(DenseVjpArgs<NA> a, DenseTab
   }
 }
 
+// C = A B as Grp::mul, with the loop over k rolled by two and A's row read
+// from LDS (ar: this lane's column of a [k][64 lanes] array): in the reverse
+// sweep, whose steps hold a dozen matrix rows, the fully unrolled product left
+// the 16-angle kernel with about a thousand registers in scratch
+template <int NA>
+__device__ __forceinline__ void mul_rolled(Grp<double, NA>& g, double* ar, double (&C)[NA],
+                                           const double (&A)[NA], const double (&B)[NA]) {
+  constexpr int RS = Slab<double, NA>::RS;
+  g.put_mat(B);
+#pragma unroll
+  for (int k = 0; k < NA; ++k) ar[64 * k] = A[k];
+  double acc[NA];
+#pragma unroll
+  for (int j = 0; j < NA; ++j) acc[j] = 0.0;
+#pragma unroll 2
+  for (int k = 0; k < NA; ++k) {
+    const double a = ar[64 * k];
+#pragma unroll
+    for (int j = 0; j < NA; ++j) acc[j] = fma(a, g.buf[k * RS + j], acc[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < NA; ++j) C[j] = acc[j];
+}
+
 // reverse sweep, top-down: dL/dq, dL/dS^g and the boundary derivatives
 template <int NA>
 __global__ __launch_bounds__(64, 1) void k_dense_vjp(DenseVjpArgs<NA> a, DenseTab<NA> tb) {
   PPRT_DENSE_GROUP_SETUP
   (void)layer_omega;                  // the albedo enters through the stored eigen solutions
+  // rows of F_T and F_C' wait in LDS from the layer operators to the layer
+  // depth's derivative at the end of the step (held in registers through the
+  // step's products they spilled to scratch); lane i keeps row i, column j at
+  // j * NA + i of its group's area
+  constexpr int KS = 2 * NA * NA + 16;
+  __shared__ double keep[F * KS];
+  double* kp = keep + grp * KS + i;
+  // the left factor's row of each product, [k][lane] (mul_rolled)
+  __shared__ double arow[NA * 64];
+  auto mul = [&](double (&C)[NA], const double (&A)[NA], const double (&B)[NA]) {
+    mul_rolled<NA>(g, arow + lane, C, A, B);
+  };
   const int64_t bk = (int64_t)b * nf + k;
   bool nonfinite = false;
   double Rb[NA], Sb;
@@ -1212,16 +1248,24 @@ __global__ __launch_bounds__(64, 1) void k_dense_vjp(DenseVjpArgs<NA> a, DenseTa
     const double kk = wsV[la * strideV + NA];
     const double Dl = layer_depth(la);
     LayerOps<double, NA> op;
-    double FT[NA], FC[NA], dtx, dcx;
-    layer_ops_grad<NA>(g, L, V, kk, Dl, op, FT, FC, dtx, dcx);
+    double dtx, dcx;
+    {
+      double FT[NA], FC[NA];
+      layer_ops_grad<NA>(g, L, V, kk, Dl, op, FT, FC, dtx, dcx);
+#pragma unroll
+      for (int j = 0; j < NA; ++j) {
+        kp[j * NA] = FT[j];
+        kp[(NA + j) * NA] = FC[j];
+      }
+    }
     const double dSg = at(a.Sg, row0 + d) - at(a.Sg, row0 + la);
     // forward quantities of the step
     double G[NA], RG[NA], T1[NA], T2[NA];
-    g.mul(T1, Rup, op.r);
+    mul(T1, Rup, op.r);
 #pragma unroll
     for (int j = 0; j < NA; ++j) T1[j] = ((j == i) ? 1.0 : 0.0) - T1[j];
     g.inv(G, T1);                                        // G = (I - R^up r)^-1
-    g.mul(RG, G, Rup);
+    mul(RG, G, Rup);
     const double v = g.mv(op.r, Sup) - dSg * op.qv;
     const double u = Sup + g.mv(RG, v);
     // S^up' = t u + dS^g Q
@@ -1246,41 +1290,48 @@ __global__ __launch_bounds__(64, 1) void k_dense_vjp(DenseVjpArgs<NA> a, DenseTa
     dSgb -= g.sum(op.qv * vb);
     qvb -= dSg * vb;
     // R^up' = r + t RG t: t gets Rb (RG t)^T + (t RG)^T Rb, RG gets t^T Rb t^T
-    g.mul(T1, RG, op.t);
+    mul(T1, RG, op.t);
     g.transpose(T2, T1);
-    g.mul(T1, Rb, T2);
+    mul(T1, Rb, T2);
 #pragma unroll
     for (int j = 0; j < NA; ++j) tb_[j] += T1[j];
-    g.mul(T1, op.t, RG);
+    mul(T1, op.t, RG);
     g.transpose(T2, T1);
-    g.mul(T1, T2, Rb);
+    mul(T1, T2, Rb);
 #pragma unroll
     for (int j = 0; j < NA; ++j) tb_[j] += T1[j];
     double tT[NA];
     g.transpose(tT, op.t);
-    g.mul(T1, tT, Rb);
-    g.mul(T2, T1, tT);
+    mul(T1, tT, Rb);
+    mul(T2, T1, tT);
 #pragma unroll
     for (int j = 0; j < NA; ++j) RGb[j] += T2[j];
     // RG = G R^up: R^up gets G^T RGb (I + r RG)^T, r gets RG^T RGb RG^T
     double Rupb[NA];
-    g.mul(T1, op.r, RG);
+    mul(T1, op.r, RG);
 #pragma unroll
     for (int j = 0; j < NA; ++j) T1[j] += (j == i) ? 1.0 : 0.0;
     g.transpose(T2, T1);                                 // (I + r RG)^T
     g.transpose(T1, G);
-    g.mul(Rupb, T1, RGb);
-    g.mul(T1, Rupb, T2);
+    mul(Rupb, T1, RGb);
+    mul(T1, Rupb, T2);
 #pragma unroll
     for (int j = 0; j < NA; ++j) Rupb[j] = T1[j];
     g.transpose(T2, RG);
-    g.mul(T1, T2, RGb);
-    g.mul(RG, T1, T2);                                   // RG no longer needed: RG^T RGb RG^T
+    mul(T1, T2, RGb);
+    mul(RG, T1, T2);                                   // RG no longer needed: RG^T RGb RG^T
 #pragma unroll
     for (int j = 0; j < NA; ++j) rb[j] += RG[j];
     // the layer optical depth: <tb, dt> + <rb, dr> + <Qb, dQ>
     double part = 0.0;
     {
+      double FT[NA], FC[NA];
+#pragma unroll
+      for (int j = 0; j < NA; ++j) {
+        FT[j] = kp[j * NA];
+        FC[j] = kp[(NA + j) * NA];
+        V[j] = wsV[la * strideV + j];
+      }
       double AT[NA], AC[NA];
 #pragma unroll
       for (int j = 0; j < NA; ++j) {
@@ -1288,16 +1339,16 @@ __global__ __launch_bounds__(64, 1) void k_dense_vjp(DenseVjpArgs<NA> a, DenseTa
         AC[j] = L.m * (rb[j] - tb_[j]);
         part = fma(AC[j], FC[j], part);                  // <A_C, F_C'>
       }
-      g.mul(T1, FT, AT);
-      g.mul(T2, T1, FT);                                 // B_T = F_T A_T F_T
-      g.mul(T1, T2, V);
+      mul(T1, FT, AT);
+      mul(T2, T1, FT);                                 // B_T = F_T A_T F_T
+      mul(T1, T2, V);
 #pragma unroll
       for (int j = 0; j < NA; ++j) T1[j] *= V[j];
       part -= dtx * g.colsum(T1);                        // - sum_j dtx_j (V^T B_T V)_jj
       const double c = g.mv(FC, L.swmu);                 // F_C' sqrt(w) mu
       const double y = g.mv(FC, 2.0 * L.m * qvb);        // F_C' (2 M Qb)
-      g.mul(T1, FC, AC);
-      g.mul(T2, T1, FC);
+      mul(T1, FC, AC);
+      mul(T2, T1, FC);
       g.put_vec(c, 1);
 #pragma unroll
       for (int j = 0; j < NA; ++j) T2[j] = Dl * T2[j] + y * g.vec(j, 1);   // B_C
@@ -1306,7 +1357,7 @@ __global__ __launch_bounds__(64, 1) void k_dense_vjp(DenseVjpArgs<NA> a, DenseTa
       for (int j = 0; j < NA; ++j)
         if (j == i) bcd = T2[j];
       part -= L.m * bcd;                                 // - <B_C, M>
-      g.mul(T1, T2, V);
+      mul(T1, T2, V);
 #pragma unroll
       for (int j = 0; j < NA; ++j) T1[j] *= V[j];
       part -= dcx * g.colsum(T1);                        // - sum_j dcx_j (V^T B_C V)_jj
