@@ -74,6 +74,8 @@ struct pprt_plan {
   int prof_blocks = 0;            // batched sweep: 0 = one wave per item, else persistent grid size
   int prof_wpc = 0;               // persistent: resident waves per CU the grid was sized for
   int32_t* d_queue = nullptr;     // persistent work counter
+  double* d_ml_part = nullptr;    // the rate solve's per-chunk maxima [nb][ml_solve_chunks(ndmax)]
+  int ndmax = 2;
   int n_cu = 256;
   int64_t ck_rows[33] = {};
   int64_t* d_off = nullptr;
@@ -573,6 +575,8 @@ pprt_status pprt_plan_create(pprt_ctx* c, const pprt_shape* sh, const double* mu
   if (e == hipSuccess) e = hipMalloc(&p->d_off, p->off.size() * sizeof(int64_t));
   if (e == hipSuccess) e = hipMalloc(&p->d_items_adj, adj.size() * sizeof(Item));
   if (e == hipSuccess) e = hipMalloc(&p->d_queue, sizeof(int32_t));
+  p->ndmax = *std::max_element(p->nd.begin(), p->nd.end());
+  if (e == hipSuccess) e = hipMalloc(&p->d_ml_part, (size_t)p->nb * ml_solve_chunks(p->ndmax) * sizeof(double));
   if (e == hipSuccess) {
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess &&
@@ -608,6 +612,7 @@ void pprt_plan_destroy(pprt_plan* p) {
   if (p->d_items_dense) (void)hipFree(p->d_items_dense);
   if (p->d_items_adj) (void)hipFree(p->d_items_adj);
   if (p->d_queue) (void)hipFree(p->d_queue);
+  if (p->d_ml_part) (void)hipFree(p->d_ml_part);
   for (auto* ck : p->d_ck_off)
     if (ck) (void)hipFree(ck);
   delete p;
@@ -1375,8 +1380,9 @@ pprt_status pprt_rates_solve(pprt_plan* p, const pprt_atom* at, const double* po
   if (!pops_old || !dRlu || !dRul || !Rsul || !pops_new)
     return fail(p->ctx, PPRT_E_INVALID_ARG, "null array");
   if (pops_new == pops_old) return fail(p->ctx, PPRT_E_INVALID_ARG, "pops_new must not alias pops_old");
-  return hip_check(p->ctx, launch_ml_solve(ml_args(p, at, pops_old), p->d_off, p->nb, dRlu, dRul, Rsul,
-                                           pops_new, max_rel, p->ctx->d_status, p->ctx->stream),
+  return hip_check(p->ctx, launch_ml_solve(ml_args(p, at, pops_old), p->d_off, p->nb, p->ndmax, dRlu,
+                                           dRul, Rsul, pops_new, p->d_ml_part, max_rel, p->ctx->d_status,
+                                           p->ctx->stream),
                    "rate solve launch");
 }
 
@@ -1454,8 +1460,8 @@ static pprt_status nlte_step_impl(pprt_plan* p, const pprt_fs_in* in, const pprt
   if (r != PPRT_OK) return r;
   r = hip_check(c, launch_ml_rates(a, J, Ls, dRlu, dRul, Rsul, c->stream), "rate assembly launch");
   if (r != PPRT_OK) return r;
-  r = hip_check(c, launch_ml_solve(a, p->d_off, p->nb, dRlu, dRul, Rsul, pn, max_rel, c->d_status,
-                                   c->stream, ctl), "rate solve launch");
+  r = hip_check(c, launch_ml_solve(a, p->d_off, p->nb, p->ndmax, dRlu, dRul, Rsul, pn, p->d_ml_part,
+                                   max_rel, c->d_status, c->stream, ctl), "rate solve launch");
   if (r != PPRT_OK) return r;
   return hip_check(c, hipMemcpyAsync(pops, pn, (size_t)p->rows * at->nlev * sizeof(double),
                                      hipMemcpyDeviceToDevice, c->stream), "population copy");

@@ -376,9 +376,15 @@ struct MlSolveCtl {
   double tol;
   int32_t max_iter;
 };
-hipError_t launch_ml_solve(const MlArgs& a, const int64_t* off, int nb, const double* dRlu,
-                           const double* dRul, const double* Rsul, double* pops_new, double* max_rel,
-                           uint32_t* status, hipStream_t s, const MlSolveCtl& ctl = MlSolveCtl{});
+// The per-depth solve on blocks of (atmosphere, chunk of depth rows); ndmax =
+// the largest depth count; part holds nb * ml_solve_chunks(ndmax) doubles
+// (each chunk's largest relative change, reduced per atmosphere by a second
+// kernel).
+int ml_solve_chunks(int ndmax);
+hipError_t launch_ml_solve(const MlArgs& a, const int64_t* off, int nb, int ndmax, const double* dRlu,
+                           const double* dRul, const double* Rsul, double* pops_new, double* part,
+                           double* max_rel, uint32_t* status, hipStream_t s,
+                           const MlSolveCtl& ctl = MlSolveCtl{});
 hipError_t launch_gather_bottom(const double* Bnu, const int64_t* off, int nb, int nf, double* Bb,
                                 double* Bp, hipStream_t s);
 
