@@ -39,16 +39,17 @@
 // pivot row from its lane through the cross-lane permute and scale no row
 // until the end (fewer instructions than a pivot lane that scales and stores
 // its row while the other lanes wait).  The two passes are two kernels, each limited to
-// 256 registers so that two waves share a SIMD (fewer spills than three); the
-// eigen solutions of pass 1 (rows of V and the roots) stay in the workspace
-// for pass 2, and each root's Newton iteration starts from the same lane's
-// root of the previous layer.  Intensities travel in difference form
+// 256 registers so that two waves share a SIMD (fewer spills than three); in
+// FP64 plans the layer operators of pass 1 (rows of t and r, elements of the
+// source vectors) stay in the workspace for pass 2, which would otherwise form
+// them again (a quarter of the formal solution), and each root's Newton
+// iteration starts from the same lane's root of the previous layer.  Intensities travel in difference form
 // D = I - S^g (scaled), whose layer sources are +-(S^g(d+1) - S^g(d)) Q with
 // Q = beta_l+ + t sqrt(w), exact because a layer reproduces a constant S^g
 // (beta_c + t sqrt(w) + r sqrt(w) = sqrt(w)); J - S^g and H then keep their
 // relative accuracy where they are small.  Pass 1 (top -> bottom) stores the composite
 // reflection R_d and source Sigma_d of every node in the workspace; pass 2
-// (bottom -> top) rebuilds the layer operators from the kept eigen solutions, builds the composites R^up,
+// (bottom -> top) takes the kept layer operators (FP32 plans: forms them again), builds the composites R^up,
 // Sigma^up of the layers below and emits the node outputs:
 //     I+ = (I - R^up R)^-1 (R^up Sigma + Sigma^up),  I- = R I+ + Sigma,
 // and the same combination of the unit-source responses of the two layers
@@ -619,7 +620,7 @@ struct FsDenseArgs {
   T *J, *JmS, *lstar, *lstar_c, *Iplus, *Iminus, *H, *Iemerg;
   T* wsR;     // [rows][nf][NA][NA]
   T* wsS;     // [rows][nf][NA]
-  double* wsV; // [rows][nf][NA][NA+1]: eigen solution of layer (d, d+1), row i and root k_i
+  double* wsV; // FP64: [rows][nf][NA][2 NA + 4]: layer (d, d+1): rows of t, r; bc, blp, blm, qv
                // (FP64 bulk only; a float bulk recomputes it in pass 2)
   T* wsZ;     // [rows][nf][NA][2]: R_d G_d beta+ and R_d G_d Q of layer (d, d+1), element i
   uint32_t* status; // device status word: NONFINITE when an output is not finite
@@ -680,8 +681,9 @@ __global__ __launch_bounds__(64, 2) void k_fs_dense(FsDenseArgs<T, NA> a, DenseT
   T* wsS = a.wsS + (row0 * nf + k) * NA + i;           // + node * nf * NA
   const int64_t strideR = (int64_t)nf * NA * NA;
   const int64_t strideS = (int64_t)nf * NA;
-  double* wsV = MIXED ? nullptr : a.wsV + ((row0 * nf + k) * NA + i) * (NA + 1);  // + layer * nf * NA * (NA + 1)
-  const int64_t strideV = (int64_t)nf * NA * (NA + 1);
+  constexpr int OW = 2 * NA + 4;     // kept operator values per lane and layer
+  double* wsV = MIXED ? nullptr : a.wsV + ((row0 * nf + k) * NA + i) * OW;  // + layer * nf * NA * OW
+  const int64_t strideV = (int64_t)nf * NA * OW;
   T* wsZ = a.wsZ + ((row0 * nf + k) * NA + i) * 2;          // + layer * nf * NA * 2
   const int64_t strideZ = (int64_t)nf * NA * 2;
   // the unit-source responses behind Lambda* (plain form) and 1 - Lambda*
@@ -714,14 +716,21 @@ __global__ __launch_bounds__(64, 2) void k_fs_dense(FsDenseArgs<T, NA> a, DenseT
       eigen<NA>(g64, tb, L64, om64, V, kk, lam_prev);
       om_prev = om64;
     }
-    if constexpr (!MIXED) {
-#pragma unroll
-      for (int j = 0; j < NA; ++j) wsV[d * strideV + j] = V[j];
-      wsV[d * strideV + NA] = kk;
-    }
     const double Dl64 = layer_depth(d);
     layer_ops<NA>(g64, tb, L64, V, kk, Dl64, op64);
     round_ops(op64, op);
+    if constexpr (!MIXED) {
+      double* po = wsV + d * strideV;
+#pragma unroll
+      for (int j = 0; j < NA; ++j) {
+        po[j] = op64.t[j];
+        po[NA + j] = op64.r[j];
+      }
+      po[2 * NA] = op64.bc;
+      po[2 * NA + 1] = op64.blp;
+      po[2 * NA + 2] = op64.blm;
+      po[2 * NA + 3] = op64.qv;
+    }
     const T Dl = (T)Dl64, om = (T)om64;
     const T dSg = at(a.Sg, row0 + d + 1) - at(a.Sg, row0 + d);
     const T bm = -dSg * op.qv;       // difference-form layer source of the way up
@@ -793,20 +802,27 @@ __global__ __launch_bounds__(64, 2) void k_fs_dense(FsDenseArgs<T, NA> a, DenseT
   for (int d = nd - 1; d >= 0; --d) {
     const bool has_a = d >= 1;  // layer a = (d-1, d) above node d
     T Da = (T)0, oma = (T)0;
-    if (has_a) {      // the eigen solution of layer a: kept by pass 1 (FP64 bulk) or recomputed
+    if (has_a) {      // the operators of layer a: kept by pass 1 (FP64 bulk) or formed again
       const double om64 = layer_omega(d - 1);
+      const double Da64 = layer_depth(d - 1);
       if constexpr (MIXED) {
         if (om64 != om_prev) {
           eigen<NA>(g64, tb, L64, om64, V, kk, lam_prev);
           om_prev = om64;
         }
+        layer_ops<NA>(g64, tb, L64, V, kk, Da64, op64);
       } else {
+        const double* po = wsV + (d - 1) * strideV;
 #pragma unroll
-        for (int j = 0; j < NA; ++j) V[j] = wsV[(d - 1) * strideV + j];
-        kk = wsV[(d - 1) * strideV + NA];
+        for (int j = 0; j < NA; ++j) {
+          op64.t[j] = po[j];
+          op64.r[j] = po[NA + j];
+        }
+        op64.bc = po[2 * NA];
+        op64.blp = po[2 * NA + 1];
+        op64.blm = po[2 * NA + 2];
+        op64.qv = po[2 * NA + 3];
       }
-      const double Da64 = layer_depth(d - 1);
-      layer_ops<NA>(g64, tb, L64, V, kk, Da64, op64);
       round_ops(op64, op);
       Da = (T)Da64;
       oma = (T)om64;
@@ -1429,10 +1445,11 @@ bool dense_na_supported(int na) { return na == 1 || na == 2 || na == 4 || na == 
 
 size_t dense_workspace_bytes(int na, int64_t rows, int nf, int precision) {
   // per node and frequency: R (na^2), Sigma (na), Z (2 na) in the bulk type,
-  // plus (lane-per-row FP64 kernels) the eigen solution (na^2 + na doubles)
+  // plus (lane-per-row FP64 kernels) each layer's t, r and four source
+  // vectors (2 na^2 + 4 na doubles)
   const size_t rf = (size_t)rows * nf;
   if (dense_mfma_na(na)) return dense_mfma_workspace_bytes(na, rows, nf, precision);
-  if (precision == PPRT_FP64) return rf * (size_t)(2 * na * na + 4 * na) * sizeof(double);
+  if (precision == PPRT_FP64) return rf * (size_t)(3 * na * na + 7 * na) * sizeof(double);
   return rf * (size_t)(na * na + 3 * na) * sizeof(float);
 }
 
