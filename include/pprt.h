@@ -216,7 +216,8 @@ pprt_status pprt_formal_solution(pprt_plan* plan, const pprt_fs_in* in, pprt_fs_
  * arrays, composites, products and the adding recursion in FP32, and runs
  * the eliminations with I - (reflection)(reflection) in FP64 where the
  * thick-layer rule selects them (pprt_plan_set_thick_mode).  An FP32 plan
- * with na = 32 keeps its arrays and the workspace in FP32 and computes in
+ * with na = 32 keeps its arrays and the workspace in FP32 (the layer
+ * operators included, rounded to FP32 for both passes) and computes in
  * FP64: every elimination is FP64 (pprt_thick_counts counts them all) and
  * the thick modes change nothing.  Needs a workspace of
  * pprt_plan_scattering_workspace_bytes() per node and frequency:
@@ -228,9 +229,10 @@ pprt_status pprt_formal_solution(pprt_plan* plan, const pprt_fs_in* in, pprt_fs_
  * pass forms again), and with na = 32 8 or 4 (na^2 + 3 na) bytes (FP64 or FP32
  * plans) plus 32 na bytes for each layer's eigen data (secular-equation
  * roots, Gu-Eisenstat vector, column norms), solved apart before the
- * recursion, and in FP64 plans 8 (2 na^2 + 4 na) bytes more for each
- * layer's t, r and source vectors, which the bottom-up pass reads instead
- * of forming them again (FP32 plans form them again); all kept between the
+ * recursion, and 8 or 4 (2 na^2 + 4 na) bytes more for each layer's t, r
+ * and source vectors, which the bottom-up pass reads instead of forming
+ * them again (an FP32 plan rounds them to FP32 for both passes); all kept
+ * between the
  * top-down and the bottom-up pass; omega = 0 everywhere reproduces
  * pprt_formal_solution to rounding. */
 pprt_status pprt_plan_scattering_workspace_bytes(const pprt_plan* plan, size_t* bytes);

@@ -38,13 +38,13 @@
 //   eigenvectors from them.  The workspace keeps R, Sigma and two unit-source
 //   responses per node in the plan's type and the eigen data in FP64:
 //   (NA^2 + 3 NA) reals + 32 NA bytes per node and frequency.
-// * FP64 plans also keep each layer's t, r and source vectors from the pass
-//   down (2 NA^2 + 4 NA doubles per layer and frequency, in the tiles'
-//   register order so that every lane moves 32 contiguous bytes per tile),
-//   and the pass up loads them instead of forming them again: the second
-//   formation was 27% of the formal solution, the loads cost one memory
-//   latency per layer.  FP32 plans, which exist to halve the workspace, form
-//   them again.
+// * The workspace also keeps each layer's t, r and source vectors from the
+//   pass down (2 NA^2 + 4 NA reals per layer and frequency in the plan's
+//   type, in the tiles' register order so that every lane moves contiguous
+//   bytes per tile), and the pass up loads them instead of forming them
+//   again: the second formation was 27% of the formal solution, the loads
+//   cost one memory latency per layer.  FP32 plans round them to FP32 before
+//   the pass down uses them, so that both passes work with the same layers.
 #include "pprt_internal.h"
 
 namespace pprt {
@@ -563,7 +563,7 @@ struct MfArgs {
   S* wsS;          // [rows][nf][NA]
   S* wsZ;          // [rows][nf][NA][2]
   double* wsRT;    // [rows][nf][NA][4]: layer (d, d+1): root origin and offset, zhat, column norm
-  double* wsO;     // FP64 plans: [rows][nf][2 NA^2 + 4 NA]: layer (d, d+1): t, r tiles, then bc, blp, blm, qv
+  S* wsO;          // [rows][nf][2 NA^2 + 4 NA]: layer (d, d+1): t, r tiles, then bc, blp, blm, qv
   uint32_t* status;
   unsigned long long* thick_stats;   // FP32 plans: [FP64 eliminations, all eliminations]
   int32_t nf, nitems, lower_bc;
@@ -718,38 +718,54 @@ __global__ __launch_bounds__(64) void k_fs_dense_mfma(MfArgs<S> a, MfTab<16 * T>
 #pragma unroll
         for (int q = 0; q < 4; ++q) M.t[ti][tj][q] = (double)src[(16 * ti + w.g + 4 * q) * NA + 16 * tj + w.c];
   };
-  // FP64 plans: the layer operators of layer (d, d+1), kept by pass 1 for pass 2
-  constexpr bool KEEP = sizeof(S) == 8;
+  // the layer operators of layer (d, d+1), kept by pass 1 for pass 2 in the
+  // plan's type; an FP32 plan rounds them before pass 1 uses them, so that
+  // both passes work with the same operators
   constexpr int64_t OPS = 2 * NA * NA + 4 * NA;
+  using S4 = S __attribute__((ext_vector_type(4)));
   auto ops_at = [&](int d) { return a.wsO + ((row0 + d) * nf + k) * OPS; };
-  auto save_ops = [&](int d, const Ops<T>& op) {
-    double* p = ops_at(d);
+  auto cvt4 = [](const v4d& x) { return S4{(S)x[0], (S)x[1], (S)x[2], (S)x[3]}; };
+  auto save_ops = [&](int d, Ops<T>& op) {
+    S* p = ops_at(d);
 #pragma unroll
     for (int ti = 0; ti < T; ++ti)
 #pragma unroll
       for (int tj = 0; tj < T; ++tj) {
         const int o4 = ((ti * T + tj) * 64 + lane) * 4;
-        *(v4d*)(p + o4) = op.t.t[ti][tj];
-        *(v4d*)(p + NA * NA + o4) = op.r.t[ti][tj];
+        const S4 t4 = cvt4(op.t.t[ti][tj]), r4 = cvt4(op.r.t[ti][tj]);
+        *(S4*)(p + o4) = t4;
+        *(S4*)(p + NA * NA + o4) = r4;
+        if constexpr (sizeof(S) == 4) {
+          op.t.t[ti][tj] = v4d{(double)t4[0], (double)t4[1], (double)t4[2], (double)t4[3]};
+          op.r.t[ti][tj] = v4d{(double)r4[0], (double)r4[1], (double)r4[2], (double)r4[3]};
+        }
       }
-    if (lane < NA) *(v4d*)(p + 2 * NA * NA + 4 * lane) = v4d{op.bc, op.blp, op.blm, op.qv};
+    const S4 v = S4{(S)op.bc, (S)op.blp, (S)op.blm, (S)op.qv};
+    if (lane < NA) *(S4*)(p + 2 * NA * NA + 4 * lane) = v;
+    if constexpr (sizeof(S) == 4) {
+      op.bc = (double)v[0];
+      op.blp = (double)v[1];
+      op.blm = (double)v[2];
+      op.qv = (double)v[3];
+    }
   };
   auto load_ops = [&](int d, Ops<T>& op) {
-    const double* p = ops_at(d);
+    const S* p = ops_at(d);
 #pragma unroll
     for (int ti = 0; ti < T; ++ti)
 #pragma unroll
       for (int tj = 0; tj < T; ++tj) {
         const int o4 = ((ti * T + tj) * 64 + lane) * 4;
-        op.t.t[ti][tj] = *(const v4d*)(p + o4);
-        op.r.t[ti][tj] = *(const v4d*)(p + NA * NA + o4);
+        const S4 t4 = *(const S4*)(p + o4), r4 = *(const S4*)(p + NA * NA + o4);
+        op.t.t[ti][tj] = v4d{(double)t4[0], (double)t4[1], (double)t4[2], (double)t4[3]};
+        op.r.t[ti][tj] = v4d{(double)r4[0], (double)r4[1], (double)r4[2], (double)r4[3]};
       }
     // lanes past NA hold zeros in compact vectors
-    const v4d v = lane < NA ? *(const v4d*)(p + 2 * NA * NA + 4 * lane) : v4d{0.0, 0.0, 0.0, 0.0};
-    op.bc = v[0];
-    op.blp = v[1];
-    op.blm = v[2];
-    op.qv = v[3];
+    const S4 v = lane < NA ? *(const S4*)(p + 2 * NA * NA + 4 * lane) : S4{0, 0, 0, 0};
+    op.bc = (double)v[0];
+    op.blp = (double)v[1];
+    op.blm = (double)v[2];
+    op.qv = (double)v[3];
   };
 
   if constexpr (PASS == 1) {
@@ -768,7 +784,7 @@ __global__ __launch_bounds__(64) void k_fs_dense_mfma(MfArgs<S> a, MfTab<16 * T>
       save_mat(wsR + d * strideR, R);
       if (act) wsS[d * strideS + lane] = (S)Sig;
       layer<T>(w, layer_omega(d), layer_depth(d), wsRT + d * strideRT, om_prev, op);
-      if constexpr (KEEP) save_ops(d, op);
+      save_ops(d, op);
       const double dSg = at(a.Sg, row0 + d + 1) - at(a.Sg, row0 + d);
       // G = (I - r R)^-1: P = G t, u = G (r Sigma + dS^g Q) and the unit
       // responses G beta_l+ and G Q, from one elimination on I - r R
@@ -843,10 +859,7 @@ __global__ __launch_bounds__(64) void k_fs_dense_mfma(MfArgs<S> a, MfTab<16 * T>
     }
     for (int d = nd - 1; d >= 0; --d) {
       const bool has_a = d >= 1;
-      if (has_a) {
-        if constexpr (KEEP) load_ops(d - 1, op);
-        else layer<T>(w, layer_omega(d - 1), layer_depth(d - 1), wsRT + (d - 1) * strideRT, om_prev, op);
-      }
+      if (has_a) load_ops(d - 1, op);
       Mat<T> Rd;
       load_mat(wsR + d * strideR, Rd);
       const double Sd = act ? (double)wsS[d * strideS + lane] : 0.0;
@@ -956,7 +969,7 @@ hipError_t run_mfma(const DenseLaunch& L, hipStream_t s) {
   a.wsS = a.wsR + rf * NA * NA;
   a.wsZ = a.wsS + rf * NA;
   a.wsRT = (double*)(a.wsZ + rf * NA * 2);
-  a.wsO = sizeof(S) == 8 ? a.wsRT + rf * NA * 4 : nullptr;
+  a.wsO = (S*)(a.wsRT + rf * NA * 4);
   a.status = L.status;
   a.thick_stats = L.thick_stats;
   a.nf = L.nf; a.nitems = L.nitems; a.lower_bc = L.lower_bc; a.outputs = L.outputs;
@@ -978,13 +991,13 @@ hipError_t run_mfma(const DenseLaunch& L, hipStream_t s) {
 bool dense_mfma_na(int na) { return na == 32; }
 
 size_t dense_mfma_workspace_bytes(int na, int64_t rows, int nf, int precision) {
-  // R, Sigma and the two unit-source responses in the plan's type, then per
-  // layer and root the origin, offset, zhat and column norm in FP64, and in
-  // FP64 plans each layer's t, r and four source vectors
+  // R, Sigma and the two unit-source responses in the plan's type, per layer
+  // and root the origin, offset, zhat and column norm in FP64, and each
+  // layer's t, r and four source vectors in the plan's type
   const size_t rf = (size_t)rows * nf;
-  const size_t keep = precision == PPRT_FP64 ? rf * (size_t)(2 * na * na + 4 * na) * sizeof(double) : 0;
-  return rf * (size_t)(na * na + 3 * na) * (precision == PPRT_FP64 ? sizeof(double) : sizeof(float)) +
-         rf * (size_t)(4 * na) * sizeof(double) + keep;
+  const size_t es = precision == PPRT_FP64 ? sizeof(double) : sizeof(float);
+  return rf * (size_t)(na * na + 3 * na) * es + rf * (size_t)(4 * na) * sizeof(double) +
+         rf * (size_t)(2 * na * na + 4 * na) * es;
 }
 
 hipError_t launch_fs_dense_mfma(const DenseLaunch& L, hipStream_t s) {
