@@ -2423,6 +2423,7 @@ struct pprt_vox_plan {
   std::vector<double> dirs, w;
   std::vector<int64_t> dir_ray0;   // [ndir + 1] first characteristic of each direction
   float* d_part = nullptr;         // FP32 plans: block sums of J and Lambda*_vv [2][nvox][nf]
+  float* d_part_band = nullptr;    // FP32 plans: block sums of the Lambda* band [nvox][27][nf], on first use
   int64_t* d_seg0 = nullptr;
   int32_t* d_dir = nullptr;
   uint8_t* d_core = nullptr;
@@ -2437,7 +2438,8 @@ namespace {
 constexpr int kVoxDirBlock = 64;   // directions per FP32 partial sum (FP32 plans)
 
 void vox_free(pprt_vox_plan* p) {
-  void* ptrs[] = {p->d_seg0, p->d_dir, p->d_core, p->d_ijk, p->d_ell, p->d_wn, p->d_dirs, p->d_part};
+  void* ptrs[] = {p->d_seg0, p->d_dir, p->d_core, p->d_ijk, p->d_ell, p->d_wn, p->d_dirs, p->d_part,
+                  p->d_part_band};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
 }
@@ -2484,23 +2486,30 @@ pprt_status vox_fs_launch(pprt_vox_plan* p, const void* chi, const void* S, cons
     VoxArgs<double, double> a{};
     vox_args(p, chi, S, I_out, I_core, J, flux, lstar, 0, p->nrays, a);
     e = launch_vox_fs(PPRT_FP64, false, &a, mode, c->stream);
-  } else if (mode == 1) {             // the full band: FP64 accumulation
-    VoxArgs<float, double> a{};
-    vox_args(p, chi, S, I_out, I_core, J, flux, lstar, 0, p->nrays, a);
-    e = launch_vox_fs(PPRT_FP32, false, &a, mode, c->stream);
   } else {
-    // FP32 sums over blocks of kVoxDirBlock directions, each added into the FP64 outputs
+    // FP32 sums over blocks of kVoxDirBlock directions, each added into the
+    // FP64 outputs (the band's 27 slots per voxel in a buffer of their own,
+    // allocated by the first call that asks for the band)
+    if (mode == 1 && !p->d_part_band) {
+      e = hipMalloc(&p->d_part_band, (size_t)27 * nvf * sizeof(float));
+      if (e != hipSuccess) {
+        p->d_part_band = nullptr;
+        return hip_check(c, e, "voxel band block sums");
+      }
+    }
+    const int64_t nl = mode == 1 ? 27 * nvf : (mode == 2 ? nvf : 0);
     float* pJ = p->d_part;
-    float* pL = p->d_part + nvf;
+    float* pL = mode == 1 ? p->d_part_band : p->d_part + nvf;
     for (int d0 = 0; d0 < p->ndir && e == hipSuccess; d0 += kVoxDirBlock) {
       const int d1 = std::min(p->ndir, d0 + kVoxDirBlock);
-      e = launch_vox_zero32(pJ, (mode == 2 ? 2 : 1) * nvf, c->stream);
+      e = launch_vox_zero32(pJ, nvf, c->stream);
+      if (e == hipSuccess && nl > 0) e = launch_vox_zero32(pL, nl, c->stream);
       VoxArgs<float, float> a{};
-      vox_args(p, chi, S, I_out, I_core, pJ, flux, mode == 2 ? pL : (float*)nullptr, p->dir_ray0[d0],
+      vox_args(p, chi, S, I_out, I_core, pJ, flux, nl > 0 ? pL : (float*)nullptr, p->dir_ray0[d0],
                p->dir_ray0[d1], a);
       if (e == hipSuccess) e = launch_vox_fs(PPRT_FP32, true, &a, mode, c->stream);
       if (e == hipSuccess) e = launch_vox_flush(pJ, J, nvf, c->stream);
-      if (e == hipSuccess && mode == 2) e = launch_vox_flush(pL, lstar, nvf, c->stream);
+      if (e == hipSuccess && nl > 0) e = launch_vox_flush(pL, lstar, nl, c->stream);
     }
   }
   return hip_check(c, e, "voxel formal-solution launch");

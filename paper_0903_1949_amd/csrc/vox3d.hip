@@ -47,10 +47,10 @@
 // Lambda* accumulate with the hardware's atomic add, one per segment and
 // frequency; that add rate bounds the kernel (about 1.9e11 FP64 or 3.3e11
 // FP32 adds per second on the whole chip for rows of 32 to 64 values).
-// FP32 plans therefore accumulate J (and the diagonal of Lambda* in the
-// operator-splitting step) in FP32 over blocks of 64 directions and add
-// each block's sums into the FP64 outputs; FP64 plans and the full band
-// accumulate in FP64 directly.
+// FP32 plans therefore accumulate J and Lambda* (its diagonal in the
+// operator-splitting step, or the full 27-neighbour band) in FP32 over blocks
+// of 64 directions and add each block's sums into the FP64 outputs; FP64
+// plans accumulate in FP64 directly.
 #include <algorithm>
 #include <atomic>
 #include <cmath>
