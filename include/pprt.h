@@ -729,8 +729,10 @@ pprt_status pprt_formal_solution_vjp(pprt_plan* plan, const pprt_fs_in* in,
  * difference-form source in its optical depth taken from the eigen form.
  * FP64 plans with na in {1, 2, 4, 8, 16} (E_UNSUPPORTED otherwise); in, omega
  * and gIemerg as for the forward call, device memory; workspace of
- * pprt_plan_scattering_vjp_workspace_bytes() = 8 (2 na^2 + 2 na) bytes per
- * node and frequency.  Every dq and dSg entry is overwritten.  Asynchronous. */
+ * pprt_plan_scattering_vjp_workspace_bytes() = 8 (4 na^2 + 2 na) bytes per
+ * node and frequency (the composites below every node, each layer's eigen
+ * solution and the rows of its F_T and F_C').  Every dq and dSg entry is
+ * overwritten.  Asynchronous. */
 pprt_status pprt_plan_scattering_vjp_workspace_bytes(const pprt_plan* plan, size_t* bytes);
 pprt_status pprt_formal_solution_scattering_vjp(pprt_plan* plan, const pprt_fs_in* in,
                                                 const void* omega, const void* gIemerg,

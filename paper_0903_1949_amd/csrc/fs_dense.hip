@@ -1024,16 +1024,10 @@ hipError_t run_dense_na(const DenseLaunch& L, hipStream_t s) {
 
 // the layer's t, r and Q (in o) with the rows of F_T and F_C' and the root's
 // derivative factors d(k tanh x)/dD and d(2 x coth x)/dD
-template <int NA>
-__device__ void layer_ops_grad(Grp<double, NA>& g, const LaneTab<double, NA>& L, const double (&V)[NA],
-                               double k_i, double Dl, LayerOps<double, NA>& o, double (&FT)[NA],
-                               double (&FC)[NA], double& dtx, double& dcx) {
-  const int i = g.i;
-  constexpr int RS = Slab<double, NA>::RS;
+// root i's derivative factors d(k tanh x)/dD and d(2 x coth x)/dD, x = k D / 2
+__device__ __forceinline__ void layer_dfac(double k_i, double Dl, double& dtx, double& dcx) {
   const double x = 0.5 * k_i * Dl;
   const double th = tanh(x);
-  g.put_vec(k_i * th, 2);
-  g.put_vec(2.0 * x_coth_x(x), 3);
   dtx = 0.5 * k_i * k_i * (1.0 - th * th);
   if (x < 0.05) {
     const double x2 = x * x;
@@ -1042,6 +1036,37 @@ __device__ void layer_ops_grad(Grp<double, NA>& g, const LaneTab<double, NA>& L,
     const double sh = sinh(x);
     dcx = k_i * (1.0 / th - x / (sh * sh));
   }
+}
+
+// t, r and Q (in o) from the rows of F_T and F_C'
+template <int NA>
+__device__ __forceinline__ void layer_ops_from_f(Grp<double, NA>& g, const LaneTab<double, NA>& L,
+                                                 const double (&FT)[NA], const double (&FC)[NA], double Dl,
+                                                 LayerOps<double, NA>& o) {
+  const int i = g.i;
+#pragma unroll
+  for (int j = 0; j < NA; ++j) {
+    const double ft = FT[j], fc = Dl * FC[j];
+    o.r[j] = L.m * (ft + fc) - ((j == i) ? 1.0 : 0.0);
+    o.t[j] = L.m * (ft - fc);
+  }
+  g.put_vec(L.swmu, 1);
+  double qv = 0.0;
+#pragma unroll
+  for (int j = 0; j < NA; ++j) qv = fma(FC[j], g.vec(j, 1), qv);
+  o.qv = 2.0 * L.m * qv;
+}
+
+template <int NA>
+__device__ void layer_ops_grad(Grp<double, NA>& g, const LaneTab<double, NA>& L, const double (&V)[NA],
+                               double k_i, double Dl, LayerOps<double, NA>& o, double (&FT)[NA],
+                               double (&FC)[NA], double& dtx, double& dcx) {
+  const int i = g.i;
+  constexpr int RS = Slab<double, NA>::RS;
+  const double x = 0.5 * k_i * Dl;
+  g.put_vec(k_i * tanh(x), 2);
+  g.put_vec(2.0 * x_coth_x(x), 3);
+  layer_dfac(k_i, Dl, dtx, dcx);
   double A[NA];
   g.put_mat(V);
   {
@@ -1073,17 +1098,7 @@ __device__ void layer_ops_grad(Grp<double, NA>& g, const LaneTab<double, NA>& L,
   }
   A[i] += Dl * L.m;             // D M + Q_C'
   g.inv(FC, A);
-#pragma unroll
-  for (int j = 0; j < NA; ++j) {
-    const double ft = FT[j], fc = Dl * FC[j];
-    o.r[j] = L.m * (ft + fc) - ((j == i) ? 1.0 : 0.0);
-    o.t[j] = L.m * (ft - fc);
-  }
-  g.put_vec(L.swmu, 1);
-  double qv = 0.0;
-#pragma unroll
-  for (int j = 0; j < NA; ++j) qv = fma(FC[j], g.vec(j, 1), qv);
-  o.qv = 2.0 * L.m * qv;
+  layer_ops_from_f<NA>(g, L, FT, FC, Dl, o);
 }
 
 template <int NA>
@@ -1094,7 +1109,7 @@ struct DenseVjpArgs {
   double *dq, *dSg, *dBbot, *dBbot_prev, *dIbot;
   double* wsR;   // [rows][nf][NA][NA]: R^up of each node
   double* wsS;   // [rows][nf][NA]: S^up of each node
-  double* wsV;   // [rows][nf][NA][NA+1]: eigen solution of layer (d, d+1), row i and root k_i
+  double* wsV;   // [rows][nf][NA][3 NA + 1]: layer (d, d+1): row i of V, root k_i, rows i of F_T, F_C'
   uint32_t* status;
   int32_t nf, nitems, lower_bc;
 };
@@ -1130,12 +1145,13 @@ struct DenseVjpArgs {
   };                                                                                        \
   double* wsR = a.wsR + ((row0 * nf + k) * NA + i) * NA;                                    \
   double* wsS = a.wsS + (row0 * nf + k) * NA + i;                                           \
-  double* wsV = a.wsV + ((row0 * nf + k) * NA + i) * (NA + 1);                              \
+  double* wsV = a.wsV + ((row0 * nf + k) * NA + i) * (3 * NA + 1);                         \
   const int64_t strideR = (int64_t)nf * NA * NA;                                            \
   const int64_t strideS = (int64_t)nf * NA;                                                 \
-  const int64_t strideV = (int64_t)nf * NA * (NA + 1);
+  const int64_t strideV = (int64_t)nf * NA * (3 * NA + 1);
 
 // the bottom-up composites R^up, S^up of every node, and the eigen solutions
+// with the rows of F_T and F_C' (the reverse sweep takes t, r and Q from them)
 template <int NA>
 __global__ __launch_bounds__(64, 1) void k_dense_up(DenseVjpArgs<NA> a, DenseTab<NA> tb) {
   PPRT_DENSE_GROUP_SETUP
@@ -1168,7 +1184,15 @@ __global__ __launch_bounds__(64, 1) void k_dense_up(DenseVjpArgs<NA> a, DenseTab
 #pragma unroll
     for (int j = 0; j < NA; ++j) wsV[la * strideV + j] = V[j];
     wsV[la * strideV + NA] = kk;
-    layer_ops<NA>(g, tb, L, V, kk, layer_depth(la), op);
+    {
+      double FT[NA], FC[NA], dtx, dcx;
+      layer_ops_grad<NA>(g, L, V, kk, layer_depth(la), op, FT, FC, dtx, dcx);
+#pragma unroll
+      for (int j = 0; j < NA; ++j) {
+        wsV[la * strideV + NA + 1 + j] = FT[j];
+        wsV[la * strideV + 2 * NA + 1 + j] = FC[j];
+      }
+    }
     const double dSg = at(a.Sg, row0 + d) - at(a.Sg, row0 + la);
     double X[NA], RG[NA];
     g.mul(X, Rup, op.r);
@@ -1221,13 +1245,6 @@ template <int NA>
 __global__ __launch_bounds__(64, 1) void k_dense_vjp(DenseVjpArgs<NA> a, DenseTab<NA> tb) {
   PPRT_DENSE_GROUP_SETUP
   (void)layer_omega;                  // the albedo enters through the stored eigen solutions
-  // rows of F_T and F_C' wait in LDS from the layer operators to the layer
-  // depth's derivative at the end of the step (held in registers through the
-  // step's products they spilled to scratch); lane i keeps row i, column j at
-  // j * NA + i of its group's area
-  constexpr int KS = 2 * NA * NA + 16;
-  __shared__ double keep[F * KS];
-  double* kp = keep + grp * KS + i;
   // the left factor's row of each product, [k][lane] (mul_rolled)
   __shared__ double arow[NA * 64];
   auto mul = [&](double (&C)[NA], const double (&A)[NA], const double (&B)[NA]) {
@@ -1263,16 +1280,20 @@ __global__ __launch_bounds__(64, 1) void k_dense_vjp(DenseVjpArgs<NA> a, DenseTa
     const double Sup = wsS[d * strideS];
     const double kk = wsV[la * strideV + NA];
     const double Dl = layer_depth(la);
+    // t, r and Q from the rows of F_T and F_C' kept by the pass up; those
+    // rows are read again (not held) for the layer depth's derivative at the
+    // end of the step
     LayerOps<double, NA> op;
     double dtx, dcx;
+    layer_dfac(kk, Dl, dtx, dcx);
     {
       double FT[NA], FC[NA];
-      layer_ops_grad<NA>(g, L, V, kk, Dl, op, FT, FC, dtx, dcx);
 #pragma unroll
       for (int j = 0; j < NA; ++j) {
-        kp[j * NA] = FT[j];
-        kp[(NA + j) * NA] = FC[j];
+        FT[j] = wsV[la * strideV + NA + 1 + j];
+        FC[j] = wsV[la * strideV + 2 * NA + 1 + j];
       }
+      layer_ops_from_f<NA>(g, L, FT, FC, Dl, op);
     }
     const double dSg = at(a.Sg, row0 + d) - at(a.Sg, row0 + la);
     // forward quantities of the step
@@ -1344,8 +1365,8 @@ __global__ __launch_bounds__(64, 1) void k_dense_vjp(DenseVjpArgs<NA> a, DenseTa
       double FT[NA], FC[NA];
 #pragma unroll
       for (int j = 0; j < NA; ++j) {
-        FT[j] = kp[j * NA];
-        FC[j] = kp[(NA + j) * NA];
+        FT[j] = wsV[la * strideV + NA + 1 + j];
+        FC[j] = wsV[la * strideV + 2 * NA + 1 + j];
         V[j] = wsV[la * strideV + j];
       }
       double AT[NA], AC[NA];
@@ -1461,7 +1482,7 @@ int dense_freqs_per_item(int na, int precision) {
 
 size_t dense_vjp_workspace_bytes(int na, int64_t rows, int nf) {
   // R^up (na^2) and S^up (na) of every node, the eigen solution (na^2 + na) of every layer
-  return (size_t)rows * nf * (size_t)(2 * na * na + 2 * na) * sizeof(double);
+  return (size_t)rows * nf * (size_t)(4 * na * na + 2 * na) * sizeof(double);
 }
 
 hipError_t launch_dense_vjp(const DenseVjpLaunch& L, hipStream_t s) {
