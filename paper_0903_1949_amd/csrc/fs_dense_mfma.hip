@@ -43,8 +43,15 @@
 //   type, in the tiles' register order so that every lane moves contiguous
 //   bytes per tile), and the pass up loads them instead of forming them
 //   again: the second formation was 27% of the formal solution, the loads
-//   cost one memory latency per layer.  FP32 plans round them to FP32 before
-//   the pass down uses them, so that both passes work with the same layers.
+//   cost one memory latency per layer.  FP32 plans round them to FP32, so
+//   that both passes work with the same layers.
+// * The operators of a layer do not depend on the recursion, so a pass of
+//   their own (PASS 0) forms them before it: 16 waves per (atmosphere,
+//   frequency), each taking every 16th layer, at two waves per SIMD (the
+//   recursion passes need one wave per SIMD's registers); it never stages a
+//   generic product, so its slab stops before the second operand's area
+//   (17.2 KB instead of 25.6 KB: eight waves per CU).  The pass down then
+//   loads them like the pass up (C5: 463 -> 419 ms per formal solution).
 #include "pprt_internal.h"
 
 namespace pprt {
@@ -84,8 +91,7 @@ struct Lay {
   static constexpr int LA = NA + 1;                 // row stride of the product operands
   static constexpr int LW = 16 * (2 * T + 1);       // width of an augmented block row
   static constexpr int A0 = 0;                      // NA x LA
-  static constexpr int B0 = A0 + NA * LA;           // NA x LA
-  static constexpr int BR = B0 + NA * LA;           // 4 x LW: block rows
+  static constexpr int BR = A0 + NA * LA;           // 4 x LW: block rows
   static constexpr int BC = BR + 4 * LW;            // NA x 5: block columns
   static constexpr int VS = BC + NA * 5;            // 8 vector slots of NA
   static constexpr int RT = VS + 8 * NA;            // 2 NA roots (origin, offset)
@@ -98,7 +104,9 @@ struct Lay {
   static constexpr int TMU = TD + NA;               // NA: mu
   static constexpr int TZ2 = TMU + NA;              // NA: w d
   static constexpr int TW = TZ2 + NA;               // NA: w
-  static constexpr int SIZE = TW + NA;
+  static constexpr int B0 = TW + NA;                // NA x LA: second product operand, last:
+  static constexpr int SIZE = B0 + NA * LA;         // the operator pass (no generic products)
+                                                    // takes a slab of B0 doubles
   // vector slots: 0 mat-vec input, 1 mat-vec output, 2..4 right-hand-side
   // columns, 5 sqrt(w), 6 sqrt(w) mu, 7 spare
 };
@@ -654,12 +662,17 @@ __global__ __launch_bounds__(64) void k_mf_roots(MfArgs<S> a, MfTab<16 * T> tb) 
   }
 }
 
+constexpr int kOpsSplit = 16;   // waves per (atmosphere, frequency) forming the layer operators
+
 template <int T, int PASS, typename S>
-__global__ __launch_bounds__(64) void k_fs_dense_mfma(MfArgs<S> a, MfTab<16 * T> tb) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(PASS == 0 ? 2 : 1)))
+void k_fs_dense_mfma(MfArgs<S> a, MfTab<16 * T> tb) {
   constexpr int NA = 16 * T;
-  __shared__ double slab[Lay<T>::SIZE];
+  __shared__ double slab[PASS == 0 ? Lay<T>::B0 : Lay<T>::SIZE];
   const int lane = (int)threadIdx.x;
-  const int item = (int)blockIdx.x;
+  // PASS 0 forms the layer operators: kOpsSplit waves per (atmosphere,
+  // frequency), wave c taking layers c, c + kOpsSplit, ...
+  const int item = PASS == 0 ? (int)(blockIdx.x / kOpsSplit) : (int)blockIdx.x;
   if (item >= a.nitems) return;
   const Item it = a.items[item];
   const int b = it.b, nd = it.nd, nf = a.nf;
@@ -768,7 +781,14 @@ __global__ __launch_bounds__(64) void k_fs_dense_mfma(MfArgs<S> a, MfTab<16 * T>
     op.qv = (double)v[3];
   };
 
-  if constexpr (PASS == 1) {
+  if constexpr (PASS == 0) {
+    // ---- the layer operators (the roots of a layer depend on its albedo
+    // alone, so a layer with the albedo of this wave's previous one keeps them)
+    for (int d = (int)(blockIdx.x % kOpsSplit); d < nd - 1; d += kOpsSplit) {
+      layer<T>(w, layer_omega(d), layer_depth(d), wsRT + d * strideRT, om_prev, op);
+      save_ops(d, op);
+    }
+  } else if constexpr (PASS == 1) {
     // ---- pass 1: top -> bottom, composite R and Sigma of every node
     Mat<T> R;
 #pragma unroll
@@ -783,8 +803,7 @@ __global__ __launch_bounds__(64) void k_fs_dense_mfma(MfArgs<S> a, MfTab<16 * T>
     for (int d = 0; d < nd - 1; ++d) {
       save_mat(wsR + d * strideR, R);
       if (act) wsS[d * strideS + lane] = (S)Sig;
-      layer<T>(w, layer_omega(d), layer_depth(d), wsRT + d * strideRT, om_prev, op);
-      save_ops(d, op);
+      load_ops(d, op);
       const double dSg = at(a.Sg, row0 + d + 1) - at(a.Sg, row0 + d);
       // G = (I - r R)^-1: P = G t, u = G (r Sigma + dS^g Q) and the unit
       // responses G beta_l+ and G Q, from one elimination on I - r R
@@ -981,6 +1000,7 @@ hipError_t run_mfma(const DenseLaunch& L, hipStream_t s) {
     tb.z2[i] = wt / (m * m); tb.sw[i] = sqrt(wt); tb.swmu[i] = sqrt(wt) * m;
   }
   hipLaunchKernelGGL((k_mf_roots<T, S>), dim3((L.nitems + 64 / NA - 1) / (64 / NA)), dim3(64), 0, s, a, tb);
+  hipLaunchKernelGGL((k_fs_dense_mfma<T, 0, S>), dim3(L.nitems * kOpsSplit), dim3(64), 0, s, a, tb);
   hipLaunchKernelGGL((k_fs_dense_mfma<T, 1, S>), dim3(L.nitems), dim3(64), 0, s, a, tb);
   hipLaunchKernelGGL((k_fs_dense_mfma<T, 2, S>), dim3(L.nitems), dim3(64), 0, s, a, tb);
   return hipGetLastError();
