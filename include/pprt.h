@@ -804,10 +804,13 @@ void pprt_vox_plan_destroy(pprt_vox_plan* plan);
  * u = (i+di, j+dj, k+dk), slot (di+1) 9 + (dj+1) 3 + (dk+1), phi periodic,
  * zero for neighbours beyond a radial boundary or a pole, followed along each
  * characteristic through its last 8 distinct voxels.  Accumulation by
- * atomic adds: FP64 plans and the Lambda* band in FP64; in FP32 plans J (and
- * the flux in FP64) as FP32 sums over blocks of 64 directions added into
- * the FP64 output.  Results agree between runs to rounding, not bit for bit.
- * The plan holds 2 x 4 nvox nf bytes of block sums in FP32 plans.
+ * atomic adds: FP64 plans in FP64; in FP32 plans J and the Lambda* band (the
+ * flux in FP64) as FP32 sums over blocks of 64 directions added into the
+ * FP64 outputs.  Results agree between runs to rounding, not bit for bit.
+ * The plan holds 2 x 4 nvox nf bytes of block sums in FP32 plans, and the
+ * first call of an FP32 plan that asks for lstar allocates 27 x 4 nvox nf
+ * bytes more for the band's block sums (kept until the plan is destroyed;
+ * E_DEVICE if that allocation fails).
  * Asynchronous on the context's stream; calls on one plan must not overlap. */
 pprt_status pprt_vox_formal_solution(pprt_vox_plan* plan, const void* chi, const void* S, const void* I_out,
                                      const void* I_core, double* J, double* flux, double* lstar);
