@@ -221,12 +221,12 @@ pprt_status pprt_formal_solution(pprt_plan* plan, const pprt_fs_in* in, pprt_fs_
  * FP64: every elimination is FP64 (pprt_thick_counts counts them all) and
  * the thick modes change nothing.  Needs a workspace of
  * pprt_plan_scattering_workspace_bytes() per node and frequency:
- * 8 (3 na^2 + 7 na) bytes in FP64 plans with na <= 16 (the composite
- * reflection and source of every node, two unit-source responses of each
- * layer and each layer's t, r and source vectors, which the bottom-up pass
- * reads instead of forming them again), 4 (na^2 + 3 na) bytes in FP32 plans
- * with na <= 16 (the same without the layer operators, which the bottom-up
- * pass forms again), and with na = 32 8 or 4 (na^2 + 3 na) bytes (FP64 or FP32
+ * 8 or 4 (3 na^2 + 7 na) bytes in FP64 or FP32 plans with na <= 16 (the
+ * composite reflection and source of every node, two unit-source responses
+ * of each layer and each layer's t, r and source vectors, which the
+ * bottom-up pass reads instead of forming them again; FP32 plans keep the
+ * rounded operators and form the FP64 ones again only for the eliminations
+ * the thick-layer rule runs in FP64), and with na = 32 8 or 4 (na^2 + 3 na) bytes (FP64 or FP32
  * plans) plus 32 na bytes for each layer's eigen data (secular-equation
  * roots, Gu-Eisenstat vector, column norms), solved apart before the
  * recursion, and 8 or 4 (2 na^2 + 4 na) bytes more for each layer's t, r

@@ -39,17 +39,17 @@
 // pivot row from its lane through the cross-lane permute and scale no row
 // until the end (fewer instructions than a pivot lane that scales and stores
 // its row while the other lanes wait).  The two passes are two kernels, each limited to
-// 256 registers so that two waves share a SIMD (fewer spills than three); in
-// FP64 plans the layer operators of pass 1 (rows of t and r, elements of the
-// source vectors) stay in the workspace for pass 2, which would otherwise form
-// them again (a quarter of the formal solution), and each root's Newton
+// 256 registers so that two waves share a SIMD (fewer spills than three); the
+// layer operators of pass 1 (rows of t and r, elements of the source vectors,
+// in the bulk type) stay in the workspace for pass 2, which would otherwise
+// form them again (a quarter of the formal solution), and each root's Newton
 // iteration starts from the same lane's root of the previous layer.  Intensities travel in difference form
 // D = I - S^g (scaled), whose layer sources are +-(S^g(d+1) - S^g(d)) Q with
 // Q = beta_l+ + t sqrt(w), exact because a layer reproduces a constant S^g
 // (beta_c + t sqrt(w) + r sqrt(w) = sqrt(w)); J - S^g and H then keep their
 // relative accuracy where they are small.  Pass 1 (top -> bottom) stores the composite
 // reflection R_d and source Sigma_d of every node in the workspace; pass 2
-// (bottom -> top) takes the kept layer operators (FP32 plans: forms them again), builds the composites R^up,
+// (bottom -> top) takes the kept layer operators, builds the composites R^up,
 // Sigma^up of the layers below and emits the node outputs:
 //     I+ = (I - R^up R)^-1 (R^up Sigma + Sigma^up),  I- = R I+ + Sigma,
 // and the same combination of the unit-source responses of the two layers
@@ -63,9 +63,9 @@
 // t and r carry is a small difference of the large non-diffusive modes, and
 // the matrix products V diag(.) V^T of an FP32 layer solution bury it in
 // rounding (the diffusion eigenvalue is ~(1 - omega) of the others), which
-// the recursion then accumulates over many layers.  The FP64 eigen solution
-// is recomputed in each pass (only when the layer albedo changes) instead of
-// being stored.  The eliminations with I - (reflection)(reflection)
+// the recursion then accumulates over many layers.  Pass 1 keeps the rounded
+// operators for pass 2, which forms the FP64 ones again only for the layers
+// whose elimination runs in FP64.  The eliminations with I - (reflection)(reflection)
 // -- G = (I - r R_d)^-1 of the way down, (I - R^up r)^-1 and (I - R^up R_d)^-1
 // of the way up -- run in FP64 where the thick-layer rule asks for it: the layer's
 // absorption depth D (1 - omega)^1/2 exceeds 1, or the bound |r|_inf |R|_inf
@@ -620,7 +620,7 @@ struct FsDenseArgs {
   T *J, *JmS, *lstar, *lstar_c, *Iplus, *Iminus, *H, *Iemerg;
   T* wsR;     // [rows][nf][NA][NA]
   T* wsS;     // [rows][nf][NA]
-  double* wsV; // FP64: [rows][nf][NA][2 NA + 4]: layer (d, d+1): rows of t, r; bc, blp, blm, qv
+  T* wsV;      // [rows][nf][NA][2 NA + 4]: layer (d, d+1): rows of t, r; bc, blp, blm, qv (bulk type)
                // (FP64 bulk only; a float bulk recomputes it in pass 2)
   T* wsZ;     // [rows][nf][NA][2]: R_d G_d beta+ and R_d G_d Q of layer (d, d+1), element i
   uint32_t* status; // device status word: NONFINITE when an output is not finite
@@ -682,7 +682,7 @@ __global__ __launch_bounds__(64, 2) void k_fs_dense(FsDenseArgs<T, NA> a, DenseT
   const int64_t strideR = (int64_t)nf * NA * NA;
   const int64_t strideS = (int64_t)nf * NA;
   constexpr int OW = 2 * NA + 4;     // kept operator values per lane and layer
-  double* wsV = MIXED ? nullptr : a.wsV + ((row0 * nf + k) * NA + i) * OW;  // + layer * nf * NA * OW
+  T* wsV = a.wsV + ((row0 * nf + k) * NA + i) * OW;  // + layer * nf * NA * OW
   const int64_t strideV = (int64_t)nf * NA * OW;
   T* wsZ = a.wsZ + ((row0 * nf + k) * NA + i) * 2;          // + layer * nf * NA * 2
   const int64_t strideZ = (int64_t)nf * NA * 2;
@@ -719,17 +719,17 @@ __global__ __launch_bounds__(64, 2) void k_fs_dense(FsDenseArgs<T, NA> a, DenseT
     const double Dl64 = layer_depth(d);
     layer_ops<NA>(g64, tb, L64, V, kk, Dl64, op64);
     round_ops(op64, op);
-    if constexpr (!MIXED) {
-      double* po = wsV + d * strideV;
+    {                 // kept for pass 2 in the bulk type (FP32 plans: the rounded operators)
+      T* po = wsV + d * strideV;
 #pragma unroll
       for (int j = 0; j < NA; ++j) {
-        po[j] = op64.t[j];
-        po[NA + j] = op64.r[j];
+        po[j] = op.t[j];
+        po[NA + j] = op.r[j];
       }
-      po[2 * NA] = op64.bc;
-      po[2 * NA + 1] = op64.blp;
-      po[2 * NA + 2] = op64.blm;
-      po[2 * NA + 3] = op64.qv;
+      po[2 * NA] = op.bc;
+      po[2 * NA + 1] = op.blp;
+      po[2 * NA + 2] = op.blm;
+      po[2 * NA + 3] = op.qv;
     }
     const T Dl = (T)Dl64, om = (T)om64;
     const T dSg = at(a.Sg, row0 + d + 1) - at(a.Sg, row0 + d);
@@ -802,28 +802,20 @@ __global__ __launch_bounds__(64, 2) void k_fs_dense(FsDenseArgs<T, NA> a, DenseT
   for (int d = nd - 1; d >= 0; --d) {
     const bool has_a = d >= 1;  // layer a = (d-1, d) above node d
     T Da = (T)0, oma = (T)0;
-    if (has_a) {      // the operators of layer a: kept by pass 1 (FP64 bulk) or formed again
+    if (has_a) {      // the operators of layer a, kept by pass 1 (FP32 plans: rounded; the
+                      // FP64 ones are formed again where an FP64 elimination needs them)
       const double om64 = layer_omega(d - 1);
       const double Da64 = layer_depth(d - 1);
-      if constexpr (MIXED) {
-        if (om64 != om_prev) {
-          eigen<NA>(g64, tb, L64, om64, V, kk, lam_prev);
-          om_prev = om64;
-        }
-        layer_ops<NA>(g64, tb, L64, V, kk, Da64, op64);
-      } else {
-        const double* po = wsV + (d - 1) * strideV;
+      const T* po = wsV + (d - 1) * strideV;
 #pragma unroll
-        for (int j = 0; j < NA; ++j) {
-          op64.t[j] = po[j];
-          op64.r[j] = po[NA + j];
-        }
-        op64.bc = po[2 * NA];
-        op64.blp = po[2 * NA + 1];
-        op64.blm = po[2 * NA + 2];
-        op64.qv = po[2 * NA + 3];
+      for (int j = 0; j < NA; ++j) {
+        op.t[j] = po[j];
+        op.r[j] = po[NA + j];
       }
-      round_ops(op64, op);
+      op.bc = po[2 * NA];
+      op.blp = po[2 * NA + 1];
+      op.blm = po[2 * NA + 2];
+      op.qv = po[2 * NA + 3];
       Da = (T)Da64;
       oma = (T)om64;
     }
@@ -918,6 +910,14 @@ __global__ __launch_bounds__(64, 2) void k_fs_dense(FsDenseArgs<T, NA> a, DenseT
         ++ntot;
       }
       if (use64) {
+        if constexpr (MIXED) {      // layer a's FP64 operators (wave-uniform branch)
+          const double om64 = layer_omega(d - 1);
+          if (om64 != om_prev) {
+            eigen<NA>(g64, tb, L64, om64, V, kk, lam_prev);
+            om_prev = om64;
+          }
+          layer_ops<NA>(g64, tb, L64, V, kk, layer_depth(d - 1), op64);
+        }
         solve_up<double>(g64, Rup, op64.r, RG);
       } else {
         T Y[NA];
@@ -974,12 +974,12 @@ hipError_t run_dense(const DenseLaunch& L, hipStream_t s) {
   a.Ibot = (const T*)L.Ibot;
   a.J = (T*)L.J; a.JmS = (T*)L.JmS; a.lstar = (T*)L.lstar; a.lstar_c = (T*)L.lstar_c;
   a.Iplus = (T*)L.Iplus; a.Iminus = (T*)L.Iminus; a.H = (T*)L.H; a.Iemerg = (T*)L.Iemerg;
-  // workspace: R | Sigma | Z in the bulk type, then (FP64 bulk) the eigen solutions
+  // workspace: R | Sigma | Z | the layer operators, all in the bulk type
   const size_t rf = (size_t)L.rows * L.nf;
   a.wsR = (T*)L.ws;
   a.wsS = a.wsR + rf * NA * NA;
   a.wsZ = a.wsS + rf * NA;
-  a.wsV = std::is_same<T, double>::value ? (double*)(a.wsZ + rf * NA * 2) : nullptr;
+  a.wsV = a.wsZ + rf * NA * 2;
   a.nf = L.nf; a.nitems = L.nitems; a.lower_bc = L.lower_bc; a.outputs = L.outputs;
   a.status = L.status;
   a.thick_stats = L.thick_stats;
@@ -1471,7 +1471,7 @@ size_t dense_workspace_bytes(int na, int64_t rows, int nf, int precision) {
   const size_t rf = (size_t)rows * nf;
   if (dense_mfma_na(na)) return dense_mfma_workspace_bytes(na, rows, nf, precision);
   if (precision == PPRT_FP64) return rf * (size_t)(3 * na * na + 7 * na) * sizeof(double);
-  return rf * (size_t)(na * na + 3 * na) * sizeof(float);
+  return rf * (size_t)(3 * na * na + 7 * na) * sizeof(float);
 }
 
 // frequencies per wave: one on the matrix cores, else 64 / na lane groups

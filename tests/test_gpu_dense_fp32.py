@@ -149,15 +149,15 @@ def test_fp32_continuum_slice_modes(gpu_ctx):
 
 
 def test_fp32_workspace_and_mode_validation(gpu_ctx):
-    """An FP32 plan needs 4 (na^2 + 3 na) bytes per node and frequency (no
-    stored layer operators), an FP64 plan 8 (3 na^2 + 7 na) up to 16 angles;
+    """Up to 16 angles a plan needs 4 or 8 (3 na^2 + 7 na) bytes per node and
+    frequency (FP32 or FP64: composites, unit responses, kept layer operators);
     at 32 angles the same 4 or 8 (na^2 + 3 na) bytes, the layers' eigen
     data (root, zhat, norm), 32 na bytes, and each layer's t, r and source
     vectors, 4 or 8 (2 na^2 + 4 na) bytes; modes outside PPRT_THICK_* are
     refused."""
     import ctypes as C
     nd, nf = [30, 20], 40
-    for na, prec, per in ((8, pprt.FP32, 4 * (8 * 8 + 3 * 8)), (8, pprt.FP64, 8 * (3 * 8 * 8 + 7 * 8)),
+    for na, prec, per in ((8, pprt.FP32, 4 * (3 * 8 * 8 + 7 * 8)), (8, pprt.FP64, 8 * (3 * 8 * 8 + 7 * 8)),
                           (32, pprt.FP32, 4 * (32 * 32 + 3 * 32) + 32 * 32 + 4 * (2 * 32 * 32 + 4 * 32)),
                           (32, pprt.FP64, 8 * (32 * 32 + 3 * 32) + 32 * 32 + 8 * (2 * 32 * 32 + 4 * 32))):
         plan = pprt.Plan(gpu_ctx, nd, na, nf, precision=prec, outputs=pprt.OUT_J)
